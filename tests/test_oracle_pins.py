@@ -1,0 +1,386 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it pins.  None of them re-types the oracle's
+formula: they use brute force, closed forms, invariants and library
+routines (SVD, linear solves, the Faddeeva function).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import slar_inputs as SI
+from oracle import cross as CR
+from oracle import feet as FT
+from oracle import grid as G
+from oracle import ht as HT
+from oracle import lomac as LM
+from oracle import macro as MA
+from oracle import spectral as SP
+from oracle import step as ST
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ grid
+def test_grid_points_printed_values():
+    """Section 4.2 prints v_70 = 11/16 (two-stream slice) and v_64 = -dv/2
+    (bump-on-tail slice) on 128-cell velocity grids: cell centres."""
+    rows = [l.split() for l in open(os.path.join(GOLD, "grid_points.txt")) if l.strip() and not l.startswith("#")]
+    assert rows
+    for lo, hi, n, i1, val in rows:
+        c = G.centres(float(lo), float(hi), int(n))
+        assert abs(c[int(i1) - 1] - float(val)) < 1e-14
+
+
+def test_quadratic_weights_closed_form():
+    """Eq. (1d_quadratic_interp_weight): partition of unity, exact on
+    quadratics, nodal at xi in {-1, 0, 1}; the general Lagrange form of width 3
+    gives the same numbers."""
+    xi = np.linspace(-0.5, 0.5, 41)
+    w = G.quadratic_weights(xi)
+    assert np.allclose(w.sum(-1), 1.0, atol=1e-15)
+    for poly in (lambda t: 1 + 0 * t, lambda t: t, lambda t: t * t):
+        exact = poly(xi)
+        interp = w @ np.array([poly(-1.0), poly(0.0), poly(1.0)])
+        assert np.allclose(interp, exact, atol=1e-14)
+    assert np.allclose(G.lagrange_weights(xi, 3), w, atol=1e-15)
+    assert np.allclose(G.quadratic_weights(np.array([0.0])), [[0, 1, 0]])
+
+
+def test_quartic_weights_exact_on_quartics():
+    """Width-5 stencil (the higher-order extension of section 3.1)."""
+    xi = np.linspace(-0.5, 0.5, 33)
+    w = G.lagrange_weights(xi, 5)
+    nodes = np.arange(-2, 3, dtype=float)
+    for deg in range(5):
+        assert np.allclose(w @ nodes ** deg, xi ** deg, atol=1e-13)
+    # a quintic is not reproduced (degree 4 exactly, not more)
+    assert np.abs(w @ nodes ** 5 - xi ** 5).max() > 1e-3
+
+
+def test_locate_half_open_cells():
+    lo, h = -1.0, 0.25
+    j, xi = G.locate(np.array([-1.0, -0.875, -0.75 + 1e-12, 0.999]), lo, h)
+    assert list(j) == [0, 0, 1, 7]
+    assert np.all(xi >= -0.5) and np.all(xi < 0.5)
+
+
+# ----------------------------------------------------- HT-SL sampling (P2)
+def _brute(F, rows, wts):
+    return HT.block_interp(HT.full(F)[None], rows, wts)[:, 0]
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("width", [3, 5])
+def test_ht_sample_equals_full_grid_interpolation_1d1v(kind, width):
+    """Section 3.1: the leaf-contraction evaluation equals eq. (tp_interp) on
+    the reconstructed tensor, for any ranks and feet."""
+    p = SI.config("landau1d", n=20)
+    F = SI.random_ht(2, p.n, (5, 7), seed=11)
+    idx = SI.random_requests(p.n, 400, 2)
+    E = 0.8 * SI.random_field((p.n[0],), 4)[None]
+    foot = FT.feet(idx, p.lo, p.hi, p.n, 1, kind, 1.3, 1.0, E)
+    rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, width, kind, 1)
+    a = HT.sample(F, rows, wts)
+    b = _brute(F, rows, wts)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("with_corr", [False, True])
+def test_ht_sample_equals_full_grid_interpolation_2d2v(with_corr):
+    p = SI.config("landau2d", n=10)
+    F = SI.random_ht(4, p.n, (3, 4, 5, 2, 6, 4), seed=5)
+    if with_corr:
+        rng = np.random.default_rng(9)
+        F["corr"] = {"C": rng.standard_normal((4, 10, 10)), "Q": rng.standard_normal((4, 10, 10))}
+    idx = SI.random_requests(p.n, 600, 3)
+    E = 0.5 * np.stack([SI.random_field((10, 10), 7), SI.random_field((10, 10), 8)])
+    foot = FT.feet(idx, p.lo, p.hi, p.n, 2, 2, 0.9, 1.0, E)
+    rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, 3, 2, 2)
+    a = HT.sample(F, rows, wts)
+    b = _brute(F, rows, wts)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+# ------------------------------------------------- stability analysis (P3-P5)
+def _g1d(lam, zeta):
+    m = np.round(lam)
+    th = lam - m
+    return np.exp(-1j * m * zeta) * (1 + th ** 2 * (np.cos(zeta) - 1) - 1j * th * np.sin(zeta))
+
+
+def test_amplification_factor_of_x_shift():
+    """Appendix A: a Fourier mode e^{i j zeta} is multiplied by
+    g = e^{-i m zeta} (1 + th^2 (cos zeta - 1) - i th sin zeta), lam = m + th,
+    for constant-coefficient advection with CFL lam = v tau / dx."""
+    Nx, Nv = 32, 9
+    lo, hi = (0.0, -3.0), (2 * math.pi, 3.0)
+    kmode = 3
+    x = G.centres(lo[0], hi[0], Nx)
+    j = np.arange(Nx)
+    zeta = 2 * math.pi * kmode / Nx
+    F = {"leaves": [np.stack([np.cos(zeta * j), np.sin(zeta * j)], 1), np.eye(Nv)],
+         "root": np.zeros((2, Nv))}
+    F["root"][0, :] = 1.0       # F[i, v] = cos(zeta i) for every v
+    tau = 0.37
+    idx = np.stack(np.meshgrid(np.arange(Nx), np.arange(Nv), indexing="ij"), -1).reshape(-1, 2)
+    foot = FT.feet(idx, lo, hi, (Nx, Nv), 1, 0, tau, 1.0)
+    rows, wts = FT.stencils(foot, idx, lo, hi, (Nx, Nv), 3, 0, 1)
+    out = HT.sample(F, rows, wts).reshape(Nx, Nv)
+    v = G.centres(lo[1], hi[1], Nv)
+    dx = (hi[0] - lo[0]) / Nx
+    for c in range(Nv):
+        g = _g1d(v[c] * tau / dx, zeta)
+        expect = np.real(g * np.exp(1j * zeta * j))
+        assert np.abs(out[:, c] - expect).max() < 1e-13
+        assert abs(g) <= 1 + 1e-15
+
+
+def test_integer_shift_is_exact_and_zero_step_is_identity():
+    """Appendix A: an integer CFL is a pure circular shift; tau = 0 leaves
+    every entry unchanged."""
+    Nx, Nv = 16, 4
+    lo, hi = (0.0, 0.5), (16.0, 4.5)       # dx = 1, v = 1, 2, 3, 4
+    F = SI.random_ht(2, (Nx, Nv), (4, 3), seed=1)
+    full = HT.full(F)
+    idx = np.stack(np.meshgrid(np.arange(Nx), np.arange(Nv), indexing="ij"), -1).reshape(-1, 2)
+    for tau, shift in ((1.0, 1), (0.0, 0)):
+        foot = FT.feet(idx, lo, hi, (Nx, Nv), 1, 0, tau, 1.0)
+        rows, wts = FT.stencils(foot, idx, lo, hi, (Nx, Nv), 3, 0, 1)
+        out = HT.sample(F, rows, wts).reshape(Nx, Nv)
+        for c in range(Nv):
+            s = shift * (c + 1)
+            assert np.abs(out[:, c] - np.roll(full[:, c], s)).max() < 1e-14
+
+
+def test_l2_nonincrease_full_grid():
+    """Theorem 1: ||F^{n+1}|| <= ||F^n|| for the constant-coefficient problem
+    at any step size (full-grid update, 2D)."""
+    rng = np.random.default_rng(0)
+    N = 24
+    f = rng.standard_normal((N, N))
+    lo, hi = (0.0, 0.0), (1.0, 1.0)
+    idx = np.stack(np.meshgrid(np.arange(N), np.arange(N), indexing="ij"), -1).reshape(-1, 2)
+    P = FT.grid_points(idx, lo, hi, (N, N))
+    for a in ((0.3, -0.7), (2.6, 11.2), (-7.45, 0.01)):
+        foot = P - np.array(a) * 0.05
+        rows, wts = [], []
+        for m in range(2):
+            j, xi = G.locate(foot[:, m], lo[m], 1.0 / N)
+            rows.append(G.stencil_rows(j, 3, N)); wts.append(G.quadratic_weights(xi))
+        g = HT.block_interp(f[None], rows, wts)[:, 0]
+        assert np.linalg.norm(g) <= np.linalg.norm(f) * (1 + 1e-14)
+
+
+# -------------------------------------------------------- cross approx (P6-P8)
+def test_aca_recovers_exact_low_rank_matrix():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((50, 4)) @ rng.standard_normal((4, 70))
+    U, V, info = CR.aca(lambda i: A[i], lambda j: A[:, j], lambda I, J: A[I, J], 50, 70,
+                        1e-12, 20, 0, SI.probe_indices(50, 70, 64, 1))
+    assert info["rank"] <= 5
+    assert np.abs(U @ V.T - A).max() < 1e-12 * np.abs(A).max()
+
+
+def test_slar_reproduces_landau_f0_exactly():
+    """An exactly low-rank input (Landau f0: ranks x-leaves 2, others 1) is
+    recovered exactly with its true ranks by a zero step."""
+    p = SI.config("landau2d", n=12)
+    o = ST.Oracle(p, probes=SI.probe_indices(144, 144, 64, 2))
+    F0 = SI.initial_ht(p)
+    Fn = o.slar(F0, 0, 0.0, 1.0, None)
+    assert HT.ranks(Fn) == (2, 2, 1, 1, 1, 1)
+    assert np.abs(HT.full(Fn) - HT.full(F0)).max() < 1e-14
+
+
+def test_slar_matches_full_grid_update_within_tolerance():
+    """SLAR(F) vs the dense SL-FD update of the same tensor: error of the
+    order of eps_Base ||F|| (cross + truncation), on a 12^4 grid."""
+    p = SI.config("landau2d", n=12).with_(tol=1e-6, rmax=40, alpha=0.3)
+    o = ST.Oracle(p, probes=SI.probe_indices(144, 144, 64, 3))
+    F0 = SI.initial_ht(p)
+    E = o.efield(F0)
+    Fn = o.slar(F0, 2, 0.5, 1.0, E)
+    idx = np.stack(np.unravel_index(np.arange(12 ** 4), (12,) * 4), 1)
+    foot = FT.feet(idx, p.lo, p.hi, p.n, 2, 2, 0.5, 1.0, E)
+    rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, 3, 2, 2)
+    dense = _brute(F0, rows, wts).reshape((12,) * 4)
+    err = np.linalg.norm(HT.full(Fn) - dense) / np.linalg.norm(dense)
+    assert err < 5 * p.tol
+
+
+def test_truncation_error_bound_and_leading_singular_vectors():
+    """HSVD error <= eps ||F|| and column 0 of each leaf = the leading left
+    singular vector of that mode's matricisation (Supplement B)."""
+    rng = np.random.default_rng(2)
+    n = 9
+    Ft = SI.random_ht(4, (n,) * 4, (4, 4, 4, 4, 6, 6), seed=7)
+    A = HT.full(Ft).reshape(n * n, n * n) + 1e-7 * rng.standard_normal((n * n, n * n))
+    tol = 1e-4
+    Fh = CR.truncate_dense(A, (n, n), (n, n), tol, 81)
+    R = HT.full(Fh).reshape(n * n, n * n)
+    assert np.linalg.norm(R - A) <= tol * np.linalg.norm(A) * (1 + 1e-12)
+    T = HT.full(Fh)
+    for mu in range(4):
+        M = np.moveaxis(T, mu, 0).reshape(n, -1)
+        u, s, _ = np.linalg.svd(M)
+        c0 = Fh["leaves"][mu][:, 0]
+        assert abs(abs(u[:, 0] @ c0) - 1.0) < 1e-8
+
+
+def test_recompress_matches_dense_svd():
+    rng = np.random.default_rng(8)
+    U = rng.standard_normal((40, 7)); V = rng.standard_normal((30, 7))
+    X, s, Y, _, _ = CR.recompress(U, V, 1e-14, 40, 2)
+    sd = np.linalg.svd(U @ V.T, compute_uv=False)
+    assert np.allclose(s, sd[: len(s)], rtol=1e-12)
+    assert np.abs(X @ np.diag(s) @ Y.T - U @ V.T).max() < 1e-12 * np.abs(U @ V.T).max()
+
+
+# ------------------------------------------------------------- Poisson (P10)
+def test_poisson_closed_form_and_zero_mean():
+    """rho = -alpha cos(kx) (n_e = 1 + alpha cos kx, n_i = 1) gives
+    E = -(alpha/k) sin(kx), eqs. (Poisson), (Efromphi)."""
+    k, a = 0.5, 0.3
+    L = 2 * math.pi / k
+    x = G.centres(0.0, L, 64)
+    _, E = SP.poisson(1 + a * np.cos(k * x), 1.0, [L])
+    assert np.abs(E[0] + (a / k) * np.sin(k * x)).max() < 1e-13
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    _, E2 = SP.poisson(1 + a * np.cos(k * X1) + a * np.cos(k * X2), 1.0, [L, L])
+    assert np.abs(E2[1] + (a / k) * np.sin(k * X2)).max() < 1e-13
+    assert abs(E2.sum()) < 1e-11
+
+
+def test_discrete_identities_sum_div_and_sum_rho_E():
+    """Spectral compatibility (section 3.2.3): sum D.F = 0, sum rho E = 0."""
+    f = SI.random_field((24, 20), 3, smooth=False)
+    F = np.stack([SI.random_field((24, 20), 4, smooth=False), SI.random_field((24, 20), 5, smooth=False)])
+    L = [3.0, 5.0]
+    assert abs(SP.div(F, L).sum()) < 1e-11
+    _, E = SP.poisson(1.0 + 0.3 * f, 1.0, L)
+    rho = -0.3 * f
+    assert np.abs((rho[None] * E).sum(axis=(1, 2))).max() < 1e-11
+
+
+# --------------------------------------------------------------- LoMaC (P9)
+def _rand_basis(seed=0, dv=2, n=12):
+    rng = np.random.default_rng(seed)
+    vg = [G.centres(-5, 5, n) for _ in range(dv)]
+    u1 = [np.exp(-0.5 * (v - rng.uniform(-1, 1)) ** 2) * (1 + 0.2 * rng.standard_normal(n)) for v in vg]
+    u1 = [u / np.linalg.norm(u) for u in u1]
+    return LM.basis(u1, vg, [10.0 / n] * dv), vg
+
+
+def test_q_basis_is_orthogonal_and_norms_factorise():
+    """Supplement B: Q_0, Q_{1,mu}, Q_2 are orthogonal in <.,.>_{v;omega^-1}
+    and their squared norms are the stated products of 1D norms."""
+    B, vg = _rand_basis()
+    h = 10.0 / 12
+    Om = np.multiply.outer(B["g"][0]["omega"], B["g"][1]["omega"])
+    Q = B["Q"]
+    Gm = np.einsum("aij,bij->ab", Q, Q / Om[None] * h * h)
+    off = Gm - np.diag(np.diag(Gm))
+    assert np.abs(off).max() < 1e-12 * np.abs(np.diag(Gm)).max()
+    assert np.allclose(np.diag(Gm), B["NQ"], rtol=1e-12)
+    assert Om.min() >= LM.DELTA ** 2
+
+
+def test_projection_preserves_moments_and_is_idempotent():
+    """Eq. (moments_pres_disc), R(U(F)) = P*F and P*(P*F) = P*F."""
+    B, vg = _rand_basis(1)
+    rng = np.random.default_rng(3)
+    Fd = rng.random((6, 5, 12, 12))
+    dvol = (10.0 / 12) ** 2
+    PF = LM.project_dense(Fd, 2, B, vg, dvol)
+    Mf = HT.dense_moments(Fd, 2, vg, dvol)[:4]
+    Mp = HT.dense_moments(PF, 2, vg, dvol)[:4]
+    assert np.abs(Mf - Mp).max() < 1e-12 * np.abs(Mf).max()
+    PPF = LM.project_dense(PF, 2, B, vg, dvol)
+    assert np.abs(PPF - PF).max() < 1e-12 * np.abs(PF).max()
+    L = [3.0, 4.0]
+    U = LM.conserved_from_raw(Mf, 1.0, L)
+    RU = LM.expand(LM.coefficients(LM.raw_from_conserved(U, 1.0, L), B), B["Q"])
+    assert np.abs(RU - PF).max() < 1e-12 * np.abs(PF).max()
+
+
+def test_gaussian_weight_symmetric_grid():
+    """A Maxwellian weight on a symmetric grid: gamma = beta = 0 and eta is the
+    discrete second moment ratio sum v^2 w / sum w (pure odd/even symmetry)."""
+    v = G.centres(-6, 6, 32)
+    u = np.exp(-0.5 * v * v)
+    g = LM.gram_schmidt_1d(u / np.linalg.norm(u), v, 12 / 32)
+    assert abs(g["gamma"]) < 1e-14 and abs(g["beta"]) < 1e-13
+    assert abs(g["eta"] - np.sum(v * v * u) / np.sum(u)) < 1e-13
+
+
+# ---------------------------------------------------------------- solvers
+def test_fgmres_solves_linear_system():
+    rng = np.random.default_rng(0)
+    A = np.eye(60) + 0.3 * rng.standard_normal((60, 60)) / math.sqrt(60)
+    b = rng.standard_normal(60)
+    x, its = MA.fgmres(lambda v: A @ v, b, 1e-12, restart=20, maxit=400)
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) < 1e-9 * np.linalg.norm(x)
+    # a preconditioner that is the exact inverse converges in one iteration
+    Ainv = np.linalg.inv(A)
+    x2, its2 = MA.fgmres(lambda v: A @ v, b, 1e-10, restart=20, maxit=400, precond=lambda v: Ainv @ v)
+    assert its2 == 1 and np.linalg.norm(x2 - x) < 1e-8 * np.linalg.norm(x)
+
+
+def test_lomac_step_conserves_and_matches_macro_state():
+    """Section 3.2.2-3.2.3 with the spectral identities: U(F^{n+1}) = U^{n+1}
+    and total mass, momentum and energy are conserved to round-off."""
+    p = SI.config("landau2d", n=16).with_(rmax=20, alpha=0.2)
+    o = ST.Oracle(p, probes=SI.probe_indices(256, 256, 64, 7))
+    F = SI.initial_ht(p)
+    U = o.conserved(F)
+    d0 = o.diagnostics(F)
+    Unm1 = None
+    for n in range(2):
+        Fs = o.slar_vp(F, p.dt)
+        F, Unew, info = o.lomac(Fs, U, Unm1, p.dt)
+        assert info["converged"]
+        Unm1, U = U, Unew
+        Uk = o.conserved(F)
+        assert np.abs(Uk - U).max() < 1e-12 * np.abs(U).max()
+    d = o.diagnostics(F)
+    assert abs(d["mass"] - d0["mass"]) < 1e-12 * d0["mass"]
+    assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
+    assert max(abs(m) for m in d["momentum"]) < 1e-12 * d0["mass"]
+
+
+# ---------------------------------------------------------- Landau (P12)
+def _landau_root(k):
+    from scipy.special import wofz
+    from scipy.optimize import fsolve
+
+    def f(z):
+        w = complex(z[0], z[1])
+        zeta = w / (math.sqrt(2) * k)
+        Z = 1j * math.sqrt(math.pi) * wofz(zeta)
+        D = 1 + (1 + zeta * Z) / k ** 2
+        return [D.real, D.imag]
+
+    r = fsolve(f, [1.4, -0.15], xtol=1e-13)
+    return r[0], r[1]
+
+
+def test_linear_landau_rate_1d1v():
+    """Linear Landau damping at k = 0.5: the electric energy envelope decays
+    as exp(2 gamma t) with gamma from the Maxwellian dispersion relation
+    (-0.1533); split 1D1V workload on 64^2."""
+    om, gam = _landau_root(0.5)
+    assert abs(gam + 0.1533) < 1e-3
+    p = SI.config("landau1d").with_(T=15.0)
+    o = ST.Oracle(p)
+    _, hist = o.run(SI.initial_ht(p), 150)
+    ee = np.log([h["elec_energy"] for h in hist])
+    t = np.arange(len(ee)) * p.dt
+    pk = [i for i in range(1, len(ee) - 1) if ee[i] > ee[i - 1] and ee[i] >= ee[i + 1]]
+    slope = np.polyfit(t[pk], ee[pk], 1)[0]
+    assert abs(slope / 2 - gam) < 0.05 * abs(gam), (slope / 2, gam)
+    # oscillation: energy peaks are half a plasma period apart
+    per = np.mean(np.diff(t[pk]))
+    assert abs(per - math.pi / om) < 0.1
