@@ -1,0 +1,234 @@
+/*
+ * slar.h -- C ABI of the MI355X (gfx950) SLAR / LoMaC time-step library.
+ *
+ * One time step of the conservative semi-Lagrangian adaptive-rank method for
+ * Vlasov--Poisson:  SL-FD entry evaluation at the feet of the
+ * characteristics (section 3.1, eq. (tp_interp)), cross approximation of the
+ * updated tensor and its HT truncation (HTACA; introduction, section 3.1,
+ * Supplement B), spectral Poisson solve (section 3.1, eq. (slarvp) and its
+ * field solver), and the adaptive-weight LoMaC projection with its implicit
+ * macroscopic solve (section 3.2, eqs. (LoMaC_update_discrete),
+ * (BE_nonlinear_system)).
+ *
+ * Conventions shared by every entry point
+ *  - All array pointers are DEVICE pointers owned by the caller unless a
+ *    comment says "host".  Arrays are dense, row-major, FP64 unless the
+ *    descriptor's dtype says FP32.  Nothing is freed or retained by the
+ *    library after a call returns, except inside an slar_workspace.
+ *  - Phase space is (x_1..x_dx, v_1..v_dv), dx == dv in {1, 2}.  Grids are
+ *    uniform, cell-centred (x_i = lo + (i + 1/2)(hi - lo)/n) and periodic in
+ *    every coordinate (section 2.1).  Nx = prod n_x, Nv = prod n_v; spatial
+ *    and velocity multi-indices are linearised row-major.
+ *  - Every call returns an slar_status and never aborts.  Arguments are
+ *    validated before anything is enqueued; on SLAR_E_INVAL nothing ran.
+ *  - Calls enqueue on the given HIP stream.  Calls whose control flow
+ *    depends on device data (slar_cross_update, slar_truncate,
+ *    slar_macro_solve) synchronise that stream before returning.
+ *  - A workspace may be used by one stream at a time.
+ */
+#ifndef SLAR_H_
+#define SLAR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SLAR_OK = 0,
+  SLAR_E_INVAL = 1,     /* bad argument; nothing was enqueued             */
+  SLAR_E_NOMEM = 2,     /* device allocation failed / buffer too small     */
+  SLAR_E_RANK_CAP = 3,  /* rank cap reached: output valid but truncated    */
+  SLAR_E_NOCONV = 4,    /* Newton did not reach its tolerance              */
+  SLAR_E_NUMERIC = 5,   /* NaN/Inf met                                     */
+  SLAR_E_HIP = 6        /* a HIP runtime call failed                       */
+} slar_status;
+
+typedef enum { SLAR_F32 = 0, SLAR_F64 = 1 } slar_dtype;
+
+/* Uniform periodic phase-space grid (section 3.1). */
+typedef struct {
+  int32_t dx, dv;       /* 1,1 or 2,2                                      */
+  int32_t n[4];         /* cells per dimension, x first; 2 <= n <= 128      */
+  double lo[4], hi[4];  /* domain [lo, hi) per dimension                    */
+} slar_grid;
+
+/* Hierarchical Tucker tensor on the tree {x}{v} (d = 2, a matrix) or
+ * {{x1,x2},{v1,v2}} (d = 4) (section 3.1; section 4.2 rank labels).
+ *   leaf[m]  : [n_m][rank[m]]            leaf bases U^(m)
+ *   B12, B34 : [rank[0]*rank[1]][rank[4]], [rank[2]*rank[3]][rank[5]]
+ *              transfer tensors, index (a*r_right + b)
+ *   root     : d = 4: [rank[4]][rank[5]];  d = 2: [rank[0]][rank[1]]
+ * F[i1,i2,i3,i4] = sum U1[i1,a] U2[i2,b] B12[a,b,c] root[c,e] U3[i3,p] U4[i4,q] B34[p,q,e]
+ * F[i,j]         = sum Ux[i,a] root[a,b] Uv[j,b]                        (d = 2)
+ * Ranks are host values.  Element type per dtype.                           */
+typedef struct {
+  int32_t d;
+  int32_t rank[6];
+  slar_dtype dtype;
+  void* leaf[4];
+  void* B12;
+  void* B34;
+  void* root;
+} slar_ht;
+
+/* Frame form of a tensor: F[I, J] = sum_c X[I][c] P[J][c], I spatial, J
+ * velocity (linear indices).  X is [Nx][ld], P is [Nv][ld], FP64, columns
+ * 0..r-1 used.  This is the {x}|{v} matricisation with the root folded
+ * into P; it also holds the LoMaC-corrected tensor exactly (the correction
+ * columns are appended, eq. (LoMaC_update_discrete)).                        */
+typedef struct {
+  int32_t r;
+  int32_t ld;
+  double* X;
+  double* P;
+} slar_frames;
+
+/* One linear sub-flow of the SL update (section 3.1 and eq. (slarvp)):
+ * characteristics dx/dt = cv * v, dv/dt = -E(x), traced back over tau.
+ *   kind 0: split x-shift  x* = x - cv v tau                (exact)
+ *   kind 1: split v-shift  v* = v + E(x) tau, E on the grid  (exact)
+ *   kind 2: frozen-field flow, one classical RK4 step backwards in time;
+ *           E between grid points by periodic degree-4 Lagrange interpolation
+ * The frozen field is cE[0]*E[0] + cE[1]*E[1]; E[i] is [dx][Nx] FP64 (E[1]
+ * may be NULL).  order is the interpolation stencil width, 3 or 5.          */
+typedef struct {
+  int32_t kind;
+  int32_t order;
+  double tau;
+  double cv;
+  const double* E[2];
+  double cE[2];
+} slar_adv;
+
+/* Result of the cross approximation: F ~ sum_l U[l][:] (x) V[l][:],
+ * U is [kmax][Nx], V is [kmax][Nv] (FP64, caller-owned, written).           */
+typedef struct {
+  int32_t k;
+  double* U;
+  double* V;
+} slar_lowrank;
+
+typedef struct {
+  int32_t rank;          /* cross rank k                                    */
+  int32_t iterations;    /* pivot rows visited                              */
+  int32_t probe_rounds;  /* continuations forced by the random probes       */
+  int32_t converged;
+  int64_t samples;       /* SL-FD entries evaluated                         */
+} slar_cross_info;
+
+typedef struct slar_workspace slar_workspace;
+
+const char* slar_status_str(slar_status s);
+
+/* Allocates every device buffer the calls below need for grid g and rank
+ * cap rmax (<= 64), once.  *ws is written on success.                       */
+slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspace** ws);
+slar_status slar_workspace_destroy(slar_workspace* ws);
+
+/* SL-FD update at requested grid points, evaluated directly on an HT tensor
+ * by the leaf interpolation c^(mu) = w(xi_mu) U^(mu)_{J_mu} and the transfer
+ * contractions up to the root, O(d r^3) per point (section 3.1, eqs.
+ * (1d_quadratic_interp_weight), (tp_interp)).
+ *   idx : [n][d] int32 grid multi-indices (0-based) of the points to update
+ *   out : [n] values f(x_i, t+tau) = f(x*, t), dtype of F (FP32 contracts
+ *         on the matrix cores with FP32 accumulation; feet are FP64).
+ * Supports order 3 and 5 for d = 2, order 3 for d = 4; ranks <= 64.          */
+slar_status slar_ht_sample(const slar_grid* g, const slar_ht* F, const slar_adv* a, int64_t n,
+                           const int32_t* idx, void* out, hipStream_t stream);
+
+/* Frame form of an HT tensor (the x node frame (U1 (x) U2) B12 and the v
+ * node frame times root^T).  out->X, out->P must have ld >= rank[4]
+ * (d = 4) or rank[0] (d = 2) columns; out->r is written.                    */
+slar_status slar_frames_from_ht(const slar_grid* g, const slar_ht* F, slar_frames* out,
+                                slar_workspace* ws, hipStream_t stream);
+
+/* The same SL-FD update evaluated from the frame form: stencil-weighted
+ * gathers of the node frames (mathematically eq. (tp_interp) of the same
+ * tensor).  dtype selects FP64 tables or FP32 copies made in ws.            */
+slar_status slar_frame_sample(const slar_grid* g, const slar_frames* F, const slar_adv* a,
+                              slar_dtype dtype, int64_t n, const int32_t* idx, double* out,
+                              slar_workspace* ws, hipStream_t stream);
+
+/* SLAR(F; a, dt, eps_Base) sampling stage (section 3.1; HTACA, introduction):
+ * adaptive cross approximation with partial pivoting of the updated tensor
+ * in its {x}|{v} matricisation, sampling whole fibers through the SL-FD
+ * evaluator.  Pivot rules: first row 0; column pivot = lowest index within a
+ * relative 1e-10 of the residual maximum; stop when |u_k||v_k| <= tol
+ * ||S_k||_F or k == kmax; on stopping, nprobe host-given random entries
+ * probes[nprobe][2] (row, col; device int32) are checked and the
+ * approximation continues from the worst one if its residual exceeds
+ * tol ||S_k||_F / sqrt(Nx Nv).  dtype is the precision of the sampled
+ * tables.  Returns SLAR_E_RANK_CAP when kmax was hit before convergence.  */
+slar_status slar_cross_update(const slar_grid* g, const slar_frames* src, const slar_adv* a,
+                              slar_dtype dtype, double tol, int32_t kmax, int32_t nprobe,
+                              const int32_t* probes, slar_lowrank* out, slar_cross_info* info,
+                              slar_workspace* ws, hipStream_t stream);
+
+/* HTACA's final truncation (Supplement B): orthogonalise both factor sets,
+ * SVD of the small core, root truncation with theta = tol ||F||_F /
+ * sqrt(2d-3), then (d = 4) each leaf = leading left singular vectors of its
+ * mode matricisation (same theta), transfer tensors by projection.  Column 0
+ * of each leaf is the leading left singular vector of its mode.  out must
+ * point to FP64 buffers sized for rmax in every rank; out->rank is written.
+ * Returns SLAR_E_RANK_CAP if some rank was capped at rmax.                  */
+slar_status slar_truncate(const slar_grid* g, const slar_lowrank* in, double tol, int32_t rmax,
+                          slar_ht* out, slar_workspace* ws, hipStream_t stream);
+
+/* Velocity moments on the x-grid (eqs. (raw moments), (disc_m0)-(disc_m2) and
+ * the flux moments of eq. (macro_sys_comp)): M is [nmom][Nx] with rows
+ * 1, v_1..v_dv, |v|^2, v_mu v_nu (mu <= nu), |v|^2 v_mu
+ * (nmom = 5 for dv = 1, 9 for dv = 2).                                      */
+slar_status slar_moments(const slar_grid* g, const slar_frames* F, double* M,
+                         slar_workspace* ws, hipStream_t stream);
+
+/* Spectral Poisson solve (eqs. (Poisson), (Efromphi), (charge_density)):
+ * rho = n_i - n_e, -D.D phi = rho on the non-null Fourier modes (phi = 0 on
+ * the null ones), E = -D phi, D the spectral derivative with the Nyquist
+ * mode set to 0.  n_e, phi are [Nx]; E is [dx][Nx].  phi may be NULL.       */
+slar_status slar_poisson(const slar_grid* g, const double* n_e, double n_i, double* phi,
+                         double* E, slar_workspace* ws, hipStream_t stream);
+
+/* Conserved variables U = (n, m n u, e_k + e_p) of a tensor ([dv+2][Nx]),
+ * eq. (macro_sys_comp) with m_e = 1.                                        */
+slar_status slar_conserved(const slar_grid* g, const slar_frames* F, double n_i, double* U,
+                           slar_workspace* ws, hipStream_t stream);
+
+/* LoMaC closure of F* (Supplement B): the weight omega^(mu) = max(|U^(v_mu)[:,0]|,
+ * delta) from column 0 of the velocity leaves of the truncated F*, the
+ * weighted Gram--Schmidt basis Q_0, Q_{1,mu}, Q_2 and norms, the moments of
+ * F* and its projection coefficients.  Kept in ws for the two calls below.  */
+slar_status slar_lomac_prepare(const slar_grid* g, const slar_ht* Fstar,
+                               const slar_frames* Fstar_frames, double delta, double n_i,
+                               slar_workspace* ws, hipStream_t stream);
+
+/* Implicit macroscopic update (section 3.2.3): solves
+ *   G(U) = U - U_hist + b dt (D.F(U) - S(U)) = 0
+ * (bdf_order 1: backward Euler, U_hist = U_n, b = 1; 2: BDF2,
+ * U_hist = 4/3 U_n - 1/3 U_nm1, b = 2/3) by Jacobian-free Newton--GMRES
+ * started from U(F*).  The flux is closed by the corrected kinetic state of
+ * the prepared LoMaC closure.  cnn: NULL for plain GMRES, else a
+ * preconditioner made by slar_cnn_create (flexible GMRES).  iters (host,
+ * int32[2]) receives the Newton and Krylov iteration counts.
+ * Returns SLAR_E_NOCONV if Newton did not reach newton_tol.                 */
+typedef struct slar_cnn slar_cnn;
+slar_status slar_macro_solve(const slar_grid* g, const double* U_n, const double* U_nm1,
+                             double dt, int32_t bdf_order, double newton_tol, double krylov_tol,
+                             const slar_cnn* cnn, double* U_out, int32_t* iters,
+                             slar_workspace* ws, hipStream_t stream);
+
+/* LoMaC update eq. (LoMaC_update_discrete):
+ *   F^{n+1} = F* - R(U(F*)) + R(U_new) = F* + sum_k dC_k (x) Q_k,
+ * returned exactly (no re-truncation) in frame form: out->X = [X* | dC],
+ * out->P = [P* | Q]; out->ld >= Fstar_frames->r + dv + 2.                   */
+slar_status slar_lomac_project(const slar_grid* g, const slar_frames* Fstar_frames,
+                               const double* U_new, slar_frames* out, slar_workspace* ws,
+                               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLAR_H_ */

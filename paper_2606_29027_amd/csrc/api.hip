@@ -1,0 +1,306 @@
+// C ABI entry points: argument validation, workspace management and the
+// host-side orchestration of the kernels in the other translation units.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "slar_internal.h"
+#include "dense.h"
+#include "fields.h"
+#include "lomac.h"
+
+namespace slar {
+hipError_t ht_sample(hipStream_t st, const GridDev& G, const AdvDev& A, const slar_ht& F,
+                     long long n, const int* idx, void* out);
+hipError_t frames_from_ht(hipStream_t s, Workspace* ws, const GridDev& G, const slar_ht& F,
+                          slar_frames* out);
+hipError_t table_copy(hipStream_t s, int rows, int r, int ldin, const double* in, int ldo,
+                      float* o32, double* o64);
+hipError_t frame_points(hipStream_t s, const GridDev& G, const AdvDev& A, slar_dtype dt,
+                        const void* X, const void* P, int ld, int r, long long n, const int* idx,
+                        double* out);
+slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, const slar_adv& adv,
+                      slar_dtype dt, double tol, int kmax, int nprobe, const int* probes,
+                      slar_lowrank* out, slar_cross_info* info);
+slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, double tol,
+                         int rmax, slar_ht* out);
+size_t aca_ctl_bytes();
+size_t truncate_scratch_elems(const GridDev& G);
+}  // namespace slar
+
+using namespace slar;
+
+static bool grid_ok(const slar_grid* g) {
+  if (!g) return false;
+  if (g->dx != g->dv || (g->dx != 1 && g->dx != 2)) return false;
+  for (int m = 0; m < g->dx + g->dv; ++m) {
+    if (g->n[m] < 4 || g->n[m] > SLAR_NMAX) return false;
+    if (!(g->hi[m] > g->lo[m]) || !std::isfinite(g->lo[m]) || !std::isfinite(g->hi[m])) return false;
+  }
+  return true;
+}
+
+static bool same_grid(const slar_grid* a, const slar_grid* b) {
+  if (a->dx != b->dx || a->dv != b->dv) return false;
+  for (int m = 0; m < a->dx + a->dv; ++m)
+    if (a->n[m] != b->n[m] || a->lo[m] != b->lo[m] || a->hi[m] != b->hi[m]) return false;
+  return true;
+}
+
+static bool adv_ok(const slar_grid* g, const slar_adv* a) {
+  if (!a) return false;
+  if (a->kind < 0 || a->kind > 2) return false;
+  if (a->order != 3 && a->order != 5) return false;
+  if (!std::isfinite(a->tau) || !std::isfinite(a->cv)) return false;
+  if (a->kind != 0 && a->E[0] == nullptr) return false;
+  if (g->dx == 2 && a->order != 3) return false;
+  return true;
+}
+
+static bool ht_ok(const slar_grid* g, const slar_ht* F) {
+  if (!F || F->d != g->dx + g->dv) return false;
+  const int nr = F->d == 2 ? 2 : 6;
+  for (int m = 0; m < nr; ++m)
+    if (F->rank[m] < 1 || F->rank[m] > 64) return false;
+  for (int m = 0; m < F->d; ++m)
+    if (!F->leaf[m]) return false;
+  if (!F->root) return false;
+  if (F->d == 4 && (!F->B12 || !F->B34)) return false;
+  if (F->dtype != SLAR_F32 && F->dtype != SLAR_F64) return false;
+  return true;
+}
+
+static bool frames_ok(const slar_frames* F) {
+  return F && F->X && F->P && F->r >= 1 && F->r <= SLAR_KMAX && F->ld >= F->r;
+}
+
+static AdvDev make_adv(const slar_adv* a, const double* Eeff) {
+  return AdvDev{a->kind, a->order, a->tau, a->cv, Eeff, nullptr, 1.0, 0.0};
+}
+
+extern "C" {
+
+const char* slar_status_str(slar_status s) {
+  switch (s) {
+    case SLAR_OK: return "ok";
+    case SLAR_E_INVAL: return "invalid argument";
+    case SLAR_E_NOMEM: return "out of device memory";
+    case SLAR_E_RANK_CAP: return "rank cap reached";
+    case SLAR_E_NOCONV: return "Newton did not converge";
+    case SLAR_E_NUMERIC: return "non-finite value";
+    case SLAR_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+slar_status slar_workspace_destroy(slar_workspace* w) {
+  if (!w) return SLAR_OK;
+  Workspace& ws = w->w;
+  void* dev[] = {ws.Eeff, ws.X32, ws.P32, ws.aca_ctl, ws.aca_part, ws.used, ws.resid, ws.dwork,
+                 ws.small, ws.ismall, ws.tw[0], ws.tw[1], ws.cbuf, ws.psi, ws.lm, ws.kry};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (ws.aca_ctl_host) (void)hipHostFree(ws.aca_ctl_host);
+  if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
+  delete w;
+  return SLAR_OK;
+}
+
+slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspace** out) {
+  if (!out || !grid_ok(g) || rmax < 1 || rmax > 64) return SLAR_E_INVAL;
+  *out = nullptr;
+  slar_workspace* w = new (std::nothrow) slar_workspace();
+  if (!w) return SLAR_E_NOMEM;
+  Workspace& ws = w->w;
+  ws.grid = *g;
+  ws.G = make_grid(*g);
+  ws.rmax = rmax;
+  const GridDev& G = ws.G;
+  const size_t K = SLAR_KMAX;
+  ws.ld32 = SLAR_KMAX;
+  ws.dwork_elems = std::max({(size_t)2 * (G.nx + G.nv) * K + 64,
+                             (size_t)SLAR_NMAX * K * K + (size_t)G.nv * K + 64,
+                             (size_t)SLAR_NMAX * SLAR_NMAX * SLAR_NMAX + 64,
+                             (size_t)(G.nx / 256 + 2) * K * 9 + (size_t)(G.nx / 512 + 2) * K * K,
+                             (size_t)(SLAR_NMAX * K / 512 + 2) * SLAR_NMAX * SLAR_NMAX});
+  ws.small_elems = truncate_scratch_elems(G) + 8192;
+  ws.cbuf_elems = cbuf_elems_for(G.nx);
+  const int nm = nmom_of(G.dv);
+  const LmLayout L = lm_layout(G);
+  ws.lm_elems = L.total;
+  ws.kry_elems = kry_elems_for(G.nx, G.dv + 2, KRY_RESTART);
+  bool ok = true;
+  auto dalloc = [&](void** p, size_t bytes) {
+    if (!ok) return;
+    if (hipMalloc(p, std::max(bytes, (size_t)256)) != hipSuccess) ok = false;
+  };
+  dalloc((void**)&ws.Eeff, sizeof(double) * G.dx * G.nx);
+  dalloc((void**)&ws.X32, sizeof(float) * G.nx * ws.ld32);
+  dalloc((void**)&ws.P32, sizeof(float) * G.nv * ws.ld32);
+  dalloc(&ws.aca_ctl, aca_ctl_bytes());
+  dalloc((void**)&ws.aca_part, sizeof(double) * (K + 4) * 1024);
+  dalloc((void**)&ws.used, G.nx);
+  dalloc((void**)&ws.dwork, sizeof(double) * ws.dwork_elems);
+  dalloc((void**)&ws.small, sizeof(double) * ws.small_elems);
+  dalloc((void**)&ws.tw[0], sizeof(double) * 2 * SLAR_NMAX);
+  dalloc((void**)&ws.tw[1], sizeof(double) * 2 * SLAR_NMAX);
+  dalloc((void**)&ws.cbuf, sizeof(double) * ws.cbuf_elems);
+  dalloc((void**)&ws.psi, sizeof(double) * G.nv * nm);
+  dalloc((void**)&ws.lm, sizeof(double) * ws.lm_elems);
+  dalloc((void**)&ws.kry, sizeof(double) * ws.kry_elems);
+  if (ok && hipHostMalloc(&ws.aca_ctl_host, aca_ctl_bytes(), 0) != hipSuccess) ok = false;
+  if (ok && hipHostMalloc(&ws.host_pinned, 65536, 0) != hipSuccess) ok = false;
+  if (!ok) {
+    slar_workspace_destroy(w);
+    return SLAR_E_NOMEM;
+  }
+  std::vector<double> tw;
+  for (int m = 0; m < G.dx; ++m) {
+    host_twiddles(G.n[m], tw);
+    if (hipMemcpy(ws.tw[m], tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      slar_workspace_destroy(w);
+      return SLAR_E_HIP;
+    }
+  }
+  if (psi_build(0, &ws) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    slar_workspace_destroy(w);
+    return SLAR_E_HIP;
+  }
+  *out = w;
+  return SLAR_OK;
+}
+
+slar_status slar_ht_sample(const slar_grid* g, const slar_ht* F, const slar_adv* a, int64_t n,
+                           const int32_t* idx, void* out, hipStream_t stream) {
+  if (!grid_ok(g) || !ht_ok(g, F) || !adv_ok(g, a) || n < 0) return SLAR_E_INVAL;
+  if (n > 0 && (!idx || !out)) return SLAR_E_INVAL;
+  if (a->kind == 2 && a->E[0] == nullptr) return SLAR_E_INVAL;
+  if (F->d == 4 && a->order != 3) return SLAR_E_INVAL;
+  if (n == 0) return SLAR_OK;
+  GridDev G = make_grid(*g);
+  // the two frozen fields are combined node by node inside the kernel
+  AdvDev A{a->kind, a->order, a->tau, a->cv, a->E[0], a->E[1], a->cE[0], a->cE[1]};
+  hipError_t e = ht_sample(stream, G, A, *F, n, idx, out);
+  return e == hipSuccess ? SLAR_OK : SLAR_E_HIP;
+}
+
+slar_status slar_frames_from_ht(const slar_grid* g, const slar_ht* F, slar_frames* out,
+                                slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !ht_ok(g, F) || !out || !out->X || !out->P)
+    return SLAR_E_INVAL;
+  if (F->dtype != SLAR_F64) return SLAR_E_INVAL;
+  const int need = F->d == 2 ? F->rank[0] : F->rank[4];
+  if (out->ld < need) return SLAR_E_INVAL;
+  return frames_from_ht(stream, &w->w, w->w.G, *F, out) == hipSuccess ? SLAR_OK : SLAR_E_HIP;
+}
+
+slar_status slar_frame_sample(const slar_grid* g, const slar_frames* F, const slar_adv* a,
+                              slar_dtype dtype, int64_t n, const int32_t* idx, double* out,
+                              slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !frames_ok(F) || !adv_ok(g, a) || n < 0)
+    return SLAR_E_INVAL;
+  if (dtype != SLAR_F32 && dtype != SLAR_F64) return SLAR_E_INVAL;
+  if (n > 0 && (!idx || !out)) return SLAR_E_INVAL;
+  if (n == 0) return SLAR_OK;
+  Workspace& ws = w->w;
+  const GridDev& G = ws.G;
+  const int ldt = (F->r + 3) & ~3;
+  if (combine_field(stream, G, a, ws.Eeff) != hipSuccess) return SLAR_E_HIP;
+  AdvDev A = make_adv(a, ws.Eeff);
+  const void *X, *P;
+  if (dtype == SLAR_F32) {
+    if (table_copy(stream, G.nx, F->r, F->ld, F->X, ldt, ws.X32, nullptr) != hipSuccess) return SLAR_E_HIP;
+    if (table_copy(stream, G.nv, F->r, F->ld, F->P, ldt, ws.P32, nullptr) != hipSuccess) return SLAR_E_HIP;
+    X = ws.X32; P = ws.P32;
+  } else {
+    double* X64 = ws.dwork;
+    double* P64 = ws.dwork + (size_t)G.nx * ldt;
+    if (table_copy(stream, G.nx, F->r, F->ld, F->X, ldt, nullptr, X64) != hipSuccess) return SLAR_E_HIP;
+    if (table_copy(stream, G.nv, F->r, F->ld, F->P, ldt, nullptr, P64) != hipSuccess) return SLAR_E_HIP;
+    X = X64; P = P64;
+  }
+  return frame_points(stream, G, A, dtype, X, P, ldt, F->r, n, idx, out) == hipSuccess ? SLAR_OK
+                                                                                        : SLAR_E_HIP;
+}
+
+slar_status slar_cross_update(const slar_grid* g, const slar_frames* src, const slar_adv* a,
+                              slar_dtype dtype, double tol, int32_t kmax, int32_t nprobe,
+                              const int32_t* probes, slar_lowrank* out, slar_cross_info* info,
+                              slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !frames_ok(src) || !adv_ok(g, a))
+    return SLAR_E_INVAL;
+  if (!(tol > 0.0) || kmax < 1 || kmax > 64 || nprobe < 0 || nprobe > 1024) return SLAR_E_INVAL;
+  if (nprobe > 0 && !probes) return SLAR_E_INVAL;
+  if (!out || !out->U || !out->V) return SLAR_E_INVAL;
+  if (dtype != SLAR_F32 && dtype != SLAR_F64) return SLAR_E_INVAL;
+  return cross_run(stream, &w->w, *src, *a, dtype, tol, kmax, nprobe, probes, out, info);
+}
+
+slar_status slar_truncate(const slar_grid* g, const slar_lowrank* in, double tol, int32_t rmax,
+                          slar_ht* out, slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !in || !in->U || !in->V) return SLAR_E_INVAL;
+  if (in->k < 1 || in->k > 64 || !(tol > 0.0) || rmax < 1 || rmax > 64 || !out) return SLAR_E_INVAL;
+  const int d = g->dx + g->dv;
+  for (int m = 0; m < d; ++m)
+    if (!out->leaf[m]) return SLAR_E_INVAL;
+  if (!out->root || (d == 4 && (!out->B12 || !out->B34))) return SLAR_E_INVAL;
+  return truncate_run(stream, &w->w, *in, tol, rmax, out);
+}
+
+slar_status slar_moments(const slar_grid* g, const slar_frames* F, double* M, slar_workspace* w,
+                         hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !frames_ok(F) || !M) return SLAR_E_INVAL;
+  return moments_run(stream, &w->w, *F, M) == hipSuccess ? SLAR_OK : SLAR_E_HIP;
+}
+
+slar_status slar_poisson(const slar_grid* g, const double* n_e, double n_i, double* phi, double* E,
+                         slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !n_e || !E || !std::isfinite(n_i))
+    return SLAR_E_INVAL;
+  return poisson_run(stream, &w->w, n_e, n_i, phi, E) == hipSuccess ? SLAR_OK : SLAR_E_HIP;
+}
+
+slar_status slar_conserved(const slar_grid* g, const slar_frames* F, double n_i, double* U,
+                           slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !frames_ok(F) || !U) return SLAR_E_INVAL;
+  Workspace& ws = w->w;
+  // moments into the Krylov scratch (free outside slar_macro_solve)
+  double* Mtmp = ws.kry;
+  if (moments_run(stream, &ws, *F, Mtmp) != hipSuccess) return SLAR_E_HIP;
+  return conserved_from_moments(stream, &ws, Mtmp, n_i, U) == hipSuccess ? SLAR_OK : SLAR_E_HIP;
+}
+
+slar_status slar_lomac_prepare(const slar_grid* g, const slar_ht* Fstar,
+                               const slar_frames* Fstar_frames, double delta, double n_i,
+                               slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !ht_ok(g, Fstar) || !frames_ok(Fstar_frames))
+    return SLAR_E_INVAL;
+  if (Fstar->dtype != SLAR_F64 || !(delta > 0.0) || !std::isfinite(n_i)) return SLAR_E_INVAL;
+  return lomac_prepare_run(stream, &w->w, *Fstar, *Fstar_frames, delta, n_i);
+}
+
+slar_status slar_macro_solve(const slar_grid* g, const double* U_n, const double* U_nm1,
+                             double dt, int32_t bdf_order, double newton_tol, double krylov_tol,
+                             const slar_cnn* cnn, double* U_out, int32_t* iters,
+                             slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !U_n || !U_out) return SLAR_E_INVAL;
+  if (!(dt > 0.0) || (bdf_order != 1 && bdf_order != 2) || !(newton_tol > 0.0) ||
+      !(krylov_tol > 0.0 && krylov_tol < 1.0))
+    return SLAR_E_INVAL;
+  if (bdf_order == 2 && !U_nm1) return SLAR_E_INVAL;
+  return macro_solve_run(stream, &w->w, U_n, U_nm1, dt, bdf_order, newton_tol, krylov_tol, cnn,
+                         U_out, iters);
+}
+
+slar_status slar_lomac_project(const slar_grid* g, const slar_frames* Fstar_frames,
+                               const double* U_new, slar_frames* out, slar_workspace* w,
+                               hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !frames_ok(Fstar_frames) || !U_new || !out ||
+      !out->X || !out->P)
+    return SLAR_E_INVAL;
+  if (out->ld < Fstar_frames->r + g->dv + 2 || Fstar_frames->r + g->dv + 2 > SLAR_KMAX) return SLAR_E_INVAL;
+  return lomac_project_run(stream, &w->w, *Fstar_frames, U_new, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,14 @@
+// Dense FP64 helpers shared by the truncation, LoMaC and Krylov code.
+#pragma once
+#include "slar_internal.h"
+
+namespace slar {
+hipError_t gram_rows(hipStream_t s, Workspace* ws, int k, int n, const double* A, int lda, double* G);
+hipError_t chol_inv(hipStream_t s, int k, const double* G, double* Linv, double* R, const double* Rprev);
+hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z);
+hipError_t eig_sym(hipStream_t s, int n, const double* G, double* lam, double* Vwork, double* V);
+hipError_t sign_fix(hipStream_t s, int rows, int cols, double* A, int lda, double* B, int ldb, int rowsB);
+hipError_t copy2d(hipStream_t s, int rows, int cols, const double* A, int lda, double* B, int ldb,
+                  const double* colscale);
+hipError_t fill(hipStream_t s, double* p, long long n, double v);
+}  // namespace slar

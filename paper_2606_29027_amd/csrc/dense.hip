@@ -1,0 +1,479 @@
+// Small dense FP64 linear algebra for the truncation: tiled GEMM (optionally
+// summed over a batch in a fixed order), Cholesky-QR helpers, one-sided
+// Jacobi SVD and two-sided Jacobi symmetric eigensolver.  All single-block
+// factorizations keep their matrix in LDS (gfx950: 160 KB per CU).
+#include "slar_internal.h"
+#include "dense.h"
+
+namespace slar {
+
+// ------------------------------------------------------------------ GEMM
+// C_b = alpha op(A_b) op(B_b) + beta C_b, row-major.  64x64 tile, BK = 16,
+// 256 threads, 4x4 outputs per thread.
+constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+
+__global__ __launch_bounds__(256) void k_gemm(bool ta, bool tb, int M, int N, int K, double alpha,
+                                              const double* __restrict__ A, int lda, long long sA,
+                                              const double* __restrict__ B, int ldb, long long sB,
+                                              double beta, double* __restrict__ C, int ldc,
+                                              long long sC) {
+  __shared__ double As[GB_K][GB_M + 1];
+  __shared__ double Bs[GB_K][GB_N + 1];
+  const int b = blockIdx.z;
+  A += sA * b; B += sB * b; C += sC * b;
+  const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
+  const int tid = threadIdx.x;
+  const int tr = tid / 16, tc = tid % 16;   // 16x16 thread grid, 4x4 each
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += GB_K) {
+    // load A tile (GB_M x GB_K) -> As[k][m]
+    for (int e = tid; e < GB_M * GB_K; e += 256) {
+      int mm, kk;
+      if (!ta) { mm = e / GB_K; kk = e % GB_K; } else { kk = e / GB_M; mm = e % GB_M; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < M && gk < K) v = ta ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
+      As[kk][mm] = v;
+    }
+    for (int e = tid; e < GB_N * GB_K; e += 256) {
+      int nn, kk;
+      if (!tb) { kk = e / GB_N; nn = e % GB_N; } else { nn = e / GB_K; kk = e % GB_K; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      double v = 0.0;
+      if (gn < N && gk < K) v = tb ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GB_K; ++kk) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + tr + 16 * i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + tc + 16 * j;
+      if (gn >= N) continue;
+      double* c = C + (long long)gm * ldc + gn;
+      *c = (beta == 0.0) ? alpha * acc[i][j] : alpha * acc[i][j] + beta * (*c);
+    }
+  }
+}
+
+hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+                    const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
+                    double beta, double* C, int ldc, long long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
+  k_gemm<<<grid, 256, 0, s>>>(ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  return hipGetLastError();
+}
+
+__global__ void k_sum_batches(const double* __restrict__ P, int M, int N, int batch,
+                              double* __restrict__ C, int ldc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  double acc = 0.0;
+  for (int b = 0; b < batch; ++b) acc += P[(long long)b * M * N + e];
+  C[(long long)(e / N) * ldc + (e % N)] = acc;
+}
+
+hipError_t gemm_f64_sumbatch(hipStream_t s, Workspace* ws, bool ta, bool tb, int M, int N, int K,
+                             const double* A, int lda, long long sA, const double* B, int ldb,
+                             long long sB, double* C, int ldc, int batch) {
+  const size_t need = (size_t)batch * M * N;
+  if (need > ws->dwork_elems) return hipErrorInvalidValue;
+  hipError_t e = gemm_f64(s, ta, tb, M, N, K, 1.0, A, lda, sA, B, ldb, sB, 0.0, ws->dwork, N,
+                          (long long)M * N, batch);
+  if (e != hipSuccess) return e;
+  k_sum_batches<<<(M * N + 255) / 256, 256, 0, s>>>(ws->dwork, M, N, batch, C, ldc);
+  return hipGetLastError();
+}
+
+// Gram G = A A^T for A = [k][n] row vectors (long n), split over n.
+hipError_t gram_rows(hipStream_t s, Workspace* ws, int k, int n, const double* A, int lda,
+                     double* G) {
+  int chunk = 512;
+  int batch = (n + chunk - 1) / chunk;
+  while ((size_t)batch * k * k > ws->dwork_elems && chunk < n) { chunk *= 2; batch = (n + chunk - 1) / chunk; }
+  if (batch * chunk != n) {
+    // ragged tail: sum the full chunks, then add the tail block
+    const int full = n / chunk;
+    const int tail = n - full * chunk;
+    if (full > 0) {
+      hipError_t e = gemm_f64_sumbatch(s, ws, false, true, k, k, chunk, A, lda, chunk, A, lda,
+                                       chunk, G, k, full);
+      if (e != hipSuccess) return e;
+    }
+    return gemm_f64(s, false, true, k, k, tail, 1.0, A + (long long)full * chunk, lda, 0,
+                    A + (long long)full * chunk, lda, 0, full > 0 ? 1.0 : 0.0, G, k, 0, 1);
+  }
+  return gemm_f64_sumbatch(s, ws, false, true, k, k, chunk, A, lda, chunk, A, lda, chunk, G, k,
+                           batch);
+}
+
+// --------------------------------------------------- Cholesky-QR helpers
+// From Gram G (k x k): column scaling d = sqrt(diag G), Cholesky of
+// D^-1 G D^-1 = L L^T.  Writes Linv_scaled = L^-1 D^-1 (k x k, lower) and
+// R = L^T D (upper).  A zero column keeps d = 1 and a unit pivot.
+__global__ void k_chol_inv(int k, const double* __restrict__ G, double* __restrict__ Linv,
+                           double* __restrict__ R, const double* __restrict__ Rprev) {
+  __shared__ double L[SLAR_KMAX][SLAR_KMAX + 1];
+  __shared__ double Li[SLAR_KMAX][SLAR_KMAX + 1];
+  __shared__ double d[SLAR_KMAX];
+  const int t = threadIdx.x;
+  for (int i = t; i < k; i += blockDim.x) {
+    const double g = G[i * k + i];
+    d[i] = g > 0.0 ? sqrt(g) : 1.0;
+  }
+  __syncthreads();
+  for (int e = t; e < k * k; e += blockDim.x) {
+    const int i = e / k, j = e % k;
+    L[i][j] = G[e] / (d[i] * d[j]);
+  }
+  __syncthreads();
+  // right-looking Cholesky (lower)
+  for (int c = 0; c < k; ++c) {
+    if (t == 0) {
+      double v = L[c][c];
+      L[c][c] = v > 1e-300 ? sqrt(v) : 1.0;
+    }
+    __syncthreads();
+    for (int i = c + 1 + t; i < k; i += blockDim.x) L[i][c] /= L[c][c];
+    __syncthreads();
+    for (int e = t; e < (k - c - 1) * (k - c - 1); e += blockDim.x) {
+      const int i = c + 1 + e / (k - c - 1), j = c + 1 + e % (k - c - 1);
+      if (j <= i) L[i][j] -= L[i][c] * L[j][c];
+    }
+    __syncthreads();
+  }
+  // inverse of lower triangular L, column by column (independent columns)
+  for (int j = t; j < k; j += blockDim.x) {
+    for (int i = 0; i < k; ++i) Li[i][j] = 0.0;
+    Li[j][j] = 1.0 / L[j][j];
+    for (int i = j + 1; i < k; ++i) {
+      double acc = 0.0;
+      for (int m = j; m < i; ++m) acc += L[i][m] * Li[m][j];
+      Li[i][j] = -acc / L[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < k * k; e += blockDim.x) {
+    const int i = e / k, j = e % k;
+    Linv[e] = Li[i][j] / d[j];
+    // R = L^T D (upper), optionally times Rprev (R_total = R * Rprev)
+    double r = (i <= j) ? L[j][i] * d[j] : 0.0;
+    if (Rprev == nullptr) R[e] = r;
+  }
+  if (Rprev != nullptr) {
+    __syncthreads();
+    for (int e = t; e < k * k; e += blockDim.x) {
+      const int i = e / k, j = e % k;
+      double acc = 0.0;
+      for (int m = i; m < k; ++m) acc += L[m][i] * d[m] * Rprev[m * k + j];
+      R[e] = acc;
+    }
+  }
+}
+
+hipError_t chol_inv(hipStream_t s, int k, const double* G, double* Linv, double* R,
+                    const double* Rprev) {
+  k_chol_inv<<<1, 256, 0, s>>>(k, G, Linv, R, Rprev);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- one-sided Jacobi SVD
+// M (k x k, row-major) = W diag(s) Z^T, s descending.  Outputs W, Z as
+// row-major k x k (columns are singular vectors).
+__global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restrict__ Min,
+                                                    double* __restrict__ W, double* __restrict__ sv,
+                                                    double* __restrict__ Z) {
+  __shared__ double A[SLAR_KMAX][SLAR_KMAX + 1];   // A[row][col]
+  __shared__ double V[SLAR_KMAX][SLAR_KMAX + 1];
+  __shared__ int pairs[SLAR_KMAX];
+  __shared__ int rotated;
+  __shared__ double nrm[SLAR_KMAX];
+  __shared__ int order[SLAR_KMAX];
+  const int t = threadIdx.x;
+  const int kp = (k + 1) & ~1;   // even count (a zero column pads odd k)
+  for (int e = t; e < kp * kp; e += blockDim.x) {
+    const int i = e / kp, j = e % kp;
+    A[i][j] = (i < k && j < k) ? Min[i * k + j] : 0.0;
+    V[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int i = t; i < kp; i += blockDim.x) pairs[i] = i;
+  __syncthreads();
+  const int npair = kp / 2;
+  const int team = (npair > 0) ? max(1, min(32, 256 / npair)) : 1;  // power of 2 below
+  int tm = 1;
+  while (tm * 2 <= team) tm *= 2;
+  const int pid = t / tm, lane = t % tm;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (t == 0) rotated = 0;
+    __syncthreads();
+    for (int step = 0; step < kp - 1; ++step) {
+      if (pid < npair) {
+        const int p = pairs[2 * pid], q = pairs[2 * pid + 1];
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int r = lane; r < kp; r += tm) {
+          const double x = A[r][p], y = A[r][q];
+          al += x * x; be += y * y; ga += x * y;
+        }
+        for (int o = tm / 2; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, tm);
+          be += __shfl_xor(be, o, tm);
+          ga += __shfl_xor(ga, o, tm);
+        }
+        if (fabs(ga) > 1e-15 * sqrt(al * be) && ga != 0.0) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+          for (int r = lane; r < kp; r += tm) {
+            const double x = A[r][p], y = A[r][q];
+            A[r][p] = c * x - sn * y;
+            A[r][q] = sn * x + c * y;
+            const double vx = V[r][p], vy = V[r][q];
+            V[r][p] = c * vx - sn * vy;
+            V[r][q] = sn * vx + c * vy;
+          }
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+      // round-robin rotation of the pairing (position 0 fixed)
+      if (t == 0) {
+        const int last = pairs[kp - 1];
+        for (int i = kp - 1; i > 1; --i) pairs[i] = pairs[i - 1];
+        pairs[1] = last;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int c = t; c < kp; c += blockDim.x) {
+    double acc = 0.0;
+    for (int r = 0; r < kp; ++r) acc += A[r][c] * A[r][c];
+    nrm[c] = sqrt(acc);
+  }
+  __syncthreads();
+  // descending order, ties by index
+  for (int c = t; c < kp; c += blockDim.x) {
+    int rank = 0;
+    for (int o = 0; o < kp; ++o)
+      if (nrm[o] > nrm[c] || (nrm[o] == nrm[c] && o < c)) ++rank;
+    order[rank] = c;
+  }
+  __syncthreads();
+  for (int e = t; e < k * k; e += blockDim.x) {
+    const int r = e / k, j = e % k;
+    const int c = order[j];
+    W[e] = nrm[c] > 0.0 ? A[r][c] / nrm[c] : (r == j ? 1.0 : 0.0);
+    Z[e] = V[r][c];
+  }
+  for (int j = t; j < k; j += blockDim.x) sv[j] = nrm[order[j]];
+}
+
+hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z) {
+  k_svd_jacobi<<<1, 256, 0, s>>>(k, M, W, sv, Z);
+  return hipGetLastError();
+}
+
+// ------------------------------------------ symmetric Jacobi eigensolver
+// G (n x n, symmetric) = V diag(lam) V^T, lam descending; V row-major with
+// eigenvectors as columns, written to Vout (n x n).  Matrix kept in LDS.
+__global__ __launch_bounds__(256) void k_eig_jacobi(int n, const double* __restrict__ Gin,
+                                                    double* __restrict__ lam,
+                                                    double* __restrict__ Vw,
+                                                    double* __restrict__ Vout) {
+  extern __shared__ double smem[];
+  double* G = smem;                        // n*n
+  __shared__ int pairs[SLAR_NMAX];
+  __shared__ double cs[SLAR_NMAX / 2], sn[SLAR_NMAX / 2];
+  __shared__ int rotated;
+  __shared__ double dg[SLAR_NMAX];
+  __shared__ int order[SLAR_NMAX];
+  const int t = threadIdx.x;
+  const int np = (n + 1) & ~1;
+  for (int e = t; e < np * np; e += blockDim.x) {
+    const int i = e / np, j = e % np;
+    G[e] = (i < n && j < n) ? Gin[i * n + j] : 0.0;
+    Vw[e] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int i = t; i < np; i += blockDim.x) pairs[i] = i;
+  __syncthreads();
+  const int npair = np / 2;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (t == 0) rotated = 0;
+    __syncthreads();
+    for (int step = 0; step < np - 1; ++step) {
+      for (int pi = t; pi < npair; pi += blockDim.x) {
+        const int p = pairs[2 * pi], q = pairs[2 * pi + 1];
+        const double app = G[p * np + p], aqq = G[q * np + q], apq = G[p * np + q];
+        double c = 1.0, s_ = 0.0;
+        if (apq != 0.0 && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
+          const double th = (aqq - app) / (2.0 * apq);
+          const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(tt * tt + 1.0);
+          s_ = tt * c;
+          rotated = 1;
+        }
+        cs[pi] = c; sn[pi] = s_;
+      }
+      __syncthreads();
+      // rows: G <- J^T G
+      for (int e = t; e < npair * np; e += blockDim.x) {
+        const int pi = e / np, j = e % np;
+        const double c = cs[pi], s_ = sn[pi];
+        if (s_ == 0.0) continue;
+        const int p = pairs[2 * pi], q = pairs[2 * pi + 1];
+        const double gp = G[p * np + j], gq = G[q * np + j];
+        G[p * np + j] = c * gp - s_ * gq;
+        G[q * np + j] = s_ * gp + c * gq;
+      }
+      __syncthreads();
+      // columns: G <- G J, and V <- V J
+      for (int e = t; e < npair * np; e += blockDim.x) {
+        const int pi = e / np, i = e % np;
+        const double c = cs[pi], s_ = sn[pi];
+        if (s_ == 0.0) continue;
+        const int p = pairs[2 * pi], q = pairs[2 * pi + 1];
+        const double gp = G[i * np + p], gq = G[i * np + q];
+        G[i * np + p] = c * gp - s_ * gq;
+        G[i * np + q] = s_ * gp + c * gq;
+        const double vp = Vw[i * np + p], vq = Vw[i * np + q];
+        Vw[i * np + p] = c * vp - s_ * vq;
+        Vw[i * np + q] = s_ * vp + c * vq;
+      }
+      __syncthreads();
+      if (t == 0) {
+        const int last = pairs[np - 1];
+        for (int i = np - 1; i > 1; --i) pairs[i] = pairs[i - 1];
+        pairs[1] = last;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int i = t; i < np; i += blockDim.x) dg[i] = (i < n) ? G[i * np + i] : -1e300;
+  __syncthreads();
+  for (int c = t; c < np; c += blockDim.x) {
+    int rank = 0;
+    for (int o = 0; o < np; ++o)
+      if (dg[o] > dg[c] || (dg[o] == dg[c] && o < c)) ++rank;
+    order[rank] = c;
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += blockDim.x) {
+    const int r = e / n, j = e % n;
+    Vout[e] = Vw[r * np + order[j]];
+  }
+  for (int j = t; j < n; j += blockDim.x) lam[j] = dg[order[j]];
+}
+
+hipError_t eig_sym(hipStream_t s, int n, const double* G, double* lam, double* Vwork,
+                   double* V) {
+  const int np = (n + 1) & ~1;
+  const size_t shm = (size_t)np * np * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_eig_jacobi,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       SLAR_NMAX * SLAR_NMAX * (int)sizeof(double));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  k_eig_jacobi<<<1, 256, shm, s>>>(n, G, lam, Vwork, V);
+  return hipGetLastError();
+}
+
+// Sign rule on columns: the entry of largest magnitude (lowest index on
+// near-ties within 1e-10) is made positive; the same flip is applied to the
+// matching column of B (if given).  A is [rows][lda] (column c), one block
+// per column.
+__global__ void k_sign_fix(int rows, int cols, double* __restrict__ A, int lda,
+                           double* __restrict__ B, int ldb, int rowsB) {
+  const int c = blockIdx.x;
+  if (c >= cols) return;
+  __shared__ double red[256];
+  __shared__ int redi[256];
+  const int t = threadIdx.x;
+  double m = -1.0;
+  for (int r = t; r < rows; r += blockDim.x) m = fmax(m, fabs(A[(long long)r * lda + c]));
+  red[t] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] = fmax(red[t], red[t + o]);
+    __syncthreads();
+  }
+  const double top = red[0];
+  __syncthreads();
+  int best = rows;
+  for (int r = t; r < rows; r += blockDim.x)
+    if (fabs(A[(long long)r * lda + c]) >= top * (1.0 - 1e-10)) { best = r; break; }
+  redi[t] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) redi[t] = min(redi[t], redi[t + o]);
+    __syncthreads();
+  }
+  const int p = redi[0];
+  if (p >= rows || top <= 0.0) return;
+  if (A[(long long)p * lda + c] < 0.0) {
+    for (int r = t; r < rows; r += blockDim.x) A[(long long)r * lda + c] = -A[(long long)r * lda + c];
+    if (B != nullptr)
+      for (int r = t; r < rowsB; r += blockDim.x) B[(long long)r * ldb + c] = -B[(long long)r * ldb + c];
+  }
+}
+
+hipError_t sign_fix(hipStream_t s, int rows, int cols, double* A, int lda, double* B, int ldb,
+                    int rowsB) {
+  if (cols <= 0) return hipSuccess;
+  k_sign_fix<<<cols, 256, 0, s>>>(rows, cols, A, lda, B, ldb, rowsB);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- helpers
+__global__ void k_copy2d(int rows, int cols, const double* __restrict__ A, int lda,
+                         double* __restrict__ B, int ldb, const double* __restrict__ colscale) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)rows * cols) return;
+  const int r = (int)(e / cols), c = (int)(e % cols);
+  double v = A[(long long)r * lda + c];
+  if (colscale) v *= colscale[c];
+  B[(long long)r * ldb + c] = v;
+}
+
+hipError_t copy2d(hipStream_t s, int rows, int cols, const double* A, int lda, double* B, int ldb,
+                  const double* colscale) {
+  const long long n = (long long)rows * cols;
+  if (n <= 0) return hipSuccess;
+  k_copy2d<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rows, cols, A, lda, B, ldb, colscale);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* p, long long n, double v) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+hipError_t fill(hipStream_t s, double* p, long long n, double v) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace slar

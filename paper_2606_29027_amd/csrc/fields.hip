@@ -1,0 +1,277 @@
+// Fields on the x-grid: velocity moments of a frame-form tensor and the
+// spectral (DFT) Poisson solve / derivatives (eqs. (Poisson), (Efromphi);
+// section 3.2.3 uses FFT-based differentiation for all field terms).
+//
+// The transforms are direct DFTs along each axis, one block per line with
+// the line and the twiddle table in LDS: N <= 128 per axis, so a line is
+// N^2 <= 16384 complex FMAs and the whole 2D transform of a 128^2 field is
+// spread over 2 x 128 blocks.  This handles every N (the batched workload
+// has N = 48, 96), not only powers of two.
+#include <cmath>
+
+#include "slar_internal.h"
+#include "dense.h"
+#include "fields.h"
+
+namespace slar {
+
+// ---------------------------------------------------------- twiddles
+void host_twiddles(int n, std::vector<double>& tw) {
+  tw.resize(2 * n);
+  for (int t = 0; t < n; ++t) {
+    // reduce the angle exactly: 2 pi t / n
+    const double a = 2.0 * M_PI * (double)t / (double)n;
+    tw[2 * t] = std::cos(a);
+    tw[2 * t + 1] = std::sin(a);
+  }
+}
+
+// line transform along the last axis (axis = 1) or the first (axis = 0)
+// of [B][n0][n1] complex (double2) data; sign -1 forward, +1 inverse.
+__global__ void k_dft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
+                           const double* __restrict__ realin, double2* __restrict__ out,
+                           const double* __restrict__ tw) {
+  __shared__ double2 line[SLAR_NMAX];
+  __shared__ double2 w[SLAR_NMAX];
+  const int b = blockIdx.y;
+  const int L = axis == 1 ? n1 : n0;          // line length
+  const int other = blockIdx.x;               // index along the other axis
+  const long long base = (long long)b * n0 * n1;
+  const int t = threadIdx.x;
+  for (int e = t; e < L; e += blockDim.x) {
+    const long long off = axis == 1 ? base + (long long)other * n1 + e : base + (long long)e * n1 + other;
+    line[e] = realin ? make_double2(realin[off], 0.0) : in[off];
+    w[e] = make_double2(tw[2 * e], sign * tw[2 * e + 1]);
+  }
+  __syncthreads();
+  for (int kk = t; kk < L; kk += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    int idx = 0;
+    for (int i = 0; i < L; ++i) {
+      const double2 x = line[i], ww = w[idx];
+      re += x.x * ww.x - x.y * ww.y;
+      im += x.x * ww.y + x.y * ww.x;
+      idx += kk;
+      if (idx >= L) idx -= L;
+    }
+    const long long off = axis == 1 ? base + (long long)other * n1 + kk : base + (long long)kk * n1 + other;
+    out[off] = make_double2(re, im);
+  }
+}
+
+__global__ void k_take_real(long long n, const double2* __restrict__ in, double scale,
+                            double* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = in[e].x * scale;
+}
+
+// Forward 2D DFT of B real fields [B][Nx] into complex [B][Nx].
+hipError_t dft_forward(hipStream_t s, Workspace* ws, int B, const double* in, double2* out,
+                       double2* tmp) {
+  const GridDev& G = ws->G;
+  const int n0 = G.n[0], n1 = (G.dx == 2) ? G.n[1] : 1;
+  if (G.dx == 2) {
+    k_dft_line<<<dim3(n0, B), 128, 0, s>>>(n0, n1, 1, -1.0, nullptr, in, tmp, ws->tw[1]);
+    k_dft_line<<<dim3(n1, B), 128, 0, s>>>(n0, n1, 0, -1.0, tmp, nullptr, out, ws->tw[0]);
+  } else {
+    k_dft_line<<<dim3(1, B), 128, 0, s>>>(n0, 1, 0, -1.0, nullptr, in, out, ws->tw[0]);
+  }
+  return hipGetLastError();
+}
+
+// Inverse 2D DFT of B complex fields, real part, scaled by 1/Nx.
+hipError_t dft_inverse(hipStream_t s, Workspace* ws, int B, const double2* in, double* out,
+                       double2* tmp) {
+  const GridDev& G = ws->G;
+  const int n0 = G.n[0], n1 = (G.dx == 2) ? G.n[1] : 1;
+  const long long tot = (long long)B * G.nx;
+  if (G.dx == 2) {
+    k_dft_line<<<dim3(n1, B), 128, 0, s>>>(n0, n1, 0, 1.0, in, nullptr, tmp, ws->tw[0]);
+    k_dft_line<<<dim3(n0, B), 128, 0, s>>>(n0, n1, 1, 1.0, tmp, nullptr, (double2*)tmp + tot, ws->tw[1]);
+    k_take_real<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(tot, (double2*)tmp + tot, 1.0 / G.nx, out);
+  } else {
+    k_dft_line<<<dim3(1, B), 128, 0, s>>>(n0, 1, 0, 1.0, in, nullptr, tmp, ws->tw[0]);
+    k_take_real<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(tot, tmp, 1.0 / G.nx, out);
+  }
+  return hipGetLastError();
+}
+
+// wavenumber of index i on an axis of n cells and length L, Nyquist -> 0
+__device__ __forceinline__ double wavenum(int i, int n, double L) {
+  if ((n % 2) == 0 && i == n / 2) return 0.0;
+  const int m = (i < (n + 1) / 2) ? i : i - n;
+  return 2.0 * M_PI * (double)m / L;
+}
+
+struct Kgrid { int n0, n1, dx; double L0, L1; };
+
+__device__ __forceinline__ void kvec(const Kgrid& K, long long e, double* k) {
+  const int i0 = (int)(e / K.n1), i1 = (int)(e % K.n1);
+  k[0] = wavenum(i0, K.n0, K.L0);
+  k[1] = K.dx == 2 ? wavenum(i1, K.n1, K.L1) : 0.0;
+}
+
+// Symbol application.  op: 0 Poisson (rho^ -> phi^, E^_m = -i k_m phi^),
+// 1 gradient (f^ -> i k_m f^), 2 divergence (F^[m] -> sum i k_m F^_m),
+// 3 inverse negative Laplacian (f^ -> f^ / |k|^2, 0 on null modes).
+// in/out strides are in fields of Nx complex values.
+__global__ void k_symbol(Kgrid K, int op, int nvec, const double2* __restrict__ in,
+                         double2* __restrict__ out, int Nx) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)Nx * nvec) return;
+  const int v = (int)(e / Nx);
+  const long long p = e % Nx;
+  double k[2];
+  kvec(K, p, k);
+  const double k2 = k[0] * k[0] + k[1] * k[1];
+  if (op == 0) {
+    const double2 r = in[(long long)v * Nx + p];
+    const double2 ph = k2 > 0.0 ? make_double2(r.x / k2, r.y / k2) : make_double2(0.0, 0.0);
+    double2* o = out + (long long)v * (1 + K.dx) * Nx;
+    o[p] = ph;
+    for (int m = 0; m < K.dx; ++m)  // -i k ph
+      o[(long long)(1 + m) * Nx + p] = make_double2(k[m] * ph.y, -k[m] * ph.x);
+  } else if (op == 1) {
+    const double2 f = in[(long long)v * Nx + p];
+    for (int m = 0; m < K.dx; ++m)
+      out[((long long)v * K.dx + m) * Nx + p] = make_double2(-k[m] * f.y, k[m] * f.x);
+  } else if (op == 2) {
+    double re = 0.0, im = 0.0;
+    for (int m = 0; m < K.dx; ++m) {
+      const double2 f = in[((long long)v * K.dx + m) * Nx + p];
+      re += -k[m] * f.y;
+      im += k[m] * f.x;
+    }
+    out[(long long)v * Nx + p] = make_double2(re, im);
+  } else {
+    const double2 f = in[(long long)v * Nx + p];
+    out[(long long)v * Nx + p] = k2 > 0.0 ? make_double2(f.x / k2, f.y / k2) : make_double2(0.0, 0.0);
+  }
+}
+
+hipError_t spectral_symbol(hipStream_t s, Workspace* ws, int op, int nvec, const double2* in,
+                           double2* out) {
+  const GridDev& G = ws->G;
+  Kgrid K{G.n[0], G.dx == 2 ? G.n[1] : 1, G.dx, ws->grid.hi[0] - ws->grid.lo[0],
+          G.dx == 2 ? ws->grid.hi[1] - ws->grid.lo[1] : 1.0};
+  const long long n = (long long)G.nx * nvec;
+  k_symbol<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(K, op, nvec, in, out, G.nx);
+  return hipGetLastError();
+}
+
+__global__ void k_rho(int n, const double* ne, double ni, double* rho) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) rho[e] = ni - ne[e];
+}
+
+// phi (may be null) and E [dx][Nx] from n_e.
+hipError_t poisson_run(hipStream_t s, Workspace* ws, const double* n_e, double n_i, double* phi,
+                       double* E) {
+  const GridDev& G = ws->G;
+  const int Nx = G.nx;
+  double2* c0 = (double2*)ws->cbuf;
+  double2* c1 = c0 + (size_t)4 * Nx;
+  double2* tmp = c0 + (size_t)12 * Nx;
+  double* rho = ws->cbuf + (size_t)2 * 40 * Nx;
+  k_rho<<<(Nx + 255) / 256, 256, 0, s>>>(Nx, n_e, n_i, rho);
+  hipError_t e = dft_forward(s, ws, 1, rho, c0, tmp);
+  if (e != hipSuccess) return e;
+  e = spectral_symbol(s, ws, 0, 1, c0, c1);
+  if (e != hipSuccess) return e;
+  double* out = rho + Nx;
+  e = dft_inverse(s, ws, 1 + G.dx, c1, out, tmp);
+  if (e != hipSuccess) return e;
+  if (phi) HIP_CHK(hipMemcpyAsync(phi, out, sizeof(double) * Nx, hipMemcpyDeviceToDevice, s));
+  HIP_CHK(hipMemcpyAsync(E, out + Nx, sizeof(double) * Nx * G.dx, hipMemcpyDeviceToDevice, s));
+  return hipSuccess;
+}
+
+// ----------------------------------------------------------- moments
+// Psi[J][q]: test functions times the velocity cell volume, order
+// 1, v_mu, |v|^2, v_mu v_nu (mu <= nu), |v|^2 v_mu.
+__global__ void k_psi(GridDev g, int nmom, double* psi) {
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= g.nv) return;
+  const int dx = g.dx, dv = g.dv;
+  double v[2];
+  double vol = 1.0;
+  if (dv == 1) {
+    v[0] = g.lo[1] + ((double)J + 0.5) * g.h[1];
+    vol = g.h[1];
+  } else {
+    v[0] = g.lo[2] + ((double)(J / g.n[3]) + 0.5) * g.h[2];
+    v[1] = g.lo[3] + ((double)(J % g.n[3]) + 0.5) * g.h[3];
+    vol = g.h[2] * g.h[3];
+  }
+  double v2 = 0.0;
+  for (int m = 0; m < dv; ++m) v2 += v[m] * v[m];
+  double* o = psi + (size_t)J * nmom;
+  int q = 0;
+  o[q++] = vol;
+  for (int m = 0; m < dv; ++m) o[q++] = v[m] * vol;
+  o[q++] = v2 * vol;
+  for (int a = 0; a < dv; ++a)
+    for (int b = a; b < dv; ++b) o[q++] = v[a] * v[b] * vol;
+  for (int m = 0; m < dv; ++m) o[q++] = v2 * v[m] * vol;
+  (void)dx;
+}
+
+int nmom_of(int dv) { return dv == 1 ? 5 : 9; }
+
+hipError_t psi_build(hipStream_t s, Workspace* ws) {
+  const GridDev& G = ws->G;
+  k_psi<<<(G.nv + 255) / 256, 256, 0, s>>>(G, nmom_of(G.dv), ws->psi);
+  return hipGetLastError();
+}
+
+// C (rows x cols) = A^T B with A = [n][lda] (first `rows` cols), B = [n][ldb],
+// reduction over long n, deterministic split.
+hipError_t gemm_tn_long(hipStream_t s, Workspace* ws, int rows, int cols, int n, const double* A,
+                        int lda, const double* B, int ldb, double* C, int ldc) {
+  int chunk = 256;
+  while ((size_t)((n + chunk - 1) / chunk) * rows * cols > ws->dwork_elems) chunk *= 2;
+  const int full = n / chunk, tail = n - full * chunk;
+  if (full > 0) {
+    hipError_t e = gemm_f64_sumbatch(s, ws, true, false, rows, cols, chunk, A, lda,
+                                     (long long)chunk * lda, B, ldb, (long long)chunk * ldb, C,
+                                     ldc, full);
+    if (e != hipSuccess) return e;
+  }
+  if (tail > 0)
+    return gemm_f64(s, true, false, rows, cols, tail, 1.0, A + (long long)full * chunk * lda, lda,
+                    0, B + (long long)full * chunk * ldb, ldb, 0, full > 0 ? 1.0 : 0.0, C, ldc, 0, 1);
+  return hipSuccess;
+}
+
+// M [nmom][Nx] = X (Psi^T P)^T restricted to r columns.
+hipError_t moments_run(hipStream_t s, Workspace* ws, const slar_frames& F, double* M) {
+  const GridDev& G = ws->G;
+  const int nmom = nmom_of(G.dv);
+  double* m = ws->cbuf + (size_t)2 * 40 * G.nx + (size_t)8 * G.nx;   // [r][nmom]
+  hipError_t e = gemm_tn_long(s, ws, F.r, nmom, G.nv, F.P, F.ld, ws->psi, nmom, m, nmom);
+  if (e != hipSuccess) return e;
+  // M^T = m^T X^T  -> [nmom][Nx]
+  return gemm_f64(s, true, true, nmom, G.nx, F.r, 1.0, m, nmom, 0, F.X, F.ld, 0, 0.0, M, G.nx, 0, 1);
+}
+
+__global__ void k_conserved(int Nx, int dv, const double* M, const double* E, int dx, double* U) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nx) return;
+  double ep = 0.0;
+  for (int m = 0; m < dx; ++m) ep += E[(size_t)m * Nx + e] * E[(size_t)m * Nx + e];
+  ep *= 0.5;
+  for (int q = 0; q <= dv; ++q) U[(size_t)q * Nx + e] = M[(size_t)q * Nx + e];
+  U[(size_t)(dv + 1) * Nx + e] = 0.5 * M[(size_t)(dv + 1) * Nx + e] + ep;
+}
+
+hipError_t conserved_from_moments(hipStream_t s, Workspace* ws, const double* M, double n_i,
+                                  double* U) {
+  const GridDev& G = ws->G;
+  double* E = ws->cbuf + (size_t)2 * 40 * G.nx + (size_t)10 * G.nx;
+  hipError_t e = poisson_run(s, ws, M, n_i, nullptr, E);
+  if (e != hipSuccess) return e;
+  k_conserved<<<(G.nx + 255) / 256, 256, 0, s>>>(G.nx, G.dv, M, E, G.dx, U);
+  return hipGetLastError();
+}
+
+}  // namespace slar

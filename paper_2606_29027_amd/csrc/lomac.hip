@@ -1,0 +1,631 @@
+// Adaptive-weight LoMaC projection and the implicit macroscopic solve
+// (section 3.2 and Supplement B), FP64 throughout.
+//
+//  prepare : omega^(mu) = max(|U^(v_mu)[:,0]|, delta); 1D weighted
+//            Gram--Schmidt (gamma, q1, eta, beta, q2, norms), one block per
+//            velocity dimension; Q_0, Q_{1,mu}, Q_2 on the velocity grid;
+//            <psi, Q_k>; moments and projection coefficients of F*.
+//  residual: G(U) = U - U_hist + b dt (D.F(U) - S(U)) with the LoMaC
+//            closure; spectral Poisson / d_t phi / divergence.
+//  solve   : Newton with finite-difference Jacobian-vector products and
+//            restarted (flexible) GMRES with CGS2; each Newton step is
+//            corrected exactly on the per-component mean, where the Jacobian
+//            is the identity (the divergence and the source have zero mean).
+//  project : F^{n+1} = F* + sum_k dC_k (x) Q_k appended to the frames.
+#include <cmath>
+#include <vector>
+
+#include "slar_internal.h"
+#include "dense.h"
+#include "fields.h"
+#include "lomac.h"
+
+namespace slar {
+
+// ---------------------------------------------------------------- layout
+LmLayout lm_layout(const GridDev& G) {
+  LmLayout L{};
+  const int K = G.dv + 2, nm = nmom_of(G.dv);
+  size_t o = 0;
+  L.gs = o; o += 2 * 3 * SLAR_NMAX;
+  L.scal = o; o += 32;
+  L.Q = o; o += (size_t)K * G.nv;
+  L.psiQ = o; o += (size_t)nm * K;
+  L.Mstar = o; o += (size_t)nm * G.nx;
+  L.Cstar = o; o += (size_t)K * G.nx;
+  L.U0 = o; o += (size_t)K * G.nx;
+  L.total = o;
+  return L;
+}
+
+// 1D weighted Gram--Schmidt, one block per velocity dimension.
+// scal layout per mu (8 slots): gamma, eta, beta, n0, n1, n2.
+__global__ void k_gram_schmidt(GridDev g, const double* u0, int ld0, const double* u1, int ld1,
+                               double delta, double* gs, double* scal) {
+  const int mu = blockIdx.x;
+  const int dim = g.dx + mu;
+  const int n = g.n[dim];
+  const double h = g.h[dim];
+  const double* u = mu == 0 ? u0 : u1;
+  const int ld = mu == 0 ? ld0 : ld1;
+  double* om = gs + (size_t)mu * 3 * SLAR_NMAX;
+  double* q1 = om + SLAR_NMAX;
+  double* q2 = q1 + SLAR_NMAX;
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  auto bsum = [&](double v) -> double {
+    red[t] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) red[t] += red[t + o];
+      __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+  };
+  double vv = 0.0, w = 0.0;
+  if (t < n) {
+    vv = g.lo[dim] + ((double)t + 0.5) * h;
+    w = fmax(fabs(u[(size_t)t * ld]), delta);
+    om[t] = w;
+  }
+  const double vo = vv * w, v2o = vv * vv * w;
+  // <p,q> = sum p q h / omega
+  const double n0 = bsum(t < n ? w * w * h / w : 0.0);
+  const double gamma = bsum(t < n ? vo * w * h / w : 0.0) / n0;
+  const double q1v = vo - gamma * w;
+  const double eta = bsum(t < n ? v2o * w * h / w : 0.0) / n0;
+  const double n1 = bsum(t < n ? q1v * q1v * h / w : 0.0);
+  const double beta = bsum(t < n ? v2o * q1v * h / w : 0.0) / n1;
+  const double q2v = v2o - eta * w - beta * q1v;
+  const double n2 = bsum(t < n ? q2v * q2v * h / w : 0.0);
+  if (t < n) { q1[t] = q1v; q2[t] = q2v; }
+  if (t == 0) {
+    double* sc = scal + mu * 8;
+    sc[0] = gamma; sc[1] = eta; sc[2] = beta; sc[3] = n0; sc[4] = n1; sc[5] = n2;
+  }
+}
+
+// Q tensors (stored [Nv][K]) and squared norms NQ (scal[16 + k]).
+__global__ void k_qbasis(GridDev g, const double* gs, double* scal, double* Q) {
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  const int dv = g.dv, K = dv + 2;
+  if (J == 0) {
+    const double* s0 = scal;
+    const double* s1 = scal + 8;
+    double* NQ = scal + 16;
+    if (dv == 1) {
+      NQ[0] = s0[3]; NQ[1] = s0[4]; NQ[2] = s0[5];
+    } else {
+      NQ[0] = s0[3] * s1[3];
+      NQ[1] = s0[4] * s1[3];
+      NQ[2] = s0[3] * s1[4];
+      NQ[3] = s0[5] * s1[3] + s1[5] * s0[3];
+    }
+  }
+  if (J >= g.nv) return;
+  double* q = Q + (size_t)J * K;     // Q stored [Nv][K]
+  if (dv == 1) {
+    const double* om = gs;
+    q[0] = om[J];
+    q[1] = om[SLAR_NMAX + J];
+    q[2] = om[2 * SLAR_NMAX + J];
+    return;
+  }
+  const int a = J / g.n[3], b = J % g.n[3];
+  const double* A = gs;                    // mu = 0: omega, q1, q2
+  const double* B = gs + 3 * SLAR_NMAX;    // mu = 1
+  const double w0 = A[a], w1 = B[b];
+  q[0] = w0 * w1;
+  q[1] = A[SLAR_NMAX + a] * w1;
+  q[2] = w0 * B[SLAR_NMAX + b];
+  q[3] = A[2 * SLAR_NMAX + a] * w1 + w0 * B[2 * SLAR_NMAX + b];
+  (void)K;
+}
+
+// Projection coefficients eqs. (C0_def)-(C2_def) from raw moments
+// Mraw = (M0, M1_mu, M2) -> C [K][Nx].
+__device__ __forceinline__ void coeffs_at(int dv, const double* scal, const double* Mr, double* C) {
+  const double* NQ = scal + 16;
+  const double M0 = Mr[0];
+  C[0] = M0 / NQ[0];
+  double etas = 0.0, num = Mr[dv + 1];
+  for (int m = 0; m < dv; ++m) {
+    const double* sc = scal + 8 * m;
+    const double d1 = Mr[1 + m] - sc[0] * M0;
+    C[1 + m] = d1 / NQ[1 + m];
+    etas += sc[1];
+  }
+  num = num - etas * M0;
+  for (int m = 0; m < dv; ++m) {
+    const double* sc = scal + 8 * m;
+    num = num - sc[2] * (Mr[1 + m] - sc[0] * M0);
+  }
+  C[dv + 1] = num / NQ[dv + 1];
+}
+
+__global__ void k_cstar(int Nx, int dv, const double* scal, const double* M, double* C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nx) return;
+  double Mr[4], c[4];
+  for (int q = 0; q < dv + 2; ++q) Mr[q] = M[(size_t)q * Nx + e];
+  coeffs_at(dv, scal, Mr, c);
+  for (int q = 0; q < dv + 2; ++q) C[(size_t)q * Nx + e] = c[q];
+}
+
+slar_status lomac_prepare_run(hipStream_t s, Workspace* ws, const slar_ht& Fs,
+                              const slar_frames& Ff, double delta, double n_i) {
+  const GridDev& G = ws->G;
+  const LmLayout L = lm_layout(G);
+  double* lm = ws->lm;
+  const int dv = G.dv, K = dv + 2, nm = nmom_of(dv);
+  const double* u0 = (const double*)Fs.leaf[G.dx];
+  const int ld0 = Fs.rank[G.dx];
+  const double* u1 = dv == 2 ? (const double*)Fs.leaf[G.dx + 1] : u0;
+  const int ld1 = dv == 2 ? Fs.rank[G.dx + 1] : ld0;
+  k_gram_schmidt<<<dv, 256, 0, s>>>(G, u0, ld0, u1, ld1, delta, lm + L.gs, lm + L.scal);
+  k_qbasis<<<(G.nv + 255) / 256, 256, 0, s>>>(G, lm + L.gs, lm + L.scal, lm + L.Q);
+  HIP_TRY(hipGetLastError());
+  // <psi_q, Q_k> -> psiQ [nm][K]: sum_J Psi[J][q] Q[J][k]
+  if (gemm_tn_long(s, ws, nm, K, G.nv, ws->psi, nm, lm + L.Q, K, lm + L.psiQ, K) != hipSuccess)
+    return SLAR_E_HIP;
+  if (moments_run(s, ws, Ff, lm + L.Mstar) != hipSuccess) return SLAR_E_HIP;
+  k_cstar<<<(G.nx + 255) / 256, 256, 0, s>>>(G.nx, dv, lm + L.scal, lm + L.Mstar, lm + L.Cstar);
+  if (conserved_from_moments(s, ws, lm + L.Mstar, n_i, lm + L.U0) != hipSuccess) return SLAR_E_HIP;
+  HIP_TRY(hipMemcpyAsync(ws->lm_scal, lm + L.scal, 32 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < 20; ++i)
+    if (!std::isfinite(ws->lm_scal[i])) return SLAR_E_NUMERIC;
+  ws->n_i = n_i;
+  ws->lm_ready = true;
+  return SLAR_OK;
+}
+
+// ------------------------------------------------------------ residual
+struct MacroBufs {
+  double *rho, *phiE, *J, *gdt, *Mall, *flux, *divF;
+  double2 *c0, *c1, *tmp;
+};
+
+static MacroBufs macro_bufs(Workspace* ws) {
+  const GridDev& G = ws->G;
+  const size_t Nx = G.nx;
+  MacroBufs b;
+  double* p = ws->kry;   // first region of kry
+  b.rho = p; p += Nx;
+  b.phiE = p; p += 3 * Nx;
+  b.J = p; p += 2 * Nx;
+  b.gdt = p; p += 2 * Nx;
+  b.Mall = p; p += 9 * Nx;
+  b.flux = p; p += 8 * Nx;
+  b.divF = p; p += 4 * Nx;
+  double2* c = (double2*)ws->cbuf;
+  b.c0 = c;
+  b.c1 = c + 10 * Nx;
+  b.tmp = c + 20 * Nx;
+  return b;
+}
+
+size_t macro_fixed_elems(int Nx) { return (size_t)29 * Nx; }
+
+__global__ void k_rho_of(int Nx, const double* U, double ni, double* rho) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < Nx) rho[e] = ni - U[e];
+}
+
+// e_p, raw moments from U, dC, all corrected moments, J = -M1
+__global__ void k_closure(int Nx, int dx, int dv, int nm, const double* __restrict__ U,
+                          const double* __restrict__ phiE, const double* __restrict__ scal,
+                          const double* __restrict__ Cstar, const double* __restrict__ Mstar,
+                          const double* __restrict__ psiQ, double* __restrict__ Mall,
+                          double* __restrict__ J) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nx) return;
+  const int K = dv + 2;
+  double ep = 0.0;
+  for (int m = 0; m < dx; ++m) {
+    const double Em = phiE[(size_t)(1 + m) * Nx + e];
+    ep += Em * Em;
+  }
+  ep *= 0.5;
+  double Mr[4], C[4];
+  for (int q = 0; q <= dv; ++q) Mr[q] = U[(size_t)q * Nx + e];
+  Mr[dv + 1] = 2.0 * (U[(size_t)(dv + 1) * Nx + e] - ep);
+  coeffs_at(dv, scal, Mr, C);
+  double dC[4];
+  for (int k = 0; k < K; ++k) dC[k] = C[k] - Cstar[(size_t)k * Nx + e];
+  for (int q = 0; q < nm; ++q) {
+    double v = Mstar[(size_t)q * Nx + e];
+    for (int k = 0; k < K; ++k) v += psiQ[q * K + k] * dC[k];
+    Mall[(size_t)q * Nx + e] = v;
+  }
+  for (int m = 0; m < dx; ++m) J[(size_t)m * Nx + e] = -Mall[(size_t)(1 + m) * Nx + e];
+}
+
+// d_t phi gradient symbol: g_m = i k_m * ( -(sum_n i k_n J^_n) / |k|^2 )
+__global__ void k_dtphi_sym(int n0, int n1, int dx, double L0, double L1,
+                            const double2* __restrict__ Jh, double2* __restrict__ out, int Nx) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Nx) return;
+  auto wn = [](int i, int n, double L) {
+    if ((n % 2) == 0 && i == n / 2) return 0.0;
+    const int m = (i < (n + 1) / 2) ? i : i - n;
+    return 2.0 * M_PI * (double)m / L;
+  };
+  double k[2] = {wn(p / n1, n0, L0), dx == 2 ? wn(p % n1, n1, L1) : 0.0};
+  const double k2 = k[0] * k[0] + k[1] * k[1];
+  double dre = 0.0, dim = 0.0;   // div J^ = sum i k J
+  for (int m = 0; m < dx; ++m) {
+    const double2 f = Jh[(size_t)m * Nx + p];
+    dre += -k[m] * f.y;
+    dim += k[m] * f.x;
+  }
+  double pre = 0.0, pim = 0.0;   // dtphi^ = -div / k2
+  if (k2 > 0.0) { pre = -dre / k2; pim = -dim / k2; }
+  for (int m = 0; m < dx; ++m) out[(size_t)m * Nx + p] = make_double2(-k[m] * pim, k[m] * pre);
+}
+
+// fluxes [K][dx][Nx]
+__global__ void k_fluxes(int Nx, int dx, int dv, const double* __restrict__ Mall,
+                         const double* __restrict__ phiE, const double* __restrict__ J,
+                         const double* __restrict__ gdt, double* __restrict__ flux) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nx) return;
+  const double phi = phiE[e];
+  int pair[2][2];
+  int c = dv + 2;
+  for (int a = 0; a < dv; ++a)
+    for (int b = a; b < dv; ++b) { pair[a][b] = c; pair[b][a] = c; ++c; }
+  const int off_e = c;
+  for (int m = 0; m < dx; ++m) flux[(size_t)(0 * dx + m) * Nx + e] = Mall[(size_t)(1 + m) * Nx + e];
+  for (int a = 0; a < dv; ++a)
+    for (int m = 0; m < dx; ++m)
+      flux[(size_t)((1 + a) * dx + m) * Nx + e] = Mall[(size_t)pair[a][m] * Nx + e];
+  for (int m = 0; m < dx; ++m) {
+    const double fep = -phi * gdt[(size_t)m * Nx + e] + J[(size_t)m * Nx + e] * phi;
+    flux[(size_t)((dv + 1) * dx + m) * Nx + e] = 0.5 * Mall[(size_t)(off_e + m) * Nx + e] + fep;
+  }
+}
+
+__global__ void k_gres(int Nx, int dx, int dv, const double* __restrict__ U,
+                       const double* __restrict__ Uh, double bdt, const double* __restrict__ divF,
+                       const double* __restrict__ phiE, double* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nx) return;
+  const int K = dv + 2;
+  for (int q = 0; q < K; ++q) {
+    double S = 0.0;
+    if (q >= 1 && q <= dv) S = -U[e] * phiE[(size_t)(1 + (q - 1)) * Nx + e];
+    const size_t i = (size_t)q * Nx + e;
+    G[i] = U[i] - Uh[i] + bdt * (divF[i] - S);
+  }
+}
+
+hipError_t macro_residual(hipStream_t s, Workspace* ws, const double* U, const double* Uhist,
+                          double bdt, double* Gout) {
+  const GridDev& G = ws->G;
+  const LmLayout L = lm_layout(G);
+  const double* lm = ws->lm;
+  MacroBufs b = macro_bufs(ws);
+  const int Nx = G.nx, dx = G.dx, dv = G.dv, K = dv + 2, nm = nmom_of(dv);
+  const unsigned nb = (Nx + 255) / 256;
+  k_rho_of<<<nb, 256, 0, s>>>(Nx, U, ws->n_i, b.rho);
+  hipError_t e = dft_forward(s, ws, 1, b.rho, b.c0, b.tmp);
+  if (e != hipSuccess) return e;
+  if ((e = spectral_symbol(s, ws, 0, 1, b.c0, b.c1)) != hipSuccess) return e;
+  if ((e = dft_inverse(s, ws, 1 + dx, b.c1, b.phiE, b.tmp)) != hipSuccess) return e;
+  k_closure<<<nb, 256, 0, s>>>(Nx, dx, dv, nm, U, b.phiE, lm + L.scal, lm + L.Cstar, lm + L.Mstar,
+                               lm + L.psiQ, b.Mall, b.J);
+  if ((e = dft_forward(s, ws, dx, b.J, b.c0, b.tmp)) != hipSuccess) return e;
+  k_dtphi_sym<<<nb, 256, 0, s>>>(G.n[0], dx == 2 ? G.n[1] : 1, dx, ws->grid.hi[0] - ws->grid.lo[0],
+                                 dx == 2 ? ws->grid.hi[1] - ws->grid.lo[1] : 1.0, b.c0, b.c1, Nx);
+  if ((e = dft_inverse(s, ws, dx, b.c1, b.gdt, b.tmp)) != hipSuccess) return e;
+  k_fluxes<<<nb, 256, 0, s>>>(Nx, dx, dv, b.Mall, b.phiE, b.J, b.gdt, b.flux);
+  if ((e = dft_forward(s, ws, K * dx, b.flux, b.c0, b.tmp)) != hipSuccess) return e;
+  if ((e = spectral_symbol(s, ws, 2, K, b.c0, b.c1)) != hipSuccess) return e;
+  if ((e = dft_inverse(s, ws, K, b.c1, b.divF, b.tmp)) != hipSuccess) return e;
+  k_gres<<<nb, 256, 0, s>>>(Nx, dx, dv, U, Uhist, bdt, b.divF, b.phiE, Gout);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ vector kernels
+// partial dots: for v in [0, nv): part[v][block] = sum_e A[v][e] * w[e]
+__global__ void k_multidot(int n, int nv, const double* __restrict__ A, long long lda,
+                           const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[4][SLAR_KMAX];
+  const int t = threadIdx.x;
+  const int e0 = blockIdx.x * 1024;
+  for (int v = 0; v < nv; ++v) {
+    double acc = 0.0;
+    for (int e = e0 + t; e < min(n, e0 + 1024); e += 256) acc += A[v * lda + e] * w[e];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((t & 63) == 0) red[t >> 6][v] = acc;
+  }
+  __syncthreads();
+  for (int v = t; v < nv; v += 256)
+    part[(size_t)v * gridDim.x + blockIdx.x] = red[0][v] + red[1][v] + red[2][v] + red[3][v];
+}
+
+__global__ void k_reduce_parts(int nv, int nb, const double* __restrict__ part, double* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) acc += part[(size_t)v * nb + b];
+  out[v] = acc;
+}
+
+// w -= sum_v A[v] h[v]
+__global__ void k_subtract_combo(int n, int nv, const double* __restrict__ A, long long lda,
+                                 const double* __restrict__ h, double* __restrict__ w) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double acc = w[e];
+  for (int v = 0; v < nv; ++v) acc -= A[v * lda + e] * h[v];
+  w[e] = acc;
+}
+
+// y = a x + b y ; if x2: y += c x2
+__global__ void k_axpby(int n, double a, const double* __restrict__ x, double b, double* __restrict__ y,
+                        double c, const double* __restrict__ x2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double v = a * x[e] + (b == 0.0 ? 0.0 : b * y[e]);
+  if (x2) v += c * x2[e];
+  y[e] = v;
+}
+
+// x += sum_v A[v] y[v]
+__global__ void k_add_combo(int n, int nv, const double* __restrict__ A, long long lda,
+                            const double* __restrict__ y, double* __restrict__ x) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double acc = x[e];
+  for (int v = 0; v < nv; ++v) acc += A[v * lda + e] * y[v];
+  x[e] = acc;
+}
+
+// per-component means of d and g: out[c] = mean(d_c), out[8 + c] = mean(g_c)
+__global__ void k_comp_means(int Nx, const double* __restrict__ d, const double* __restrict__ g,
+                             double* __restrict__ out) {
+  __shared__ double r1[256], r2[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int e = t; e < Nx; e += 256) { a += d[(size_t)c * Nx + e]; b += g[(size_t)c * Nx + e]; }
+  r1[t] = a; r2[t] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) { r1[t] += r1[t + o]; r2[t] += r2[t + o]; }
+    __syncthreads();
+  }
+  if (t == 0) { out[c] = r1[0] / Nx; out[8 + c] = r2[0] / Nx; }
+}
+
+// per-component mean fix: d_c -= mean(d_c) + mean(g_c)  (means given)
+__global__ void k_meanfix(int Nx, int K, const double* __restrict__ md, const double* __restrict__ mg,
+                          double* __restrict__ d) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nx * K) return;
+  const int c = e / Nx;
+  d[e] -= md[c] + mg[c];
+}
+
+struct Krylov {
+  Workspace* ws;
+  hipStream_t s;
+  int n;
+  double* part;     // partial sums
+  double* hdev;     // device small vector
+  double* hhost;    // pinned
+  hipError_t dots(const double* A, long long lda, int nv, const double* w, double* out_dev) {
+    const int nb = (n + 1023) / 1024;
+    k_multidot<<<nb, 256, 0, s>>>(n, nv, A, lda, w, part);
+    k_reduce_parts<<<(nv + 63) / 64, 64, 0, s>>>(nv, nb, part, out_dev);
+    return hipGetLastError();
+  }
+  hipError_t fetch(const double* dev, int cnt, double* host) {
+    hipError_t e = hipMemcpyAsync(host, dev, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+  }
+  double norm(const double* x) {
+    if (dots(x, 0, 1, x, hdev) != hipSuccess) return NAN;
+    if (fetch(hdev, 1, hhost) != hipSuccess) return NAN;
+    return std::sqrt(hhost[0]);
+  }
+};
+
+struct KryBufs {
+  double *V, *Z, *w, *g0, *Uh, *Gh, *d, *r, *x, *U;
+};
+
+static KryBufs kry_bufs(Workspace* ws, int n, int m) {
+  KryBufs b;
+  double* p = ws->kry + macro_fixed_elems(ws->G.nx);
+  b.V = p; p += (size_t)(m + 1) * n;
+  b.Z = p; p += (size_t)m * n;
+  b.w = p; p += n;
+  b.g0 = p; p += n;
+  b.Uh = p; p += n;
+  b.Gh = p; p += n;
+  b.d = p; p += n;
+  b.r = p; p += n;
+  b.x = p; p += n;
+  b.U = p; p += n;
+  return b;
+}
+
+size_t kry_elems_for(int Nx, int K, int m) {
+  const size_t n = (size_t)Nx * K;
+  return macro_fixed_elems(Nx) + (size_t)(2 * m + 1) * n + 8 * n + 4096;
+}
+
+slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, const double* Unm1,
+                            double dt, int bdf, double newton_tol, double krylov_tol,
+                            const slar_cnn* cnn, double* Uout, int* iters) {
+  if (!ws->lm_ready) return SLAR_E_INVAL;
+  const GridDev& G = ws->G;
+  const int K = G.dv + 2, Nx = G.nx, n = K * Nx;
+  const int m = KRY_RESTART;
+  const LmLayout L = lm_layout(G);
+  KryBufs b = kry_bufs(ws, n, m);
+  double* hdev = ws->small;           // scratch: small device vectors
+  double* part = ws->small + 256;
+  Krylov kr{ws, s, n, part, hdev, (double*)ws->host_pinned};
+  const unsigned nb = (n + 255) / 256;
+  // U_hist and b
+  double* Uhist = b.r;   // reuse r region for U_hist (r used only in restarts below -> own copy)
+  double* Uhist_store = b.x;
+  double bdt = dt;
+  if (bdf >= 2 && Unm1 != nullptr) {
+    k_axpby<<<nb, 256, 0, s>>>(n, 4.0 / 3.0, Un, 0.0, Uhist_store, -1.0 / 3.0, Unm1);
+    bdt = 2.0 / 3.0 * dt;
+  } else {
+    HIP_TRY(hipMemcpyAsync(Uhist_store, Un, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
+  (void)Uhist;
+  double* U = b.U;
+  HIP_TRY(hipMemcpyAsync(U, ws->lm + L.U0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  const double eps = 2.220446049250313e-16;
+  int newton = 0, krylov = 0;
+  bool converged = false;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  double* hh = (double*)ws->host_pinned;
+  for (int it = 0; it <= KRY_MAX_NEWTON; ++it) {
+    if (macro_residual(s, ws, U, Uhist_store, bdt, b.g0) != hipSuccess) return SLAR_E_HIP;
+    const double gn = kr.norm(b.g0);
+    if (!std::isfinite(gn)) return SLAR_E_NUMERIC;
+    const double rms = gn / std::sqrt((double)n);
+    if (rms <= newton_tol) { converged = true; break; }
+    if (it == KRY_MAX_NEWTON) break;
+    const double Un_norm = kr.norm(U);
+    // FGMRES on J d = -g0, d0 = 0
+    HIP_TRY(hipMemsetAsync(b.d, 0, sizeof(double) * n, s));
+    const double bn = gn;
+    double beta = gn;
+    // r = -g0
+    k_axpby<<<nb, 256, 0, s>>>(n, -1.0, b.g0, 0.0, b.r, 0.0, nullptr);
+    int kits = 0;
+    bool done = false;
+    while (!done && kits < KRY_MAXIT) {
+      k_axpby<<<nb, 256, 0, s>>>(n, 1.0 / beta, b.r, 0.0, b.V, 0.0, nullptr);
+      std::fill(H.begin(), H.end(), 0.0);
+      std::fill(gv.begin(), gv.end(), 0.0);
+      gv[0] = beta;
+      int jl = 0;
+      for (int j = 0; j < m; ++j) {
+        double* vj = b.V + (size_t)j * n;
+        double* zj = cnn ? b.Z + (size_t)j * n : vj;
+        if (cnn) {
+          if (cnn_apply(s, ws, cnn, vj, U, zj) != hipSuccess) return SLAR_E_HIP;
+        }
+        // w = J z  by finite differences
+        const double zn = kr.norm(zj);
+        const double h = std::sqrt(eps) * (1.0 + Un_norm) / (zn > 0 ? zn : 1.0);
+        k_axpby<<<nb, 256, 0, s>>>(n, h, zj, 0.0, b.Uh, 1.0, U);
+        if (macro_residual(s, ws, b.Uh, Uhist_store, bdt, b.Gh) != hipSuccess) return SLAR_E_HIP;
+        k_axpby<<<nb, 256, 0, s>>>(n, 1.0 / h, b.Gh, 0.0, b.w, -1.0 / h, b.g0);
+        // CGS2
+        if (kr.dots(b.V, n, j + 1, b.w, hdev) != hipSuccess) return SLAR_E_HIP;
+        k_subtract_combo<<<nb, 256, 0, s>>>(n, j + 1, b.V, n, hdev, b.w);
+        if (kr.dots(b.V, n, j + 1, b.w, hdev + SLAR_KMAX) != hipSuccess) return SLAR_E_HIP;
+        k_subtract_combo<<<nb, 256, 0, s>>>(n, j + 1, b.V, n, hdev + SLAR_KMAX, b.w);
+        if (kr.dots(b.w, 0, 1, b.w, hdev + 2 * SLAR_KMAX) != hipSuccess) return SLAR_E_HIP;
+        HIP_TRY(hipMemcpyAsync(hh, hdev, sizeof(double) * (2 * SLAR_KMAX + 1), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[SLAR_KMAX + i];
+        const double hn = std::sqrt(std::max(hh[2 * SLAR_KMAX], 0.0));
+        H[(size_t)(j + 1) * m + j] = hn;
+        if (hn > 0) k_axpby<<<nb, 256, 0, s>>>(n, 1.0 / hn, b.w, 0.0, b.V + (size_t)(j + 1) * n, 0.0, nullptr);
+        for (int i = 0; i < j; ++i) {
+          const double t1 = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+          H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+          H[(size_t)i * m + j] = t1;
+        }
+        const double den = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+        cs[j] = den > 0 ? H[(size_t)j * m + j] / den : 1.0;
+        sn[j] = den > 0 ? H[(size_t)(j + 1) * m + j] / den : 0.0;
+        H[(size_t)j * m + j] = den;
+        H[(size_t)(j + 1) * m + j] = 0.0;
+        gv[j + 1] = -sn[j] * gv[j];
+        gv[j] = cs[j] * gv[j];
+        ++kits;
+        jl = j;
+        if (std::fabs(gv[j + 1]) <= krylov_tol * bn || kits >= KRY_MAXIT || den == 0.0) break;
+      }
+      const int kk = jl + 1;
+      for (int i = kk - 1; i >= 0; --i) {
+        double acc = gv[i];
+        for (int q = i + 1; q < kk; ++q) acc -= H[(size_t)i * m + q] * y[q];
+        y[i] = H[(size_t)i * m + i] != 0 ? acc / H[(size_t)i * m + i] : 0.0;
+      }
+      for (int i = 0; i < kk; ++i) hh[i] = y[i];
+      HIP_TRY(hipMemcpyAsync(hdev, hh, sizeof(double) * kk, hipMemcpyHostToDevice, s));
+      k_add_combo<<<nb, 256, 0, s>>>(n, kk, cnn ? b.Z : b.V, n, hdev, b.d);
+      // true residual r = -g0 - J d
+      const double dn = kr.norm(b.d);
+      if (dn == 0.0) break;
+      const double h = std::sqrt(eps) * (1.0 + Un_norm) / dn;
+      k_axpby<<<nb, 256, 0, s>>>(n, h, b.d, 0.0, b.Uh, 1.0, U);
+      if (macro_residual(s, ws, b.Uh, Uhist_store, bdt, b.Gh) != hipSuccess) return SLAR_E_HIP;
+      k_axpby<<<nb, 256, 0, s>>>(n, -1.0 / h, b.Gh, 0.0, b.r, 1.0 / h - 1.0, b.g0);
+      beta = kr.norm(b.r);
+      if (beta <= krylov_tol * bn) done = true;
+    }
+    krylov += kits;
+    // exact step on the per-component mean
+    k_comp_means<<<K, 256, 0, s>>>(Nx, b.d, b.g0, hdev + 3 * SLAR_KMAX);
+    k_meanfix<<<nb, 256, 0, s>>>(Nx, K, hdev + 3 * SLAR_KMAX, hdev + 3 * SLAR_KMAX + 8, b.d);
+    k_axpby<<<nb, 256, 0, s>>>(n, 1.0, b.d, 1.0, U, 0.0, nullptr);
+    ++newton;
+  }
+  HIP_TRY(hipMemcpyAsync(Uout, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (iters) { iters[0] = newton; iters[1] = krylov; }
+  return converged ? SLAR_OK : SLAR_E_NOCONV;
+}
+
+// --------------------------------------------------------------- project
+__global__ void k_project(int Nx, int Nv, int dv, int r, int ldo, const double* __restrict__ Uf,
+                          const double* __restrict__ phiE, const double* __restrict__ scal,
+                          const double* __restrict__ Cstar, const double* __restrict__ Q,
+                          double* __restrict__ Xo, double* __restrict__ Po, int dx) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int K = dv + 2;
+  if (e < Nx) {
+    double ep = 0.0;
+    for (int m = 0; m < dx; ++m) {
+      const double Em = phiE[(size_t)(1 + m) * Nx + e];
+      ep += Em * Em;
+    }
+    ep *= 0.5;
+    double Mr[4], C[4];
+    for (int q = 0; q <= dv; ++q) Mr[q] = Uf[(size_t)q * Nx + e];
+    Mr[dv + 1] = 2.0 * (Uf[(size_t)(dv + 1) * Nx + e] - ep);
+    coeffs_at(dv, scal, Mr, C);
+    for (int k = 0; k < K; ++k) Xo[(size_t)e * ldo + r + k] = C[k] - Cstar[(size_t)k * Nx + e];
+  }
+  if (e < Nv)
+    for (int k = 0; k < K; ++k) Po[(size_t)e * ldo + r + k] = Q[(size_t)e * K + k];
+}
+
+slar_status lomac_project_run(hipStream_t s, Workspace* ws, const slar_frames& Fs,
+                              const double* Unew, slar_frames* out) {
+  if (!ws->lm_ready) return SLAR_E_INVAL;
+  const GridDev& G = ws->G;
+  const LmLayout L = lm_layout(G);
+  const int K = G.dv + 2;
+  MacroBufs b = macro_bufs(ws);
+  if (copy2d(s, G.nx, Fs.r, Fs.X, Fs.ld, out->X, out->ld, nullptr) != hipSuccess) return SLAR_E_HIP;
+  if (copy2d(s, G.nv, Fs.r, Fs.P, Fs.ld, out->P, out->ld, nullptr) != hipSuccess) return SLAR_E_HIP;
+  if (poisson_run(s, ws, Unew, ws->n_i, b.phiE, b.phiE + G.nx) != hipSuccess) return SLAR_E_HIP;
+  const int mx = std::max(G.nx, G.nv);
+  k_project<<<(mx + 255) / 256, 256, 0, s>>>(G.nx, G.nv, G.dv, Fs.r, out->ld, Unew, b.phiE,
+                                             ws->lm + L.scal, ws->lm + L.Cstar, ws->lm + L.Q,
+                                             out->X, out->P, G.dx);
+  HIP_TRY(hipGetLastError());
+  out->r = Fs.r + K;
+  return SLAR_OK;
+}
+
+}  // namespace slar

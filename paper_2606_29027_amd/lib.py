@@ -1,0 +1,244 @@
+"""ctypes binding of ``libslar.so`` (argument marshalling only).
+
+Every function here converts torch tensors / Python numbers to the C ABI of
+``include/slar.h`` and raises on a non-OK status.  No arithmetic of the
+method happens in Python: every step runs in the HIP kernels of the library.
+Device memory and streams come from PyTorch.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslar.so")
+
+SLAR_OK, SLAR_E_INVAL, SLAR_E_NOMEM, SLAR_E_RANK_CAP, SLAR_E_NOCONV, SLAR_E_NUMERIC, SLAR_E_HIP = range(7)
+F32, F64 = 0, 1
+
+EXPORTS = (
+    "slar_status_str", "slar_workspace_create", "slar_workspace_destroy", "slar_ht_sample",
+    "slar_frames_from_ht", "slar_frame_sample", "slar_cross_update", "slar_truncate",
+    "slar_moments", "slar_poisson", "slar_conserved", "slar_lomac_prepare", "slar_macro_solve",
+    "slar_lomac_project",
+)
+
+
+class Grid(C.Structure):
+    _fields_ = [("dx", C.c_int32), ("dv", C.c_int32), ("n", C.c_int32 * 4),
+                ("lo", C.c_double * 4), ("hi", C.c_double * 4)]
+
+
+class HT(C.Structure):
+    _fields_ = [("d", C.c_int32), ("rank", C.c_int32 * 6), ("dtype", C.c_int32),
+                ("leaf", C.c_void_p * 4), ("B12", C.c_void_p), ("B34", C.c_void_p),
+                ("root", C.c_void_p)]
+
+
+class Frames(C.Structure):
+    _fields_ = [("r", C.c_int32), ("ld", C.c_int32), ("X", C.c_void_p), ("P", C.c_void_p)]
+
+
+class Adv(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("order", C.c_int32), ("tau", C.c_double),
+                ("cv", C.c_double), ("E", C.c_void_p * 2), ("cE", C.c_double * 2)]
+
+
+class LowRank(C.Structure):
+    _fields_ = [("k", C.c_int32), ("U", C.c_void_p), ("V", C.c_void_p)]
+
+
+class CrossInfo(C.Structure):
+    _fields_ = [("rank", C.c_int32), ("iterations", C.c_int32), ("probe_rounds", C.c_int32),
+                ("converged", C.c_int32), ("samples", C.c_int64)]
+
+
+class SlarError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; fails loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: run __graft_entry__.build() first")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "slar_status_str": (C.c_char_p, [i32]),
+        "slar_workspace_create": (i32, [P(Grid), i32, P(vp)]),
+        "slar_workspace_destroy": (i32, [vp]),
+        "slar_ht_sample": (i32, [P(Grid), P(HT), P(Adv), i64, vp, vp, vp]),
+        "slar_frames_from_ht": (i32, [P(Grid), P(HT), P(Frames), vp, vp]),
+        "slar_frame_sample": (i32, [P(Grid), P(Frames), P(Adv), i32, i64, vp, vp, vp, vp]),
+        "slar_cross_update": (i32, [P(Grid), P(Frames), P(Adv), i32, dbl, i32, i32, vp,
+                                    P(LowRank), P(CrossInfo), vp, vp]),
+        "slar_truncate": (i32, [P(Grid), P(LowRank), dbl, i32, P(HT), vp, vp]),
+        "slar_moments": (i32, [P(Grid), P(Frames), vp, vp, vp]),
+        "slar_poisson": (i32, [P(Grid), vp, dbl, vp, vp, vp, vp]),
+        "slar_conserved": (i32, [P(Grid), P(Frames), dbl, vp, vp, vp]),
+        "slar_lomac_prepare": (i32, [P(Grid), P(HT), P(Frames), dbl, dbl, vp, vp]),
+        "slar_macro_solve": (i32, [P(Grid), vp, vp, dbl, i32, dbl, dbl, vp, vp, P(i32), vp, vp]),
+        "slar_lomac_project": (i32, [P(Grid), P(Frames), vp, P(Frames), vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_str(s: int) -> str:
+    return load().slar_status_str(int(s)).decode()
+
+
+def _check(status, where, ok=(SLAR_OK,)):
+    if status not in ok:
+        raise SlarError(status, where)
+    return status
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_grid(p) -> Grid:
+    g = Grid()
+    g.dx, g.dv = p.dx, p.dv
+    for m in range(p.dx + p.dv):
+        g.n[m] = int(p.n[m]); g.lo[m] = float(p.lo[m]); g.hi[m] = float(p.hi[m])
+    return g
+
+
+class Workspace:
+    def __init__(self, grid: Grid, rmax: int):
+        self.grid = grid
+        h = C.c_void_p()
+        _check(load().slar_workspace_create(C.byref(grid), int(rmax), C.byref(h)), "slar_workspace_create")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.slar_workspace_destroy(self.h)
+            self.h = None
+
+
+def make_ht(tensors: dict, d: int, dtype: int) -> HT:
+    """tensors: {"leaves": [...], "B12", "B34", "root"} of contiguous device tensors."""
+    H = HT()
+    H.d = d
+    H.dtype = dtype
+    L = tensors["leaves"]
+    for m in range(d):
+        H.leaf[m] = L[m].data_ptr()
+        H.rank[m] = L[m].shape[1]
+    H.root = tensors["root"].data_ptr()
+    if d == 4:
+        H.B12 = tensors["B12"].data_ptr(); H.B34 = tensors["B34"].data_ptr()
+        H.rank[4] = tensors["root"].shape[0]; H.rank[5] = tensors["root"].shape[1]
+    H._keep = tensors
+    return H
+
+
+def make_adv(kind, tau, cv=1.0, E=None, E2=None, cE=(1.0, 0.0), order=3) -> Adv:
+    a = Adv()
+    a.kind, a.order, a.tau, a.cv = int(kind), int(order), float(tau), float(cv)
+    a.E[0] = None if E is None else E.data_ptr()
+    a.E[1] = None if E2 is None else E2.data_ptr()
+    a.cE[0], a.cE[1] = float(cE[0]), float(cE[1])
+    a._keep = (E, E2)          # the descriptor owns references to its tensors
+    return a
+
+
+def frames(X, P, r) -> Frames:
+    f = Frames()
+    f.r, f.ld = int(r), int(X.shape[1])
+    f.X, f.P = X.data_ptr(), P.data_ptr()
+    f._keep = (X, P)
+    return f
+
+
+# ------------------------------------------------------------ entry points
+def slar_ht_sample(grid, H, adv, idx, out):
+    _check(load().slar_ht_sample(C.byref(grid), C.byref(H), C.byref(adv), int(idx.shape[0]),
+                                 _ptr(idx), _ptr(out), _stream()), "slar_ht_sample")
+
+
+def slar_frames_from_ht(grid, H, F: Frames, ws):
+    _check(load().slar_frames_from_ht(C.byref(grid), C.byref(H), C.byref(F), ws.h, _stream()),
+           "slar_frames_from_ht")
+    return F
+
+
+def slar_frame_sample(grid, F, adv, dtype, idx, out, ws):
+    _check(load().slar_frame_sample(C.byref(grid), C.byref(F), C.byref(adv), int(dtype),
+                                    int(idx.shape[0]), _ptr(idx), _ptr(out), ws.h, _stream()),
+           "slar_frame_sample")
+
+
+def slar_cross_update(grid, src, adv, dtype, tol, kmax, probes, U, V, ws):
+    lr = LowRank(0, U.data_ptr(), V.data_ptr())
+    lr._keep = (U, V)
+    info = CrossInfo()
+    nprobe = 0 if probes is None else int(probes.shape[0])
+    st = load().slar_cross_update(C.byref(grid), C.byref(src), C.byref(adv), int(dtype),
+                                  float(tol), int(kmax), nprobe, _ptr(probes), C.byref(lr),
+                                  C.byref(info), ws.h, _stream())
+    _check(st, "slar_cross_update", ok=(SLAR_OK, SLAR_E_RANK_CAP))
+    return lr, info, st
+
+
+def slar_truncate(grid, lr, tol, rmax, out_ht: HT, ws):
+    st = load().slar_truncate(C.byref(grid), C.byref(lr), float(tol), int(rmax), C.byref(out_ht),
+                              ws.h, _stream())
+    _check(st, "slar_truncate", ok=(SLAR_OK, SLAR_E_RANK_CAP))
+    return st
+
+
+def slar_moments(grid, F, M, ws):
+    _check(load().slar_moments(C.byref(grid), C.byref(F), _ptr(M), ws.h, _stream()), "slar_moments")
+
+
+def slar_poisson(grid, n_e, n_i, phi, E, ws):
+    _check(load().slar_poisson(C.byref(grid), _ptr(n_e), float(n_i), _ptr(phi), _ptr(E), ws.h,
+                               _stream()), "slar_poisson")
+
+
+def slar_conserved(grid, F, n_i, U, ws):
+    _check(load().slar_conserved(C.byref(grid), C.byref(F), float(n_i), _ptr(U), ws.h, _stream()),
+           "slar_conserved")
+
+
+def slar_lomac_prepare(grid, H, F, delta, n_i, ws):
+    _check(load().slar_lomac_prepare(C.byref(grid), C.byref(H), C.byref(F), float(delta),
+                                     float(n_i), ws.h, _stream()), "slar_lomac_prepare")
+
+
+def slar_macro_solve(grid, U_n, U_nm1, dt, bdf, newton_tol, krylov_tol, cnn, U_out, ws):
+    iters = (C.c_int32 * 2)()
+    st = load().slar_macro_solve(C.byref(grid), _ptr(U_n), _ptr(U_nm1), float(dt), int(bdf),
+                                 float(newton_tol), float(krylov_tol), cnn, _ptr(U_out), iters,
+                                 ws.h, _stream())
+    _check(st, "slar_macro_solve", ok=(SLAR_OK, SLAR_E_NOCONV))
+    return st, (iters[0], iters[1])
+
+
+def slar_lomac_project(grid, Fs, U_new, out: Frames, ws):
+    _check(load().slar_lomac_project(C.byref(grid), C.byref(Fs), _ptr(U_new), C.byref(out), ws.h,
+                                     _stream()), "slar_lomac_project")
+    return out

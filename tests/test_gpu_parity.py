@@ -1,0 +1,153 @@
+"""GPU parity: every C-ABI entry point against the CPU FP64 oracle on the
+same seeded inputs.  Tolerances (normwise max|a-b|/max|b|):
+  FP64 arithmetic 1e-12; FP32 contractions 1e-6 (single-precision sums of
+  at most a few thousand O(1) terms with orthonormal leaves).
+Samples whose foot lies on a cell face (two valid stencils) are compared
+with both oracle readings."""
+import math
+
+import numpy as np
+import pytest
+
+import slar_inputs as SI
+from oracle import feet as FT
+from oracle import ht as HT
+from oracle import spectral as SP
+from oracle import step as ST
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2606_29027_amd import lib as L  # noqa: E402
+from gpu_util import dev, ht_to_dev, normwise, ht_from_dev  # noqa: E402
+
+
+def _oracle_samples(F, p, idx, kind, tau, cv, E, width):
+    foot = FT.feet(idx, p.lo, p.hi, p.n, p.dx, kind, tau, cv, E)
+    rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, width, kind, p.dx)
+    amb = FT.face_ambiguous(foot, p.lo, p.hi, p.n, kind, p.dx)
+    return HT.sample(F, rows, wts), amb
+
+
+CASES = [
+    ("landau1d", 20, 0, 5, 1.7), ("landau1d", 20, 1, 5, 1.3), ("landau1d", 20, 2, 5, 0.9),
+    ("landau1d", 33, 2, 3, 2.2), ("landau2d", 10, 2, 3, 0.8), ("landau2d", 9, 0, 3, 0.6),
+]
+
+
+@pytest.mark.parametrize("name,N,kind,width,tau", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ht_sample_matches_oracle(name, N, kind, width, tau, prec):
+    p = SI.config(name, n=N)
+    d = p.d
+    ranks = (6, 9) if d == 2 else (4, 5, 3, 6, 7, 5)
+    F = SI.random_ht(d, p.n, ranks, seed=21)
+    idx = SI.random_requests(p.n, 1000 + 37, seed=5)        # ragged tail
+    nx = p.n[: p.dx]
+    E1 = np.stack([0.6 * SI.random_field(nx, 40 + m) for m in range(p.dx)])
+    E2 = np.stack([0.6 * SI.random_field(nx, 50 + m) for m in range(p.dx)])
+    cE = (-1.0 / 12.0, 3.0 / 4.0)
+    Eo = FT.frozen_field([E1, E2], cE)
+    ref, amb = _oracle_samples(F, p, idx, kind, tau, 1.0, Eo, width)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    T = ht_to_dev(F, tdt)
+    H = L.make_ht(T, d, L.F64 if prec == "f64" else L.F32)
+    g = L.make_grid(p)
+    out = torch.zeros(len(idx), dtype=tdt, device="cuda")
+    adv = L.make_adv(kind, tau, 1.0, dev(E1), dev(E2), cE, order=width)
+    L.slar_ht_sample(g, H, adv, dev(idx, torch.int32), out)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    tol = 1e-12 if prec == "f64" else 1e-6
+    keep = ~amb
+    assert keep.sum() > 0.9 * len(idx)
+    assert normwise(got[keep], ref[keep]) < tol
+
+
+def test_ht_sample_empty_request_and_invalid_args():
+    p = SI.config("landau2d", n=8)
+    F = SI.random_ht(4, p.n, (2, 2, 2, 2, 2, 2), seed=1)
+    T = ht_to_dev(F)
+    H = L.make_ht(T, 4, L.F64)
+    g = L.make_grid(p)
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    idx = torch.zeros((0, 4), dtype=torch.int32, device="cuda")
+    L.slar_ht_sample(g, H, L.make_adv(0, 0.1), idx, out)
+    with pytest.raises(L.SlarError):
+        L.slar_ht_sample(g, H, L.make_adv(2, 0.1, 1.0, None), dev(np.zeros((4, 4)), torch.int32), out)
+
+
+@pytest.mark.parametrize("name,N", [("landau1d", 24), ("landau2d", 12)])
+@pytest.mark.parametrize("prec", [L.F64, L.F32])
+def test_frame_sampler_matches_oracle(name, N, prec):
+    p = SI.config(name, n=N)
+    d = p.d
+    ranks = (7, 5) if d == 2 else (4, 5, 3, 6, 9, 7)
+    F = SI.random_ht(d, p.n, ranks, seed=3)
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 40)
+    T = ht_to_dev(F)
+    H = L.make_ht(T, d, L.F64)
+    Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
+    X = torch.zeros((Nx, 12), dtype=torch.float64, device="cuda")
+    P = torch.zeros((Nv, 12), dtype=torch.float64, device="cuda")
+    Fr = L.slar_frames_from_ht(g, H, L.frames(X, P, 0), ws)
+    width = p.order if d == 2 else 3
+    E = np.stack([0.5 * SI.random_field(p.n[: p.dx], 7 + m) for m in range(p.dx)])
+    idx = SI.random_requests(p.n, 2000 + 3, seed=9)
+    ref, amb = _oracle_samples(F, p, idx, 2, 0.7, 1.0, E, width)
+    out = torch.zeros(len(idx), dtype=torch.float64, device="cuda")
+    L.slar_frame_sample(g, Fr, L.make_adv(2, 0.7, 1.0, dev(E), order=width), prec, dev(idx, torch.int32), out, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    tol = 1e-12 if prec == L.F64 else 1e-6
+    assert normwise(got[~amb], ref[~amb]) < tol
+    # frames themselves equal the node frames of the oracle
+    Xo = HT.x_frame(F).reshape(Nx, -1)
+    Po = (HT.v_frame(F).reshape(Nv, -1) @ F["root"].T)
+    assert normwise(X[:, : Fr.r].cpu().numpy(), Xo) < 1e-13
+    assert normwise(P[:, : Fr.r].cpu().numpy(), Po) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(64,), (48,), (32, 32), (24, 40)])
+def test_poisson_matches_oracle(shape):
+    dx = len(shape)
+    L_ = [4 * math.pi, 3.0][:dx]
+    p = SI.Problem("t", dx, dx, tuple(shape) * 2, tuple([0.0] * dx + [-6.0] * dx),
+                   tuple(L_ + [6.0] * dx), "landau", 0.1, 0.5)
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 8)
+    ne = 1.0 + 0.3 * SI.random_field(shape, 11, smooth=False)
+    phi_o, E_o = SP.poisson(ne, 1.0, L_)
+    phi = torch.zeros(int(np.prod(shape)), dtype=torch.float64, device="cuda")
+    E = torch.zeros((dx, int(np.prod(shape))), dtype=torch.float64, device="cuda")
+    L.slar_poisson(g, dev(ne.ravel()), 1.0, phi, E, ws)
+    torch.cuda.synchronize()
+    assert normwise(phi.cpu().numpy(), phi_o.ravel()) < 1e-12
+    assert normwise(E.cpu().numpy(), E_o.reshape(dx, -1)) < 1e-12
+
+
+@pytest.mark.parametrize("name,N", [("landau1d", 32), ("landau2d", 12)])
+def test_moments_match_oracle(name, N):
+    p = SI.config(name, n=N)
+    d = p.d
+    F = SI.random_ht(d, p.n, (5, 6) if d == 2 else (3, 4, 5, 3, 6, 5), seed=8)
+    o = ST.Oracle(p)
+    Mo = o.moments(F)
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 16)
+    T = ht_to_dev(F)
+    H = L.make_ht(T, d, L.F64)
+    Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
+    X = torch.zeros((Nx, 8), dtype=torch.float64, device="cuda")
+    P = torch.zeros((Nv, 8), dtype=torch.float64, device="cuda")
+    Fr = L.slar_frames_from_ht(g, H, L.frames(X, P, 0), ws)
+    M = torch.zeros((Mo.shape[0], Nx), dtype=torch.float64, device="cuda")
+    L.slar_moments(g, Fr, M, ws)
+    torch.cuda.synchronize()
+    Mg = M.cpu().numpy()
+    for q in range(Mo.shape[0]):
+        assert normwise(Mg[q], Mo[q].ravel()) < 1e-12, q
