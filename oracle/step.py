@@ -36,7 +36,7 @@ from . import spectral as SP
 
 
 class Oracle:
-    def __init__(self, p, probes=None, delta: float = LM.DELTA):
+    def __init__(self, p, probes=None, delta: float = LM.DELTA, newton_tol: float = 1e-10):
         self.p = p
         self.dx, self.dv = p.dx, p.dv
         self.n = tuple(p.n)
@@ -52,6 +52,7 @@ class Oracle:
         self.probes = probes
         self.delta = delta
         self.n_i = None
+        self.newton_tol = newton_tol
         self.stats = []
 
     # ------------------------------------------------------------ sampling
@@ -130,7 +131,7 @@ class Oracle:
             U_hist, b = (4.0 * U_n - U_nm1) / 3.0, 2.0 / 3.0
         sysm = MA.MacroSystem(Mstar, B, self.n_i, self.lengths, self.dvol_v, self.vgrids,
                               U_hist, b * h)
-        U, info = MA.jfnk(sysm, U0, precond=precond, record=record)
+        U, info = MA.jfnk(sysm, U0, newton_tol=self.newton_tol, precond=precond, record=record)
         Mraw = LM.raw_from_conserved(U, self.n_i, self.lengths)
         dC = LM.coefficients(Mraw, B) - sysm.Cstar
         Fn = dict(Fs)

@@ -216,6 +216,15 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restr
   for (int i = t; i < kp; i += blockDim.x) pairs[i] = i;
   __syncthreads();
   const int npair = kp / 2;
+  __shared__ double fro;
+  if (t == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < kp; ++i)
+      for (int j = 0; j < kp; ++j) acc += A[i][j] * A[i][j];
+    fro = acc;
+  }
+  __syncthreads();
+  const double floor_abs = 1e-300 + 1e-32 * fro;
   const int team = (npair > 0) ? max(1, min(32, 256 / npair)) : 1;  // power of 2 below
   int tm = 1;
   while (tm * 2 <= team) tm *= 2;
@@ -225,7 +234,8 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restr
     __syncthreads();
     for (int step = 0; step < kp - 1; ++step) {
       if (pid < npair) {
-        const int p = pairs[2 * pid], q = pairs[2 * pid + 1];
+        // circle-method round robin: position i meets position kp-1-i
+        const int p = pairs[pid], q = pairs[kp - 1 - pid];
         double al = 0.0, be = 0.0, ga = 0.0;
         for (int r = lane; r < kp; r += tm) {
           const double x = A[r][p], y = A[r][q];
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restr
           be += __shfl_xor(be, o, tm);
           ga += __shfl_xor(ga, o, tm);
         }
-        if (fabs(ga) > 1e-15 * sqrt(al * be) && ga != 0.0) {
+        if (fabs(ga) > 1e-14 * sqrt(al * be) && fabs(ga) > floor_abs) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
@@ -291,76 +301,117 @@ hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* s
   return hipGetLastError();
 }
 
-// ------------------------------------------ symmetric Jacobi eigensolver
-// G (n x n, symmetric) = V diag(lam) V^T, lam descending; V row-major with
-// eigenvectors as columns, written to Vout (n x n).  Matrix kept in LDS.
-__global__ __launch_bounds__(256) void k_eig_jacobi(int n, const double* __restrict__ Gin,
-                                                    double* __restrict__ lam,
-                                                    double* __restrict__ Vw,
-                                                    double* __restrict__ Vout) {
-  extern __shared__ double smem[];
-  double* G = smem;                        // n*n
-  __shared__ int pairs[SLAR_NMAX];
-  __shared__ double cs[SLAR_NMAX / 2], sn[SLAR_NMAX / 2];
+// ------------------------------------- symmetric PSD eigendecomposition
+// G (n x n, symmetric positive semidefinite, n <= 128) = U diag(lam) U^T,
+// lam descending, for the leading eigenpairs.  Two stages in one block:
+//  1. pivoted Cholesky G ~ L L^T, L (n x c) built column by column in LDS
+//     (pivot = largest remaining diagonal), stopping when the remaining
+//     diagonal drops below 1e-30 trace or after SLAR_KMAX columns;
+//  2. one-sided Jacobi on the columns of L: the rotated, normalised
+//     columns are the eigenvectors of L L^T and their squared norms the
+//     eigenvalues.
+// Eigenvalues beyond the factor rank are returned as 0 with zero vectors.
+__global__ __launch_bounds__(256) void k_eig_psd(int n, const double* __restrict__ G,
+                                                 double* __restrict__ lam,
+                                                 double* __restrict__ Uout) {
+  __shared__ double Lc[SLAR_NMAX][SLAR_KMAX + 1];   // L[i][j]
+  __shared__ double dres[SLAR_NMAX];
+  __shared__ unsigned char taken[SLAR_NMAX];
+  __shared__ double red[256];
+  __shared__ int redi[256];
+  __shared__ int ncols_s;
+  __shared__ int pairs[SLAR_KMAX + 1];
   __shared__ int rotated;
-  __shared__ double dg[SLAR_NMAX];
-  __shared__ int order[SLAR_NMAX];
+  __shared__ double nrm[SLAR_KMAX + 1];
+  __shared__ int order[SLAR_KMAX + 1];
   const int t = threadIdx.x;
-  const int np = (n + 1) & ~1;
-  for (int e = t; e < np * np; e += blockDim.x) {
-    const int i = e / np, j = e % np;
-    G[e] = (i < n && j < n) ? Gin[i * n + j] : 0.0;
-    Vw[e] = (i == j) ? 1.0 : 0.0;
-  }
-  for (int i = t; i < np; i += blockDim.x) pairs[i] = i;
+  double trace = 0.0;
+  for (int i = 0; i < n; ++i) trace += fmax(G[(size_t)i * n + i], 0.0);
+  for (int i = t; i < n; i += blockDim.x) { dres[i] = fmax(G[(size_t)i * n + i], 0.0); taken[i] = 0; }
+  for (int e = t; e < SLAR_NMAX * (SLAR_KMAX + 1); e += blockDim.x) Lc[e / (SLAR_KMAX + 1)][e % (SLAR_KMAX + 1)] = 0.0;
   __syncthreads();
-  const int npair = np / 2;
-  for (int sweep = 0; sweep < 30; ++sweep) {
+  const double stop = 1e-30 * trace + 1e-300;
+  int c = 0;
+  for (; c < SLAR_KMAX && c < n; ++c) {
+    // pivot: largest remaining diagonal (lowest index on ties)
+    double m = -1.0; int mi = n;
+    for (int i = t; i < n; i += blockDim.x)
+      if (!taken[i] && (dres[i] > m)) { m = dres[i]; mi = i; }
+    red[t] = m; redi[t] = mi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) {
+        if (red[t + o] > red[t] || (red[t + o] == red[t] && redi[t + o] < redi[t])) {
+          red[t] = red[t + o]; redi[t] = redi[t + o];
+        }
+      }
+      __syncthreads();
+    }
+    const double dp = red[0];
+    const int p = redi[0];
+    __syncthreads();
+    if (!(dp > stop) || p >= n) break;
+    const double sq = sqrt(dp);
+    for (int i = t; i < n; i += blockDim.x) {
+      double v = 0.0;
+      if (!taken[i] && i != p) {
+        v = G[(size_t)p * n + i];
+        for (int j = 0; j < c; ++j) v -= Lc[i][j] * Lc[p][j];
+        v /= sq;
+      }
+      if (i == p) v = sq;
+      Lc[i][c] = v;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += blockDim.x) {
+      if (i == p) { taken[i] = 1; dres[i] = 0.0; }
+      else if (!taken[i]) dres[i] = fmax(dres[i] - Lc[i][c] * Lc[i][c], 0.0);
+    }
+    __syncthreads();
+  }
+  if (t == 0) ncols_s = c;
+  __syncthreads();
+  const int nc = ncols_s;
+  const int kp = (nc + 1) & ~1;
+  for (int i = t; i < kp; i += blockDim.x) pairs[i] = i;
+  __syncthreads();
+  const int npair = kp / 2;
+  int tm = 1;
+  if (npair > 0) { const int team = max(1, min(32, 256 / npair)); while (tm * 2 <= team) tm *= 2; }
+  const int pid = t / tm, lane = t % tm;
+  const double floor_abs = 1e-32 * trace * trace + 1e-300;
+  for (int sweep = 0; sweep < 30 && kp >= 2; ++sweep) {
     if (t == 0) rotated = 0;
     __syncthreads();
-    for (int step = 0; step < np - 1; ++step) {
-      for (int pi = t; pi < npair; pi += blockDim.x) {
-        const int p = pairs[2 * pi], q = pairs[2 * pi + 1];
-        const double app = G[p * np + p], aqq = G[q * np + q], apq = G[p * np + q];
-        double c = 1.0, s_ = 0.0;
-        if (apq != 0.0 && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
-          const double th = (aqq - app) / (2.0 * apq);
-          const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          c = 1.0 / sqrt(tt * tt + 1.0);
-          s_ = tt * c;
-          rotated = 1;
+    for (int step = 0; step < kp - 1; ++step) {
+      if (pid < npair) {
+        const int p = pairs[pid], q = pairs[kp - 1 - pid];
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int r = lane; r < n; r += tm) {
+          const double x = Lc[r][p], y = Lc[r][q];
+          al += x * x; be += y * y; ga += x * y;
         }
-        cs[pi] = c; sn[pi] = s_;
-      }
-      __syncthreads();
-      // rows: G <- J^T G
-      for (int e = t; e < npair * np; e += blockDim.x) {
-        const int pi = e / np, j = e % np;
-        const double c = cs[pi], s_ = sn[pi];
-        if (s_ == 0.0) continue;
-        const int p = pairs[2 * pi], q = pairs[2 * pi + 1];
-        const double gp = G[p * np + j], gq = G[q * np + j];
-        G[p * np + j] = c * gp - s_ * gq;
-        G[q * np + j] = s_ * gp + c * gq;
-      }
-      __syncthreads();
-      // columns: G <- G J, and V <- V J
-      for (int e = t; e < npair * np; e += blockDim.x) {
-        const int pi = e / np, i = e % np;
-        const double c = cs[pi], s_ = sn[pi];
-        if (s_ == 0.0) continue;
-        const int p = pairs[2 * pi], q = pairs[2 * pi + 1];
-        const double gp = G[i * np + p], gq = G[i * np + q];
-        G[i * np + p] = c * gp - s_ * gq;
-        G[i * np + q] = s_ * gp + c * gq;
-        const double vp = Vw[i * np + p], vq = Vw[i * np + q];
-        Vw[i * np + p] = c * vp - s_ * vq;
-        Vw[i * np + q] = s_ * vp + c * vq;
+        for (int o = tm / 2; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, tm);
+          be += __shfl_xor(be, o, tm);
+          ga += __shfl_xor(ga, o, tm);
+        }
+        if (fabs(ga) > 1e-14 * sqrt(al * be) && fabs(ga) > floor_abs) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cc = 1.0 / sqrt(1.0 + tt * tt), sn = cc * tt;
+          for (int r = lane; r < n; r += tm) {
+            const double x = Lc[r][p], y = Lc[r][q];
+            Lc[r][p] = cc * x - sn * y;
+            Lc[r][q] = sn * x + cc * y;
+          }
+          if (lane == 0) rotated = 1;
+        }
       }
       __syncthreads();
       if (t == 0) {
-        const int last = pairs[np - 1];
-        for (int i = np - 1; i > 1; --i) pairs[i] = pairs[i - 1];
+        const int last = pairs[kp - 1];
+        for (int i = kp - 1; i > 1; --i) pairs[i] = pairs[i - 1];
         pairs[1] = last;
       }
       __syncthreads();
@@ -368,35 +419,36 @@ __global__ __launch_bounds__(256) void k_eig_jacobi(int n, const double* __restr
     if (!rotated) break;
     __syncthreads();
   }
-  for (int i = t; i < np; i += blockDim.x) dg[i] = (i < n) ? G[i * np + i] : -1e300;
+  for (int j = t; j < kp; j += blockDim.x) {
+    double acc = 0.0;
+    for (int r = 0; r < n; ++r) acc += Lc[r][j] * Lc[r][j];
+    nrm[j] = acc;
+  }
   __syncthreads();
-  for (int c = t; c < np; c += blockDim.x) {
+  for (int j = t; j < kp; j += blockDim.x) {
     int rank = 0;
-    for (int o = 0; o < np; ++o)
-      if (dg[o] > dg[c] || (dg[o] == dg[c] && o < c)) ++rank;
-    order[rank] = c;
+    for (int o = 0; o < kp; ++o)
+      if (nrm[o] > nrm[j] || (nrm[o] == nrm[j] && o < j)) ++rank;
+    order[rank] = j;
   }
   __syncthreads();
   for (int e = t; e < n * n; e += blockDim.x) {
     const int r = e / n, j = e % n;
-    Vout[e] = Vw[r * np + order[j]];
+    double v = 0.0;
+    if (j < nc) {
+      const int cidx = order[j];
+      const double s = sqrt(nrm[cidx]);
+      v = s > 0.0 ? Lc[r][cidx] / s : 0.0;
+    }
+    Uout[e] = v;
   }
-  for (int j = t; j < n; j += blockDim.x) lam[j] = dg[order[j]];
+  for (int j = t; j < n; j += blockDim.x) lam[j] = (j < nc) ? nrm[order[j]] : 0.0;
 }
 
 hipError_t eig_sym(hipStream_t s, int n, const double* G, double* lam, double* Vwork,
                    double* V) {
-  const int np = (n + 1) & ~1;
-  const size_t shm = (size_t)np * np * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_eig_jacobi,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       SLAR_NMAX * SLAR_NMAX * (int)sizeof(double));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  k_eig_jacobi<<<1, 256, shm, s>>>(n, G, lam, Vwork, V);
+  (void)Vwork;
+  k_eig_psd<<<1, 256, 0, s>>>(n, G, lam, V);
   return hipGetLastError();
 }
 

@@ -1,0 +1,192 @@
+"""One LoMaC-SLAR time step on the GPU, as a sequence of C-ABI calls.
+
+The step follows the flowchart of section 3.2 ("Fluid correction diagram"):
+SLAR_VP (eq. (slarvp), three frozen-field sub-flows of the third-order
+commutator-free exponential integrator, each one cross approximation +
+truncation) gives F*; the LoMaC closure of F* is prepared, the macroscopic
+system is solved by JFNK (backward Euler for the first step, BDF2 after), and
+the exact correction F^{n+1} = F* + sum_k dC_k Q_k is appended in frame form.
+The split 1D1V workload uses Strang splitting X(h/2) V(h) X(h/2) instead.
+
+This module only sequences library calls and owns the device buffers
+(PyTorch allocations); it does no arithmetic of the method itself.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import lib as L
+
+KCAP = 72          # frame columns (rank cap 64 + LoMaC columns)
+RCAP = 64
+
+
+class Solver:
+    def __init__(self, p, precision: int = L.F64, probes=None, delta: float = 1e-12,
+                 cnn=None, newton_tol: float = 1e-10, krylov_tol: float = 1e-4):
+        self.p = p
+        self.grid = L.make_grid(p)
+        self.ws = L.Workspace(self.grid, min(p.rmax, RCAP))
+        self.prec = precision
+        self.delta = delta
+        self.cnn = cnn
+        self.newton_tol = newton_tol
+        self.krylov_tol = krylov_tol
+        self.d = p.dx + p.dv
+        self.Nx = int(np.prod(p.n[: p.dx]))
+        self.Nv = int(np.prod(p.n[p.dx:]))
+        self.nmom = 5 if p.dv == 1 else 9
+        self.K = p.dv + 2
+        f64 = dict(dtype=torch.float64, device="cuda")
+        z = lambda *s: torch.zeros(*s, **f64)   # noqa: E731
+        self.frames_buf = [(z(self.Nx, KCAP), z(self.Nv, KCAP)) for _ in range(4)]
+        self.ht_buf = [self._ht_buffers() for _ in range(2)]
+        self.U = z(RCAP, self.Nx)
+        self.V = z(RCAP, self.Nv)
+        self.M = z(self.nmom, self.Nx)
+        self.E = [z(p.dx, self.Nx) for _ in range(3)]
+        self.Ubuf = [z(self.K, self.Nx) for _ in range(3)]
+        self.probes = None if probes is None else torch.as_tensor(
+            np.ascontiguousarray(probes), dtype=torch.int32, device="cuda")
+        self.n_i = None
+        self.state = None            # current frames (L.Frames)
+        self.state_slot = 0
+        self.U_n = None
+        self.U_nm1 = None
+        self.stats = []
+
+    # -------------------------------------------------------------- buffers
+    def _ht_buffers(self):
+        p = self.p
+        f64 = dict(dtype=torch.float64, device="cuda")
+        T = {"leaves": [torch.zeros(p.n[m] * RCAP, **f64) for m in range(self.d)],
+             "root": torch.zeros(RCAP * RCAP, **f64)}
+        if self.d == 4:
+            T["B12"] = torch.zeros(RCAP * RCAP * RCAP, **f64)
+            T["B34"] = torch.zeros(RCAP * RCAP * RCAP, **f64)
+        H = L.HT()
+        H.d = self.d
+        H.dtype = L.F64
+        for m in range(self.d):
+            H.leaf[m] = T["leaves"][m].data_ptr()
+        H.root = T["root"].data_ptr()
+        if self.d == 4:
+            H.B12 = T["B12"].data_ptr(); H.B34 = T["B34"].data_ptr()
+        H._keep = T
+        return H, T
+
+    def _frames(self, slot, r=0):
+        X, P = self.frames_buf[slot]
+        return L.frames(X, P, r)
+
+    # ---------------------------------------------------------------- setup
+    def set_initial(self, F0: dict):
+        """Upload an initial HT (host arrays, oracle layout) and build its frames."""
+        T = {"leaves": [torch.as_tensor(np.ascontiguousarray(U), dtype=torch.float64, device="cuda")
+                        for U in F0["leaves"]],
+             "root": torch.as_tensor(np.ascontiguousarray(F0["root"]), dtype=torch.float64, device="cuda")}
+        if self.d == 4:
+            for key in ("B12", "B34"):
+                b = F0[key]
+                T[key] = torch.as_tensor(np.ascontiguousarray(b.reshape(b.shape[0] * b.shape[1], b.shape[2])),
+                                         dtype=torch.float64, device="cuda")
+        H = L.make_ht(T, self.d, L.F64)
+        self.state = L.slar_frames_from_ht(self.grid, H, self._frames(0), self.ws)
+        self.state_slot = 0
+        L.slar_moments(self.grid, self.state, self.M, self.ws)
+        torch.cuda.synchronize()
+        # stationary neutralising ions: mean initial electron density
+        self.n_i = float(self.M[0].double().mean().item())
+        if self.p.lomac:
+            self.U_n = self.Ubuf[0]
+            L.slar_conserved(self.grid, self.state, self.n_i, self.U_n, self.ws)
+            self.U_nm1 = None
+
+    # ---------------------------------------------------------- components
+    def efield(self, F: L.Frames, out):
+        L.slar_moments(self.grid, F, self.M, self.ws)
+        L.slar_poisson(self.grid, self.M[0], self.n_i, None, out, self.ws)
+        return out
+
+    def slar(self, src: L.Frames, adv, ht_slot: int, frame_slot: int):
+        """One SLAR call: cross approximation + truncation + frames."""
+        lr, info, st = L.slar_cross_update(self.grid, src, adv, self.prec, self.p.tol, min(self.p.rmax, RCAP),
+                                           self.probes, self.U, self.V, self.ws)
+        H, _ = self.ht_buf[ht_slot]
+        L.slar_truncate(self.grid, lr, self.p.tol, min(self.p.rmax, RCAP), H, self.ws)
+        F = L.slar_frames_from_ht(self.grid, H, self._frames(frame_slot), self.ws)
+        self.stats.append({"rank": info.rank, "samples": int(info.samples), "iters": info.iterations,
+                           "probe_rounds": info.probe_rounds, "converged": info.converged,
+                           "ranks": tuple(H.rank[: (2 if self.d == 2 else 6)])})
+        return F, H
+
+    def _free_slots(self, n):
+        return [s for s in range(4) if s != self.state_slot][:n]
+
+    def slar_vp(self, h):
+        """Third-order commutator-free exponential integrator, section 3.1."""
+        p = self.p
+        sY2, sY3, sFs = self._free_slots(3)
+        E1 = self.efield(self.state, self.E[0])
+        Y2, _ = self.slar(self.state, L.make_adv(2, h / 3.0, 1.0, E1), 0, sY2)
+        E2 = self.efield(Y2, self.E[1])
+        Y3, _ = self.slar(self.state, L.make_adv(2, 2.0 * h / 3.0, 1.0, E2), 1, sY3)
+        E3 = self.efield(Y3, self.E[2])
+        Fs, Hs = self.slar(Y2, L.make_adv(2, h, 2.0 / 3.0, E1, E3, (-1.0 / 12.0, 3.0 / 4.0)), 1, sFs)
+        return Fs, Hs, sFs
+
+    def strang(self, h):
+        o = self.p.order
+        s1, s2, s3 = self._free_slots(3)
+        F1, _ = self.slar(self.state, L.make_adv(0, 0.5 * h, 1.0, order=o), 0, s1)
+        E = self.efield(F1, self.E[0])
+        F2, _ = self.slar(F1, L.make_adv(1, h, 1.0, E, order=o), 1, s2)
+        F3, H3 = self.slar(F2, L.make_adv(0, 0.5 * h, 1.0, order=o), 0, s3)
+        return F3, H3, s3
+
+    def step(self):
+        p = self.p
+        h = p.dt
+        t0 = time.perf_counter()
+        Fs, Hs, slot = self.strang(h) if p.split else self.slar_vp(h)
+        info = {}
+        if p.lomac:
+            L.slar_lomac_prepare(self.grid, Hs, Fs, self.delta, self.n_i, self.ws)
+            U_new = [u for u in self.Ubuf if u is not self.U_n and u is not self.U_nm1][0]
+            bdf = 1 if (self.U_nm1 is None or p.bdf == 1) else 2
+            st, (nn, nk) = L.slar_macro_solve(self.grid, self.U_n, self.U_nm1 if bdf == 2 else None, h, bdf,
+                                              self.newton_tol, self.krylov_tol, self.cnn, U_new, self.ws)
+            out_slot = [s for s in range(4) if s not in (slot,)][0]
+            Fn = L.slar_lomac_project(self.grid, Fs, U_new, self._frames(out_slot), self.ws)
+            self.U_nm1, self.U_n = self.U_n, U_new
+            self.state, self.state_slot = Fn, out_slot
+            info = {"newton": nn, "krylov": nk, "converged": st == L.SLAR_OK}
+        else:
+            self.state, self.state_slot = Fs, slot
+        torch.cuda.synchronize()
+        info["seconds"] = time.perf_counter() - t0
+        return info
+
+    # ---------------------------------------------------------- diagnostics
+    def dense(self):
+        """Full tensor (small grids only), shape p.n, via the frames on host."""
+        F = self.state
+        X, P = self.frames_buf[self.state_slot]
+        A = X[:, : F.r].cpu().numpy() @ P[:, : F.r].cpu().numpy().T
+        return A.reshape(tuple(self.p.n))
+
+    def diagnostics(self):
+        p = self.p
+        L.slar_moments(self.grid, self.state, self.M, self.ws)
+        L.slar_poisson(self.grid, self.M[0], self.n_i, None, self.E[0], self.ws)
+        M = self.M.cpu().numpy()
+        E = self.E[0].cpu().numpy()
+        dvol = float(np.prod([(p.hi[m] - p.lo[m]) / p.n[m] for m in range(p.dx)]))
+        ep = 0.5 * np.sum(E * E, axis=0)
+        return {"elec_energy": float(ep.sum() * dvol), "mass": float(M[0].sum() * dvol),
+                "momentum": [float(M[1 + m].sum() * dvol) for m in range(p.dv)],
+                "energy": float((0.5 * M[p.dv + 1] + ep).sum() * dvol)}

@@ -24,17 +24,17 @@ def normwise(a, b):
     return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
 
 
-def ht_from_dev(H, T, d):
-    """Read back an HT written by slar_truncate into numpy (oracle layout)."""
+def ht_from_dev(H, T, d, n):
+    """Read back an HT written by slar_truncate (packed leaves [n_m][r_m] at
+    the start of each flat buffer) into numpy (oracle layout)."""
     rk = list(H.rank)
-    L = [T["leaves"][m][: T["leaves"][m].shape[0]].cpu().numpy().ravel()[: T["leaves"][m].shape[0] * rk[m]]
-         .reshape(T["leaves"][m].shape[0], rk[m]) for m in range(d)]
-    out = {"leaves": L}
+    flat = lambda t, cnt: t.reshape(-1)[:cnt].cpu().numpy()   # noqa: E731
+    out = {"leaves": [flat(T["leaves"][m], n[m] * rk[m]).reshape(n[m], rk[m]) for m in range(d)]}
     if d == 2:
-        out["root"] = T["root"].cpu().numpy().ravel()[: rk[0] * rk[1]].reshape(rk[0], rk[1])
+        out["root"] = flat(T["root"], rk[0] * rk[1]).reshape(rk[0], rk[1])
     else:
         r1, r2, r3, r4, r12, r34 = rk
-        out["B12"] = T["B12"].cpu().numpy().ravel()[: r1 * r2 * r12].reshape(r1, r2, r12)
-        out["B34"] = T["B34"].cpu().numpy().ravel()[: r3 * r4 * r34].reshape(r3, r4, r34)
-        out["root"] = T["root"].cpu().numpy().ravel()[: r12 * r34].reshape(r12, r34)
+        out["B12"] = flat(T["B12"], r1 * r2 * r12).reshape(r1, r2, r12)
+        out["B34"] = flat(T["B34"], r3 * r4 * r34).reshape(r3, r4, r34)
+        out["root"] = flat(T["root"], r12 * r34).reshape(r12, r34)
     return out
