@@ -209,15 +209,22 @@ slar_status slar_lomac_prepare(const slar_grid* g, const slar_ht* Fstar,
  *   G(U) = U - U_hist + b dt (D.F(U) - S(U)) = 0
  * (bdf_order 1: backward Euler, U_hist = U_n, b = 1; 2: BDF2,
  * U_hist = 4/3 U_n - 1/3 U_nm1, b = 2/3) by Jacobian-free Newton--GMRES
- * started from U(F*).  The flux is closed by the corrected kinetic state of
- * the prepared LoMaC closure.  cnn: NULL for plain GMRES, else a
- * preconditioner made by slar_cnn_create (flexible GMRES).  iters (host,
- * int32[2]) receives the Newton and Krylov iteration counts.
+ * started from U(F*) (section 4 tolerances: Newton 1e-10 on the RMS
+ * residual, Krylov 1e-4 relative).  The flux is closed by the corrected
+ * kinetic state of the prepared LoMaC closure.
+ *   precond 0: plain GMRES (the paper's solver);
+ *           1: flexible GMRES right-preconditioned by the exact per-Fourier-
+ *              mode inverse of the linear constant-coefficient part of the
+ *              Jacobian (kinetic flux of the closure + linearised Poisson
+ *              source);
+ *           2: as 1 plus the learned convolutional correction cnn.
+ * The converged answer is the same Newton root; only the iteration counts
+ * change.  iters (host, int32[2]) receives Newton and Krylov counts.
  * Returns SLAR_E_NOCONV if Newton did not reach newton_tol.                 */
 typedef struct slar_cnn slar_cnn;
 slar_status slar_macro_solve(const slar_grid* g, const double* U_n, const double* U_nm1,
                              double dt, int32_t bdf_order, double newton_tol, double krylov_tol,
-                             const slar_cnn* cnn, double* U_out, int32_t* iters,
+                             int32_t precond, const slar_cnn* cnn, double* U_out, int32_t* iters,
                              slar_workspace* ws, hipStream_t stream);
 
 /* LoMaC update eq. (LoMaC_update_discrete):

@@ -282,15 +282,16 @@ slar_status slar_lomac_prepare(const slar_grid* g, const slar_ht* Fstar,
 
 slar_status slar_macro_solve(const slar_grid* g, const double* U_n, const double* U_nm1,
                              double dt, int32_t bdf_order, double newton_tol, double krylov_tol,
-                             const slar_cnn* cnn, double* U_out, int32_t* iters,
+                             int32_t precond, const slar_cnn* cnn, double* U_out, int32_t* iters,
                              slar_workspace* w, hipStream_t stream) {
   if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !U_n || !U_out) return SLAR_E_INVAL;
   if (!(dt > 0.0) || (bdf_order != 1 && bdf_order != 2) || !(newton_tol > 0.0) ||
       !(krylov_tol > 0.0 && krylov_tol < 1.0))
     return SLAR_E_INVAL;
   if (bdf_order == 2 && !U_nm1) return SLAR_E_INVAL;
-  return macro_solve_run(stream, &w->w, U_n, U_nm1, dt, bdf_order, newton_tol, krylov_tol, cnn,
-                         U_out, iters);
+  if (precond < 0 || precond > 2 || (precond == 2 && !cnn)) return SLAR_E_INVAL;
+  return macro_solve_run(stream, &w->w, U_n, U_nm1, dt, bdf_order, newton_tol, krylov_tol, precond,
+                         cnn, U_out, iters);
 }
 
 slar_status slar_lomac_project(const slar_grid* g, const slar_frames* Fstar_frames,

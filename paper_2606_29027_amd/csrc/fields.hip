@@ -59,6 +59,62 @@ __global__ void k_dft_line(int n0, int n1, int axis, double sign, const double2*
   }
 }
 
+// Radix-2 Cooley--Tukey FFT of one line in LDS (n a power of two <= 128):
+// bit-reversed load, log2(n) butterfly stages, one butterfly per thread.
+__global__ void k_fft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
+                           const double* __restrict__ realin, double2* __restrict__ out,
+                           const double* __restrict__ tw, int logL) {
+  __shared__ double2 a[SLAR_NMAX];
+  const int b = blockIdx.y;
+  const int L = axis == 1 ? n1 : n0;
+  const int other = blockIdx.x;
+  const long long base = (long long)b * n0 * n1;
+  const int t = threadIdx.x;
+  for (int e = t; e < L; e += blockDim.x) {
+    const long long off = axis == 1 ? base + (long long)other * n1 + e : base + (long long)e * n1 + other;
+    const double2 v = realin ? make_double2(realin[off], 0.0) : in[off];
+    const int r = __brev((unsigned)e) >> (32 - logL);
+    a[r] = v;
+  }
+  __syncthreads();
+  for (int len = 2; len <= L; len <<= 1) {
+    const int hl = len >> 1;
+    for (int bt = t; bt < L / 2; bt += blockDim.x) {
+      const int grp = bt / hl, pos = bt % hl;
+      const int i = grp * len + pos, j = i + hl;
+      const int ti = pos * (L / len);
+      const double wr = tw[2 * ti], wi = sign * tw[2 * ti + 1];
+      const double2 u = a[i], x = a[j];
+      const double2 v = make_double2(x.x * wr - x.y * wi, x.x * wi + x.y * wr);
+      a[i] = make_double2(u.x + v.x, u.y + v.y);
+      a[j] = make_double2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < L; e += blockDim.x) {
+    const long long off = axis == 1 ? base + (long long)other * n1 + e : base + (long long)e * n1 + other;
+    out[off] = a[e];
+  }
+}
+
+static int log2_exact(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return ((1 << l) == n) ? l : -1;
+}
+
+// one batch of line transforms along an axis: FFT for powers of two, DFT otherwise
+static void line_transform(hipStream_t s, int n0, int n1, int axis, double sign, const double2* in,
+                           const double* realin, double2* out, const double* tw, int B) {
+  const int L = axis == 1 ? n1 : n0;
+  const int others = axis == 1 ? n0 : n1;
+  const int lg = log2_exact(L);
+  if (lg >= 1)
+    k_fft_line<<<dim3(others, B), 64, 0, s>>>(n0, n1, axis, sign, in, realin, out, tw, lg);
+  else
+    k_dft_line<<<dim3(others, B), 128, 0, s>>>(n0, n1, axis, sign, in, realin, out, tw);
+}
+
 __global__ void k_take_real(long long n, const double2* __restrict__ in, double scale,
                             double* __restrict__ out) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,10 +127,10 @@ hipError_t dft_forward(hipStream_t s, Workspace* ws, int B, const double* in, do
   const GridDev& G = ws->G;
   const int n0 = G.n[0], n1 = (G.dx == 2) ? G.n[1] : 1;
   if (G.dx == 2) {
-    k_dft_line<<<dim3(n0, B), 128, 0, s>>>(n0, n1, 1, -1.0, nullptr, in, tmp, ws->tw[1]);
-    k_dft_line<<<dim3(n1, B), 128, 0, s>>>(n0, n1, 0, -1.0, tmp, nullptr, out, ws->tw[0]);
+    line_transform(s, n0, n1, 1, -1.0, nullptr, in, tmp, ws->tw[1], B);
+    line_transform(s, n0, n1, 0, -1.0, tmp, nullptr, out, ws->tw[0], B);
   } else {
-    k_dft_line<<<dim3(1, B), 128, 0, s>>>(n0, 1, 0, -1.0, nullptr, in, out, ws->tw[0]);
+    line_transform(s, n0, 1, 0, -1.0, nullptr, in, out, ws->tw[0], B);
   }
   return hipGetLastError();
 }
@@ -86,11 +142,11 @@ hipError_t dft_inverse(hipStream_t s, Workspace* ws, int B, const double2* in, d
   const int n0 = G.n[0], n1 = (G.dx == 2) ? G.n[1] : 1;
   const long long tot = (long long)B * G.nx;
   if (G.dx == 2) {
-    k_dft_line<<<dim3(n1, B), 128, 0, s>>>(n0, n1, 0, 1.0, in, nullptr, tmp, ws->tw[0]);
-    k_dft_line<<<dim3(n0, B), 128, 0, s>>>(n0, n1, 1, 1.0, tmp, nullptr, (double2*)tmp + tot, ws->tw[1]);
+    line_transform(s, n0, n1, 0, 1.0, in, nullptr, tmp, ws->tw[0], B);
+    line_transform(s, n0, n1, 1, 1.0, tmp, nullptr, (double2*)tmp + tot, ws->tw[1], B);
     k_take_real<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(tot, (double2*)tmp + tot, 1.0 / G.nx, out);
   } else {
-    k_dft_line<<<dim3(1, B), 128, 0, s>>>(n0, 1, 0, 1.0, in, nullptr, tmp, ws->tw[0]);
+    line_transform(s, n0, 1, 0, 1.0, in, nullptr, tmp, ws->tw[0], B);
     k_take_real<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(tot, tmp, 1.0 / G.nx, out);
   }
   return hipGetLastError();

@@ -8,7 +8,7 @@ constexpr int KRY_MAXIT = 500;      // Krylov iterations per Newton step
 constexpr int KRY_MAX_NEWTON = 30;
 
 struct LmLayout {
-  size_t gs, scal, Q, psiQ, Mstar, Cstar, U0, total;
+  size_t gs, scal, Q, psiQ, Mstar, Cstar, U0, Aflux, total;
 };
 LmLayout lm_layout(const GridDev& G);
 size_t kry_elems_for(int Nx, int K, int m);
@@ -17,7 +17,7 @@ slar_status lomac_prepare_run(hipStream_t s, Workspace* ws, const slar_ht& Fs,
 hipError_t macro_residual(hipStream_t s, Workspace* ws, const double* U, const double* Uhist,
                           double bdt, double* Gout);
 slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, const double* Unm1,
-                            double dt, int bdf, double newton_tol, double krylov_tol,
+                            double dt, int bdf, double newton_tol, double krylov_tol, int precond,
                             const slar_cnn* cnn, double* Uout, int* iters);
 slar_status lomac_project_run(hipStream_t s, Workspace* ws, const slar_frames& Fs,
                               const double* Unew, slar_frames* out);

@@ -22,6 +22,8 @@
 
 namespace slar {
 
+static void flux_jacobian(const GridDev& G, const double* scal, const double* psiQ, double* A);
+
 // ---------------------------------------------------------------- layout
 LmLayout lm_layout(const GridDev& G) {
   LmLayout L{};
@@ -34,6 +36,7 @@ LmLayout lm_layout(const GridDev& G) {
   L.Mstar = o; o += (size_t)nm * G.nx;
   L.Cstar = o; o += (size_t)K * G.nx;
   L.U0 = o; o += (size_t)K * G.nx;
+  L.Aflux = o; o += 2 * 4 * 4;
   L.total = o;
   return L;
 }
@@ -174,9 +177,14 @@ slar_status lomac_prepare_run(hipStream_t s, Workspace* ws, const slar_ht& Fs,
   k_cstar<<<(G.nx + 255) / 256, 256, 0, s>>>(G.nx, dv, lm + L.scal, lm + L.Mstar, lm + L.Cstar);
   if (conserved_from_moments(s, ws, lm + L.Mstar, n_i, lm + L.U0) != hipSuccess) return SLAR_E_HIP;
   HIP_TRY(hipMemcpyAsync(ws->lm_scal, lm + L.scal, 32 * sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> psiQ_h((size_t)nm * K), Af(2 * 4 * 4, 0.0);
+  HIP_TRY(hipMemcpyAsync(psiQ_h.data(), lm + L.psiQ, sizeof(double) * nm * K, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int i = 0; i < 20; ++i)
     if (!std::isfinite(ws->lm_scal[i])) return SLAR_E_NUMERIC;
+  flux_jacobian(G, ws->lm_scal, psiQ_h.data(), Af.data());
+  HIP_TRY(hipMemcpyAsync(lm + L.Aflux, Af.data(), sizeof(double) * Af.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
   ws->n_i = n_i;
   ws->lm_ready = true;
   return SLAR_OK;
@@ -330,20 +338,41 @@ hipError_t macro_residual(hipStream_t s, Workspace* ws, const double* U, const d
 }
 
 // ------------------------------------------------------ vector kernels
-// partial dots: for v in [0, nv): part[v][block] = sum_e A[v][e] * w[e]
-__global__ void k_multidot(int n, int nv, const double* __restrict__ A, long long lda,
-                           const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double red[4][SLAR_KMAX];
+constexpr int MD_CHUNK = 512;   // elements per block in the Krylov passes
+
+// One classical Gram--Schmidt pass over the basis V[0..nv):
+//   if sub: w -= sum_v V[v] h[v]   (h from the previous pass)
+//   part[v][block] = V[v] . w  (v < nv),  part[nv][block] = w . w
+__global__ __launch_bounds__(256) void k_cgs_pass(int n, int nv, const double* __restrict__ V,
+                                                  long long ldv, const double* __restrict__ h,
+                                                  double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[4][SLAR_KMAX + 1];
   const int t = threadIdx.x;
-  const int e0 = blockIdx.x * 1024;
-  for (int v = 0; v < nv; ++v) {
+  const int e0 = blockIdx.x * MD_CHUNK;
+  double wl[MD_CHUNK / 256];
+  for (int q = 0; q < MD_CHUNK / 256; ++q) {
+    const int e = e0 + t + q * 256;
+    double x = 0.0;
+    if (e < n) {
+      x = w[e];
+      if (h) {
+        for (int v = 0; v < nv; ++v) x -= V[v * ldv + e] * h[v];
+        w[e] = x;
+      }
+    }
+    wl[q] = x;
+  }
+  for (int v = 0; v <= nv; ++v) {
     double acc = 0.0;
-    for (int e = e0 + t; e < min(n, e0 + 1024); e += 256) acc += A[v * lda + e] * w[e];
+    for (int q = 0; q < MD_CHUNK / 256; ++q) {
+      const int e = e0 + t + q * 256;
+      if (e < n) acc += (v < nv ? V[v * ldv + e] : wl[q]) * wl[q];
+    }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((t & 63) == 0) red[t >> 6][v] = acc;
   }
   __syncthreads();
-  for (int v = t; v < nv; v += 256)
+  for (int v = t; v <= nv; v += 256)
     part[(size_t)v * gridDim.x + blockIdx.x] = red[0][v] + red[1][v] + red[2][v] + red[3][v];
 }
 
@@ -355,16 +384,6 @@ __global__ void k_reduce_parts(int nv, int nb, const double* __restrict__ part, 
   out[v] = acc;
 }
 
-// w -= sum_v A[v] h[v]
-__global__ void k_subtract_combo(int n, int nv, const double* __restrict__ A, long long lda,
-                                 const double* __restrict__ h, double* __restrict__ w) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  double acc = w[e];
-  for (int v = 0; v < nv; ++v) acc -= A[v * lda + e] * h[v];
-  w[e] = acc;
-}
-
 // y = a x + b y ; if x2: y += c x2
 __global__ void k_axpby(int n, double a, const double* __restrict__ x, double b, double* __restrict__ y,
                         double c, const double* __restrict__ x2) {
@@ -373,6 +392,37 @@ __global__ void k_axpby(int n, double a, const double* __restrict__ x, double b,
   double v = a * x[e] + (b == 0.0 ? 0.0 : b * y[e]);
   if (x2) v += c * x2[e];
   y[e] = v;
+}
+
+// finite-difference point: h = cst / sqrt(nrm2) (cst if nrm2 == 0),
+// Uh = U + h z; h is stored for k_fd_diff
+__global__ void k_fd_point(int n, const double* __restrict__ U, const double* __restrict__ z,
+                           const double* __restrict__ nrm2, double cst, double* __restrict__ Uh,
+                           double* __restrict__ hout) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const double nz = nrm2 ? sqrt(nrm2[0]) : 1.0;
+  const double h = nz > 0.0 ? cst / nz : cst;
+  if (e == 0) hout[0] = h;
+  if (e < n) Uh[e] = U[e] + h * z[e];
+}
+
+// w = (Gh - g0) / h  (scale < 0 : w = -(Gh - g0)/h - g0, the true residual)
+__global__ void k_fd_diff(int n, const double* __restrict__ Gh, const double* __restrict__ g0,
+                          const double* __restrict__ hdev, int residual_form, double* __restrict__ w) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double h = hdev[0];
+  const double jv = (Gh[e] - g0[e]) / h;
+  w[e] = residual_form ? -g0[e] - jv : jv;
+}
+
+// w_out = w / sqrt(nrm2)
+__global__ void k_scale_by_norm(int n, const double* __restrict__ w, const double* __restrict__ nrm2,
+                                double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double nz = sqrt(nrm2[0]);
+  out[e] = nz > 0.0 ? w[e] / nz : 0.0;
 }
 
 // x += sum_v A[v] y[v]
@@ -410,30 +460,100 @@ __global__ void k_meanfix(int Nx, int K, const double* __restrict__ md, const do
   d[e] -= md[c] + mg[c];
 }
 
-struct Krylov {
-  Workspace* ws;
-  hipStream_t s;
-  int n;
-  double* part;     // partial sums
-  double* hdev;     // device small vector
-  double* hhost;    // pinned
-  hipError_t dots(const double* A, long long lda, int nv, const double* w, double* out_dev) {
-    const int nb = (n + 1023) / 1024;
-    k_multidot<<<nb, 256, 0, s>>>(n, nv, A, lda, w, part);
-    k_reduce_parts<<<(nv + 63) / 64, 64, 0, s>>>(nv, nb, part, out_dev);
-    return hipGetLastError();
+// --------------------------------------------- spectral preconditioner
+// The kinetic part of the LoMaC flux is linear in U with x-independent
+// coefficients (the closure basis Q_k depends on v only, the coefficient
+// map of eqs. (C0_def)-(C2_def) is linear in the raw moments, and
+// M2 = 2 (U2 - e_p)); with the linearised Poisson source -n_i E(dU_0) this
+// gives, per Fourier mode k, the K x K system
+//   (I + b dt [ sum_mu i k_mu A_mu + n_i (i k_mu / |k|^2) e_{1+mu} e_0^T ]) z^ = r^.
+// Solved exactly per mode (complex Gaussian elimination, partial pivoting);
+// the field-energy flux and the E-dependent parts are left to the Krylov
+// iteration.  A_mu [dx][K][K] is precomputed on the host.
+__global__ void k_spec_solve(int n0, int n1, int dx, double L0, double L1, int K,
+                             const double* __restrict__ A, double bdt, double ni,
+                             const double2* __restrict__ rhs, double2* __restrict__ out, int Nx) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Nx) return;
+  auto wn = [](int i, int n, double Lx) {
+    if ((n % 2) == 0 && i == n / 2) return 0.0;
+    const int m = (i < (n + 1) / 2) ? i : i - n;
+    return 2.0 * M_PI * (double)m / Lx;
+  };
+  double k[2] = {wn(p / n1, n0, L0), dx == 2 ? wn(p % n1, n1, L1) : 0.0};
+  const double k2 = k[0] * k[0] + k[1] * k[1];
+  double Mr[4][4], Mi[4][4], br[4], bi[4];
+  for (int a = 0; a < K; ++a) {
+    for (int b = 0; b < K; ++b) {
+      double im = 0.0;
+      for (int mu = 0; mu < dx; ++mu) im += k[mu] * A[(mu * K + a) * K + b];
+      Mr[a][b] = (a == b) ? 1.0 : 0.0;
+      Mi[a][b] = bdt * im;
+    }
+    const double2 r = rhs[(size_t)a * Nx + p];
+    br[a] = r.x; bi[a] = r.y;
   }
-  hipError_t fetch(const double* dev, int cnt, double* host) {
-    hipError_t e = hipMemcpyAsync(host, dev, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(s);
+  if (k2 > 0.0)
+    for (int mu = 0; mu < dx; ++mu) Mi[1 + mu][0] += bdt * ni * k[mu] / k2;
+  // Gaussian elimination with partial pivoting (complex)
+  for (int c = 0; c < K; ++c) {
+    int piv = c;
+    double best = Mr[c][c] * Mr[c][c] + Mi[c][c] * Mi[c][c];
+    for (int r = c + 1; r < K; ++r) {
+      const double v = Mr[r][c] * Mr[r][c] + Mi[r][c] * Mi[r][c];
+      if (v > best) { best = v; piv = r; }
+    }
+    if (piv != c) {
+      for (int b = 0; b < K; ++b) {
+        double t = Mr[c][b]; Mr[c][b] = Mr[piv][b]; Mr[piv][b] = t;
+        t = Mi[c][b]; Mi[c][b] = Mi[piv][b]; Mi[piv][b] = t;
+      }
+      double t = br[c]; br[c] = br[piv]; br[piv] = t;
+      t = bi[c]; bi[c] = bi[piv]; bi[piv] = t;
+    }
+    const double dr = Mr[c][c], di = Mi[c][c], dd = dr * dr + di * di;
+    for (int r = c + 1; r < K; ++r) {
+      // f = M[r][c] / M[c][c]
+      const double fr = (Mr[r][c] * dr + Mi[r][c] * di) / dd;
+      const double fi = (Mi[r][c] * dr - Mr[r][c] * di) / dd;
+      for (int b = c; b < K; ++b) {
+        Mr[r][b] -= fr * Mr[c][b] - fi * Mi[c][b];
+        Mi[r][b] -= fr * Mi[c][b] + fi * Mr[c][b];
+      }
+      br[r] -= fr * br[c] - fi * bi[c];
+      bi[r] -= fr * bi[c] + fi * br[c];
+    }
   }
-  double norm(const double* x) {
-    if (dots(x, 0, 1, x, hdev) != hipSuccess) return NAN;
-    if (fetch(hdev, 1, hhost) != hipSuccess) return NAN;
-    return std::sqrt(hhost[0]);
+  double xr[4], xi[4];
+  for (int c = K - 1; c >= 0; --c) {
+    double sr = br[c], si = bi[c];
+    for (int b = c + 1; b < K; ++b) {
+      sr -= Mr[c][b] * xr[b] - Mi[c][b] * xi[b];
+      si -= Mr[c][b] * xi[b] + Mi[c][b] * xr[b];
+    }
+    const double dr = Mr[c][c], di = Mi[c][c], dd = dr * dr + di * di;
+    xr[c] = (sr * dr + si * di) / dd;
+    xi[c] = (si * dr - sr * di) / dd;
   }
-};
+  for (int a = 0; a < K; ++a) out[(size_t)a * Nx + p] = make_double2(xr[a], xi[a]);
+}
+
+static hipError_t spectral_precond(hipStream_t s, Workspace* ws, const double* v, double bdt,
+                                   double* z) {
+  const GridDev& G = ws->G;
+  const int K = G.dv + 2, Nx = G.nx;
+  double2* c = (double2*)ws->cbuf;
+  double2* c0 = c + 24 * Nx;     // above the residual's complex scratch
+  double2* c1 = c0 + 4 * Nx;
+  double2* tmp = c1 + 4 * Nx;     // needs 2 K Nx complex (inverse)
+  HIP_CHK(dft_forward(s, ws, K, v, c0, tmp));
+  k_spec_solve<<<(Nx + 255) / 256, 256, 0, s>>>(G.n[0], G.dx == 2 ? G.n[1] : 1, G.dx,
+                                                ws->grid.hi[0] - ws->grid.lo[0],
+                                                G.dx == 2 ? ws->grid.hi[1] - ws->grid.lo[1] : 1.0,
+                                                K, ws->lm + lm_layout(G).Aflux, bdt, ws->n_i, c0, c1, Nx);
+  HIP_CHK(hipGetLastError());
+  return dft_inverse(s, ws, K, c1, z, tmp);
+}
 
 struct KryBufs {
   double *V, *Z, *w, *g0, *Uh, *Gh, *d, *r, *x, *U;
@@ -460,8 +580,46 @@ size_t kry_elems_for(int Nx, int K, int m) {
   return macro_fixed_elems(Nx) + (size_t)(2 * m + 1) * n + 8 * n + 4096;
 }
 
+// host-side flux Jacobian of the closure (see k_spec_solve)
+static void flux_jacobian(const GridDev& G, const double* scal, const double* psiQ, double* A) {
+  const int dv = G.dv, K = dv + 2, dx = G.dx;
+  const double* NQ = scal + 16;
+  double Cc[4][4] = {};
+  Cc[0][0] = 1.0 / NQ[0];
+  double etas = 0.0, bg = 0.0;
+  for (int a = 0; a < dv; ++a) {
+    const double* sc = scal + 8 * a;
+    Cc[1 + a][0] = -sc[0] / NQ[1 + a];
+    Cc[1 + a][1 + a] = 1.0 / NQ[1 + a];
+    etas += sc[1];
+    bg += sc[2] * sc[0];
+  }
+  Cc[dv + 1][0] = (-etas + bg) / NQ[dv + 1];
+  for (int a = 0; a < dv; ++a) Cc[dv + 1][1 + a] = -scal[8 * a + 2] / NQ[dv + 1];
+  Cc[dv + 1][dv + 1] = 1.0 / NQ[dv + 1];
+  // dMraw/dU = diag(1, .., 1, 2)
+  for (int k = 0; k < K; ++k) Cc[k][dv + 1] *= 2.0;
+  int pair[2][2];
+  int c = dv + 2;
+  for (int a = 0; a < dv; ++a)
+    for (int b = a; b < dv; ++b) { pair[a][b] = pair[b][a] = c; ++c; }
+  const int off_e = c;
+  for (int mu = 0; mu < dx; ++mu)
+    for (int comp = 0; comp < K; ++comp) {
+      int q; double wgt = 1.0;
+      if (comp == 0) q = 1 + mu;
+      else if (comp <= dv) q = pair[comp - 1][mu];
+      else { q = off_e + mu; wgt = 0.5; }
+      for (int j = 0; j < K; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) acc += psiQ[q * K + k] * Cc[k][j];
+        A[(mu * K + comp) * K + j] = wgt * acc;
+      }
+    }
+}
+
 slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, const double* Unm1,
-                            double dt, int bdf, double newton_tol, double krylov_tol,
+                            double dt, int bdf, double newton_tol, double krylov_tol, int precond,
                             const slar_cnn* cnn, double* Uout, int* iters) {
   if (!ws->lm_ready) return SLAR_E_INVAL;
   const GridDev& G = ws->G;
@@ -469,41 +627,56 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, cons
   const int m = KRY_RESTART;
   const LmLayout L = lm_layout(G);
   KryBufs b = kry_bufs(ws, n, m);
-  double* hdev = ws->small;           // scratch: small device vectors
-  double* part = ws->small + 256;
-  Krylov kr{ws, s, n, part, hdev, (double*)ws->host_pinned};
+  double* hdev = ws->small;            // [0..72] dots, [80..] second pass, [160] h, [170..] means
+  double* h1 = hdev, * h2 = hdev + 80, * hval = hdev + 160, * means = hdev + 170;
+  double* nrm = hdev + 200;            // norms
+  double* part = ws->small + 512;
+  double* hh = (double*)ws->host_pinned;
   const unsigned nb = (n + 255) / 256;
-  // U_hist and b
-  double* Uhist = b.r;   // reuse r region for U_hist (r used only in restarts below -> own copy)
-  double* Uhist_store = b.x;
+  const int nbk = (n + MD_CHUNK - 1) / MD_CHUNK;
+  auto cgs = [&](int nv, const double* V, const double* hprev, double* w, double* out) {
+    k_cgs_pass<<<nbk, 256, 0, s>>>(n, nv, V, n, hprev, w, part);
+    k_reduce_parts<<<1, 128, 0, s>>>(nv + 1, nbk, part, out);
+  };
+  auto norm2 = [&](double* x, double* out) { cgs(0, nullptr, nullptr, x, out); };
+  double* Uhist = b.x;
   double bdt = dt;
   if (bdf >= 2 && Unm1 != nullptr) {
-    k_axpby<<<nb, 256, 0, s>>>(n, 4.0 / 3.0, Un, 0.0, Uhist_store, -1.0 / 3.0, Unm1);
+    k_axpby<<<nb, 256, 0, s>>>(n, 4.0 / 3.0, Un, 0.0, Uhist, -1.0 / 3.0, Unm1);
     bdt = 2.0 / 3.0 * dt;
   } else {
-    HIP_TRY(hipMemcpyAsync(Uhist_store, Un, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(Uhist, Un, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   }
-  (void)Uhist;
   double* U = b.U;
   HIP_TRY(hipMemcpyAsync(U, ws->lm + L.U0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  const double eps = 2.220446049250313e-16;
+  const double sqeps = std::sqrt(2.220446049250313e-16);
   int newton = 0, krylov = 0;
   bool converged = false;
+  const bool flexible = precond != 0;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
-  double* hh = (double*)ws->host_pinned;
+  auto apply_pc = [&](const double* v, double* z) -> hipError_t {
+    if (precond == 1) return spectral_precond(s, ws, v, bdt, z);
+    if (precond == 2) {
+      HIP_CHK(spectral_precond(s, ws, v, bdt, z));
+      return cnn_apply(s, ws, cnn, v, U, z);
+    }
+    return hipErrorInvalidValue;
+  };
   for (int it = 0; it <= KRY_MAX_NEWTON; ++it) {
-    if (macro_residual(s, ws, U, Uhist_store, bdt, b.g0) != hipSuccess) return SLAR_E_HIP;
-    const double gn = kr.norm(b.g0);
+    if (macro_residual(s, ws, U, Uhist, bdt, b.g0) != hipSuccess) return SLAR_E_HIP;
+    norm2(b.g0, nrm);
+    norm2(U, nrm + 1);
+    HIP_TRY(hipMemcpyAsync(hh, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double gn = std::sqrt(hh[0]);
     if (!std::isfinite(gn)) return SLAR_E_NUMERIC;
     const double rms = gn / std::sqrt((double)n);
     if (rms <= newton_tol) { converged = true; break; }
     if (it == KRY_MAX_NEWTON) break;
-    const double Un_norm = kr.norm(U);
-    // FGMRES on J d = -g0, d0 = 0
+    const double fdc = sqeps * (1.0 + std::sqrt(hh[1]));
     HIP_TRY(hipMemsetAsync(b.d, 0, sizeof(double) * n, s));
     const double bn = gn;
     double beta = gn;
-    // r = -g0
     k_axpby<<<nb, 256, 0, s>>>(n, -1.0, b.g0, 0.0, b.r, 0.0, nullptr);
     int kits = 0;
     bool done = false;
@@ -515,28 +688,25 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, cons
       int jl = 0;
       for (int j = 0; j < m; ++j) {
         double* vj = b.V + (size_t)j * n;
-        double* zj = cnn ? b.Z + (size_t)j * n : vj;
-        if (cnn) {
-          if (cnn_apply(s, ws, cnn, vj, U, zj) != hipSuccess) return SLAR_E_HIP;
+        double* zj = flexible ? b.Z + (size_t)j * n : vj;
+        if (flexible) {
+          if (apply_pc(vj, zj) != hipSuccess) return SLAR_E_HIP;
+          norm2(zj, nrm + 2);
         }
-        // w = J z  by finite differences
-        const double zn = kr.norm(zj);
-        const double h = std::sqrt(eps) * (1.0 + Un_norm) / (zn > 0 ? zn : 1.0);
-        k_axpby<<<nb, 256, 0, s>>>(n, h, zj, 0.0, b.Uh, 1.0, U);
-        if (macro_residual(s, ws, b.Uh, Uhist_store, bdt, b.Gh) != hipSuccess) return SLAR_E_HIP;
-        k_axpby<<<nb, 256, 0, s>>>(n, 1.0 / h, b.Gh, 0.0, b.w, -1.0 / h, b.g0);
-        // CGS2
-        if (kr.dots(b.V, n, j + 1, b.w, hdev) != hipSuccess) return SLAR_E_HIP;
-        k_subtract_combo<<<nb, 256, 0, s>>>(n, j + 1, b.V, n, hdev, b.w);
-        if (kr.dots(b.V, n, j + 1, b.w, hdev + SLAR_KMAX) != hipSuccess) return SLAR_E_HIP;
-        k_subtract_combo<<<nb, 256, 0, s>>>(n, j + 1, b.V, n, hdev + SLAR_KMAX, b.w);
-        if (kr.dots(b.w, 0, 1, b.w, hdev + 2 * SLAR_KMAX) != hipSuccess) return SLAR_E_HIP;
-        HIP_TRY(hipMemcpyAsync(hh, hdev, sizeof(double) * (2 * SLAR_KMAX + 1), hipMemcpyDeviceToHost, s));
+        // w = J z by a finite difference with h = sqrt(eps)(1 + ||U||)/||z||
+        k_fd_point<<<nb, 256, 0, s>>>(n, U, zj, flexible ? nrm + 2 : nullptr, fdc, b.Uh, hval);
+        if (macro_residual(s, ws, b.Uh, Uhist, bdt, b.Gh) != hipSuccess) return SLAR_E_HIP;
+        k_fd_diff<<<nb, 256, 0, s>>>(n, b.Gh, b.g0, hval, 0, b.w);
+        // CGS2 against V[0..j]
+        cgs(j + 1, b.V, nullptr, b.w, h1);
+        cgs(j + 1, b.V, h1, b.w, h2);
+        cgs(0, b.V, h2, b.w, nrm + 3);       // w -= V h2 ; ||w||^2
+        k_scale_by_norm<<<nb, 256, 0, s>>>(n, b.w, nrm + 3, b.V + (size_t)(j + 1) * n);
+        HIP_TRY(hipMemcpyAsync(hh, hdev, sizeof(double) * 208, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[SLAR_KMAX + i];
-        const double hn = std::sqrt(std::max(hh[2 * SLAR_KMAX], 0.0));
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[80 + i];
+        const double hn = std::sqrt(std::max(hh[203], 0.0));
         H[(size_t)(j + 1) * m + j] = hn;
-        if (hn > 0) k_axpby<<<nb, 256, 0, s>>>(n, 1.0 / hn, b.w, 0.0, b.V + (size_t)(j + 1) * n, 0.0, nullptr);
         for (int i = 0; i < j; ++i) {
           const double t1 = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
           H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
@@ -559,23 +729,25 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, cons
         for (int q = i + 1; q < kk; ++q) acc -= H[(size_t)i * m + q] * y[q];
         y[i] = H[(size_t)i * m + i] != 0 ? acc / H[(size_t)i * m + i] : 0.0;
       }
-      for (int i = 0; i < kk; ++i) hh[i] = y[i];
-      HIP_TRY(hipMemcpyAsync(hdev, hh, sizeof(double) * kk, hipMemcpyHostToDevice, s));
-      k_add_combo<<<nb, 256, 0, s>>>(n, kk, cnn ? b.Z : b.V, n, hdev, b.d);
+      double* ydev = hdev + 256;
+      for (int i = 0; i < kk; ++i) hh[256 + i] = y[i];
+      HIP_TRY(hipMemcpyAsync(ydev, hh + 256, sizeof(double) * kk, hipMemcpyHostToDevice, s));
+      k_add_combo<<<nb, 256, 0, s>>>(n, kk, flexible ? b.Z : b.V, n, ydev, b.d);
       // true residual r = -g0 - J d
-      const double dn = kr.norm(b.d);
-      if (dn == 0.0) break;
-      const double h = std::sqrt(eps) * (1.0 + Un_norm) / dn;
-      k_axpby<<<nb, 256, 0, s>>>(n, h, b.d, 0.0, b.Uh, 1.0, U);
-      if (macro_residual(s, ws, b.Uh, Uhist_store, bdt, b.Gh) != hipSuccess) return SLAR_E_HIP;
-      k_axpby<<<nb, 256, 0, s>>>(n, -1.0 / h, b.Gh, 0.0, b.r, 1.0 / h - 1.0, b.g0);
-      beta = kr.norm(b.r);
-      if (beta <= krylov_tol * bn) done = true;
+      norm2(b.d, nrm + 4);
+      k_fd_point<<<nb, 256, 0, s>>>(n, U, b.d, nrm + 4, fdc, b.Uh, hval);
+      if (macro_residual(s, ws, b.Uh, Uhist, bdt, b.Gh) != hipSuccess) return SLAR_E_HIP;
+      k_fd_diff<<<nb, 256, 0, s>>>(n, b.Gh, b.g0, hval, 1, b.r);
+      norm2(b.r, nrm + 5);
+      HIP_TRY(hipMemcpyAsync(hh, nrm + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      beta = std::sqrt(std::max(hh[0], 0.0));
+      if (beta <= krylov_tol * bn || beta == 0.0) done = true;
     }
     krylov += kits;
     // exact step on the per-component mean
-    k_comp_means<<<K, 256, 0, s>>>(Nx, b.d, b.g0, hdev + 3 * SLAR_KMAX);
-    k_meanfix<<<nb, 256, 0, s>>>(Nx, K, hdev + 3 * SLAR_KMAX, hdev + 3 * SLAR_KMAX + 8, b.d);
+    k_comp_means<<<K, 256, 0, s>>>(Nx, b.d, b.g0, means);
+    k_meanfix<<<nb, 256, 0, s>>>(Nx, K, means, means + 8, b.d);
     k_axpby<<<nb, 256, 0, s>>>(n, 1.0, b.d, 1.0, U, 0.0, nullptr);
     ++newton;
   }

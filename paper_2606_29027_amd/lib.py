@@ -88,7 +88,7 @@ def load(path: str = LIB_PATH):
         "slar_poisson": (i32, [P(Grid), vp, dbl, vp, vp, vp, vp]),
         "slar_conserved": (i32, [P(Grid), P(Frames), dbl, vp, vp, vp]),
         "slar_lomac_prepare": (i32, [P(Grid), P(HT), P(Frames), dbl, dbl, vp, vp]),
-        "slar_macro_solve": (i32, [P(Grid), vp, vp, dbl, i32, dbl, dbl, vp, vp, P(i32), vp, vp]),
+        "slar_macro_solve": (i32, [P(Grid), vp, vp, dbl, i32, dbl, dbl, i32, vp, vp, P(i32), vp, vp]),
         "slar_lomac_project": (i32, [P(Grid), P(Frames), vp, P(Frames), vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -229,11 +229,11 @@ def slar_lomac_prepare(grid, H, F, delta, n_i, ws):
                                      float(n_i), ws.h, _stream()), "slar_lomac_prepare")
 
 
-def slar_macro_solve(grid, U_n, U_nm1, dt, bdf, newton_tol, krylov_tol, cnn, U_out, ws):
+def slar_macro_solve(grid, U_n, U_nm1, dt, bdf, newton_tol, krylov_tol, precond, cnn, U_out, ws):
     iters = (C.c_int32 * 2)()
     st = load().slar_macro_solve(C.byref(grid), _ptr(U_n), _ptr(U_nm1), float(dt), int(bdf),
-                                 float(newton_tol), float(krylov_tol), cnn, _ptr(U_out), iters,
-                                 ws.h, _stream())
+                                 float(newton_tol), float(krylov_tol), int(precond), cnn, _ptr(U_out),
+                                 iters, ws.h, _stream())
     _check(st, "slar_macro_solve", ok=(SLAR_OK, SLAR_E_NOCONV))
     return st, (iters[0], iters[1])
 

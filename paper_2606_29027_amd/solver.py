@@ -27,12 +27,13 @@ RCAP = 64
 
 class Solver:
     def __init__(self, p, precision: int = L.F64, probes=None, delta: float = 1e-12,
-                 cnn=None, newton_tol: float = 1e-10, krylov_tol: float = 1e-4):
+                 precond: int = 0, cnn=None, newton_tol: float = 1e-10, krylov_tol: float = 1e-4):
         self.p = p
         self.grid = L.make_grid(p)
         self.ws = L.Workspace(self.grid, min(p.rmax, RCAP))
         self.prec = precision
         self.delta = delta
+        self.precond = precond
         self.cnn = cnn
         self.newton_tol = newton_tol
         self.krylov_tol = krylov_tol
@@ -159,7 +160,8 @@ class Solver:
             U_new = [u for u in self.Ubuf if u is not self.U_n and u is not self.U_nm1][0]
             bdf = 1 if (self.U_nm1 is None or p.bdf == 1) else 2
             st, (nn, nk) = L.slar_macro_solve(self.grid, self.U_n, self.U_nm1 if bdf == 2 else None, h, bdf,
-                                              self.newton_tol, self.krylov_tol, self.cnn, U_new, self.ws)
+                                              self.newton_tol, self.krylov_tol, self.precond,
+                                              None if self.cnn is None else self.cnn.handle, U_new, self.ws)
             out_slot = [s for s in range(4) if s not in (slot,)][0]
             Fn = L.slar_lomac_project(self.grid, Fs, U_new, self._frames(out_slot), self.ws)
             self.U_nm1, self.U_n = self.U_n, U_new

@@ -71,3 +71,23 @@ def test_lomac_steps_match_oracle_and_conserve(prec):
     assert max(abs(m) for m in d["momentum"]) < 1e-12 * d0["mass"]
     err = normwise(s.dense(), HT.full(Fo))
     assert err < (1e-8 if prec == L.F64 else 10 * p.tol), err
+
+
+def test_spectral_preconditioner_same_root_fewer_iterations():
+    """Preconditioning changes only the Krylov path: the Newton root agrees
+    with the unpreconditioned one to the Newton tolerance, in fewer Krylov
+    iterations, and conservation is unchanged."""
+    p = SI.config("stronglandau2d", n=16).with_(rmax=40)
+    pr = _probes(p)
+    out = {}
+    for pc in (0, 1):
+        s = Solver(p, L.F64, probes=pr, precond=pc, newton_tol=1e-12)
+        s.set_initial(SI.initial_ht(p))
+        d0 = s.diagnostics()
+        infos = [s.step() for _ in range(2)]
+        d = s.diagnostics()
+        assert abs(d["mass"] - d0["mass"]) < 1e-12 * d0["mass"]
+        assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
+        out[pc] = (s.U_n.cpu().numpy(), sum(i["krylov"] for i in infos))
+    assert normwise(out[1][0], out[0][0]) < 1e-9
+    assert out[1][1] < out[0][1], (out[0][1], out[1][1])
