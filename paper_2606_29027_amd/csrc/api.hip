@@ -139,7 +139,7 @@ slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspa
   dalloc((void**)&ws.X32, sizeof(float) * G.nx * ws.ld32);
   dalloc((void**)&ws.P32, sizeof(float) * G.nv * ws.ld32);
   dalloc(&ws.aca_ctl, aca_ctl_bytes());
-  dalloc((void**)&ws.aca_part, sizeof(double) * (K + 4) * 1024);
+  dalloc((void**)&ws.aca_part, sizeof(double) * (2 * (K + 4) + 4) * 1024);
   dalloc((void**)&ws.used, G.nx);
   dalloc((void**)&ws.dwork, sizeof(double) * ws.dwork_elems);
   dalloc((void**)&ws.small, sizeof(double) * ws.small_elems);

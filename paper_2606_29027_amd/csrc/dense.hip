@@ -194,10 +194,18 @@ hipError_t chol_inv(hipStream_t s, int k, const double* G, double* Linv, double*
   return hipGetLastError();
 }
 
+// Circle-method round robin on kp (even) players: at step `step` position 0
+// holds player 0 and position i >= 1 holds player 1 + (i - 1 + step) mod (kp - 1);
+// pair `pid` meets positions pid and kp - 1 - pid.  Every pair meets once
+// per kp - 1 steps.
+__device__ __forceinline__ int rr_player(int pos, int step, int kp) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + step) % (kp - 1);
+}
+
 // ---------------------------------------------------- one-sided Jacobi SVD
 // M (k x k, row-major) = W diag(s) Z^T, s descending.  Outputs W, Z as
 // row-major k x k (columns are singular vectors).
-__global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restrict__ Min,
+__global__ __launch_bounds__(1024) void k_svd_jacobi(int k, const double* __restrict__ Min,
                                                     double* __restrict__ W, double* __restrict__ sv,
                                                     double* __restrict__ Z) {
   __shared__ double A[SLAR_KMAX][SLAR_KMAX + 1];   // A[row][col]
@@ -224,8 +232,8 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restr
     fro = acc;
   }
   __syncthreads();
-  const double floor_abs = 1e-300 + 1e-32 * fro;
-  const int team = (npair > 0) ? max(1, min(32, 256 / npair)) : 1;  // power of 2 below
+  const double floor_abs = 1e-300 + 1e-22 * fro;   // columns below this are negligible
+  const int team = (npair > 0) ? max(1, min(64, (int)blockDim.x / npair)) : 1;  // power of 2 below
   int tm = 1;
   while (tm * 2 <= team) tm *= 2;
   const int pid = t / tm, lane = t % tm;
@@ -234,8 +242,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restr
     __syncthreads();
     for (int step = 0; step < kp - 1; ++step) {
       if (pid < npair) {
-        // circle-method round robin: position i meets position kp-1-i
-        const int p = pairs[pid], q = pairs[kp - 1 - pid];
+        const int p = rr_player(pid, step, kp), q = rr_player(kp - 1 - pid, step, kp);
         double al = 0.0, be = 0.0, ga = 0.0;
         for (int r = lane; r < kp; r += tm) {
           const double x = A[r][p], y = A[r][q];
@@ -246,7 +253,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restr
           be += __shfl_xor(be, o, tm);
           ga += __shfl_xor(ga, o, tm);
         }
-        if (fabs(ga) > 1e-14 * sqrt(al * be) && fabs(ga) > floor_abs) {
+        if (fabs(ga) > 1e-14 * sqrt(al * be) && sqrt(al * be) > floor_abs) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
@@ -260,13 +267,6 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restr
           }
           if (lane == 0) rotated = 1;
         }
-      }
-      __syncthreads();
-      // round-robin rotation of the pairing (position 0 fixed)
-      if (t == 0) {
-        const int last = pairs[kp - 1];
-        for (int i = kp - 1; i > 1; --i) pairs[i] = pairs[i - 1];
-        pairs[1] = last;
       }
       __syncthreads();
     }
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) void k_svd_jacobi(int k, const double* __restr
 }
 
 hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z) {
-  k_svd_jacobi<<<1, 256, 0, s>>>(k, M, W, sv, Z);
+  k_svd_jacobi<<<1, 1024, 0, s>>>(k, M, W, sv, Z);
   return hipGetLastError();
 }
 
@@ -311,14 +311,23 @@ hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* s
 //     columns are the eigenvectors of L L^T and their squared norms the
 //     eigenvalues.
 // Eigenvalues beyond the factor rank are returned as 0 with zero vectors.
-__global__ __launch_bounds__(256) void k_eig_psd(int n, const double* __restrict__ G,
-                                                 double* __restrict__ lam,
-                                                 double* __restrict__ Uout) {
+struct EigBatch {
+  int n[4];
+  const double* G[4];
+  double* lam[4];
+  double* U[4];
+};
+
+__global__ __launch_bounds__(1024) void k_eig_psd(EigBatch B) {
+  const int n = B.n[blockIdx.x];
+  const double* __restrict__ G = B.G[blockIdx.x];
+  double* __restrict__ lam = B.lam[blockIdx.x];
+  double* __restrict__ Uout = B.U[blockIdx.x];
   __shared__ double Lc[SLAR_NMAX][SLAR_KMAX + 1];   // L[i][j]
   __shared__ double dres[SLAR_NMAX];
   __shared__ unsigned char taken[SLAR_NMAX];
-  __shared__ double red[256];
-  __shared__ int redi[256];
+  __shared__ double red[1024];
+  __shared__ int redi[1024];
   __shared__ int ncols_s;
   __shared__ int pairs[SLAR_KMAX + 1];
   __shared__ int rotated;
@@ -337,18 +346,17 @@ __global__ __launch_bounds__(256) void k_eig_psd(int n, const double* __restrict
     double m = -1.0; int mi = n;
     for (int i = t; i < n; i += blockDim.x)
       if (!taken[i] && (dres[i] > m)) { m = dres[i]; mi = i; }
-    red[t] = m; redi[t] = mi;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (t < o) {
-        if (red[t + o] > red[t] || (red[t + o] == red[t] && redi[t + o] < redi[t])) {
-          red[t] = red[t + o]; redi[t] = redi[t + o];
-        }
-      }
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      const double m2 = __shfl_xor(m, o, 64);
+      const int i2 = __shfl_xor(mi, o, 64);
+      if (m2 > m || (m2 == m && i2 < mi)) { m = m2; mi = i2; }
     }
-    const double dp = red[0];
-    const int p = redi[0];
+    if ((t & 63) == 0) { red[t >> 6] = m; redi[t >> 6] = mi; }
+    __syncthreads();
+    double dp = red[0];
+    int p = redi[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      if (red[w] > dp || (red[w] == dp && redi[w] < p)) { dp = red[w]; p = redi[w]; }
     __syncthreads();
     if (!(dp > stop) || p >= n) break;
     const double sq = sqrt(dp);
@@ -377,15 +385,15 @@ __global__ __launch_bounds__(256) void k_eig_psd(int n, const double* __restrict
   __syncthreads();
   const int npair = kp / 2;
   int tm = 1;
-  if (npair > 0) { const int team = max(1, min(32, 256 / npair)); while (tm * 2 <= team) tm *= 2; }
+  if (npair > 0) { const int team = max(1, min(64, (int)blockDim.x / npair)); while (tm * 2 <= team) tm *= 2; }
   const int pid = t / tm, lane = t % tm;
-  const double floor_abs = 1e-32 * trace * trace + 1e-300;
+  const double floor_abs = 1e-22 * trace + 1e-300;   // columns below this are negligible
   for (int sweep = 0; sweep < 30 && kp >= 2; ++sweep) {
     if (t == 0) rotated = 0;
     __syncthreads();
     for (int step = 0; step < kp - 1; ++step) {
       if (pid < npair) {
-        const int p = pairs[pid], q = pairs[kp - 1 - pid];
+        const int p = rr_player(pid, step, kp), q = rr_player(kp - 1 - pid, step, kp);
         double al = 0.0, be = 0.0, ga = 0.0;
         for (int r = lane; r < n; r += tm) {
           const double x = Lc[r][p], y = Lc[r][q];
@@ -396,7 +404,7 @@ __global__ __launch_bounds__(256) void k_eig_psd(int n, const double* __restrict
           be += __shfl_xor(be, o, tm);
           ga += __shfl_xor(ga, o, tm);
         }
-        if (fabs(ga) > 1e-14 * sqrt(al * be) && fabs(ga) > floor_abs) {
+        if (fabs(ga) > 1e-14 * sqrt(al * be) && sqrt(al * be) > floor_abs) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cc = 1.0 / sqrt(1.0 + tt * tt), sn = cc * tt;
@@ -407,12 +415,6 @@ __global__ __launch_bounds__(256) void k_eig_psd(int n, const double* __restrict
           }
           if (lane == 0) rotated = 1;
         }
-      }
-      __syncthreads();
-      if (t == 0) {
-        const int last = pairs[kp - 1];
-        for (int i = kp - 1; i > 1; --i) pairs[i] = pairs[i - 1];
-        pairs[1] = last;
       }
       __syncthreads();
     }
@@ -448,7 +450,18 @@ __global__ __launch_bounds__(256) void k_eig_psd(int n, const double* __restrict
 hipError_t eig_sym(hipStream_t s, int n, const double* G, double* lam, double* Vwork,
                    double* V) {
   (void)Vwork;
-  k_eig_psd<<<1, 256, 0, s>>>(n, G, lam, V);
+  EigBatch B{};
+  B.n[0] = n; B.G[0] = G; B.lam[0] = lam; B.U[0] = V;
+  k_eig_psd<<<1, 1024, 0, s>>>(B);
+  return hipGetLastError();
+}
+
+// up to four independent eigenproblems in one launch (one block each)
+hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* const* G,
+                         double* const* lam, double* const* V) {
+  EigBatch B{};
+  for (int i = 0; i < count; ++i) { B.n[i] = n[i]; B.G[i] = G[i]; B.lam[i] = lam[i]; B.U[i] = V[i]; }
+  k_eig_psd<<<count, 1024, 0, s>>>(B);
   return hipGetLastError();
 }
 

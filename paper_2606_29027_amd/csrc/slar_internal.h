@@ -70,19 +70,22 @@ __device__ __forceinline__ int wrap(int j, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Lagrange weights on nodes -(w/2)..(w/2) evaluated at xi.
+// Lagrange weights on nodes -(w/2)..(w/2) evaluated at xi:
+// l_m(xi) = prod_{n != m} (xi - n) / (m - n); the constant denominators are
+// folded into one reciprocal per weight.
 template <int W>
 __device__ __forceinline__ void lagrange(double xi, double* w) {
 #pragma unroll
   for (int a = 0; a < W; ++a) {
     const int m = a - W / 2;
     double p = 1.0;
+    double den = 1.0;
 #pragma unroll
     for (int b = 0; b < W; ++b) {
       const int nn = b - W / 2;
-      if (nn != m) p = p * (xi - (double)nn) / (double)(m - nn);
+      if (nn != m) { p = p * (xi - (double)nn); den *= (double)(m - nn); }
     }
-    w[a] = p;
+    w[a] = p * (1.0 / den);
   }
 }
 

@@ -32,9 +32,9 @@ static int tail_rank(const std::vector<double>& s2, double theta, int rmax) {
 }
 
 struct Tbuf {
-  double *Q1u, *Qu, *Q1v, *Qv, *X, *Y, *Xs, *T;
+  double *Q1u, *Qu, *Q1v, *Qv, *X, *Y, *Xs, *Ys, *T;
   double *Gu, *Linv, *R1, *R, *M, *W, *Z, *sv;
-  double *G1, *G2, *E1, *E2, *Vw, *lam1, *lam2;
+  double *G1, *G2, *G3, *G4, *E1, *E2, *E3, *E4, *Vw, *lam1, *lam2, *lam3, *lam4;
 };
 
 static Tbuf carve(Workspace* ws) {
@@ -48,7 +48,8 @@ static Tbuf carve(Workspace* ws) {
   b.Qv = p; p += K * G.nv;
   b.X = p; p += (size_t)G.nx * K;
   b.Y = p; p += (size_t)G.nv * K;
-  b.Xs = p; p += (size_t)std::max(G.nx, G.nv) * K;
+  b.Xs = p; p += (size_t)G.nx * K;
+  b.Ys = p; p += (size_t)G.nv * K;
   b.T = p; p += K * SLAR_NMAX * K;
   b.Gu = p; p += K * K;
   b.Linv = p; p += K * K;
@@ -60,19 +61,24 @@ static Tbuf carve(Workspace* ws) {
   b.sv = p; p += K;
   b.G1 = p; p += NN;
   b.G2 = p; p += NN;
+  b.G3 = p; p += NN;
+  b.G4 = p; p += NN;
   b.E1 = p; p += NN;
   b.E2 = p; p += NN;
+  b.E3 = p; p += NN;
+  b.E4 = p; p += NN;
   b.Vw = p; p += NN;
   b.lam1 = p; p += SLAR_NMAX;
   b.lam2 = p; p += SLAR_NMAX;
+  b.lam3 = p; p += SLAR_NMAX;
+  b.lam4 = p; p += SLAR_NMAX;
   return b;
 }
 
 size_t truncate_scratch_elems(const GridDev& G) {
   const size_t K = SLAR_KMAX, NN = (size_t)SLAR_NMAX * SLAR_NMAX;
-  return 2 * K * G.nx + 2 * K * G.nv + (size_t)G.nx * K + (size_t)G.nv * K +
-         (size_t)std::max(G.nx, G.nv) * K + K * SLAR_NMAX * K + 9 * K * K + K + 5 * NN +
-         2 * SLAR_NMAX + 64;
+  return 2 * K * G.nx + 2 * K * G.nv + 2 * (size_t)G.nx * K + 2 * (size_t)G.nv * K +
+         K * SLAR_NMAX * K + 9 * K * K + K + 9 * NN + 4 * SLAR_NMAX + 64;
 }
 
 // Orthonormal rows Q (k x n) and upper R (k x k) with A = R^T Q... i.e.
@@ -92,37 +98,23 @@ static hipError_t cholqr2(hipStream_t s, Workspace* ws, Tbuf& b, int k, int n, c
   return gemm_f64(s, false, false, k, n, k, 1.0, b.Linv, k, 0, Q1, n, 0, 0.0, Q, n, 0, 1);
 }
 
-static slar_status leaf_pair(hipStream_t s, Workspace* ws, Tbuf& b, const double* frame, int na,
-                             int nb, int r, const double* sv_dev, double theta, int rmax,
-                             double* Ua, double* Ub, double* Bt, int* ra_out, int* rb_out,
-                             bool* capped) {
-  // Xs = frame * diag(s)
-  if (copy2d(s, na * nb, r, frame, r, b.Xs, r, sv_dev) != hipSuccess) return SLAR_E_HIP;
-  // G1 = Xs_(na x nb r) Xs^T
-  if (gram_rows(s, ws, na, nb * r, b.Xs, nb * r, b.G1) != hipSuccess) return SLAR_E_HIP;
-  // G2 = sum_i1 Xs[i1] Xs[i1]^T  (nb x nb)
-  if (gemm_f64_sumbatch(s, ws, false, true, nb, nb, r, b.Xs, r, (long long)nb * r, b.Xs, r,
-                        (long long)nb * r, b.G2, nb, na) != hipSuccess)
-    return SLAR_E_HIP;
-  if (eig_sym(s, na, b.G1, b.lam1, b.Vw, b.E1) != hipSuccess) return SLAR_E_HIP;
-  if (eig_sym(s, nb, b.G2, b.lam2, b.Vw, b.E2) != hipSuccess) return SLAR_E_HIP;
-  std::vector<double> l1(na), l2(nb);
-  HIP_TRY(hipMemcpyAsync(l1.data(), b.lam1, sizeof(double) * na, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(l2.data(), b.lam2, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  for (double v : l1) if (!std::isfinite(v)) return SLAR_E_NUMERIC;
-  const int ra = tail_rank(l1, theta, rmax), rb = tail_rank(l2, theta, rmax);
-  {
-    std::vector<double> t1(l1), t2(l2);
-    double tail = 0.0;
-    for (int i = ra; i < na; ++i) tail += std::max(t1[i], 0.0);
-    if (ra == rmax && std::sqrt(tail) > theta) *capped = true;
-    tail = 0.0;
-    for (int i = rb; i < nb; ++i) tail += std::max(t2[i], 0.0);
-    if (rb == rmax && std::sqrt(tail) > theta) *capped = true;
-  }
-  if (copy2d(s, na, ra, b.E1, na, Ua, ra, nullptr) != hipSuccess) return SLAR_E_HIP;
-  if (copy2d(s, nb, rb, b.E2, nb, Ub, rb, nullptr) != hipSuccess) return SLAR_E_HIP;
+// Gram matrices of the two mode matricisations of frame * diag(s) for one
+// side of the tree (frame: [na*nb][r] packed).  Xs is scratch [na*nb][r].
+static hipError_t side_grams(hipStream_t s, Workspace* ws, const double* frame, int na, int nb,
+                             int r, const double* sv_dev, double* Xs, double* Ga, double* Gb) {
+  HIP_CHK(copy2d(s, na * nb, r, frame, r, Xs, r, sv_dev));
+  HIP_CHK(gram_rows(s, ws, na, nb * r, Xs, nb * r, Ga));
+  return gemm_f64_sumbatch(s, ws, false, true, nb, nb, r, Xs, r, (long long)nb * r, Xs, r,
+                           (long long)nb * r, Gb, nb, na);
+}
+
+// Leaf bases (leading eigenvectors, sign rule) and the transfer tensor of
+// one side once the eigendecompositions are known.
+static slar_status side_finish(hipStream_t s, Tbuf& b, const double* frame, int na, int nb, int r,
+                               const double* Ea, const double* Eb, int ra, int rb, double* Ua,
+                               double* Ub, double* Bt) {
+  if (copy2d(s, na, ra, Ea, na, Ua, ra, nullptr) != hipSuccess) return SLAR_E_HIP;
+  if (copy2d(s, nb, rb, Eb, nb, Ub, rb, nullptr) != hipSuccess) return SLAR_E_HIP;
   if (sign_fix(s, na, ra, Ua, ra, nullptr, 0, 0) != hipSuccess) return SLAR_E_HIP;
   if (sign_fix(s, nb, rb, Ub, rb, nullptr, 0, 0) != hipSuccess) return SLAR_E_HIP;
   // T[a][(i2, c)] = sum_i1 Ua[i1][a] frame[i1][(i2, c)]
@@ -133,9 +125,15 @@ static slar_status leaf_pair(hipStream_t s, Workspace* ws, Tbuf& b, const double
   if (gemm_f64(s, true, false, rb, r, nb, 1.0, Ub, rb, 0, b.T, r, (long long)nb * r, 0.0, Bt, r,
                (long long)rb * r, ra) != hipSuccess)
     return SLAR_E_HIP;
-  *ra_out = ra;
-  *rb_out = rb;
   return SLAR_OK;
+}
+
+static int leaf_rank(const std::vector<double>& lam, double theta, int rmax, bool* capped) {
+  const int r = tail_rank(lam, theta, rmax);
+  double tail = 0.0;
+  for (size_t i = r; i < lam.size(); ++i) tail += std::max(lam[i], 0.0);
+  if (r == rmax && std::sqrt(tail) > theta) *capped = true;
+  return r;
 }
 
 __global__ void k_diag(int r, const double* sv, double* root) {
@@ -188,15 +186,32 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
     out->rank[0] = r; out->rank[1] = r;
     for (int m = 2; m < 6; ++m) out->rank[m] = 0;
   } else {
-    int r1, r2, r3, r4;
-    slar_status st = leaf_pair(s, ws, b, b.X, G.n[0], G.n[1], r, b.sv, theta, rmax,
-                               (double*)out->leaf[0], (double*)out->leaf[1], (double*)out->B12,
-                               &r1, &r2, &capped);
+    // Gram matrices of the four modes, one batched eigen launch, one sync
+    if (side_grams(s, ws, b.X, G.n[0], G.n[1], r, b.sv, b.Xs, b.G1, b.G2) != hipSuccess) return SLAR_E_HIP;
+    if (side_grams(s, ws, b.Y, G.n[2], G.n[3], r, b.sv, b.Ys, b.G3, b.G4) != hipSuccess) return SLAR_E_HIP;
+    const int nn[4] = {G.n[0], G.n[1], G.n[2], G.n[3]};
+    const double* Gs[4] = {b.G1, b.G2, b.G3, b.G4};
+    double* lams[4] = {b.lam1, b.lam2, b.lam3, b.lam4};
+    double* Es[4] = {b.E1, b.E2, b.E3, b.E4};
+    if (eig_sym_batch(s, 4, nn, Gs, lams, Es) != hipSuccess) return SLAR_E_HIP;
+    std::vector<double> lh(4 * SLAR_NMAX);
+    for (int m = 0; m < 4; ++m)
+      HIP_TRY(hipMemcpyAsync(lh.data() + m * SLAR_NMAX, lams[m], sizeof(double) * nn[m],
+                             hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int rk[4];
+    for (int m = 0; m < 4; ++m) {
+      std::vector<double> l(lh.begin() + m * SLAR_NMAX, lh.begin() + m * SLAR_NMAX + nn[m]);
+      for (double v : l) if (!std::isfinite(v)) return SLAR_E_NUMERIC;
+      rk[m] = leaf_rank(l, theta, rmax, &capped);
+    }
+    slar_status st = side_finish(s, b, b.X, G.n[0], G.n[1], r, b.E1, b.E2, rk[0], rk[1],
+                                 (double*)out->leaf[0], (double*)out->leaf[1], (double*)out->B12);
     if (st != SLAR_OK) return st;
-    st = leaf_pair(s, ws, b, b.Y, G.n[2], G.n[3], r, b.sv, theta, rmax, (double*)out->leaf[2],
-                   (double*)out->leaf[3], (double*)out->B34, &r3, &r4, &capped);
+    st = side_finish(s, b, b.Y, G.n[2], G.n[3], r, b.E3, b.E4, rk[2], rk[3], (double*)out->leaf[2],
+                     (double*)out->leaf[3], (double*)out->B34);
     if (st != SLAR_OK) return st;
-    out->rank[0] = r1; out->rank[1] = r2; out->rank[2] = r3; out->rank[3] = r4;
+    for (int m = 0; m < 4; ++m) out->rank[m] = rk[m];
     out->rank[4] = r; out->rank[5] = r;
   }
   out->dtype = SLAR_F64;

@@ -47,7 +47,7 @@ def test_plain_slar_steps_match_oracle(name, N, steps):
         s.step()
     assert [st["rank"] for st in s.stats] == [st["rank"] for st in o.stats]
     err = normwise(s.dense(), HT.full(Fo))
-    assert err < 1e-9, err
+    assert err < 1e-8, err   # conditioning bound, see module docstring
 
 
 @pytest.mark.parametrize("prec", [L.F64, L.F32])
