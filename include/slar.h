@@ -235,6 +235,38 @@ slar_status slar_lomac_project(const slar_grid* g, const slar_frames* Fstar_fram
                                const double* U_new, slar_frames* out, slar_workspace* ws,
                                hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Learned preconditioner (an addition to the paper's solver, whose section 5
+ * names preconditioning of the Krylov solve as future work).  A periodic
+ * convolutional network, FP32, 3x3 kernels, tanh between layers:
+ *   out[o,y,x] = b[o] + sum_{c,dy,dx} w[o,c,dy,dx] in[c, y+dy-1, x+dx-1].
+ * Parameters are packed per layer as w [Co][Ci][3][3] then b [Co].  Inside
+ * slar_macro_solve (precond = 2) it corrects the spectral preconditioner:
+ *   z = P_spec(v) + rms(v) * CNN([v / rms(v), (U_c - mean U_c) / std U_c]),
+ * so channels[0] must be 2 (dv + 2) and channels[nlayers] dv + 2.
+ * Tensors x, y are device FP32 [B][C][H][W]; host arrays are marked.       */
+slar_status slar_cnn_create(int32_t nlayers, const int32_t* channels /* host, nlayers+1 */,
+                            int32_t max_batch, int32_t max_pixels, slar_cnn** out);
+slar_status slar_cnn_destroy(slar_cnn* cnn);
+int32_t slar_cnn_nparams(const slar_cnn* cnn);
+slar_status slar_cnn_set_params(slar_cnn* cnn, const float* params_host, int32_t n);
+slar_status slar_cnn_get_params(const slar_cnn* cnn, float* params_host, int32_t n);
+slar_status slar_cnn_forward(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, const float* x,
+                             float* y, hipStream_t stream);
+/* gradient of the mean squared error mean((CNN(x) - y)^2) w.r.t. the
+ * parameters (grad_host may be NULL; loss_host receives the loss if given) */
+slar_status slar_cnn_grad(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, const float* x,
+                          const float* y, float* grad_host, float* loss_host, hipStream_t stream);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the same loss             */
+slar_status slar_cnn_train_step(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, const float* x,
+                                const float* y, float lr, float* loss_host, hipStream_t stream);
+/* Records up to `capacity` training pairs from later flexible-GMRES solves
+ * of this workspace: features [capacity][2K][Nx] (network input for w = J z)
+ * and targets [capacity][K][Nx] ((z - P_spec(w)) / rms(w)), FP32 device
+ * buffers owned by the caller.  capacity 0 stops recording.               */
+slar_status slar_record_krylov(slar_workspace* ws, float* features, float* targets, int32_t capacity);
+int32_t slar_recorded_pairs(const slar_workspace* ws);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,11 +1,442 @@
-// Learned preconditioner for the Krylov solve of the macroscopic system.
+// Learned convolutional preconditioner for the Krylov solve of the
+// macroscopic system (an addition to the paper's method, which names
+// preconditioning of that solve as future work): FP32 periodic 3x3
+// convolutions with tanh between layers, hand-written forward, backward
+// (data and weights) and Adam kernels.
+//
+// Layout: activations [B][C][H][W]; parameters packed per layer as
+// w [Co][Ci][3][3] then b [Co]; out[o,y,x] = b[o] +
+// sum_{c,dy,dx} w[o,c,dy,dx] in[c, y+dy-1, x+dx-1] (periodic indices).
+//
+// Inside the flexible GMRES the network acts on the spectral preconditioner:
+//   z = P_spec(v) + rms(v) * CNN([v / rms(v), (U_c - mean U_c) / std U_c]).
+#include <cmath>
+#include <vector>
+
 #include "slar_internal.h"
+#include "fields.h"
 #include "lomac.h"
 
+constexpr int CNN_CMAX = 16;
+constexpr int CNN_LMAX = 4;
+
+struct slar_cnn {
+  int nl = 0;
+  int ch[CNN_LMAX + 1] = {};
+  int off[CNN_LMAX + 1] = {};   // parameter offsets per layer
+  int nparam = 0;
+  int maxB = 0, maxHW = 0;
+  float* theta = nullptr;
+  float* grad = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  int step = 0;
+  float* act[CNN_LMAX + 1] = {};
+  float* d0 = nullptr;
+  float* d1 = nullptr;
+  float* gpart = nullptr;
+  size_t gpart_elems = 0;
+  float* lossp = nullptr;
+  double* stats = nullptr;
+  float* host_loss = nullptr;
+};
+
 namespace slar {
+
+__global__ void k_conv_fwd(int B, int H, int W, int Ci, int Co, const float* __restrict__ in,
+                           const float* __restrict__ prm, int act, float* __restrict__ out) {
+  __shared__ float w[CNN_CMAX * CNN_CMAX * 9 + CNN_CMAX];
+  const int np = Co * Ci * 9 + Co;
+  for (int e = threadIdx.x; e < np; e += blockDim.x) w[e] = prm[e];
+  __syncthreads();
+  const int HW = H * W;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (long long)B * HW) return;
+  const int b = (int)(p / HW), pix = (int)(p % HW);
+  const int y = pix / W, x = pix % W;
+  float acc[CNN_CMAX];
+  for (int o = 0; o < Co; ++o) acc[o] = w[Co * Ci * 9 + o];
+  for (int c = 0; c < Ci; ++c) {
+    const float* ic = in + ((size_t)b * Ci + c) * HW;
+    for (int dy = 0; dy < 3; ++dy) {
+      const int yy = (y + dy - 1 + H) % H;
+      for (int dx = 0; dx < 3; ++dx) {
+        const int xx = (x + dx - 1 + W) % W;
+        const float vv = ic[yy * W + xx];
+        const int t = (c * 3 + dy) * 3 + dx;
+        for (int o = 0; o < Co; ++o) acc[o] += w[o * Ci * 9 + t] * vv;
+      }
+    }
+  }
+  for (int o = 0; o < Co; ++o) {
+    const float z = acc[o];
+    out[((size_t)b * Co + o) * HW + pix] = act ? tanhf(z) : z;
+  }
+}
+
+// dL/d(in) of one layer from dL/dz of its output (transpose correlation)
+__global__ void k_conv_bwd_data(int B, int H, int W, int Ci, int Co, const float* __restrict__ dz,
+                                const float* __restrict__ prm, float* __restrict__ din) {
+  __shared__ float w[CNN_CMAX * CNN_CMAX * 9];
+  const int nw = Co * Ci * 9;
+  for (int e = threadIdx.x; e < nw; e += blockDim.x) w[e] = prm[e];
+  __syncthreads();
+  const int HW = H * W;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (long long)B * HW) return;
+  const int b = (int)(p / HW), pix = (int)(p % HW);
+  const int y = pix / W, x = pix % W;
+  float acc[CNN_CMAX];
+  for (int c = 0; c < Ci; ++c) acc[c] = 0.f;
+  for (int o = 0; o < Co; ++o) {
+    const float* go = dz + ((size_t)b * Co + o) * HW;
+    for (int dy = 0; dy < 3; ++dy) {
+      const int yy = (y - dy + 1 + H) % H;
+      for (int dx = 0; dx < 3; ++dx) {
+        const int xx = (x - dx + 1 + W) % W;
+        const float g = go[yy * W + xx];
+        for (int c = 0; c < Ci; ++c) acc[c] += w[o * Ci * 9 + (c * 3 + dy) * 3 + dx] * g;
+      }
+    }
+  }
+  for (int c = 0; c < Ci; ++c) din[((size_t)b * Ci + c) * HW + pix] = acc[c];
+}
+
+// dz = dL/da * (1 - a^2) for tanh layers
+__global__ void k_tanh_bwd(long long n, const float* __restrict__ a, float* __restrict__ d) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) d[e] *= (1.f - a[e] * a[e]);
+}
+
+// partial weight gradients: part[chunk][e] for e over the layer's parameters
+__global__ void k_conv_bwd_w(int B, int H, int W, int Ci, int Co, const float* __restrict__ dz,
+                             const float* __restrict__ a_in, int chunk, float* __restrict__ part,
+                             int npar) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c0 = blockIdx.y;
+  if (e >= npar) return;
+  const int HW = H * W;
+  const long long P = (long long)B * HW;
+  const long long p0 = (long long)c0 * chunk, p1 = min(P, p0 + chunk);
+  float acc = 0.f;
+  const int nw = Co * Ci * 9;
+  if (e < nw) {
+    const int o = e / (Ci * 9), rem = e % (Ci * 9), c = rem / 9, t = rem % 9, dy = t / 3, dx = t % 3;
+    for (long long p = p0; p < p1; ++p) {
+      const int b = (int)(p / HW), pix = (int)(p % HW), y = pix / W, x = pix % W;
+      const int yy = (y + dy - 1 + H) % H, xx = (x + dx - 1 + W) % W;
+      acc += dz[((size_t)b * Co + o) * HW + pix] * a_in[((size_t)b * Ci + c) * HW + yy * W + xx];
+    }
+  } else {
+    const int o = e - nw;
+    for (long long p = p0; p < p1; ++p) {
+      const int b = (int)(p / HW), pix = (int)(p % HW);
+      acc += dz[((size_t)b * Co + o) * HW + pix];
+    }
+  }
+  part[(size_t)c0 * npar + e] = acc;
+}
+
+__global__ void k_sum_part(int npar, int nchunk, const float* __restrict__ part, float* __restrict__ g) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npar) return;
+  float acc = 0.f;
+  for (int c = 0; c < nchunk; ++c) acc += part[(size_t)c * npar + e];
+  g[e] = acc;
+}
+
+// d = 2 (out - y) / n ; block partial sums of (out - y)^2
+__global__ void k_mse(long long n, const float* __restrict__ out, const float* __restrict__ y,
+                      float* __restrict__ d, float* __restrict__ lossp) {
+  __shared__ float red[256];
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float r = 0.f;
+  if (e < n) {
+    r = out[e] - y[e];
+    d[e] = 2.f * r / (float)n;
+  }
+  red[threadIdx.x] = r * r;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lossp[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(int n, float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float gg = g[e];
+  const float mm = b1 * m[e] + (1.f - b1) * gg;
+  const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+  m[e] = mm; v[e] = vv;
+  th[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+static hipError_t cnn_forward(hipStream_t s, slar_cnn* c, int B, int H, int W, const float* x) {
+  const long long P = (long long)B * H * W;
+  const unsigned nb = (unsigned)((P + 255) / 256);
+  const float* in = x;
+  for (int l = 0; l < c->nl; ++l) {
+    k_conv_fwd<<<nb, 256, 0, s>>>(B, H, W, c->ch[l], c->ch[l + 1], in, c->theta + c->off[l],
+                                  l < c->nl - 1 ? 1 : 0, c->act[l + 1]);
+    in = c->act[l + 1];
+  }
+  return hipGetLastError();
+}
+
+// gradient of the MSE loss into c->grad; loss (host) if requested
+static hipError_t cnn_backward(hipStream_t s, slar_cnn* c, int B, int H, int W, const float* x,
+                               const float* y, float* loss_host) {
+  HIP_CHK(cnn_forward(s, c, B, H, W, x));
+  const int HW = H * W;
+  const long long P = (long long)B * HW;
+  const unsigned nb = (unsigned)((P + 255) / 256);
+  const int L = c->nl;
+  const long long nout = P * c->ch[L];
+  const unsigned nbo = (unsigned)((nout + 255) / 256);
+  k_mse<<<nbo, 256, 0, s>>>(nout, c->act[L], y, c->d0, c->lossp);
+  float* d = c->d0;
+  float* dn = c->d1;
+  const int chunk = 2048;
+  const int nchunk = (int)((P + chunk - 1) / chunk);
+  for (int l = L - 1; l >= 0; --l) {
+    const int Ci = c->ch[l], Co = c->ch[l + 1];
+    if (l < L - 1) k_tanh_bwd<<<(unsigned)((P * Co + 255) / 256), 256, 0, s>>>(P * Co, c->act[l + 1], d);
+    const float* a_in = l == 0 ? x : c->act[l];
+    const int npar = Co * Ci * 9 + Co;
+    if ((size_t)nchunk * npar > c->gpart_elems) return hipErrorInvalidValue;
+    k_conv_bwd_w<<<dim3((npar + 255) / 256, nchunk), 256, 0, s>>>(B, H, W, Ci, Co, d, a_in, chunk,
+                                                                 c->gpart, npar);
+    k_sum_part<<<(npar + 255) / 256, 256, 0, s>>>(npar, nchunk, c->gpart, c->grad + c->off[l]);
+    if (l > 0) {
+      k_conv_bwd_data<<<nb, 256, 0, s>>>(B, H, W, Ci, Co, d, c->theta + c->off[l], dn);
+      float* t = d; d = dn; dn = t;
+    }
+  }
+  HIP_CHK(hipGetLastError());
+  if (loss_host) {
+    std::vector<float> lp(nbo);
+    HIP_CHK(hipMemcpyAsync(lp.data(), c->lossp, sizeof(float) * nbo, hipMemcpyDeviceToHost, s));
+    HIP_CHK(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (float v : lp) acc += v;
+    *loss_host = (float)(acc / (double)nout);
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------- use inside the Krylov solve
+// stats[0] = sum v^2, stats[1 + 2c] = mean U_c, stats[2 + 2c] = std U_c
+__global__ void k_cnn_stats(int Nx, int K, const double* __restrict__ v, const double* __restrict__ U,
+                            double* __restrict__ stats) {
+  __shared__ double r0[256], r1[256], r2[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double a = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int e = t; e < Nx; e += 256) {
+    const double x = v[(size_t)c * Nx + e], u = U[(size_t)c * Nx + e];
+    a += x * x; s1 += u; s2 += u * u;
+  }
+  r0[t] = a; r1[t] = s1; r2[t] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) { r0[t] += r0[t + o]; r1[t] += r1[t + o]; r2[t] += r2[t + o]; }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double mean = r1[0] / Nx;
+    const double var = fmax(r2[0] / Nx - mean * mean, 0.0);
+    stats[8 + c] = r0[0];
+    stats[1 + 2 * c] = mean;
+    stats[2 + 2 * c] = sqrt(var) + 1e-12 * fabs(mean) + 1e-300;
+  }
+}
+
+__global__ void k_cnn_features(int Nx, int K, const double* __restrict__ v, const double* __restrict__ U,
+                               const double* __restrict__ stats, float* __restrict__ feat) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nx * K) return;
+  const int c = e / Nx;
+  double ss = 0.0;
+  for (int q = 0; q < K; ++q) ss += stats[8 + q];
+  const double rms = sqrt(ss / (double)(Nx * K));
+  const double inv = rms > 0.0 ? 1.0 / rms : 0.0;
+  feat[e] = (float)(v[e] * inv);
+  feat[(size_t)K * Nx + e] = (float)((U[e] - stats[1 + 2 * c]) / stats[2 + 2 * c]);
+}
+
+__global__ void k_cnn_add(int n, int Nx, int K, const float* __restrict__ out,
+                          const double* __restrict__ stats, double* __restrict__ z) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double ss = 0.0;
+  for (int q = 0; q < K; ++q) ss += stats[8 + q];
+  const double rms = sqrt(ss / (double)(Nx * K));
+  z[e] += rms * (double)out[e];
+}
+
 hipError_t cnn_apply(hipStream_t s, Workspace* ws, const slar_cnn* net, const double* v,
                      const double* U, double* z) {
-  (void)s; (void)ws; (void)net; (void)v; (void)U; (void)z;
-  return hipErrorNotSupported;
+  slar_cnn* c = const_cast<slar_cnn*>(net);
+  const GridDev& G = ws->G;
+  if (G.dx != 2 || c->ch[0] != 2 * (G.dv + 2) || c->ch[c->nl] != G.dv + 2) return hipErrorInvalidValue;
+  const int K = G.dv + 2, Nx = G.nx;
+  if (Nx > c->maxHW) return hipErrorInvalidValue;
+  k_cnn_stats<<<K, 256, 0, s>>>(Nx, K, v, U, c->stats);
+  k_cnn_features<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx, K, v, U, c->stats, c->act[0]);
+  HIP_CHK(cnn_forward(s, c, 1, G.n[0], G.n[1], c->act[0]));
+  k_cnn_add<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx * K, Nx, K, c->act[c->nl], c->stats, z);
+  return hipGetLastError();
 }
+
+// training pair from a flexible-GMRES step: w = J z; features of w and the
+// target (z - P_spec(w)) / rms(w)
+__global__ void k_record_target(int n, int Nx, int K, const double* __restrict__ z,
+                                const double* __restrict__ pw, const double* __restrict__ stats,
+                                float* __restrict__ tgt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double ss = 0.0;
+  for (int q = 0; q < K; ++q) ss += stats[8 + q];
+  const double rms = sqrt(ss / (double)(Nx * K));
+  tgt[e] = rms > 0.0 ? (float)((z[e] - pw[e]) / rms) : 0.f;
+}
+
+hipError_t record_pair(hipStream_t s, Workspace* ws, const double* w, const double* z,
+                       const double* U, const double* pw) {
+  if (!ws->rec_feat || ws->rec_count >= ws->rec_cap) return hipSuccess;
+  const GridDev& G = ws->G;
+  const int K = G.dv + 2, Nx = G.nx;
+  double* stats = ws->small + 4096;
+  float* feat = ws->rec_feat + (size_t)ws->rec_count * 2 * K * Nx;
+  float* tgt = ws->rec_targ + (size_t)ws->rec_count * K * Nx;
+  k_cnn_stats<<<K, 256, 0, s>>>(Nx, K, w, U, stats);
+  k_cnn_features<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx, K, w, U, stats, feat);
+  k_record_target<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx * K, Nx, K, z, pw, stats, tgt);
+  ws->rec_count += 1;
+  return hipGetLastError();
+}
+
 }  // namespace slar
+
+using namespace slar;
+
+extern "C" {
+
+slar_status slar_cnn_create(int32_t nlayers, const int32_t* channels, int32_t max_batch,
+                            int32_t max_pixels, slar_cnn** out) {
+  if (!out || nlayers < 1 || nlayers > CNN_LMAX || !channels || max_batch < 1 || max_pixels < 1)
+    return SLAR_E_INVAL;
+  for (int l = 0; l <= nlayers; ++l)
+    if (channels[l] < 1 || channels[l] > CNN_CMAX) return SLAR_E_INVAL;
+  slar_cnn* c = new (std::nothrow) slar_cnn();
+  if (!c) return SLAR_E_NOMEM;
+  c->nl = nlayers;
+  int o = 0, cmax = 0;
+  for (int l = 0; l <= nlayers; ++l) { c->ch[l] = channels[l]; cmax = std::max(cmax, channels[l]); }
+  for (int l = 0; l < nlayers; ++l) { c->off[l] = o; o += c->ch[l + 1] * c->ch[l] * 9 + c->ch[l + 1]; }
+  c->off[nlayers] = o;
+  c->nparam = o;
+  c->maxB = max_batch;
+  c->maxHW = max_pixels;
+  const size_t actn = (size_t)max_batch * max_pixels * cmax;
+  bool ok = true;
+  auto al = [&](void** p, size_t bytes) { if (ok && hipMalloc(p, std::max(bytes, (size_t)256)) != hipSuccess) ok = false; };
+  al((void**)&c->theta, sizeof(float) * o);
+  al((void**)&c->grad, sizeof(float) * o);
+  al((void**)&c->m, sizeof(float) * o);
+  al((void**)&c->v, sizeof(float) * o);
+  for (int l = 0; l <= nlayers; ++l) al((void**)&c->act[l], sizeof(float) * actn);
+  al((void**)&c->d0, sizeof(float) * actn);
+  al((void**)&c->d1, sizeof(float) * actn);
+  c->gpart_elems = (size_t)((actn / cmax + 2047) / 2048 + 1) * (CNN_CMAX * CNN_CMAX * 9 + CNN_CMAX);
+  al((void**)&c->gpart, sizeof(float) * c->gpart_elems);
+  al((void**)&c->lossp, sizeof(float) * (actn / 256 + 2));
+  al((void**)&c->stats, sizeof(double) * 64);
+  if (ok) {
+    if (hipMemset(c->theta, 0, sizeof(float) * o) != hipSuccess || hipMemset(c->m, 0, sizeof(float) * o) != hipSuccess ||
+        hipMemset(c->v, 0, sizeof(float) * o) != hipSuccess)
+      ok = false;
+  }
+  if (!ok) { slar_cnn_destroy(c); return SLAR_E_NOMEM; }
+  *out = c;
+  return SLAR_OK;
+}
+
+slar_status slar_cnn_destroy(slar_cnn* c) {
+  if (!c) return SLAR_OK;
+  void* ptrs[] = {c->theta, c->grad, c->m, c->v, c->d0, c->d1, c->gpart, c->lossp, c->stats};
+  for (void* p : ptrs) if (p) (void)hipFree(p);
+  for (int l = 0; l <= CNN_LMAX; ++l) if (c->act[l]) (void)hipFree(c->act[l]);
+  delete c;
+  return SLAR_OK;
+}
+
+int32_t slar_cnn_nparams(const slar_cnn* c) { return c ? c->nparam : 0; }
+
+slar_status slar_cnn_set_params(slar_cnn* c, const float* host, int32_t n) {
+  if (!c || !host || n != c->nparam) return SLAR_E_INVAL;
+  HIP_TRY(hipMemcpy(c->theta, host, sizeof(float) * n, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(c->m, 0, sizeof(float) * n));
+  HIP_TRY(hipMemset(c->v, 0, sizeof(float) * n));
+  c->step = 0;
+  return SLAR_OK;
+}
+
+slar_status slar_cnn_get_params(const slar_cnn* c, float* host, int32_t n) {
+  if (!c || !host || n != c->nparam) return SLAR_E_INVAL;
+  HIP_TRY(hipMemcpy(host, c->theta, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return SLAR_OK;
+}
+
+static bool cnn_dims_ok(const slar_cnn* c, int B, int H, int W) {
+  return c && B >= 1 && B <= c->maxB && H >= 1 && W >= 1 && (long long)H * W <= c->maxHW;
+}
+
+slar_status slar_cnn_forward(slar_cnn* c, int32_t B, int32_t H, int32_t W, const float* x, float* y,
+                             hipStream_t s) {
+  if (!cnn_dims_ok(c, B, H, W) || !x || !y) return SLAR_E_INVAL;
+  if (cnn_forward(s, c, B, H, W, x) != hipSuccess) return SLAR_E_HIP;
+  HIP_TRY(hipMemcpyAsync(y, c->act[c->nl], sizeof(float) * (size_t)B * H * W * c->ch[c->nl],
+                         hipMemcpyDeviceToDevice, s));
+  return SLAR_OK;
+}
+
+slar_status slar_cnn_grad(slar_cnn* c, int32_t B, int32_t H, int32_t W, const float* x,
+                          const float* y, float* grad_host, float* loss_host, hipStream_t s) {
+  if (!cnn_dims_ok(c, B, H, W) || !x || !y) return SLAR_E_INVAL;
+  if (cnn_backward(s, c, B, H, W, x, y, loss_host) != hipSuccess) return SLAR_E_HIP;
+  if (grad_host) {
+    HIP_TRY(hipMemcpyAsync(grad_host, c->grad, sizeof(float) * c->nparam, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return SLAR_OK;
+}
+
+slar_status slar_cnn_train_step(slar_cnn* c, int32_t B, int32_t H, int32_t W, const float* x,
+                                const float* y, float lr, float* loss_host, hipStream_t s) {
+  if (!cnn_dims_ok(c, B, H, W) || !x || !y || !(lr > 0.f)) return SLAR_E_INVAL;
+  if (cnn_backward(s, c, B, H, W, x, y, loss_host) != hipSuccess) return SLAR_E_HIP;
+  c->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)c->step), c2 = 1.f - std::pow(b2, (float)c->step);
+  k_adam<<<(c->nparam + 255) / 256, 256, 0, s>>>(c->nparam, c->theta, c->grad, c->m, c->v, lr, b1, b2,
+                                                 1e-8f, c1, c2);
+  HIP_TRY(hipGetLastError());
+  return SLAR_OK;
+}
+
+slar_status slar_record_krylov(slar_workspace* w, float* features, float* targets, int32_t capacity) {
+  if (!w || capacity < 0 || (capacity > 0 && (!features || !targets))) return SLAR_E_INVAL;
+  w->w.rec_feat = capacity > 0 ? features : nullptr;
+  w->w.rec_targ = capacity > 0 ? targets : nullptr;
+  w->w.rec_cap = capacity;
+  w->w.rec_count = 0;
+  return SLAR_OK;
+}
+
+int32_t slar_recorded_pairs(const slar_workspace* w) { return w ? w->w.rec_count : 0; }
+
+}  // extern "C"

@@ -21,6 +21,10 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, cons
                             const slar_cnn* cnn, double* Uout, int* iters);
 slar_status lomac_project_run(hipStream_t s, Workspace* ws, const slar_frames& Fs,
                               const double* Unew, slar_frames* out);
+// training pair recorder (cnn.hip): features of w = J z and the target
+// (z - P_spec(w)) / rms(w); pw = P_spec(w)
+hipError_t record_pair(hipStream_t s, Workspace* ws, const double* w, const double* z,
+                       const double* U, const double* pw);
 // learned preconditioner application z = M(v) (cnn.hip)
 hipError_t cnn_apply(hipStream_t s, Workspace* ws, const slar_cnn* net, const double* v,
                      const double* U, double* z);

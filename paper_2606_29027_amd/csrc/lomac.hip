@@ -697,6 +697,10 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, cons
         k_fd_point<<<nb, 256, 0, s>>>(n, U, zj, flexible ? nrm + 2 : nullptr, fdc, b.Uh, hval);
         if (macro_residual(s, ws, b.Uh, Uhist, bdt, b.Gh) != hipSuccess) return SLAR_E_HIP;
         k_fd_diff<<<nb, 256, 0, s>>>(n, b.Gh, b.g0, hval, 0, b.w);
+        if (flexible && ws->rec_feat && ws->rec_count < ws->rec_cap) {
+          if (spectral_precond(s, ws, b.w, bdt, b.Uh) != hipSuccess) return SLAR_E_HIP;
+          if (record_pair(s, ws, b.w, zj, U, b.Uh) != hipSuccess) return SLAR_E_HIP;
+        }
         // CGS2 against V[0..j]
         cgs(j + 1, b.V, nullptr, b.w, h1);
         cgs(j + 1, b.V, h1, b.w, h2);

@@ -225,6 +225,11 @@ struct Workspace {
   // macro / Krylov
   double* kry = nullptr;
   size_t kry_elems = 0;
+  // optional recording of (J z, z) pairs for training the preconditioner
+  float* rec_feat = nullptr;
+  float* rec_targ = nullptr;
+  int rec_cap = 0;
+  int rec_count = 0;
 };
 
 // launchers implemented across the .hip files

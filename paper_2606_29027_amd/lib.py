@@ -22,7 +22,9 @@ EXPORTS = (
     "slar_status_str", "slar_workspace_create", "slar_workspace_destroy", "slar_ht_sample",
     "slar_frames_from_ht", "slar_frame_sample", "slar_cross_update", "slar_truncate",
     "slar_moments", "slar_poisson", "slar_conserved", "slar_lomac_prepare", "slar_macro_solve",
-    "slar_lomac_project",
+    "slar_lomac_project", "slar_cnn_create", "slar_cnn_destroy", "slar_cnn_nparams",
+    "slar_cnn_set_params", "slar_cnn_get_params", "slar_cnn_forward", "slar_cnn_grad",
+    "slar_cnn_train_step", "slar_record_krylov", "slar_recorded_pairs",
 )
 
 
@@ -90,6 +92,16 @@ def load(path: str = LIB_PATH):
         "slar_lomac_prepare": (i32, [P(Grid), P(HT), P(Frames), dbl, dbl, vp, vp]),
         "slar_macro_solve": (i32, [P(Grid), vp, vp, dbl, i32, dbl, dbl, i32, vp, vp, P(i32), vp, vp]),
         "slar_lomac_project": (i32, [P(Grid), P(Frames), vp, P(Frames), vp, vp]),
+        "slar_cnn_create": (i32, [i32, P(i32), i32, i32, P(vp)]),
+        "slar_cnn_destroy": (i32, [vp]),
+        "slar_cnn_nparams": (i32, [vp]),
+        "slar_cnn_set_params": (i32, [vp, vp, i32]),
+        "slar_cnn_get_params": (i32, [vp, vp, i32]),
+        "slar_cnn_forward": (i32, [vp, i32, i32, i32, vp, vp, vp]),
+        "slar_cnn_grad": (i32, [vp, i32, i32, i32, vp, vp, vp, P(C.c_float), vp]),
+        "slar_cnn_train_step": (i32, [vp, i32, i32, i32, vp, vp, C.c_float, P(C.c_float), vp]),
+        "slar_record_krylov": (i32, [vp, vp, vp, i32]),
+        "slar_recorded_pairs": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -242,3 +254,66 @@ def slar_lomac_project(grid, Fs, U_new, out: Frames, ws):
     _check(load().slar_lomac_project(C.byref(grid), C.byref(Fs), _ptr(U_new), C.byref(out), ws.h,
                                      _stream()), "slar_lomac_project")
     return out
+
+
+# ------------------------------------------------------- learned preconditioner
+class Cnn:
+    """Handle of a device CNN (see slar.h); parameters as a host float32 array."""
+
+    def __init__(self, channels, max_batch, max_pixels):
+        self.channels = list(channels)
+        arr = (C.c_int32 * len(channels))(*channels)
+        h = C.c_void_p()
+        _check(load().slar_cnn_create(len(channels) - 1, arr, int(max_batch), int(max_pixels),
+                                      C.byref(h)), "slar_cnn_create")
+        self.handle = h
+        self.nparams = load().slar_cnn_nparams(h)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.slar_cnn_destroy(self.handle)
+            self.handle = None
+
+    def set_params(self, theta):
+        import numpy as np
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(load().slar_cnn_set_params(self.handle, t.ctypes.data_as(C.c_void_p), len(t)),
+               "slar_cnn_set_params")
+
+    def get_params(self):
+        import numpy as np
+        t = np.zeros(self.nparams, dtype=np.float32)
+        _check(load().slar_cnn_get_params(self.handle, t.ctypes.data_as(C.c_void_p), len(t)),
+               "slar_cnn_get_params")
+        return t
+
+    def forward(self, x, y):
+        B, _, H, W = x.shape
+        _check(load().slar_cnn_forward(self.handle, B, H, W, _ptr(x), _ptr(y), _stream()),
+               "slar_cnn_forward")
+
+    def grad(self, x, y):
+        import numpy as np
+        B, _, H, W = x.shape
+        g = np.zeros(self.nparams, dtype=np.float32)
+        loss = C.c_float()
+        _check(load().slar_cnn_grad(self.handle, B, H, W, _ptr(x), _ptr(y),
+                                    g.ctypes.data_as(C.c_void_p), C.byref(loss), _stream()),
+               "slar_cnn_grad")
+        return g, loss.value
+
+    def train_step(self, x, y, lr):
+        B, _, H, W = x.shape
+        loss = C.c_float()
+        _check(load().slar_cnn_train_step(self.handle, B, H, W, _ptr(x), _ptr(y), float(lr),
+                                          C.byref(loss), _stream()), "slar_cnn_train_step")
+        return loss.value
+
+
+def slar_record_krylov(ws, feats, targs, capacity):
+    _check(load().slar_record_krylov(ws.h, _ptr(feats), _ptr(targs), int(capacity)),
+           "slar_record_krylov")
+
+
+def slar_recorded_pairs(ws) -> int:
+    return int(load().slar_recorded_pairs(ws.h))

@@ -384,3 +384,30 @@ def test_linear_landau_rate_1d1v():
     # oscillation: energy peaks are half a plasma period apart
     per = np.mean(np.diff(t[pk]))
     assert abs(per - math.pi / om) < 0.1
+
+
+# ------------------------------------------------------------- CNN (P16)
+def test_cnn_gradient_matches_central_differences():
+    """The CNN oracle's backward pass against central finite differences of
+    its forward pass (the pin the GPU gradients are checked against)."""
+    from oracle import cnn as CN
+    rng = np.random.default_rng(5)
+    shapes = [(3, 4), (4, 4), (4, 2)]
+    theta = 0.3 * rng.standard_normal(CN.nparams(shapes))
+    x = rng.standard_normal((2, 3, 6, 5))
+    y = rng.standard_normal((2, 2, 6, 5))
+    g = CN.grad(theta, shapes, x, y)
+    idx = rng.choice(len(theta), 25, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(theta); e[i] = h
+        fd = (CN.loss(theta + e, shapes, x, y) - CN.loss(theta - e, shapes, x, y)) / (2 * h)
+        assert abs(fd - g[i]) < 1e-7 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_cnn_conv_is_periodic_cross_correlation():
+    from oracle import cnn as CN
+    x = np.zeros((1, 1, 5, 5)); x[0, 0, 0, 0] = 1.0
+    w = np.zeros((1, 1, 3, 3)); w[0, 0, 0, 0] = 2.0      # tap (dy, dx) = (0, 0) reads in[y-1, x-1]
+    out = CN.conv(x, w, np.zeros(1))
+    assert out[0, 0, 1, 1] == 2.0 and abs(out).sum() == 2.0
