@@ -40,8 +40,11 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="cells per dimension")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--variants", default="plain,spectral",
-                    help="comma list of macro solvers to time: plain, spectral, learned")
+    ap.add_argument("--variants", default="plain,spectral,learned",
+                    help="comma list of macro solvers to time: plain, spectral, learned "
+                         "(the last one listed is the headline)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, run one device copy of this size (for counter calibration)")
     return ap.parse_args()
 
 
@@ -90,6 +93,12 @@ def main():
     probes = SI.probe_indices(Nx, Nv, 64, 1234)
     prec = L.F32 if args.precision == "f32" else L.F64
     pc_code = {"plain": 0, "spectral": 1, "learned": 2}
+    if args.calib_copy_mib > 0:
+        a = torch.ones(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     runs = {}
     for name in [v for v in args.variants.split(",") if v]:
         cnn = None
@@ -103,19 +112,34 @@ def main():
         torch.cuda.synchronize()
         n0 = len(s.stats)
         infos = []
+        L.slar_timing_enable(s.ws, True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             infos.append(s.step())
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        tim = L.slar_timing_read(s.ws)
+        L.slar_timing_enable(s.ws, False)
         samples = sum(st["samples"] for st in s.stats[n0:])
         runs[name] = {"value": samples / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
                       "samples_per_step": samples / args.steps,
                       "newton_krylov": [[i.get("newton"), i.get("krylov")] for i in infos],
-                      "ranks": [st["ranks"] for st in s.stats[-3:]]}
+                      "ranks": [st["ranks"] for st in s.stats[-3:]], "timing": tim}
         del s
-    head = "learned" if "learned" in runs else ("spectral" if "spectral" in runs else list(runs)[0])
+    head = [v for v in args.variants.split(",") if v][-1]
     H = runs[head]
+    tim = H.pop("timing")
+    for r in runs.values():
+        r.pop("timing", None)
+    # dominant sampling kernel: whichever fiber kernel took more time
+    which = "row" if tim["row_ms"] >= tim["col_ms"] else "col"
+    ms, nl, by = tim[which + "_ms"], tim[which + "_launches"], tim[which + "_bytes"]
+    achieved = (by / nl) / (ms / nl * 1e-3) / 1e9 if nl > 0 and ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_aca_row" if which == "row" else "k_aca_col",
+                "avg_launch_us": 1e3 * ms / nl if nl else None, "launches": int(nl),
+                "algorithmic_bytes_per_launch": by / nl if nl else None}
     out = {
         "metric": "HT-SL sampled entries/s & time/step, 2D2V 128^4, learned vs plain at 1e-6",
         "value": H["value"],
@@ -132,7 +156,7 @@ def main():
         "config": {"workload": f"2D2V strong Landau alpha=0.5 k=0.5, {p.n[0]}^4, tol 1e-5, rmax 60, "
                                f"dt 0.2, CF3 + LoMaC/JFNK (BDF2), macro solver: {head}",
                    "variants": runs},
-        "roofline": None,
+        "roofline": roofline,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

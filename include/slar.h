@@ -267,6 +267,16 @@ slar_status slar_cnn_train_step(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, 
 slar_status slar_record_krylov(slar_workspace* ws, float* features, float* targets, int32_t capacity);
 int32_t slar_recorded_pairs(const slar_workspace* ws);
 
+/* In-stream timing of the two sampling kernels of slar_cross_update (HIP
+ * events recorded around every row-fiber and column-fiber launch while
+ * enabled; enabling clears the counters).  slar_timing_read fills host
+ * out[8] = {row ms, row launches, row algorithmic bytes, column ms, column
+ * launches, column algorithmic bytes, 0, 0}; algorithmic bytes per sampled
+ * entry = both stencil gathers of the frame tables + 16 k bytes of previous
+ * cross vectors + 8 bytes written.                                         */
+slar_status slar_timing_enable(slar_workspace* ws, int32_t on);
+slar_status slar_timing_read(const slar_workspace* ws, double* out);
+
 #ifdef __cplusplus
 }
 #endif

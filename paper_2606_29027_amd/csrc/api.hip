@@ -101,6 +101,7 @@ slar_status slar_workspace_destroy(slar_workspace* w) {
                  ws.small, ws.ismall, ws.tw[0], ws.tw[1], ws.cbuf, ws.psi, ws.lm, ws.kry};
   for (void* p : dev)
     if (p) (void)hipFree(p);
+  for (hipEvent_t e : ws.events) (void)hipEventDestroy(e);
   if (ws.aca_ctl_host) (void)hipHostFree(ws.aca_ctl_host);
   if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
   delete w;
@@ -302,6 +303,29 @@ slar_status slar_lomac_project(const slar_grid* g, const slar_frames* Fstar_fram
     return SLAR_E_INVAL;
   if (out->ld < Fstar_frames->r + g->dv + 2 || Fstar_frames->r + g->dv + 2 > SLAR_KMAX) return SLAR_E_INVAL;
   return lomac_project_run(stream, &w->w, *Fstar_frames, U_new, out);
+}
+
+slar_status slar_timing_enable(slar_workspace* w, int32_t on) {
+  if (!w) return SLAR_E_INVAL;
+  Workspace& ws = w->w;
+  if (on && ws.events.empty()) {
+    const int need = 3 * (64 + 64 + 1);
+    ws.events.resize(need);
+    for (int i = 0; i < need; ++i)
+      if (hipEventCreate(&ws.events[i]) != hipSuccess) {
+        ws.events.resize(i);
+        return SLAR_E_HIP;
+      }
+  }
+  ws.timing = on != 0;
+  for (double& v : ws.tstat) v = 0.0;
+  return SLAR_OK;
+}
+
+slar_status slar_timing_read(const slar_workspace* w, double* out /* host [8] */) {
+  if (!w || !out) return SLAR_E_INVAL;
+  for (int i = 0; i < 8; ++i) out[i] = w->w.tstat[i];
+  return SLAR_OK;
 }
 
 }  // extern "C"

@@ -429,11 +429,14 @@ size_t aca_ctl_bytes() { return sizeof(AcaCtl); }
 template <typename T, int W, int DX>
 static hipError_t aca_iterate(hipStream_t s, const GridDev& G, const AdvDev& A, const T* X,
                               const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
-                              unsigned char* used, double* part, int nprobe, const int* probes) {
+                              unsigned char* used, double* part, int nprobe, const int* probes,
+                              hipEvent_t* ev) {
   const unsigned bRow = (G.nv + FS_SAMPLES - 1) / FS_SAMPLES;
   const unsigned bCol = (G.nx + FS_SAMPLES - 1) / FS_SAMPLES;
   k_aca_row<T, W, DX><<<bRow, FS_THREADS, 0, s>>>(G, A, X, P, ld, r, ctl, U, V, used, part);
+  if (ev) HIP_CHK(hipEventRecord(ev[0], s));
   k_aca_col<T, W, DX><<<bCol, FS_THREADS, 0, s>>>(G, A, X, P, ld, r, ctl, U, V, used, part, (int)bRow);
+  if (ev) HIP_CHK(hipEventRecord(ev[1], s));
   k_aca_fin<T, W, DX><<<1, FS_THREADS, 0, s>>>(G, A, X, P, ld, r, ctl, U, V, used, part, (int)bRow,
                                                 (int)bCol, nprobe, probes);
   return hipGetLastError();
@@ -443,12 +446,12 @@ template <typename T>
 static hipError_t aca_iter_dispatch(hipStream_t s, const GridDev& G, const AdvDev& A, const T* X,
                                     const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
                                     unsigned char* used, double* part, int nprobe,
-                                    const int* probes) {
+                                    const int* probes, hipEvent_t* ev) {
   if (G.dx == 1) {
-    if (A.order == 5) return aca_iterate<T, 5, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes);
-    return aca_iterate<T, 3, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes);
+    if (A.order == 5) return aca_iterate<T, 5, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev);
+    return aca_iterate<T, 3, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev);
   }
-  return aca_iterate<T, 3, 2>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes);
+  return aca_iterate<T, 3, 2>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev);
 }
 
 hipError_t table_copy(hipStream_t s, int rows, int r, int ldin, const double* in, int ldo,
@@ -481,23 +484,47 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   HIP_TRY(hipMemcpyAsync(ctl, hc, sizeof(AcaCtl), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(ws->used, 0, G.nx, s));
   const int maxit = kmax + 64;
-  for (int it = 0; it < maxit; ++it) {
+  // algorithmic bytes of one sampled entry: both stencil gathers, the reads
+  // of the previous cross vectors (residual and dot products) and the write
+  const int rx = (G.dx == 2) ? adv.order * adv.order : adv.order;
+  const double gather_bytes = 2.0 * rx * ldt * (dt == SLAR_F32 ? 4.0 : 8.0) + 8.0;
+  const bool timing = ws->timing && (int)ws->events.size() >= 3 * (maxit + 1);
+  int k_known = 0, it_timed = 0;
+  auto harvest = [&](int upto) -> hipError_t {
+    for (; it_timed < upto; ++it_timed) {
+      float ms_row = 0.f, ms_col = 0.f;
+      HIP_CHK(hipEventElapsedTime(&ms_row, ws->events[3 * it_timed], ws->events[3 * it_timed + 1]));
+      HIP_CHK(hipEventElapsedTime(&ms_col, ws->events[3 * it_timed + 1], ws->events[3 * it_timed + 2]));
+      const double per = gather_bytes + 16.0 * k_known;
+      ws->tstat[0] += ms_row; ws->tstat[1] += 1; ws->tstat[2] += per * G.nv;
+      ws->tstat[3] += ms_col; ws->tstat[4] += 1; ws->tstat[5] += per * G.nx;
+    }
+    return hipSuccess;
+  };
+  int it = 0;
+  for (; it < maxit; ++it) {
     hipError_t e;
+    if (timing) HIP_TRY(hipEventRecord(ws->events[3 * it], s));
     if (dt == SLAR_F32)
       e = aca_iter_dispatch<float>(s, G, A, ws->X32, ws->P32, ldt, r, ctl, out->U, out->V,
-                                   ws->used, ws->aca_part, nprobe, probes);
+                                   ws->used, ws->aca_part, nprobe, probes,
+                                   timing ? &ws->events[3 * it + 1] : nullptr);
     else
       e = aca_iter_dispatch<double>(s, G, A, X64, P64, ldt, r, ctl, out->U, out->V, ws->used,
-                                    ws->aca_part, nprobe, probes);
+                                    ws->aca_part, nprobe, probes,
+                                    timing ? &ws->events[3 * it + 1] : nullptr);
     if (e != hipSuccess) return SLAR_E_HIP;
     if ((it % 4) == 3 || it == maxit - 1) {
       HIP_TRY(hipMemcpyAsync(hc, ctl, sizeof(AcaCtl), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      if (hc->phase == ACA_DONE) break;
+      if (timing && harvest(it + 1) != hipSuccess) return SLAR_E_HIP;
+      k_known = hc->k;
+      if (hc->phase == ACA_DONE) { ++it; break; }
     }
   }
   HIP_TRY(hipMemcpyAsync(hc, ctl, sizeof(AcaCtl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (timing && harvest(it) != hipSuccess) return SLAR_E_HIP;
   out->k = hc->k;
   if (info) {
     info->rank = hc->k;

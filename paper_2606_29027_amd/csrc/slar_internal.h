@@ -225,6 +225,12 @@ struct Workspace {
   // macro / Krylov
   double* kry = nullptr;
   size_t kry_elems = 0;
+  // optional in-stream event timing of the cross-approximation sampling
+  // kernels: [0] row ms, [1] row launches, [2] row bytes, [3] col ms,
+  // [4] col launches, [5] col bytes
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  double tstat[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // optional recording of (J z, z) pairs for training the preconditioner
   float* rec_feat = nullptr;
   float* rec_targ = nullptr;

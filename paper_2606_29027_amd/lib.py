@@ -24,7 +24,8 @@ EXPORTS = (
     "slar_moments", "slar_poisson", "slar_conserved", "slar_lomac_prepare", "slar_macro_solve",
     "slar_lomac_project", "slar_cnn_create", "slar_cnn_destroy", "slar_cnn_nparams",
     "slar_cnn_set_params", "slar_cnn_get_params", "slar_cnn_forward", "slar_cnn_grad",
-    "slar_cnn_train_step", "slar_record_krylov", "slar_recorded_pairs",
+    "slar_cnn_train_step", "slar_record_krylov", "slar_recorded_pairs", "slar_timing_enable",
+    "slar_timing_read",
 )
 
 
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH):
         "slar_cnn_train_step": (i32, [vp, i32, i32, i32, vp, vp, C.c_float, P(C.c_float), vp]),
         "slar_record_krylov": (i32, [vp, vp, vp, i32]),
         "slar_recorded_pairs": (i32, [vp]),
+        "slar_timing_enable": (i32, [vp, i32]),
+        "slar_timing_read": (i32, [vp, P(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -317,3 +320,14 @@ def slar_record_krylov(ws, feats, targs, capacity):
 
 def slar_recorded_pairs(ws) -> int:
     return int(load().slar_recorded_pairs(ws.h))
+
+
+def slar_timing_enable(ws, on: bool):
+    _check(load().slar_timing_enable(ws.h, 1 if on else 0), "slar_timing_enable")
+
+
+def slar_timing_read(ws):
+    out = (C.c_double * 8)()
+    _check(load().slar_timing_read(ws.h, out), "slar_timing_read")
+    keys = ("row_ms", "row_launches", "row_bytes", "col_ms", "col_launches", "col_bytes")
+    return {k: out[i] for i, k in enumerate(keys)}

@@ -1,0 +1,104 @@
+"""C ABI checks that need no GPU: every function declared in include/*.h is
+exported by the built library, the ctypes mirrors of the public structs have
+the C layout, and argument validation rejects bad input before touching the
+device."""
+import ctypes as C
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slar.h")
+LIB = os.path.join(ROOT, "paper_2606_29027_amd", "libslar.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w ]*\*?\s+\*?(slar_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+@needs_lib
+def test_every_declared_symbol_is_exported():
+    lib = C.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@needs_lib
+def test_binding_covers_header():
+    from paper_2606_29027_amd import lib as L
+    assert set(declared_functions()) <= set(L.EXPORTS)
+
+
+@needs_lib
+def test_status_strings_and_invalid_arguments_without_gpu():
+    from paper_2606_29027_amd import lib as L
+    lib = L.load()
+    assert L.status_str(0) == "ok" and "rank" in L.status_str(3)
+    g = L.Grid()
+    g.dx, g.dv = 2, 1                           # dx != dv: rejected before any HIP call
+    h = C.c_void_p()
+    assert lib.slar_workspace_create(C.byref(g), 40, C.byref(h)) == L.SLAR_E_INVAL
+    g.dx, g.dv = 1, 1
+    g.n[0], g.n[1] = 2, 64                      # too few cells
+    g.hi[0], g.hi[1] = 1.0, 1.0
+    assert lib.slar_workspace_create(C.byref(g), 40, C.byref(h)) == L.SLAR_E_INVAL
+    assert lib.slar_cnn_create(0, None, 1, 1, C.byref(h)) == L.SLAR_E_INVAL
+    assert lib.slar_truncate(None, None, 1e-6, 10, None, None, None) == L.SLAR_E_INVAL
+
+
+LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "slar.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("slar_grid %zu\n", sizeof(slar_grid));
+  P(slar_grid, n) P(slar_grid, lo) P(slar_grid, hi)
+  printf("slar_ht %zu\n", sizeof(slar_ht));
+  P(slar_ht, rank) P(slar_ht, dtype) P(slar_ht, leaf) P(slar_ht, B12) P(slar_ht, root)
+  printf("slar_frames %zu\n", sizeof(slar_frames));
+  P(slar_frames, X) P(slar_frames, P)
+  printf("slar_adv %zu\n", sizeof(slar_adv));
+  P(slar_adv, tau) P(slar_adv, cv) P(slar_adv, E) P(slar_adv, cE)
+  printf("slar_lowrank %zu\n", sizeof(slar_lowrank));
+  P(slar_lowrank, U) P(slar_lowrank, V)
+  printf("slar_cross_info %zu\n", sizeof(slar_cross_info));
+  P(slar_cross_info, samples)
+  return 0;
+}
+"""
+
+
+def test_ctypes_struct_layout_matches_header(tmp_path):
+    gcc = shutil.which("gcc")
+    inc = "/opt/rocm/include"
+    if gcc is None or not os.path.isdir(inc):
+        pytest.skip("no C compiler or HIP headers")
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    r = subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", inc,
+                        str(src), "-o", str(exe)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("header does not compile as C here: " + r.stderr[-300:])
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split("\n") if l)
+    from paper_2606_29027_amd import lib as L
+    mirror = {"slar_grid": L.Grid, "slar_ht": L.HT, "slar_frames": L.Frames, "slar_adv": L.Adv,
+              "slar_lowrank": L.LowRank, "slar_cross_info": L.CrossInfo}
+    for key, val in out.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(mirror[t], f).offset == int(val), key
+        else:
+            assert C.sizeof(mirror[key]) == int(val), key
