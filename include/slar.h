@@ -277,6 +277,80 @@ int32_t slar_recorded_pairs(const slar_workspace* ws);
 slar_status slar_timing_enable(slar_workspace* ws, int32_t on);
 slar_status slar_timing_read(const slar_workspace* ws, double* out);
 
+/* ------------------------------------------------------------------------
+ * Many independent instances of uneven grid size and rank (each a separate
+ * Vlasov--Poisson problem advanced by the same SLAR sub-flows, section 3.1).
+ * A batch owns one workspace per instance, the device tables of the
+ * persistent multi-instance cross approximation, a captured hipGraph of its
+ * iteration chunk, and a pool of host threads with one stream each for the
+ * per-instance work that contains host decisions (truncation ranks).
+ * Array arguments below are host arrays of `count` entries, in instance
+ * order; the device buffers they point to belong to the caller.  A batch is
+ * used from one host thread and one caller stream at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct slar_batch slar_batch;
+
+/* grids[count]: the instances' grids (each validated as for
+ * slar_workspace_create); rmax bounds every rank.  Allocates device memory
+ * for count workspaces; synchronises the device.                            */
+slar_status slar_batch_create(int32_t count, const slar_grid* grids, int32_t rmax,
+                              slar_batch** out);
+slar_status slar_batch_destroy(slar_batch* b);
+
+/* The workspace of instance q (owned by the batch; NULL if q is out of
+ * range), for the one-instance calls (set-up, moments, diagnostics).        */
+slar_workspace* slar_batch_workspace(slar_batch* b, int32_t q);
+
+/* slar_cross_update for every instance at once, FP32 tables, 3-point
+ * stencils (order 3 only).  Per instance: src[q], adv[q], probes[q]
+ * (device int32 [nprobe][2], may be NULL when nprobe == 0), out[q] (U/V
+ * device buffers, k written), info[q] (may be NULL as a whole).  tol, kmax,
+ * nprobe are shared.  The pivoting and stopping rules, and with team width
+ * 16 every sampled value, are those of slar_cross_update with SLAR_F32.
+ * Returns the most severe per-instance status (SLAR_E_RANK_CAP if any
+ * instance hit kmax).  Synchronises the stream.                             */
+slar_status slar_batch_cross_update(slar_batch* b, const slar_frames* src, const slar_adv* adv,
+                                    double tol, int32_t kmax, int32_t nprobe,
+                                    const int32_t* const* probes, slar_lowrank* out,
+                                    slar_cross_info* info, hipStream_t stream);
+
+/* slar_truncate for every instance (host thread pool, one stream per
+ * thread, ordered after the work already on `stream`), followed, when
+ * frames != NULL, by slar_frames_from_ht into frames[q] (ld >= rmax).
+ * status (host int32[count], may be NULL) receives per-instance statuses;
+ * the return value is the most severe of them.                              */
+slar_status slar_batch_truncate(slar_batch* b, const slar_lowrank* in, double tol, int32_t rmax,
+                                slar_ht* out, slar_frames* frames, int32_t* status,
+                                hipStream_t stream);
+
+/* Per instance: moments M[q] ([nmom][Nx], as slar_moments) of F[q] and the
+ * spectral Poisson field E[q] ([dx][Nx]) with ion density n_i[q] (host).
+ * Enqueued by the pool; `stream` waits for the result.                      */
+slar_status slar_batch_efield(slar_batch* b, const slar_frames* F, const double* n_i,
+                              double* const* M, double* const* E, hipStream_t stream);
+
+/* Launch configuration of the batched cross approximation (host int32[8]):
+ * {persistent grid blocks, 64-sample tiles per work item, iterations per
+ * captured graph chunk, gather team width for source rank <= 16, <= 32,
+ * > 32, graph captures so far (read only), 0}.  Team widths are 4, 8 or 16
+ * lanes per sample; a width other than 16 changes FP32 rounding order only. */
+slar_status slar_batch_get_config(const slar_batch* b, int32_t* cfg);
+slar_status slar_batch_set_config(slar_batch* b, const int32_t* cfg);
+
+/* Autotuner: times reps full batched cross approximations of the given
+ * inputs per candidate, coordinate-wise over grid size {256..4096}, tiles
+ * per item {1,2,4}, team width per occupied rank bucket {4,8,16} and chunk
+ * {4,8,16}, and keeps the fastest configuration.  out is overwritten.      */
+slar_status slar_batch_tune(slar_batch* b, const slar_frames* src, const slar_adv* adv, double tol,
+                            int32_t kmax, int32_t nprobe, const int32_t* const* probes,
+                            slar_lowrank* out, int32_t reps, hipStream_t stream);
+
+/* Accumulated batched cross time: host double[4] = {device ms from the
+ * first preparation launch to the end of the last graph chunk, graph chunks
+ * launched, sum over calls of the largest instance iteration count, calls}. */
+slar_status slar_batch_timing(const slar_batch* b, double* out);
+slar_status slar_batch_timing_reset(slar_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

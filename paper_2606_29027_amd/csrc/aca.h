@@ -1,0 +1,446 @@
+// Device side of the adaptive cross approximation: control block, the
+// per-instance argument record and the three per-iteration bodies (row
+// fiber, column fiber, bookkeeping).  The bodies take one instance record
+// and one 64-sample tile index, so the same code serves one launch per
+// instance and the persistent multi-instance launches.
+#pragma once
+#include <cmath>
+
+#include "slar_internal.h"
+#include "frame_sampler.h"
+
+namespace slar {
+
+enum { ACA_RUN = 0, ACA_PROBE = 1, ACA_DONE = 2 };
+
+struct AcaCtl {
+  int phase, k, i, j;
+  int iters, probe_rounds, converged, capped;
+  unsigned cnt_row, cnt_col;
+  int kmax, pad;
+  double pivot, norm2, tol;
+  long long samples;
+  double gv[SLAR_KMAX + 1];
+  double gu[SLAR_KMAX + 1];
+};
+
+constexpr int ACA_MAXBLK = 1024;   // partial slots
+
+// Everything one cross approximation reads or writes (one instance).
+struct AcaInst {
+  GridDev g;
+  AdvDev a;
+  const void* X;
+  const void* P;
+  int ld, r;
+  AcaCtl* ctl;
+  double* U;
+  double* V;
+  unsigned char* used;
+  double* part;
+  int nbrow, nbcol, nprobe;
+  int team;            // lanes per sample in the fiber gathers (4, 8 or 16)
+  const int* probes;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block max of |v| over 256 threads -> returns in all threads
+__device__ double block_max(double v, double* red) {
+  const int t = threadIdx.x;
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return m;
+}
+
+// Lowest index in [0, n) with |x[idx]| >= thr among entries with mask==0
+// (mask may be null).  One block; every thread scans its strided share in
+// full (independent loads, no early exit) and the block takes the minimum.
+__device__ int block_first_at_least(const double* x, int n, double thr, const unsigned char* mask,
+                                    int* redi) {
+  const int t = threadIdx.x;
+  int best = n;
+  for (int e = t; e < n; e += blockDim.x) {
+    const bool ok = fabs(x[e]) >= thr && !(mask && mask[e]);
+    if (ok && e < best) best = e;
+  }
+  for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+  if ((t & 63) == 0) redi[t >> 6] = best;
+  __syncthreads();
+  const int b = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+  __syncthreads();
+  return b;
+}
+
+// out[l] = sum_b part[(1 + l) * ACA_MAXBLK + b] for l in [0, cnt), fixed
+// summation order: four interleaved partial sums per l, then combined.
+__device__ void block_sum_parts(const double* part, int nb, int cnt, double* lds4, double* out) {
+  const int t = threadIdx.x;
+  const int g = t >> 6, l0 = t & 63;
+  for (int base = 0; base < cnt; base += 64) {
+    const int l = base + l0;
+    double acc = 0.0;
+    if (l < cnt)
+      for (int b = g; b < nb; b += 4) acc += part[(size_t)(1 + l) * ACA_MAXBLK + b];
+    lds4[g * 64 + l0] = acc;
+    __syncthreads();
+    if (g == 0 && l < cnt) out[l] = ((lds4[l0] + lds4[64 + l0]) + lds4[128 + l0]) + lds4[192 + l0];
+    __syncthreads();
+  }
+}
+
+__device__ double block_max_masked(const double* x, int n, const unsigned char* mask, double* red) {
+  double m = -1.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x)
+    if (!(mask && mask[e])) m = fmax(m, fabs(x[e]));
+  return block_max(m, red);
+}
+
+__device__ __forceinline__ void unravel_x(const GridDev& g, int I, int* gi) {
+  if (g.dx == 1) gi[0] = I; else { gi[0] = I / g.n[1]; gi[1] = I % g.n[1]; }
+}
+__device__ __forceinline__ void unravel_v(const GridDev& g, int J, int* gi) {
+  if (g.dv == 1) gi[1] = J; else { gi[2] = J / g.n[3]; gi[3] = J % g.n[3]; }
+}
+
+// Partial-sum layout (doubles): part[q * ACA_MAXBLK + b]
+//   row kernel: q = 0 block max|r|, q = 1 block candidate index,
+//               q = 2 + l  v_l . r  (l <= k)
+//   col kernel: same with base PCOL
+constexpr int PCOL = SLAR_KMAX + 4;
+
+// Per-block max of |x| (entries with skip() excluded) and the lowest index
+// in the block whose |x| is within the tie tolerance of that block max.
+template <typename Skip>
+__device__ void block_candidate(const double* xs, int ns, int base, Skip skip, double* red, int* redi,
+                                double* out_max, double* out_idx) {
+  const int t = threadIdx.x;
+  double v = -1.0;
+  if (t < ns && !skip(base + t)) v = fabs(xs[t]);
+  const double m = block_max(v, red);
+  int cand = 1 << 30;
+  if (t < ns && !skip(base + t) && m >= 0.0 && fabs(xs[t]) >= m * (1.0 - 1e-10)) cand = base + t;
+  for (int o = 32; o > 0; o >>= 1) cand = min(cand, __shfl_xor(cand, o, 64));
+  if ((t & 63) == 0) redi[t >> 6] = cand;
+  __syncthreads();
+  if (t == 0) {
+    *out_max = m;
+    *out_idx = (double)min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+  }
+  __syncthreads();
+}
+
+// Global pivot from per-block candidates: lowest index whose |x| is within
+// the tie tolerance of the global maximum M (M < 0: nothing eligible).
+template <typename Skip>
+__device__ int pivot_from_parts(const double* x, const double* pmax, const double* pidx, int nb,
+                                int n, Skip skip, double* red, int* redi, double* M_out) {
+  const int t = threadIdx.x;
+  double m = -1.0;
+  for (int b = t; b < nb; b += blockDim.x) m = fmax(m, pmax[b]);
+  const double M = block_max(m, red);
+  *M_out = M;
+  if (!(M >= 0.0)) return n;
+  const double thr = M * (1.0 - 1e-10);
+  int bb = nb;
+  for (int b = t; b < nb; b += blockDim.x)
+    if (pmax[b] >= thr && b < bb) bb = b;
+  for (int o = 32; o > 0; o >>= 1) bb = min(bb, __shfl_xor(bb, o, 64));
+  if ((t & 63) == 0) redi[t >> 6] = bb;
+  __syncthreads();
+  bb = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+  __syncthreads();
+  if (bb >= nb) return n;
+  const int cand = (int)pidx[bb];
+  if (cand < n && fabs(x[cand]) >= thr) return cand;
+  // the block maximum is close to M but below it: rescan that block's range
+  int best = n;
+  const int e = bb * FS_SAMPLES + t;
+  if (t < FS_SAMPLES && e < n && !skip(e) && fabs(x[e]) >= thr) best = e;
+  for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+  if ((t & 63) == 0) redi[t >> 6] = best;
+  __syncthreads();
+  best = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+  __syncthreads();
+  return best;
+}
+
+struct NoSkip {
+  __device__ bool operator()(int) const { return false; }
+};
+struct SkipUsed {
+  const unsigned char* used;
+  int also;
+  __device__ bool operator()(int e) const { return used[e] != 0 || e == also; }
+};
+
+template <typename T, int W, int DX>
+__device__ void aca_row_body(const AcaInst& I, int tile) {
+  const GridDev& g = I.g;
+  const AdvDev& a = I.a;
+  const T* __restrict__ X = (const T*)I.X;
+  const T* __restrict__ P = (const T*)I.P;
+  const int ld = I.ld, r = I.r;
+  AcaCtl* ctl = I.ctl;
+  double* __restrict__ U = I.U;
+  double* __restrict__ V = I.V;
+  double* __restrict__ part = I.part;
+  __shared__ FsLds<W, DX> L;
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  __shared__ int s_phase, s_i, s_k;
+  __shared__ double acc4[4][FS_SAMPLES];
+  __shared__ double rres[FS_SAMPLES];
+  const int t = threadIdx.x;
+  if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; }
+  __syncthreads();
+  if (s_phase != ACA_RUN) return;
+  const int i = s_i, k = s_k;
+  const int Nx = g.nx, Nv = g.nv;
+  const int J0 = tile * FS_SAMPLES;
+  const int ns = min(FS_SAMPLES, Nv - J0);
+  if (t < ns) {
+    int gi[4];
+    unravel_x(g, i, gi);
+    unravel_v(g, J0 + t, gi);
+    fs_prepare<W, DX>(g, a, gi, L, t);
+  }
+  __syncthreads();
+  fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
+  __syncthreads();
+  // residual r_J = A[i, J] - sum_l u_l[i] v_l[J]: the l-sum is split over
+  // the four waves (wave w takes l = w, w + 4, ...) and combined in LDS
+  const int wv = t >> 6, ln = t & 63;
+  {
+    double acc = 0.0;
+    if (ln < ns)
+      for (int l = wv; l < k; l += 4) acc += U[(size_t)l * Nx + i] * V[(size_t)l * Nv + J0 + ln];
+    acc4[wv][ln] = acc;
+  }
+  __syncthreads();
+  if (t < 64) {
+    double rv = 0.0;
+    if (t < ns) {
+      rv = L.val[t] - (((acc4[0][t] + acc4[1][t]) + acc4[2][t]) + acc4[3][t]);
+      V[(size_t)k * Nv + J0 + t] = rv;
+    }
+    rres[t] = rv;
+  }
+  __syncthreads();
+  for (int l = wv; l <= k; l += 4) {
+    const double r_ = rres[ln];
+    double p = 0.0;
+    if (ln < ns) p = (l < k ? V[(size_t)l * Nv + J0 + ln] : r_) * r_;
+    p = wave_sum(p);
+    if (ln == 0) part[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+  }
+  block_candidate(rres, ns, J0, NoSkip{}, red, redi, &part[tile], &part[ACA_MAXBLK + tile]);
+}
+
+template <typename T, int W, int DX>
+__device__ void aca_col_body(const AcaInst& I, int tile) {
+  const GridDev& g = I.g;
+  const AdvDev& a = I.a;
+  const T* __restrict__ X = (const T*)I.X;
+  const T* __restrict__ P = (const T*)I.P;
+  const int ld = I.ld, r = I.r;
+  AcaCtl* ctl = I.ctl;
+  double* __restrict__ U = I.U;
+  const double* __restrict__ V = I.V;
+  const unsigned char* __restrict__ used = I.used;
+  double* __restrict__ part = I.part;
+  const int nbrow = I.nbrow;
+  __shared__ FsLds<W, DX> L;
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  __shared__ int s_phase, s_i, s_k;
+  __shared__ double s_norm2, s_tol;
+  __shared__ double acc4[4][FS_SAMPLES];
+  __shared__ double ures[FS_SAMPLES];
+  const int t = threadIdx.x;
+  if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; s_norm2 = ctl->norm2; s_tol = ctl->tol; }
+  __syncthreads();
+  if (s_phase != ACA_RUN) return;
+  const int i = s_i, k = s_k;
+  const int Nx = g.nx, Nv = g.nv;
+  // column pivot of the row residual (every block computes the same)
+  double M;
+  const double* vk = V + (size_t)k * Nv;
+  const int j = pivot_from_parts(vk, part, part + ACA_MAXBLK, nbrow, Nv, NoSkip{}, red, redi, &M);
+  const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
+  if (M == 0.0 || M <= thr || j >= Nv) return;   // row already reproduced
+  const double piv = vk[j];
+  const int I0 = tile * FS_SAMPLES;
+  const int ns = min(FS_SAMPLES, Nx - I0);
+  if (t < ns) {
+    int gi[4];
+    unravel_x(g, I0 + t, gi);
+    unravel_v(g, j, gi);
+    fs_prepare<W, DX>(g, a, gi, L, t);
+  }
+  __syncthreads();
+  fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
+  __syncthreads();
+  const int wv = t >> 6, ln = t & 63;
+  {
+    double acc = 0.0;
+    if (ln < ns)
+      for (int l = wv; l < k; l += 4) acc += V[(size_t)l * Nv + j] * U[(size_t)l * Nx + I0 + ln];
+    acc4[wv][ln] = acc;
+  }
+  __syncthreads();
+  if (t < 64) {
+    double u = 0.0;
+    if (t < ns) {
+      u = (L.val[t] - (((acc4[0][t] + acc4[1][t]) + acc4[2][t]) + acc4[3][t])) / piv;
+      U[(size_t)k * Nx + I0 + t] = u;
+    }
+    ures[t] = u;
+  }
+  __syncthreads();
+  double* pc = part + (size_t)PCOL * ACA_MAXBLK;
+  for (int l = wv; l <= k; l += 4) {
+    const double u_ = ures[ln];
+    double p = 0.0;
+    if (ln < ns) p = (l < k ? U[(size_t)l * Nx + I0 + ln] : u_) * u_;
+    p = wave_sum(p);
+    if (ln == 0) pc[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+  }
+  block_candidate(ures, ns, I0, SkipUsed{used, i}, red, redi, &pc[tile], &pc[ACA_MAXBLK + tile]);
+}
+
+// One block: bookkeeping of the iteration, stopping test, next row pivot,
+// and the random-probe check whenever the approximation wants to stop.
+template <typename T, int W, int DX>
+__device__ void aca_fin_body(const AcaInst& I) {
+  const GridDev& g = I.g;
+  const AdvDev& a = I.a;
+  const T* __restrict__ X = (const T*)I.X;
+  const T* __restrict__ P = (const T*)I.P;
+  const int ld = I.ld, r = I.r;
+  AcaCtl* ctl = I.ctl;
+  const double* __restrict__ U = I.U;
+  const double* __restrict__ V = I.V;
+  unsigned char* __restrict__ used = I.used;
+  double* __restrict__ part = I.part;
+  const int nbrow = I.nbrow, nbcol = I.nbcol, nprobe = I.nprobe;
+  const int* __restrict__ probes = I.probes;
+  __shared__ FsLds<W, DX> L;
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  __shared__ double lds4[256];
+  __shared__ double res[1024];
+  __shared__ int pi[1024];
+  __shared__ int s_phase, s_i, s_k, s_stop;
+  const int t = threadIdx.x;
+  if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; }
+  __syncthreads();
+  if (s_phase != ACA_RUN) return;
+  const int i = s_i;
+  int k = s_k;
+  const int Nx = g.nx, Nv = g.nv;
+  double M;
+  const double* vk = V + (size_t)k * Nv;
+  const int j = pivot_from_parts(vk, part, part + ACA_MAXBLK, nbrow, Nv, NoSkip{}, red, redi, &M);
+  const double thr = ctl->tol * sqrt(ctl->norm2) / sqrt((double)Nx * (double)Nv);
+  const bool zero_row = (M == 0.0 || M <= thr || j >= Nv);
+  if (t == 0) {
+    used[i] = 1;
+    ctl->iters += 1;
+    ctl->samples += Nv;
+  }
+  if (!zero_row) {
+    double* pc = part + (size_t)PCOL * ACA_MAXBLK;
+    block_sum_parts(part + ACA_MAXBLK, nbrow, k + 1, lds4, ctl->gv);
+    block_sum_parts(pc + ACA_MAXBLK, nbcol, k + 1, lds4, ctl->gu);
+    __syncthreads();
+    if (t == 0) {
+      ctl->samples += Nx;
+      ctl->j = j;
+      ctl->pivot = vk[j];
+      double cross = 0.0;
+      for (int l = 0; l < k; ++l) cross += ctl->gu[l] * ctl->gv[l];
+      const double nk = ctl->gu[k] * ctl->gv[k];
+      ctl->norm2 = ctl->norm2 + 2.0 * cross + nk;
+      ctl->k = k + 1;
+      s_stop = 0;
+      if (sqrt(nk) <= ctl->tol * sqrt(fmax(ctl->norm2, 0.0))) s_stop = 1;            // probe
+      else if (k + 1 >= ctl->kmax) { ctl->phase = ACA_DONE; ctl->capped = 1; s_stop = 2; }
+    }
+    __syncthreads();
+    k = k + 1;
+    if (s_stop == 2) return;
+    if (s_stop == 0) {
+      // next row pivot: unused row maximising |u_k| (block candidates)
+      const double* uk = U + (size_t)(k - 1) * Nx;
+      double Mu;
+      const int ip = pivot_from_parts(uk, pc, pc + ACA_MAXBLK, nbcol, Nx, SkipUsed{used, i}, red, redi, &Mu);
+      if (t == 0) {
+        if (!(Mu >= 0.0) || ip >= Nx) ctl->phase = ACA_DONE;
+        else ctl->i = ip;
+      }
+      return;
+    }
+  }
+  // ---- probe check (the approximation wants to stop)
+  if (k == 0 || nprobe <= 0) {
+    if (t == 0) { ctl->phase = ACA_DONE; ctl->converged = 1; }
+    return;
+  }
+  const double thr2 = ctl->tol * sqrt(fmax(ctl->norm2, 0.0)) / sqrt((double)Nx * (double)Nv);
+  for (int base = 0; base < nprobe; base += FS_SAMPLES) {
+    const int ns = min(FS_SAMPLES, nprobe - base);
+    if (t < ns) {
+      int gi[4];
+      unravel_x(g, probes[2 * (base + t)], gi);
+      unravel_v(g, probes[2 * (base + t) + 1], gi);
+      fs_prepare<W, DX>(g, a, gi, L, t);
+    }
+    __syncthreads();
+    fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
+    __syncthreads();
+    if (t < ns) {
+      const int I = probes[2 * (base + t)], J = probes[2 * (base + t) + 1];
+      double v = L.val[t];
+      for (int l = 0; l < k; ++l) v -= U[(size_t)l * Nx + I] * V[(size_t)l * Nv + J];
+      const bool bad = fabs(v) > thr2 && !used[I];
+      res[base + t] = bad ? fabs(v) : -1.0;
+      pi[base + t] = I;
+    }
+    __syncthreads();
+  }
+  double m = -1.0;
+  for (int e = t; e < nprobe; e += blockDim.x) m = fmax(m, res[e]);
+  m = block_max(m, red);
+  int best = nprobe;
+  if (m > 0.0) {
+    for (int e = t; e < nprobe; e += blockDim.x)
+      if (res[e] > 0.0 && res[e] >= m * (1.0 - 1e-10) && e < best) best = e;
+    for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+    if ((t & 63) == 0) redi[t >> 6] = best;
+    __syncthreads();
+    best = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+  }
+  if (t == 0) {
+    ctl->samples += nprobe;
+    if (m <= 0.0 || best >= nprobe) {
+      ctl->phase = ACA_DONE;
+      ctl->converged = 1;
+    } else if (k >= ctl->kmax) {
+      ctl->phase = ACA_DONE;
+      ctl->capped = 1;
+    } else {
+      ctl->probe_rounds += 1;
+      ctl->i = pi[best];
+    }
+  }
+}
+
+
+}  // namespace slar

@@ -6,9 +6,10 @@
 // i.e. a stencil-weighted gather of w^dx rows of X and w^dv rows of P
 // followed by one length-r dot product.  One block of 256 threads evaluates
 // 64 samples per round: 64 threads trace the feet (FP64) and write stencil
-// rows/weights to LDS, then 16-lane teams (4 columns per lane, float4 or
-// 2 x double2 loads) gather the rows and reduce the dot product with
-// cross-lane shuffles.
+// rows/weights to LDS, then teams of TEAM lanes (4 columns per lane per
+// pass, float4 or 2 x double2 loads) gather the rows and reduce the dot
+// product with cross-lane shuffles.  The team width trades idle lanes at
+// small rank (r < 4 TEAM) against samples per team; 16 is the default.
 #pragma once
 #include "slar_internal.h"
 
@@ -73,15 +74,16 @@ template <> struct Vec4<double> {
 
 // Phase 2: values of the prepared samples [0, ns) into L.val (FP64).
 // Tables are [rows][ld] with ld % 4 == 0 and zero columns beyond r.
-template <typename T, int W, int DX>
+template <typename T, int W, int DX, int TEAM = 16>
 __device__ __forceinline__ void fs_evaluate(const T* __restrict__ X, const T* __restrict__ P,
                                             int ld, int r, FsLds<W, DX>& L, int ns) {
+  static_assert(TEAM == 4 || TEAM == 8 || TEAM == 16, "team width");
   constexpr int RX = FsLds<W, DX>::RX;
-  const int team = threadIdx.x / 16;     // 16 teams
-  const int lane = threadIdx.x % 16;
-  for (int s = team; s < ns; s += FS_THREADS / 16) {
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  for (int s = team; s < ns; s += FS_THREADS / TEAM) {
     T acc = 0;
-    for (int c0 = lane * 4; c0 < r; c0 += 64) {
+    for (int c0 = lane * 4; c0 < r; c0 += 4 * TEAM) {
       T y[4] = {0, 0, 0, 0}, z[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int b = 0; b < RX; ++b) {
@@ -99,9 +101,19 @@ __device__ __forceinline__ void fs_evaluate(const T* __restrict__ X, const T* __
       for (int e = 0; e < 4; ++e) acc += y[e] * z[e];
     }
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    for (int o = TEAM / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, TEAM);
     if (lane == 0) L.val[s] = (double)acc;
   }
+}
+
+// Runtime choice of the team width (uniform across the block).
+template <typename T, int W, int DX>
+__device__ __forceinline__ void fs_evaluate_team(int team, const T* __restrict__ X,
+                                                 const T* __restrict__ P, int ld, int r,
+                                                 FsLds<W, DX>& L, int ns) {
+  if (team == 4) fs_evaluate<T, W, DX, 4>(X, P, ld, r, L, ns);
+  else if (team == 8) fs_evaluate<T, W, DX, 8>(X, P, ld, r, L, ns);
+  else fs_evaluate<T, W, DX, 16>(X, P, ld, r, L, ns);
 }
 
 }  // namespace slar

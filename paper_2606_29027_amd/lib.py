@@ -25,7 +25,9 @@ EXPORTS = (
     "slar_lomac_project", "slar_cnn_create", "slar_cnn_destroy", "slar_cnn_nparams",
     "slar_cnn_set_params", "slar_cnn_get_params", "slar_cnn_forward", "slar_cnn_grad",
     "slar_cnn_train_step", "slar_record_krylov", "slar_recorded_pairs", "slar_timing_enable",
-    "slar_timing_read",
+    "slar_timing_read", "slar_batch_create", "slar_batch_destroy", "slar_batch_workspace",
+    "slar_batch_cross_update", "slar_batch_truncate", "slar_batch_efield", "slar_batch_get_config",
+    "slar_batch_set_config", "slar_batch_tune", "slar_batch_timing", "slar_batch_timing_reset",
 )
 
 
@@ -105,6 +107,18 @@ def load(path: str = LIB_PATH):
         "slar_recorded_pairs": (i32, [vp]),
         "slar_timing_enable": (i32, [vp, i32]),
         "slar_timing_read": (i32, [vp, P(C.c_double)]),
+        "slar_batch_create": (i32, [i32, P(Grid), i32, P(vp)]),
+        "slar_batch_destroy": (i32, [vp]),
+        "slar_batch_workspace": (vp, [vp, i32]),
+        "slar_batch_cross_update": (i32, [vp, P(Frames), P(Adv), dbl, i32, i32, P(vp), P(LowRank),
+                                          P(CrossInfo), vp]),
+        "slar_batch_truncate": (i32, [vp, P(LowRank), dbl, i32, P(HT), P(Frames), P(i32), vp]),
+        "slar_batch_efield": (i32, [vp, P(Frames), P(dbl), P(vp), P(vp), vp]),
+        "slar_batch_get_config": (i32, [vp, P(i32)]),
+        "slar_batch_set_config": (i32, [vp, P(i32)]),
+        "slar_batch_tune": (i32, [vp, P(Frames), P(Adv), dbl, i32, i32, P(vp), P(LowRank), i32, vp]),
+        "slar_batch_timing": (i32, [vp, P(C.c_double)]),
+        "slar_batch_timing_reset": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -331,3 +345,106 @@ def slar_timing_read(ws):
     _check(load().slar_timing_read(ws.h, out), "slar_timing_read")
     keys = ("row_ms", "row_launches", "row_bytes", "col_ms", "col_launches", "col_bytes")
     return {k: out[i] for i, k in enumerate(keys)}
+
+
+# ------------------------------------------------------------------ batches
+def _array(T, items):
+    arr = (T * len(items))(*items)
+    arr._keep = [getattr(x, "_keep", None) for x in items]
+    return arr
+
+
+def _ptrs(tensors):
+    arr = (C.c_void_p * len(tensors))(*[None if t is None else t.data_ptr() for t in tensors])
+    arr._keep = list(tensors)
+    return arr
+
+
+class Batch:
+    """Handle of a multi-instance batch (slar_batch_*)."""
+
+    def __init__(self, grids, rmax: int):
+        self.grids = list(grids)
+        self.count = len(self.grids)
+        h = C.c_void_p()
+        arr = (Grid * self.count)(*self.grids)
+        _check(load().slar_batch_create(self.count, arr, int(rmax), C.byref(h)), "slar_batch_create")
+        self.h = h
+        # views of the per-instance workspaces (owned by the batch)
+        self.ws = [_BorrowedWorkspace(g, load().slar_batch_workspace(h, q)) for q, g in enumerate(self.grids)]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.slar_batch_destroy(self.h)
+            self.h = None
+
+    def cross_update(self, src, advs, tol, kmax, probes, U, V):
+        lrs = [LowRank(0, u.data_ptr(), v.data_ptr()) for u, v in zip(U, V)]
+        out = _array(LowRank, lrs)
+        info = (CrossInfo * self.count)()
+        nprobe = 0 if probes is None else int(probes[0].shape[0])
+        pp = None if probes is None else _ptrs(probes)
+        st = load().slar_batch_cross_update(self.h, _array(Frames, src), _array(Adv, advs), float(tol),
+                                            int(kmax), nprobe, pp, out, info, _stream())
+        _check(st, "slar_batch_cross_update", ok=(SLAR_OK, SLAR_E_RANK_CAP))
+        res = []
+        for q in range(self.count):
+            lr = LowRank(out[q].k, out[q].U, out[q].V)
+            lr._keep = (U[q], V[q])
+            res.append(lr)
+        return res, list(info), st
+
+    def truncate(self, lrs, tol, rmax, hts, frames_out=None):
+        status = (C.c_int32 * self.count)()
+        hts_arr = _array(HT, hts)
+        fr = None if frames_out is None else _array(Frames, frames_out)
+        st = load().slar_batch_truncate(self.h, _array(LowRank, lrs), float(tol), int(rmax), hts_arr, fr,
+                                        status, _stream())
+        _check(st, "slar_batch_truncate", ok=(SLAR_OK, SLAR_E_RANK_CAP))
+        for q in range(self.count):             # ranks written by the library
+            hts[q].rank[:] = hts_arr[q].rank[:]
+            if frames_out is not None:
+                frames_out[q].r = fr[q].r
+        return list(status)
+
+    def efield(self, F, n_i, M, E):
+        nis = (C.c_double * self.count)(*[float(x) for x in n_i])
+        _check(load().slar_batch_efield(self.h, _array(Frames, F), nis, _ptrs(M), _ptrs(E), _stream()),
+               "slar_batch_efield")
+
+    def config(self):
+        cfg = (C.c_int32 * 8)()
+        _check(load().slar_batch_get_config(self.h, cfg), "slar_batch_get_config")
+        keys = ("grid", "group", "chunk", "team_r16", "team_r32", "team_rmax", "captures")
+        return {k: int(cfg[i]) for i, k in enumerate(keys)}
+
+    def set_config(self, grid, group, chunk, teams=(16, 16, 16)):
+        cfg = (C.c_int32 * 8)(int(grid), int(group), int(chunk), *[int(t) for t in teams], 0, 0)
+        _check(load().slar_batch_set_config(self.h, cfg), "slar_batch_set_config")
+
+    def tune(self, src, advs, tol, kmax, probes, U, V, reps=2):
+        lrs = [LowRank(0, u.data_ptr(), v.data_ptr()) for u, v in zip(U, V)]
+        nprobe = 0 if probes is None else int(probes[0].shape[0])
+        pp = None if probes is None else _ptrs(probes)
+        _check(load().slar_batch_tune(self.h, _array(Frames, src), _array(Adv, advs), float(tol), int(kmax),
+                                      nprobe, pp, _array(LowRank, lrs), int(reps), _stream()),
+               "slar_batch_tune")
+        return self.config()
+
+    def timing(self):
+        out = (C.c_double * 4)()
+        _check(load().slar_batch_timing(self.h, out), "slar_batch_timing")
+        return {"cross_ms": out[0], "chunks": out[1], "iterations": out[2], "calls": out[3]}
+
+    def timing_reset(self):
+        _check(load().slar_batch_timing_reset(self.h), "slar_batch_timing_reset")
+
+
+class _BorrowedWorkspace:
+    """A workspace owned by a batch (usable with the one-instance calls)."""
+
+    def __init__(self, grid, handle):
+        if not handle:
+            raise RuntimeError("slar_batch_workspace returned NULL")
+        self.grid = grid
+        self.h = C.c_void_p(handle)

@@ -204,17 +204,23 @@ def random_field(shape: Sequence[int], seed: int, smooth: bool = True) -> np.nda
     return out
 
 
-def batched_instances(count: int = 64) -> List[Problem]:
+def batched_instances(count: int = 64, sizes: Sequence[int] = (32, 48, 64, 96, 128),
+                      sizes_1d: Optional[Sequence[int]] = None) -> List[Problem]:
     """Independent Landau instances of uneven size (per-instance seed i):
     1D1V or 2D2V with probability 1/2, N per dimension from
     {32, 48, 64, 96, 128}, alpha ~ U[0.005, 0.5], k ~ U[0.3, 0.6],
-    x in [0, 2 pi / k) so the perturbation is periodic, v in [-6, 6]."""
+    x in [0, 2 pi / k) so the perturbation is periodic, v in [-6, 6].
+    ``sizes`` / ``sizes_1d`` replace the size menu of the 2D2V / 1D1V
+    instances (small test cases) without changing the other draws."""
+    s2 = list(sizes)
+    s1 = list(sizes if sizes_1d is None else sizes_1d)
     out = []
     for i in range(count):
         rng = np.random.default_rng(i)
         two = bool(rng.integers(0, 2))
         dims = 4 if two else 2
-        ns = tuple(int(rng.choice([32, 48, 64, 96, 128])) for _ in range(dims))
+        menu = s2 if two else s1
+        ns = tuple(int(menu[rng.integers(0, len(menu))]) for _ in range(dims))
         alpha = float(rng.uniform(0.005, 0.5))
         k = float(rng.uniform(0.3, 0.6))
         L = 2.0 * math.pi / k

@@ -1,0 +1,111 @@
+"""Batched multi-instance path (slar_batch_*): the persistent multi-instance
+cross approximation replayed from a captured hipGraph against the
+one-instance library call, and whole batched steps against the CPU oracle.
+
+With the default team width (16 lanes per sample) a batched tile runs the
+same arithmetic as the one-instance kernels on the same FP32 tables, so U,
+V, ranks and iteration counts must agree bit for bit.  Several calls in a
+row (three sub-flows, with eager field solves between them) replay the
+captured graph; every replay is checked against the eager one-instance call.
+Against the FP64 oracle the FP32 tables allow 10 tol (normwise) per step,
+the bound the one-instance FP32 step tests use."""
+import numpy as np
+import pytest
+
+import slar_inputs as SI
+from oracle import ht as HT
+from oracle import step as ST
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2606_29027_amd import lib as L  # noqa: E402
+from paper_2606_29027_amd.batch import BatchSolver  # noqa: E402
+from gpu_util import normwise  # noqa: E402
+
+
+def _probes(p, seed):
+    Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
+    return SI.probe_indices(Nx, Nv, 64, seed)
+
+
+def _solver(problems):
+    pr = [_probes(p, 100 + q) for q, p in enumerate(problems)]
+    b = BatchSolver(problems, probes=pr)
+    b.set_initial([SI.initial_ht(p) for p in problems])
+    return b, pr
+
+
+def _single_cross(b, q, src, adv):
+    I = b.inst[q]
+    ws = b.batch.ws[q]
+    U = torch.zeros_like(I.U); V = torch.zeros_like(I.V)
+    lr, info, _ = L.slar_cross_update(ws.grid, src, adv, L.F32, b.tol, b.rmax, b.probes[q], U, V, ws)
+    torch.cuda.synchronize()
+    return U, V, info
+
+
+def test_batch_cross_bitwise_equals_single_instance_over_replays():
+    problems = SI.batched_instances(10)
+    b, _ = _solver(problems)
+    assert b.batch.config()["team_r16"] == 16
+    h = b.dt
+    E1 = b.efield(b.state, 0)
+    stages = [(b.state, [L.make_adv(2, h / 3.0, 1.0, E) for E in E1]),
+              (b.state, [L.make_adv(2, 2.0 * h / 3.0, 1.0, E) for E in E1]),
+              (b.state, [L.make_adv(2, h, 2.0 / 3.0, E, E, (-1.0 / 12.0, 3.0 / 4.0)) for E in E1])]
+    for src, advs in stages:
+        lrs, info, _ = b.batch.cross_update(src, advs, b.tol, b.rmax, b.probes,
+                                            [I.U for I in b.inst], [I.V for I in b.inst])
+        torch.cuda.synchronize()
+        got = [(I.U.clone(), I.V.clone()) for I in b.inst]
+        b.efield(src, 1)                    # eager work between graph replays
+        for q in range(b.count):
+            U, V, inf = _single_cross(b, q, src[q], advs[q])
+            k = inf.rank
+            assert info[q].rank == k and info[q].iterations == inf.iterations, q
+            assert info[q].samples == inf.samples and info[q].probe_rounds == inf.probe_rounds, q
+            assert torch.equal(got[q][0][:k], U[:k]) and torch.equal(got[q][1][:k], V[:k]), q
+    assert b.batch.config()["captures"] == 1
+
+
+def test_batch_step_matches_oracle():
+    problems = SI.batched_instances(6, sizes=(8, 12), sizes_1d=(24, 32))
+    b, pr = _solver(problems)
+    b.step()
+    for q, p in enumerate(problems):
+        o = ST.Oracle(p, probes=pr[q])
+        F0 = SI.initial_ht(p)
+        o.efield(F0)
+        Fo = o.slar_vp(F0, p.dt)
+        err = normwise(b.dense(q), HT.full(Fo))
+        assert err < 10 * p.tol, (q, p.n, err)
+
+
+def test_tuned_configuration_keeps_the_answer():
+    problems = SI.batched_instances(8, sizes=(8, 12, 16), sizes_1d=(32, 48, 64))
+    b0, _ = _solver(problems)
+    b0.step()
+    ref = [b0.dense(q) for q in range(b0.count)]
+    b1, _ = _solver(problems)
+    cfg = b1.tune(reps=1)
+    assert cfg["grid"] in (256, 512, 1024, 2048, 4096) and cfg["group"] in (1, 2, 4)
+    assert cfg["chunk"] in (4, 8, 16)
+    b1.step()
+    for q, p in enumerate(problems):
+        assert normwise(b1.dense(q), ref[q]) < 10 * p.tol, q
+
+
+def test_batch_rejects_bad_arguments():
+    p = SI.batched_instances(2)
+    b, _ = _solver(p)
+    bad = [L.make_adv(2, 0.1, 1.0, b.inst[q].E[0], order=5) for q in range(2)]
+    with pytest.raises(L.SlarError) as e:
+        b.batch.cross_update(b.state, bad, b.tol, b.rmax, b.probes,
+                             [I.U for I in b.inst], [I.V for I in b.inst])
+    assert e.value.status == L.SLAR_E_INVAL
+    with pytest.raises(L.SlarError):
+        b.batch.set_config(256, 1, 8, (4, 5, 16))
