@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--variants", default="plain,spectral,learned",
                     help="comma list of macro solvers to time: plain, spectral, learned "
                          "(the last one listed is the headline)")
+    ap.add_argument("--workload", choices=["stronglandau2d", "batched"], default="stronglandau2d",
+                    help="batched: 64 independent 1D1V/2D2V Landau instances of uneven size")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch configuration")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one device copy of this size (for counter calibration)")
     return ap.parse_args()
@@ -77,12 +81,85 @@ def cpu_baseline(p, budget_s: float):
                       f"{p.n[0]}^4 workload, FP64 NumPy"}
 
 
+def batched_main(args):
+    """64 independent Landau instances (1D1V or 2D2V, N per dimension from
+    {32, 48, 64, 96, 128}) advanced together: one SLAR_VP step of every
+    instance per step; value = sampled entries of all instances per second."""
+    import torch
+    import slar_inputs as SI
+    from paper_2606_29027_amd.batch import BatchSolver
+
+    problems = SI.batched_instances(args.instances)
+    probes = []
+    for q, p in enumerate(problems):
+        Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
+        probes.append(SI.probe_indices(Nx, Nv, 64, 1000 + q))
+    b = BatchSolver(problems, probes=probes)
+    b.set_initial([SI.initial_ht(p) for p in problems])
+    tuned = None
+    t_tune = time.perf_counter()
+    if not args.no_tune:
+        tuned = b.tune(reps=2)
+    t_tune = time.perf_counter() - t_tune
+    for _ in range(args.warmup):
+        b.step()
+    torch.cuda.synchronize()
+    n0 = len(b.stats)
+    b.batch.timing_reset()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tim = b.batch.timing()
+    samples = sum(st["samples"] for st in b.stats[n0:])
+    # algorithmic bytes of the batched cross approximations: per sampled
+    # entry both FP32 stencil gathers (3^dx rows of X, 3^dv rows of P, ldt
+    # columns), the 8-byte write and 16 k bytes of earlier cross vectors
+    # (k taken at half the final rank of the call)
+    by = 0.0
+    for st in b.stats[n0:]:
+        for q, p in enumerate(problems):
+            rx = 3 ** p.dx
+            r = st["src_ranks"][q]
+            ldt = (r + 3) & ~3
+            by += st["samples_q"][q] * (2.0 * rx * ldt * 4 + 8 + 16 * st["ranks"][q] / 2.0)
+    achieved = by / (tim["cross_ms"] * 1e-3) / 1e9 if tim["cross_ms"] > 0 else 0.0
+    n1 = sum(1 for p in problems if p.dx == 1)
+    out = {
+        "metric": "HT-SL sampled entries/s & time/step, batched independent instances",
+        "value": samples / elapsed,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(problems)} independent Landau instances ({n1} 1D1V, {len(problems) - n1} 2D2V), "
+                               "N per dim from {32,48,64,96,128}, tol 1e-6, rmax 40, dt 0.1, CF3, FP32 tables",
+                   "tuned": tuned, "tune_seconds": t_tune,
+                   "cross_ms_per_step": tim["cross_ms"] / args.steps,
+                   "graph_chunks_per_step": tim["chunks"] / args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "batched cross approximation (prep + row + col + fin launches, graph replays)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return batched_main(args)
     import torch
     import slar_inputs as SI
     from paper_2606_29027_amd import lib as L

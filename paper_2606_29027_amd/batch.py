@@ -133,6 +133,7 @@ class BatchSolver:
         outs = [I.frames(frame_slot) for I in self.inst]
         self.batch.truncate(lrs, self.tol, self.rmax, hts, outs)
         self.stats.append({"ranks": [x.rank for x in info], "samples": int(sum(x.samples for x in info)),
+                           "samples_q": [int(x.samples) for x in info], "src_ranks": [f.r for f in src],
                            "iters": max(x.iterations for x in info)})
         return outs, hts
 

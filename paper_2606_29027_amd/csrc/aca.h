@@ -20,8 +20,6 @@ struct AcaCtl {
   int kmax, pad;
   double pivot, norm2, tol;
   long long samples;
-  double gv[SLAR_KMAX + 1];
-  double gu[SLAR_KMAX + 1];
 };
 
 constexpr int ACA_MAXBLK = 1024;   // partial slots
@@ -59,54 +57,27 @@ __device__ double block_max(double v, double* red) {
   return m;
 }
 
-// Lowest index in [0, n) with |x[idx]| >= thr among entries with mask==0
-// (mask may be null).  One block; every thread scans its strided share in
-// full (independent loads, no early exit) and the block takes the minimum.
-__device__ int block_first_at_least(const double* x, int n, double thr, const unsigned char* mask,
-                                    int* redi) {
+// out[l] = sum_b part[(1 + l) * ACA_MAXBLK + b] for l in [0, cnt), one wave
+// per l (l = wave, wave + 4, ...), lanes over b (coalesced), fixed order.
+__device__ void block_sum_parts(const double* part, int nb, int cnt, double* out) {
   const int t = threadIdx.x;
-  int best = n;
-  for (int e = t; e < n; e += blockDim.x) {
-    const bool ok = fabs(x[e]) >= thr && !(mask && mask[e]);
-    if (ok && e < best) best = e;
-  }
-  for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
-  if ((t & 63) == 0) redi[t >> 6] = best;
-  __syncthreads();
-  const int b = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
-  __syncthreads();
-  return b;
-}
-
-// out[l] = sum_b part[(1 + l) * ACA_MAXBLK + b] for l in [0, cnt), fixed
-// summation order: four interleaved partial sums per l, then combined.
-__device__ void block_sum_parts(const double* part, int nb, int cnt, double* lds4, double* out) {
-  const int t = threadIdx.x;
-  const int g = t >> 6, l0 = t & 63;
-  for (int base = 0; base < cnt; base += 64) {
-    const int l = base + l0;
+  const int wv = t >> 6, ln = t & 63;
+  for (int l = wv; l < cnt; l += 4) {
+    const double* q = part + (size_t)(1 + l) * ACA_MAXBLK;
     double acc = 0.0;
-    if (l < cnt)
-      for (int b = g; b < nb; b += 4) acc += part[(size_t)(1 + l) * ACA_MAXBLK + b];
-    lds4[g * 64 + l0] = acc;
-    __syncthreads();
-    if (g == 0 && l < cnt) out[l] = ((lds4[l0] + lds4[64 + l0]) + lds4[128 + l0]) + lds4[192 + l0];
-    __syncthreads();
+    for (int b = ln; b < nb; b += 64) acc += q[b];
+    acc = wave_sum(acc);
+    if (ln == 0) out[l] = acc;
   }
 }
 
-__device__ double block_max_masked(const double* x, int n, const unsigned char* mask, double* red) {
-  double m = -1.0;
-  for (int e = threadIdx.x; e < n; e += blockDim.x)
-    if (!(mask && mask[e])) m = fmax(m, fabs(x[e]));
-  return block_max(m, red);
-}
-
+template <int DX>
 __device__ __forceinline__ void unravel_x(const GridDev& g, int I, int* gi) {
-  if (g.dx == 1) gi[0] = I; else { gi[0] = I / g.n[1]; gi[1] = I % g.n[1]; }
+  if (DX == 1) gi[0] = I; else { gi[0] = I / g.n[1]; gi[1] = I % g.n[1]; }
 }
+template <int DX>
 __device__ __forceinline__ void unravel_v(const GridDev& g, int J, int* gi) {
-  if (g.dv == 1) gi[1] = J; else { gi[2] = J / g.n[3]; gi[3] = J % g.n[3]; }
+  if (DX == 1) gi[1] = J; else { gi[2] = J / g.n[3]; gi[3] = J % g.n[3]; }
 }
 
 // Partial-sum layout (doubles): part[q * ACA_MAXBLK + b]
@@ -180,6 +151,11 @@ struct SkipUsed {
   __device__ bool operator()(int e) const { return used[e] != 0 || e == also; }
 };
 
+// Earlier cross vectors at this thread's position, cached in registers:
+// slot m holds l = wave + 4 m (k <= 64, so m < 16).
+constexpr int ACA_LREG = 16;
+static_assert(4 * ACA_LREG >= 64, "register cache covers every earlier cross vector (kmax <= 64)");
+
 template <typename T, int W, int DX>
 __device__ void aca_row_body(const AcaInst& I, int tile) {
   const GridDev& g = I.g;
@@ -188,7 +164,7 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
   const T* __restrict__ P = (const T*)I.P;
   const int ld = I.ld, r = I.r;
   AcaCtl* ctl = I.ctl;
-  double* __restrict__ U = I.U;
+  const double* __restrict__ U = I.U;
   double* __restrict__ V = I.V;
   double* __restrict__ part = I.part;
   __shared__ FsLds<W, DX> L;
@@ -205,24 +181,36 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
   const int Nx = g.nx, Nv = g.nv;
   const int J0 = tile * FS_SAMPLES;
   const int ns = min(FS_SAMPLES, Nv - J0);
-  if (t < ns) {
-    int gi[4];
-    unravel_x(g, i, gi);
-    unravel_v(g, J0 + t, gi);
-    fs_prepare<W, DX>(g, a, gi, L, t);
+  const int wv = t >> 6, ln = t & 63;
+  // earlier row vectors v_l[J] and u_l[i] (loads in flight during the feet)
+  double vl[ACA_LREG], ui[ACA_LREG];
+#pragma unroll
+  for (int m = 0; m < ACA_LREG; ++m) {
+    const int l = wv + 4 * m;
+    const bool ok = l < k && ln < ns;
+    vl[m] = ok ? V[(size_t)l * Nv + J0 + ln] : 0.0;
+    ui[m] = ok ? U[(size_t)l * Nx + i] : 0.0;
+  }
+  {
+    const int s = t >> 2;
+    if (s < ns) {
+      int gi[4];
+      unravel_x<DX>(g, i, gi);
+      unravel_v<DX>(g, J0 + s, gi);
+      fs_prepare<W, DX, 4>(g, a, gi, L, s, t & 3);
+    }
+  }
+  // residual r_J = A[i, J] - sum_l u_l[i] v_l[J]: the l-sum is split over
+  // the four waves (wave w takes l = w, w + 4, ...) and combined in LDS
+  {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < ACA_LREG; ++m)
+      if (wv + 4 * m < k) acc += ui[m] * vl[m];
+    acc4[wv][ln] = acc;
   }
   __syncthreads();
   fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
-  __syncthreads();
-  // residual r_J = A[i, J] - sum_l u_l[i] v_l[J]: the l-sum is split over
-  // the four waves (wave w takes l = w, w + 4, ...) and combined in LDS
-  const int wv = t >> 6, ln = t & 63;
-  {
-    double acc = 0.0;
-    if (ln < ns)
-      for (int l = wv; l < k; l += 4) acc += U[(size_t)l * Nx + i] * V[(size_t)l * Nv + J0 + ln];
-    acc4[wv][ln] = acc;
-  }
   __syncthreads();
   if (t < 64) {
     double rv = 0.0;
@@ -233,12 +221,16 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
     rres[t] = rv;
   }
   __syncthreads();
-  for (int l = wv; l <= k; l += 4) {
-    const double r_ = rres[ln];
-    double p = 0.0;
-    if (ln < ns) p = (l < k ? V[(size_t)l * Nv + J0 + ln] : r_) * r_;
-    p = wave_sum(p);
-    if (ln == 0) part[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+  {
+    const double r_ = (ln < ns) ? rres[ln] : 0.0;
+#pragma unroll
+    for (int m = 0; m < ACA_LREG; ++m) {
+      const int l = wv + 4 * m;
+      if (l <= k) {
+        const double p = wave_sum((l < k ? vl[m] : r_) * r_);
+        if (ln == 0) part[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+      }
+    }
   }
   block_candidate(rres, ns, J0, NoSkip{}, red, redi, &part[tile], &part[ACA_MAXBLK + tile]);
 }
@@ -269,6 +261,16 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
   if (s_phase != ACA_RUN) return;
   const int i = s_i, k = s_k;
   const int Nx = g.nx, Nv = g.nv;
+  const int I0 = tile * FS_SAMPLES;
+  const int ns = min(FS_SAMPLES, Nx - I0);
+  const int wv = t >> 6, ln = t & 63;
+  // earlier column vectors u_l[I] (independent of the pivot: issued first)
+  double ul[ACA_LREG];
+#pragma unroll
+  for (int m = 0; m < ACA_LREG; ++m) {
+    const int l = wv + 4 * m;
+    ul[m] = (l < k && ln < ns) ? U[(size_t)l * Nx + I0 + ln] : 0.0;
+  }
   // column pivot of the row residual (every block computes the same)
   double M;
   const double* vk = V + (size_t)k * Nv;
@@ -276,24 +278,30 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
   const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
   if (M == 0.0 || M <= thr || j >= Nv) return;   // row already reproduced
   const double piv = vk[j];
-  const int I0 = tile * FS_SAMPLES;
-  const int ns = min(FS_SAMPLES, Nx - I0);
-  if (t < ns) {
-    int gi[4];
-    unravel_x(g, I0 + t, gi);
-    unravel_v(g, j, gi);
-    fs_prepare<W, DX>(g, a, gi, L, t);
+  double vj[ACA_LREG];
+#pragma unroll
+  for (int m = 0; m < ACA_LREG; ++m) {
+    const int l = wv + 4 * m;
+    vj[m] = (l < k) ? V[(size_t)l * Nv + j] : 0.0;
+  }
+  {
+    const int s = t >> 2;
+    if (s < ns) {
+      int gi[4];
+      unravel_x<DX>(g, I0 + s, gi);
+      unravel_v<DX>(g, j, gi);
+      fs_prepare<W, DX, 4>(g, a, gi, L, s, t & 3);
+    }
+  }
+  {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < ACA_LREG; ++m)
+      if (wv + 4 * m < k) acc += vj[m] * ul[m];
+    acc4[wv][ln] = acc;
   }
   __syncthreads();
   fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
-  __syncthreads();
-  const int wv = t >> 6, ln = t & 63;
-  {
-    double acc = 0.0;
-    if (ln < ns)
-      for (int l = wv; l < k; l += 4) acc += V[(size_t)l * Nv + j] * U[(size_t)l * Nx + I0 + ln];
-    acc4[wv][ln] = acc;
-  }
   __syncthreads();
   if (t < 64) {
     double u = 0.0;
@@ -305,12 +313,16 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
   }
   __syncthreads();
   double* pc = part + (size_t)PCOL * ACA_MAXBLK;
-  for (int l = wv; l <= k; l += 4) {
-    const double u_ = ures[ln];
-    double p = 0.0;
-    if (ln < ns) p = (l < k ? U[(size_t)l * Nx + I0 + ln] : u_) * u_;
-    p = wave_sum(p);
-    if (ln == 0) pc[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+  {
+    const double u_ = (ln < ns) ? ures[ln] : 0.0;
+#pragma unroll
+    for (int m = 0; m < ACA_LREG; ++m) {
+      const int l = wv + 4 * m;
+      if (l <= k) {
+        const double p = wave_sum((l < k ? ul[m] : u_) * u_);
+        if (ln == 0) pc[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+      }
+    }
   }
   block_candidate(ures, ns, I0, SkipUsed{used, i}, red, redi, &pc[tile], &pc[ACA_MAXBLK + tile]);
 }
@@ -334,12 +346,13 @@ __device__ void aca_fin_body(const AcaInst& I) {
   __shared__ FsLds<W, DX> L;
   __shared__ double red[4];
   __shared__ int redi[4];
-  __shared__ double lds4[256];
+  __shared__ double sgv[SLAR_KMAX + 1], sgu[SLAR_KMAX + 1];
   __shared__ double res[1024];
   __shared__ int pi[1024];
   __shared__ int s_phase, s_i, s_k, s_stop;
+  __shared__ double s_tol, s_norm2;
   const int t = threadIdx.x;
-  if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; }
+  if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; s_tol = ctl->tol; s_norm2 = ctl->norm2; }
   __syncthreads();
   if (s_phase != ACA_RUN) return;
   const int i = s_i;
@@ -348,7 +361,7 @@ __device__ void aca_fin_body(const AcaInst& I) {
   double M;
   const double* vk = V + (size_t)k * Nv;
   const int j = pivot_from_parts(vk, part, part + ACA_MAXBLK, nbrow, Nv, NoSkip{}, red, redi, &M);
-  const double thr = ctl->tol * sqrt(ctl->norm2) / sqrt((double)Nx * (double)Nv);
+  const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
   const bool zero_row = (M == 0.0 || M <= thr || j >= Nv);
   if (t == 0) {
     used[i] = 1;
@@ -357,21 +370,26 @@ __device__ void aca_fin_body(const AcaInst& I) {
   }
   if (!zero_row) {
     double* pc = part + (size_t)PCOL * ACA_MAXBLK;
-    block_sum_parts(part + ACA_MAXBLK, nbrow, k + 1, lds4, ctl->gv);
-    block_sum_parts(pc + ACA_MAXBLK, nbcol, k + 1, lds4, ctl->gu);
+    block_sum_parts(part + ACA_MAXBLK, nbrow, k + 1, sgv);
+    block_sum_parts(pc + ACA_MAXBLK, nbcol, k + 1, sgu);
     __syncthreads();
-    if (t == 0) {
-      ctl->samples += Nx;
-      ctl->j = j;
-      ctl->pivot = vk[j];
-      double cross = 0.0;
-      for (int l = 0; l < k; ++l) cross += ctl->gu[l] * ctl->gv[l];
-      const double nk = ctl->gu[k] * ctl->gv[k];
-      ctl->norm2 = ctl->norm2 + 2.0 * cross + nk;
-      ctl->k = k + 1;
-      s_stop = 0;
-      if (sqrt(nk) <= ctl->tol * sqrt(fmax(ctl->norm2, 0.0))) s_stop = 1;            // probe
-      else if (k + 1 >= ctl->kmax) { ctl->phase = ACA_DONE; ctl->capped = 1; s_stop = 2; }
+    if (t < 64) {
+      // cross terms sum_{l<k} (u_l . u_k)(v_l . v_k), k <= 64
+      double c = (t < k) ? sgu[t] * sgv[t] : 0.0;
+      c = wave_sum(c);
+      if (t == 0) {
+        ctl->samples += Nx;
+        ctl->j = j;
+        ctl->pivot = vk[j];
+        const double nk = sgu[k] * sgv[k];
+        const double norm2 = s_norm2 + 2.0 * c + nk;
+        ctl->norm2 = norm2;
+        ctl->k = k + 1;
+        s_norm2 = norm2;
+        s_stop = 0;
+        if (sqrt(nk) <= s_tol * sqrt(fmax(norm2, 0.0))) s_stop = 1;            // probe
+        else if (k + 1 >= ctl->kmax) { ctl->phase = ACA_DONE; ctl->capped = 1; s_stop = 2; }
+      }
     }
     __syncthreads();
     k = k + 1;
@@ -393,25 +411,33 @@ __device__ void aca_fin_body(const AcaInst& I) {
     if (t == 0) { ctl->phase = ACA_DONE; ctl->converged = 1; }
     return;
   }
-  const double thr2 = ctl->tol * sqrt(fmax(ctl->norm2, 0.0)) / sqrt((double)Nx * (double)Nv);
+  const double thr2 = s_tol * sqrt(fmax(s_norm2, 0.0)) / sqrt((double)Nx * (double)Nv);
   for (int base = 0; base < nprobe; base += FS_SAMPLES) {
     const int ns = min(FS_SAMPLES, nprobe - base);
-    if (t < ns) {
+    const int s = t >> 2, q = t & 3;
+    int pI = 0, pJ = 0;
+    if (s < ns) {
+      pI = probes[2 * (base + s)];
+      pJ = probes[2 * (base + s) + 1];
       int gi[4];
-      unravel_x(g, probes[2 * (base + t)], gi);
-      unravel_v(g, probes[2 * (base + t) + 1], gi);
-      fs_prepare<W, DX>(g, a, gi, L, t);
+      unravel_x<DX>(g, pI, gi);
+      unravel_v<DX>(g, pJ, gi);
+      fs_prepare<W, DX, 4>(g, a, gi, L, s, q);
     }
+    // approximation at the probe: the quad splits the l-sum
+    double ap = 0.0;
+    if (s < ns)
+      for (int l = q; l < k; l += 4) ap += U[(size_t)l * Nx + pI] * V[(size_t)l * Nv + pJ];
+    ap += __shfl_xor(ap, 1, 4);
+    ap += __shfl_xor(ap, 2, 4);
     __syncthreads();
     fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
     __syncthreads();
-    if (t < ns) {
-      const int I = probes[2 * (base + t)], J = probes[2 * (base + t) + 1];
-      double v = L.val[t];
-      for (int l = 0; l < k; ++l) v -= U[(size_t)l * Nx + I] * V[(size_t)l * Nv + J];
-      const bool bad = fabs(v) > thr2 && !used[I];
-      res[base + t] = bad ? fabs(v) : -1.0;
-      pi[base + t] = I;
+    if (s < ns && q == 0) {
+      const double v = L.val[s] - ap;
+      const bool bad = fabs(v) > thr2 && !used[pI];
+      res[base + s] = bad ? fabs(v) : -1.0;
+      pi[base + s] = pI;
     }
     __syncthreads();
   }
@@ -441,6 +467,5 @@ __device__ void aca_fin_body(const AcaInst& I) {
     }
   }
 }
-
 
 }  // namespace slar

@@ -76,7 +76,7 @@ static bool frames_ok(const slar_frames* F) {
 }
 
 static AdvDev make_adv(const slar_adv* a, const double* Eeff) {
-  return AdvDev{a->kind, a->order, a->tau, a->cv, Eeff, nullptr, 1.0, 0.0};
+  return AdvDev{a->kind, a->order, a->tau, a->cv, Eeff, nullptr, 1.0, 0.0, 1};
 }
 
 extern "C" {
@@ -181,7 +181,7 @@ slar_status slar_ht_sample(const slar_grid* g, const slar_ht* F, const slar_adv*
   if (n == 0) return SLAR_OK;
   GridDev G = make_grid(*g);
   // the two frozen fields are combined node by node inside the kernel
-  AdvDev A{a->kind, a->order, a->tau, a->cv, a->E[0], a->E[1], a->cE[0], a->cE[1]};
+  AdvDev A{a->kind, a->order, a->tau, a->cv, a->E[0], a->E[1], a->cE[0], a->cE[1], 0};
   hipError_t e = ht_sample(stream, G, A, *F, n, idx, out);
   return e == hipSuccess ? SLAR_OK : SLAR_E_HIP;
 }

@@ -82,12 +82,14 @@ __global__ __launch_bounds__(256) void k_batch_prep(const BPrep* __restrict__ pr
     const int row = (int)(e / p.ldt), c = (int)(e % p.ldt);
     p.P32[e] = (float)((c < p.r) ? p.P[(long long)row * p.ldin + c] : 0.0);
   }
+  // combined field, node-interleaved [Nx][dx] (inputs planar [dx][Nx])
   const long long nE = (long long)p.dx * p.nx;
   for (long long e = e0; e < nE; e += stride) {
+    const long long in = (e % p.dx) * p.nx + e / p.dx;
     double v = 0.0;
     if (p.E0 != nullptr) {
-      v = p.c0 * p.E0[e];
-      if (p.E1 != nullptr) v = v + p.c1 * p.E1[e];
+      v = p.c0 * p.E0[in];
+      if (p.E1 != nullptr) v = v + p.c1 * p.E1[in];
     }
     p.Eeff[e] = v;
   }
@@ -332,7 +334,7 @@ static slar_status batch_cross(slar_batch* b, const slar_frames* src, const slar
     p.Eeff = w.Eeff; p.used = w.used; p.ctl = (AcaCtl*)w.aca_ctl; p.kmax = kmax; p.tol = tol;
     AcaInst& I = b->h_inst[q];
     I.g = w.G;
-    I.a = AdvDev{a.kind, a.order, a.tau, a.cv, w.Eeff, nullptr, 1.0, 0.0};
+    I.a = AdvDev{a.kind, a.order, a.tau, a.cv, w.Eeff, nullptr, 1.0, 0.0, 1};
     I.X = w.X32; I.P = w.P32; I.ld = ldt; I.r = r;
     I.ctl = (AcaCtl*)w.aca_ctl; I.U = out[q].U; I.V = out[q].V; I.used = w.used;
     I.part = w.aca_part; I.nbrow = b->nbrow[q]; I.nbcol = b->nbcol[q];

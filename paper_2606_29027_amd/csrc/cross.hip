@@ -84,7 +84,7 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
     if (table_copy(s, G.nv, r, src.ld, src.P, ldt, nullptr, P64) != hipSuccess) return SLAR_E_HIP;
   }
   if (combine_field(s, G, &adv, ws->Eeff) != hipSuccess) return SLAR_E_HIP;
-  AdvDev A{adv.kind, adv.order, adv.tau, adv.cv, ws->Eeff, nullptr, 1.0, 0.0};
+  AdvDev A{adv.kind, adv.order, adv.tau, adv.cv, ws->Eeff, nullptr, 1.0, 0.0, 1};
   AcaCtl h{};
   h.phase = ACA_RUN; h.k = 0; h.i = 0; h.j = 0; h.kmax = kmax; h.tol = tol; h.norm2 = 0.0;
   AcaCtl* ctl = (AcaCtl*)ws->aca_ctl;

@@ -29,14 +29,18 @@ struct FsLds {
 };
 
 // Phase 1 for one sample: grid multi-index -> stencil rows and weights.
-template <int W, int DX>
+// NL = 4: the four lanes of a quad share the foot computation (all pass the
+// same sample); lane 0 writes the LDS entries.
+template <int W, int DX, int NL = 1>
 __device__ __forceinline__ void fs_prepare(const GridDev& g, const AdvDev& a, const int* gidx,
-                                           FsLds<W, DX>& L, int s) {
+                                           FsLds<W, DX>& L, int s, int lane = 0) {
   double ft[4];
-  foot_of(g, a, gidx, ft);
+  foot_of<DX, NL>(g, a, gidx, ft, lane);
   int r[4][W];
   double w[4][W];
+#pragma unroll
   for (int m = 0; m < 2 * DX; ++m) stencil_of<W>(g, a, m, ft[m], gidx[m], r[m], w[m]);
+  if (lane != 0) return;
   if (DX == 1) {
 #pragma unroll
     for (int b = 0; b < W; ++b) {
@@ -56,6 +60,8 @@ __device__ __forceinline__ void fs_prepare(const GridDev& g, const AdvDev& a, co
       }
   }
 }
+
+static_assert(FS_THREADS == 4 * FS_SAMPLES, "one lane quad per sample in the cooperative prepare");
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> {

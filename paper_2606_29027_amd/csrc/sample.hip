@@ -42,7 +42,8 @@ __global__ __launch_bounds__(256) void k_ht_sample(GridDev g, AdvDev a, HtDev<T>
     int gi[4];
     for (int m = 0; m < d; ++m) gi[m] = idx[(s0 + t) * d + m];
     double ft[4];
-    foot_of(g, a, gi, ft);
+    if (g.dx == 1) foot_of<1>(g, a, gi, ft);
+    else foot_of<2>(g, a, gi, ft);
     for (int m = 0; m < d; ++m) stencil_of<W>(g, a, m, ft[m], gi[m], rows[t][m], wts[t][m]);
   }
   __syncthreads();
@@ -130,19 +131,23 @@ hipError_t ht_sample(hipStream_t st, const GridDev& G, const AdvDev& A, const sl
 }
 
 // ------------------------------------------------------- frozen field
-__global__ void k_combine(int count, const double* E0, double c0, const double* E1, double c1,
+// Combined frozen field, node-interleaved: out[lin][m] = c0 E0[m][lin] +
+// c1 E1[m][lin] (inputs planar [dx][Nx]).
+__global__ void k_combine(int nx, int dx, const double* E0, double c0, const double* E1, double c1,
                           double* out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= count) return;
-  double v = c0 * E0[e];
-  if (E1 != nullptr) v = v + c1 * E1[e];
+  if (e >= nx * dx) return;
+  const int lin = e / dx, m = e % dx;
+  const size_t in = (size_t)m * nx + lin;
+  double v = c0 * E0[in];
+  if (E1 != nullptr) v = v + c1 * E1[in];
   out[e] = v;
 }
 
 hipError_t combine_field(hipStream_t s, const GridDev& G, const slar_adv* a, double* out) {
   const int count = G.dx * G.nx;
   if (a->E[0] == nullptr) return hipMemsetAsync(out, 0, sizeof(double) * count, s);
-  k_combine<<<(count + 255) / 256, 256, 0, s>>>(count, a->E[0], a->cE[0], a->E[1], a->cE[1], out);
+  k_combine<<<(count + 255) / 256, 256, 0, s>>>(G.nx, G.dx, a->E[0], a->cE[0], a->E[1], a->cE[1], out);
   return hipGetLastError();
 }
 
@@ -218,10 +223,13 @@ __global__ __launch_bounds__(FS_THREADS) void k_frame_points(GridDev g, AdvDev a
   const long long s0 = (long long)blockIdx.x * FS_SAMPLES;
   const int ns = (int)min((long long)FS_SAMPLES, n - s0);
   const int t = threadIdx.x;
-  if (t < ns) {
-    int gi[4];
-    for (int m = 0; m < 2 * DX; ++m) gi[m] = idx[(s0 + t) * (2 * DX) + m];
-    fs_prepare<W, DX>(g, a, gi, L, t);
+  {
+    const int s = t >> 2;
+    if (s < ns) {
+      int gi[4];
+      for (int m = 0; m < 2 * DX; ++m) gi[m] = idx[(s0 + s) * (2 * DX) + m];
+      fs_prepare<W, DX, 4>(g, a, gi, L, s, t & 3);
+    }
   }
   __syncthreads();
   fs_evaluate<T, W, DX>(X, P, ld, r, L, ns);
