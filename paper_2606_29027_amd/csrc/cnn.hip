@@ -175,14 +175,69 @@ __global__ void k_adam(int n, float* __restrict__ th, const float* __restrict__ 
   th[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
+// The same layer with the channel counts fixed at compile time: one thread
+// per (pixel, group of OG output channels), weights read with uniform
+// addresses (scalar loads), accumulators in registers.  Per output channel
+// the summation order is that of k_conv_fwd (bias, then c, dy, dx).
+template <int CI, int CO, int OG>
+__global__ __launch_bounds__(256) void k_conv_fwd_t(int B, int H, int W, const float* __restrict__ in,
+                                                    const float* __restrict__ prm, int act,
+                                                    float* __restrict__ out) {
+  static_assert(CO % OG == 0, "output groups");
+  const int HW = H * W;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (long long)B * HW) return;
+  const int o0 = blockIdx.y * OG;
+  const int b = (int)(p / HW), pix = (int)(p % HW);
+  const int y = pix / W, x = pix % W;
+  const int rm = (y == 0 ? H - 1 : y - 1) * W, r0 = y * W, rp = (y == H - 1 ? 0 : y + 1) * W;
+  const int xm = (x == 0 ? W - 1 : x - 1), xp = (x == W - 1 ? 0 : x + 1);
+  float acc[OG];
+#pragma unroll
+  for (int o = 0; o < OG; ++o) acc[o] = prm[CO * CI * 9 + o0 + o];
+#pragma unroll
+  for (int c = 0; c < CI; ++c) {
+    const float* ic = in + ((size_t)b * CI + c) * HW;
+    const float v[9] = {ic[rm + xm], ic[rm + x], ic[rm + xp], ic[r0 + xm], ic[r0 + x],
+                        ic[r0 + xp], ic[rp + xm], ic[rp + x], ic[rp + xp]};
+#pragma unroll
+    for (int o = 0; o < OG; ++o) {
+      const float* wo = prm + ((size_t)(o0 + o) * CI + c) * 9;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc[o] += wo[t] * v[t];
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < OG; ++o) {
+    const float z = acc[o];
+    out[((size_t)b * CO + o0 + o) * HW + pix] = act ? tanhf(z) : z;
+  }
+}
+
+template <int CI, int CO>
+static bool conv_fixed(hipStream_t s, int ci, int co, unsigned nb, int B, int H, int W, const float* in,
+                       const float* prm, int act, float* out) {
+  if (ci != CI || co != CO) return false;
+  constexpr int OG = CO < 4 ? CO : 4;
+  k_conv_fwd_t<CI, CO, OG><<<dim3(nb, CO / OG), 256, 0, s>>>(B, H, W, in, prm, act, out);
+  return true;
+}
+
 static hipError_t cnn_forward(hipStream_t s, slar_cnn* c, int B, int H, int W, const float* x) {
   const long long P = (long long)B * H * W;
   const unsigned nb = (unsigned)((P + 255) / 256);
   const float* in = x;
   for (int l = 0; l < c->nl; ++l) {
-    k_conv_fwd<<<nb, 256, 0, s>>>(B, H, W, c->ch[l], c->ch[l + 1], in, c->theta + c->off[l],
-                                  l < c->nl - 1 ? 1 : 0, c->act[l + 1]);
-    in = c->act[l + 1];
+    const int ci = c->ch[l], co = c->ch[l + 1], act = l < c->nl - 1 ? 1 : 0;
+    const float* prm = c->theta + c->off[l];
+    float* out = c->act[l + 1];
+    const bool fixed = conv_fixed<8, 16>(s, ci, co, nb, B, H, W, in, prm, act, out) ||
+                       conv_fixed<16, 16>(s, ci, co, nb, B, H, W, in, prm, act, out) ||
+                       conv_fixed<16, 4>(s, ci, co, nb, B, H, W, in, prm, act, out) ||
+                       conv_fixed<8, 8>(s, ci, co, nb, B, H, W, in, prm, act, out) ||
+                       conv_fixed<8, 4>(s, ci, co, nb, B, H, W, in, prm, act, out);
+    if (!fixed) k_conv_fwd<<<nb, 256, 0, s>>>(B, H, W, ci, co, in, prm, act, out);
+    in = out;
   }
   return hipGetLastError();
 }
@@ -230,18 +285,19 @@ static hipError_t cnn_backward(hipStream_t s, slar_cnn* c, int B, int H, int W, 
 
 // ---------------------------------------------- use inside the Krylov solve
 // stats[0] = sum v^2, stats[1 + 2c] = mean U_c, stats[2 + 2c] = std U_c
-__global__ void k_cnn_stats(int Nx, int K, const double* __restrict__ v, const double* __restrict__ U,
-                            double* __restrict__ stats) {
-  __shared__ double r0[256], r1[256], r2[256];
+__global__ __launch_bounds__(1024) void k_cnn_stats(int Nx, int K, const double* __restrict__ v,
+                                                    const double* __restrict__ U,
+                                                    double* __restrict__ stats) {
+  __shared__ double r0[1024], r1[1024], r2[1024];
   const int c = blockIdx.x, t = threadIdx.x;
   double a = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int e = t; e < Nx; e += 256) {
+  for (int e = t; e < Nx; e += 1024) {
     const double x = v[(size_t)c * Nx + e], u = U[(size_t)c * Nx + e];
     a += x * x; s1 += u; s2 += u * u;
   }
   r0[t] = a; r1[t] = s1; r2[t] = s2;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = 512; o > 0; o >>= 1) {
     if (t < o) { r0[t] += r0[t + o]; r1[t] += r1[t + o]; r2[t] += r2[t + o]; }
     __syncthreads();
   }
@@ -284,7 +340,7 @@ hipError_t cnn_apply(hipStream_t s, Workspace* ws, const slar_cnn* net, const do
   if (G.dx != 2 || c->ch[0] != 2 * (G.dv + 2) || c->ch[c->nl] != G.dv + 2) return hipErrorInvalidValue;
   const int K = G.dv + 2, Nx = G.nx;
   if (Nx > c->maxHW) return hipErrorInvalidValue;
-  k_cnn_stats<<<K, 256, 0, s>>>(Nx, K, v, U, c->stats);
+  k_cnn_stats<<<K, 1024, 0, s>>>(Nx, K, v, U, c->stats);
   k_cnn_features<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx, K, v, U, c->stats, c->act[0]);
   HIP_CHK(cnn_forward(s, c, 1, G.n[0], G.n[1], c->act[0]));
   k_cnn_add<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx * K, Nx, K, c->act[c->nl], c->stats, z);
@@ -312,7 +368,7 @@ hipError_t record_pair(hipStream_t s, Workspace* ws, const double* w, const doub
   double* stats = ws->small + 4096;
   float* feat = ws->rec_feat + (size_t)ws->rec_count * 2 * K * Nx;
   float* tgt = ws->rec_targ + (size_t)ws->rec_count * K * Nx;
-  k_cnn_stats<<<K, 256, 0, s>>>(Nx, K, w, U, stats);
+  k_cnn_stats<<<K, 1024, 0, s>>>(Nx, K, w, U, stats);
   k_cnn_features<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx, K, w, U, stats, feat);
   k_record_target<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx * K, Nx, K, z, pw, stats, tgt);
   ws->rec_count += 1;

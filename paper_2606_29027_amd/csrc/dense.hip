@@ -202,80 +202,120 @@ __device__ __forceinline__ int rr_player(int pos, int step, int kp) {
   return pos == 0 ? 0 : 1 + (pos - 1 + step) % (kp - 1);
 }
 
-// ---------------------------------------------------- one-sided Jacobi SVD
-// M (k x k, row-major) = W diag(s) Z^T, s descending.  Outputs W, Z as
-// row-major k x k (columns are singular vectors).
-__global__ __launch_bounds__(1024) void k_svd_jacobi(int k, const double* __restrict__ Min,
-                                                    double* __restrict__ W, double* __restrict__ sv,
-                                                    double* __restrict__ Z) {
-  __shared__ double A[SLAR_KMAX][SLAR_KMAX + 1];   // A[row][col]
-  __shared__ double V[SLAR_KMAX][SLAR_KMAX + 1];
-  __shared__ int pairs[SLAR_KMAX];
-  __shared__ int rotated;
-  __shared__ double nrm[SLAR_KMAX];
-  __shared__ int order[SLAR_KMAX];
-  const int t = threadIdx.x;
-  const int kp = (k + 1) & ~1;   // even count (a zero column pads odd k)
-  for (int e = t; e < kp * kp; e += blockDim.x) {
-    const int i = e / kp, j = e % kp;
-    A[i][j] = (i < k && j < k) ? Min[i * k + j] : 0.0;
-    V[i][j] = (i == j) ? 1.0 : 0.0;
-  }
-  for (int i = t; i < kp; i += blockDim.x) pairs[i] = i;
-  __syncthreads();
+// ------------------------------------------- one-sided Jacobi, team form
+// Columns of C (col-major in LDS, column c at C + c * ldc, n <= 32 RPL
+// rows, kp <= 64 columns, kp even) are orthogonalised by cyclic one-sided
+// Jacobi rotations in circle-method order; the same rotations are applied
+// to V (kv <= 32 VPL rows) when VPL > 0.  1024 threads: team = 32 lanes,
+// team i owns pair i of every step, so a step is one pass over registers
+// and one barrier.  A pair is rotated when |x.y| exceeds the rounding
+// level of its dot product (orth |x| |y|) and |x| |y| > floor_abs.
+// Returns the number of sweeps.
+template <int RPL, int VPL>
+__device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv, int kv, double orth,
+                           double floor_abs, int maxsweep, int* s_rot) {
+  const int team = threadIdx.x >> 5, lane = threadIdx.x & 31;
   const int npair = kp / 2;
-  __shared__ double fro;
-  if (t == 0) {
-    double acc = 0.0;
-    for (int i = 0; i < kp; ++i)
-      for (int j = 0; j < kp; ++j) acc += A[i][j] * A[i][j];
-    fro = acc;
-  }
-  __syncthreads();
-  const double floor_abs = 1e-300 + 1e-22 * fro;   // columns below this are negligible
-  const int team = (npair > 0) ? max(1, min(64, (int)blockDim.x / npair)) : 1;  // power of 2 below
-  int tm = 1;
-  while (tm * 2 <= team) tm *= 2;
-  const int pid = t / tm, lane = t % tm;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (t == 0) rotated = 0;
+  int sweep = 0;
+  for (; sweep < maxsweep; ++sweep) {
+    if (threadIdx.x == 0) *s_rot = 0;
     __syncthreads();
+    bool rotated = false;
     for (int step = 0; step < kp - 1; ++step) {
-      if (pid < npair) {
-        const int p = rr_player(pid, step, kp), q = rr_player(kp - 1 - pid, step, kp);
+      if (team < npair) {
+        const int p = rr_player(team, step, kp), q = rr_player(kp - 1 - team, step, kp);
+        double* cp = C + (size_t)p * ldc;
+        double* cq = C + (size_t)q * ldc;
+        double x[RPL], y[RPL];
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int r = lane; r < kp; r += tm) {
-          const double x = A[r][p], y = A[r][q];
-          al += x * x; be += y * y; ga += x * y;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int r = lane + 32 * i;
+          x[i] = (r < n) ? cp[r] : 0.0;
+          y[i] = (r < n) ? cq[r] : 0.0;
+          al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i];
         }
-        for (int o = tm / 2; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, tm);
-          be += __shfl_xor(be, o, tm);
-          ga += __shfl_xor(ga, o, tm);
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, 32);
+          be += __shfl_xor(be, o, 32);
+          ga += __shfl_xor(ga, o, 32);
         }
-        if (fabs(ga) > 1e-14 * sqrt(al * be) && sqrt(al * be) > floor_abs) {
+        const double ab = sqrt(al * be);
+        if (fabs(ga) > orth * ab && ab > floor_abs) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
-          for (int r = lane; r < kp; r += tm) {
-            const double x = A[r][p], y = A[r][q];
-            A[r][p] = c * x - sn * y;
-            A[r][q] = sn * x + c * y;
-            const double vx = V[r][p], vy = V[r][q];
-            V[r][p] = c * vx - sn * vy;
-            V[r][q] = sn * vx + c * vy;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int r = lane + 32 * i;
+            if (r < n) {
+              cp[r] = c * x[i] - sn * y[i];
+              cq[r] = sn * x[i] + c * y[i];
+            }
           }
-          if (lane == 0) rotated = 1;
+          if (VPL > 0) {
+            double* vp = V + (size_t)p * ldv;
+            double* vq = V + (size_t)q * ldv;
+#pragma unroll
+            for (int i = 0; i < (VPL > 0 ? VPL : 1); ++i) {
+              const int r = lane + 32 * i;
+              if (r < kv) {
+                const double vx = vp[r], vy = vq[r];
+                vp[r] = c * vx - sn * vy;
+                vq[r] = sn * vx + c * vy;
+              }
+            }
+          }
+          rotated = true;
         }
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    if (rotated && lane == 0) *s_rot = 1;
     __syncthreads();
+    if (*s_rot == 0) break;
   }
+  return sweep;
+}
+
+// ---------------------------------------------------- one-sided Jacobi SVD
+// M (k x k, row-major, k <= 64) = W diag(s) Z^T, s descending.  Jacobi on
+// the columns of M (rotations accumulated in Z); the rotated column norms
+// are the singular values.  Outputs W, Z as row-major k x k (columns are
+// singular vectors).
+constexpr int SVD_KM = 64;
+
+__global__ __launch_bounds__(1024) void k_svd_jacobi(int k, const double* __restrict__ Min,
+                                                    double* __restrict__ W, double* __restrict__ sv,
+                                                    double* __restrict__ Z) {
+  __shared__ double A[SVD_KM * SVD_KM];   // column c at A + c * SVD_KM
+  __shared__ double V[SVD_KM * SVD_KM];
+  __shared__ double nrm[SVD_KM];
+  __shared__ int order[SVD_KM];
+  __shared__ double red[16];
+  __shared__ int s_rot;
+  const int t = threadIdx.x;
+  const int kp = (k + 1) & ~1;   // even count (a zero column pads odd k)
+  double part = 0.0;
+  for (int e = t; e < kp * kp; e += blockDim.x) {
+    const int c = e / kp, r = e % kp;
+    const double v = (r < k && c < k) ? Min[r * k + c] : 0.0;
+    A[c * SVD_KM + r] = v;
+    V[c * SVD_KM + r] = (r == c) ? 1.0 : 0.0;
+    part += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((t & 63) == 0) red[t >> 6] = part;
+  __syncthreads();
+  double fro = 0.0;
+  for (int w = 0; w < 16; ++w) fro += red[w];
+  const double floor_abs = 1e-300 + 1e-22 * fro;   // columns below this are negligible
+  const double orth = 4.0 * kp * 2.220446049250313e-16;
+  jacobi_cols<2, 2>(A, SVD_KM, kp, kp, V, SVD_KM, kp, orth, floor_abs, 60, &s_rot);
   for (int c = t; c < kp; c += blockDim.x) {
     double acc = 0.0;
-    for (int r = 0; r < kp; ++r) acc += A[r][c] * A[r][c];
+    for (int r = 0; r < kp; ++r) acc += A[c * SVD_KM + r] * A[c * SVD_KM + r];
     nrm[c] = sqrt(acc);
   }
   __syncthreads();
@@ -290,13 +330,14 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi(int k, const double* __rest
   for (int e = t; e < k * k; e += blockDim.x) {
     const int r = e / k, j = e % k;
     const int c = order[j];
-    W[e] = nrm[c] > 0.0 ? A[r][c] / nrm[c] : (r == j ? 1.0 : 0.0);
-    Z[e] = V[r][c];
+    W[e] = nrm[c] > 0.0 ? A[c * SVD_KM + r] / nrm[c] : (r == j ? 1.0 : 0.0);
+    Z[e] = V[c * SVD_KM + r];
   }
   for (int j = t; j < k; j += blockDim.x) sv[j] = nrm[order[j]];
 }
 
 hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z) {
+  if (k < 1 || k > SVD_KM) return hipErrorInvalidValue;
   k_svd_jacobi<<<1, 1024, 0, s>>>(k, M, W, sv, Z);
   return hipGetLastError();
 }
@@ -305,12 +346,17 @@ hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* s
 // G (n x n, symmetric positive semidefinite, n <= 128) = U diag(lam) U^T,
 // lam descending, for the leading eigenpairs.  Two stages in one block:
 //  1. pivoted Cholesky G ~ L L^T, L (n x c) built column by column in LDS
-//     (pivot = largest remaining diagonal), stopping when the remaining
-//     diagonal drops below 1e-30 trace or after SLAR_KMAX columns;
+//     (pivot = largest remaining diagonal, lowest index on ties), stopping
+//     when the remaining diagonal drops below 1e-30 trace or after 64
+//     columns; eight threads share each row's inner product;
 //  2. one-sided Jacobi on the columns of L: the rotated, normalised
 //     columns are the eigenvectors of L L^T and their squared norms the
 //     eigenvalues.
-// Eigenvalues beyond the factor rank are returned as 0 with zero vectors.
+// Eigenvalues beyond the factor rank are returned as 0 with zero vectors,
+// except that lam[c] (c < n) receives the trace left after c columns, so
+// that tail sums over lam never undercount.
+constexpr int EIG_CM = 64;
+
 struct EigBatch {
   int n[4];
   const double* G[4];
@@ -323,107 +369,85 @@ __global__ __launch_bounds__(1024) void k_eig_psd(EigBatch B) {
   const double* __restrict__ G = B.G[blockIdx.x];
   double* __restrict__ lam = B.lam[blockIdx.x];
   double* __restrict__ Uout = B.U[blockIdx.x];
-  __shared__ double Lc[SLAR_NMAX][SLAR_KMAX + 1];   // L[i][j]
+  __shared__ double L[EIG_CM * SLAR_NMAX];   // column c at L + c * SLAR_NMAX
   __shared__ double dres[SLAR_NMAX];
   __shared__ unsigned char taken[SLAR_NMAX];
-  __shared__ double red[1024];
-  __shared__ int redi[1024];
-  __shared__ int ncols_s;
-  __shared__ int pairs[SLAR_KMAX + 1];
-  __shared__ int rotated;
-  __shared__ double nrm[SLAR_KMAX + 1];
-  __shared__ int order[SLAR_KMAX + 1];
+  __shared__ double nrm[EIG_CM];
+  __shared__ int order[EIG_CM];
+  __shared__ double s_piv;
+  __shared__ int s_p, s_rot, s_nc;
+  __shared__ double s_trace, s_rest;
   const int t = threadIdx.x;
-  double trace = 0.0;
-  for (int i = 0; i < n; ++i) trace += fmax(G[(size_t)i * n + i], 0.0);
   for (int i = t; i < n; i += blockDim.x) { dres[i] = fmax(G[(size_t)i * n + i], 0.0); taken[i] = 0; }
-  for (int e = t; e < SLAR_NMAX * (SLAR_KMAX + 1); e += blockDim.x) Lc[e / (SLAR_KMAX + 1)][e % (SLAR_KMAX + 1)] = 0.0;
   __syncthreads();
+  if (t < 64) {
+    double a = 0.0;
+    for (int i = t; i < n; i += 64) a += dres[i];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (t == 0) s_trace = a;
+  }
+  __syncthreads();
+  const double trace = s_trace;
   const double stop = 1e-30 * trace + 1e-300;
+  const int row = t >> 3, sub = t & 7;   // eight threads per row
   int c = 0;
-  for (; c < SLAR_KMAX && c < n; ++c) {
-    // pivot: largest remaining diagonal (lowest index on ties)
-    double m = -1.0; int mi = n;
-    for (int i = t; i < n; i += blockDim.x)
-      if (!taken[i] && (dres[i] > m)) { m = dres[i]; mi = i; }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double m2 = __shfl_xor(m, o, 64);
-      const int i2 = __shfl_xor(mi, o, 64);
-      if (m2 > m || (m2 == m && i2 < mi)) { m = m2; mi = i2; }
+  for (; c < EIG_CM && c < n; ++c) {
+    // pivot: largest remaining diagonal (lowest index on ties), one wave
+    if (t < 64) {
+      double m = -1.0;
+      int mi = n;
+      for (int i = t; i < n; i += 64)
+        if (!taken[i] && dres[i] > m) { m = dres[i]; mi = i; }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double m2 = __shfl_xor(m, o, 64);
+        const int i2 = __shfl_xor(mi, o, 64);
+        if (m2 > m || (m2 == m && i2 < mi)) { m = m2; mi = i2; }
+      }
+      if (t == 0) { s_piv = m; s_p = mi; }
     }
-    if ((t & 63) == 0) { red[t >> 6] = m; redi[t >> 6] = mi; }
     __syncthreads();
-    double dp = red[0];
-    int p = redi[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-      if (red[w] > dp || (red[w] == dp && redi[w] < p)) { dp = red[w]; p = redi[w]; }
-    __syncthreads();
+    const double dp = s_piv;
+    const int p = s_p;
     if (!(dp > stop) || p >= n) break;
     const double sq = sqrt(dp);
-    for (int i = t; i < n; i += blockDim.x) {
+    if (row < n) {
       double v = 0.0;
-      if (!taken[i] && i != p) {
-        v = G[(size_t)p * n + i];
-        for (int j = 0; j < c; ++j) v -= Lc[i][j] * Lc[p][j];
-        v /= sq;
+      for (int j = sub; j < c; j += 8) v += L[j * SLAR_NMAX + row] * L[j * SLAR_NMAX + p];
+      v += __shfl_xor(v, 1, 8);
+      v += __shfl_xor(v, 2, 8);
+      v += __shfl_xor(v, 4, 8);
+      if (sub == 0) {
+        double out = 0.0;
+        if (row == p) out = sq;
+        else if (!taken[row]) out = (G[(size_t)p * n + row] - v) / sq;
+        L[c * SLAR_NMAX + row] = out;
       }
-      if (i == p) v = sq;
-      Lc[i][c] = v;
     }
     __syncthreads();
-    for (int i = t; i < n; i += blockDim.x) {
-      if (i == p) { taken[i] = 1; dres[i] = 0.0; }
-      else if (!taken[i]) dres[i] = fmax(dres[i] - Lc[i][c] * Lc[i][c], 0.0);
+    if (t < n) {
+      if (t == p) { taken[t] = 1; dres[t] = 0.0; }
+      else if (!taken[t]) dres[t] = fmax(dres[t] - L[c * SLAR_NMAX + t] * L[c * SLAR_NMAX + t], 0.0);
     }
     __syncthreads();
   }
-  if (t == 0) ncols_s = c;
+  if (t < 64) {
+    double a = 0.0;
+    for (int i = t; i < n; i += 64) a += taken[i] ? 0.0 : dres[i];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (t == 0) { s_rest = a; s_nc = c; }
+  }
   __syncthreads();
-  const int nc = ncols_s;
+  const int nc = s_nc;
   const int kp = (nc + 1) & ~1;
-  for (int i = t; i < kp; i += blockDim.x) pairs[i] = i;
+  if (nc < kp)   // zero padding column
+    for (int i = t; i < n; i += blockDim.x) L[nc * SLAR_NMAX + i] = 0.0;
   __syncthreads();
-  const int npair = kp / 2;
-  int tm = 1;
-  if (npair > 0) { const int team = max(1, min(64, (int)blockDim.x / npair)); while (tm * 2 <= team) tm *= 2; }
-  const int pid = t / tm, lane = t % tm;
   const double floor_abs = 1e-22 * trace + 1e-300;   // columns below this are negligible
-  for (int sweep = 0; sweep < 30 && kp >= 2; ++sweep) {
-    if (t == 0) rotated = 0;
-    __syncthreads();
-    for (int step = 0; step < kp - 1; ++step) {
-      if (pid < npair) {
-        const int p = rr_player(pid, step, kp), q = rr_player(kp - 1 - pid, step, kp);
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int r = lane; r < n; r += tm) {
-          const double x = Lc[r][p], y = Lc[r][q];
-          al += x * x; be += y * y; ga += x * y;
-        }
-        for (int o = tm / 2; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, tm);
-          be += __shfl_xor(be, o, tm);
-          ga += __shfl_xor(ga, o, tm);
-        }
-        if (fabs(ga) > 1e-14 * sqrt(al * be) && sqrt(al * be) > floor_abs) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cc = 1.0 / sqrt(1.0 + tt * tt), sn = cc * tt;
-          for (int r = lane; r < n; r += tm) {
-            const double x = Lc[r][p], y = Lc[r][q];
-            Lc[r][p] = cc * x - sn * y;
-            Lc[r][q] = sn * x + cc * y;
-          }
-          if (lane == 0) rotated = 1;
-        }
-      }
-      __syncthreads();
-    }
-    if (!rotated) break;
-    __syncthreads();
-  }
+  const double orth = 4.0 * n * 2.220446049250313e-16;
+  if (kp >= 2) jacobi_cols<4, 0>(L, SLAR_NMAX, n, kp, nullptr, 0, 0, orth, floor_abs, 40, &s_rot);
   for (int j = t; j < kp; j += blockDim.x) {
     double acc = 0.0;
-    for (int r = 0; r < n; ++r) acc += Lc[r][j] * Lc[r][j];
+    for (int r = 0; r < n; ++r) acc += L[j * SLAR_NMAX + r] * L[j * SLAR_NMAX + r];
     nrm[j] = acc;
   }
   __syncthreads();
@@ -440,27 +464,23 @@ __global__ __launch_bounds__(1024) void k_eig_psd(EigBatch B) {
     if (j < nc) {
       const int cidx = order[j];
       const double s = sqrt(nrm[cidx]);
-      v = s > 0.0 ? Lc[r][cidx] / s : 0.0;
+      v = s > 0.0 ? L[cidx * SLAR_NMAX + r] / s : 0.0;
     }
     Uout[e] = v;
   }
-  for (int j = t; j < n; j += blockDim.x) lam[j] = (j < nc) ? nrm[order[j]] : 0.0;
-}
-
-hipError_t eig_sym(hipStream_t s, int n, const double* G, double* lam, double* Vwork,
-                   double* V) {
-  (void)Vwork;
-  EigBatch B{};
-  B.n[0] = n; B.G[0] = G; B.lam[0] = lam; B.U[0] = V;
-  k_eig_psd<<<1, 1024, 0, s>>>(B);
-  return hipGetLastError();
+  for (int j = t; j < n; j += blockDim.x)
+    lam[j] = (j < nc) ? nrm[order[j]] : (j == nc ? s_rest : 0.0);
 }
 
 // up to four independent eigenproblems in one launch (one block each)
 hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* const* G,
                          double* const* lam, double* const* V) {
+  if (count < 1 || count > 4) return hipErrorInvalidValue;
   EigBatch B{};
-  for (int i = 0; i < count; ++i) { B.n[i] = n[i]; B.G[i] = G[i]; B.lam[i] = lam[i]; B.U[i] = V[i]; }
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > SLAR_NMAX) return hipErrorInvalidValue;
+    B.n[i] = n[i]; B.G[i] = G[i]; B.lam[i] = lam[i]; B.U[i] = V[i];
+  }
   k_eig_psd<<<count, 1024, 0, s>>>(B);
   return hipGetLastError();
 }
