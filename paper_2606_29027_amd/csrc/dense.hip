@@ -203,18 +203,52 @@ __device__ __forceinline__ int rr_player(int pos, int step, int kp) {
 }
 
 // ------------------------------------------- one-sided Jacobi, team form
-// Columns of C (col-major in LDS, column c at C + c * ldc, n <= 32 RPL
+// Sum over the 16 lanes of a DPP row (every lane gets the total): quad
+// exchanges, then the half-row and row mirrors.  Pure VALU data movement,
+// so concurrent teams do not queue on the LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);   // row_half_mirror
+  v += dpp_move<0x140>(v);   // row_mirror
+  return v;
+}
+
+// Reciprocal and reciprocal square root from the hardware estimates with
+// two Newton steps each (the estimates carry about half the FP64 mantissa;
+// a Jacobi rotation needs c^2 + s^2 = 1 to rounding, not the exact angle).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  const double h = 0.5 * x * r;
+  return fma(r, fma(-h, r, 0.5), r);
+}
+
+// Columns of C (col-major in LDS, column c at C + c * ldc, n <= 16 RPL
 // rows, kp <= 64 columns, kp even) are orthogonalised by cyclic one-sided
 // Jacobi rotations in circle-method order; the same rotations are applied
-// to V (kv <= 32 VPL rows) when VPL > 0.  1024 threads: team = 32 lanes,
-// team i owns pair i of every step, so a step is one pass over registers
-// and one barrier.  A pair is rotated when |x.y| exceeds the rounding
-// level of its dot product (orth |x| |y|) and |x| |y| > floor_abs.
-// Returns the number of sweeps.
+// to V (kv <= 16 VPL rows) when VPL > 0.  512 threads: a team is one
+// 16-lane DPP row, team i owns pair i of every step, so a step is one pass
+// over registers and one barrier (eight waves keep the SIMDs' issue slots
+// for the active teams).  A pair is rotated when |x.y| exceeds
+// the rounding level of its dot product (orth |x| |y|) and
+// |x| |y| > floor_abs.  Returns the number of sweeps.
 template <int RPL, int VPL>
 __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv, int kv, double orth,
                            double floor_abs, int maxsweep, int* s_rot) {
-  const int team = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  const int team = threadIdx.x >> 4, lane = threadIdx.x & 15;
   const int npair = kp / 2;
   int sweep = 0;
   for (; sweep < maxsweep; ++sweep) {
@@ -223,32 +257,43 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
     bool rotated = false;
     for (int step = 0; step < kp - 1; ++step) {
       if (team < npair) {
-        const int p = rr_player(team, step, kp), q = rr_player(kp - 1 - team, step, kp);
+        // rr_player without a division: positions 1 .. kp-1 rotate by step
+        int pp = team - 1 + step, qq = kp - 2 - team + step;
+        pp -= (pp >= kp - 1) ? kp - 1 : 0;
+        qq -= (qq >= kp - 1) ? kp - 1 : 0;
+        const int p = (team == 0) ? 0 : 1 + pp;
+        const int q = 1 + qq;
         double* cp = C + (size_t)p * ldc;
         double* cq = C + (size_t)q * ldc;
         double x[RPL], y[RPL];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
-          const int r = lane + 32 * i;
+          const int r = lane + 16 * i;
           x[i] = (r < n) ? cp[r] : 0.0;
           y[i] = (r < n) ? cq[r] : 0.0;
           al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i];
         }
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, 32);
-          be += __shfl_xor(be, o, 32);
-          ga += __shfl_xor(ga, o, 32);
-        }
-        const double ab = sqrt(al * be);
-        if (fabs(ga) > orth * ab && ab > floor_abs) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+        al = row16_sum(al);
+        be = row16_sum(be);
+        ga = row16_sum(ga);
+        const double ab2 = al * be;
+        if (ga * ga > orth * orth * ab2 && ab2 > floor_abs * floor_abs) {
+          const double zeta = (be - al) * rcp_nr(2.0 * ga);
+          const double az = fabs(zeta);
+          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)); 1 / (2 zeta) for huge |zeta|
+          double tt;
+          if (az < 1e100) {
+            const double z2 = fma(zeta, zeta, 1.0);
+            tt = rcp_nr(az + z2 * rsq_nr(z2));
+          } else {
+            tt = 0.5 * rcp_nr(az);
+          }
+          tt = (zeta >= 0.0) ? tt : -tt;
+          const double c = rsq_nr(fma(tt, tt, 1.0)), sn = c * tt;
 #pragma unroll
           for (int i = 0; i < RPL; ++i) {
-            const int r = lane + 32 * i;
+            const int r = lane + 16 * i;
             if (r < n) {
               cp[r] = c * x[i] - sn * y[i];
               cq[r] = sn * x[i] + c * y[i];
@@ -259,7 +304,7 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
             double* vq = V + (size_t)q * ldv;
 #pragma unroll
             for (int i = 0; i < (VPL > 0 ? VPL : 1); ++i) {
-              const int r = lane + 32 * i;
+              const int r = lane + 16 * i;
               if (r < kv) {
                 const double vx = vp[r], vy = vq[r];
                 vp[r] = c * vx - sn * vy;
@@ -286,14 +331,14 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
 // singular vectors).
 constexpr int SVD_KM = 64;
 
-__global__ __launch_bounds__(1024) void k_svd_jacobi(int k, const double* __restrict__ Min,
+__global__ __launch_bounds__(512) void k_svd_jacobi(int k, const double* __restrict__ Min,
                                                     double* __restrict__ W, double* __restrict__ sv,
                                                     double* __restrict__ Z) {
   __shared__ double A[SVD_KM * SVD_KM];   // column c at A + c * SVD_KM
   __shared__ double V[SVD_KM * SVD_KM];
   __shared__ double nrm[SVD_KM];
   __shared__ int order[SVD_KM];
-  __shared__ double red[16];
+  __shared__ double red[8];
   __shared__ int s_rot;
   const int t = threadIdx.x;
   const int kp = (k + 1) & ~1;   // even count (a zero column pads odd k)
@@ -309,10 +354,10 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi(int k, const double* __rest
   if ((t & 63) == 0) red[t >> 6] = part;
   __syncthreads();
   double fro = 0.0;
-  for (int w = 0; w < 16; ++w) fro += red[w];
+  for (int w = 0; w < 8; ++w) fro += red[w];
   const double floor_abs = 1e-300 + 1e-22 * fro;   // columns below this are negligible
   const double orth = 4.0 * kp * 2.220446049250313e-16;
-  jacobi_cols<2, 2>(A, SVD_KM, kp, kp, V, SVD_KM, kp, orth, floor_abs, 60, &s_rot);
+  jacobi_cols<4, 4>(A, SVD_KM, kp, kp, V, SVD_KM, kp, orth, floor_abs, 60, &s_rot);
   for (int c = t; c < kp; c += blockDim.x) {
     double acc = 0.0;
     for (int r = 0; r < kp; ++r) acc += A[c * SVD_KM + r] * A[c * SVD_KM + r];
@@ -338,7 +383,7 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi(int k, const double* __rest
 
 hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z) {
   if (k < 1 || k > SVD_KM) return hipErrorInvalidValue;
-  k_svd_jacobi<<<1, 1024, 0, s>>>(k, M, W, sv, Z);
+  k_svd_jacobi<<<1, 512, 0, s>>>(k, M, W, sv, Z);
   return hipGetLastError();
 }
 
@@ -348,7 +393,7 @@ hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* s
 //  1. pivoted Cholesky G ~ L L^T, L (n x c) built column by column in LDS
 //     (pivot = largest remaining diagonal, lowest index on ties), stopping
 //     when the remaining diagonal drops below 1e-30 trace or after 64
-//     columns; eight threads share each row's inner product;
+//     columns; four threads share each row's inner product;
 //  2. one-sided Jacobi on the columns of L: the rotated, normalised
 //     columns are the eigenvectors of L L^T and their squared norms the
 //     eigenvalues.
@@ -364,7 +409,7 @@ struct EigBatch {
   double* U[4];
 };
 
-__global__ __launch_bounds__(1024) void k_eig_psd(EigBatch B) {
+__global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
   const int n = B.n[blockIdx.x];
   const double* __restrict__ G = B.G[blockIdx.x];
   double* __restrict__ lam = B.lam[blockIdx.x];
@@ -389,7 +434,7 @@ __global__ __launch_bounds__(1024) void k_eig_psd(EigBatch B) {
   __syncthreads();
   const double trace = s_trace;
   const double stop = 1e-30 * trace + 1e-300;
-  const int row = t >> 3, sub = t & 7;   // eight threads per row
+  const int row = t >> 2, sub = t & 3;   // four threads per row
   int c = 0;
   for (; c < EIG_CM && c < n; ++c) {
     // pivot: largest remaining diagonal (lowest index on ties), one wave
@@ -412,10 +457,9 @@ __global__ __launch_bounds__(1024) void k_eig_psd(EigBatch B) {
     const double sq = sqrt(dp);
     if (row < n) {
       double v = 0.0;
-      for (int j = sub; j < c; j += 8) v += L[j * SLAR_NMAX + row] * L[j * SLAR_NMAX + p];
-      v += __shfl_xor(v, 1, 8);
-      v += __shfl_xor(v, 2, 8);
-      v += __shfl_xor(v, 4, 8);
+      for (int j = sub; j < c; j += 4) v += L[j * SLAR_NMAX + row] * L[j * SLAR_NMAX + p];
+      v += dpp_move<0xB1>(v);
+      v += dpp_move<0x4E>(v);
       if (sub == 0) {
         double out = 0.0;
         if (row == p) out = sq;
@@ -444,7 +488,7 @@ __global__ __launch_bounds__(1024) void k_eig_psd(EigBatch B) {
   __syncthreads();
   const double floor_abs = 1e-22 * trace + 1e-300;   // columns below this are negligible
   const double orth = 4.0 * n * 2.220446049250313e-16;
-  if (kp >= 2) jacobi_cols<4, 0>(L, SLAR_NMAX, n, kp, nullptr, 0, 0, orth, floor_abs, 40, &s_rot);
+  if (kp >= 2) jacobi_cols<8, 0>(L, SLAR_NMAX, n, kp, nullptr, 0, 0, orth, floor_abs, 40, &s_rot);
   for (int j = t; j < kp; j += blockDim.x) {
     double acc = 0.0;
     for (int r = 0; r < n; ++r) acc += L[j * SLAR_NMAX + r] * L[j * SLAR_NMAX + r];
@@ -481,7 +525,7 @@ hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* c
     if (n[i] < 1 || n[i] > SLAR_NMAX) return hipErrorInvalidValue;
     B.n[i] = n[i]; B.G[i] = G[i]; B.lam[i] = lam[i]; B.U[i] = V[i];
   }
-  k_eig_psd<<<count, 1024, 0, s>>>(B);
+  k_eig_psd<<<count, 512, 0, s>>>(B);
   return hipGetLastError();
 }
 
