@@ -25,6 +25,7 @@ struct AcaCtl {
 constexpr int ACA_MAXBLK = 1024;   // partial slots
 
 // Everything one cross approximation reads or writes (one instance).
+// Fibers have at most 128^2 samples, so at most 256 blocks of 64.
 struct AcaInst {
   GridDev g;
   AdvDev a;
@@ -82,15 +83,20 @@ __device__ __forceinline__ void unravel_v(const GridDev& g, int J, int* gi) {
 
 // Partial-sum layout (doubles): part[q * ACA_MAXBLK + b]
 //   row kernel: q = 0 block max|r|, q = 1 block candidate index,
-//               q = 2 + l  v_l . r  (l <= k)
+//               q = 2 + l  v_l . r  (l <= k < 64), q = PVAL candidate |r|
 //   col kernel: same with base PCOL
+//   q = GSUM: sum over row blocks of v_l . r at slot l (written by the
+//   column kernel, read by the bookkeeping kernel)
 constexpr int PCOL = SLAR_KMAX + 4;
+constexpr int PVAL = PCOL - 1;
+constexpr int GSUM = 66;
 
-// Per-block max of |x| (entries with skip() excluded) and the lowest index
-// in the block whose |x| is within the tie tolerance of that block max.
+// Per-block max of |x| (entries with skip() excluded), the lowest index in
+// the block whose |x| is within the tie tolerance of that block max, and
+// |x| at that index (-1 when the block has no eligible entry).
 template <typename Skip>
 __device__ void block_candidate(const double* xs, int ns, int base, Skip skip, double* red, int* redi,
-                                double* out_max, double* out_idx) {
+                                double* out_max, double* out_idx, double* out_val) {
   const int t = threadIdx.x;
   double v = -1.0;
   if (t < ns && !skip(base + t)) v = fabs(xs[t]);
@@ -101,17 +107,23 @@ __device__ void block_candidate(const double* xs, int ns, int base, Skip skip, d
   if ((t & 63) == 0) redi[t >> 6] = cand;
   __syncthreads();
   if (t == 0) {
+    const int c = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
     *out_max = m;
-    *out_idx = (double)min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+    *out_idx = (double)c;
+    *out_val = (c < base + ns) ? fabs(xs[c - base]) : -1.0;
   }
   __syncthreads();
 }
 
 // Global pivot from per-block candidates: lowest index whose |x| is within
 // the tie tolerance of the global maximum M (M < 0: nothing eligible).
+// pmax / pidx / pval are the per-block maximum, candidate index and
+// candidate value; only when the first qualifying block's candidate falls
+// below the tolerance is that block's range of x rescanned.
 template <typename Skip>
-__device__ int pivot_from_parts(const double* x, const double* pmax, const double* pidx, int nb,
-                                int n, Skip skip, double* red, int* redi, double* M_out) {
+__device__ int pivot_from_parts(const double* x, const double* pmax, const double* pidx,
+                                const double* pval, int nb, int n, Skip skip, double* red, int* redi,
+                                double* M_out) {
   const int t = threadIdx.x;
   double m = -1.0;
   for (int b = t; b < nb; b += blockDim.x) m = fmax(m, pmax[b]);
@@ -129,7 +141,7 @@ __device__ int pivot_from_parts(const double* x, const double* pmax, const doubl
   __syncthreads();
   if (bb >= nb) return n;
   const int cand = (int)pidx[bb];
-  if (cand < n && fabs(x[cand]) >= thr) return cand;
+  if (cand < n && pval[bb] >= thr) return cand;
   // the block maximum is close to M but below it: rescan that block's range
   int best = n;
   const int e = bb * FS_SAMPLES + t;
@@ -232,7 +244,8 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
       }
     }
   }
-  block_candidate(rres, ns, J0, NoSkip{}, red, redi, &part[tile], &part[ACA_MAXBLK + tile]);
+  block_candidate(rres, ns, J0, NoSkip{}, red, redi, &part[tile], &part[ACA_MAXBLK + tile],
+                  &part[(size_t)PVAL * ACA_MAXBLK + tile]);
 }
 
 template <typename T, int W, int DX>
@@ -274,9 +287,22 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
   // column pivot of the row residual (every block computes the same)
   double M;
   const double* vk = V + (size_t)k * Nv;
-  const int j = pivot_from_parts(vk, part, part + ACA_MAXBLK, nbrow, Nv, NoSkip{}, red, redi, &M);
+  const int j = pivot_from_parts(vk, part, part + ACA_MAXBLK, part + (size_t)PVAL * ACA_MAXBLK, nbrow, Nv,
+                                 NoSkip{}, red, redi, &M);
   const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
   if (M == 0.0 || M <= thr || j >= Nv) return;   // row already reproduced
+  // finish the row-fiber dot products for the bookkeeping launch:
+  // gv[l] = sum_b (v_l . r)_b, block `tile` takes l = tile, tile + nbcol, ...
+  for (int l = tile; l <= k; l += I.nbcol) {
+    const double* q = part + (size_t)(2 + l) * ACA_MAXBLK;
+    double acc = 0.0;
+    for (int b = t; b < nbrow; b += FS_THREADS) acc += q[b];
+    acc = wave_sum(acc);
+    if (ln == 0) acc4[wv][0] = acc;
+    __syncthreads();
+    if (t == 0) part[(size_t)GSUM * ACA_MAXBLK + l] = ((acc4[0][0] + acc4[1][0]) + acc4[2][0]) + acc4[3][0];
+    __syncthreads();
+  }
   const double piv = vk[j];
   double vj[ACA_LREG];
 #pragma unroll
@@ -324,11 +350,18 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
       }
     }
   }
-  block_candidate(ures, ns, I0, SkipUsed{used, i}, red, redi, &pc[tile], &pc[ACA_MAXBLK + tile]);
+  block_candidate(ures, ns, I0, SkipUsed{used, i}, red, redi, &pc[tile], &pc[ACA_MAXBLK + tile],
+                  &pc[(size_t)PVAL * ACA_MAXBLK + tile]);
 }
 
 // One block: bookkeeping of the iteration, stopping test, next row pivot,
 // and the random-probe check whenever the approximation wants to stop.
+// Every partial the iteration needs (block maxima, candidates and their
+// values of both fibers, and the per-block dot products) is loaded in one
+// pass of independent loads; the rest works from LDS.
+constexpr int FIN_NB = 256;   // blocks per fiber staged in LDS
+static_assert(FIN_NB * FS_SAMPLES >= SLAR_NMAX * SLAR_NMAX, "every fiber fits the staged partials");
+
 template <typename T, int W, int DX>
 __device__ void aca_fin_body(const AcaInst& I) {
   const GridDev& g = I.g;
@@ -340,19 +373,28 @@ __device__ void aca_fin_body(const AcaInst& I) {
   const double* __restrict__ U = I.U;
   const double* __restrict__ V = I.V;
   unsigned char* __restrict__ used = I.used;
-  double* __restrict__ part = I.part;
+  const double* __restrict__ part = I.part;
   const int nbrow = I.nbrow, nbcol = I.nbcol, nprobe = I.nprobe;
   const int* __restrict__ probes = I.probes;
   __shared__ FsLds<W, DX> L;
   __shared__ double red[4];
   __shared__ int redi[4];
   __shared__ double sgv[SLAR_KMAX + 1], sgu[SLAR_KMAX + 1];
+  __shared__ double rmax_[FIN_NB], ridx_[FIN_NB], rval_[FIN_NB];
+  __shared__ double cmax_[FIN_NB], cidx_[FIN_NB], cval_[FIN_NB];
   __shared__ double res[1024];
   __shared__ int pi[1024];
   __shared__ int s_phase, s_i, s_k, s_stop;
   __shared__ double s_tol, s_norm2;
   const int t = threadIdx.x;
   if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; s_tol = ctl->tol; s_norm2 = ctl->norm2; }
+  const double* pc = part + (size_t)PCOL * ACA_MAXBLK;
+  if (t < nbrow) {
+    rmax_[t] = part[t]; ridx_[t] = part[ACA_MAXBLK + t]; rval_[t] = part[(size_t)PVAL * ACA_MAXBLK + t];
+  }
+  if (t < nbcol) {
+    cmax_[t] = pc[t]; cidx_[t] = pc[ACA_MAXBLK + t]; cval_[t] = pc[(size_t)PVAL * ACA_MAXBLK + t];
+  }
   __syncthreads();
   if (s_phase != ACA_RUN) return;
   const int i = s_i;
@@ -360,7 +402,7 @@ __device__ void aca_fin_body(const AcaInst& I) {
   const int Nx = g.nx, Nv = g.nv;
   double M;
   const double* vk = V + (size_t)k * Nv;
-  const int j = pivot_from_parts(vk, part, part + ACA_MAXBLK, nbrow, Nv, NoSkip{}, red, redi, &M);
+  const int j = pivot_from_parts(vk, rmax_, ridx_, rval_, nbrow, Nv, NoSkip{}, red, redi, &M);
   const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
   const bool zero_row = (M == 0.0 || M <= thr || j >= Nv);
   if (t == 0) {
@@ -369,18 +411,71 @@ __device__ void aca_fin_body(const AcaInst& I) {
     ctl->samples += Nv;
   }
   if (!zero_row) {
-    double* pc = part + (size_t)PCOL * ACA_MAXBLK;
-    block_sum_parts(part + ACA_MAXBLK, nbrow, k + 1, sgv);
-    block_sum_parts(pc + ACA_MAXBLK, nbcol, k + 1, sgu);
+    // gv[l]: reduced by the column launch; gu[l] = sum_b (u_l . u)_b here:
+    // wave w takes l = w + 4 m (m < 16), lanes run over the blocks, all
+    // loads are issued before the sums, then a butterfly reduce-scatter
+    // leaves the total of value m(lane) in every lane
+    {
+      const int wv = t >> 6, ln = t & 63;
+      double acc[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int l = min(wv + 4 * m, 63);
+        const double* q = pc + (size_t)(2 + l) * ACA_MAXBLK;
+        double a4 = 0.0;
+#pragma unroll
+        for (int i4 = 0; i4 < FIN_NB / 64; ++i4) {
+          const int b = ln + 64 * i4;
+          const double v = q[b];
+          a4 += (b < nbcol) ? v : 0.0;
+        }
+        acc[m] = (wv + 4 * m <= k) ? a4 : 0.0;
+      }
+      // reduce-scatter: after the steps lane ln holds the sum of value
+      // 8 b5 + 4 b4 + 2 b3 + b2 (b_i = bit i of ln) over all 64 lanes
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const bool hi = ln & 32;
+        const double send = hi ? acc[m] : acc[m + 8];
+        const double keep = hi ? acc[m + 8] : acc[m];
+        acc[m] = keep + __shfl_xor(send, 32, 64);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bool hi = ln & 16;
+        const double send = hi ? acc[m] : acc[m + 4];
+        const double keep = hi ? acc[m + 4] : acc[m];
+        acc[m] = keep + __shfl_xor(send, 16, 64);
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const bool hi = ln & 8;
+        const double send = hi ? acc[m] : acc[m + 2];
+        const double keep = hi ? acc[m + 2] : acc[m];
+        acc[m] = keep + __shfl_xor(send, 8, 64);
+      }
+      {
+        const bool hi = ln & 4;
+        const double send = hi ? acc[0] : acc[1];
+        const double keep = hi ? acc[1] : acc[0];
+        acc[0] = keep + __shfl_xor(send, 4, 64);
+      }
+      acc[0] += __shfl_xor(acc[0], 2, 64);
+      acc[0] += __shfl_xor(acc[0], 1, 64);
+      const int m = ((ln >> 5) & 1) * 8 + ((ln >> 4) & 1) * 4 + ((ln >> 3) & 1) * 2 + ((ln >> 2) & 1);
+      const int l = wv + 4 * m;
+      if ((ln & 3) == 0 && l <= k) sgu[l] = acc[0];
+      if (t <= k) sgv[t] = part[(size_t)GSUM * ACA_MAXBLK + t];
+    }
     __syncthreads();
     if (t < 64) {
-      // cross terms sum_{l<k} (u_l . u_k)(v_l . v_k), k <= 64
+      // cross terms sum_{l<k} (u_l . u_k)(v_l . v_k), k < 64
       double c = (t < k) ? sgu[t] * sgv[t] : 0.0;
       c = wave_sum(c);
       if (t == 0) {
         ctl->samples += Nx;
         ctl->j = j;
-        ctl->pivot = vk[j];
+        ctl->pivot = M;   // row residual maximum (diagnostic; the column kernel reads v_k[j])
         const double nk = sgu[k] * sgv[k];
         const double norm2 = s_norm2 + 2.0 * c + nk;
         ctl->norm2 = norm2;
@@ -398,7 +493,7 @@ __device__ void aca_fin_body(const AcaInst& I) {
       // next row pivot: unused row maximising |u_k| (block candidates)
       const double* uk = U + (size_t)(k - 1) * Nx;
       double Mu;
-      const int ip = pivot_from_parts(uk, pc, pc + ACA_MAXBLK, nbcol, Nx, SkipUsed{used, i}, red, redi, &Mu);
+      const int ip = pivot_from_parts(uk, cmax_, cidx_, cval_, nbcol, Nx, SkipUsed{used, i}, red, redi, &Mu);
       if (t == 0) {
         if (!(Mu >= 0.0) || ip >= Nx) ctl->phase = ACA_DONE;
         else ctl->i = ip;
