@@ -2,6 +2,8 @@
 // summed over a batch in a fixed order), Cholesky-QR helpers, one-sided
 // Jacobi SVD and two-sided Jacobi symmetric eigensolver.  All single-block
 // factorizations keep their matrix in LDS (gfx950: 160 KB per CU).
+#include <algorithm>
+
 #include "slar_internal.h"
 #include "dense.h"
 
@@ -102,42 +104,132 @@ hipError_t gemm_f64_sumbatch(hipStream_t s, Workspace* ws, bool ta, bool tb, int
   return hipGetLastError();
 }
 
-// Gram G = A A^T for A = [k][n] row vectors (long n), split over n.
+// ------------------------------------------------------------ Gram
+// G = A A^T for A with k <= 128 rows and a long column range, element
+// (i, j) read through an addressing functor.  Stage 1: block b takes the
+// 32-column chunks b, b + grid, ..., stages each chunk (k x 32) in LDS and
+// accumulates its k x k partial in registers (16 x 16 threads, MT x MT
+// outputs each); stage 2 sums the partials in block order.  Both triangles
+// are computed with the same products in the same order, so G is exactly
+// symmetric.
+constexpr int GR_C = 32;
+
+struct RowMajor {
+  const double* A;
+  int lda;
+  __device__ double operator()(int i, int j) const { return A[(long long)i * lda + j]; }
+};
+// mode-2 unfolding of a frame Xs[(i1 * nb + i2) * r + c]: row i2, column
+// j = i1 * r + c
+struct Mode2 {
+  const double* X;
+  int nb, r;
+  __device__ double operator()(int i, int j) const {
+    const int i1 = j / r, c = j - i1 * r;
+    return X[((long long)i1 * nb + i) * r + c];
+  }
+};
+
+template <int MT, class Addr>
+__global__ __launch_bounds__(256) void k_gram_part(int k, int n, Addr A, double* __restrict__ part) {
+  __shared__ double S[16 * MT][GR_C + 1];
+  const int t = threadIdx.x;
+  const int tr = t >> 4, tc = t & 15;
+  double acc[MT][MT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < MT; ++b) acc[a][b] = 0.0;
+  const int nchunk = (n + GR_C - 1) / GR_C;
+  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int j0 = ch * GR_C;
+    __syncthreads();
+    for (int e = t; e < 16 * MT * GR_C; e += 256) {
+      const int i = e / GR_C, c = e - (e / GR_C) * GR_C;
+      S[i][c] = (i < k && j0 + c < n) ? A(i, j0 + c) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < GR_C; ++c) {
+      double x[MT], y[MT];
+#pragma unroll
+      for (int a = 0; a < MT; ++a) { x[a] = S[tr + 16 * a][c]; y[a] = S[tc + 16 * a][c]; }
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < MT; ++b) acc[a][b] = fma(x[a], y[b], acc[a][b]);
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * k * k;
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < MT; ++b) {
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      if (i < k && j < k) out[i * k + j] = acc[a][b];
+    }
+}
+
+// 64 outputs per block, four waves each summing every fourth partial
+// (coalesced over the outputs), combined in a fixed order.
+__global__ __launch_bounds__(256) void k_gram_sum(int kk, int nblk, const double* __restrict__ part,
+                                                  double* __restrict__ G) {
+  __shared__ double q4[4][64];
+  const int t = threadIdx.x, ln = t & 63, w = t >> 6;
+  const int e = blockIdx.x * 64 + ln;
+  double acc = 0.0;
+  if (e < kk) {
+#pragma unroll 8
+    for (int b = w; b < nblk; b += 4) acc += part[(size_t)b * kk + e];
+  }
+  q4[w][ln] = acc;
+  __syncthreads();
+  if (w == 0 && e < kk) G[e] = ((q4[0][ln] + q4[1][ln]) + q4[2][ln]) + q4[3][ln];
+}
+
+template <class Addr>
+static hipError_t gram_launch(hipStream_t s, Workspace* ws, int k, int n, Addr A, double* G) {
+  if (k < 1 || k > 128 || n < 1) return hipErrorInvalidValue;
+  const int nchunk = (n + GR_C - 1) / GR_C;
+  int nblk = std::min(nchunk, 128);
+  while (nblk > 1 && (size_t)nblk * k * k > ws->dwork_elems) nblk /= 2;
+  if ((size_t)nblk * k * k > ws->dwork_elems) return hipErrorInvalidValue;
+  if (k <= 64) k_gram_part<4><<<nblk, 256, 0, s>>>(k, n, A, ws->dwork);
+  else k_gram_part<8><<<nblk, 256, 0, s>>>(k, n, A, ws->dwork);
+  k_gram_sum<<<(k * k + 63) / 64, 256, 0, s>>>(k * k, nblk, ws->dwork, G);
+  return hipGetLastError();
+}
+
+// Gram G = A A^T for A = [k][n] row vectors (long n).
 hipError_t gram_rows(hipStream_t s, Workspace* ws, int k, int n, const double* A, int lda,
                      double* G) {
-  int chunk = 512;
-  int batch = (n + chunk - 1) / chunk;
-  while ((size_t)batch * k * k > ws->dwork_elems && chunk < n) { chunk *= 2; batch = (n + chunk - 1) / chunk; }
-  if (batch * chunk != n) {
-    // ragged tail: sum the full chunks, then add the tail block
-    const int full = n / chunk;
-    const int tail = n - full * chunk;
-    if (full > 0) {
-      hipError_t e = gemm_f64_sumbatch(s, ws, false, true, k, k, chunk, A, lda, chunk, A, lda,
-                                       chunk, G, k, full);
-      if (e != hipSuccess) return e;
-    }
-    return gemm_f64(s, false, true, k, k, tail, 1.0, A + (long long)full * chunk, lda, 0,
-                    A + (long long)full * chunk, lda, 0, full > 0 ? 1.0 : 0.0, G, k, 0, 1);
-  }
-  return gemm_f64_sumbatch(s, ws, false, true, k, k, chunk, A, lda, chunk, A, lda, chunk, G, k,
-                           batch);
+  return gram_launch(s, ws, k, n, RowMajor{A, lda}, G);
+}
+
+// Gram of the mode-2 unfolding of X[(i1 * nb + i2) * r + c] (i1 < na):
+// G[i2][i2'] = sum_{i1, c} X[i1, i2, c] X[i1, i2', c].
+hipError_t gram_mode2(hipStream_t s, Workspace* ws, int na, int nb, int r, const double* X, double* G) {
+  return gram_launch(s, ws, nb, na * r, Mode2{X, nb, r}, G);
 }
 
 // --------------------------------------------------- Cholesky-QR helpers
 // From Gram G (k x k): column scaling d = sqrt(diag G), Cholesky of
 // D^-1 G D^-1 = L L^T.  Writes Linv_scaled = L^-1 D^-1 (k x k, lower) and
 // R = L^T D (upper).  A zero column keeps d = 1 and a unit pivot.
-__global__ void k_chol_inv(int k, const double* __restrict__ G, double* __restrict__ Linv,
-                           double* __restrict__ R, const double* __restrict__ Rprev) {
+__global__ __launch_bounds__(256) void k_chol_inv(int k, const double* __restrict__ G,
+                                                  double* __restrict__ Linv, double* __restrict__ R,
+                                                  const double* __restrict__ Rprev) {
   __shared__ double L[SLAR_KMAX][SLAR_KMAX + 1];
   __shared__ double Li[SLAR_KMAX][SLAR_KMAX + 1];
+  __shared__ double Rp[SLAR_KMAX][SLAR_KMAX + 1];
   __shared__ double d[SLAR_KMAX];
   const int t = threadIdx.x;
   for (int i = t; i < k; i += blockDim.x) {
     const double g = G[i * k + i];
     d[i] = g > 0.0 ? sqrt(g) : 1.0;
   }
+  if (Rprev != nullptr)
+    for (int e = t; e < k * k; e += blockDim.x) Rp[e / k][e % k] = Rprev[e];
   __syncthreads();
   for (int e = t; e < k * k; e += blockDim.x) {
     const int i = e / k, j = e % k;
@@ -146,16 +238,18 @@ __global__ void k_chol_inv(int k, const double* __restrict__ G, double* __restri
   __syncthreads();
   // right-looking Cholesky (lower)
   for (int c = 0; c < k; ++c) {
-    if (t == 0) {
-      double v = L[c][c];
-      L[c][c] = v > 1e-300 ? sqrt(v) : 1.0;
-    }
+    const double v = L[c][c];
+    const double dc = v > 1e-300 ? sqrt(v) : 1.0;
     __syncthreads();
-    for (int i = c + 1 + t; i < k; i += blockDim.x) L[i][c] /= L[c][c];
+    if (t == 0) L[c][c] = dc;
+    for (int i = c + 1 + t; i < k; i += blockDim.x) L[i][c] /= dc;
     __syncthreads();
-    for (int e = t; e < (k - c - 1) * (k - c - 1); e += blockDim.x) {
-      const int i = c + 1 + e / (k - c - 1), j = c + 1 + e % (k - c - 1);
-      if (j <= i) L[i][j] -= L[i][c] * L[j][c];
+    // trailing update of the lower triangle: eight threads per row
+    const int m = k - c - 1;
+    for (int w = t; w < m * 8; w += blockDim.x) {
+      const int i = c + 1 + (w >> 3);
+      const double lic = L[i][c];
+      for (int j = c + 1 + (w & 7); j <= i; j += 8) L[i][j] -= lic * L[j][c];
     }
     __syncthreads();
   }
@@ -174,15 +268,11 @@ __global__ void k_chol_inv(int k, const double* __restrict__ G, double* __restri
     const int i = e / k, j = e % k;
     Linv[e] = Li[i][j] / d[j];
     // R = L^T D (upper), optionally times Rprev (R_total = R * Rprev)
-    double r = (i <= j) ? L[j][i] * d[j] : 0.0;
-    if (Rprev == nullptr) R[e] = r;
-  }
-  if (Rprev != nullptr) {
-    __syncthreads();
-    for (int e = t; e < k * k; e += blockDim.x) {
-      const int i = e / k, j = e % k;
+    if (Rprev == nullptr) {
+      R[e] = (i <= j) ? L[j][i] * d[j] : 0.0;
+    } else {
       double acc = 0.0;
-      for (int m = i; m < k; ++m) acc += L[m][i] * d[m] * Rprev[m * k + j];
+      for (int m = i; m < k; ++m) acc += L[m][i] * d[m] * Rp[m][j];
       R[e] = acc;
     }
   }

@@ -104,8 +104,7 @@ static hipError_t side_grams(hipStream_t s, Workspace* ws, const double* frame, 
                              int r, const double* sv_dev, double* Xs, double* Ga, double* Gb) {
   HIP_CHK(copy2d(s, na * nb, r, frame, r, Xs, r, sv_dev));
   HIP_CHK(gram_rows(s, ws, na, nb * r, Xs, nb * r, Ga));
-  return gemm_f64_sumbatch(s, ws, false, true, nb, nb, r, Xs, r, (long long)nb * r, Xs, r,
-                           (long long)nb * r, Gb, nb, na);
+  return gram_mode2(s, ws, na, nb, r, Xs, Gb);
 }
 
 // Leaf bases (leading eigenvectors, sign rule) and the transfer tensor of
