@@ -29,6 +29,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_k_aca_col_stronglandau2d_128.md")
+# sources that define the column-fiber kernel; the counter-measured traffic
+# is reported only for the source state it was measured on
+KERNEL_SOURCES = ["aca.h", "frame_sampler.h", "slar_internal.h", "cross.hip"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_29027_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per column-fiber launch from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    try:
+        vals = {}
+        with open(TRAFFIC_SUMMARY) as fh:
+            for line in fh:
+                if ":" in line and line.split(":")[0].strip() in ("source_sha256", "traffic_bytes_per_launch"):
+                    k, v = line.split(":", 1)
+                    vals[k.strip()] = v.strip().strip("`")
+        if vals.get("source_sha256") != kernel_source_hash():
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -54,8 +84,10 @@ def parse():
 
 def cpu_baseline(p, budget_s: float):
     """The oracle's SL-FD entry evaluation (HT contraction of section 3.1) on
-    whole row fibers of the first cross approximation of the workload,
-    evaluated until about ``budget_s`` seconds of CPU time are spent."""
+    whole row fibers of a 128^4 tensor at the workload's rank (random HT,
+    all six ranks 60, seed 11), first RK sub-flow (tau = dt / 3) in the
+    field of the initial state, until about ``budget_s`` seconds of CPU
+    time are spent."""
     import slar_inputs as SI
     from oracle import step as ST
     try:
@@ -64,21 +96,22 @@ def cpu_baseline(p, budget_s: float):
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
     o = ST.Oracle(p)
-    F0 = SI.initial_ht(p)
-    E = o.efield(F0)
-    Nv = int(np.prod(p.n[p.dx:]))
+    E = o.efield(SI.initial_ht(p))
+    r = min(p.rmax, 60)
+    F = SI.random_ht(4, p.n, (r,) * 6, seed=11)
+    Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
     done = 0
     t0 = time.perf_counter()
     fib = 0
     while time.perf_counter() - t0 < budget_s:
-        idx = o._idx(np.full(Nv, fib * 997 % int(np.prod(p.n[: p.dx]))), np.arange(Nv))
-        o.entries(F0, idx, 2, p.dt / 3.0, 1.0, E)
+        idx = o._idx(np.full(Nv, fib * 997 % Nx), np.arange(Nv))
+        o.entries(F, idx, 2, p.dt / 3.0, 1.0, E)
         done += Nv
         fib += 1
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "entries/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{fib} row fibers ({done} SL-FD entries) of the first RK stage of the "
-                      f"{p.n[0]}^4 workload, FP64 NumPy"}
+            "sample": f"{fib} row fibers ({done} SL-FD entries) of a rank-{r} random HT on the "
+                      f"{p.n[0]}^4 grid, first RK sub-flow of the workload, FP64 NumPy"}
 
 
 def batched_main(args):
@@ -213,7 +246,8 @@ def main():
     ms, nl, by = tim[which + "_ms"], tim[which + "_launches"], tim[which + "_bytes"]
     achieved = (by / nl) / (ms / nl * 1e-3) / 1e9 if nl > 0 and ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic() if which == "col" else None,
                 "kernel": "k_aca_row" if which == "row" else "k_aca_col",
                 "avg_launch_us": 1e3 * ms / nl if nl else None, "launches": int(nl),
                 "algorithmic_bytes_per_launch": by / nl if nl else None}

@@ -134,8 +134,8 @@ slar_status slar_workspace_destroy(slar_workspace* ws);
  * contractions up to the root, O(d r^3) per point (section 3.1, eqs.
  * (1d_quadratic_interp_weight), (tp_interp)).
  *   idx : [n][d] int32 grid multi-indices (0-based) of the points to update
- *   out : [n] values f(x_i, t+tau) = f(x*, t), dtype of F (FP32 contracts
- *         on the matrix cores with FP32 accumulation; feet are FP64).
+ *   out : [n] values f(x_i, t+tau) = f(x*, t), dtype of F (contractions
+ *         in that precision; feet are FP64).
  * Supports order 3 and 5 for d = 2, order 3 for d = 4; ranks <= 64.          */
 slar_status slar_ht_sample(const slar_grid* g, const slar_ht* F, const slar_adv* a, int64_t n,
                            const int32_t* idx, void* out, hipStream_t stream);
@@ -267,13 +267,14 @@ slar_status slar_cnn_train_step(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, 
 slar_status slar_record_krylov(slar_workspace* ws, float* features, float* targets, int32_t capacity);
 int32_t slar_recorded_pairs(const slar_workspace* ws);
 
-/* In-stream timing of the two sampling kernels of slar_cross_update (HIP
- * events recorded around every row-fiber and column-fiber launch while
- * enabled; enabling clears the counters).  slar_timing_read fills host
- * out[8] = {row ms, row launches, row algorithmic bytes, column ms, column
- * launches, column algorithmic bytes, 0, 0}; algorithmic bytes per sampled
- * entry = both stencil gathers of the frame tables + 16 k bytes of previous
- * cross vectors + 8 bytes written.                                         */
+/* Timing of the two sampling kernels of slar_cross_update: while enabled,
+ * every row-fiber and column-fiber launch carries start/stop HIP events on
+ * its own dispatch (kernel duration, no marker packets in between);
+ * enabling clears the counters.  slar_timing_read fills host out[8] = {row
+ * ms, row launches, row algorithmic bytes, column ms, column launches,
+ * column algorithmic bytes, 0, 0}; algorithmic bytes per sampled entry =
+ * both stencil gathers of the frame tables + 16 k bytes of previous cross
+ * vectors + 8 bytes written.                                               */
 slar_status slar_timing_enable(slar_workspace* ws, int32_t on);
 slar_status slar_timing_read(const slar_workspace* ws, double* out);
 

@@ -309,7 +309,7 @@ slar_status slar_timing_enable(slar_workspace* w, int32_t on) {
   if (!w) return SLAR_E_INVAL;
   Workspace& ws = w->w;
   if (on && ws.events.empty()) {
-    const int need = 3 * (64 + 64 + 1);
+    const int need = 4 * (64 + 64);
     ws.events.resize(need);
     for (int i = 0; i < need; ++i)
       if (hipEventCreate(&ws.events[i]) != hipSuccess) {

@@ -21,6 +21,8 @@
 // v_k = row residual (the same product as the textbook v = r / r_j).
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "aca.h"
 
 namespace slar {
@@ -43,10 +45,15 @@ static hipError_t aca_iterate(hipStream_t s, const GridDev& G, const AdvDev& A, 
   const unsigned bRow = (G.nv + FS_SAMPLES - 1) / FS_SAMPLES;
   const unsigned bCol = (G.nx + FS_SAMPLES - 1) / FS_SAMPLES;
   AcaInst I{G, A, X, P, ld, r, ctl, U, V, used, part, (int)bRow, (int)bCol, nprobe, 16, probes};
-  k_aca_row<T, W, DX><<<bRow, FS_THREADS, 0, s>>>(I);
-  if (ev) HIP_CHK(hipEventRecord(ev[0], s));
-  k_aca_col<T, W, DX><<<bCol, FS_THREADS, 0, s>>>(I);
-  if (ev) HIP_CHK(hipEventRecord(ev[1], s));
+  if (ev) {
+    // events attached to the dispatches themselves: start and end of the
+    // kernel, without marker packets between the launches
+    hipExtLaunchKernelGGL(k_aca_row<T, W, DX>, dim3(bRow), dim3(FS_THREADS), 0, s, ev[0], ev[1], 0, I);
+    hipExtLaunchKernelGGL(k_aca_col<T, W, DX>, dim3(bCol), dim3(FS_THREADS), 0, s, ev[2], ev[3], 0, I);
+  } else {
+    k_aca_row<T, W, DX><<<bRow, FS_THREADS, 0, s>>>(I);
+    k_aca_col<T, W, DX><<<bCol, FS_THREADS, 0, s>>>(I);
+  }
   k_aca_fin<T, W, DX><<<1, FS_THREADS, 0, s>>>(I);
   return hipGetLastError();
 }
@@ -97,13 +104,13 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   // of the previous cross vectors (residual and dot products) and the write
   const int rx = (G.dx == 2) ? adv.order * adv.order : adv.order;
   const double gather_bytes = 2.0 * rx * ldt * (dt == SLAR_F32 ? 4.0 : 8.0) + 8.0;
-  const bool timing = ws->timing && (int)ws->events.size() >= 3 * (maxit + 1);
+  const bool timing = ws->timing && (int)ws->events.size() >= 4 * maxit;
   int k_known = 0, it_timed = 0;
   auto harvest = [&](int upto) -> hipError_t {
     for (; it_timed < upto; ++it_timed) {
       float ms_row = 0.f, ms_col = 0.f;
-      HIP_CHK(hipEventElapsedTime(&ms_row, ws->events[3 * it_timed], ws->events[3 * it_timed + 1]));
-      HIP_CHK(hipEventElapsedTime(&ms_col, ws->events[3 * it_timed + 1], ws->events[3 * it_timed + 2]));
+      HIP_CHK(hipEventElapsedTime(&ms_row, ws->events[4 * it_timed], ws->events[4 * it_timed + 1]));
+      HIP_CHK(hipEventElapsedTime(&ms_col, ws->events[4 * it_timed + 2], ws->events[4 * it_timed + 3]));
       const double per = gather_bytes + 16.0 * k_known;
       ws->tstat[0] += ms_row; ws->tstat[1] += 1; ws->tstat[2] += per * G.nv;
       ws->tstat[3] += ms_col; ws->tstat[4] += 1; ws->tstat[5] += per * G.nx;
@@ -113,15 +120,14 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   int it = 0;
   for (; it < maxit; ++it) {
     hipError_t e;
-    if (timing) HIP_TRY(hipEventRecord(ws->events[3 * it], s));
     if (dt == SLAR_F32)
       e = aca_iter_dispatch<float>(s, G, A, ws->X32, ws->P32, ldt, r, ctl, out->U, out->V,
                                    ws->used, ws->aca_part, nprobe, probes,
-                                   timing ? &ws->events[3 * it + 1] : nullptr);
+                                   timing ? &ws->events[4 * it] : nullptr);
     else
       e = aca_iter_dispatch<double>(s, G, A, X64, P64, ldt, r, ctl, out->U, out->V, ws->used,
                                     ws->aca_part, nprobe, probes,
-                                    timing ? &ws->events[3 * it + 1] : nullptr);
+                                    timing ? &ws->events[4 * it] : nullptr);
     if (e != hipSuccess) return SLAR_E_HIP;
     if ((it % 4) == 3 || it == maxit - 1) {
       HIP_TRY(hipMemcpyAsync(hc, ctl, sizeof(AcaCtl), hipMemcpyDeviceToHost, s));
