@@ -1,0 +1,99 @@
+"""Physics of whole GPU runs (LoMaC-SLAR, spectral-preconditioned JFNK)
+against rates fixed by linear theory, not by the oracle:
+
+* 2D2V weak Landau damping, k = 0.5 on both x-directions: the electric
+  energy envelope decays as exp(2 gamma t), with gamma the root of the
+  Maxwellian dispersion relation 1 + (1 + zeta Z(zeta)) / k^2 = 0,
+  zeta = omega / (sqrt 2 k) (gamma = -0.1534), and its peaks are half a
+  plasma period pi / omega apart;
+* 2D2V two-stream instability, beams at +-2.4 along v1, k = 0.2: the x1
+  mode grows at the purely imaginary root of
+  1 + (1 / 2k^2) sum_+- (1 + zeta_+- Z(zeta_+-)) = 0,
+  zeta_+- = (omega / k -+ v0) / sqrt 2 (gamma = 0.2258), so the electric
+  energy grows as exp(2 gamma t) in the linear phase.  The initial
+  perturbation also excites the oscillating beam modes of the same k,
+  which dominate the field until t ~ 12 (the growth rate measured over
+  one time unit alternates in sign there); the fit takes t in [15, 25],
+  after the growing root dominates and before saturation (it reads 0.224).
+Z is the plasma dispersion function, Z(zeta) = i sqrt(pi) w(zeta) with the
+Faddeeva function w.  Grids are reduced to 32^4 so a run takes seconds,
+and the Landau run uses dt = 0.1: at the workload's dt = 0.2 the time
+discretisation (CF3 sub-flows and the BDF2 macroscopic step of LoMaC)
+adds about 10 % damping at this frequency (omega dt = 0.28; measured
+gamma -0.170 at dt 0.2 against -0.158 at dt 0.1 on 32^4, and -0.1635 with
+/ -0.1586 without LoMaC on 64^4 at dt 0.2).  The rates are checked to 5 %.
+Mass and energy stay conserved to round-off along the runs."""
+import math
+
+import numpy as np
+import pytest
+
+import slar_inputs as SI
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2606_29027_amd import lib as L  # noqa: E402
+from paper_2606_29027_amd.solver import Solver  # noqa: E402
+
+
+def _root(k, v0, guess):
+    from scipy.special import wofz
+    from scipy.optimize import fsolve
+
+    def f(z):
+        w = complex(z[0], z[1])
+        D = 1.0
+        beams = (0.0,) if v0 == 0.0 else (v0, -v0)
+        for b in beams:
+            zeta = (w / k - b) / math.sqrt(2)
+            Z = 1j * math.sqrt(math.pi) * wofz(zeta)
+            D += (1 + zeta * Z) / (k * k * len(beams))
+        return [D.real, D.imag]
+
+    r = fsolve(f, guess, xtol=1e-13)
+    return r[0], r[1]
+
+
+def _run(p, steps):
+    Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
+    s = Solver(p, L.F64, probes=SI.probe_indices(Nx, Nv, 64, 7), precond=1)
+    s.set_initial(SI.initial_ht(p))
+    d0 = s.diagnostics()
+    ee = [d0["elec_energy"]]
+    for _ in range(steps):
+        info = s.step()
+        assert info["converged"]
+        ee.append(s.diagnostics()["elec_energy"])
+    d = s.diagnostics()
+    assert abs(d["mass"] - d0["mass"]) < 1e-12 * d0["mass"]
+    assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
+    return np.array(ee), np.arange(steps + 1) * p.dt
+
+
+def test_landau_damping_rate_2d2v():
+    om, gam = _root(0.5, 0.0, [1.4, -0.15])
+    assert abs(gam + 0.1534) < 1e-3
+    p = SI.config("landau2d", n=32).with_(dt=0.1)
+    ee, t = _run(p, 150)                     # T = 15
+    le = np.log(ee)
+    pk = [i for i in range(1, len(le) - 1) if le[i] > le[i - 1] and le[i] >= le[i + 1]]
+    assert len(pk) >= 4
+    slope = np.polyfit(t[pk], le[pk], 1)[0]
+    assert abs(slope / 2 - gam) < 0.05 * abs(gam), (slope / 2, gam)
+    per = np.mean(np.diff(t[pk]))
+    assert abs(per - math.pi / om) < 0.15, (per, math.pi / om)
+
+
+def test_two_stream_growth_rate_2d2v():
+    om, gam = _root(0.2, 2.4, [0.0, 0.2])
+    assert abs(om) < 1e-8 and abs(gam - 0.2258) < 1e-3
+    p = SI.config("twostream2d", n=32)
+    ee, t = _run(p, 250)                     # T = 25
+    le = np.log(ee)
+    sel = (t >= 15.0) & (t <= 25.0)
+    slope = np.polyfit(t[sel], le[sel], 1)[0]
+    assert abs(slope / 2 - gam) < 0.05 * gam, (slope / 2, gam)
