@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_k_aca_col_stronglandau2d_128.md")
 # sources that define the column-fiber kernel; the counter-measured traffic
 # is reported only for the source state it was measured on
-KERNEL_SOURCES = ["aca.h", "frame_sampler.h", "slar_internal.h", "cross.hip"]
+KERNEL_SOURCES = ["aca.h", "frame_sampler.h", "sl_device.h", "cross.hip"]
 
 
 def kernel_source_hash() -> str:

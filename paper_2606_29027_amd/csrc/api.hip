@@ -102,6 +102,9 @@ slar_status slar_workspace_destroy(slar_workspace* w) {
   for (void* p : dev)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : ws.events) (void)hipEventDestroy(e);
+  if (ws.ev_fork) (void)hipEventDestroy(ws.ev_fork);
+  if (ws.ev_join) (void)hipEventDestroy(ws.ev_join);
+  if (ws.aux) (void)hipStreamDestroy(ws.aux);
   if (ws.aca_ctl_host) (void)hipHostFree(ws.aca_ctl_host);
   if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
   delete w;
@@ -152,6 +155,9 @@ slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspa
   dalloc((void**)&ws.kry, sizeof(double) * ws.kry_elems);
   if (ok && hipHostMalloc(&ws.aca_ctl_host, aca_ctl_bytes(), 0) != hipSuccess) ok = false;
   if (ok && hipHostMalloc(&ws.host_pinned, 65536, 0) != hipSuccess) ok = false;
+  if (ok && hipStreamCreateWithFlags(&ws.aux, hipStreamNonBlocking) != hipSuccess) ok = false;
+  if (ok && hipEventCreateWithFlags(&ws.ev_fork, hipEventDisableTiming) != hipSuccess) ok = false;
+  if (ok && hipEventCreateWithFlags(&ws.ev_join, hipEventDisableTiming) != hipSuccess) ok = false;
   if (!ok) {
     slar_workspace_destroy(w);
     return SLAR_E_NOMEM;

@@ -3,8 +3,13 @@
 #include "slar_internal.h"
 
 namespace slar {
-hipError_t gram_rows(hipStream_t s, Workspace* ws, int k, int n, const double* A, int lda, double* G);
-hipError_t gram_mode2(hipStream_t s, Workspace* ws, int na, int nb, int r, const double* X, double* G);
+// device scratch region (cap doubles)
+struct Scratch {
+  double* p;
+  size_t cap;
+};
+hipError_t gram_rows(hipStream_t s, const Scratch& part, int k, int n, const double* A, int lda, double* G);
+hipError_t gram_mode2(hipStream_t s, const Scratch& part, int na, int nb, int r, const double* X, double* G);
 hipError_t chol_inv(hipStream_t s, int k, const double* G, double* Linv, double* R, const double* Rprev);
 hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z);
 hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* const* G,

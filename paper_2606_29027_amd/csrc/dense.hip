@@ -187,29 +187,32 @@ __global__ __launch_bounds__(256) void k_gram_sum(int kk, int nblk, const double
   if (w == 0 && e < kk) G[e] = ((q4[0][ln] + q4[1][ln]) + q4[2][ln]) + q4[3][ln];
 }
 
+// part: scratch for the per-block partials, cap doubles (the block count
+// shrinks to fit).
 template <class Addr>
-static hipError_t gram_launch(hipStream_t s, Workspace* ws, int k, int n, Addr A, double* G) {
+static hipError_t gram_launch(hipStream_t s, const Scratch& part, int k, int n, Addr A, double* G) {
   if (k < 1 || k > 128 || n < 1) return hipErrorInvalidValue;
   const int nchunk = (n + GR_C - 1) / GR_C;
   int nblk = std::min(nchunk, 128);
-  while (nblk > 1 && (size_t)nblk * k * k > ws->dwork_elems) nblk /= 2;
-  if ((size_t)nblk * k * k > ws->dwork_elems) return hipErrorInvalidValue;
-  if (k <= 64) k_gram_part<4><<<nblk, 256, 0, s>>>(k, n, A, ws->dwork);
-  else k_gram_part<8><<<nblk, 256, 0, s>>>(k, n, A, ws->dwork);
-  k_gram_sum<<<(k * k + 63) / 64, 256, 0, s>>>(k * k, nblk, ws->dwork, G);
+  while (nblk > 1 && (size_t)nblk * k * k > part.cap) nblk /= 2;
+  if ((size_t)nblk * k * k > part.cap) return hipErrorInvalidValue;
+  if (k <= 64) k_gram_part<4><<<nblk, 256, 0, s>>>(k, n, A, part.p);
+  else k_gram_part<8><<<nblk, 256, 0, s>>>(k, n, A, part.p);
+  k_gram_sum<<<(k * k + 63) / 64, 256, 0, s>>>(k * k, nblk, part.p, G);
   return hipGetLastError();
 }
 
 // Gram G = A A^T for A = [k][n] row vectors (long n).
-hipError_t gram_rows(hipStream_t s, Workspace* ws, int k, int n, const double* A, int lda,
+hipError_t gram_rows(hipStream_t s, const Scratch& part, int k, int n, const double* A, int lda,
                      double* G) {
-  return gram_launch(s, ws, k, n, RowMajor{A, lda}, G);
+  return gram_launch(s, part, k, n, RowMajor{A, lda}, G);
 }
 
 // Gram of the mode-2 unfolding of X[(i1 * nb + i2) * r + c] (i1 < na):
 // G[i2][i2'] = sum_{i1, c} X[i1, i2, c] X[i1, i2', c].
-hipError_t gram_mode2(hipStream_t s, Workspace* ws, int na, int nb, int r, const double* X, double* G) {
-  return gram_launch(s, ws, nb, na * r, Mode2{X, nb, r}, G);
+hipError_t gram_mode2(hipStream_t s, const Scratch& part, int na, int nb, int r, const double* X,
+                      double* G) {
+  return gram_launch(s, part, nb, na * r, Mode2{X, nb, r}, G);
 }
 
 // --------------------------------------------------- Cholesky-QR helpers

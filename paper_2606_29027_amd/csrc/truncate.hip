@@ -31,9 +31,17 @@ static int tail_rank(const std::vector<double>& s2, double theta, int rmax) {
   return r;
 }
 
+// Scratch of one truncation.  The U and V chains (and the x and v sides of
+// the tree) run concurrently on two streams, so each has its own small
+// matrices and half of the dense work buffer.
+struct Chain {
+  double *G, *Linv, *R1;
+  Scratch part;
+};
 struct Tbuf {
-  double *Q1u, *Qu, *Q1v, *Qv, *X, *Y, *Xs, *Ys, *T;
-  double *Gu, *Linv, *R1, *R, *M, *W, *Z, *sv;
+  double *Q1u, *Qu, *Q1v, *Qv, *X, *Y, *Xs, *Ys, *T, *T2;
+  Chain cu, cv;
+  double *R, *M, *W, *Z, *sv;
   double *G1, *G2, *G3, *G4, *E1, *E2, *E3, *E4, *Vw, *lam1, *lam2, *lam3, *lam4;
 };
 
@@ -51,9 +59,15 @@ static Tbuf carve(Workspace* ws) {
   b.Xs = p; p += (size_t)G.nx * K;
   b.Ys = p; p += (size_t)G.nv * K;
   b.T = p; p += K * SLAR_NMAX * K;
-  b.Gu = p; p += K * K;
-  b.Linv = p; p += K * K;
-  b.R1 = p; p += K * K;
+  b.T2 = p; p += K * SLAR_NMAX * K;
+  for (Chain* c : {&b.cu, &b.cv}) {
+    c->G = p; p += K * K;
+    c->Linv = p; p += K * K;
+    c->R1 = p; p += K * K;
+  }
+  const size_t half = ws->dwork_elems / 2;
+  b.cu.part = Scratch{ws->dwork, half};
+  b.cv.part = Scratch{ws->dwork + half, half};
   b.R = p; p += K * K * 2;
   b.M = p; p += K * K;
   b.W = p; p += K * K;
@@ -78,38 +92,48 @@ static Tbuf carve(Workspace* ws) {
 size_t truncate_scratch_elems(const GridDev& G) {
   const size_t K = SLAR_KMAX, NN = (size_t)SLAR_NMAX * SLAR_NMAX;
   return 2 * K * G.nx + 2 * K * G.nv + 2 * (size_t)G.nx * K + 2 * (size_t)G.nv * K +
-         K * SLAR_NMAX * K + 9 * K * K + K + 9 * NN + 4 * SLAR_NMAX + 64;
+         2 * K * SLAR_NMAX * K + 12 * K * K + K + 9 * NN + 4 * SLAR_NMAX + 64;
 }
 
 // Orthonormal rows Q (k x n) and upper R (k x k) with A = R^T Q... i.e.
 // A^T = Q^T R, by two Cholesky-QR passes.
-static hipError_t cholqr2(hipStream_t s, Workspace* ws, Tbuf& b, int k, int n, const double* A,
-                          double* Q1, double* Q, double* Rout) {
-  hipError_t e = gram_rows(s, ws, k, n, A, n, b.Gu);
+static hipError_t cholqr2(hipStream_t s, const Chain& c, int k, int n, const double* A, double* Q1,
+                          double* Q, double* Rout) {
+  hipError_t e = gram_rows(s, c.part, k, n, A, n, c.G);
   if (e != hipSuccess) return e;
-  e = chol_inv(s, k, b.Gu, b.Linv, b.R1, nullptr);
+  e = chol_inv(s, k, c.G, c.Linv, c.R1, nullptr);
   if (e != hipSuccess) return e;
-  e = gemm_f64(s, false, false, k, n, k, 1.0, b.Linv, k, 0, A, n, 0, 0.0, Q1, n, 0, 1);
+  e = gemm_f64(s, false, false, k, n, k, 1.0, c.Linv, k, 0, A, n, 0, 0.0, Q1, n, 0, 1);
   if (e != hipSuccess) return e;
-  e = gram_rows(s, ws, k, n, Q1, n, b.Gu);
+  e = gram_rows(s, c.part, k, n, Q1, n, c.G);
   if (e != hipSuccess) return e;
-  e = chol_inv(s, k, b.Gu, b.Linv, Rout, b.R1);
+  e = chol_inv(s, k, c.G, c.Linv, Rout, c.R1);
   if (e != hipSuccess) return e;
-  return gemm_f64(s, false, false, k, n, k, 1.0, b.Linv, k, 0, Q1, n, 0, 0.0, Q, n, 0, 1);
+  return gemm_f64(s, false, false, k, n, k, 1.0, c.Linv, k, 0, Q1, n, 0, 0.0, Q, n, 0, 1);
 }
 
 // Gram matrices of the two mode matricisations of frame * diag(s) for one
 // side of the tree (frame: [na*nb][r] packed).  Xs is scratch [na*nb][r].
-static hipError_t side_grams(hipStream_t s, Workspace* ws, const double* frame, int na, int nb,
+static hipError_t side_grams(hipStream_t s, const Scratch& part, const double* frame, int na, int nb,
                              int r, const double* sv_dev, double* Xs, double* Ga, double* Gb) {
   HIP_CHK(copy2d(s, na * nb, r, frame, r, Xs, r, sv_dev));
-  HIP_CHK(gram_rows(s, ws, na, nb * r, Xs, nb * r, Ga));
-  return gram_mode2(s, ws, na, nb, r, Xs, Gb);
+  HIP_CHK(gram_rows(s, part, na, nb * r, Xs, nb * r, Ga));
+  return gram_mode2(s, part, na, nb, r, Xs, Gb);
+}
+
+// aux waits for the work already on s / s waits for everything on aux
+static hipError_t fork(hipStream_t s, Workspace* ws) {
+  HIP_CHK(hipEventRecord(ws->ev_fork, s));
+  return hipStreamWaitEvent(ws->aux, ws->ev_fork, 0);
+}
+static hipError_t join(hipStream_t s, Workspace* ws) {
+  HIP_CHK(hipEventRecord(ws->ev_join, ws->aux));
+  return hipStreamWaitEvent(s, ws->ev_join, 0);
 }
 
 // Leaf bases (leading eigenvectors, sign rule) and the transfer tensor of
 // one side once the eigendecompositions are known.
-static slar_status side_finish(hipStream_t s, Tbuf& b, const double* frame, int na, int nb, int r,
+static slar_status side_finish(hipStream_t s, double* T, const double* frame, int na, int nb, int r,
                                const double* Ea, const double* Eb, int ra, int rb, double* Ua,
                                double* Ub, double* Bt) {
   if (copy2d(s, na, ra, Ea, na, Ua, ra, nullptr) != hipSuccess) return SLAR_E_HIP;
@@ -117,11 +141,11 @@ static slar_status side_finish(hipStream_t s, Tbuf& b, const double* frame, int 
   if (sign_fix(s, na, ra, Ua, ra, nullptr, 0, 0) != hipSuccess) return SLAR_E_HIP;
   if (sign_fix(s, nb, rb, Ub, rb, nullptr, 0, 0) != hipSuccess) return SLAR_E_HIP;
   // T[a][(i2, c)] = sum_i1 Ua[i1][a] frame[i1][(i2, c)]
-  if (gemm_f64(s, true, false, ra, nb * r, na, 1.0, Ua, ra, 0, frame, nb * r, 0, 0.0, b.T, nb * r,
+  if (gemm_f64(s, true, false, ra, nb * r, na, 1.0, Ua, ra, 0, frame, nb * r, 0, 0.0, T, nb * r,
                0, 1) != hipSuccess)
     return SLAR_E_HIP;
   // Bt[a][b][c] = sum_i2 Ub[i2][b] T[a][i2][c]   (batched over a)
-  if (gemm_f64(s, true, false, rb, r, nb, 1.0, Ub, rb, 0, b.T, r, (long long)nb * r, 0.0, Bt, r,
+  if (gemm_f64(s, true, false, rb, r, nb, 1.0, Ub, rb, 0, T, r, (long long)nb * r, 0.0, Bt, r,
                (long long)rb * r, ra) != hipSuccess)
     return SLAR_E_HIP;
   return SLAR_OK;
@@ -146,9 +170,12 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
   const GridDev& G = ws->G;
   Tbuf b = carve(ws);
   const int k = in.k;
-  if (cholqr2(s, ws, b, k, G.nx, in.U, b.Q1u, b.Qu, b.R) != hipSuccess) return SLAR_E_HIP;
   double* Rv = b.R + SLAR_KMAX * SLAR_KMAX;
-  if (cholqr2(s, ws, b, k, G.nv, in.V, b.Q1v, b.Qv, Rv) != hipSuccess) return SLAR_E_HIP;
+  // the U and V orthogonalisations are independent: U on s, V on aux
+  if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
+  if (cholqr2(s, b.cu, k, G.nx, in.U, b.Q1u, b.Qu, b.R) != hipSuccess) return SLAR_E_HIP;
+  if (cholqr2(ws->aux, b.cv, k, G.nv, in.V, b.Q1v, b.Qv, Rv) != hipSuccess) return SLAR_E_HIP;
+  if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
   // core M = Ru Rv^T
   if (gemm_f64(s, false, true, k, k, k, 1.0, b.R, k, 0, Rv, k, 0, 0.0, b.M, k, 0, 1) != hipSuccess)
     return SLAR_E_HIP;
@@ -173,10 +200,12 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
     if (r == rmax && std::sqrt(tail) > theta) capped = true;
   }
   // frames X = Qu^T W_r (Nx x r), Y = Qv^T Z_r (Nv x r)
+  if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
   if (gemm_f64(s, true, false, G.nx, r, k, 1.0, b.Qu, G.nx, 0, b.W, k, 0, 0.0, b.X, r, 0, 1) != hipSuccess)
     return SLAR_E_HIP;
-  if (gemm_f64(s, true, false, G.nv, r, k, 1.0, b.Qv, G.nv, 0, b.Z, k, 0, 0.0, b.Y, r, 0, 1) != hipSuccess)
+  if (gemm_f64(ws->aux, true, false, G.nv, r, k, 1.0, b.Qv, G.nv, 0, b.Z, k, 0, 0.0, b.Y, r, 0, 1) != hipSuccess)
     return SLAR_E_HIP;
+  if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
   if (sign_fix(s, G.nx, r, b.X, r, b.Y, r, G.nv) != hipSuccess) return SLAR_E_HIP;
   k_diag<<<(r * r + 255) / 256, 256, 0, s>>>(r, b.sv, (double*)out->root);
   if (d == 2) {
@@ -186,8 +215,11 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
     for (int m = 2; m < 6; ++m) out->rank[m] = 0;
   } else {
     // Gram matrices of the four modes, one batched eigen launch, one sync
-    if (side_grams(s, ws, b.X, G.n[0], G.n[1], r, b.sv, b.Xs, b.G1, b.G2) != hipSuccess) return SLAR_E_HIP;
-    if (side_grams(s, ws, b.Y, G.n[2], G.n[3], r, b.sv, b.Ys, b.G3, b.G4) != hipSuccess) return SLAR_E_HIP;
+    if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
+    if (side_grams(s, b.cu.part, b.X, G.n[0], G.n[1], r, b.sv, b.Xs, b.G1, b.G2) != hipSuccess) return SLAR_E_HIP;
+    if (side_grams(ws->aux, b.cv.part, b.Y, G.n[2], G.n[3], r, b.sv, b.Ys, b.G3, b.G4) != hipSuccess)
+      return SLAR_E_HIP;
+    if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
     const int nn[4] = {G.n[0], G.n[1], G.n[2], G.n[3]};
     const double* Gs[4] = {b.G1, b.G2, b.G3, b.G4};
     double* lams[4] = {b.lam1, b.lam2, b.lam3, b.lam4};
@@ -204,12 +236,14 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
       for (double v : l) if (!std::isfinite(v)) return SLAR_E_NUMERIC;
       rk[m] = leaf_rank(l, theta, rmax, &capped);
     }
-    slar_status st = side_finish(s, b, b.X, G.n[0], G.n[1], r, b.E1, b.E2, rk[0], rk[1],
+    if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
+    slar_status st = side_finish(s, b.T, b.X, G.n[0], G.n[1], r, b.E1, b.E2, rk[0], rk[1],
                                  (double*)out->leaf[0], (double*)out->leaf[1], (double*)out->B12);
     if (st != SLAR_OK) return st;
-    st = side_finish(s, b, b.Y, G.n[2], G.n[3], r, b.E3, b.E4, rk[2], rk[3], (double*)out->leaf[2],
-                     (double*)out->leaf[3], (double*)out->B34);
+    st = side_finish(ws->aux, b.T2, b.Y, G.n[2], G.n[3], r, b.E3, b.E4, rk[2], rk[3],
+                     (double*)out->leaf[2], (double*)out->leaf[3], (double*)out->B34);
     if (st != SLAR_OK) return st;
+    if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
     for (int m = 0; m < 4; ++m) out->rank[m] = rk[m];
     out->rank[4] = r; out->rank[5] = r;
   }
