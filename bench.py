@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense matrix-core peaks
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_k_aca_col_stronglandau2d_128.md")
 # sources that define the column-fiber kernel; the counter-measured traffic
 # is reported only for the source state it was measured on
@@ -73,7 +74,7 @@ def parse():
     ap.add_argument("--variants", default="plain,spectral,learned",
                     help="comma list of macro solvers to time: plain, spectral, learned "
                          "(the last one listed is the headline)")
-    ap.add_argument("--workload", choices=["stronglandau2d", "batched"], default="stronglandau2d",
+    ap.add_argument("--workload", choices=["stronglandau2d", "batched", "samplers"], default="stronglandau2d",
                     help="batched: 64 independent 1D1V/2D2V Landau instances of uneven size")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch configuration")
@@ -185,6 +186,74 @@ def batched_main(args):
     print(json.dumps(out))
 
 
+def samplers_main(args):
+    """Entry-evaluation microbenchmark on the 128^4 grid: a random HT of
+    uniform rank r (orthonormal leaves, Gaussian transfer tensors, seed
+    1000 + r), 2^20 uniform random requests (seed 1234), the first sub-flow
+    of the strong-Landau workload (RK4 frozen-field feet, tau = dt / 3).
+    For each r and precision it times the leaf-to-root HT contraction
+    (slar_ht_sample, matrix cores) and the frame-table sampler
+    (slar_frame_sample; its per-call FP64 -> table copy included) with HIP
+    events on the launch stream, and prints one JSON line per case:
+    entries/s, and the contraction's flops against the dense matrix-core
+    peak of its dtype, or the tables' algorithmic gather bytes (mostly L2
+    hits: 2 x 2.4 MB tables at r = 60) per second."""
+    import torch
+    import slar_inputs as SI
+    from oracle import step as ST          # field of the initial state only (input generation)
+    from paper_2606_29027_amd import lib as L
+    p = SI.config("stronglandau2d", n=128)
+    E = torch.as_tensor(ST.Oracle(p).efield(SI.initial_ht(p)), dtype=torch.float64, device="cuda")
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 64)
+    S = 1 << 20
+    idx = torch.as_tensor(SI.random_requests(p.n, S, seed=1234), dtype=torch.int32, device="cuda")
+    adv = L.make_adv(2, p.dt / 3.0, 1.0, E)
+    Nx = 128 * 128
+    peak = {"f32": MFMA_PEAK_TFLOPS["f32"], "f64": MFMA_PEAK_TFLOPS["f64"]}
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / args.steps
+
+    for r in (8, 16, 24, 32, 40, 48, 60):
+        F = SI.random_ht(4, p.n, (r,) * 6, seed=1000 + r)
+        T64 = {"leaves": [torch.as_tensor(U, device="cuda") for U in F["leaves"]],
+               "root": torch.as_tensor(F["root"], device="cuda"),
+               "B12": torch.as_tensor(F["B12"].reshape(r * r, r), device="cuda"),
+               "B34": torch.as_tensor(F["B34"].reshape(r * r, r), device="cuda")}
+        H64 = L.make_ht(T64, 4, L.F64)
+        X = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
+        P = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
+        Fr = L.slar_frames_from_ht(g, H64, L.frames(X, P, 0), ws)
+        for prec in ("f32", "f64"):
+            tdt = torch.float32 if prec == "f32" else torch.float64
+            T = {k: ([x.to(tdt) for x in v] if isinstance(v, list) else v.to(tdt)) for k, v in T64.items()}
+            H = L.make_ht(T, 4, L.F32 if prec == "f32" else L.F64)
+            out = torch.zeros(S, dtype=tdt, device="cuda")
+            dt = timed(lambda: L.slar_ht_sample(g, H, adv, idx, out))
+            flops = 2.0 * (4 * 3 * r + 2 * r ** 3 + r * r) * S
+            print(json.dumps({"sampler": "ht_contraction", "dtype": prec, "rank": r, "entries": S,
+                              "entries_per_s": S / dt, "ms": 1e3 * dt,
+                              "tflops": flops / dt / 1e12,
+                              "frac_of_mfma_peak": flops / dt / 1e12 / peak[prec]}), flush=True)
+            outd = torch.zeros(S, dtype=torch.float64, device="cuda")
+            dtc = L.F32 if prec == "f32" else L.F64
+            dt = timed(lambda: L.slar_frame_sample(g, Fr, adv, dtc, idx, outd, ws))
+            ldt = (r + 3) & ~3
+            by = S * (2.0 * 9 * ldt * (4 if prec == "f32" else 8) + 8 + 16)
+            print(json.dumps({"sampler": "frame_tables", "dtype": prec, "rank": r, "entries": S,
+                              "entries_per_s": S / dt, "ms": 1e3 * dt,
+                              "gather_GBps": by / dt / 1e9}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -193,6 +262,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return batched_main(args)
+    if args.workload == "samplers":
+        return samplers_main(args)
     import torch
     import slar_inputs as SI
     from paper_2606_29027_amd import lib as L

@@ -2,9 +2,9 @@
 //  * k_ht_sample: the paper's contraction on an HT tensor: per sample the
 //    leaf interpolations c^(mu) = w(xi_mu) U^(mu)_{J_mu}, then the transfer
 //    contractions y12 = (c1 (x) c2) B12, y34 = (c3 (x) c4) B34 and the root
-//    bilinear form (O(d r^3) per point).  32 samples per block; the
-//    contraction loops read B12/B34 with consecutive output ranks on
-//    consecutive lanes (coalesced, L2-resident) and c^(mu) from LDS.
+//    bilinear form (O(d r^3) per point).  64 samples per block; the
+//    transfer contractions and the root form run on the matrix cores
+//    (16x16x4 FP32 / FP64 steps) with B12/B34 streamed from L2.
 //  * frame build: X = (U1 (x) U2) B12 and P = ((U3 (x) U4) B34) root^T as
 //    two GEMMs per node.
 //  * k_frame_points: eq. (tp_interp) from the node frames (frame_sampler.h)
@@ -25,86 +25,236 @@ struct HtDev {
   const T* root;
 };
 
-constexpr int HS_TILE = 32;
+// ---------------------------------------------------------------- MFMA
+// 16x16x4 matrix-core step, D = A B + C, for one 64-lane wave.  Lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator v = 0..3 of
+// lane l is D[row(l / 16, v)][l % 16], with row = 4 (l / 16) + v for the
+// FP32 step and (l / 16) + 4 v for the FP64 step.
+typedef float hs_v4f __attribute__((ext_vector_type(4)));
+typedef double hs_v4d __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  using acc = hs_v4f;
+  static __device__ __forceinline__ acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+};
+template <> struct Mfma<double> {
+  using acc = hs_v4d;
+  static __device__ __forceinline__ acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int v) { return q + 4 * v; }
+};
 
+// A block evaluates HS_S entries with four waves.  Each transfer node is
+// the GEMM y[s][c] = sum_(a,b) (c_a[s][a] c_b[s][b]) B[(a,b)][c] with
+// M = 64 entries, K = r_a r_b and N = r_parent; the Khatri-Rao operand is
+// formed lane by lane from the leaf interpolations in LDS, one product per
+// matrix-core step.  The (M, N) plane is 4 x NT tiles of 16 x 16; wave w
+// owns column tile w % NT and the row tiles w / NT + k (4 / NT), k < NT,
+// so every B fragment it loads feeds NT steps.
+constexpr int HS_S = 64;
+template <typename T>
+struct HsLds {
+  static constexpr int LDC = sizeof(T) == 4 ? 68 : 66;   // conflict-free A reads
+  int rows[HS_S][12];           // stencil rows, [dim][point] (d W <= 12)
+  double wts[HS_S][12];
+  T c[2][HS_S][LDC];            // two operand slots, zero beyond the rank
+  T part[4][HS_S];              // per column tile partial sums
+};
+
+// c[slot][s][a] = sum_w w U^(mu)[row_w][a] for the leaves m0, m0 + 1.
 template <typename T, int W>
+__device__ __forceinline__ void hs_interp(const HtDev<T>& F, int m0, HsLds<T>& L, int t) {
+#pragma unroll 4
+  for (int e = t; e < 2 * HS_S * 64; e += 256) {
+    const int slot = e / (HS_S * 64), s = (e / 64) % HS_S, col = e % 64;
+    const int m = m0 + slot, rm = F.r[m];
+    T acc = 0;
+    if (col < rm) {
+      const T* U = F.U[m];
+#pragma unroll
+      for (int b = 0; b < W; ++b)
+        acc += (T)L.wts[s][m * W + b] * U[(size_t)L.rows[s][m * W + b] * rm + col];
+    }
+    L.c[slot][s][col] = acc;
+  }
+}
+
+// One transfer node: acc[k] = tile (w / NT + k (4 / NT), w % NT) of
+// (c_a (x) c_b) B, with B [ra rb][rc] row-major.  K steps run a-major; a B
+// fragment is fetched four steps ahead of its use.
+template <typename T, int NT>
+__device__ __forceinline__ void hs_node(const HsLds<T>& L, int ra, int rb, int rc,
+                                        const T* __restrict__ B, int w, int lane,
+                                        typename Mfma<T>::acc* acc) {
+  const int q = lane >> 4, i = lane & 15;
+  const int col = 16 * (w % NT) + i;
+  const bool colok = col < rc;
+  const int nj = (rb + 3) >> 2, nk = ra * nj;
+  const float rinv = 1.0f / (float)nj;   // exact floor of (kk + 1/2) / nj for kk < 2^12
+  const T(*ca)[HsLds<T>::LDC] = L.c[0];
+  const T(*cb)[HsLds<T>::LDC] = L.c[1];
+  int mrow[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    mrow[k] = 16 * (w / NT + k * (4 / NT)) + i;
+    acc[k] = typename Mfma<T>::acc{0, 0, 0, 0};
+  }
+  // B fragments are loaded unconditionally from a clamped address (element
+  // 0 outside the matrix), so the loads stay in flight across steps: rows
+  // past rb meet zero A entries (the slots are zero beyond the rank), and
+  // columns past rc are cleared after the loop.
+  auto fetch = [&](int kk) -> T {
+    const int a = (int)(((float)kk + 0.5f) * rinv);
+    const int b = 4 * (kk - a * nj) + q;
+    const bool ok = kk < nk && b < rb && colok;
+    return B[ok ? (size_t)(a * rb + b) * rc + col : 0];
+  };
+  int acur = -1;
+  T c1[NT];
+  // one K step: the Khatri-Rao entries of this lane times the B fragment
+  auto step = [&](int kk, T bv) {
+    const int a = (int)(((float)kk + 0.5f) * rinv);
+    const int b = 4 * (kk - a * nj) + q;
+    if (a != acur) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) c1[k] = ca[mrow[k]][a];
+      acur = a;
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) acc[k] = Mfma<T>::step(c1[k] * cb[mrow[k]][b], bv, acc[k]);
+  };
+  T ring[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) ring[p] = fetch(p);
+  // whole groups of four steps run unguarded, so the fetches stay counted
+  // in flight across the loop; a slot is refilled once its steps issue
+  const int nk4 = nk & ~3;
+  for (int k0 = 0; k0 < nk4; k0 += 4) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      step(k0 + p, ring[p]);
+      ring[p] = fetch(k0 + p + 4);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+    if (nk4 + p < nk) step(nk4 + p, ring[p]);
+  if (!colok) {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) acc[k] = typename Mfma<T>::acc{0, 0, 0, 0};
+  }
+}
+
+// Root form f[s] = sum_c Lop[s][c] sum_e root[c][e] R[s][e], with R in
+// slot 1 (K = rk), Lop in slot 0 (N = rn), root [rn][rk].  Ends with the
+// per-entry sums in L.part[w % NT][s].
+template <typename T, int NT>
+__device__ __forceinline__ void hs_root(HsLds<T>& L, int rn, int rk, const T* __restrict__ root,
+                                        int w, int lane) {
+  const int q = lane >> 4, i = lane & 15;
+  const int nt = w % NT, col = 16 * nt + i;
+  const bool colok = col < rn;
+  typename Mfma<T>::acc z[NT];
+  int mrow[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    mrow[k] = 16 * (w / NT + k * (4 / NT));
+    z[k] = typename Mfma<T>::acc{0, 0, 0, 0};
+  }
+  const int nj = (rk + 3) >> 2;
+  for (int j = 0; j < nj; ++j) {
+    const int e = 4 * j + q;
+    const T bv = (colok && e < rk) ? root[(size_t)col * rk + e] : (T)0;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) z[k] = Mfma<T>::step(L.c[1][mrow[k] + i][e], bv, z[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NT; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int s = mrow[k] + Mfma<T>::row(q, v);
+      T x = z[k][v] * L.c[0][s][col];
+      x += __shfl_xor(x, 8, 16);
+      x += __shfl_xor(x, 4, 16);
+      x += __shfl_xor(x, 2, 16);
+      x += __shfl_xor(x, 1, 16);
+      if (i == 0) L.part[nt][s] = x;
+    }
+}
+
+template <typename T, int W, int DX, int NT>
 __global__ __launch_bounds__(256) void k_ht_sample(GridDev g, AdvDev a, HtDev<T> F, long long n,
                                                    const int* __restrict__ idx, T* __restrict__ out) {
-  __shared__ int rows[HS_TILE][4][W];
-  __shared__ double wts[HS_TILE][4][W];
-  __shared__ T c[4][HS_TILE][SLAR_KMAX];
-  __shared__ T y[2][HS_TILE][SLAR_KMAX];
-  const int t = threadIdx.x;
-  const long long s0 = (long long)blockIdx.x * HS_TILE;
-  const int ns = (int)min((long long)HS_TILE, n - s0);
-  const int d = F.d;
-  if (t < ns) {
-    int gi[4];
-    for (int m = 0; m < d; ++m) gi[m] = idx[(s0 + t) * d + m];
-    double ft[4];
-    if (g.dx == 1) foot_of<1>(g, a, gi, ft);
-    else foot_of<2>(g, a, gi, ft);
-    for (int m = 0; m < d; ++m) stencil_of<W>(g, a, m, ft[m], gi[m], rows[t][m], wts[t][m]);
-  }
-  __syncthreads();
-  // leaf interpolation c^(mu)[s][a] = sum_w w U^(mu)[row_w][a]
-  for (int m = 0; m < d; ++m) {
-    const int rm = F.r[m];
-    const T* U = F.U[m];
-    for (int e = t; e < ns * rm; e += blockDim.x) {
-      const int s = e / rm, aa = e % rm;
-      T acc = 0;
+  constexpr int d = 2 * DX;
+  __shared__ HsLds<T> L;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const long long s0 = (long long)blockIdx.x * HS_S;
+  {
+    // feet: the four lanes of a quad share one entry (entries past n trace
+    // grid point 0 and are not stored)
+    const int s = t >> 2;
+    int gi[4] = {0, 0, 0, 0};
+    if (s0 + s < n) {
 #pragma unroll
-      for (int b = 0; b < W; ++b) acc += (T)wts[s][m][b] * U[(size_t)rows[s][m][b] * rm + aa];
-      c[m][s][aa] = acc;
+      for (int m = 0; m < d; ++m) gi[m] = idx[(s0 + s) * d + m];
+    }
+    double ft[4];
+    foot_of<DX, 4>(g, a, gi, ft, t & 3);
+    int r[4][W];
+    double wt[4][W];
+#pragma unroll
+    for (int m = 0; m < d; ++m) stencil_of<W>(g, a, m, ft[m], gi[m], r[m], wt[m]);
+    if ((t & 3) == 0) {
+#pragma unroll
+      for (int m = 0; m < d; ++m)
+#pragma unroll
+        for (int b = 0; b < W; ++b) { L.rows[s][m * W + b] = r[m][b]; L.wts[s][m * W + b] = wt[m][b]; }
     }
   }
   __syncthreads();
-  const int wave = t / 64, lane = t % 64;
-  if (d == 2) {
-    const int rx = F.r[0], rv = F.r[1];
-    for (int s = wave; s < ns; s += 4) {
-      T p = 0;
-      for (int b = lane; b < rv; b += 64) {
-        T z = 0;
-        for (int aa = 0; aa < rx; ++aa) z += c[0][s][aa] * F.root[aa * rv + b];
-        p += z * c[1][s][b];
+  hs_interp<T, W>(F, 0, L, t);
+  __syncthreads();
+  if (d == 4) {
+    typename Mfma<T>::acc y12[NT], y34[NT];
+    hs_node<T, NT>(L, F.r[0], F.r[1], F.r[4], F.B12, w, lane, y12);
+    __syncthreads();
+    hs_interp<T, W>(F, 2, L, t);
+    __syncthreads();
+    hs_node<T, NT>(L, F.r[2], F.r[3], F.r[5], F.B34, w, lane, y34);
+    __syncthreads();
+    const int q = lane >> 4, i = lane & 15, col = 16 * (w % NT) + i;
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int s = 16 * (w / NT + k * (4 / NT)) + Mfma<T>::row(q, v);
+        L.c[0][s][col] = y12[k][v];
+        L.c[1][s][col] = y34[k][v];
       }
-      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-      if (lane == 0) out[s0 + s] = p;
-    }
-    return;
-  }
-  // transfer contractions of both internal nodes
-  for (int node = 0; node < 2; ++node) {
-    const int ra = F.r[2 * node], rb = F.r[2 * node + 1], rc = F.r[4 + node];
-    const T* B = node == 0 ? F.B12 : F.B34;
-    const T(*ca)[SLAR_KMAX] = c[2 * node];
-    const T(*cb)[SLAR_KMAX] = c[2 * node + 1];
-    for (int e = t; e < ns * rc; e += blockDim.x) {
-      const int s = e / rc, cc = e % rc;
-      T acc = 0;
-      for (int aa = 0; aa < ra; ++aa) {
-        T inner = 0;
-        const T* Ba = B + (size_t)aa * rb * rc + cc;
-        for (int bb = 0; bb < rb; ++bb) inner += cb[s][bb] * Ba[(size_t)bb * rc];
-        acc += ca[s][aa] * inner;
-      }
-      y[node][s][cc] = acc;
-    }
+    __syncthreads();
+    hs_root<T, NT>(L, F.r[4], F.r[5], F.root, w, lane);
+  } else {
+    hs_root<T, NT>(L, F.r[0], F.r[1], F.root, w, lane);
   }
   __syncthreads();
-  const int r12 = F.r[4], r34 = F.r[5];
-  for (int s = wave; s < ns; s += 4) {
-    T p = 0;
-    for (int e = lane; e < r34; e += 64) {
-      T z = 0;
-      for (int cc = 0; cc < r12; ++cc) z += y[0][s][cc] * F.root[cc * r34 + e];
-      p += z * y[1][s][e];
-    }
-    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-    if (lane == 0) out[s0 + s] = p;
+  if (t < HS_S && s0 + t < n) {
+    T f = 0;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) f += L.part[k][t];
+    out[s0 + t] = f;
   }
+}
+
+template <typename T, int W, int DX>
+static void launch_ht_nt(hipStream_t st, unsigned blocks, int nt, const GridDev& G, const AdvDev& A,
+                         const HtDev<T>& H, long long n, const int* idx, T* out) {
+  if (nt == 1) k_ht_sample<T, W, DX, 1><<<blocks, 256, 0, st>>>(G, A, H, n, idx, out);
+  else if (nt == 2) k_ht_sample<T, W, DX, 2><<<blocks, 256, 0, st>>>(G, A, H, n, idx, out);
+  else k_ht_sample<T, W, DX, 4><<<blocks, 256, 0, st>>>(G, A, H, n, idx, out);
 }
 
 template <typename T>
@@ -115,11 +265,13 @@ static hipError_t launch_ht_sample(hipStream_t st, const GridDev& G, const AdvDe
   for (int m = 0; m < 6; ++m) H.r[m] = F.rank[m];
   for (int m = 0; m < F.d; ++m) H.U[m] = (const T*)F.leaf[m];
   H.B12 = (const T*)F.B12; H.B34 = (const T*)F.B34; H.root = (const T*)F.root;
-  const unsigned blocks = (unsigned)((n + HS_TILE - 1) / HS_TILE);
-  if (A.order == 5)
-    k_ht_sample<T, 5><<<blocks, 256, 0, st>>>(G, A, H, n, idx, (T*)out);
-  else
-    k_ht_sample<T, 3><<<blocks, 256, 0, st>>>(G, A, H, n, idx, (T*)out);
+  // column tiles: the widest GEMM output (node ranks, or the x rank of a 2-leaf root)
+  const int ncol = F.d == 4 ? (F.rank[4] > F.rank[5] ? F.rank[4] : F.rank[5]) : F.rank[0];
+  const int nt = ncol <= 16 ? 1 : (ncol <= 32 ? 2 : 4);
+  const unsigned blocks = (unsigned)((n + HS_S - 1) / HS_S);
+  if (F.d == 4) launch_ht_nt<T, 3, 2>(st, blocks, nt, G, A, H, n, idx, (T*)out);
+  else if (A.order == 5) launch_ht_nt<T, 5, 1>(st, blocks, nt, G, A, H, n, idx, (T*)out);
+  else launch_ht_nt<T, 3, 1>(st, blocks, nt, G, A, H, n, idx, (T*)out);
   return hipGetLastError();
 }
 

@@ -67,6 +67,69 @@ def test_ht_sample_matches_oracle(name, N, kind, width, tau, prec):
     assert normwise(got[keep], ref[keep]) < tol
 
 
+# Ranks that take one, two and four 16-column matrix-core tiles, ranks that
+# are not multiples of the 4-deep K step, r12 != r34, the rank cap 64, both
+# trees and both stencil widths; 221 entries = three whole 64-entry blocks
+# and a ragged one.
+HIGH_RANK = [
+    ("landau2d", 32, (13, 18, 21, 10, 29, 17), 3),
+    ("landau2d", 64, (40, 37, 45, 33, 61, 50), 3),
+    ("landau2d", 64, (64, 64, 64, 64, 64, 64), 3),
+    ("landau1d", 64, (27, 21), 5),
+    ("landau1d", 128, (64, 55), 3),
+    ("landau1d", 48, (3, 47), 5),
+]
+
+
+@pytest.mark.parametrize("name,N,ranks,width", HIGH_RANK)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ht_sample_high_rank_within_rounding_bound(name, N, ranks, width, prec):
+    """FP64: every entry lies within the rounding-error bound of its
+    contraction, |f~ - f| <= gamma_n |f|(x), gamma_n = n u / (1 - n u), where
+    |f|(x) is the same contraction of the absolute values of the weights,
+    leaves, transfer tensors and root (computed by the oracle) and n bounds
+    the roundings along any term: W-point sum and product (W + 2), the
+    Khatri-Rao product, the K = r_a r_b sum with its products, the root sum
+    over r_k, the product with the left factor and the column sums
+    (n = K + r_k + r_n + W + 16).  Random Gaussian transfer tensors cancel
+    strongly (|f|(x) / |f| ~ 1e5 at rank 64), so in FP32 that bound says
+    nothing; there the bar is normwise, 3e-5, the size of FP32 sums of up
+    to 4096 terms of comparable magnitude (sqrt(4096) 2^-24 ~ 4e-6, with
+    margin).  FP64 also meets 1e-12 normwise."""
+    p = SI.config(name, n=N)
+    d = p.d
+    F = SI.random_ht(d, p.n, ranks, seed=31)
+    idx = SI.random_requests(p.n, 3 * 64 + 29, seed=6)
+    E = np.stack([0.6 * SI.random_field(p.n[: p.dx], 60 + m) for m in range(p.dx)])
+    foot = FT.feet(idx, p.lo, p.hi, p.n, p.dx, 2, 0.9, 1.0, E)
+    rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, width, 2, p.dx)
+    amb = FT.face_ambiguous(foot, p.lo, p.hi, p.n, 2, p.dx)
+    ref = HT.sample(F, rows, wts)
+    Fa = {k: ([np.abs(x) for x in v] if k == "leaves" else np.abs(v)) for k, v in F.items()}
+    scale = HT.sample(Fa, rows, [np.abs(w) for w in wts])
+    if d == 2:
+        K, rk, rn = ranks[1], ranks[1], ranks[0]
+    else:
+        K, rk, rn = max(ranks[0] * ranks[1], ranks[2] * ranks[3]), ranks[5], ranks[4]
+    u = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
+    nr = K + rk + rn + width + 16
+    gamma = nr * u / (1 - nr * u)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    H = L.make_ht(ht_to_dev(F, tdt), d, L.F64 if prec == "f64" else L.F32)
+    g = L.make_grid(p)
+    out = torch.zeros(len(idx), dtype=tdt, device="cuda")
+    adv = L.make_adv(2, 0.9, 1.0, dev(E), order=width)
+    L.slar_ht_sample(g, H, adv, dev(idx, torch.int32), out)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    keep = ~amb
+    assert keep.sum() > 0.9 * len(idx)
+    err = np.abs(got - ref)[keep]
+    if prec == "f64":
+        assert np.all(err <= gamma * scale[keep]), float(np.max(err / (gamma * scale[keep])))
+    assert normwise(got[keep], ref[keep]) < (1e-12 if prec == "f64" else 3e-5)
+
+
 def test_ht_sample_empty_request_and_invalid_args():
     p = SI.config("landau2d", n=8)
     F = SI.random_ht(4, p.n, (2, 2, 2, 2, 2, 2), seed=1)
