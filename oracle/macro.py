@@ -4,7 +4,8 @@ Section 3.2.3, eqs. (BE_macro), (BE_nonlinear_system): with the LoMaC
 closure, the conserved variables U = (n, m n u, e) solve
   G(U) = U - U_hist + b dt ( D.F(U) - S(U) ) = 0,
   backward Euler: U_hist = U^n, b = 1;  BDF2: U_hist = 4/3 U^n - 1/3 U^{n-1},
-  b = 2/3 (the paper's default multistep family; the start-up step is BE).
+  b = 2/3 (the start-up step is BE); the paper's own DIRK-3 start-up and
+  variable-step BDF-3 give other U_hist and b (``timeint``).
 The flux (eq. (macro_sys_comp)) is taken from the corrected kinetic state
 F(U) = F* + sum_k dC_k(U) Q_k (eq. (LoMaC_update_discrete)):
   mass      <v f>,
@@ -58,6 +59,10 @@ class MacroSystem:
         return self.Mstar + np.tensordot(self.psiQ, dC, axes=([1], [0])), dC
 
     def residual(self, U: np.ndarray) -> np.ndarray:
+        return U - self.U_hist + self.beta_dt * self.rhs(U)
+
+    def rhs(self, U: np.ndarray) -> np.ndarray:
+        """R(U) = D.F(U) - S(U), so that the moment system reads U' = -R(U)."""
         dv = self.dv
         L = self.lengths
         M, _ = self.corrected_moments(U)
@@ -82,7 +87,7 @@ class MacroSystem:
         divF[dv + 1] = SP.div(0.5 * M[off_e: off_e + dv] + Fep, L)
         S = np.zeros_like(U)
         S[1: dv + 1] = -U[0][None] * E
-        return U - self.U_hist + self.beta_dt * (divF - S)
+        return divF - S
 
 
 def fgmres(Aop, b, tol, restart=50, maxit=500, precond=None, record=None):

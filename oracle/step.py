@@ -16,7 +16,10 @@
     splitting);
   * LoMaC step (fig. "Fluid correction diagram"): weight and basis from F*,
     JFNK on G(U) = 0, exact correction F^{n+1} = F* + sum dC_k Q_k, with
-    U^{n+1} the macroscopic state carried to the next step;
+    U^{n+1} the macroscopic state carried to the next step; the implicit
+    macroscopic integrator is BE then BDF2, or (section 4) two S-stable
+    DIRK-3 start-up steps, each stage one SLAR_VP from F^n to its stage time
+    and one JFNK solve, then variable-step BDF-3 (``timeint``);
   * background ion density n_i = mean_x n_e(x, 0) (stationary neutralising
     ions, section 2.1).
 """
@@ -33,6 +36,7 @@ from . import ht as HT
 from . import lomac as LM
 from . import macro as MA
 from . import spectral as SP
+from . import timeint as TI
 
 
 class Oracle:
@@ -119,18 +123,23 @@ class Oracle:
         return LM.conserved_from_raw(M[: self.dv + 2], self.n_i, self.lengths)
 
     def lomac(self, Fs, U_n, U_nm1, h, precond=None, record=None):
-        """Returns (F^{n+1}, U^{n+1}, jfnk info)."""
+        """Returns (F^{n+1}, U^{n+1}, jfnk info); BE, then BDF2."""
+        if U_nm1 is None or self.p.bdf == 1:
+            U_hist, b = U_n, 1.0
+        else:
+            U_hist, b = (4.0 * U_n - U_nm1) / 3.0, 2.0 / 3.0
+        return self.lomac_solve(Fs, U_hist, b * h, precond, record)
+
+    def lomac_solve(self, Fs, U_hist, beta_dt, precond=None, record=None):
+        """LoMaC closure of F*, the implicit solve of
+        U - U_hist + beta_dt R(U) = 0, and the exact correction."""
         L = Fs["leaves"]
         u1 = [L[self.dx + m][:, 0] for m in range(self.dv)]
         B = LM.basis(u1, self.vgrids, self.h[self.dx:], self.delta)
         Mstar = self.moments(Fs)
         U0 = LM.conserved_from_raw(Mstar[: self.dv + 2], self.n_i, self.lengths)
-        if U_nm1 is None or self.p.bdf == 1:
-            U_hist, b = U_n, 1.0
-        else:
-            U_hist, b = (4.0 * U_n - U_nm1) / 3.0, 2.0 / 3.0
         sysm = MA.MacroSystem(Mstar, B, self.n_i, self.lengths, self.dvol_v, self.vgrids,
-                              U_hist, b * h)
+                              U_hist, beta_dt)
         U, info = MA.jfnk(sysm, U0, newton_tol=self.newton_tol, precond=precond, record=record)
         Mraw = LM.raw_from_conserved(U, self.n_i, self.lengths)
         dC = LM.coefficients(Mraw, B) - sysm.Cstar
@@ -155,19 +164,60 @@ class Oracle:
         }
         return out
 
-    def run(self, F, steps, lomac=None, precond=None, callback=None):
+    def dirk3_step(self, F, U_n, h, precond=None):
+        """One step of the S-stable three-stage DIRK (``timeint``): stage i
+        takes F*_i = SLAR_VP(F^n; c_i h) (the stage distribution at
+        t_n + c_i h) and solves its implicit system with the LoMaC closure
+        of F*_i; the last stage (c = 1) is the new state.  Returns
+        (F^{n+1}, U^{n+1}, info summed over the stages)."""
+        info = {"newton": 0, "krylov": 0, "converged": True}
+        last = {}
+
+        def stage(i, tau, U_hist, beta):
+            Fs = self.slar_vp(F, tau)
+            Fi, Ui, inf = self.lomac_solve(Fs, U_hist, beta, precond)
+            for key in ("newton", "krylov"):
+                info[key] += inf[key]
+            info["converged"] &= inf["converged"]
+            last["F"] = Fi
+            return Ui, inf["system"].rhs
+
+        U = TI.dirk3_step(U_n, h, stage)
+        return last["F"], U, info
+
+    def bdf3_step(self, F, Us, ts, h, precond=None):
+        """One variable-step BDF-3 step of size h after the states Us at
+        times ts (the last three are used)."""
+        U_hist, beta = TI.bdf_history(Us, ts, h)
+        Fs = self.slar_vp(F, h)
+        return self.lomac_solve(Fs, U_hist, beta, precond)
+
+    def run(self, F, steps, lomac=None, precond=None, callback=None, integrator=None, dts=None):
+        """integrator: "bdf2" (BE start-up, then fixed-step BDF2) or
+        "dirk3_bdf3" (two DIRK-3 start-up steps, then variable-step BDF-3);
+        dts: optional per-step sizes (default p.dt)."""
         p = self.p
         lomac = p.lomac if lomac is None else lomac
-        h = p.dt
+        integrator = integrator or p.integrator
         U_n = self.conserved(F) if lomac else None
         U_nm1 = None
+        Us, ts = [U_n], [0.0]
         hist = [self.diagnostics(F)]
         for n in range(steps):
-            Fs = self.strang(F, h) if p.split else self.slar_vp(F, h)
-            if lomac:
+            h = p.dt if dts is None else dts[n]
+            if lomac and integrator == "dirk3_bdf3":
+                if n < 2:
+                    F, U_new, info = self.dirk3_step(F, Us[-1], h, precond)
+                else:
+                    F, U_new, info = self.bdf3_step(F, Us, ts, h, precond)
+                Us.append(U_new)
+                ts.append(ts[-1] + h)
+            elif lomac:
+                Fs = self.strang(F, h) if p.split else self.slar_vp(F, h)
                 F, U_new, info = self.lomac(Fs, U_n, U_nm1, h, precond)
                 U_nm1, U_n = U_n, U_new
             else:
+                Fs = self.strang(F, h) if p.split else self.slar_vp(F, h)
                 F, info = Fs, {}
             d = self.diagnostics(F)
             d["ranks"] = HT.ranks(F)

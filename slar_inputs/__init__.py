@@ -55,6 +55,7 @@ class Problem:
     split: bool = False          # Strang splitting (1D1V workload)
     lomac: bool = True
     bdf: int = 2
+    integrator: str = "bdf2"      # or "dirk3_bdf3" (the paper's section 4 choice)
 
     @property
     def d(self) -> int:

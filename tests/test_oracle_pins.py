@@ -19,6 +19,7 @@ from oracle import lomac as LM
 from oracle import macro as MA
 from oracle import spectral as SP
 from oracle import step as ST
+from oracle import timeint as TI
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -411,3 +412,88 @@ def test_cnn_conv_is_periodic_cross_correlation():
     w = np.zeros((1, 1, 3, 3)); w[0, 0, 0, 0] = 2.0      # tap (dy, dx) = (0, 0) reads in[y-1, x-1]
     out = CN.conv(x, w, np.zeros(1))
     assert out[0, 0, 1, 1] == 2.0 and abs(out).sum() == 2.0
+
+
+# ---------------------------------------------------------------------------
+# Macroscopic time integrators (section 4: S-stable DIRK-3 start-up, then
+# variable-step BDF-3).
+
+def test_dirk3_tableau_is_third_order_stiffly_accurate_and_l_stable():
+    """Order conditions up to three, c = A 1, last row = b, and the stability
+    function R(z) = 1 + z b^T (I - z A)^{-1} 1 is bounded by 1 on the
+    imaginary axis and vanishes at infinity (L-stability: 1 - b^T A^{-1} 1)."""
+    A, b, c = TI.dirk3()
+    one = np.ones(3)
+    assert np.allclose(A @ one, c, atol=1e-15, rtol=0)
+    assert np.allclose(A[2], b, atol=0, rtol=0)
+    assert np.allclose(np.triu(A, 1), 0.0, atol=0, rtol=0)
+    assert abs(b @ one - 1.0) < 1e-14
+    assert abs(b @ c - 0.5) < 1e-14
+    assert abs(b @ (c * c) - 1.0 / 3.0) < 1e-14
+    assert abs(b @ A @ c - 1.0 / 6.0) < 1e-14
+    assert abs(A[0, 0] - A[1, 1]) == 0.0 and abs(A[1, 1] - A[2, 2]) == 0.0
+    assert abs(1.0 - b @ np.linalg.solve(A, one)) < 1e-13
+    for y in np.linspace(-50.0, 50.0, 401):
+        z = 1j * y
+        R = 1.0 + z * (b @ np.linalg.solve(np.eye(3) - z * A, one))
+        assert abs(R) <= 1.0 + 1e-12
+
+
+def test_bdf_weights_reduce_to_textbook_and_are_exact_for_cubics():
+    """Equal steps: backward Euler, BDF2 (4/3, -1/3; 2h/3) and BDF3 (18/11,
+    -9/11, 2/11; 6h/11).  Any distinct nodes: U(t0) - sum_j c_j U(t_j) =
+    beta U'(t0) holds exactly for every cubic (the weights differentiate the
+    interpolating polynomial)."""
+    h = 0.37
+    c, beta = TI.bdf([h, 0.0])
+    assert np.allclose(c, [1.0], rtol=1e-15) and abs(beta - h) < 1e-16
+    c, beta = TI.bdf([2 * h, h, 0.0])
+    assert np.allclose(c, [4.0 / 3.0, -1.0 / 3.0], rtol=1e-14) and abs(beta - 2 * h / 3) < 1e-15
+    c, beta = TI.bdf([3 * h, 2 * h, h, 0.0])
+    assert np.allclose(c, [18 / 11, -9 / 11, 2 / 11], rtol=1e-14) and abs(beta - 6 * h / 11) < 1e-15
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        steps = rng.uniform(0.05, 0.5, 3)
+        t = np.cumsum(np.concatenate([[0.0], steps]))[::-1]      # t0 > t1 > t2 > t3
+        c, beta = TI.bdf(t)
+        assert abs(c.sum() - 1.0) < 1e-13
+        coef = rng.standard_normal(4)
+        P = np.polynomial.Polynomial(coef)
+        lhs = P(t[0]) - sum(c[j] * P(t[1 + j]) for j in range(3))
+        assert abs(lhs - beta * P.deriv()(t[0])) < 1e-12 * (1 + np.abs(coef).sum())
+
+
+def _linear_run(lam, hs):
+    """u' = -lam u (R(u) = lam u) from u(0) = 1 with the step sequencing of
+    the kinetic driver: two DIRK-3 start-up steps, then BDF-3."""
+    Us, ts = [np.array([1.0])], [0.0]
+
+    def stage(i, tau, U_hist, beta):
+        return U_hist / (1.0 + beta * lam), (lambda u: lam * u)
+
+    for n, h in enumerate(hs):
+        if n < 2:
+            U = TI.dirk3_step(Us[-1], h, stage)
+        else:
+            U_hist, beta = TI.bdf_history(Us, ts, h)
+            U = U_hist / (1.0 + beta * lam)
+        Us.append(U)
+        ts.append(ts[-1] + h)
+    return float(Us[-1][0]), ts[-1]
+
+
+def test_dirk3_bdf3_sequencing_converges_at_third_order():
+    """The shared step sequencing (stage history sums, BDF history) on
+    u' = -lam u: the error at T = 2 falls by ~8 per halving of the step,
+    with equal steps and with steps alternating by a ratio 1.25."""
+    lam = 1.3
+    for pattern in ([1.0], [1.0, 1.25]):
+        errs = []
+        for m in (20, 40, 80):
+            base = 2.0 / m
+            hs = [base * pattern[i % len(pattern)] for i in range(m)]
+            hs = [x * 2.0 / sum(hs) for x in hs]
+            u, T = _linear_run(lam, hs)
+            errs.append(abs(u - np.exp(-lam * T)))
+        rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+        assert all(2.7 < r < 3.3 for r in rates), (pattern, errs, rates)
