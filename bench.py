@@ -294,6 +294,7 @@ def main():
         n0 = len(s.stats)
         infos = []
         L.slar_timing_enable(s.ws, True)
+        s.tphase = {k: 0.0 for k in s.tphase}
         t0 = time.perf_counter()
         for _ in range(args.steps):
             infos.append(s.step())
@@ -302,8 +303,14 @@ def main():
         tim = L.slar_timing_read(s.ws)
         L.slar_timing_enable(s.ws, False)
         samples = sum(st["samples"] for st in s.stats[n0:])
+        kern_s = (tim["row_ms"] + tim["col_ms"]) * 1e-3
+        phase = {k: 1e3 * v / args.steps for k, v in s.tphase.items()}
+        phase["other"] = 1e3 * elapsed / args.steps - sum(phase.values())
         runs[name] = {"value": samples / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
                       "samples_per_step": samples / args.steps,
+                      "entries_per_s_cross": samples / (s.tphase["cross"] or float("nan")),
+                      "entries_per_s_fiber_kernels": samples / kern_s if kern_s > 0 else None,
+                      "phase_ms_per_step": phase,
                       "newton_krylov": [[i.get("newton"), i.get("krylov")] for i in infos],
                       "ranks": [st["ranks"] for st in s.stats[-3:]], "timing": tim}
         del s

@@ -227,6 +227,57 @@ slar_status slar_macro_solve(const slar_grid* g, const double* U_n, const double
                              int32_t precond, const slar_cnn* cnn, double* U_out, int32_t* iters,
                              slar_workspace* ws, hipStream_t stream);
 
+/* General implicit macroscopic system, the form every stage of the
+ * section 4 integrators takes (two S-stable DIRK-3 start-up steps, then
+ * variable-step BDF-3; section 3.2.3 for the stage structure):
+ *   G(U) = U - sum_{j<nhist} c[j] U[j] + sum_{j<nstage} d[j] R[j]
+ *          + beta (D.F(U) - S(U)) = 0,
+ * solved like slar_macro_solve (same closure, preconditioners, tolerances,
+ * status and iteration counts).  U[j] are history states and R[j] right-hand
+ * sides of earlier stages (device, [dv+2][Nx] FP64, caller-owned, not
+ * U_out); beta > 0 includes the step size.  Weights with sum c = 1 keep the
+ * mean of every component exact, hence mass, momentum and energy
+ * conserved to round-off.  Backward Euler: nhist 1, c 1, beta dt; a DIRK
+ * stage i: U[0] = U_n, c 1, R[j] the earlier stages' right-hand sides with
+ * d[j] = dt a_ij, beta = dt a_ii; BDF-k: slar_bdf_weights.                */
+typedef struct {
+  int32_t nhist;
+  const double* U[3];
+  double c[3];
+  int32_t nstage;
+  const double* R[3];
+  double d[3];
+  double beta;
+} slar_macro_system;
+slar_status slar_macro_solve_system(const slar_grid* g, const slar_macro_system* S,
+                                    double newton_tol, double krylov_tol, int32_t precond,
+                                    const slar_cnn* cnn, double* U_out, int32_t* iters,
+                                    slar_workspace* ws, hipStream_t stream);
+
+/* Right-hand side R(U) = D.F(U) - S(U) of the moment system U' = -R(U)
+ * (eq. (BE_nonlinear_system) without the history), with the closure of the
+ * last slar_lomac_prepare on ws (SLAR_E_INVAL if none).  U, R_out device
+ * [dv+2][Nx] FP64, distinct.  Enqueued on stream.                          */
+slar_status slar_macro_rhs(const slar_grid* g, const double* U, double* R_out,
+                           slar_workspace* ws, hipStream_t stream);
+
+/* Butcher tableau of the S-stable three-stage DIRK method (Alexander 1977,
+ * Theorem 5) that section 4 uses for start-up: gamma the root in (1/6, 1/2)
+ * of 6x^3 - 18x^2 + 9x - 1; c = (gamma, (1 + gamma)/2, 1); A (host,
+ * row-major [3][3]) lower triangular with diagonal gamma, a21 = (1-gamma)/2,
+ * last row b1 = -(6 gamma^2 - 16 gamma + 1)/4, b2 = (6 gamma^2 - 20 gamma
+ * + 5)/4, gamma (= b).  Host only.                                        */
+slar_status slar_dirk3_tableau(double* A, double* c);
+
+/* Weights of the classical variable-step BDF-k (Gear 1971), k = 1..3: the
+ * derivative at t[0] of the polynomial through (t[j], U_j), j = 0..k (host,
+ * t[0] = t_{n+1} > t[1] = t_n > ...), set to -R(U_0), gives
+ *   U_0 - sum_{j=1..k} c[j-1] U_j + beta R(U_0) = 0.
+ * c (host [k]) and *beta (host) out.  Equal steps h and k = 3 give
+ * 18/11, -9/11, 2/11 and 6h/11.  Host only; SLAR_E_INVAL unless the times
+ * decrease strictly.                                                       */
+slar_status slar_bdf_weights(int32_t k, const double* t, double* c, double* beta);
+
 /* LoMaC update eq. (LoMaC_update_discrete):
  *   F^{n+1} = F* - R(U(F*)) + R(U_new) = F* + sum_k dC_k (x) Q_k,
  * returned exactly (no re-truncation) in frame form: out->X = [X* | dC],

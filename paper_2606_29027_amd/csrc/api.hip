@@ -297,8 +297,83 @@ slar_status slar_macro_solve(const slar_grid* g, const double* U_n, const double
     return SLAR_E_INVAL;
   if (bdf_order == 2 && !U_nm1) return SLAR_E_INVAL;
   if (precond < 0 || precond > 2 || (precond == 2 && !cnn)) return SLAR_E_INVAL;
-  return macro_solve_run(stream, &w->w, U_n, U_nm1, dt, bdf_order, newton_tol, krylov_tol, precond,
-                         cnn, U_out, iters);
+  MacroHist h{};
+  double beta = dt;
+  h.nh = 1; h.U[0] = U_n; h.c[0] = 1.0;
+  if (bdf_order == 2) {
+    h.nh = 2; h.c[0] = 4.0 / 3.0; h.U[1] = U_nm1; h.c[1] = -1.0 / 3.0;
+    beta = 2.0 / 3.0 * dt;
+  }
+  return macro_solve_run(stream, &w->w, h, beta, newton_tol, krylov_tol, precond, cnn, U_out, iters);
+}
+
+slar_status slar_macro_solve_system(const slar_grid* g, const slar_macro_system* S,
+                                    double newton_tol, double krylov_tol, int32_t precond,
+                                    const slar_cnn* cnn, double* U_out, int32_t* iters,
+                                    slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !S || !U_out) return SLAR_E_INVAL;
+  if (S->nhist < 1 || S->nhist > 3 || S->nstage < 0 || S->nstage > 3) return SLAR_E_INVAL;
+  if (!(S->beta > 0.0) || !std::isfinite(S->beta) || !(newton_tol > 0.0) ||
+      !(krylov_tol > 0.0 && krylov_tol < 1.0))
+    return SLAR_E_INVAL;
+  if (precond < 0 || precond > 2 || (precond == 2 && !cnn)) return SLAR_E_INVAL;
+  MacroHist h{};
+  h.nh = S->nhist;
+  h.nr = S->nstage;
+  for (int j = 0; j < S->nhist; ++j) {
+    if (!S->U[j] || !std::isfinite(S->c[j]) || S->U[j] == U_out) return SLAR_E_INVAL;
+    h.U[j] = S->U[j]; h.c[j] = S->c[j];
+  }
+  for (int j = 0; j < S->nstage; ++j) {
+    if (!S->R[j] || !std::isfinite(S->d[j]) || S->R[j] == U_out) return SLAR_E_INVAL;
+    h.R[j] = S->R[j]; h.d[j] = S->d[j];
+  }
+  return macro_solve_run(stream, &w->w, h, S->beta, newton_tol, krylov_tol, precond, cnn, U_out, iters);
+}
+
+slar_status slar_macro_rhs(const slar_grid* g, const double* U, double* R_out, slar_workspace* w,
+                           hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !U || !R_out || U == R_out) return SLAR_E_INVAL;
+  if (!w->w.lm_ready) return SLAR_E_INVAL;
+  return macro_rhs(stream, &w->w, U, R_out) == hipSuccess ? SLAR_OK : SLAR_E_HIP;
+}
+
+slar_status slar_dirk3_tableau(double* A, double* c) {
+  if (!A || !c) return SLAR_E_INVAL;
+  // gamma: the root in (1/6, 1/2) of p(x) = 6x^3 - 18x^2 + 9x - 1, by bisection
+  // (p(1/6) = 1/36 > 0 > p(1/2) = -1/4 and p has one root there)
+  double lo = 1.0 / 6.0, hi = 0.5;
+  auto p = [](double x) { return ((6.0 * x - 18.0) * x + 9.0) * x - 1.0; };
+  for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (p(mid) > 0.0) lo = mid; else hi = mid;
+  }
+  const double gm = 0.5 * (lo + hi);
+  const double b1 = -(6.0 * gm * gm - 16.0 * gm + 1.0) / 4.0;
+  const double b2 = (6.0 * gm * gm - 20.0 * gm + 5.0) / 4.0;
+  const double T[9] = {gm, 0.0, 0.0, (1.0 - gm) / 2.0, gm, 0.0, b1, b2, gm};
+  for (int i = 0; i < 9; ++i) A[i] = T[i];
+  c[0] = gm; c[1] = (1.0 + gm) / 2.0; c[2] = 1.0;
+  return SLAR_OK;
+}
+
+slar_status slar_bdf_weights(int32_t k, const double* t, double* c, double* beta) {
+  if (k < 1 || k > 3 || !t || !c || !beta) return SLAR_E_INVAL;
+  for (int j = 0; j < k; ++j)
+    if (!(t[j] > t[j + 1]) || !std::isfinite(t[j]) || !std::isfinite(t[j + 1])) return SLAR_E_INVAL;
+  double l0 = 0.0;
+  for (int m = 1; m <= k; ++m) l0 += 1.0 / (t[0] - t[m]);
+  for (int j = 1; j <= k; ++j) {
+    double num = 1.0, den = 1.0;
+    for (int m = 1; m <= k; ++m)
+      if (m != j) num *= t[0] - t[m];
+    for (int m = 0; m <= k; ++m)
+      if (m != j) den *= t[j] - t[m];
+    c[j - 1] = -(num / den) / l0;
+  }
+  *beta = 1.0 / l0;
+  return SLAR_OK;
 }
 
 slar_status slar_lomac_project(const slar_grid* g, const slar_frames* Fstar_frames,

@@ -16,9 +16,21 @@ slar_status lomac_prepare_run(hipStream_t s, Workspace* ws, const slar_ht& Fs,
                               const slar_frames& Ff, double delta, double n_i);
 hipError_t macro_residual(hipStream_t s, Workspace* ws, const double* U, const double* Uhist,
                           double bdt, double* Gout);
-slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, const double* Unm1,
-                            double dt, int bdf, double newton_tol, double krylov_tol, int precond,
+// history of one implicit macroscopic system (DIRK stage or BDF step):
+//   G(U) = U - sum_j c_j U_j + sum_j d_j R_j + beta R(U)
+struct MacroHist {
+  int nh;
+  const double* U[3];
+  double c[3];
+  int nr;
+  const double* R[3];
+  double d[3];
+};
+slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist, double beta,
+                            double newton_tol, double krylov_tol, int precond,
                             const slar_cnn* cnn, double* Uout, int* iters);
+// R(U) = D.F(U) - S(U) with the prepared closure
+hipError_t macro_rhs(hipStream_t s, Workspace* ws, const double* U, double* Rout);
 slar_status lomac_project_run(hipStream_t s, Workspace* ws, const slar_frames& Fs,
                               const double* Unew, slar_frames* out);
 // training pair recorder (cnn.hip): features of w = J z and the target

@@ -5,7 +5,7 @@
 //            Gram--Schmidt (gamma, q1, eta, beta, q2, norms), one block per
 //            velocity dimension; Q_0, Q_{1,mu}, Q_2 on the velocity grid;
 //            <psi, Q_k>; moments and projection coefficients of F*.
-//  residual: G(U) = U - U_hist + b dt (D.F(U) - S(U)) with the LoMaC
+//  residual: G(U) = U - U_hist + beta (D.F(U) - S(U)) with the LoMaC
 //            closure; spectral Poisson / d_t phi / divergence.
 //  solve   : Newton with finite-difference Jacobian-vector products and
 //            restarted (flexible) GMRES with CGS2; each Newton step is
@@ -618,8 +618,23 @@ static void flux_jacobian(const GridDev& G, const double* scal, const double* ps
     }
 }
 
-slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, const double* Unm1,
-                            double dt, int bdf, double newton_tol, double krylov_tol, int precond,
+// Uhist = sum_j c_j U_j - sum_j d_j R_j, accumulated in that order
+__global__ void k_hist_combine(int n, MacroHist h, double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double v = h.c[0] * h.U[0][e];
+  for (int j = 1; j < h.nh; ++j) v += h.c[j] * h.U[j][e];
+  for (int j = 0; j < h.nr; ++j) v -= h.d[j] * h.R[j][e];
+  out[e] = v;
+}
+
+hipError_t macro_rhs(hipStream_t s, Workspace* ws, const double* U, double* Rout) {
+  // G = U - U + 1 (D.F - S): the history cancels exactly
+  return macro_residual(s, ws, U, U, 1.0, Rout);
+}
+
+slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist, double beta,
+                            double newton_tol, double krylov_tol, int precond,
                             const slar_cnn* cnn, double* Uout, int* iters) {
   if (!ws->lm_ready) return SLAR_E_INVAL;
   const GridDev& G = ws->G;
@@ -640,13 +655,8 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const double* Un, cons
   };
   auto norm2 = [&](double* x, double* out) { cgs(0, nullptr, nullptr, x, out); };
   double* Uhist = b.x;
-  double bdt = dt;
-  if (bdf >= 2 && Unm1 != nullptr) {
-    k_axpby<<<nb, 256, 0, s>>>(n, 4.0 / 3.0, Un, 0.0, Uhist, -1.0 / 3.0, Unm1);
-    bdt = 2.0 / 3.0 * dt;
-  } else {
-    HIP_TRY(hipMemcpyAsync(Uhist, Un, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  }
+  const double bdt = beta;
+  k_hist_combine<<<nb, 256, 0, s>>>(n, hist, Uhist);
   double* U = b.U;
   HIP_TRY(hipMemcpyAsync(U, ws->lm + L.U0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   const double sqeps = std::sqrt(2.220446049250313e-16);

@@ -28,6 +28,7 @@ EXPORTS = (
     "slar_timing_read", "slar_batch_create", "slar_batch_destroy", "slar_batch_workspace",
     "slar_batch_cross_update", "slar_batch_truncate", "slar_batch_efield", "slar_batch_get_config",
     "slar_batch_set_config", "slar_batch_tune", "slar_batch_timing", "slar_batch_timing_reset",
+    "slar_macro_solve_system", "slar_macro_rhs", "slar_dirk3_tableau", "slar_bdf_weights",
 )
 
 
@@ -58,6 +59,12 @@ class LowRank(C.Structure):
 class CrossInfo(C.Structure):
     _fields_ = [("rank", C.c_int32), ("iterations", C.c_int32), ("probe_rounds", C.c_int32),
                 ("converged", C.c_int32), ("samples", C.c_int64)]
+
+
+class MacroSystem(C.Structure):
+    _fields_ = [("nhist", C.c_int32), ("U", C.c_void_p * 3), ("c", C.c_double * 3),
+                ("nstage", C.c_int32), ("R", C.c_void_p * 3), ("d", C.c_double * 3),
+                ("beta", C.c_double)]
 
 
 class SlarError(RuntimeError):
@@ -119,6 +126,10 @@ def load(path: str = LIB_PATH):
         "slar_batch_tune": (i32, [vp, P(Frames), P(Adv), dbl, i32, i32, P(vp), P(LowRank), i32, vp]),
         "slar_batch_timing": (i32, [vp, P(C.c_double)]),
         "slar_batch_timing_reset": (i32, [vp]),
+        "slar_macro_solve_system": (i32, [P(Grid), P(MacroSystem), dbl, dbl, i32, vp, vp, P(i32), vp, vp]),
+        "slar_macro_rhs": (i32, [P(Grid), vp, vp, vp, vp]),
+        "slar_dirk3_tableau": (i32, [P(dbl), P(dbl)]),
+        "slar_bdf_weights": (i32, [i32, P(dbl), P(dbl), P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -265,6 +276,44 @@ def slar_macro_solve(grid, U_n, U_nm1, dt, bdf, newton_tol, krylov_tol, precond,
                                  iters, ws.h, _stream())
     _check(st, "slar_macro_solve", ok=(SLAR_OK, SLAR_E_NOCONV))
     return st, (iters[0], iters[1])
+
+
+def slar_macro_solve_system(grid, hist, stages, beta, newton_tol, krylov_tol, precond, cnn, U_out, ws):
+    """hist: [(U_j, c_j)] (1..3), stages: [(R_j, d_j)] (0..3)."""
+    S = MacroSystem()
+    S.nhist = len(hist)
+    for j, (U, c) in enumerate(hist):
+        S.U[j] = U.data_ptr(); S.c[j] = float(c)
+    S.nstage = len(stages)
+    for j, (R, d) in enumerate(stages):
+        S.R[j] = R.data_ptr(); S.d[j] = float(d)
+    S.beta = float(beta)
+    iters = (C.c_int32 * 2)()
+    st = load().slar_macro_solve_system(C.byref(grid), C.byref(S), float(newton_tol), float(krylov_tol),
+                                        int(precond), cnn, _ptr(U_out), iters, ws.h, _stream())
+    _check(st, "slar_macro_solve_system", ok=(SLAR_OK, SLAR_E_NOCONV))
+    return st, (iters[0], iters[1])
+
+
+def slar_macro_rhs(grid, U, R_out, ws):
+    _check(load().slar_macro_rhs(C.byref(grid), _ptr(U), _ptr(R_out), ws.h, _stream()), "slar_macro_rhs")
+    return R_out
+
+
+def slar_dirk3_tableau():
+    A = (C.c_double * 9)()
+    c = (C.c_double * 3)()
+    _check(load().slar_dirk3_tableau(A, c), "slar_dirk3_tableau")
+    return [[A[3 * i + j] for j in range(3)] for i in range(3)], [c[i] for i in range(3)]
+
+
+def slar_bdf_weights(times):
+    k = len(times) - 1
+    t = (C.c_double * (k + 1))(*[float(x) for x in times])
+    c = (C.c_double * max(k, 1))()
+    beta = C.c_double()
+    _check(load().slar_bdf_weights(int(k), t, c, C.byref(beta)), "slar_bdf_weights")
+    return [c[j] for j in range(k)], beta.value
 
 
 def slar_lomac_project(grid, Fs, U_new, out: Frames, ws):

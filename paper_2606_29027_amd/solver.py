@@ -7,6 +7,10 @@ truncation) gives F*; the LoMaC closure of F* is prepared, the macroscopic
 system is solved by JFNK (backward Euler for the first step, BDF2 after), and
 the exact correction F^{n+1} = F* + sum_k dC_k Q_k is appended in frame form.
 The split 1D1V workload uses Strang splitting X(h/2) V(h) X(h/2) instead.
+With p.integrator == "dirk3_bdf3" the macroscopic integrator is the one of
+section 4: two S-stable DIRK-3 start-up steps (each stage one SLAR_VP from
+F^n to its stage time, one closure and one implicit solve), then
+variable-step BDF-3; step sizes may vary from step to step.
 
 This module only sequences library calls and owns the device buffers
 (PyTorch allocations); it does no arithmetic of the method itself.
@@ -50,7 +54,11 @@ class Solver:
         self.V = z(RCAP, self.Nv)
         self.M = z(self.nmom, self.Nx)
         self.E = [z(p.dx, self.Nx) for _ in range(3)]
-        self.Ubuf = [z(self.K, self.Nx) for _ in range(3)]
+        self.Ubuf = [z(self.K, self.Nx) for _ in range(4)]
+        self.Rstage = [z(self.K, self.Nx) for _ in range(2)]
+        self.Ustage = [z(self.K, self.Nx) for _ in range(2)]
+        self.U_hist = []              # DIRK-3/BDF-3: newest last, at times self.t_hist
+        self.t_hist = []
         self.probes = None if probes is None else torch.as_tensor(
             np.ascontiguousarray(probes), dtype=torch.int32, device="cuda")
         self.n_i = None
@@ -59,6 +67,9 @@ class Solver:
         self.U_n = None
         self.U_nm1 = None
         self.stats = []
+        # host wall time of the phases whose calls synchronise their stream
+        # (work queued before them is counted in them)
+        self.tphase = {"cross": 0.0, "truncation": 0.0, "macro": 0.0}
 
     # -------------------------------------------------------------- buffers
     def _ht_buffers(self):
@@ -106,6 +117,7 @@ class Solver:
             self.U_n = self.Ubuf[0]
             L.slar_conserved(self.grid, self.state, self.n_i, self.U_n, self.ws)
             self.U_nm1 = None
+            self.U_hist, self.t_hist = [self.U_n], [0.0]
 
     # ---------------------------------------------------------- components
     def efield(self, F: L.Frames, out):
@@ -115,10 +127,14 @@ class Solver:
 
     def slar(self, src: L.Frames, adv, ht_slot: int, frame_slot: int):
         """One SLAR call: cross approximation + truncation + frames."""
+        t0 = time.perf_counter()
         lr, info, st = L.slar_cross_update(self.grid, src, adv, self.prec, self.p.tol, min(self.p.rmax, RCAP),
                                            self.probes, self.U, self.V, self.ws)
+        t1 = time.perf_counter()
         H, _ = self.ht_buf[ht_slot]
         L.slar_truncate(self.grid, lr, self.p.tol, min(self.p.rmax, RCAP), H, self.ws)
+        self.tphase["cross"] += t1 - t0
+        self.tphase["truncation"] += time.perf_counter() - t1
         F = L.slar_frames_from_ht(self.grid, H, self._frames(frame_slot), self.ws)
         self.stats.append({"rank": info.rank, "samples": int(info.samples), "iters": info.iterations,
                            "probe_rounds": info.probe_rounds, "converged": info.converged,
@@ -149,19 +165,64 @@ class Solver:
         F3, H3 = self.slar(F2, L.make_adv(0, 0.5 * h, 1.0, order=o), 0, s3)
         return F3, H3, s3
 
-    def step(self):
-        p = self.p
-        h = p.dt
+    def _solve(self, Hs, Fs, hist, stages, beta, U_out):
+        L.slar_lomac_prepare(self.grid, Hs, Fs, self.delta, self.n_i, self.ws)
         t0 = time.perf_counter()
+        st, (nn, nk) = L.slar_macro_solve_system(self.grid, hist, stages, beta, self.newton_tol,
+                                                 self.krylov_tol, self.precond,
+                                                 None if self.cnn is None else self.cnn.handle, U_out, self.ws)
+        self.tphase["macro"] += time.perf_counter() - t0
+        return st == L.SLAR_OK, nn, nk
+
+    def _step_dirk3_bdf3(self, h):
+        """One step of the section 4 integrator (see the module docstring)."""
+        U_n, t_n = self.U_hist[-1], self.t_hist[-1]
+        U_new = [u for u in self.Ubuf if all(u is not v for v in self.U_hist[-3:])][0]
+        ok, nn, nk = True, 0, 0
+        if len(self.U_hist) < 3:
+            A, c = L.slar_dirk3_tableau()
+            for i in range(3):
+                Fs, Hs, slot = self.slar_vp(c[i] * h)
+                U_i = U_new if i == 2 else self.Ustage[i]
+                stages = [(self.Rstage[j], h * A[i][j]) for j in range(i)]
+                o, a, b = self._solve(Hs, Fs, [(U_n, 1.0)], stages, h * A[i][i], U_i)
+                ok, nn, nk = ok and o, nn + a, nk + b
+                if i < 2:
+                    L.slar_macro_rhs(self.grid, U_i, self.Rstage[i], self.ws)
+        else:
+            cw, beta = L.slar_bdf_weights([t_n + h, t_n, self.t_hist[-2], self.t_hist[-3]])
+            Fs, Hs, slot = self.slar_vp(h)
+            hist = [(self.U_hist[-1 - j], cw[j]) for j in range(3)]
+            ok, nn, nk = self._solve(Hs, Fs, hist, [], beta, U_new)
+        out_slot = [s for s in range(4) if s != slot][0]
+        Fn = L.slar_lomac_project(self.grid, Fs, U_new, self._frames(out_slot), self.ws)
+        self.U_hist = (self.U_hist + [U_new])[-3:]
+        self.t_hist = (self.t_hist + [t_n + h])[-3:]
+        self.U_nm1, self.U_n = U_n, U_new
+        self.state, self.state_slot = Fn, out_slot
+        return {"newton": nn, "krylov": nk, "converged": ok}
+
+    def step(self, h=None):
+        """One time step of size h (default p.dt)."""
+        p = self.p
+        h = p.dt if h is None else h
+        t0 = time.perf_counter()
+        if p.lomac and p.integrator == "dirk3_bdf3":
+            info = self._step_dirk3_bdf3(h)
+            torch.cuda.synchronize()
+            info["seconds"] = time.perf_counter() - t0
+            return info
         Fs, Hs, slot = self.strang(h) if p.split else self.slar_vp(h)
         info = {}
         if p.lomac:
             L.slar_lomac_prepare(self.grid, Hs, Fs, self.delta, self.n_i, self.ws)
             U_new = [u for u in self.Ubuf if u is not self.U_n and u is not self.U_nm1][0]
             bdf = 1 if (self.U_nm1 is None or p.bdf == 1) else 2
+            tm = time.perf_counter()
             st, (nn, nk) = L.slar_macro_solve(self.grid, self.U_n, self.U_nm1 if bdf == 2 else None, h, bdf,
                                               self.newton_tol, self.krylov_tol, self.precond,
                                               None if self.cnn is None else self.cnn.handle, U_new, self.ws)
+            self.tphase["macro"] += time.perf_counter() - tm
             out_slot = [s for s in range(4) if s not in (slot,)][0]
             Fn = L.slar_lomac_project(self.grid, Fs, U_new, self._frames(out_slot), self.ws)
             self.U_nm1, self.U_n = self.U_n, U_new

@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "Problem", "config", "CONFIG_NAMES", "cell_centres", "initial_ht",
     "random_ht", "random_requests", "fiber_requests", "probe_indices",
-    "batched_instances", "random_field",
+    "batched_instances", "random_field", "PAPER_WORKLOADS",
 ]
 
 
@@ -56,6 +56,7 @@ class Problem:
     lomac: bool = True
     bdf: int = 2
     integrator: str = "bdf2"      # or "dirk3_bdf3" (the paper's section 4 choice)
+    bump: tuple = ()              # bump-on-tail (n_p, n_b, u, v_t)
 
     @property
     def d(self) -> int:
@@ -90,10 +91,36 @@ def config(name: str, n: Optional[int] = None) -> Problem:
         return Problem(name, 2, 2, (N,) * 4, (0.0, 0.0, -6.0, -6.0),
                        (p4, p4, 6.0, 6.0), "landau", 0.5, 0.5, tol=1e-5,
                        rmax=60, dt=0.2, T=30.0)
+    # --- the paper's own section 4 setups (CFL 5 read as dt = 5 dx / v_max,
+    # unsplit CF3 with 3-point stencils, LoMaC, DIRK-3 start-up + BDF-3)
+    if name in ("landau1d_paper", "stronglandau1d"):
+        N = n or 256
+        weak = name == "landau1d_paper"
+        return Problem(name, 1, 1, (N, N), (0.0, -2.0 * math.pi), (p4, 2.0 * math.pi), "landau",
+                       0.01 if weak else 0.5, 0.5, tol=1e-5 if weak else 1e-4, rmax=64,
+                       dt=5.0 * (p4 / N) / (2.0 * math.pi), T=40.0, order=3,
+                       integrator="dirk3_bdf3")
+    if name == "bumpontail1d":
+        N = n or 256
+        Lx = 20.0 * math.pi / 3.0
+        s2p = math.sqrt(2.0 * math.pi)
+        return Problem(name, 1, 1, (N, N), (0.0, -13.0), (Lx, 13.0), "bumpontail", 0.04, 0.3,
+                       tol=1e-4, rmax=64, dt=5.0 * (Lx / N) / 13.0, T=40.0, order=3,
+                       integrator="dirk3_bdf3", bump=(9.0 / (10.0 * s2p), 2.0 / (10.0 * s2p), 4.5, 0.5))
+    if name == "bumpontail2d":
+        N = n or 128
+        Lx = 20.0 * math.pi / 3.0
+        vt = 2.4
+        return Problem(name, 2, 2, (N,) * 4, (0.0, 0.0, -13.0, -13.0), (Lx, Lx, 13.0, 13.0),
+                       "bumpontail", 0.04, 0.3, tol=1e-4, rmax=60, dt=5.0 * (Lx / N) / 13.0,
+                       T=30.0, integrator="dirk3_bdf3",
+                       bump=(17.0 / (40.0 * math.pi), 3.0 / (40.0 * math.pi * vt), 4.5, vt))
     raise KeyError(name)
 
 
 CONFIG_NAMES = ("landau1d", "landau2d", "twostream2d", "stronglandau2d")
+# section 4 setups of the paper run on the same path
+PAPER_WORKLOADS = ("landau1d_paper", "stronglandau1d", "bumpontail1d", "bumpontail2d")
 
 
 def cell_centres(lo: float, hi: float, n: int) -> np.ndarray:
@@ -111,18 +138,36 @@ def initial_ht(p: Problem) -> dict:
     Landau: f0 = (1 + alpha sum_mu cos(k x_mu)) prod_mu M(v_mu).
     Two-stream (bimodal in v1 only): the v1 factor is
     exp(-(v-v0)^2/2) + exp(-(v+v0)^2/2), normalised with 1/(4 pi) overall.
+    Bump-on-tail (section 4): 1D1V (1 + alpha cos kx)(n_p e^{-v^2/2} +
+    n_b e^{-(v-u)^2/(2 v_t)}); 2D2V (1 + alpha cos kx_1 cos kx_2) / (8 pi)
+    (n_p e^{-|v|^2/2} + n_b e^{-((v_1-u)^2 + v_2^2)/(2 v_t)}).
     """
     xs = [cell_centres(p.lo[m], p.hi[m], p.n[m]) for m in range(p.d)]
     if p.dx == 1:
         x = xs[0]
         Ux = np.stack([np.ones_like(x), np.cos(p.k * x)], axis=1)
-        Uv = _maxwell(xs[1])[:, None]
+        if p.kind == "bumpontail":
+            n_p, n_b, u, vt = p.bump
+            v = xs[1]
+            Uv = (n_p * np.exp(-0.5 * v * v) + n_b * np.exp(-0.5 * (v - u) ** 2 / vt))[:, None]
+        else:
+            Uv = _maxwell(xs[1])[:, None]
         B = np.array([[1.0], [p.alpha]])
         return {"leaves": [Ux, Uv], "root": B}
     U1 = np.stack([np.ones_like(xs[0]), np.cos(p.k * xs[0])], axis=1)
     U2 = np.stack([np.ones_like(xs[1]), np.cos(p.k * xs[1])], axis=1)
     B12 = np.zeros((2, 2, 1))
     B12[0, 0, 0] = 1.0
+    if p.kind == "bumpontail":
+        B12[1, 1, 0] = p.alpha                  # product of the two cosines
+        n_p, n_b, u, vt = p.bump
+        v1, v2 = xs[2], xs[3]
+        U3 = np.stack([np.exp(-0.5 * v1 * v1), np.exp(-0.5 * (v1 - u) ** 2 / vt)], axis=1)
+        U4 = np.stack([np.exp(-0.5 * v2 * v2), np.exp(-0.5 * v2 * v2 / vt)], axis=1)
+        B34 = np.zeros((2, 2, 1))
+        B34[0, 0, 0] = n_p / (8.0 * math.pi)
+        B34[1, 1, 0] = n_b / (8.0 * math.pi)
+        return {"leaves": [U1, U2, U3, U4], "B12": B12, "B34": B34, "root": np.ones((1, 1))}
     B12[1, 0, 0] = p.alpha
     B12[0, 1, 0] = p.alpha
     if p.kind == "landau":

@@ -75,6 +75,9 @@ int main(void) {
   P(slar_lowrank, U) P(slar_lowrank, V)
   printf("slar_cross_info %zu\n", sizeof(slar_cross_info));
   P(slar_cross_info, samples)
+  printf("slar_macro_system %zu\n", sizeof(slar_macro_system));
+  P(slar_macro_system, U) P(slar_macro_system, c) P(slar_macro_system, nstage)
+  P(slar_macro_system, R) P(slar_macro_system, d) P(slar_macro_system, beta)
   return 0;
 }
 """
@@ -95,10 +98,37 @@ def test_ctypes_struct_layout_matches_header(tmp_path):
     out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split("\n") if l)
     from paper_2606_29027_amd import lib as L
     mirror = {"slar_grid": L.Grid, "slar_ht": L.HT, "slar_frames": L.Frames, "slar_adv": L.Adv,
-              "slar_lowrank": L.LowRank, "slar_cross_info": L.CrossInfo}
+              "slar_lowrank": L.LowRank, "slar_cross_info": L.CrossInfo,
+              "slar_macro_system": L.MacroSystem}
     for key, val in out.items():
         if "." in key:
             t, f = key.split(".")
             assert getattr(mirror[t], f).offset == int(val), key
         else:
             assert C.sizeof(mirror[key]) == int(val), key
+
+
+@needs_lib
+def test_host_time_integrator_weights_match_oracle():
+    """The library's DIRK-3 tableau and variable-step BDF weights (host
+    code, no GPU) equal the oracle's, including unequal steps; times that do
+    not decrease are rejected."""
+    import numpy as np
+    from oracle import timeint as TI
+    from paper_2606_29027_amd import lib as L
+    A, c = L.slar_dirk3_tableau()
+    Ao, _, co = TI.dirk3()
+    # gamma: bisection here, a companion-matrix eigenvalue in the oracle; both
+    # agree to ~1e-15, and b1, b2 scale that by at most ~4
+    assert np.allclose(A, Ao, rtol=0, atol=1e-14) and np.allclose(c, co, rtol=0, atol=1e-14)
+    rng = np.random.default_rng(3)
+    for k in (1, 2, 3):
+        for _ in range(5):
+            t = np.cumsum(np.concatenate([[0.0], rng.uniform(0.05, 0.4, k)]))[::-1] + 1.7
+            cw, beta = L.slar_bdf_weights(list(t))
+            cwo, betao = TI.bdf(t)
+            assert np.allclose(cw, cwo, rtol=1e-13, atol=0) and abs(beta - betao) < 1e-15
+    with pytest.raises(L.SlarError):
+        L.slar_bdf_weights([1.0, 1.0, 0.5])
+    with pytest.raises(L.SlarError):
+        L.slar_bdf_weights([1.0, 0.9, 0.8, 0.7, 0.6])

@@ -497,3 +497,33 @@ def test_dirk3_bdf3_sequencing_converges_at_third_order():
             errs.append(abs(u - np.exp(-lam * T)))
         rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
         assert all(2.7 < r < 3.3 for r in rates), (pattern, errs, rates)
+
+
+@pytest.mark.parametrize("name,N", [("landau1d_paper", 32), ("stronglandau1d", 24),
+                                    ("bumpontail1d", 40), ("bumpontail2d", 10)])
+def test_paper_workload_initial_data(name, N):
+    """The low-rank initial HT of each section 4 setup reconstructs the
+    printed initial condition at every cell centre, and its step is the
+    CFL-5 step dt = 5 dx / v_max."""
+    p = SI.config(name, n=N)
+    F = HT.full(SI.initial_ht(p))
+    xs = [SI.cell_centres(p.lo[m], p.hi[m], p.n[m]) for m in range(p.d)]
+    G_ = np.meshgrid(*xs, indexing="ij")
+    if p.dx == 1:
+        x, v = G_
+        if p.kind == "landau":
+            f = (1 + p.alpha * np.cos(0.5 * x)) * np.exp(-v * v / 2) / math.sqrt(2 * math.pi)
+        else:
+            s2p = math.sqrt(2 * math.pi)
+            f = (1 + 0.04 * np.cos(0.3 * x)) * (9 / (10 * s2p) * np.exp(-v * v / 2)
+                                               + 2 / (10 * s2p) * np.exp(-(v - 4.5) ** 2 / (2 * 0.5)))
+    else:
+        x1, x2, v1, v2 = G_
+        vt = 2.4
+        f = (1 + 0.04 * np.cos(0.3 * x1) * np.cos(0.3 * x2)) / (2 * math.sqrt(2 * math.pi)) ** 2 * (
+            17 / (40 * math.pi) * np.exp(-(v1 * v1 + v2 * v2) / 2)
+            + 3 / (40 * math.pi * vt) * np.exp(-((v1 - 4.5) ** 2 + v2 * v2) / (2 * vt)))
+    assert np.abs(F - f).max() < 1e-15 * max(1.0, np.abs(f).max())
+    dx = (p.hi[0] - p.lo[0]) / p.n[0]
+    assert abs(p.dt - 5 * dx / p.hi[p.dx]) < 1e-15
+    assert p.integrator == "dirk3_bdf3" and not p.split and p.order == 3
