@@ -33,7 +33,7 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense matrix-core peak
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_k_aca_col_stronglandau2d_128.md")
 # sources that define the column-fiber kernel; the counter-measured traffic
 # is reported only for the source state it was measured on
-KERNEL_SOURCES = ["aca.h", "frame_sampler.h", "sl_device.h", "cross.hip"]
+KERNEL_SOURCES = ["aca.h", "frame_sampler.h", "sl_device.h"]
 
 
 def kernel_source_hash() -> str:
@@ -293,7 +293,10 @@ def main():
         torch.cuda.synchronize()
         n0 = len(s.stats)
         infos = []
-        L.slar_timing_enable(s.ws, True)
+        # every 8th cross iteration carries dispatch events: the average
+        # kernel duration without the ~2 ms per step that timing every
+        # dispatch adds to the pipeline
+        L.slar_timing_enable(s.ws, True, every=8)
         s.tphase = {k: 0.0 for k in s.tphase}
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -303,7 +306,11 @@ def main():
         tim = L.slar_timing_read(s.ws)
         L.slar_timing_enable(s.ws, False)
         samples = sum(st["samples"] for st in s.stats[n0:])
-        kern_s = (tim["row_ms"] + tim["col_ms"]) * 1e-3
+        # fiber-kernel time of all iterations: sampled average per launch
+        # times the iterations that ran
+        n_it = sum(st["iters"] for st in s.stats[n0:])
+        per_it = (tim["row_ms"] / max(tim["row_launches"], 1) + tim["col_ms"] / max(tim["col_launches"], 1))
+        kern_s = n_it * per_it * 1e-3
         phase = {k: 1e3 * v / args.steps for k, v in s.tphase.items()}
         phase["other"] = 1e3 * elapsed / args.steps - sum(phase.values())
         runs[name] = {"value": samples / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,

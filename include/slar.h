@@ -318,10 +318,15 @@ slar_status slar_cnn_train_step(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, 
 slar_status slar_record_krylov(slar_workspace* ws, float* features, float* targets, int32_t capacity);
 int32_t slar_recorded_pairs(const slar_workspace* ws);
 
-/* Timing of the two sampling kernels of slar_cross_update: while enabled,
- * every row-fiber and column-fiber launch carries start/stop HIP events on
- * its own dispatch (kernel duration, no marker packets in between);
- * enabling clears the counters.  slar_timing_read fills host out[8] = {row
+/* Timing of the two sampling kernels of slar_cross_update.  on = 0 turns
+ * it off; on = n >= 1 times every n-th iteration of each cross
+ * approximation (iterations n-1, 2n-1, ...): its row-fiber and
+ * column-fiber launches carry start/stop HIP events on their own dispatch
+ * (kernel duration, no marker packets in between).  Each timed dispatch
+ * costs a few microseconds of pipeline time, so n > 1 keeps the timed
+ * program close to the untimed one while the sampled launches still give
+ * the average duration.  Enabling clears the counters.  Only iterations
+ * that did their work are counted.  slar_timing_read fills host out[8] = {row
  * ms, row launches, row algorithmic bytes, column ms, column launches,
  * column algorithmic bytes, 0, 0}; algorithmic bytes per sampled entry =
  * both stencil gathers of the frame tables + 16 k bytes of previous cross

@@ -576,4 +576,12 @@ __device__ void aca_fin_body(const AcaInst& I) {
   }
 }
 
+// --------------------------------------------------- single-instance kernels
+template <typename T, int W, int DX>
+__global__ __launch_bounds__(FS_THREADS) void k_aca_row(AcaInst I) { aca_row_body<T, W, DX>(I, blockIdx.x); }
+template <typename T, int W, int DX>
+__global__ __launch_bounds__(FS_THREADS) void k_aca_col(AcaInst I) { aca_col_body<T, W, DX>(I, blockIdx.x); }
+template <typename T, int W, int DX>
+__global__ __launch_bounds__(FS_THREADS) void k_aca_fin(AcaInst I) { aca_fin_body<T, W, DX>(I); }
+
 }  // namespace slar

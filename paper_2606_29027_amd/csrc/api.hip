@@ -104,6 +104,8 @@ slar_status slar_workspace_destroy(slar_workspace* w) {
   for (hipEvent_t e : ws.events) (void)hipEventDestroy(e);
   if (ws.ev_fork) (void)hipEventDestroy(ws.ev_fork);
   if (ws.ev_join) (void)hipEventDestroy(ws.ev_join);
+  for (hipEvent_t e : ws.poll_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ws.aux) (void)hipStreamDestroy(ws.aux);
   if (ws.aca_ctl_host) (void)hipHostFree(ws.aca_ctl_host);
   if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
@@ -153,7 +155,9 @@ slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspa
   dalloc((void**)&ws.psi, sizeof(double) * G.nv * nm);
   dalloc((void**)&ws.lm, sizeof(double) * ws.lm_elems);
   dalloc((void**)&ws.kry, sizeof(double) * ws.kry_elems);
-  if (ok && hipHostMalloc(&ws.aca_ctl_host, aca_ctl_bytes(), 0) != hipSuccess) ok = false;
+  if (ok && hipHostMalloc(&ws.aca_ctl_host, 3 * aca_ctl_bytes(), 0) != hipSuccess) ok = false;
+  for (hipEvent_t& e : ws.poll_ev)
+    if (ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
   if (ok && hipHostMalloc(&ws.host_pinned, 65536, 0) != hipSuccess) ok = false;
   if (ok && hipStreamCreateWithFlags(&ws.aux, hipStreamNonBlocking) != hipSuccess) ok = false;
   if (ok && hipEventCreateWithFlags(&ws.ev_fork, hipEventDisableTiming) != hipSuccess) ok = false;
@@ -398,7 +402,9 @@ slar_status slar_timing_enable(slar_workspace* w, int32_t on) {
         return SLAR_E_HIP;
       }
   }
+  if (on < 0) return SLAR_E_INVAL;
   ws.timing = on != 0;
+  ws.timing_every = on > 0 ? on : 1;
   for (double& v : ws.tstat) v = 0.0;
   return SLAR_OK;
 }

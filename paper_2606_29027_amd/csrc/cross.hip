@@ -27,14 +27,6 @@
 
 namespace slar {
 
-// --------------------------------------------------- single-instance kernels
-template <typename T, int W, int DX>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_row(AcaInst I) { aca_row_body<T, W, DX>(I, blockIdx.x); }
-template <typename T, int W, int DX>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_col(AcaInst I) { aca_col_body<T, W, DX>(I, blockIdx.x); }
-template <typename T, int W, int DX>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_fin(AcaInst I) { aca_fin_body<T, W, DX>(I); }
-
 size_t aca_ctl_bytes() { return sizeof(AcaCtl); }
 
 template <typename T, int W, int DX>
@@ -105,41 +97,54 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   const int rx = (G.dx == 2) ? adv.order * adv.order : adv.order;
   const double gather_bytes = 2.0 * rx * ldt * (dt == SLAR_F32 ? 4.0 : 8.0) + 8.0;
   const bool timing = ws->timing && (int)ws->events.size() >= 4 * maxit;
-  int k_known = 0, it_timed = 0;
-  auto harvest = [&](int upto) -> hipError_t {
-    for (; it_timed < upto; ++it_timed) {
-      float ms_row = 0.f, ms_col = 0.f;
-      HIP_CHK(hipEventElapsedTime(&ms_row, ws->events[4 * it_timed], ws->events[4 * it_timed + 1]));
-      HIP_CHK(hipEventElapsedTime(&ms_col, ws->events[4 * it_timed + 2], ws->events[4 * it_timed + 3]));
-      const double per = gather_bytes + 16.0 * k_known;
-      ws->tstat[0] += ms_row; ws->tstat[1] += 1; ws->tstat[2] += per * G.nv;
-      ws->tstat[3] += ms_col; ws->tstat[4] += 1; ws->tstat[5] += per * G.nx;
+  // Iterations are enqueued in chunks of CH; after each chunk a copy of the
+  // control block goes to one of two pinned slots with an event.  The host
+  // waits for the previous chunk's copy only after the next chunk is
+  // queued, so the device never idles on a poll.  Iterations enqueued after
+  // the stop see phase != RUN and exit at once (their launches did no work
+  // and are left out of the timing below).
+  constexpr int CH = 4;
+  auto timed = [&](int q) { return timing && (q % ws->timing_every) == ws->timing_every - 1; };
+  AcaCtl* ring = hc + 1;
+  int it = 0, pending = -1;
+  bool stop = false;
+  while (it < maxit && !stop) {
+    const int c = it / CH;
+    for (const int end = std::min(it + CH, maxit); it < end; ++it) {
+      hipError_t e;
+      if (dt == SLAR_F32)
+        e = aca_iter_dispatch<float>(s, G, A, ws->X32, ws->P32, ldt, r, ctl, out->U, out->V,
+                                     ws->used, ws->aca_part, nprobe, probes,
+                                     timed(it) ? &ws->events[4 * it] : nullptr);
+      else
+        e = aca_iter_dispatch<double>(s, G, A, X64, P64, ldt, r, ctl, out->U, out->V, ws->used,
+                                      ws->aca_part, nprobe, probes,
+                                      timed(it) ? &ws->events[4 * it] : nullptr);
+      if (e != hipSuccess) return SLAR_E_HIP;
     }
-    return hipSuccess;
-  };
-  int it = 0;
-  for (; it < maxit; ++it) {
-    hipError_t e;
-    if (dt == SLAR_F32)
-      e = aca_iter_dispatch<float>(s, G, A, ws->X32, ws->P32, ldt, r, ctl, out->U, out->V,
-                                   ws->used, ws->aca_part, nprobe, probes,
-                                   timing ? &ws->events[4 * it] : nullptr);
-    else
-      e = aca_iter_dispatch<double>(s, G, A, X64, P64, ldt, r, ctl, out->U, out->V, ws->used,
-                                    ws->aca_part, nprobe, probes,
-                                    timing ? &ws->events[4 * it] : nullptr);
-    if (e != hipSuccess) return SLAR_E_HIP;
-    if ((it % 4) == 3 || it == maxit - 1) {
-      HIP_TRY(hipMemcpyAsync(hc, ctl, sizeof(AcaCtl), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      if (timing && harvest(it + 1) != hipSuccess) return SLAR_E_HIP;
-      k_known = hc->k;
-      if (hc->phase == ACA_DONE) { ++it; break; }
+    HIP_TRY(hipMemcpyAsync(&ring[c & 1], ctl, sizeof(AcaCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ws->poll_ev[c & 1], s));
+    if (pending >= 0) {
+      HIP_TRY(hipEventSynchronize(ws->poll_ev[pending & 1]));
+      stop = ring[pending & 1].phase == ACA_DONE;
     }
+    pending = c;
   }
   HIP_TRY(hipMemcpyAsync(hc, ctl, sizeof(AcaCtl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (timing && harvest(it) != hipSuccess) return SLAR_E_HIP;
+  if (timing) {
+    // iterations 0 .. iters-1 did their work; the rank grows by one per
+    // iteration except in those that met a reproduced row
+    for (int q = 0; q < std::min(it, hc->iters); ++q) {
+      if (!timed(q)) continue;
+      float ms_row = 0.f, ms_col = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms_row, ws->events[4 * q], ws->events[4 * q + 1]));
+      HIP_TRY(hipEventElapsedTime(&ms_col, ws->events[4 * q + 2], ws->events[4 * q + 3]));
+      const double per = gather_bytes + 16.0 * std::min(q, hc->k);
+      ws->tstat[0] += ms_row; ws->tstat[1] += 1; ws->tstat[2] += per * G.nv;
+      ws->tstat[3] += ms_col; ws->tstat[4] += 1; ws->tstat[5] += per * G.nx;
+    }
+  }
   out->k = hc->k;
   if (info) {
     info->rank = hc->k;

@@ -256,17 +256,23 @@ __global__ __launch_bounds__(256) void k_chol_inv(int k, const double* __restric
     }
     __syncthreads();
   }
-  // inverse of lower triangular L, column by column (independent columns)
-  for (int j = t; j < k; j += blockDim.x) {
-    for (int i = 0; i < k; ++i) Li[i][j] = 0.0;
-    Li[j][j] = 1.0 / L[j][j];
-    for (int i = j + 1; i < k; ++i) {
-      double acc = 0.0;
-      for (int m = j; m < i; ++m) acc += L[i][m] * Li[m][j];
-      Li[i][j] = -acc / L[i][i];
-    }
-  }
+  // inverse of lower triangular L by forward elimination on [L | I]: after
+  // step c row c of Li is row c of L^-1 (columns j <= c; the rest stay 0)
+  for (int i = t >> 3; i < k; i += blockDim.x >> 3)
+    for (int j = t & 7; j < k; j += 8) Li[i][j] = (i == j) ? 1.0 : 0.0;
   __syncthreads();
+  for (int c = 0; c < k; ++c) {
+    const double inv = 1.0 / L[c][c];
+    for (int j = t; j <= c; j += blockDim.x) Li[c][j] *= inv;
+    __syncthreads();
+    const int m = k - c - 1;
+    for (int w = t; w < m * 8; w += blockDim.x) {     // eight threads per row
+      const int i = c + 1 + (w >> 3);
+      const double lic = L[i][c];
+      for (int j = w & 7; j <= c; j += 8) Li[i][j] -= lic * Li[c][j];
+    }
+    __syncthreads();
+  }
   for (int e = t; e < k * k; e += blockDim.x) {
     const int i = e / k, j = e % k;
     Linv[e] = Li[i][j] / d[j];

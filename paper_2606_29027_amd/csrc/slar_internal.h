@@ -40,7 +40,8 @@ struct Workspace {
   int ld32 = 0;
   // cross approximation
   void* aca_ctl = nullptr;       // AcaCtl
-  void* aca_ctl_host = nullptr;  // pinned copy
+  void* aca_ctl_host = nullptr;  // pinned copies: [0] final, [1], [2] polling ring
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};   // completion of the ring copies
   double* aca_part = nullptr;    // partial reductions
   unsigned char* used = nullptr; // [Nx]
   double* resid = nullptr;       // [max(Nx,Nv)]
@@ -74,6 +75,7 @@ struct Workspace {
   // kernels: [0] row ms, [1] row launches, [2] row bytes, [3] col ms,
   // [4] col launches, [5] col bytes
   bool timing = false;
+  int timing_every = 1;          // time iterations every-1, 2 every-1, ...
   std::vector<hipEvent_t> events;
   double tstat[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // optional recording of (J z, z) pairs for training the preconditioner

@@ -385,8 +385,9 @@ def slar_recorded_pairs(ws) -> int:
     return int(load().slar_recorded_pairs(ws.h))
 
 
-def slar_timing_enable(ws, on: bool):
-    _check(load().slar_timing_enable(ws.h, 1 if on else 0), "slar_timing_enable")
+def slar_timing_enable(ws, on, every: int = 1):
+    """on: False / True; every: time every n-th cross iteration."""
+    _check(load().slar_timing_enable(ws.h, int(every) if on else 0), "slar_timing_enable")
 
 
 def slar_timing_read(ws):
