@@ -52,7 +52,7 @@ typedef enum { SLAR_F32 = 0, SLAR_F64 = 1 } slar_dtype;
 /* Uniform periodic phase-space grid (section 3.1). */
 typedef struct {
   int32_t dx, dv;       /* 1,1 or 2,2                                      */
-  int32_t n[4];         /* cells per dimension, x first; 2 <= n <= 128      */
+  int32_t n[4];         /* cells per dimension, x first; 4 <= n <= 128 (2D2V) or 512 (1D1V) */
   double lo[4], hi[4];  /* domain [lo, hi) per dimension                    */
 } slar_grid;
 

@@ -403,7 +403,8 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
 // values of both fibers, and the per-block dot products) is loaded in one
 // pass of independent loads; the rest works from LDS.
 constexpr int FIN_NB = 256;   // blocks per fiber staged in LDS
-static_assert(FIN_NB * FS_SAMPLES >= SLAR_NMAX * SLAR_NMAX, "every fiber fits the staged partials");
+static_assert(FIN_NB * FS_SAMPLES >= SLAR_NMAX * SLAR_NMAX && FIN_NB * FS_SAMPLES >= SLAR_NMAX_1D,
+              "every fiber fits the staged partials");
 
 template <typename T, int W, int DX>
 __device__ void aca_fin_body(const AcaInst& I) {

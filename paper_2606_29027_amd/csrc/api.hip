@@ -35,7 +35,7 @@ static bool grid_ok(const slar_grid* g) {
   if (!g) return false;
   if (g->dx != g->dv || (g->dx != 1 && g->dx != 2)) return false;
   for (int m = 0; m < g->dx + g->dv; ++m) {
-    if (g->n[m] < 4 || g->n[m] > SLAR_NMAX) return false;
+    if (g->n[m] < 4 || g->n[m] > (g->dx == 1 ? SLAR_NMAX_1D : SLAR_NMAX)) return false;
     if (!(g->hi[m] > g->lo[m]) || !std::isfinite(g->lo[m]) || !std::isfinite(g->hi[m])) return false;
   }
   return true;
@@ -149,8 +149,8 @@ slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspa
   dalloc((void**)&ws.used, G.nx);
   dalloc((void**)&ws.dwork, sizeof(double) * ws.dwork_elems);
   dalloc((void**)&ws.small, sizeof(double) * ws.small_elems);
-  dalloc((void**)&ws.tw[0], sizeof(double) * 2 * SLAR_NMAX);
-  dalloc((void**)&ws.tw[1], sizeof(double) * 2 * SLAR_NMAX);
+  dalloc((void**)&ws.tw[0], sizeof(double) * 2 * SLAR_NLINE);
+  dalloc((void**)&ws.tw[1], sizeof(double) * 2 * SLAR_NLINE);
   dalloc((void**)&ws.cbuf, sizeof(double) * ws.cbuf_elems);
   dalloc((void**)&ws.psi, sizeof(double) * G.nv * nm);
   dalloc((void**)&ws.lm, sizeof(double) * ws.lm_elems);

@@ -31,8 +31,8 @@ void host_twiddles(int n, std::vector<double>& tw) {
 __global__ void k_dft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
                            const double* __restrict__ realin, double2* __restrict__ out,
                            const double* __restrict__ tw) {
-  __shared__ double2 line[SLAR_NMAX];
-  __shared__ double2 w[SLAR_NMAX];
+  __shared__ double2 line[SLAR_NLINE];
+  __shared__ double2 w[SLAR_NLINE];
   const int b = blockIdx.y;
   const int L = axis == 1 ? n1 : n0;          // line length
   const int other = blockIdx.x;               // index along the other axis
@@ -59,12 +59,12 @@ __global__ void k_dft_line(int n0, int n1, int axis, double sign, const double2*
   }
 }
 
-// Radix-2 Cooley--Tukey FFT of one line in LDS (n a power of two <= 128):
+// Radix-2 Cooley--Tukey FFT of one line in LDS (n a power of two <= SLAR_NLINE):
 // bit-reversed load, log2(n) butterfly stages, one butterfly per thread.
 __global__ void k_fft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
                            const double* __restrict__ realin, double2* __restrict__ out,
                            const double* __restrict__ tw, int logL) {
-  __shared__ double2 a[SLAR_NMAX];
+  __shared__ double2 a[SLAR_NLINE];
   const int b = blockIdx.y;
   const int L = axis == 1 ? n1 : n0;
   const int other = blockIdx.x;

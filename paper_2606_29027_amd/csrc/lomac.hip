@@ -29,7 +29,7 @@ LmLayout lm_layout(const GridDev& G) {
   LmLayout L{};
   const int K = G.dv + 2, nm = nmom_of(G.dv);
   size_t o = 0;
-  L.gs = o; o += 2 * 3 * SLAR_NMAX;
+  L.gs = o; o += 2 * 3 * SLAR_NLINE;
   L.scal = o; o += 32;
   L.Q = o; o += (size_t)K * G.nv;
   L.psiQ = o; o += (size_t)nm * K;
@@ -51,9 +51,9 @@ __global__ void k_gram_schmidt(GridDev g, const double* u0, int ld0, const doubl
   const double h = g.h[dim];
   const double* u = mu == 0 ? u0 : u1;
   const int ld = mu == 0 ? ld0 : ld1;
-  double* om = gs + (size_t)mu * 3 * SLAR_NMAX;
-  double* q1 = om + SLAR_NMAX;
-  double* q2 = q1 + SLAR_NMAX;
+  double* om = gs + (size_t)mu * 3 * SLAR_NLINE;
+  double* q1 = om + SLAR_NLINE;
+  double* q2 = q1 + SLAR_NLINE;
   __shared__ double red[256];
   const int t = threadIdx.x;
   auto bsum = [&](double v) -> double {
@@ -67,23 +67,44 @@ __global__ void k_gram_schmidt(GridDev g, const double* u0, int ld0, const doubl
     __syncthreads();
     return r;
   };
-  double vv = 0.0, w = 0.0;
-  if (t < n) {
-    vv = g.lo[dim] + ((double)t + 0.5) * h;
-    w = fmax(fabs(u[(size_t)t * ld]), delta);
-    om[t] = w;
+  // cells c = t, t + blockDim.x, ... (n <= SLAR_NLINE); a thread's partial
+  // sums run over its cells in order, then over the block
+  const int nb = blockDim.x;
+  auto wof = [&](int c) { return fmax(fabs(u[(size_t)c * ld]), delta); };
+  auto vof = [&](int c) { return g.lo[dim] + ((double)c + 0.5) * h; };
+  double p0 = 0.0, pg = 0.0, pe = 0.0;
+  for (int c = t; c < n; c += nb) {
+    const double w = wof(c), vv = vof(c);
+    const double vo = vv * w, v2o = vv * vv * w;
+    om[c] = w;
+    p0 += w * w * h / w;
+    pg += vo * w * h / w;
+    pe += v2o * w * h / w;
   }
-  const double vo = vv * w, v2o = vv * vv * w;
-  // <p,q> = sum p q h / omega
-  const double n0 = bsum(t < n ? w * w * h / w : 0.0);
-  const double gamma = bsum(t < n ? vo * w * h / w : 0.0) / n0;
-  const double q1v = vo - gamma * w;
-  const double eta = bsum(t < n ? v2o * w * h / w : 0.0) / n0;
-  const double n1 = bsum(t < n ? q1v * q1v * h / w : 0.0);
-  const double beta = bsum(t < n ? v2o * q1v * h / w : 0.0) / n1;
-  const double q2v = v2o - eta * w - beta * q1v;
-  const double n2 = bsum(t < n ? q2v * q2v * h / w : 0.0);
-  if (t < n) { q1[t] = q1v; q2[t] = q2v; }
+  const double n0 = bsum(p0);
+  const double gamma = bsum(pg) / n0;
+  const double eta = bsum(pe) / n0;
+  double p1 = 0.0, pb = 0.0;
+  for (int c = t; c < n; c += nb) {
+    const double w = wof(c), vv = vof(c);
+    const double vo = vv * w, v2o = vv * vv * w;
+    const double q1v = vo - gamma * w;
+    p1 += q1v * q1v * h / w;
+    pb += v2o * q1v * h / w;
+  }
+  const double n1 = bsum(p1);
+  const double beta = bsum(pb) / n1;
+  double p2 = 0.0;
+  for (int c = t; c < n; c += nb) {
+    const double w = wof(c), vv = vof(c);
+    const double vo = vv * w, v2o = vv * vv * w;
+    const double q1v = vo - gamma * w;
+    const double q2v = v2o - eta * w - beta * q1v;
+    q1[c] = q1v;
+    q2[c] = q2v;
+    p2 += q2v * q2v * h / w;
+  }
+  const double n2 = bsum(p2);
   if (t == 0) {
     double* sc = scal + mu * 8;
     sc[0] = gamma; sc[1] = eta; sc[2] = beta; sc[3] = n0; sc[4] = n1; sc[5] = n2;
@@ -112,18 +133,18 @@ __global__ void k_qbasis(GridDev g, const double* gs, double* scal, double* Q) {
   if (dv == 1) {
     const double* om = gs;
     q[0] = om[J];
-    q[1] = om[SLAR_NMAX + J];
-    q[2] = om[2 * SLAR_NMAX + J];
+    q[1] = om[SLAR_NLINE + J];
+    q[2] = om[2 * SLAR_NLINE + J];
     return;
   }
   const int a = J / g.n[3], b = J % g.n[3];
   const double* A = gs;                    // mu = 0: omega, q1, q2
-  const double* B = gs + 3 * SLAR_NMAX;    // mu = 1
+  const double* B = gs + 3 * SLAR_NLINE;    // mu = 1
   const double w0 = A[a], w1 = B[b];
   q[0] = w0 * w1;
-  q[1] = A[SLAR_NMAX + a] * w1;
-  q[2] = w0 * B[SLAR_NMAX + b];
-  q[3] = A[2 * SLAR_NMAX + a] * w1 + w0 * B[2 * SLAR_NMAX + b];
+  q[1] = A[SLAR_NLINE + a] * w1;
+  q[2] = w0 * B[SLAR_NLINE + b];
+  q[3] = A[2 * SLAR_NLINE + a] * w1 + w0 * B[2 * SLAR_NLINE + b];
   (void)K;
 }
 

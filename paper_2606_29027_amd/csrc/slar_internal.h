@@ -9,7 +9,9 @@
 #include "sl_device.h"
 
 #define SLAR_KMAX 72      // largest cross rank / frame width handled
-#define SLAR_NMAX 128     // largest cells per dimension
+#define SLAR_NMAX 128     // largest cells per dimension of a 2D2V grid
+#define SLAR_NMAX_1D 512  // largest cells per dimension of a 1D1V grid
+#define SLAR_NLINE 512    // longest 1D line: FFT lines, 1D velocity bases
 #define SLAR_MAXMOM 9     // moments for dv = 2
 
 #define HIP_TRY(expr)                                       \
