@@ -15,6 +15,14 @@ against rates fixed by linear theory, not by the oracle:
   which dominate the field until t ~ 12 (the growth rate measured over
   one time unit alternates in sign there); the fit takes t in [15, 25],
   after the growing root dominates and before saturation (it reads 0.224).
+* 1D1V bump-on-tail (the section 4 setup: bulk density 0.9, bump density
+  n_b sqrt(2 pi v_t) at u = 4.5 with variance v_t = 0.5, k = 0.3): the
+  only unstable root of 1 + sum_s (n_s / (k^2 s_s^2)) (1 + zeta_s Z(zeta_s))
+  = 0, zeta_s = (omega / k - u_s) / (sqrt 2 s_s), is omega = 0.9587 +
+  0.1917 i.  With the setup's alpha = 0.04 the field saturates by t ~ 18,
+  while the start-up transient still dominates; alpha = 1e-3 leaves the
+  single growing travelling wave alone for t in [15, 30] (fit 0.188 on
+  128^2).
 Z is the plasma dispersion function, Z(zeta) = i sqrt(pi) w(zeta) with the
 Faddeeva function w.  Grids are reduced to 32^4 so a run takes seconds,
 and the Landau run uses dt = 0.1: at the workload's dt = 0.2 the time
@@ -52,6 +60,25 @@ def _root(k, v0, guess):
             zeta = (w / k - b) / math.sqrt(2)
             Z = 1j * math.sqrt(math.pi) * wofz(zeta)
             D += (1 + zeta * Z) / (k * k * len(beams))
+        return [D.real, D.imag]
+
+    r = fsolve(f, guess, xtol=1e-13)
+    return r[0], r[1]
+
+
+def _root_maxwellians(k, comps, guess):
+    """Root of the dispersion relation of a sum of drifting Maxwellians,
+    comps = [(density, drift, variance)]."""
+    from scipy.special import wofz
+    from scipy.optimize import fsolve
+
+    def f(z):
+        w = complex(z[0], z[1])
+        D = 1.0
+        for n, u, s2 in comps:
+            zeta = (w / k - u) / math.sqrt(2 * s2)
+            Z = 1j * math.sqrt(math.pi) * wofz(zeta)
+            D += n / (k * k * s2) * (1 + zeta * Z)
         return [D.real, D.imag]
 
     r = fsolve(f, guess, xtol=1e-13)
@@ -96,4 +123,16 @@ def test_two_stream_growth_rate_2d2v():
     le = np.log(ee)
     sel = (t >= 15.0) & (t <= 25.0)
     slope = np.polyfit(t[sel], le[sel], 1)[0]
+    assert abs(slope / 2 - gam) < 0.05 * gam, (slope / 2, gam)
+
+
+def test_bump_on_tail_growth_rate_1d1v():
+    p = SI.config("bumpontail1d", n=128).with_(alpha=1e-3)
+    n_p, n_b, u, vt = p.bump
+    comps = [(n_p * math.sqrt(2 * math.pi), 0.0, 1.0), (n_b * math.sqrt(2 * math.pi * vt), u, vt)]
+    om, gam = _root_maxwellians(p.k, comps, [1.0, 0.2])
+    assert abs(om - 0.9587) < 1e-3 and abs(gam - 0.1917) < 1e-3
+    ee, t = _run(p, int(round(30.0 / p.dt)))
+    sel = (t >= 15.0) & (t <= 30.0)
+    slope = np.polyfit(t[sel], np.log(ee[sel]), 1)[0]
     assert abs(slope / 2 - gam) < 0.05 * gam, (slope / 2, gam)
