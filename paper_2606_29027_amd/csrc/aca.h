@@ -1,7 +1,7 @@
 // Device side of the adaptive cross approximation: control block, the
 // per-instance argument record and the three per-iteration bodies (row
 // fiber, column fiber, bookkeeping).  The bodies take one instance record
-// and one 64-sample tile index, so the same code serves one launch per
+// and one fiber tile index, so the same code serves one launch per
 // instance and the persistent multi-instance launches.
 #pragma once
 #include <cmath>
@@ -23,9 +23,14 @@ struct AcaCtl {
 };
 
 constexpr int ACA_MAXBLK = 1024;   // partial slots
+// Entries per fiber block (a lane quad per foot in a 256-thread block).  A
+// fiber has at most 128^2 entries, i.e. 256 blocks.  Tiles of 32 (two
+// blocks per CU) left the sampling launch as long (each block's time is
+// the latency of its feet and gathers) and made the bookkeeping launch
+// stage twice the candidates, so 64 it is.
+constexpr int ACA_TILE = 64;
 
 // Everything one cross approximation reads or writes (one instance).
-// Fibers have at most 128^2 samples, so at most 256 blocks of 64.
 struct AcaInst {
   GridDev g;
   AdvDev a;
@@ -185,8 +190,8 @@ __device__ int pivot_from_parts(const double* x, const double* pmax, const doubl
   if (cand < n && pval[bb] >= thr) return cand;
   // the block maximum is close to M but below it: rescan that block's range
   int best = n;
-  const int e = bb * FS_SAMPLES + t;
-  if (t < FS_SAMPLES && e < n && !skip(e) && fabs(x[e]) >= thr) best = e;
+  const int e = bb * ACA_TILE + t;
+  if (t < ACA_TILE && e < n && !skip(e) && fabs(x[e]) >= thr) best = e;
   for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
   if ((t & 63) == 0) redi[t >> 6] = best;
   __syncthreads();
@@ -232,8 +237,8 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
   if (s_phase != ACA_RUN) return;
   const int i = s_i, k = s_k;
   const int Nx = g.nx, Nv = g.nv;
-  const int J0 = tile * FS_SAMPLES;
-  const int ns = min(FS_SAMPLES, Nv - J0);
+  const int J0 = tile * ACA_TILE;
+  const int ns = min(ACA_TILE, Nv - J0);
   const int wv = t >> 6, ln = t & 63;
   // earlier row vectors v_l[J] and u_l[i] (loads in flight during the feet)
   double vl[ACA_LREG], ui[ACA_LREG];
@@ -316,8 +321,8 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
   if (s_phase != ACA_RUN) return;
   const int i = s_i, k = s_k;
   const int Nx = g.nx, Nv = g.nv;
-  const int I0 = tile * FS_SAMPLES;
-  const int ns = min(FS_SAMPLES, Nx - I0);
+  const int I0 = tile * ACA_TILE;
+  const int ns = min(ACA_TILE, Nx - I0);
   const int wv = t >> 6, ln = t & 63;
   // earlier column vectors u_l[I] (independent of the pivot: issued first)
   double ul[ACA_LREG];
@@ -403,7 +408,8 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
 // values of both fibers, and the per-block dot products) is loaded in one
 // pass of independent loads; the rest works from LDS.
 constexpr int FIN_NB = 256;   // blocks per fiber staged in LDS
-static_assert(FIN_NB * FS_SAMPLES >= SLAR_NMAX * SLAR_NMAX && FIN_NB * FS_SAMPLES >= SLAR_NMAX_1D,
+static_assert(ACA_TILE <= FS_SAMPLES, "a fiber tile fits the sampler's LDS rows");
+static_assert(FIN_NB * ACA_TILE >= SLAR_NMAX * SLAR_NMAX && FIN_NB * ACA_TILE >= SLAR_NMAX_1D,
               "every fiber fits the staged partials");
 
 template <typename T, int W, int DX>
@@ -433,11 +439,11 @@ __device__ void aca_fin_body(const AcaInst& I) {
   const int t = threadIdx.x;
   if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; s_tol = ctl->tol; s_norm2 = ctl->norm2; }
   const double* pc = part + (size_t)PCOL * ACA_MAXBLK;
-  if (t < nbrow) {
-    rmax_[t] = part[t]; ridx_[t] = part[ACA_MAXBLK + t]; rval_[t] = part[(size_t)PVAL * ACA_MAXBLK + t];
+  for (int b = t; b < nbrow; b += blockDim.x) {
+    rmax_[b] = part[b]; ridx_[b] = part[ACA_MAXBLK + b]; rval_[b] = part[(size_t)PVAL * ACA_MAXBLK + b];
   }
-  if (t < nbcol) {
-    cmax_[t] = pc[t]; cidx_[t] = pc[ACA_MAXBLK + t]; cval_[t] = pc[(size_t)PVAL * ACA_MAXBLK + t];
+  for (int b = t; b < nbcol; b += blockDim.x) {
+    cmax_[b] = pc[b]; cidx_[b] = pc[ACA_MAXBLK + b]; cval_[b] = pc[(size_t)PVAL * ACA_MAXBLK + b];
   }
   __syncthreads();
   if (s_phase != ACA_RUN) return;

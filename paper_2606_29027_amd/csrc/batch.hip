@@ -3,7 +3,7 @@
 //
 // Cross approximation: one persistent launch per phase serves every
 // instance.  A fixed grid walks a table of work items (instance, first
-// 64-sample tile, tile count); each instance keeps its own control block and
+// fiber tile, tile count); each instance keeps its own control block and
 // partial-sum slots, so the per-tile arithmetic and the pivot decisions are
 // those of the one-instance kernels, whatever block runs a tile.  A chunk of
 // iterations (row / column / bookkeeping launches) plus an active-instance
@@ -38,7 +38,7 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
 
 struct BItem {
   int q;    // instance
-  int t0;   // first 64-sample tile
+  int t0;   // first fiber tile (ACA_TILE entries)
   int nt;   // tiles
   int pad;
 };
@@ -463,8 +463,8 @@ slar_status slar_batch_create(int32_t count, const slar_grid* grids, int32_t rma
     const slar_status st = slar_workspace_create(&grids[q], rmax, &b->ws[q]);
     if (st != SLAR_OK) return fail(st);
     const GridDev& G = b->ws[q]->w.G;
-    b->nbrow.push_back((G.nv + FS_SAMPLES - 1) / FS_SAMPLES);
-    b->nbcol.push_back((G.nx + FS_SAMPLES - 1) / FS_SAMPLES);
+    b->nbrow.push_back((G.nv + ACA_TILE - 1) / ACA_TILE);
+    b->nbcol.push_back((G.nx + ACA_TILE - 1) / ACA_TILE);
   }
   // largest sampling work first: stencil rows x fiber lengths
   b->order.resize(count);

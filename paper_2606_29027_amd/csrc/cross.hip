@@ -34,8 +34,8 @@ static hipError_t aca_iterate(hipStream_t s, const GridDev& G, const AdvDev& A, 
                               const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
                               unsigned char* used, double* part, int nprobe, const int* probes,
                               hipEvent_t* ev) {
-  const unsigned bRow = (G.nv + FS_SAMPLES - 1) / FS_SAMPLES;
-  const unsigned bCol = (G.nx + FS_SAMPLES - 1) / FS_SAMPLES;
+  const unsigned bRow = (G.nv + ACA_TILE - 1) / ACA_TILE;
+  const unsigned bCol = (G.nx + ACA_TILE - 1) / ACA_TILE;
   AcaInst I{G, A, X, P, ld, r, ctl, U, V, used, part, (int)bRow, (int)bCol, nprobe, 16, probes};
   if (ev) {
     // events attached to the dispatches themselves: start and end of the
