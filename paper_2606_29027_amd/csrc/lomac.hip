@@ -397,12 +397,15 @@ __global__ __launch_bounds__(256) void k_cgs_pass(int n, int nv, const double* _
     part[(size_t)v * gridDim.x + blockIdx.x] = red[0][v] + red[1][v] + red[2][v] + red[3][v];
 }
 
-__global__ void k_reduce_parts(int nv, int nb, const double* __restrict__ part, double* __restrict__ out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
+// out[v] = sum_b part[v][b]: one wave per v, lanes over b (coalesced),
+// fixed order (lane partial sums, then a butterfly)
+__global__ __launch_bounds__(64) void k_reduce_parts(int nb, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+  const int v = blockIdx.x, ln = threadIdx.x;
   double acc = 0.0;
-  for (int b = 0; b < nb; ++b) acc += part[(size_t)v * nb + b];
-  out[v] = acc;
+  for (int b = ln; b < nb; b += 64) acc += part[(size_t)v * nb + b];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (ln == 0) out[v] = acc;
 }
 
 // y = a x + b y ; if x2: y += c x2
@@ -488,12 +491,14 @@ __global__ void k_meanfix(int Nx, int K, const double* __restrict__ md, const do
 // M2 = 2 (U2 - e_p)); with the linearised Poisson source -n_i E(dU_0) this
 // gives, per Fourier mode k, the K x K system
 //   (I + b dt [ sum_mu i k_mu A_mu + n_i (i k_mu / |k|^2) e_{1+mu} e_0^T ]) z^ = r^.
-// Solved exactly per mode (complex Gaussian elimination, partial pivoting);
-// the field-energy flux and the E-dependent parts are left to the Krylov
-// iteration.  A_mu [dx][K][K] is precomputed on the host.
-__global__ void k_spec_solve(int n0, int n1, int dx, double L0, double L1, int K,
+// The K x K matrix of each mode is inverted once per macroscopic solve
+// (complex Gauss-Jordan, partial pivoting) and applied as a matrix-vector
+// product; the field-energy flux and the E-dependent parts are left to the
+// Krylov iteration.  A_mu [dx][K][K] is precomputed on the host.
+// Minv[(a K + b) Nx + p] holds entry (a, b) of mode p's inverse.
+__global__ void k_spec_setup(int n0, int n1, int dx, double L0, double L1, int K,
                              const double* __restrict__ A, double bdt, double ni,
-                             const double2* __restrict__ rhs, double2* __restrict__ out, int Nx) {
+                             double2* __restrict__ Minv, int Nx) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= Nx) return;
   auto wn = [](int i, int n, double Lx) {
@@ -503,20 +508,19 @@ __global__ void k_spec_solve(int n0, int n1, int dx, double L0, double L1, int K
   };
   double k[2] = {wn(p / n1, n0, L0), dx == 2 ? wn(p % n1, n1, L1) : 0.0};
   const double k2 = k[0] * k[0] + k[1] * k[1];
-  double Mr[4][4], Mi[4][4], br[4], bi[4];
-  for (int a = 0; a < K; ++a) {
+  // [M | I] with M = I + i bdt (sum_mu k_mu A_mu + n_i k_mu / |k|^2 e_{1+mu} e_0^T)
+  double Mr[4][8], Mi[4][8];
+  for (int a = 0; a < K; ++a)
     for (int b = 0; b < K; ++b) {
       double im = 0.0;
       for (int mu = 0; mu < dx; ++mu) im += k[mu] * A[(mu * K + a) * K + b];
       Mr[a][b] = (a == b) ? 1.0 : 0.0;
       Mi[a][b] = bdt * im;
+      Mr[a][K + b] = (a == b) ? 1.0 : 0.0;
+      Mi[a][K + b] = 0.0;
     }
-    const double2 r = rhs[(size_t)a * Nx + p];
-    br[a] = r.x; bi[a] = r.y;
-  }
   if (k2 > 0.0)
     for (int mu = 0; mu < dx; ++mu) Mi[1 + mu][0] += bdt * ni * k[mu] / k2;
-  // Gaussian elimination with partial pivoting (complex)
   for (int c = 0; c < K; ++c) {
     int piv = c;
     double best = Mr[c][c] * Mr[c][c] + Mi[c][c] * Mi[c][c];
@@ -524,42 +528,61 @@ __global__ void k_spec_solve(int n0, int n1, int dx, double L0, double L1, int K
       const double v = Mr[r][c] * Mr[r][c] + Mi[r][c] * Mi[r][c];
       if (v > best) { best = v; piv = r; }
     }
-    if (piv != c) {
-      for (int b = 0; b < K; ++b) {
+    if (piv != c)
+      for (int b = 0; b < 2 * K; ++b) {
         double t = Mr[c][b]; Mr[c][b] = Mr[piv][b]; Mr[piv][b] = t;
         t = Mi[c][b]; Mi[c][b] = Mi[piv][b]; Mi[piv][b] = t;
       }
-      double t = br[c]; br[c] = br[piv]; br[piv] = t;
-      t = bi[c]; bi[c] = bi[piv]; bi[piv] = t;
-    }
+    // scale row c by 1 / M[c][c]
     const double dr = Mr[c][c], di = Mi[c][c], dd = dr * dr + di * di;
-    for (int r = c + 1; r < K; ++r) {
-      // f = M[r][c] / M[c][c]
-      const double fr = (Mr[r][c] * dr + Mi[r][c] * di) / dd;
-      const double fi = (Mi[r][c] * dr - Mr[r][c] * di) / dd;
-      for (int b = c; b < K; ++b) {
+    const double ir = dr / dd, ii = -di / dd;
+    for (int b = 0; b < 2 * K; ++b) {
+      const double xr = Mr[c][b], xi = Mi[c][b];
+      Mr[c][b] = xr * ir - xi * ii;
+      Mi[c][b] = xr * ii + xi * ir;
+    }
+    for (int r = 0; r < K; ++r) {
+      if (r == c) continue;
+      const double fr = Mr[r][c], fi = Mi[r][c];
+      for (int b = 0; b < 2 * K; ++b) {
         Mr[r][b] -= fr * Mr[c][b] - fi * Mi[c][b];
         Mi[r][b] -= fr * Mi[c][b] + fi * Mr[c][b];
       }
-      br[r] -= fr * br[c] - fi * bi[c];
-      bi[r] -= fr * bi[c] + fi * br[c];
     }
   }
-  double xr[4], xi[4];
-  for (int c = K - 1; c >= 0; --c) {
-    double sr = br[c], si = bi[c];
-    for (int b = c + 1; b < K; ++b) {
-      sr -= Mr[c][b] * xr[b] - Mi[c][b] * xi[b];
-      si -= Mr[c][b] * xi[b] + Mi[c][b] * xr[b];
-    }
-    const double dr = Mr[c][c], di = Mi[c][c], dd = dr * dr + di * di;
-    xr[c] = (sr * dr + si * di) / dd;
-    xi[c] = (si * dr - sr * di) / dd;
-  }
-  for (int a = 0; a < K; ++a) out[(size_t)a * Nx + p] = make_double2(xr[a], xi[a]);
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b) Minv[(size_t)(a * K + b) * Nx + p] = make_double2(Mr[a][K + b], Mi[a][K + b]);
 }
 
-static hipError_t spectral_precond(hipStream_t s, Workspace* ws, const double* v, double bdt,
+// out[a][p] = sum_b Minv[a][b][p] rhs[b][p]
+__global__ void k_spec_apply(int K, const double2* __restrict__ Minv, const double2* __restrict__ rhs,
+                             double2* __restrict__ out, int Nx) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Nx) return;
+  double2 r[4];
+  for (int b = 0; b < K; ++b) r[b] = rhs[(size_t)b * Nx + p];
+  for (int a = 0; a < K; ++a) {
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < K; ++b) {
+      const double2 m = Minv[(size_t)(a * K + b) * Nx + p];
+      sr += m.x * r[b].x - m.y * r[b].y;
+      si += m.x * r[b].y + m.y * r[b].x;
+    }
+    out[(size_t)a * Nx + p] = make_double2(sr, si);
+  }
+}
+
+static hipError_t spectral_setup(hipStream_t s, Workspace* ws, double bdt, double2* Minv) {
+  const GridDev& G = ws->G;
+  const int K = G.dv + 2, Nx = G.nx;
+  k_spec_setup<<<(Nx + 255) / 256, 256, 0, s>>>(G.n[0], G.dx == 2 ? G.n[1] : 1, G.dx,
+                                                ws->grid.hi[0] - ws->grid.lo[0],
+                                                G.dx == 2 ? ws->grid.hi[1] - ws->grid.lo[1] : 1.0,
+                                                K, ws->lm + lm_layout(G).Aflux, bdt, ws->n_i, Minv, Nx);
+  return hipGetLastError();
+}
+
+static hipError_t spectral_precond(hipStream_t s, Workspace* ws, const double* v, const double2* Minv,
                                    double* z) {
   const GridDev& G = ws->G;
   const int K = G.dv + 2, Nx = G.nx;
@@ -568,16 +591,14 @@ static hipError_t spectral_precond(hipStream_t s, Workspace* ws, const double* v
   double2* c1 = c0 + 4 * Nx;
   double2* tmp = c1 + 4 * Nx;     // needs 2 K Nx complex (inverse)
   HIP_CHK(dft_forward(s, ws, K, v, c0, tmp));
-  k_spec_solve<<<(Nx + 255) / 256, 256, 0, s>>>(G.n[0], G.dx == 2 ? G.n[1] : 1, G.dx,
-                                                ws->grid.hi[0] - ws->grid.lo[0],
-                                                G.dx == 2 ? ws->grid.hi[1] - ws->grid.lo[1] : 1.0,
-                                                K, ws->lm + lm_layout(G).Aflux, bdt, ws->n_i, c0, c1, Nx);
+  k_spec_apply<<<(Nx + 255) / 256, 256, 0, s>>>(K, Minv, c0, c1, Nx);
   HIP_CHK(hipGetLastError());
   return dft_inverse(s, ws, K, c1, z, tmp);
 }
 
 struct KryBufs {
   double *V, *Z, *w, *g0, *Uh, *Gh, *d, *r, *x, *U;
+  double2* Minv;   // spectral preconditioner inverses [K][K][Nx]
 };
 
 static KryBufs kry_bufs(Workspace* ws, int n, int m) {
@@ -593,15 +614,16 @@ static KryBufs kry_bufs(Workspace* ws, int n, int m) {
   b.r = p; p += n;
   b.x = p; p += n;
   b.U = p; p += n;
+  b.Minv = (double2*)p; p += (size_t)2 * 4 * n;   // K^2 Nx complex, K <= 4
   return b;
 }
 
 size_t kry_elems_for(int Nx, int K, int m) {
   const size_t n = (size_t)Nx * K;
-  return macro_fixed_elems(Nx) + (size_t)(2 * m + 1) * n + 8 * n + 4096;
+  return macro_fixed_elems(Nx) + (size_t)(2 * m + 1) * n + 8 * n + (size_t)8 * n + 4096;
 }
 
-// host-side flux Jacobian of the closure (see k_spec_solve)
+// host-side flux Jacobian of the closure (see k_spec_setup)
 static void flux_jacobian(const GridDev& G, const double* scal, const double* psiQ, double* A) {
   const int dv = G.dv, K = dv + 2, dx = G.dx;
   const double* NQ = scal + 16;
@@ -672,12 +694,13 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
   const int nbk = (n + MD_CHUNK - 1) / MD_CHUNK;
   auto cgs = [&](int nv, const double* V, const double* hprev, double* w, double* out) {
     k_cgs_pass<<<nbk, 256, 0, s>>>(n, nv, V, n, hprev, w, part);
-    k_reduce_parts<<<1, 128, 0, s>>>(nv + 1, nbk, part, out);
+    k_reduce_parts<<<nv + 1, 64, 0, s>>>(nbk, part, out);
   };
   auto norm2 = [&](double* x, double* out) { cgs(0, nullptr, nullptr, x, out); };
   double* Uhist = b.x;
   const double bdt = beta;
   k_hist_combine<<<nb, 256, 0, s>>>(n, hist, Uhist);
+  if (precond != 0) HIP_TRY(spectral_setup(s, ws, bdt, b.Minv));
   double* U = b.U;
   HIP_TRY(hipMemcpyAsync(U, ws->lm + L.U0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   const double sqeps = std::sqrt(2.220446049250313e-16);
@@ -686,9 +709,9 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
   const bool flexible = precond != 0;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
   auto apply_pc = [&](const double* v, double* z) -> hipError_t {
-    if (precond == 1) return spectral_precond(s, ws, v, bdt, z);
+    if (precond == 1) return spectral_precond(s, ws, v, b.Minv, z);
     if (precond == 2) {
-      HIP_CHK(spectral_precond(s, ws, v, bdt, z));
+      HIP_CHK(spectral_precond(s, ws, v, b.Minv, z));
       return cnn_apply(s, ws, cnn, v, U, z);
     }
     return hipErrorInvalidValue;
@@ -729,7 +752,7 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
         if (macro_residual(s, ws, b.Uh, Uhist, bdt, b.Gh) != hipSuccess) return SLAR_E_HIP;
         k_fd_diff<<<nb, 256, 0, s>>>(n, b.Gh, b.g0, hval, 0, b.w);
         if (flexible && ws->rec_feat && ws->rec_count < ws->rec_cap) {
-          if (spectral_precond(s, ws, b.w, bdt, b.Uh) != hipSuccess) return SLAR_E_HIP;
+          if (spectral_precond(s, ws, b.w, b.Minv, b.Uh) != hipSuccess) return SLAR_E_HIP;
           if (record_pair(s, ws, b.w, zj, U, b.Uh) != hipSuccess) return SLAR_E_HIP;
         }
         // CGS2 against V[0..j]
