@@ -97,6 +97,7 @@ const char* slar_status_str(slar_status s) {
 slar_status slar_workspace_destroy(slar_workspace* w) {
   if (!w) return SLAR_OK;
   Workspace& ws = w->w;
+  blas_release(&ws);
   void* dev[] = {ws.Eeff, ws.X32, ws.P32, ws.aca_ctl, ws.aca_part, ws.used, ws.resid, ws.dwork,
                  ws.small, ws.ismall, ws.tw[0], ws.tw[1], ws.cbuf, ws.psi, ws.lm, ws.kry};
   for (void* p : dev)

@@ -1,8 +1,10 @@
-// Small dense FP64 linear algebra for the truncation: tiled GEMM (optionally
-// summed over a batch in a fixed order), Cholesky-QR helpers, one-sided
+// Small dense FP64 linear algebra for the truncation: GEMM (rocBLAS),
+// split-K Gram matrices, Cholesky-QR helpers, one-sided
 // Jacobi SVD and two-sided Jacobi symmetric eigensolver.  All single-block
 // factorizations keep their matrix in LDS (gfx950: 160 KB per CU).
 #include <algorithm>
+
+#include <rocblas/rocblas.h>
 
 #include "slar_internal.h"
 #include "dense.h"
@@ -10,98 +12,46 @@
 namespace slar {
 
 // ------------------------------------------------------------------ GEMM
-// C_b = alpha op(A_b) op(B_b) + beta C_b, row-major.  64x64 tile, BK = 16,
-// 256 threads, 4x4 outputs per thread.
-constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
-
-__global__ __launch_bounds__(256) void k_gemm(bool ta, bool tb, int M, int N, int K, double alpha,
-                                              const double* __restrict__ A, int lda, long long sA,
-                                              const double* __restrict__ B, int ldb, long long sB,
-                                              double beta, double* __restrict__ C, int ldc,
-                                              long long sC) {
-  __shared__ double As[GB_K][GB_M + 1];
-  __shared__ double Bs[GB_K][GB_N + 1];
-  const int b = blockIdx.z;
-  A += sA * b; B += sB * b; C += sC * b;
-  const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;   // 16x16 thread grid, 4x4 each
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += GB_K) {
-    // load A tile (GB_M x GB_K) -> As[k][m]
-    for (int e = tid; e < GB_M * GB_K; e += 256) {
-      int mm, kk;
-      if (!ta) { mm = e / GB_K; kk = e % GB_K; } else { kk = e / GB_M; mm = e % GB_M; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < M && gk < K) v = ta ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
-      As[kk][mm] = v;
-    }
-    for (int e = tid; e < GB_N * GB_K; e += 256) {
-      int nn, kk;
-      if (!tb) { kk = e / GB_N; nn = e % GB_N; } else { nn = e / GB_K; kk = e % GB_K; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < N && gk < K) v = tb ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GB_K; ++kk) {
-      double a[4], bb[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tc + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
-    }
-    __syncthreads();
+// C_b = alpha op(A_b) op(B_b) + beta C_b, row-major, through rocBLAS (the
+// products of the path are plain GEMMs).  A row-major C = op(A) op(B) is the
+// column-major C^T = op(B)^T op(A)^T, i.e. rocBLAS with the operands
+// swapped.  The workspace keeps one handle per stream, so products enqueued
+// on its two streams never share a handle's scratch; atomics are disallowed,
+// so every product is reproducible bit for bit.
+static rocblas_handle blas_for(Workspace* ws, hipStream_t s) {
+  for (const auto& p : ws->blas)
+    if (p.first == s) return static_cast<rocblas_handle>(p.second);
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+  if (rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) != rocblas_status_success ||
+      rocblas_set_stream(h, s) != rocblas_status_success) {
+    rocblas_destroy_handle(h);
+    return nullptr;
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = m0 + tr + 16 * i;
-    if (gm >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + tc + 16 * j;
-      if (gn >= N) continue;
-      double* c = C + (long long)gm * ldc + gn;
-      *c = (beta == 0.0) ? alpha * acc[i][j] : alpha * acc[i][j] + beta * (*c);
-    }
-  }
+  ws->blas.emplace_back(s, static_cast<void*>(h));
+  return h;
 }
 
-hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
-                    const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
-                    double beta, double* C, int ldc, long long sC, int batch) {
+void blas_release(Workspace* ws) {
+  for (const auto& p : ws->blas) rocblas_destroy_handle(static_cast<rocblas_handle>(p.second));
+  ws->blas.clear();
+}
+
+hipError_t gemm_f64(Workspace* ws, hipStream_t s, bool ta, bool tb, int M, int N, int K,
+                    double alpha, const double* A, int lda, long long sA, const double* B, int ldb,
+                    long long sB, double beta, double* C, int ldc, long long sC, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
-  k_gemm<<<grid, 256, 0, s>>>(ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-  return hipGetLastError();
-}
-
-__global__ void k_sum_batches(const double* __restrict__ P, int M, int N, int batch,
-                              double* __restrict__ C, int ldc) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M * N) return;
-  double acc = 0.0;
-  for (int b = 0; b < batch; ++b) acc += P[(long long)b * M * N + e];
-  C[(long long)(e / N) * ldc + (e % N)] = acc;
-}
-
-hipError_t gemm_f64_sumbatch(hipStream_t s, Workspace* ws, bool ta, bool tb, int M, int N, int K,
-                             const double* A, int lda, long long sA, const double* B, int ldb,
-                             long long sB, double* C, int ldc, int batch) {
-  const size_t need = (size_t)batch * M * N;
-  if (need > ws->dwork_elems) return hipErrorInvalidValue;
-  hipError_t e = gemm_f64(s, ta, tb, M, N, K, 1.0, A, lda, sA, B, ldb, sB, 0.0, ws->dwork, N,
-                          (long long)M * N, batch);
-  if (e != hipSuccess) return e;
-  k_sum_batches<<<(M * N + 255) / 256, 256, 0, s>>>(ws->dwork, M, N, batch, C, ldc);
-  return hipGetLastError();
+  rocblas_handle h = blas_for(ws, s);
+  if (h == nullptr) return hipErrorUnknown;
+  const rocblas_operation opB = tb ? rocblas_operation_transpose : rocblas_operation_none;
+  const rocblas_operation opA = ta ? rocblas_operation_transpose : rocblas_operation_none;
+  rocblas_status st;
+  if (batch == 1)
+    st = rocblas_dgemm(h, opB, opA, N, M, K, &alpha, B, ldb, A, lda, &beta, C, ldc);
+  else
+    st = rocblas_dgemm_strided_batched(h, opB, opA, N, M, K, &alpha, B, ldb, sB, A, lda, sA, &beta, C,
+                                       ldc, sC, batch);
+  return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
 }
 
 // ------------------------------------------------------------ Gram

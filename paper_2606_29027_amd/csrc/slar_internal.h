@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <utility>
 #include <vector>
 
 #include "../../include/slar.h"
@@ -85,16 +86,20 @@ struct Workspace {
   float* rec_targ = nullptr;
   int rec_cap = 0;
   int rec_count = 0;
+  // rocBLAS handles of the GEMMs, one per stream the workspace has run a
+  // product on (bound to that stream); released by blas_release
+  std::vector<std::pair<hipStream_t, void*>> blas;
 };
 
 // launchers implemented across the .hip files
-hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+// C_b = alpha op(A_b) op(B_b) + beta C_b (row-major, FP64) on stream s with
+// the rocBLAS handle ws keeps for s (created on first use: call it once
+// eagerly on a stream before capturing a graph on it)
+hipError_t gemm_f64(Workspace* ws, hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
                     const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
                     double beta, double* C, int ldc, long long sC, int batch);
-// C = sum over batch of op(A_b) op(B_b) (deterministic); partial buffer in ws
-hipError_t gemm_f64_sumbatch(hipStream_t s, Workspace* ws, bool ta, bool tb, int M, int N, int K,
-                             const double* A, int lda, long long sA, const double* B, int ldb,
-                             long long sB, double* C, int ldc, int batch);
+// destroys the handles gemm_f64 created for ws (the workspace's streams idle)
+void blas_release(Workspace* ws);
 hipError_t combine_field(hipStream_t s, const GridDev& G, const slar_adv* a, double* out);
 
 }  // namespace slar
