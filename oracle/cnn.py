@@ -9,7 +9,16 @@ with tanh after every layer but the last.  Loss: mean squared error over
 all output entries.  Parameters are packed per layer as w (Co, Ci, 3, 3)
 then b (Co).
 
-Parity: pinned by central finite differences of this forward pass.
+Network input and target inside the Krylov solve (K = d_v + 2 conserved
+components on the N_x-point spatial grid):
+  input  = [v / rms(v) ; (U_c - mean U_c) / std U_c for each c]  (2K channels)
+  output correction z = P_spec(v) + rms(v) net(input),
+  training target (z - P_spec(w)) / rms(w) for a recorded pair (w = J z, z),
+with rms(v) over all K N_x entries and mean/std per channel of U.
+
+Parity: the network is pinned by central finite differences of this forward
+pass; the input and target definitions by their invariants (standardised U
+channels, unit-rms residual channels, invariance under scaling of v).
 """
 from __future__ import annotations
 
@@ -83,3 +92,28 @@ def grad(theta, shapes, x, y):
         g = gin
     grads.reverse()
     return np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in grads])
+
+
+def features(v: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Network input for residual v and state U, both (K, H, W): (2K, H, W).
+    The std of a U channel gets 1e-12 |mean| + 1e-300 added (a constant
+    channel maps to zero instead of dividing by zero)."""
+    rms = np.sqrt(np.mean(v ** 2))
+    vin = v / rms if rms > 0.0 else np.zeros_like(v)
+    mean = U.mean(axis=(1, 2), keepdims=True)
+    std = np.sqrt(np.maximum((U ** 2).mean(axis=(1, 2), keepdims=True) - mean ** 2, 0.0))
+    std = std + 1e-12 * np.abs(mean) + 1e-300
+    return np.concatenate([vin, (U - mean) / std], axis=0)
+
+
+def target(z: np.ndarray, pw: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Training target for the pair (w = J z, z) with P_spec(w) = pw."""
+    rms = np.sqrt(np.mean(w ** 2))
+    return (z - pw) / rms if rms > 0.0 else np.zeros_like(z)
+
+
+def apply(theta, shapes, v: np.ndarray, U: np.ndarray, pv: np.ndarray) -> np.ndarray:
+    """Preconditioned vector z = P_spec(v) + rms(v) net(features(v, U)),
+    with P_spec(v) = pv given."""
+    out, _ = forward(theta, shapes, features(v, U)[None])
+    return pv + np.sqrt(np.mean(v ** 2)) * out[0]

@@ -284,7 +284,13 @@ static hipError_t cnn_backward(hipStream_t s, slar_cnn* c, int B, int H, int W, 
 }
 
 // ---------------------------------------------- use inside the Krylov solve
-// stats[0] = sum v^2, stats[1 + 2c] = mean U_c, stats[2 + 2c] = std U_c
+// Normalisation statistics of one network input, per channel c < K:
+// stats[ST_SS + c] = sum v_c^2, stats[ST_MEAN + c] = mean U_c,
+// stats[ST_STD + c] = std U_c (three disjoint ranges of ST_STRIDE entries).
+constexpr int ST_STRIDE = 16, ST_SS = 0, ST_MEAN = ST_STRIDE, ST_STD = 2 * ST_STRIDE;
+constexpr int ST_ELEMS = 3 * ST_STRIDE;
+static_assert(ST_STRIDE >= CNN_CMAX / 2, "K = input channels / 2 fits one range");
+
 __global__ __launch_bounds__(1024) void k_cnn_stats(int Nx, int K, const double* __restrict__ v,
                                                     const double* __restrict__ U,
                                                     double* __restrict__ stats) {
@@ -304,10 +310,17 @@ __global__ __launch_bounds__(1024) void k_cnn_stats(int Nx, int K, const double*
   if (t == 0) {
     const double mean = r1[0] / Nx;
     const double var = fmax(r2[0] / Nx - mean * mean, 0.0);
-    stats[8 + c] = r0[0];
-    stats[1 + 2 * c] = mean;
-    stats[2 + 2 * c] = sqrt(var) + 1e-12 * fabs(mean) + 1e-300;
+    stats[ST_SS + c] = r0[0];
+    stats[ST_MEAN + c] = mean;
+    stats[ST_STD + c] = sqrt(var) + 1e-12 * fabs(mean) + 1e-300;
   }
+}
+
+// rms of v over all K channels
+__device__ inline double cnn_rms(const double* __restrict__ stats, int Nx, int K) {
+  double ss = 0.0;
+  for (int q = 0; q < K; ++q) ss += stats[ST_SS + q];
+  return sqrt(ss / (double)(Nx * K));
 }
 
 __global__ void k_cnn_features(int Nx, int K, const double* __restrict__ v, const double* __restrict__ U,
@@ -315,22 +328,17 @@ __global__ void k_cnn_features(int Nx, int K, const double* __restrict__ v, cons
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= Nx * K) return;
   const int c = e / Nx;
-  double ss = 0.0;
-  for (int q = 0; q < K; ++q) ss += stats[8 + q];
-  const double rms = sqrt(ss / (double)(Nx * K));
+  const double rms = cnn_rms(stats, Nx, K);
   const double inv = rms > 0.0 ? 1.0 / rms : 0.0;
   feat[e] = (float)(v[e] * inv);
-  feat[(size_t)K * Nx + e] = (float)((U[e] - stats[1 + 2 * c]) / stats[2 + 2 * c]);
+  feat[(size_t)K * Nx + e] = (float)((U[e] - stats[ST_MEAN + c]) / stats[ST_STD + c]);
 }
 
 __global__ void k_cnn_add(int n, int Nx, int K, const float* __restrict__ out,
                           const double* __restrict__ stats, double* __restrict__ z) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  double ss = 0.0;
-  for (int q = 0; q < K; ++q) ss += stats[8 + q];
-  const double rms = sqrt(ss / (double)(Nx * K));
-  z[e] += rms * (double)out[e];
+  z[e] += cnn_rms(stats, Nx, K) * (double)out[e];
 }
 
 hipError_t cnn_apply(hipStream_t s, Workspace* ws, const slar_cnn* net, const double* v,
@@ -354,9 +362,7 @@ __global__ void k_record_target(int n, int Nx, int K, const double* __restrict__
                                 float* __restrict__ tgt) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  double ss = 0.0;
-  for (int q = 0; q < K; ++q) ss += stats[8 + q];
-  const double rms = sqrt(ss / (double)(Nx * K));
+  const double rms = cnn_rms(stats, Nx, K);
   tgt[e] = rms > 0.0 ? (float)((z[e] - pw[e]) / rms) : 0.f;
 }
 
@@ -410,7 +416,7 @@ slar_status slar_cnn_create(int32_t nlayers, const int32_t* channels, int32_t ma
   c->gpart_elems = (size_t)((actn / cmax + 2047) / 2048 + 1) * (CNN_CMAX * CNN_CMAX * 9 + CNN_CMAX);
   al((void**)&c->gpart, sizeof(float) * c->gpart_elems);
   al((void**)&c->lossp, sizeof(float) * (actn / 256 + 2));
-  al((void**)&c->stats, sizeof(double) * 64);
+  al((void**)&c->stats, sizeof(double) * ST_ELEMS);
   if (ok) {
     if (hipMemset(c->theta, 0, sizeof(float) * o) != hipSuccess || hipMemset(c->m, 0, sizeof(float) * o) != hipSuccess ||
         hipMemset(c->v, 0, sizeof(float) * o) != hipSuccess)

@@ -73,3 +73,44 @@ def test_learned_preconditioner_same_root_fewer_iterations_than_plain():
         out[pc] = (s.U_n.cpu().numpy(), sum(i["krylov"] for i in infos))
     assert normwise(out[2][0], out[0][0]) < 1e-9
     assert out[2][1] < out[0][1]
+
+
+def test_recorded_features_are_standardised():
+    """Every recorded network input has the normalisation of oracle.cnn.features:
+    U channels of mean 0 and std 1 one by one, residual channels of rms 1
+    over all channels together (FP32 inputs: bar 1e-5)."""
+    p = SI.config("stronglandau2d", n=16).with_(rmax=40)
+    K = p.dv + 2
+    feats, targs, _ = CNN.collect([p], steps=2, capacity=16)[0]
+    f = feats.double().cpu().numpy()
+    assert f.shape[0] > 4 and np.all(np.isfinite(f)) and np.all(np.isfinite(targs.cpu().numpy()))
+    for q in range(f.shape[0]):
+        assert abs(np.sqrt(np.mean(f[q, :K] ** 2)) - 1.0) < 1e-5, q
+        for c in range(K):
+            u = f[q, K + c]
+            assert abs(u.mean()) < 1e-5, (q, c)
+            assert abs(u.std() - 1.0) < 1e-5, (q, c)
+
+
+def test_learned_solve_is_bitwise_reproducible():
+    """Two learned-preconditioner runs from the same state give the same bits
+    (no atomics, fixed reduction orders), with a network whose output
+    depends on every normalisation statistic."""
+    p = SI.config("stronglandau2d", n=16).with_(rmax=40)
+    chs = CNN.channels(p.dv)
+    net = L.Cnn(chs, 8, 16 * 16)
+    rng = np.random.default_rng(21)
+    net.set_params((0.05 * rng.standard_normal(net.nparams)).astype(np.float32))
+    pr = SI.probe_indices(256, 256, 64, 5)
+    runs = []
+    for _ in range(2):
+        s = Solver(p, L.F64, probes=pr, precond=2, cnn=net)
+        s.set_initial(SI.initial_ht(p))
+        infos = [s.step() for _ in range(2)]
+        X, P = s.frames_buf[s.state_slot]
+        r = s.state.r
+        runs.append((s.U_n.cpu().numpy(), X[:, :r].cpu().numpy(), P[:, :r].cpu().numpy(),
+                     [(i["newton"], i["krylov"]) for i in infos]))
+    (U0, X0, P0, it0), (U1, X1, P1, it1) = runs
+    assert it0 == it1
+    assert np.array_equal(U0, U1) and np.array_equal(X0, X1) and np.array_equal(P0, P1)

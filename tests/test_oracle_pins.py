@@ -414,6 +414,54 @@ def test_cnn_conv_is_periodic_cross_correlation():
     assert out[0, 0, 1, 1] == 2.0 and abs(out).sum() == 2.0
 
 
+def test_cnn_features_invariants():
+    """Network input: U channels standardised one by one (mean 0, std 1),
+    residual channels of rms 1 over all channels together (not one by one),
+    invariance under any scaling of v and any affine map of each U channel,
+    and a constant U channel mapped to zero."""
+    from oracle import cnn as CN
+    rng = np.random.default_rng(11)
+    K, H, W = 4, 6, 5
+    v = rng.standard_normal((K, H, W)) * np.array([1.0, 3.0, 0.1, 7.0])[:, None, None]
+    U = rng.standard_normal((K, H, W)) * np.array([2.0, 0.5, 9.0, 1.0])[:, None, None] + 4.0
+    f = CN.features(v, U)
+    assert f.shape == (2 * K, H, W)
+    assert abs(np.sqrt(np.mean(f[:K] ** 2)) - 1.0) < 1e-14
+    # channel scales are kept relative to each other (one rms for all)
+    assert np.allclose(f[:K] / v, f[0, 0, 0] / v[0, 0, 0], rtol=1e-13, atol=0)
+    for c in range(K):
+        assert abs(f[K + c].mean()) < 1e-13
+        # the std guard adds 1e-12 |mean| / std (< 1e-10 here) to the std
+        assert abs(f[K + c].std() - 1.0) < 1e-10
+    a = rng.uniform(0.5, 2.0, K)[:, None, None]
+    b = rng.uniform(-3.0, 3.0, K)[:, None, None]
+    assert np.allclose(CN.features(-37.0 * v, a * U + b)[:K], -f[:K], rtol=1e-13, atol=1e-15)
+    assert np.allclose(CN.features(v, a * U + b)[K:], f[K:], rtol=1e-10, atol=1e-12)
+    U2 = U.copy(); U2[3] = 2.5
+    f2 = CN.features(v, U2)
+    assert np.all(np.isfinite(f2)) and np.all(f2[K + 3] == 0.0)
+    assert np.all(CN.features(np.zeros_like(v), U)[:K] == 0.0)
+
+
+def test_cnn_apply_and_target_are_inverse():
+    """An untrained network (last layer zero) leaves the spectral
+    preconditioner unchanged, and the training target of the pair
+    (w, apply(w)) is exactly the network output scaled back by rms(w)."""
+    from oracle import cnn as CN
+    rng = np.random.default_rng(12)
+    K, H, W = 4, 5, 4
+    shapes = [(2 * K, 6), (6, K)]
+    theta = 0.3 * rng.standard_normal(CN.nparams(shapes))
+    w = rng.standard_normal((K, H, W)); U = rng.standard_normal((K, H, W))
+    pw = rng.standard_normal((K, H, W))
+    th0 = theta.copy(); th0[CN.nparams([shapes[0]]):] = 0.0
+    assert np.array_equal(CN.apply(th0, shapes, w, U, pw), pw)
+    z = CN.apply(theta, shapes, w, U, pw)
+    out, _ = CN.forward(theta, shapes, CN.features(w, U)[None])
+    assert np.allclose(CN.target(z, pw, w), out[0], rtol=1e-12, atol=1e-14)
+    assert np.allclose(CN.apply(theta, shapes, 5.0 * w, U, 5.0 * pw), 5.0 * z, rtol=1e-12, atol=1e-14)
+
+
 # ---------------------------------------------------------------------------
 # Macroscopic time integrators (section 4: S-stable DIRK-3 start-up, then
 # variable-step BDF-3).
