@@ -59,10 +59,34 @@ __global__ void k_dft_line(int n0, int n1, int axis, double sign, const double2*
   }
 }
 
-// Radix-2 Cooley--Tukey FFT of one line in LDS (n a power of two <= SLAR_NLINE):
-// bit-reversed load, log2(n) butterfly stages, one butterfly per thread.
+// Radix-2 Cooley--Tukey stages over `nl` lines of length L = 2^logL held
+// in LDS in bit-reversed order (line l at a + l * L); the block's threads
+// share the butterflies of all lines, one barrier per stage.
+__device__ void fft_stages(double2* a, int nl, int L, const double* __restrict__ tw, double sign) {
+  const int nt = blockDim.x, t = threadIdx.x;
+  for (int len = 2; len <= L; len <<= 1) {
+    const int hl = len >> 1;
+    for (int q = t; q < nl * (L / 2); q += nt) {
+      const int l = q / (L / 2), bt = q % (L / 2);
+      const int grp = bt / hl, pos = bt % hl;
+      const int i = l * L + grp * len + pos, j = i + hl;
+      const int ti = pos * (L / len);
+      const double wr = tw[2 * ti], wi = sign * tw[2 * ti + 1];
+      const double2 u = a[i], x = a[j];
+      const double2 v = make_double2(x.x * wr - x.y * wi, x.x * wi + x.y * wr);
+      a[i] = make_double2(u.x + v.x, u.y + v.y);
+      a[j] = make_double2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+}
+
+// FFT of one line (n a power of two <= SLAR_NLINE) per block: bit-reversed
+// load, log2(n) butterfly stages.  With realout set, the scaled real part
+// is stored instead of the complex line.
 __global__ void k_fft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
                            const double* __restrict__ realin, double2* __restrict__ out,
+                           double* __restrict__ realout, double scale,
                            const double* __restrict__ tw, int logL) {
   __shared__ double2 a[SLAR_NLINE];
   const int b = blockIdx.y;
@@ -77,23 +101,11 @@ __global__ void k_fft_line(int n0, int n1, int axis, double sign, const double2*
     a[r] = v;
   }
   __syncthreads();
-  for (int len = 2; len <= L; len <<= 1) {
-    const int hl = len >> 1;
-    for (int bt = t; bt < L / 2; bt += blockDim.x) {
-      const int grp = bt / hl, pos = bt % hl;
-      const int i = grp * len + pos, j = i + hl;
-      const int ti = pos * (L / len);
-      const double wr = tw[2 * ti], wi = sign * tw[2 * ti + 1];
-      const double2 u = a[i], x = a[j];
-      const double2 v = make_double2(x.x * wr - x.y * wi, x.x * wi + x.y * wr);
-      a[i] = make_double2(u.x + v.x, u.y + v.y);
-      a[j] = make_double2(u.x - v.x, u.y - v.y);
-    }
-    __syncthreads();
-  }
+  fft_stages(a, 1, L, tw, sign);
   for (int e = t; e < L; e += blockDim.x) {
     const long long off = axis == 1 ? base + (long long)other * n1 + e : base + (long long)e * n1 + other;
-    out[off] = a[e];
+    if (realout) realout[off] = a[e].x * scale;
+    else out[off] = a[e];
   }
 }
 
@@ -110,7 +122,7 @@ static void line_transform(hipStream_t s, int n0, int n1, int axis, double sign,
   const int others = axis == 1 ? n0 : n1;
   const int lg = log2_exact(L);
   if (lg >= 1)
-    k_fft_line<<<dim3(others, B), 64, 0, s>>>(n0, n1, axis, sign, in, realin, out, tw, lg);
+    k_fft_line<<<dim3(others, B), 64, 0, s>>>(n0, n1, axis, sign, in, realin, out, nullptr, 0.0, tw, lg);
   else
     k_dft_line<<<dim3(others, B), 128, 0, s>>>(n0, n1, axis, sign, in, realin, out, tw);
 }
@@ -213,6 +225,157 @@ hipError_t spectral_symbol(hipStream_t s, Workspace* ws, int op, int nvec, const
   const long long n = (long long)G.nx * nvec;
   k_symbol<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(K, op, nvec, in, out, G.nx);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------ spectral stages
+// A spectral stage maps Bin real fields to Bout real fields through one
+// pointwise operation per Fourier mode (all field terms of the macroscopic
+// residual and the per-mode preconditioner are of this form):
+//   SPEC_POISSON  rho -> (phi, E_m = -i k_m phi), phi = rho / |k|^2
+//   SPEC_DTPHI    J_m -> i k_m dtphi, dtphi = -(sum_m i k_m J_m) / |k|^2
+//   SPEC_DIV      F[q][m] -> sum_m i k_m F[q][m]
+//   SPEC_PRECOND  x_b -> sum_b Minv[a][b] x_b (per-mode K x K inverse)
+// Null modes (|k| = 0) and Nyquist wavenumbers map to zero as in k_symbol.
+constexpr int SPEC_MAXIN = 8, SPEC_MAXOUT = 4;
+
+__device__ __forceinline__ void spec_map(int op, int dx, int K, const double* k, const double2* x,
+                                         double2* y, const double2* __restrict__ Minv, long long p,
+                                         int Nx) {
+  const double k2 = k[0] * k[0] + k[1] * k[1];
+  if (op == SPEC_POISSON) {
+    const double2 ph = k2 > 0.0 ? make_double2(x[0].x / k2, x[0].y / k2) : make_double2(0.0, 0.0);
+    y[0] = ph;
+    for (int m = 0; m < dx; ++m) y[1 + m] = make_double2(k[m] * ph.y, -k[m] * ph.x);
+  } else if (op == SPEC_DTPHI) {
+    double dre = 0.0, dim = 0.0;
+    for (int m = 0; m < dx; ++m) {
+      dre += -k[m] * x[m].y;
+      dim += k[m] * x[m].x;
+    }
+    double pre = 0.0, pim = 0.0;
+    if (k2 > 0.0) { pre = -dre / k2; pim = -dim / k2; }
+    for (int m = 0; m < dx; ++m) y[m] = make_double2(-k[m] * pim, k[m] * pre);
+  } else if (op == SPEC_DIV) {
+    for (int q = 0; q < K; ++q) {
+      double re = 0.0, im = 0.0;
+      for (int m = 0; m < dx; ++m) {
+        re += -k[m] * x[q * dx + m].y;
+        im += k[m] * x[q * dx + m].x;
+      }
+      y[q] = make_double2(re, im);
+    }
+  } else {
+    for (int a = 0; a < K; ++a) {
+      double sr = 0.0, si = 0.0;
+      for (int b = 0; b < K; ++b) {
+        const double2 m = Minv[(size_t)(a * K + b) * Nx + p];
+        sr += m.x * x[b].x - m.y * x[b].y;
+        si += m.x * x[b].y + m.y * x[b].x;
+      }
+      y[a] = make_double2(sr, si);
+    }
+  }
+}
+
+static void spec_counts(int op, int dx, int K, int* bin, int* bout) {
+  switch (op) {
+    case SPEC_POISSON: *bin = 1; *bout = 1 + dx; break;
+    case SPEC_DTPHI: *bin = dx; *bout = dx; break;
+    case SPEC_DIV: *bin = K * dx; *bout = K; break;
+    default: *bin = K; *bout = K; break;
+  }
+}
+
+// Fused axis-0 part of a stage: per block one line (index `other` along
+// axis 1) of every input field: forward FFT, the pointwise map (outputs
+// written in bit-reversed order), inverse FFT, store.  Inputs complex
+// (after the axis-1 forward pass) or real (1D); outputs complex (before
+// the axis-1 inverse pass) or scaled real (1D).  Dynamic LDS:
+// (Bin + Bout) lines of n0 complex values.
+__global__ __launch_bounds__(256) void k_spec_line(Kgrid Kg, int op, int K, int Bin, int Bout,
+                                                   const double2* __restrict__ cin,
+                                                   const double* __restrict__ realin,
+                                                   double2* __restrict__ cout, double* __restrict__ realout,
+                                                   double scale, const double2* __restrict__ Minv,
+                                                   const double* __restrict__ tw, int logL) {
+  extern __shared__ double2 sl[];
+  const int L = Kg.n0, n1 = Kg.n1, Nx = Kg.n0 * Kg.n1;
+  const int other = blockIdx.x, t = threadIdx.x;
+  double2* a = sl;
+  double2* b = sl + (size_t)Bin * L;
+  for (int q = t; q < Bin * L; q += blockDim.x) {
+    const int f = q / L, e = q % L;
+    const long long off = (long long)f * Nx + (long long)e * n1 + other;
+    const int r = __brev((unsigned)e) >> (32 - logL);
+    a[f * L + r] = realin ? make_double2(realin[off], 0.0) : cin[off];
+  }
+  __syncthreads();
+  fft_stages(a, Bin, L, tw, -1.0);
+  for (int e = t; e < L; e += blockDim.x) {
+    const long long p = (long long)e * n1 + other;
+    double k[2];
+    kvec(Kg, p, k);
+    double2 x[SPEC_MAXIN], y[SPEC_MAXOUT];
+    for (int f = 0; f < Bin; ++f) x[f] = a[f * L + e];
+    spec_map(op, Kg.dx, K, k, x, y, Minv, p, Nx);
+    const int r = __brev((unsigned)e) >> (32 - logL);
+    for (int g = 0; g < Bout; ++g) b[g * L + r] = y[g];
+  }
+  __syncthreads();
+  fft_stages(b, Bout, L, tw, 1.0);
+  for (int q = t; q < Bout * L; q += blockDim.x) {
+    const int g = q / L, e = q % L;
+    const long long off = (long long)g * Nx + (long long)e * n1 + other;
+    if (realout) realout[off] = b[g * L + e].x * scale;
+    else cout[off] = b[g * L + e];
+  }
+}
+
+// the pointwise map alone, for grids the fused path does not take
+__global__ void k_spec_point(Kgrid Kg, int op, int K, int Bin, int Bout, const double2* __restrict__ in,
+                             double2* __restrict__ out, const double2* __restrict__ Minv, int Nx) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Nx) return;
+  double k[2];
+  kvec(Kg, p, k);
+  double2 x[SPEC_MAXIN], y[SPEC_MAXOUT];
+  for (int f = 0; f < Bin; ++f) x[f] = in[(size_t)f * Nx + p];
+  spec_map(op, Kg.dx, K, k, x, y, Minv, p, Nx);
+  for (int g = 0; g < Bout; ++g) out[(size_t)g * Nx + p] = y[g];
+}
+
+hipError_t spectral_stage(hipStream_t s, Workspace* ws, int op, const double* in, double* out,
+                          const double2* Minv, double2* scr) {
+  const GridDev& G = ws->G;
+  const int Nx = G.nx, dx = G.dx, K = G.dv + 2;
+  int Bin = 0, Bout = 0;
+  spec_counts(op, dx, K, &Bin, &Bout);
+  if (Bin > SPEC_MAXIN || Bout > SPEC_MAXOUT || (op == SPEC_PRECOND && !Minv)) return hipErrorInvalidValue;
+  const Kgrid Kg{G.n[0], dx == 2 ? G.n[1] : 1, dx, ws->grid.hi[0] - ws->grid.lo[0],
+                 dx == 2 ? ws->grid.hi[1] - ws->grid.lo[1] : 1.0};
+  const int lg0 = log2_exact(Kg.n0), lg1 = dx == 2 ? log2_exact(Kg.n1) : 0;
+  double2* c0 = scr;                          // Bin fields
+  double2* c1 = scr + (size_t)Bin * Nx;       // Bout fields
+  const size_t lds = sizeof(double2) * (size_t)(Bin + Bout) * Kg.n0;
+  if (lg0 >= 1 && lg1 >= (dx == 2 ? 1 : 0)) {
+    if (dx == 2) {
+      k_fft_line<<<dim3(Kg.n0, Bin), 64, 0, s>>>(Kg.n0, Kg.n1, 1, -1.0, nullptr, in, c0, nullptr, 0.0,
+                                                ws->tw[1], lg1);
+      k_spec_line<<<Kg.n1, 256, lds, s>>>(Kg, op, K, Bin, Bout, c0, nullptr, c1, nullptr, 0.0, Minv,
+                                          ws->tw[0], lg0);
+      k_fft_line<<<dim3(Kg.n0, Bout), 64, 0, s>>>(Kg.n0, Kg.n1, 1, 1.0, c1, nullptr, nullptr, out,
+                                                 1.0 / Nx, ws->tw[1], lg1);
+    } else {
+      k_spec_line<<<1, 256, lds, s>>>(Kg, op, K, Bin, Bout, nullptr, in, nullptr, out, 1.0 / Nx, Minv,
+                                      ws->tw[0], lg0);
+    }
+    return hipGetLastError();
+  }
+  double2* tmp = c1 + (size_t)Bout * Nx;      // max(Bin, 2 Bout) fields
+  HIP_CHK(dft_forward(s, ws, Bin, in, c0, tmp));
+  k_spec_point<<<(Nx + 255) / 256, 256, 0, s>>>(Kg, op, K, Bin, Bout, c0, c1, Minv, Nx);
+  HIP_CHK(hipGetLastError());
+  return dft_inverse(s, ws, Bout, c1, out, tmp);
 }
 
 __global__ void k_rho(int n, const double* ne, double ni, double* rho) {

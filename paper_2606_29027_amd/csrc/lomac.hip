@@ -214,7 +214,7 @@ slar_status lomac_prepare_run(hipStream_t s, Workspace* ws, const slar_ht& Fs,
 // ------------------------------------------------------------ residual
 struct MacroBufs {
   double *rho, *phiE, *J, *gdt, *Mall, *flux, *divF;
-  double2 *c0, *c1, *tmp;
+  double2* c0;
 };
 
 static MacroBufs macro_bufs(Workspace* ws) {
@@ -230,9 +230,7 @@ static MacroBufs macro_bufs(Workspace* ws) {
   b.flux = p; p += 8 * Nx;
   b.divF = p; p += 4 * Nx;
   double2* c = (double2*)ws->cbuf;
-  b.c0 = c;
-  b.c1 = c + 10 * Nx;
-  b.tmp = c + 20 * Nx;
+  b.c0 = c;   // spectral-stage scratch, 20 Nx complex
   return b;
 }
 
@@ -273,28 +271,6 @@ __global__ void k_closure(int Nx, int dx, int dv, int nm, const double* __restri
 }
 
 // d_t phi gradient symbol: g_m = i k_m * ( -(sum_n i k_n J^_n) / |k|^2 )
-__global__ void k_dtphi_sym(int n0, int n1, int dx, double L0, double L1,
-                            const double2* __restrict__ Jh, double2* __restrict__ out, int Nx) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= Nx) return;
-  auto wn = [](int i, int n, double L) {
-    if ((n % 2) == 0 && i == n / 2) return 0.0;
-    const int m = (i < (n + 1) / 2) ? i : i - n;
-    return 2.0 * M_PI * (double)m / L;
-  };
-  double k[2] = {wn(p / n1, n0, L0), dx == 2 ? wn(p % n1, n1, L1) : 0.0};
-  const double k2 = k[0] * k[0] + k[1] * k[1];
-  double dre = 0.0, dim = 0.0;   // div J^ = sum i k J
-  for (int m = 0; m < dx; ++m) {
-    const double2 f = Jh[(size_t)m * Nx + p];
-    dre += -k[m] * f.y;
-    dim += k[m] * f.x;
-  }
-  double pre = 0.0, pim = 0.0;   // dtphi^ = -div / k2
-  if (k2 > 0.0) { pre = -dre / k2; pim = -dim / k2; }
-  for (int m = 0; m < dx; ++m) out[(size_t)m * Nx + p] = make_double2(-k[m] * pim, k[m] * pre);
-}
-
 // fluxes [K][dx][Nx]
 __global__ void k_fluxes(int Nx, int dx, int dv, const double* __restrict__ Mall,
                          const double* __restrict__ phiE, const double* __restrict__ J,
@@ -340,20 +316,13 @@ hipError_t macro_residual(hipStream_t s, Workspace* ws, const double* U, const d
   const int Nx = G.nx, dx = G.dx, dv = G.dv, K = dv + 2, nm = nmom_of(dv);
   const unsigned nb = (Nx + 255) / 256;
   k_rho_of<<<nb, 256, 0, s>>>(Nx, U, ws->n_i, b.rho);
-  hipError_t e = dft_forward(s, ws, 1, b.rho, b.c0, b.tmp);
+  hipError_t e = spectral_stage(s, ws, SPEC_POISSON, b.rho, b.phiE, nullptr, b.c0);
   if (e != hipSuccess) return e;
-  if ((e = spectral_symbol(s, ws, 0, 1, b.c0, b.c1)) != hipSuccess) return e;
-  if ((e = dft_inverse(s, ws, 1 + dx, b.c1, b.phiE, b.tmp)) != hipSuccess) return e;
   k_closure<<<nb, 256, 0, s>>>(Nx, dx, dv, nm, U, b.phiE, lm + L.scal, lm + L.Cstar, lm + L.Mstar,
                                lm + L.psiQ, b.Mall, b.J);
-  if ((e = dft_forward(s, ws, dx, b.J, b.c0, b.tmp)) != hipSuccess) return e;
-  k_dtphi_sym<<<nb, 256, 0, s>>>(G.n[0], dx == 2 ? G.n[1] : 1, dx, ws->grid.hi[0] - ws->grid.lo[0],
-                                 dx == 2 ? ws->grid.hi[1] - ws->grid.lo[1] : 1.0, b.c0, b.c1, Nx);
-  if ((e = dft_inverse(s, ws, dx, b.c1, b.gdt, b.tmp)) != hipSuccess) return e;
+  if ((e = spectral_stage(s, ws, SPEC_DTPHI, b.J, b.gdt, nullptr, b.c0)) != hipSuccess) return e;
   k_fluxes<<<nb, 256, 0, s>>>(Nx, dx, dv, b.Mall, b.phiE, b.J, b.gdt, b.flux);
-  if ((e = dft_forward(s, ws, K * dx, b.flux, b.c0, b.tmp)) != hipSuccess) return e;
-  if ((e = spectral_symbol(s, ws, 2, K, b.c0, b.c1)) != hipSuccess) return e;
-  if ((e = dft_inverse(s, ws, K, b.c1, b.divF, b.tmp)) != hipSuccess) return e;
+  if ((e = spectral_stage(s, ws, SPEC_DIV, b.flux, b.divF, nullptr, b.c0)) != hipSuccess) return e;
   k_gres<<<nb, 256, 0, s>>>(Nx, dx, dv, U, Uhist, bdt, b.divF, b.phiE, Gout);
   return hipGetLastError();
 }
@@ -554,24 +523,6 @@ __global__ void k_spec_setup(int n0, int n1, int dx, double L0, double L1, int K
     for (int b = 0; b < K; ++b) Minv[(size_t)(a * K + b) * Nx + p] = make_double2(Mr[a][K + b], Mi[a][K + b]);
 }
 
-// out[a][p] = sum_b Minv[a][b][p] rhs[b][p]
-__global__ void k_spec_apply(int K, const double2* __restrict__ Minv, const double2* __restrict__ rhs,
-                             double2* __restrict__ out, int Nx) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= Nx) return;
-  double2 r[4];
-  for (int b = 0; b < K; ++b) r[b] = rhs[(size_t)b * Nx + p];
-  for (int a = 0; a < K; ++a) {
-    double sr = 0.0, si = 0.0;
-    for (int b = 0; b < K; ++b) {
-      const double2 m = Minv[(size_t)(a * K + b) * Nx + p];
-      sr += m.x * r[b].x - m.y * r[b].y;
-      si += m.x * r[b].y + m.y * r[b].x;
-    }
-    out[(size_t)a * Nx + p] = make_double2(sr, si);
-  }
-}
-
 static hipError_t spectral_setup(hipStream_t s, Workspace* ws, double bdt, double2* Minv) {
   const GridDev& G = ws->G;
   const int K = G.dv + 2, Nx = G.nx;
@@ -584,16 +535,8 @@ static hipError_t spectral_setup(hipStream_t s, Workspace* ws, double bdt, doubl
 
 static hipError_t spectral_precond(hipStream_t s, Workspace* ws, const double* v, const double2* Minv,
                                    double* z) {
-  const GridDev& G = ws->G;
-  const int K = G.dv + 2, Nx = G.nx;
-  double2* c = (double2*)ws->cbuf;
-  double2* c0 = c + 24 * Nx;     // above the residual's complex scratch
-  double2* c1 = c0 + 4 * Nx;
-  double2* tmp = c1 + 4 * Nx;     // needs 2 K Nx complex (inverse)
-  HIP_CHK(dft_forward(s, ws, K, v, c0, tmp));
-  k_spec_apply<<<(Nx + 255) / 256, 256, 0, s>>>(K, Minv, c0, c1, Nx);
-  HIP_CHK(hipGetLastError());
-  return dft_inverse(s, ws, K, c1, z, tmp);
+  // scratch above the residual's (20 Nx complex each)
+  return spectral_stage(s, ws, SPEC_PRECOND, v, z, Minv, (double2*)ws->cbuf + (size_t)24 * ws->G.nx);
 }
 
 struct KryBufs {
