@@ -291,17 +291,39 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // to V (kv <= 16 VPL rows) when VPL > 0.  512 threads: a team is one
 // 16-lane DPP row, team i owns pair i of every step, so a step is one pass
 // over registers and one barrier (eight waves keep the SIMDs' issue slots
-// for the active teams).  A pair is rotated when |x.y| exceeds
-// the rounding level of its dot product (orth |x| |y|) and
-// |x| |y| > floor_abs.  Returns the number of sweeps.
+// for the active teams).
+//  * Squared column norms live in nrm2[kp] (LDS): computed exactly at the
+//    start of every sweep and updated by each rotation (alpha' = alpha -
+//    t gamma, beta' = beta + t gamma), so a step reduces one dot product.
+//  * Odd teams visit their register slots shifted by one 16-row block, so
+//    the two teams of a half-wave touch disjoint LDS banks whatever their
+//    columns (ldc and ldv are multiples of 32 doubles).
+// A pair is rotated when |x.y| exceeds the rounding level of its dot
+// product (orth |x| |y|) and |x| |y| > floor_abs.  Returns the number of
+// sweeps.
 template <int RPL, int VPL>
 __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv, int kv, double orth,
-                           double floor_abs, int maxsweep, int* s_rot) {
+                           double floor_abs, int maxsweep, double* nrm2, int* s_rot) {
+  static_assert((RPL & (RPL - 1)) == 0 && (VPL == 0 || (VPL & (VPL - 1)) == 0), "power-of-two slots");
   const int team = threadIdx.x >> 4, lane = threadIdx.x & 15;
+  const int odd = team & 1;
+  const int nteam = blockDim.x >> 4;
   const int npair = kp / 2;
   int sweep = 0;
   for (; sweep < maxsweep; ++sweep) {
     if (threadIdx.x == 0) *s_rot = 0;
+    for (int c = team; c < kp; c += nteam) {
+      const double* cc = C + (size_t)c * ldc;
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = lane + 16 * ((i + odd) & (RPL - 1));
+        const double v = (r < n) ? cc[r] : 0.0;
+        a += v * v;
+      }
+      a = row16_sum(a);
+      if (lane == 0) nrm2[c] = a;
+    }
     __syncthreads();
     bool rotated = false;
     for (int step = 0; step < kp - 1; ++step) {
@@ -314,17 +336,16 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
         const int q = 1 + qq;
         double* cp = C + (size_t)p * ldc;
         double* cq = C + (size_t)q * ldc;
+        const double al = nrm2[p], be = nrm2[q];
         double x[RPL], y[RPL];
-        double al = 0.0, be = 0.0, ga = 0.0;
+        double ga = 0.0;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
-          const int r = lane + 16 * i;
+          const int r = lane + 16 * ((i + odd) & (RPL - 1));
           x[i] = (r < n) ? cp[r] : 0.0;
           y[i] = (r < n) ? cq[r] : 0.0;
-          al += x[i] * x[i]; be += y[i] * y[i]; ga += x[i] * y[i];
+          ga += x[i] * y[i];
         }
-        al = row16_sum(al);
-        be = row16_sum(be);
         ga = row16_sum(ga);
         const double ab2 = al * be;
         if (ga * ga > orth * orth * ab2 && ab2 > floor_abs * floor_abs) {
@@ -342,7 +363,7 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
           const double c = rsq_nr(fma(tt, tt, 1.0)), sn = c * tt;
 #pragma unroll
           for (int i = 0; i < RPL; ++i) {
-            const int r = lane + 16 * i;
+            const int r = lane + 16 * ((i + odd) & (RPL - 1));
             if (r < n) {
               cp[r] = c * x[i] - sn * y[i];
               cq[r] = sn * x[i] + c * y[i];
@@ -353,13 +374,17 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
             double* vq = V + (size_t)q * ldv;
 #pragma unroll
             for (int i = 0; i < (VPL > 0 ? VPL : 1); ++i) {
-              const int r = lane + 16 * i;
+              const int r = lane + 16 * ((i + odd) & ((VPL > 0 ? VPL : 1) - 1));
               if (r < kv) {
                 const double vx = vp[r], vy = vq[r];
                 vp[r] = c * vx - sn * vy;
                 vq[r] = sn * vx + c * vy;
               }
             }
+          }
+          if (lane == 0) {
+            nrm2[p] = fmax(al - tt * ga, 0.0);
+            nrm2[q] = fmax(be + tt * ga, 0.0);
           }
           rotated = true;
         }
@@ -368,7 +393,9 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
     }
     if (rotated && lane == 0) *s_rot = 1;
     __syncthreads();
-    if (*s_rot == 0) break;
+    const bool again = *s_rot != 0;
+    __syncthreads();   // every wave has read the flag before thread 0 resets it
+    if (!again) break;
   }
   return sweep;
 }
@@ -406,7 +433,7 @@ __global__ __launch_bounds__(512) void k_svd_jacobi(int k, const double* __restr
   for (int w = 0; w < 8; ++w) fro += red[w];
   const double floor_abs = 1e-300 + 1e-22 * fro;   // columns below this are negligible
   const double orth = 4.0 * kp * 2.220446049250313e-16;
-  jacobi_cols<4, 4>(A, SVD_KM, kp, kp, V, SVD_KM, kp, orth, floor_abs, 60, &s_rot);
+  jacobi_cols<4, 4>(A, SVD_KM, kp, kp, V, SVD_KM, kp, orth, floor_abs, 60, nrm, &s_rot);
   for (int c = t; c < kp; c += blockDim.x) {
     double acc = 0.0;
     for (int r = 0; r < kp; ++r) acc += A[c * SVD_KM + r] * A[c * SVD_KM + r];
@@ -483,7 +510,10 @@ __global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
   __syncthreads();
   const double trace = s_trace;
   const double stop = 1e-30 * trace + 1e-300;
-  const int row = t >> 2, sub = t & 3;   // four threads per row
+  // four groups of 128 threads (two waves each) split every inner product
+  // over the factor columns; a wave reads 64 consecutive rows of one column
+  const int row = t & 127, sub = t >> 7;
+  __shared__ double part[4][SLAR_NMAX];
   int c = 0;
   for (; c < EIG_CM && c < n; ++c) {
     // pivot: largest remaining diagonal (lowest index on ties), one wave
@@ -507,19 +537,21 @@ __global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
     if (row < n) {
       double v = 0.0;
       for (int j = sub; j < c; j += 4) v += L[j * SLAR_NMAX + row] * L[j * SLAR_NMAX + p];
-      v += dpp_move<0xB1>(v);
-      v += dpp_move<0x4E>(v);
-      if (sub == 0) {
-        double out = 0.0;
-        if (row == p) out = sq;
-        else if (!taken[row]) out = (G[(size_t)p * n + row] - v) / sq;
-        L[c * SLAR_NMAX + row] = out;
-      }
+      part[sub][row] = v;
     }
     __syncthreads();
-    if (t < n) {
-      if (t == p) { taken[t] = 1; dres[t] = 0.0; }
-      else if (!taken[t]) dres[t] = fmax(dres[t] - L[c * SLAR_NMAX + t] * L[c * SLAR_NMAX + t], 0.0);
+    if (sub == 0 && row < n) {
+      const double v = (part[0][row] + part[1][row]) + (part[2][row] + part[3][row]);
+      double out = 0.0;
+      if (row == p) {
+        out = sq;
+        taken[row] = 1;
+        dres[row] = 0.0;
+      } else if (!taken[row]) {
+        out = (G[(size_t)p * n + row] - v) / sq;
+        dres[row] = fmax(dres[row] - out * out, 0.0);
+      }
+      L[c * SLAR_NMAX + row] = out;
     }
     __syncthreads();
   }
@@ -537,7 +569,7 @@ __global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
   __syncthreads();
   const double floor_abs = 1e-22 * trace + 1e-300;   // columns below this are negligible
   const double orth = 4.0 * n * 2.220446049250313e-16;
-  if (kp >= 2) jacobi_cols<8, 0>(L, SLAR_NMAX, n, kp, nullptr, 0, 0, orth, floor_abs, 40, &s_rot);
+  if (kp >= 2) jacobi_cols<8, 0>(L, SLAR_NMAX, n, kp, nullptr, 0, 0, orth, floor_abs, 40, nrm, &s_rot);
   for (int j = t; j < kp; j += blockDim.x) {
     double acc = 0.0;
     for (int r = 0; r < n; ++r) acc += L[j * SLAR_NMAX + r] * L[j * SLAR_NMAX + r];
