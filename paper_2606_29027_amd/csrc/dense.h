@@ -15,6 +15,10 @@ hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* s
 hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* const* G,
                          double* const* lam, double* const* V);
 hipError_t sign_fix(hipStream_t s, int rows, int cols, double* A, int lda, double* B, int ldb, int rowsB);
+// the same rule for tall A (cols <= 64) in three coalesced passes; scratch
+// holds (min(256, rows / 64) + 1) cols doubles (else the one-pass form runs)
+hipError_t sign_fix_tall(hipStream_t s, double* scratch, size_t scratch_elems, int rows, int cols,
+                         double* A, int lda, double* B, int ldb, int rowsB);
 hipError_t copy2d(hipStream_t s, int rows, int cols, const double* A, int lda, double* B, int ldb,
                   const double* colscale);
 hipError_t fill(hipStream_t s, double* p, long long n, double v);

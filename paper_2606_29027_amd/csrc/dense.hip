@@ -656,6 +656,107 @@ hipError_t sign_fix(hipStream_t s, int rows, int cols, double* A, int lda, doubl
   return hipGetLastError();
 }
 
+// The same sign rule for tall A (rows >> cols, cols <= 64), in three
+// coalesced passes: per-block column maxima; per column the maximum, the
+// first block reaching the near-tie threshold and the first such row in
+// it (the lowest qualifying index overall); the flips.
+constexpr int SF_COLS = 64;
+
+__global__ __launch_bounds__(256) void k_sign_part(int rows, int cols, const double* __restrict__ A,
+                                                   int lda, int rb, double* __restrict__ part) {
+  __shared__ double red[4][SF_COLS];
+  const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * rb, r1 = min(rows, r0 + rb);
+  double m = -1.0;
+  if (c < cols)
+    for (int r = r0 + rl; r < r1; r += 4) m = fmax(m, fabs(A[(long long)r * lda + c]));
+  red[rl][c] = m;
+  __syncthreads();
+  if (rl == 0 && c < cols)
+    part[(size_t)blockIdx.x * cols + c] = fmax(fmax(red[0][c], red[1][c]), fmax(red[2][c], red[3][c]));
+}
+
+__global__ __launch_bounds__(256) void k_sign_decide(int rows, int cols, const double* __restrict__ A,
+                                                     int lda, int rb, int nb,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ sgn) {
+  __shared__ double redm[256];
+  __shared__ int redi[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double m = -1.0;
+  for (int b = t; b < nb; b += blockDim.x) m = fmax(m, part[(size_t)b * cols + c]);
+  redm[t] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) redm[t] = fmax(redm[t], redm[t + o]);
+    __syncthreads();
+  }
+  const double top = redm[0];
+  const double thr = top * (1.0 - 1e-10);
+  int bb = nb;
+  for (int b = t; b < nb; b += blockDim.x)
+    if (part[(size_t)b * cols + c] >= thr) { bb = b; break; }
+  redi[t] = bb;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) redi[t] = min(redi[t], redi[t + o]);
+    __syncthreads();
+  }
+  const int bstar = redi[0];
+  __syncthreads();
+  int best = rows;
+  if (bstar < nb) {
+    const int r1 = min(rows, (bstar + 1) * rb);
+    for (int r = bstar * rb + t; r < r1; r += blockDim.x)
+      if (fabs(A[(long long)r * lda + c]) >= thr) { best = r; break; }
+  }
+  redi[t] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) redi[t] = min(redi[t], redi[t + o]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int p = redi[0];
+    sgn[c] = (p < rows && top > 0.0 && A[(long long)p * lda + c] < 0.0) ? -1.0 : 1.0;
+  }
+}
+
+__global__ void k_sign_apply(long long na, int cols, double* __restrict__ A, int lda, long long nbe,
+                             double* __restrict__ B, int ldb, const double* __restrict__ sgn) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < na) {
+    const int c = (int)(e % cols);
+    if (sgn[c] < 0.0) {
+      double* a = A + (e / cols) * lda + c;
+      *a = -*a;
+    }
+  } else if (e < na + nbe) {
+    const long long f = e - na;
+    const int c = (int)(f % cols);
+    if (sgn[c] < 0.0) {
+      double* b = B + (f / cols) * ldb + c;
+      *b = -*b;
+    }
+  }
+}
+
+hipError_t sign_fix_tall(hipStream_t s, double* scratch, size_t scratch_elems, int rows, int cols,
+                         double* A, int lda, double* B, int ldb, int rowsB) {
+  if (cols <= 0) return hipSuccess;
+  const int nb = std::min(256, std::max(1, (rows + 63) / 64));
+  const int rb = (rows + nb - 1) / nb;
+  if (cols > SF_COLS || (size_t)(nb + 1) * cols > scratch_elems)
+    return sign_fix(s, rows, cols, A, lda, B, ldb, rowsB);
+  double* part = scratch;
+  double* sgn = scratch + (size_t)nb * cols;
+  k_sign_part<<<nb, 256, 0, s>>>(rows, cols, A, lda, rb, part);
+  k_sign_decide<<<cols, 256, 0, s>>>(rows, cols, A, lda, rb, nb, part, sgn);
+  const long long na = (long long)rows * cols, nbe = B ? (long long)rowsB * cols : 0;
+  k_sign_apply<<<(unsigned)((na + nbe + 255) / 256), 256, 0, s>>>(na, cols, A, lda, nbe, B, ldb, sgn);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------- helpers
 __global__ void k_copy2d(int rows, int cols, const double* __restrict__ A, int lda,
                          double* __restrict__ B, int ldb, const double* __restrict__ colscale) {

@@ -206,7 +206,9 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
   if (gemm_f64(ws, ws->aux, true, false, G.nv, r, k, 1.0, b.Qv, G.nv, 0, b.Z, k, 0, 0.0, b.Y, r, 0, 1) != hipSuccess)
     return SLAR_E_HIP;
   if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
-  if (sign_fix(s, G.nx, r, b.X, r, b.Y, r, G.nv) != hipSuccess) return SLAR_E_HIP;
+  // the Cholesky-QR partials in dwork are dead once both chains have joined
+  if (sign_fix_tall(s, ws->dwork, ws->dwork_elems, G.nx, r, b.X, r, b.Y, r, G.nv) != hipSuccess)
+    return SLAR_E_HIP;
   k_diag<<<(r * r + 255) / 256, 256, 0, s>>>(r, b.sv, (double*)out->root);
   if (d == 2) {
     if (copy2d(s, G.nx, r, b.X, r, (double*)out->leaf[0], r, nullptr) != hipSuccess) return SLAR_E_HIP;
