@@ -336,6 +336,7 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
   const double* vk = V + (size_t)k * Nv;
   const int j = pivot_from_parts(vk, part, part + ACA_MAXBLK, part + (size_t)PVAL * ACA_MAXBLK, nbrow, Nv,
                                  NoSkip{}, red, redi, &M);
+  if (tile == 0 && t == 0) { ctl->j = j; ctl->pivot = M; }   // read by the bookkeeping launch
   const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
   if (M == 0.0 || M <= thr || j >= Nv) return;   // row already reproduced
   // finish the row-fiber dot products for the bookkeeping launch:
@@ -424,24 +425,23 @@ __device__ void aca_fin_body(const AcaInst& I) {
   const double* __restrict__ V = I.V;
   unsigned char* __restrict__ used = I.used;
   const double* __restrict__ part = I.part;
-  const int nbrow = I.nbrow, nbcol = I.nbcol, nprobe = I.nprobe;
+  const int nbcol = I.nbcol, nprobe = I.nprobe;
   const int* __restrict__ probes = I.probes;
   __shared__ FsLds<W, DX> L;
   __shared__ double red[4];
   __shared__ int redi[4];
   __shared__ double sgv[SLAR_KMAX + 1], sgu[SLAR_KMAX + 1];
-  __shared__ double rmax_[FIN_NB], ridx_[FIN_NB], rval_[FIN_NB];
   __shared__ double cmax_[FIN_NB], cidx_[FIN_NB], cval_[FIN_NB];
   __shared__ double res[1024];
   __shared__ int pi[1024];
-  __shared__ int s_phase, s_i, s_k, s_stop;
-  __shared__ double s_tol, s_norm2;
+  __shared__ int s_phase, s_i, s_k, s_stop, s_j;
+  __shared__ double s_tol, s_norm2, s_M;
   const int t = threadIdx.x;
-  if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; s_tol = ctl->tol; s_norm2 = ctl->norm2; }
-  const double* pc = part + (size_t)PCOL * ACA_MAXBLK;
-  for (int b = t; b < nbrow; b += blockDim.x) {
-    rmax_[b] = part[b]; ridx_[b] = part[ACA_MAXBLK + b]; rval_[b] = part[(size_t)PVAL * ACA_MAXBLK + b];
+  if (t == 0) {
+    s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; s_tol = ctl->tol; s_norm2 = ctl->norm2;
+    s_j = ctl->j; s_M = ctl->pivot;
   }
+  const double* pc = part + (size_t)PCOL * ACA_MAXBLK;
   for (int b = t; b < nbcol; b += blockDim.x) {
     cmax_[b] = pc[b]; cidx_[b] = pc[ACA_MAXBLK + b]; cval_[b] = pc[(size_t)PVAL * ACA_MAXBLK + b];
   }
@@ -450,9 +450,10 @@ __device__ void aca_fin_body(const AcaInst& I) {
   const int i = s_i;
   int k = s_k;
   const int Nx = g.nx, Nv = g.nv;
-  double M;
-  const double* vk = V + (size_t)k * Nv;
-  const int j = pivot_from_parts(vk, rmax_, ridx_, rval_, nbrow, Nv, NoSkip{}, red, redi, &M);
+  // column pivot j of the row residual and its maximum M, as every block
+  // of the column launch derived them from the row partials
+  const int j = s_j;
+  const double M = s_M;
   const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
   const bool zero_row = (M == 0.0 || M <= thr || j >= Nv);
   if (t == 0) {
@@ -494,8 +495,6 @@ __device__ void aca_fin_body(const AcaInst& I) {
       c = wave_sum(c);
       if (t == 0) {
         ctl->samples += Nx;
-        ctl->j = j;
-        ctl->pivot = M;   // row residual maximum (diagnostic; the column kernel reads v_k[j])
         const double nk = sgu[k] * sgv[k];
         const double norm2 = s_norm2 + 2.0 * c + nk;
         ctl->norm2 = norm2;
