@@ -17,6 +17,7 @@ from oracle import grid as G
 from oracle import ht as HT
 from oracle import lomac as LM
 from oracle import macro as MA
+from oracle import nested_cross as NC
 from oracle import spectral as SP
 from oracle import step as ST
 from oracle import timeint as TI
@@ -210,6 +211,94 @@ def test_slar_matches_full_grid_update_within_tolerance():
     dense = _brute(F0, rows, wts).reshape((12,) * 4)
     err = np.linalg.norm(HT.full(Fn) - dense) / np.linalg.norm(dense)
     assert err < 5 * p.tol
+
+
+# ------------------------------------------- nested HT cross (next: row 3)
+def _lookup(A):
+    return lambda idx: A[idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3]]
+
+
+def _probes4(n, m, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.integers(0, n[a], m) for a in range(4)], 1)
+
+
+@pytest.mark.parametrize("n,ranks", [((7, 6, 8, 5), (3, 2, 3, 4, 4, 4)),
+                                     ((12, 12, 12, 12), (5, 5, 5, 5, 8, 8)),
+                                     ((10, 9, 11, 8), (4, 5, 3, 4, 6, 6))])
+def test_nested_cross_recovers_exact_ht_ranks(n, ranks):
+    """A tensor of exact HT ranks is reproduced to rounding by the nested
+    skeleton, with exactly those ranks (brute force: full reconstruction)."""
+    A = HT.full(SI.random_ht(4, n, ranks, seed=21))
+    F, info = NC.nested_cross(_lookup(A), n, 1e-12, 30, _probes4(n, 64, 22), seed_index=(1, 2, 3, 1))
+    assert np.linalg.norm(HT.full(F) - A) <= 1e-11 * np.linalg.norm(A)
+    assert info["ranks"] == list(ranks)
+    assert info["samples"] < A.size
+
+
+def test_nested_cross_reproduces_its_sampled_blocks():
+    """The skeleton interpolates: every entry of A[R1 x R2, P_v] and of
+    A[P_x, R3 x R4] that it sampled is reproduced exactly."""
+    n = (9, 8, 10, 7)
+    A = HT.full(SI.random_ht(4, n, (4, 3, 5, 3, 5, 5), seed=23))
+    A = A + 1e-3 * np.sin(np.arange(A.size).reshape(A.shape))      # not of low rank
+    F, info = NC.nested_cross(_lookup(A), n, 1e-4, 30, _probes4(n, 64, 24))
+    B = HT.full(F)
+    s = info["sets"]
+    for a in s["R"][0]:
+        for b in s["R"][1]:
+            for (j1, j2) in s["Pv"]:
+                assert abs(B[a, b, j1, j2] - A[a, b, j1, j2]) <= 1e-10 * np.abs(A).max()
+    for (i1, i2) in s["Px"]:
+        for p in s["R"][2]:
+            for q in s["R"][3]:
+                assert abs(B[i1, i2, p, q] - A[i1, i2, p, q]) <= 1e-9 * np.abs(A).max()
+
+
+def test_nested_cross_matches_full_grid_sl_update():
+    """Nested cross of the SL-FD update (entries from the dense update of a
+    12^4 Landau state, section 3.1) against that dense update: error of the
+    order of the tolerance."""
+    p = SI.config("landau2d", n=12).with_(tol=1e-6, rmax=40, alpha=0.3)
+    o = ST.Oracle(p, probes=SI.probe_indices(144, 144, 64, 3))
+    F0 = SI.initial_ht(p)
+    E = o.efield(F0)
+    idx = np.stack(np.unravel_index(np.arange(12 ** 4), (12,) * 4), 1)
+    foot = FT.feet(idx, p.lo, p.hi, p.n, 2, 2, 0.5, 1.0, E)
+    rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, 3, 2, 2)
+    dense = _brute(F0, rows, wts).reshape((12,) * 4)
+    F, info = NC.nested_cross(_lookup(dense), (12,) * 4, p.tol, 64, _probes4((12,) * 4, 64, 25),
+                              seed_index=(0, 0, 6, 6))
+    err = np.linalg.norm(HT.full(F) - dense) / np.linalg.norm(dense)
+    assert err < 5 * p.tol, err
+    assert info["converged"]
+
+
+def test_nested_cross_zero_and_rank_one():
+    n = (6, 5, 7, 4)
+    F, info = NC.nested_cross(_lookup(np.zeros(n)), n, 1e-8, 10, _probes4(n, 16, 26))
+    assert np.all(HT.full(F) == 0.0) and info["ranks"] == [0] * 6
+    rng = np.random.default_rng(27)
+    a = [rng.standard_normal(k) + 2.0 for k in n]
+    A = np.einsum("i,j,k,l->ijkl", *a)
+    F, info = NC.nested_cross(_lookup(A), n, 1e-10, 10, _probes4(n, 16, 28))
+    assert info["ranks"] == [1] * 6
+    assert np.abs(HT.full(F) - A).max() <= 1e-12 * np.abs(A).max()
+
+
+def test_nested_cross_samples_grow_linearly_in_n():
+    """Fixed HT ranks, n doubled: the nested skeleton samples grow about
+    linearly in n; cross approximation on the {x}|{v} matricisation would
+    sample k (N_x + N_v) = 2 k n^2 entries, four times more."""
+    ranks = (3, 3, 3, 3, 4, 4)
+    s = []
+    for n in (16, 32):
+        A = HT.full(SI.random_ht(4, (n,) * 4, ranks, seed=29))
+        F, info = NC.nested_cross(_lookup(A), (n,) * 4, 1e-12, 20, _probes4((n,) * 4, 64, 30))
+        assert np.linalg.norm(HT.full(F) - A) <= 1e-10 * np.linalg.norm(A)
+        s.append(info["samples"])
+    assert s[1] < 2.5 * s[0]
+    assert s[1] < 2 * 4 * 32 ** 2
 
 
 def test_truncation_error_bound_and_leading_singular_vectors():
