@@ -168,6 +168,41 @@ slar_status slar_cross_update(const slar_grid* g, const slar_frames* src, const 
                               const int32_t* probes, slar_lowrank* out, slar_cross_info* info,
                               slar_workspace* ws, hipStream_t stream);
 
+/* Nested HT cross approximation of the same SL-FD update (d = 4, stencil
+ * order 3): the cheaper cross sampler sections 4 and 5 call for, in the
+ * nested skeleton form of Ballani, Grasedyck and Kluge (2013).  Leaf pivot
+ * rows R_mu and complements Q_mu are searched inside (sibling rows) x
+ * (parent complement), the root pivots P_x, P_v inside the products of the
+ * leaf rows, each search being the cross approximation of
+ * slar_cross_update (same pivot, tie, stopping and probe rules) at
+ * tol / 10; the probes (four per sweep in rotation, and the worst failing
+ * one) enrich the candidate sets, and after every sweep from the second on
+ * they check the skeleton against tol ||F||_F / sqrt(Nx Nv).  Output, a
+ * non-orthogonal HT (the skeleton):
+ *   leaf[m]  = A^(m)[:, Q_m] A^(m)[R_m, Q_m]^-1            [n_m][rank[m]]
+ *   B12      = A[R1, R2, P_v],  B34 = A[P_x, R3, R4]       (slar_ht layout)
+ *   root     = A[P_x, P_v]^-1                               [k][k]
+ *   probes : host int32 [nprobe][4] grid multi-indices (nprobe <= 1024)
+ *   seed   : host int32 [4], the first pivot of every leaf
+ *   out    : d = 4, FP64, caller-allocated with capacity leaf[m] n_m*kmax,
+ *            B12 and B34 kmax^3, root kmax^2 doubles; ranks are written
+ *   kmax   : 1 <= kmax <= 64
+ * Synchronises the stream.  SLAR_E_NOCONV: the probes still fail after 12
+ * sweeps (out holds the last skeleton); SLAR_E_NUMERIC: an all-zero update
+ * or a singular pivot block.                                                  */
+typedef struct {
+  int32_t sweeps;
+  int32_t probe_rounds;
+  int32_t converged;
+  int32_t rank[6];       /* r1, r2, r3, r4, k, k                            */
+  int64_t samples;       /* SL-FD entries evaluated                         */
+} slar_nested_info;
+
+slar_status slar_nested_cross(const slar_grid* g, const slar_frames* src, const slar_adv* a,
+                              slar_dtype dtype, double tol, int32_t kmax, int32_t nprobe,
+                              const int32_t* probes, const int32_t* seed, slar_ht* out,
+                              slar_nested_info* info, slar_workspace* ws, hipStream_t stream);
+
 /* HTACA's final truncation (Supplement B): orthogonalise both factor sets,
  * SVD of the small core, root truncation with theta = tol ||F||_F /
  * sqrt(2d-3), then (d = 4) each leaf = leading left singular vectors of its

@@ -222,7 +222,7 @@ def nested_cross(f, n, tol: float, kmax: int, probes, seed_index=(0, 0, 0, 0),
     F = None
     for sweep in range(max_sweeps):
         # enrichment: `enrich` probes in rotation, plus the last failed probe
-        E = [tuple(int(v) for v in pr[(sweep * enrich + t) % m]) for t in range(min(enrich, m))]
+        E = _union([], [tuple(int(v) for v in pr[(sweep * enrich + t) % m]) for t in range(min(enrich, m))])
         E = _union(E, forced)
         Ru = [_union(R[a], [e[a] for e in E]) for a in range(4)]
         Pxu = _union(Px, [(e[0], e[1]) for e in E])

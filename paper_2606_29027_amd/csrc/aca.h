@@ -45,6 +45,14 @@ struct AcaInst {
   int nbrow, nbcol, nprobe;
   int team;            // lanes per sample in the fiber gathers (4, 8 or 16)
   const int* probes;
+  // index-table mode (nested cross searches): the matrix is nrows x ncols,
+  // entry (row, col) is the grid point whose multi-index joins
+  // rowtab[4 row ..] and coltab[4 col ..] (entries < 0 unset); accepted
+  // pivots (row, col) are logged in piv[2 k ..]
+  int nrows = 0, ncols = 0;
+  const int* rowtab = nullptr;
+  const int* coltab = nullptr;
+  int* piv = nullptr;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -125,6 +133,21 @@ __device__ __forceinline__ void unravel_x(const GridDev& g, int I, int* gi) {
 template <int DX>
 __device__ __forceinline__ void unravel_v(const GridDev& g, int J, int* gi) {
   if (DX == 1) gi[1] = J; else { gi[2] = J / g.n[3]; gi[3] = J % g.n[3]; }
+}
+
+// Grid multi-index of matrix entry (row, col): the {x}|{v} matricisation,
+// or (TAB) the union of the partial multi-indices of the two tables.
+template <int DX, bool TAB>
+__device__ __forceinline__ void entry_index(const AcaInst& I, int row, int col, int* gi) {
+  if (TAB) {
+    const int* rt = I.rowtab + 4 * row;
+    const int* ct = I.coltab + 4 * col;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) gi[d] = rt[d] >= 0 ? rt[d] : ct[d];
+  } else {
+    unravel_x<DX>(I.g, row, gi);
+    unravel_v<DX>(I.g, col, gi);
+  }
 }
 
 // Partial-sum layout (doubles): part[q * ACA_MAXBLK + b]
@@ -214,7 +237,7 @@ struct SkipUsed {
 constexpr int ACA_LREG = 16;
 static_assert(4 * ACA_LREG >= 64, "register cache covers every earlier cross vector (kmax <= 64)");
 
-template <typename T, int W, int DX>
+template <typename T, int W, int DX, bool TAB = false>
 __device__ void aca_row_body(const AcaInst& I, int tile) {
   const GridDev& g = I.g;
   const AdvDev& a = I.a;
@@ -236,7 +259,7 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
   __syncthreads();
   if (s_phase != ACA_RUN) return;
   const int i = s_i, k = s_k;
-  const int Nx = g.nx, Nv = g.nv;
+  const int Nx = TAB ? I.nrows : g.nx, Nv = TAB ? I.ncols : g.nv;
   const int J0 = tile * ACA_TILE;
   const int ns = min(ACA_TILE, Nv - J0);
   const int wv = t >> 6, ln = t & 63;
@@ -253,8 +276,7 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
     const int s = t >> 2;
     if (s < ns) {
       int gi[4];
-      unravel_x<DX>(g, i, gi);
-      unravel_v<DX>(g, J0 + s, gi);
+      entry_index<DX, TAB>(I, i, J0 + s, gi);
       fs_prepare<W, DX, 4>(g, a, gi, L, s, t & 3);
     }
   }
@@ -295,7 +317,7 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
                   &part[(size_t)PVAL * ACA_MAXBLK + tile]);
 }
 
-template <typename T, int W, int DX>
+template <typename T, int W, int DX, bool TAB = false>
 __device__ void aca_col_body(const AcaInst& I, int tile) {
   const GridDev& g = I.g;
   const AdvDev& a = I.a;
@@ -320,7 +342,7 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
   __syncthreads();
   if (s_phase != ACA_RUN) return;
   const int i = s_i, k = s_k;
-  const int Nx = g.nx, Nv = g.nv;
+  const int Nx = TAB ? I.nrows : g.nx, Nv = TAB ? I.ncols : g.nv;
   const int I0 = tile * ACA_TILE;
   const int ns = min(ACA_TILE, Nx - I0);
   const int wv = t >> 6, ln = t & 63;
@@ -362,8 +384,7 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
     const int s = t >> 2;
     if (s < ns) {
       int gi[4];
-      unravel_x<DX>(g, I0 + s, gi);
-      unravel_v<DX>(g, j, gi);
+      entry_index<DX, TAB>(I, I0 + s, j, gi);
       fs_prepare<W, DX, 4>(g, a, gi, L, s, t & 3);
     }
   }
@@ -413,7 +434,7 @@ static_assert(ACA_TILE <= FS_SAMPLES, "a fiber tile fits the sampler's LDS rows"
 static_assert(FIN_NB * ACA_TILE >= SLAR_NMAX * SLAR_NMAX && FIN_NB * ACA_TILE >= SLAR_NMAX_1D,
               "every fiber fits the staged partials");
 
-template <typename T, int W, int DX>
+template <typename T, int W, int DX, bool TAB = false>
 __device__ void aca_fin_body(const AcaInst& I) {
   const GridDev& g = I.g;
   const AdvDev& a = I.a;
@@ -449,7 +470,7 @@ __device__ void aca_fin_body(const AcaInst& I) {
   if (s_phase != ACA_RUN) return;
   const int i = s_i;
   int k = s_k;
-  const int Nx = g.nx, Nv = g.nv;
+  const int Nx = TAB ? I.nrows : g.nx, Nv = TAB ? I.ncols : g.nv;
   // column pivot j of the row residual and its maximum M, as every block
   // of the column launch derived them from the row partials
   const int j = s_j;
@@ -495,6 +516,7 @@ __device__ void aca_fin_body(const AcaInst& I) {
       c = wave_sum(c);
       if (t == 0) {
         ctl->samples += Nx;
+        if (TAB && I.piv) { I.piv[2 * k] = i; I.piv[2 * k + 1] = j; }
         const double nk = sgu[k] * sgv[k];
         const double norm2 = s_norm2 + 2.0 * c + nk;
         ctl->norm2 = norm2;
@@ -534,8 +556,7 @@ __device__ void aca_fin_body(const AcaInst& I) {
       pI = probes[2 * (base + s)];
       pJ = probes[2 * (base + s) + 1];
       int gi[4];
-      unravel_x<DX>(g, pI, gi);
-      unravel_v<DX>(g, pJ, gi);
+      entry_index<DX, TAB>(I, pI, pJ, gi);
       fs_prepare<W, DX, 4>(g, a, gi, L, s, q);
     }
     // approximation at the probe: the quad splits the l-sum
@@ -583,11 +604,11 @@ __device__ void aca_fin_body(const AcaInst& I) {
 }
 
 // --------------------------------------------------- single-instance kernels
-template <typename T, int W, int DX>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_row(AcaInst I) { aca_row_body<T, W, DX>(I, blockIdx.x); }
-template <typename T, int W, int DX>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_col(AcaInst I) { aca_col_body<T, W, DX>(I, blockIdx.x); }
-template <typename T, int W, int DX>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_fin(AcaInst I) { aca_fin_body<T, W, DX>(I); }
+template <typename T, int W, int DX, bool TAB = false>
+__global__ __launch_bounds__(FS_THREADS) void k_aca_row(AcaInst I) { aca_row_body<T, W, DX, TAB>(I, blockIdx.x); }
+template <typename T, int W, int DX, bool TAB = false>
+__global__ __launch_bounds__(FS_THREADS) void k_aca_col(AcaInst I) { aca_col_body<T, W, DX, TAB>(I, blockIdx.x); }
+template <typename T, int W, int DX, bool TAB = false>
+__global__ __launch_bounds__(FS_THREADS) void k_aca_fin(AcaInst I) { aca_fin_body<T, W, DX, TAB>(I); }
 
 }  // namespace slar

@@ -99,7 +99,10 @@ slar_status slar_workspace_destroy(slar_workspace* w) {
   Workspace& ws = w->w;
   blas_release(&ws);
   void* dev[] = {ws.Eeff, ws.X32, ws.P32, ws.aca_ctl, ws.aca_part, ws.used, ws.resid, ws.dwork,
-                 ws.small, ws.ismall, ws.tw[0], ws.tw[1], ws.cbuf, ws.psi, ws.lm, ws.kry};
+                 ws.small, ws.ismall, ws.tw[0], ws.tw[1], ws.cbuf, ws.psi, ws.lm, ws.kry,
+                 ws.nest_U, ws.nest_V, ws.nest_used, ws.nest_rowtab, ws.nest_coltab, ws.nest_probes,
+                 ws.nest_piv, ws.nest_idx, ws.nest_vals, ws.nest_small, ws.nest_flag, ws.nest_fX,
+                 ws.nest_fP, ws.nest_X64, ws.nest_P64};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : ws.events) (void)hipEventDestroy(e);
@@ -156,6 +159,24 @@ slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspa
   dalloc((void**)&ws.psi, sizeof(double) * G.nv * nm);
   dalloc((void**)&ws.lm, sizeof(double) * ws.lm_elems);
   dalloc((void**)&ws.kry, sizeof(double) * ws.kry_elems);
+  if (G.d == 4) {
+    const size_t NT = 16384, NL = nest_list_elems();
+    dalloc((void**)&ws.nest_U, sizeof(double) * 64 * NT);
+    dalloc((void**)&ws.nest_V, sizeof(double) * 64 * NT);
+    dalloc((void**)&ws.nest_used, NT);
+    dalloc((void**)&ws.nest_rowtab, sizeof(int) * 4 * NT);
+    dalloc((void**)&ws.nest_coltab, sizeof(int) * 4 * NT);
+    dalloc((void**)&ws.nest_probes, sizeof(int) * 2 * 128);
+    dalloc((void**)&ws.nest_piv, sizeof(int) * 2 * SLAR_KMAX);
+    dalloc((void**)&ws.nest_idx, sizeof(int) * 4 * NL);
+    dalloc((void**)&ws.nest_vals, sizeof(double) * NL);
+    dalloc((void**)&ws.nest_small, sizeof(double) * 6 * 64 * 64);
+    dalloc((void**)&ws.nest_flag, sizeof(int) * 4);
+    dalloc((void**)&ws.nest_fX, sizeof(double) * G.nx * SLAR_KMAX);
+    dalloc((void**)&ws.nest_fP, sizeof(double) * G.nv * SLAR_KMAX);
+    dalloc((void**)&ws.nest_X64, sizeof(double) * G.nx * SLAR_KMAX);
+    dalloc((void**)&ws.nest_P64, sizeof(double) * G.nv * SLAR_KMAX);
+  }
   if (ok && hipHostMalloc(&ws.aca_ctl_host, 3 * aca_ctl_bytes(), 0) != hipSuccess) ok = false;
   for (hipEvent_t& e : ws.poll_ev)
     if (ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
@@ -234,6 +255,27 @@ slar_status slar_frame_sample(const slar_grid* g, const slar_frames* F, const sl
   }
   return frame_points(stream, G, A, dtype, X, P, ldt, F->r, n, idx, out) == hipSuccess ? SLAR_OK
                                                                                         : SLAR_E_HIP;
+}
+
+slar_status slar_nested_cross(const slar_grid* g, const slar_frames* src, const slar_adv* a,
+                              slar_dtype dtype, double tol, int32_t kmax, int32_t nprobe,
+                              const int32_t* probes, const int32_t* seed, slar_ht* out,
+                              slar_nested_info* info, slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !frames_ok(src) || !adv_ok(g, a))
+    return SLAR_E_INVAL;
+  const GridDev& G = w->w.G;
+  if (G.d != 4 || a->order != 3 || (dtype != SLAR_F32 && dtype != SLAR_F64)) return SLAR_E_INVAL;
+  if (!(tol > 0.0) || kmax < 1 || kmax > 64 || nprobe < 0 || nprobe > 1024) return SLAR_E_INVAL;
+  if ((nprobe > 0 && !probes) || !seed || !out) return SLAR_E_INVAL;
+  if (!out->leaf[0] || !out->leaf[1] || !out->leaf[2] || !out->leaf[3] || !out->B12 || !out->B34 ||
+      !out->root)
+    return SLAR_E_INVAL;
+  for (int m = 0; m < 4; ++m)
+    if (seed[m] < 0 || seed[m] >= G.n[m]) return SLAR_E_INVAL;
+  for (int q = 0; q < nprobe; ++q)
+    for (int m = 0; m < 4; ++m)
+      if (probes[4 * q + m] < 0 || probes[4 * q + m] >= G.n[m]) return SLAR_E_INVAL;
+  return nested_run(stream, &w->w, *src, *a, dtype, tol, kmax, nprobe, probes, seed, out, info);
 }
 
 slar_status slar_cross_update(const slar_grid* g, const slar_frames* src, const slar_adv* a,

@@ -89,6 +89,24 @@ struct Workspace {
   // rocBLAS handles of the GEMMs, one per stream the workspace has run a
   // product on (bound to that stream); released by blas_release
   std::vector<std::pair<hipStream_t, void*>> blas;
+  // nested HT cross (d = 4 only): search factors and tables, sample lists,
+  // small matrices, frames for the norm, FP64 sampling tables
+  double* nest_U = nullptr;        // [64][NEST_TAB]
+  double* nest_V = nullptr;        // [64][NEST_TAB]
+  unsigned char* nest_used = nullptr;
+  int* nest_rowtab = nullptr;      // [NEST_TAB][4]
+  int* nest_coltab = nullptr;      // [NEST_TAB][4]
+  int* nest_probes = nullptr;      // [128][2]
+  int* nest_piv = nullptr;         // [2 SLAR_KMAX]
+  int* nest_idx = nullptr;         // [nest_list_elems][4]
+  double* nest_vals = nullptr;     // [nest_list_elems]
+  double* nest_small = nullptr;    // [6][64 * 64]
+  int* nest_flag = nullptr;        // [4]
+  double* nest_fX = nullptr;       // [Nx][SLAR_KMAX]
+  double* nest_fP = nullptr;       // [Nv][SLAR_KMAX]
+  double* nest_X64 = nullptr;      // [Nx][SLAR_KMAX]
+  double* nest_P64 = nullptr;      // [Nv][SLAR_KMAX]
+  long long nest_samples = 0;
 };
 
 // launchers implemented across the .hip files
@@ -98,6 +116,10 @@ struct Workspace {
 hipError_t gemm_f64(Workspace* ws, hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
                     const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
                     double beta, double* C, int ldc, long long sC, int batch);
+size_t nest_list_elems();
+slar_status nested_run(hipStream_t s, Workspace* ws, const slar_frames& src, const slar_adv& adv,
+                       slar_dtype dt, double tol, int kmax, int nprobe, const int* probes, const int* seed,
+                       slar_ht* out, slar_nested_info* info);
 // destroys the handles gemm_f64 created for ws (the workspace's streams idle)
 void blas_release(Workspace* ws);
 hipError_t combine_field(hipStream_t s, const GridDev& G, const slar_adv* a, double* out);

@@ -20,7 +20,7 @@ F32, F64 = 0, 1
 
 EXPORTS = (
     "slar_status_str", "slar_workspace_create", "slar_workspace_destroy", "slar_ht_sample",
-    "slar_frames_from_ht", "slar_frame_sample", "slar_cross_update", "slar_truncate",
+    "slar_frames_from_ht", "slar_frame_sample", "slar_cross_update", "slar_nested_cross", "slar_truncate",
     "slar_moments", "slar_poisson", "slar_conserved", "slar_lomac_prepare", "slar_macro_solve",
     "slar_lomac_project", "slar_cnn_create", "slar_cnn_destroy", "slar_cnn_nparams",
     "slar_cnn_set_params", "slar_cnn_get_params", "slar_cnn_forward", "slar_cnn_grad",
@@ -61,6 +61,11 @@ class CrossInfo(C.Structure):
                 ("converged", C.c_int32), ("samples", C.c_int64)]
 
 
+class NestedInfo(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("probe_rounds", C.c_int32), ("converged", C.c_int32),
+                ("rank", C.c_int32 * 6), ("samples", C.c_int64)]
+
+
 class MacroSystem(C.Structure):
     _fields_ = [("nhist", C.c_int32), ("U", C.c_void_p * 3), ("c", C.c_double * 3),
                 ("nstage", C.c_int32), ("R", C.c_void_p * 3), ("d", C.c_double * 3),
@@ -95,6 +100,8 @@ def load(path: str = LIB_PATH):
         "slar_frame_sample": (i32, [P(Grid), P(Frames), P(Adv), i32, i64, vp, vp, vp, vp]),
         "slar_cross_update": (i32, [P(Grid), P(Frames), P(Adv), i32, dbl, i32, i32, vp,
                                     P(LowRank), P(CrossInfo), vp, vp]),
+        "slar_nested_cross": (i32, [P(Grid), P(Frames), P(Adv), i32, dbl, i32, i32, vp, vp, P(HT),
+                                    P(NestedInfo), vp, vp]),
         "slar_truncate": (i32, [P(Grid), P(LowRank), dbl, i32, P(HT), vp, vp]),
         "slar_moments": (i32, [P(Grid), P(Frames), vp, vp, vp]),
         "slar_poisson": (i32, [P(Grid), vp, dbl, vp, vp, vp, vp]),
@@ -241,6 +248,23 @@ def slar_cross_update(grid, src, adv, dtype, tol, kmax, probes, U, V, ws):
                                   C.byref(info), ws.h, _stream())
     _check(st, "slar_cross_update", ok=(SLAR_OK, SLAR_E_RANK_CAP))
     return lr, info, st
+
+
+def slar_nested_cross(grid, src, adv, dtype, tol, kmax, probes, seed, out: HT, ws):
+    """Nested HT cross of the SL-FD update (d = 4).  probes: host int32
+    (m, 4) array, seed: 4 ints; out: HT of FP64 device buffers with the
+    capacities documented in slar.h (ranks are written).  Returns
+    (info, status); SLAR_E_NOCONV is returned, not raised."""
+    import numpy as np
+    pr = np.ascontiguousarray(np.asarray(probes, dtype=np.int32).reshape(-1, 4))
+    sd = np.ascontiguousarray(np.asarray(seed, dtype=np.int32).reshape(4))
+    info = NestedInfo()
+    st = load().slar_nested_cross(C.byref(grid), C.byref(src), C.byref(adv), int(dtype), float(tol),
+                                  int(kmax), int(pr.shape[0]), pr.ctypes.data_as(C.c_void_p),
+                                  sd.ctypes.data_as(C.c_void_p), C.byref(out), C.byref(info), ws.h,
+                                  _stream())
+    _check(st, "slar_nested_cross", ok=(SLAR_OK, SLAR_E_NOCONV))
+    return info, st
 
 
 def slar_truncate(grid, lr, tol, rmax, out_ht: HT, ws):

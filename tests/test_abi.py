@@ -55,6 +55,8 @@ def test_status_strings_and_invalid_arguments_without_gpu():
     assert lib.slar_workspace_create(C.byref(g), 40, C.byref(h)) == L.SLAR_E_INVAL
     assert lib.slar_cnn_create(0, None, 1, 1, C.byref(h)) == L.SLAR_E_INVAL
     assert lib.slar_truncate(None, None, 1e-6, 10, None, None, None) == L.SLAR_E_INVAL
+    assert lib.slar_nested_cross(None, None, None, L.F64, 1e-6, 10, 0, None, None, None, None, None,
+                                 None) == L.SLAR_E_INVAL
 
 
 LAYOUT_C = r"""
@@ -75,6 +77,8 @@ int main(void) {
   P(slar_lowrank, U) P(slar_lowrank, V)
   printf("slar_cross_info %zu\n", sizeof(slar_cross_info));
   P(slar_cross_info, samples)
+  printf("slar_nested_info %zu\n", sizeof(slar_nested_info));
+  P(slar_nested_info, rank) P(slar_nested_info, samples)
   printf("slar_macro_system %zu\n", sizeof(slar_macro_system));
   P(slar_macro_system, U) P(slar_macro_system, c) P(slar_macro_system, nstage)
   P(slar_macro_system, R) P(slar_macro_system, d) P(slar_macro_system, beta)
@@ -99,7 +103,7 @@ def test_ctypes_struct_layout_matches_header(tmp_path):
     from paper_2606_29027_amd import lib as L
     mirror = {"slar_grid": L.Grid, "slar_ht": L.HT, "slar_frames": L.Frames, "slar_adv": L.Adv,
               "slar_lowrank": L.LowRank, "slar_cross_info": L.CrossInfo,
-              "slar_macro_system": L.MacroSystem}
+              "slar_macro_system": L.MacroSystem, "slar_nested_info": L.NestedInfo}
     for key, val in out.items():
         if "." in key:
             t, f = key.split(".")

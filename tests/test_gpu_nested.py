@@ -1,0 +1,142 @@
+"""Nested HT cross on the GPU (slar_nested_cross) against the oracle's
+nested cross of the same SL-FD update: identical ranks and skeleton
+factors (FP64 tables), and the reconstruction within the tolerance of the
+dense full-grid update."""
+import numpy as np
+import pytest
+
+import slar_inputs as SI
+from oracle import feet as FT
+from oracle import ht as HT
+from oracle import nested_cross as NC
+from oracle import step as ST
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2606_29027_amd import lib as L  # noqa: E402
+from gpu_util import dev, ht_from_dev, normwise  # noqa: E402
+
+
+def _problem(N, tol, alpha, tau):
+    p = SI.config("landau2d", n=N).with_(tol=tol, rmax=40, alpha=alpha)
+    o = ST.Oracle(p, probes=SI.probe_indices(N * N, N * N, 64, 3))
+    F0 = SI.initial_ht(p)
+    E = o.efield(F0)
+    idx = np.stack(np.unravel_index(np.arange(N ** 4), (N,) * 4), 1)
+    foot = FT.feet(idx, p.lo, p.hi, p.n, 2, 2, tau, 1.0, E)
+    rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, 3, 2, 2)
+    dense = HT.block_interp(HT.full(F0)[None], rows, wts)[:, 0].reshape((N,) * 4)
+    return p, F0, E, dense
+
+
+def _frames(F0, N):
+    X = HT.x_frame(F0).reshape(N * N, -1)
+    Vf = HT.v_frame(F0).reshape(N * N, -1)
+    P = Vf @ F0["root"].T
+    return np.ascontiguousarray(X), np.ascontiguousarray(P)
+
+
+def _out_ht(n, kmax):
+    T = {"leaves": [torch.zeros(n[m] * kmax, dtype=torch.float64, device="cuda") for m in range(4)],
+         "B12": torch.zeros(kmax ** 3, dtype=torch.float64, device="cuda"),
+         "B34": torch.zeros(kmax ** 3, dtype=torch.float64, device="cuda"),
+         "root": torch.zeros(kmax ** 2, dtype=torch.float64, device="cuda")}
+    H = L.HT()
+    H.d = 4
+    H.dtype = L.F64
+    for m in range(4):
+        H.leaf[m] = T["leaves"][m].data_ptr()
+    H.B12 = T["B12"].data_ptr()
+    H.B34 = T["B34"].data_ptr()
+    H.root = T["root"].data_ptr()
+    H._keep = T
+    return H, T
+
+
+def _run_gpu(p, F0, E, N, dtype, tol, kmax, probes, seed, tau):
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 40)
+    X, P = _frames(F0, N)
+    Xd, Pd = dev(X), dev(P)
+    Fr = L.Frames(X.shape[1], X.shape[1], Xd.data_ptr(), Pd.data_ptr())
+    adv = L.make_adv(2, tau, 1.0, dev(E), order=3)
+    H, T = _out_ht(p.n, kmax)
+    info, st = L.slar_nested_cross(g, Fr, adv, dtype, tol, kmax, probes, seed, H, ws)
+    torch.cuda.synchronize()
+    return ht_from_dev(H, T, 4, p.n), info, st
+
+
+def _put(m, i, comp):
+    """Full multi-index: value i on axis m, the complement elsewhere."""
+    c = list(comp)
+    c.insert(m, i)
+    return tuple(c)
+
+
+def _probes(n, m, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.integers(0, n[a], m) for a in range(4)], 1).astype(np.int32)
+
+
+@pytest.mark.parametrize("N,tol,alpha", [(12, 1e-6, 0.3), (16, 1e-5, 0.1), (20, 1e-4, 0.1)])
+def test_nested_cross_matches_oracle_fp64(N, tol, alpha):
+    tau = 0.5
+    p, F0, E, dense = _problem(N, tol, alpha, tau)
+    pr = _probes(p.n, 64, 25)
+    seed = (0, 0, N // 2, N // 2)
+    Fo, io = NC.nested_cross(lambda i: dense[i[:, 0], i[:, 1], i[:, 2], i[:, 3]], p.n, tol, 64, pr,
+                             seed_index=seed)
+    Fg, ig, st = _run_gpu(p, F0, E, N, L.F64, tol, 64, pr, seed, tau)
+    assert st == L.SLAR_OK and ig.converged == 1 and io["converged"]
+    assert list(ig.rank) == io["ranks"]
+    assert ig.sweeps == io["sweeps"] and ig.probe_rounds == io["probe_rounds"]
+    # sampled blocks: entries of the update (frame sampler vs dense update)
+    assert normwise(Fg["B12"], Fo["B12"]) < 1e-12
+    assert normwise(Fg["B34"], Fo["B34"]) < 1e-12
+    # interpolants and the inverse core: two backward-stable inverses
+    # (Gauss-Jordan here, LAPACK LU in the oracle) agree to about
+    # cond(block) eps; the bar is 64 eps cond of the oracle's own blocks
+    eps = np.finfo(float).eps
+    s = io["sets"]
+    at = lambda idx: dense[tuple(np.asarray(idx).T)]   # noqa: E731
+    worst = 0.0
+    for m in range(4):
+        blk = np.array([[at([_put(m, i, q)])[0] for q in s["Q"][m]] for i in s["R"][m]])
+        bar = max(1e-12, 64 * eps * np.linalg.cond(blk))
+        worst = max(worst, bar)
+        assert normwise(Fg["leaves"][m], Fo["leaves"][m]) < bar, (m, bar)
+    core = np.array([[at([(x[0], x[1], v[0], v[1])])[0] for v in s["Pv"]] for x in s["Px"]])
+    bar = max(1e-12, 64 * eps * np.linalg.cond(core))
+    worst = max(worst, bar)
+    assert normwise(Fg["root"], Fo["root"]) < bar, bar
+    full = HT.full(Fg)
+    assert normwise(full, HT.full(Fo)) < max(1e-10, worst)
+    assert np.linalg.norm(full - dense) / np.linalg.norm(dense) < 5 * tol
+
+
+def test_nested_cross_fp32_tables_within_tolerance():
+    N, tol, tau = 12, 1e-5, 0.5
+    p, F0, E, dense = _problem(N, tol, 0.3, tau)
+    Fg, ig, st = _run_gpu(p, F0, E, N, L.F32, tol, 64, _probes(p.n, 64, 26), (0, 0, 6, 6), tau)
+    assert st in (L.SLAR_OK, L.SLAR_E_NOCONV)
+    assert np.linalg.norm(HT.full(Fg) - dense) / np.linalg.norm(dense) < 10 * tol
+
+
+def test_nested_cross_rejects_bad_arguments():
+    N = 12
+    p = SI.config("landau2d", n=N)
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 40)
+    X = dev(np.zeros((N * N, 4)))
+    Fr = L.Frames(4, 4, X.data_ptr(), X.data_ptr())
+    adv = L.make_adv(0, 0.1, 1.0, None, order=3)
+    H, _ = _out_ht(p.n, 8)
+    bad_probe = np.array([[0, 0, 0, N]], dtype=np.int32)
+    with pytest.raises(L.SlarError):
+        L.slar_nested_cross(g, Fr, adv, L.F64, 1e-6, 8, bad_probe, (0, 0, 0, 0), H, ws)
+    with pytest.raises(L.SlarError):
+        L.slar_nested_cross(g, Fr, adv, L.F64, 1e-6, 65, _probes(p.n, 4, 1), (0, 0, 0, 0), H, ws)
