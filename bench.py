@@ -69,12 +69,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--n", type=int, default=128, help="cells per dimension")
+    ap.add_argument("--nested-config", default="stronglandau2d",
+                    help="2D2V workload whose state the nested workload compares the samplers on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--variants", default="plain,spectral,learned",
                     help="comma list of macro solvers to time: plain, spectral, learned "
                          "(the last one listed is the headline)")
-    ap.add_argument("--workload", choices=["stronglandau2d", "batched", "samplers"], default="stronglandau2d",
+    ap.add_argument("--workload", choices=["stronglandau2d", "batched", "samplers", "nested"], default="stronglandau2d",
                     help="batched: 64 independent 1D1V/2D2V Landau instances of uneven size")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch configuration")
@@ -186,6 +188,84 @@ def batched_main(args):
     print(json.dumps(out))
 
 
+def nested_main(args):
+    """Nested HT cross against HTACA on one SL-FD update of a 2D2V workload
+    (--nested-config, default strong Landau; 128^4 unless --n): the state
+    after two steps of the workload, the first CF3 sub-flow of the next
+    step (RK4 frozen-field feet, tau = dt / 3, the state's own field).
+    HTACA (slar_cross_update, rank cap 60) and the nested cross
+    (slar_nested_cross, rank cap 64, 64 seeded probes) both sample through
+    FP32 frame tables; each is timed with events on the stream (three runs
+    after one warm-up, the median reported), and its approximation is
+    compared with the exact update (FP64 tables) at 4096 seeded random
+    entries.  One JSON line."""
+    import torch
+    import slar_inputs as SI
+    from paper_2606_29027_amd import lib as L
+    from paper_2606_29027_amd.solver import Solver
+    n = args.n
+    p = SI.config(args.nested_config, n=n)
+    Nx = n * n
+    s = Solver(p, L.F32, probes=SI.probe_indices(Nx, Nx, 64, 1234), precond=1)
+    s.set_initial(SI.initial_ht(p))
+    for _ in range(2):
+        s.step()
+    src = s.state
+    E1 = s.efield(src, s.E[0]).clone()
+    adv = L.make_adv(2, p.dt / 3.0, 1.0, E1)
+    g, ws = s.grid, s.ws
+    rng = np.random.default_rng(4321)
+    probes4 = np.stack([rng.integers(0, n, 64) for _ in range(4)], 1).astype(np.int32)
+    seed = (0, 0, n // 2, n // 2)
+    kmax = 64
+    T = {"leaves": [torch.zeros(n * kmax, dtype=torch.float64, device="cuda") for _ in range(4)],
+         "B12": torch.zeros(kmax ** 3, dtype=torch.float64, device="cuda"),
+         "B34": torch.zeros(kmax ** 3, dtype=torch.float64, device="cuda"),
+         "root": torch.zeros(kmax ** 2, dtype=torch.float64, device="cuda")}
+    H = L.HT()
+    H.d, H.dtype = 4, L.F64
+    for m in range(4):
+        H.leaf[m] = T["leaves"][m].data_ptr()
+    H.B12, H.B34, H.root = T["B12"].data_ptr(), T["B34"].data_ptr(), T["root"].data_ptr()
+
+    def timed(fn):
+        fn()
+        ms = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return sorted(ms)[1], out
+
+    ms_h, (lr, ih, sth) = timed(lambda: L.slar_cross_update(g, src, adv, L.F32, p.tol, 60, s.probes, s.U, s.V, ws))
+    ms_n, (inn, stn) = timed(lambda: L.slar_nested_cross(g, src, adv, L.F32, p.tol, kmax, probes4, seed, H, ws))
+    # accuracy at random entries against the exact update (FP64 tables)
+    idx = SI.random_requests(p.n, 4096, seed=99)
+    idx_d = torch.as_tensor(idx, dtype=torch.int32, device="cuda")
+    exact = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    L.slar_frame_sample(g, src, adv, L.F64, idx_d, exact, ws)
+    I = torch.as_tensor(idx[:, 0] * n + idx[:, 1], device="cuda")
+    J = torch.as_tensor(idx[:, 2] * n + idx[:, 3], device="cuda")
+    k = lr.k
+    approx_h = (s.U[:k][:, I] * s.V[:k][:, J]).sum(0)
+    approx_n = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    L.slar_ht_sample(g, H, L.make_adv(0, 0.0), idx_d, approx_n)
+    torch.cuda.synchronize()
+    rel = lambda a: float(torch.linalg.norm(a - exact) / torch.linalg.norm(exact))   # noqa: E731
+    print(json.dumps({
+        "workload": f"nested HT cross vs HTACA, one SL-FD update of the {args.nested_config} {n}^4 state "
+                    "after two steps (first CF3 sub-flow), FP32 tables, tol %g" % p.tol,
+        "htaca": {"ms": ms_h, "samples": int(ih.samples), "rank": int(ih.rank), "converged": int(ih.converged),
+                  "status": int(sth), "rel_err_4096": rel(approx_h)},
+        "nested": {"ms": ms_n, "samples": int(inn.samples), "ranks": list(inn.rank), "sweeps": int(inn.sweeps),
+                   "probe_rounds": int(inn.probe_rounds), "converged": int(inn.converged), "status": int(stn),
+                   "rel_err_4096": rel(approx_n)}}))
+    return 0
+
+
 def samplers_main(args):
     """Entry-evaluation microbenchmark on the 128^4 grid: a random HT of
     uniform rank r (orthonormal leaves, Gaussian transfer tensors, seed
@@ -200,10 +280,13 @@ def samplers_main(args):
     hits: 2 x 2.4 MB tables at r = 60) per second."""
     import torch
     import slar_inputs as SI
-    from oracle import step as ST          # field of the initial state only (input generation)
     from paper_2606_29027_amd import lib as L
+    from paper_2606_29027_amd.solver import Solver
     p = SI.config("stronglandau2d", n=128)
-    E = torch.as_tensor(ST.Oracle(p).efield(SI.initial_ht(p)), dtype=torch.float64, device="cuda")
+    s0 = Solver(p, L.F64)                  # field of the initial state, by the library's Poisson solve
+    s0.set_initial(SI.initial_ht(p))
+    E = s0.efield(s0.state, s0.E[0]).clone()
+    del s0
     g = L.make_grid(p)
     ws = L.Workspace(g, 64)
     S = 1 << 20
@@ -262,6 +345,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return batched_main(args)
+    if args.workload == "nested":
+        return nested_main(args)
     if args.workload == "samplers":
         return samplers_main(args)
     import torch
