@@ -534,6 +534,9 @@ __global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
     const int p = s_p;
     if (!(dp > stop) || p >= n) break;
     const double sq = sqrt(dp);
+    // the pivot row of G is read before the inner products, so its global
+    // load latency overlaps them
+    const double gpr = (sub == 0 && row < n) ? G[(size_t)p * n + row] : 0.0;
     if (row < n) {
       double v = 0.0;
       for (int j = sub; j < c; j += 4) v += L[j * SLAR_NMAX + row] * L[j * SLAR_NMAX + p];
@@ -548,7 +551,7 @@ __global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
         taken[row] = 1;
         dres[row] = 0.0;
       } else if (!taken[row]) {
-        out = (G[(size_t)p * n + row] - v) / sq;
+        out = (gpr - v) / sq;
         dres[row] = fmax(dres[row] - out * out, 0.0);
       }
       L[c * SLAR_NMAX + row] = out;
