@@ -97,7 +97,6 @@ const char* slar_status_str(slar_status s) {
 slar_status slar_workspace_destroy(slar_workspace* w) {
   if (!w) return SLAR_OK;
   Workspace& ws = w->w;
-  blas_release(&ws);
   void* dev[] = {ws.Eeff, ws.X32, ws.P32, ws.aca_ctl, ws.aca_part, ws.used, ws.resid, ws.dwork,
                  ws.small, ws.ismall, ws.tw[0], ws.tw[1], ws.cbuf, ws.psi, ws.lm, ws.kry,
                  ws.nest_U, ws.nest_V, ws.nest_used, ws.nest_rowtab, ws.nest_coltab, ws.nest_probes,
@@ -110,7 +109,11 @@ slar_status slar_workspace_destroy(slar_workspace* w) {
   if (ws.ev_join) (void)hipEventDestroy(ws.ev_join);
   for (hipEvent_t e : ws.poll_ev)
     if (e) (void)hipEventDestroy(e);
-  if (ws.aux) (void)hipStreamDestroy(ws.aux);
+  if (ws.aux) {
+    (void)hipStreamSynchronize(ws.aux);
+    blas_forget(ws.aux);
+    (void)hipStreamDestroy(ws.aux);
+  }
   if (ws.aca_ctl_host) (void)hipHostFree(ws.aca_ctl_host);
   if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
   delete w;

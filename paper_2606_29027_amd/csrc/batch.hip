@@ -430,7 +430,11 @@ slar_status slar_batch_destroy(slar_batch* b) {
   delete b->pool;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  for (hipStream_t s : b->streams) {
+    (void)hipStreamSynchronize(s);
+    blas_forget(s);
+    (void)hipStreamDestroy(s);
+  }
   for (hipEvent_t e : b->ev_done) (void)hipEventDestroy(e);
   for (hipEvent_t e : {b->ev_in, b->ev0, b->ev1})
     if (e) (void)hipEventDestroy(e);
@@ -462,6 +466,7 @@ slar_status slar_batch_create(int32_t count, const slar_grid* grids, int32_t rma
   for (int q = 0; q < count; ++q) {
     const slar_status st = slar_workspace_create(&grids[q], rmax, &b->ws[q]);
     if (st != SLAR_OK) return fail(st);
+    b->ws[q]->w.fork_aux = false;
     const GridDev& G = b->ws[q]->w.G;
     b->nbrow.push_back((G.nv + ACA_TILE - 1) / ACA_TILE);
     b->nbcol.push_back((G.nx + ACA_TILE - 1) / ACA_TILE);

@@ -3,6 +3,8 @@
 // Jacobi SVD and two-sided Jacobi symmetric eigensolver.  All single-block
 // factorizations keep their matrix in LDS (gfx950: 160 KB per CU).
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 
 #include <rocblas/rocblas.h>
 
@@ -15,12 +17,17 @@ namespace slar {
 // C_b = alpha op(A_b) op(B_b) + beta C_b, row-major, through rocBLAS (the
 // products of the path are plain GEMMs).  A row-major C = op(A) op(B) is the
 // column-major C^T = op(B)^T op(A)^T, i.e. rocBLAS with the operands
-// swapped.  The workspace keeps one handle per stream, so products enqueued
-// on its two streams never share a handle's scratch; atomics are disallowed,
-// so every product is reproducible bit for bit.
-static rocblas_handle blas_for(Workspace* ws, hipStream_t s) {
-  for (const auto& p : ws->blas)
-    if (p.first == s) return static_cast<rocblas_handle>(p.second);
+// swapped.  One handle per stream, shared by every workspace that runs
+// products on it (a stream is driven by one host thread at a time: the
+// caller's, or one pool thread's), created on first use; atomics are
+// disallowed, so every product is reproducible bit for bit.
+static std::mutex g_blas_mu;
+static std::unordered_map<hipStream_t, rocblas_handle> g_blas;
+
+static rocblas_handle blas_for(hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_blas_mu);
+  const auto it = g_blas.find(s);
+  if (it != g_blas.end()) return it->second;
   rocblas_handle h = nullptr;
   if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
   if (rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) != rocblas_status_success ||
@@ -28,20 +35,23 @@ static rocblas_handle blas_for(Workspace* ws, hipStream_t s) {
     rocblas_destroy_handle(h);
     return nullptr;
   }
-  ws->blas.emplace_back(s, static_cast<void*>(h));
+  g_blas.emplace(s, h);
   return h;
 }
 
-void blas_release(Workspace* ws) {
-  for (const auto& p : ws->blas) rocblas_destroy_handle(static_cast<rocblas_handle>(p.second));
-  ws->blas.clear();
+void blas_forget(hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_blas_mu);
+  const auto it = g_blas.find(s);
+  if (it == g_blas.end()) return;
+  rocblas_destroy_handle(it->second);
+  g_blas.erase(it);
 }
 
-hipError_t gemm_f64(Workspace* ws, hipStream_t s, bool ta, bool tb, int M, int N, int K,
-                    double alpha, const double* A, int lda, long long sA, const double* B, int ldb,
-                    long long sB, double beta, double* C, int ldc, long long sC, int batch) {
+hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+                    const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
+                    double beta, double* C, int ldc, long long sC, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  rocblas_handle h = blas_for(ws, s);
+  rocblas_handle h = blas_for(s);
   if (h == nullptr) return hipErrorUnknown;
   const rocblas_operation opB = tb ? rocblas_operation_transpose : rocblas_operation_none;
   const rocblas_operation opA = ta ? rocblas_operation_transpose : rocblas_operation_none;

@@ -463,14 +463,14 @@ hipError_t gemm_tn_long(hipStream_t s, Workspace* ws, int rows, int cols, int n,
   while ((size_t)((n + chunk - 1) / chunk) * rows * cols > ws->dwork_elems) chunk *= 2;
   const int full = n / chunk, tail = n - full * chunk;
   if (full > 0) {
-    hipError_t e = gemm_f64(ws, s, true, false, rows, cols, chunk, 1.0, A, lda, (long long)chunk * lda, B, ldb,
+    hipError_t e = gemm_f64(s, true, false, rows, cols, chunk, 1.0, A, lda, (long long)chunk * lda, B, ldb,
                             (long long)chunk * ldb, 0.0, ws->dwork, cols, (long long)rows * cols, full);
     if (e != hipSuccess) return e;
     k_sum_batches<<<(rows * cols + 255) / 256, 256, 0, s>>>(ws->dwork, rows, cols, full, C, ldc, 0.0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (tail > 0)
-    return gemm_f64(ws, s, true, false, rows, cols, tail, 1.0, A + (long long)full * chunk * lda, lda,
+    return gemm_f64(s, true, false, rows, cols, tail, 1.0, A + (long long)full * chunk * lda, lda,
                     0, B + (long long)full * chunk * ldb, ldb, 0, full > 0 ? 1.0 : 0.0, C, ldc, 0, 1);
   return hipSuccess;
 }
@@ -483,7 +483,7 @@ hipError_t moments_run(hipStream_t s, Workspace* ws, const slar_frames& F, doubl
   hipError_t e = gemm_tn_long(s, ws, F.r, nmom, G.nv, F.P, F.ld, ws->psi, nmom, m, nmom);
   if (e != hipSuccess) return e;
   // M^T = m^T X^T  -> [nmom][Nx]
-  return gemm_f64(ws, s, true, true, nmom, G.nx, F.r, 1.0, m, nmom, 0, F.X, F.ld, 0, 0.0, M, G.nx, 0, 1);
+  return gemm_f64(s, true, true, nmom, G.nx, F.r, 1.0, m, nmom, 0, F.X, F.ld, 0, 0.0, M, G.nx, 0, 1);
 }
 
 __global__ void k_conserved(int Nx, int dv, const double* M, const double* E, int dx, double* U) {

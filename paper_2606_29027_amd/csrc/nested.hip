@@ -356,7 +356,7 @@ static slar_status nested_impl(const NestCtx& c, double tol, int kmax, const std
       for (int i : R[a]) for (const Idx4& q : Q[a]) LR.push_back(leaf_entry(a, i, q));
       if (sample_list(c, LR, vals + (size_t)n[a] * rk[a]) != hipSuccess) return SLAR_E_HIP;
       if (inverse(s, ws, rk[a], vals + (size_t)n[a] * rk[a], sm) != hipSuccess) return SLAR_E_HIP;
-      if (gemm_f64(ws, s, false, false, n[a], rk[a], rk[a], 1.0, vals, rk[a], 0, sm, rk[a], 0, 0.0,
+      if (gemm_f64(s, false, false, n[a], rk[a], rk[a], 1.0, vals, rk[a], 0, sm, rk[a], 0, 0.0,
                    (double*)out->leaf[a], rk[a], 0, 1) != hipSuccess)
         return SLAR_E_HIP;
     }

@@ -314,7 +314,7 @@ hipError_t frames_from_ht(hipStream_t s, Workspace* ws, const GridDev& G, const 
     // X = Ux (n0 x rx); P = Uv root^T (n1 x rx)
     hipError_t e = copy2d(s, G.n[0], rx, (const double*)F.leaf[0], rx, out->X, ld, nullptr);
     if (e != hipSuccess) return e;
-    e = gemm_f64(ws, s, false, true, G.n[1], rx, rv, 1.0, (const double*)F.leaf[1], rv, 0,
+    e = gemm_f64(s, false, true, G.n[1], rx, rv, 1.0, (const double*)F.leaf[1], rv, 0,
                  (const double*)F.root, rv, 0, 0.0, out->P, ld, 0, 1);
     out->r = rx;
     return e;
@@ -325,21 +325,21 @@ hipError_t frames_from_ht(hipStream_t s, Workspace* ws, const GridDev& G, const 
   double* Z = ws->dwork;   // scratch: max(n1*r2*r12, n3*r4*r34) + n3*n4*r34
   double* V = ws->dwork + (size_t)SLAR_NMAX * SLAR_KMAX * SLAR_KMAX;
   // Z[i1][b*r12 + c] = sum_a U1[i1][a] B12[a][b*r12 + c]
-  hipError_t e = gemm_f64(ws, s, false, false, n1, r2 * r12, r1, 1.0, (const double*)F.leaf[0], r1, 0,
+  hipError_t e = gemm_f64(s, false, false, n1, r2 * r12, r1, 1.0, (const double*)F.leaf[0], r1, 0,
                           (const double*)F.B12, r2 * r12, 0, 0.0, Z, r2 * r12, 0, 1);
   if (e != hipSuccess) return e;
   // X[i1][i2][c] = sum_b U2[i2][b] Z[i1][b][c]   (batched over i1)
-  e = gemm_f64(ws, s, false, false, n2, r12, r2, 1.0, (const double*)F.leaf[1], r2, 0, Z, r12,
+  e = gemm_f64(s, false, false, n2, r12, r2, 1.0, (const double*)F.leaf[1], r2, 0, Z, r12,
                (long long)r2 * r12, 0.0, out->X, ld, (long long)n2 * ld, n1);
   if (e != hipSuccess) return e;
-  e = gemm_f64(ws, s, false, false, n3, r4 * r34, r3, 1.0, (const double*)F.leaf[2], r3, 0,
+  e = gemm_f64(s, false, false, n3, r4 * r34, r3, 1.0, (const double*)F.leaf[2], r3, 0,
                (const double*)F.B34, r4 * r34, 0, 0.0, Z, r4 * r34, 0, 1);
   if (e != hipSuccess) return e;
-  e = gemm_f64(ws, s, false, false, n4, r34, r4, 1.0, (const double*)F.leaf[3], r4, 0, Z, r34,
+  e = gemm_f64(s, false, false, n4, r34, r4, 1.0, (const double*)F.leaf[3], r4, 0, Z, r34,
                (long long)r4 * r34, 0.0, V, r34, (long long)n4 * r34, n3);
   if (e != hipSuccess) return e;
   // P = V root^T  (Nv x r12)
-  e = gemm_f64(ws, s, false, true, n3 * n4, r12, r34, 1.0, V, r34, 0, (const double*)F.root, r34, 0,
+  e = gemm_f64(s, false, true, n3 * n4, r12, r34, 1.0, V, r34, 0, (const double*)F.root, r34, 0,
                0.0, out->P, ld, 0, 1);
   out->r = r12;
   return e;

@@ -71,8 +71,12 @@ struct Workspace {
   double* kry = nullptr;
   size_t kry_elems = 0;
   // second stream (default priority) for independent chains inside a call,
-  // joined back before the call returns
+  // joined back before the call returns; fork_aux = false keeps every chain
+  // on the caller's stream (batched instances: the pool already overlaps
+  // instances, and one more stream per instance would only share the same
+  // hardware queues)
   hipStream_t aux = nullptr;
+  bool fork_aux = true;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional in-stream event timing of the cross-approximation sampling
   // kernels: [0] row ms, [1] row launches, [2] row bytes, [3] col ms,
@@ -86,9 +90,6 @@ struct Workspace {
   float* rec_targ = nullptr;
   int rec_cap = 0;
   int rec_count = 0;
-  // rocBLAS handles of the GEMMs, one per stream the workspace has run a
-  // product on (bound to that stream); released by blas_release
-  std::vector<std::pair<hipStream_t, void*>> blas;
   // nested HT cross (d = 4 only): search factors and tables, sample lists,
   // small matrices, frames for the norm, FP64 sampling tables
   double* nest_U = nullptr;        // [64][NEST_TAB]
@@ -111,17 +112,17 @@ struct Workspace {
 
 // launchers implemented across the .hip files
 // C_b = alpha op(A_b) op(B_b) + beta C_b (row-major, FP64) on stream s with
-// the rocBLAS handle ws keeps for s (created on first use: call it once
-// eagerly on a stream before capturing a graph on it)
-hipError_t gemm_f64(Workspace* ws, hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+// the rocBLAS handle of s (created on first use: call it once eagerly on a
+// stream before capturing a graph on it)
+hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
                     const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
                     double beta, double* C, int ldc, long long sC, int batch);
 size_t nest_list_elems();
 slar_status nested_run(hipStream_t s, Workspace* ws, const slar_frames& src, const slar_adv& adv,
                        slar_dtype dt, double tol, int kmax, int nprobe, const int* probes, const int* seed,
                        slar_ht* out, slar_nested_info* info);
-// destroys the handles gemm_f64 created for ws (the workspace's streams idle)
-void blas_release(Workspace* ws);
+// destroys the rocBLAS handle of stream s (before the library destroys s)
+void blas_forget(hipStream_t s);
 hipError_t combine_field(hipStream_t s, const GridDev& G, const slar_adv* a, double* out);
 
 }  // namespace slar

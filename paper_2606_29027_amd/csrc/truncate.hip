@@ -97,19 +97,19 @@ size_t truncate_scratch_elems(const GridDev& G) {
 
 // Orthonormal rows Q (k x n) and upper R (k x k) with A = R^T Q... i.e.
 // A^T = Q^T R, by two Cholesky-QR passes.
-static hipError_t cholqr2(hipStream_t s, Workspace* ws, const Chain& c, int k, int n, const double* A, double* Q1,
+static hipError_t cholqr2(hipStream_t s, const Chain& c, int k, int n, const double* A, double* Q1,
                           double* Q, double* Rout) {
   hipError_t e = gram_rows(s, c.part, k, n, A, n, c.G);
   if (e != hipSuccess) return e;
   e = chol_inv(s, k, c.G, c.Linv, c.R1, nullptr);
   if (e != hipSuccess) return e;
-  e = gemm_f64(ws, s, false, false, k, n, k, 1.0, c.Linv, k, 0, A, n, 0, 0.0, Q1, n, 0, 1);
+  e = gemm_f64(s, false, false, k, n, k, 1.0, c.Linv, k, 0, A, n, 0, 0.0, Q1, n, 0, 1);
   if (e != hipSuccess) return e;
   e = gram_rows(s, c.part, k, n, Q1, n, c.G);
   if (e != hipSuccess) return e;
   e = chol_inv(s, k, c.G, c.Linv, Rout, c.R1);
   if (e != hipSuccess) return e;
-  return gemm_f64(ws, s, false, false, k, n, k, 1.0, c.Linv, k, 0, Q1, n, 0, 0.0, Q, n, 0, 1);
+  return gemm_f64(s, false, false, k, n, k, 1.0, c.Linv, k, 0, Q1, n, 0, 0.0, Q, n, 0, 1);
 }
 
 // Gram matrices of the two mode matricisations of frame * diag(s) for one
@@ -123,29 +123,31 @@ static hipError_t side_grams(hipStream_t s, const Scratch& part, const double* f
 
 // aux waits for the work already on s / s waits for everything on aux
 static hipError_t fork(hipStream_t s, Workspace* ws) {
+  if (!ws->fork_aux) return hipSuccess;
   HIP_CHK(hipEventRecord(ws->ev_fork, s));
   return hipStreamWaitEvent(ws->aux, ws->ev_fork, 0);
 }
 static hipError_t join(hipStream_t s, Workspace* ws) {
+  if (!ws->fork_aux) return hipSuccess;
   HIP_CHK(hipEventRecord(ws->ev_join, ws->aux));
   return hipStreamWaitEvent(s, ws->ev_join, 0);
 }
 
 // Leaf bases (leading eigenvectors, sign rule) and the transfer tensor of
 // one side once the eigendecompositions are known.
-static slar_status side_finish(hipStream_t s, Workspace* ws, double* T, const double* frame,
-                               int na, int nb, int r, const double* Ea, const double* Eb, int ra,
-                               int rb, double* Ua, double* Ub, double* Bt) {
+static slar_status side_finish(hipStream_t s, double* T, const double* frame, int na, int nb, int r,
+                               const double* Ea, const double* Eb, int ra, int rb, double* Ua,
+                               double* Ub, double* Bt) {
   if (copy2d(s, na, ra, Ea, na, Ua, ra, nullptr) != hipSuccess) return SLAR_E_HIP;
   if (copy2d(s, nb, rb, Eb, nb, Ub, rb, nullptr) != hipSuccess) return SLAR_E_HIP;
   if (sign_fix(s, na, ra, Ua, ra, nullptr, 0, 0) != hipSuccess) return SLAR_E_HIP;
   if (sign_fix(s, nb, rb, Ub, rb, nullptr, 0, 0) != hipSuccess) return SLAR_E_HIP;
   // T[a][(i2, c)] = sum_i1 Ua[i1][a] frame[i1][(i2, c)]
-  if (gemm_f64(ws, s, true, false, ra, nb * r, na, 1.0, Ua, ra, 0, frame, nb * r, 0, 0.0, T, nb * r,
+  if (gemm_f64(s, true, false, ra, nb * r, na, 1.0, Ua, ra, 0, frame, nb * r, 0, 0.0, T, nb * r,
                0, 1) != hipSuccess)
     return SLAR_E_HIP;
   // Bt[a][b][c] = sum_i2 Ub[i2][b] T[a][i2][c]   (batched over a)
-  if (gemm_f64(ws, s, true, false, rb, r, nb, 1.0, Ub, rb, 0, T, r, (long long)nb * r, 0.0, Bt, r,
+  if (gemm_f64(s, true, false, rb, r, nb, 1.0, Ub, rb, 0, T, r, (long long)nb * r, 0.0, Bt, r,
                (long long)rb * r, ra) != hipSuccess)
     return SLAR_E_HIP;
   return SLAR_OK;
@@ -170,14 +172,15 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
   const GridDev& G = ws->G;
   Tbuf b = carve(ws);
   const int k = in.k;
+  const hipStream_t sa = ws->fork_aux ? ws->aux : s;   // the V-side chain
   double* Rv = b.R + SLAR_KMAX * SLAR_KMAX;
   // the U and V orthogonalisations are independent: U on s, V on aux
   if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
-  if (cholqr2(s, ws, b.cu, k, G.nx, in.U, b.Q1u, b.Qu, b.R) != hipSuccess) return SLAR_E_HIP;
-  if (cholqr2(ws->aux, ws, b.cv, k, G.nv, in.V, b.Q1v, b.Qv, Rv) != hipSuccess) return SLAR_E_HIP;
+  if (cholqr2(s, b.cu, k, G.nx, in.U, b.Q1u, b.Qu, b.R) != hipSuccess) return SLAR_E_HIP;
+  if (cholqr2(sa, b.cv, k, G.nv, in.V, b.Q1v, b.Qv, Rv) != hipSuccess) return SLAR_E_HIP;
   if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
   // core M = Ru Rv^T
-  if (gemm_f64(ws, s, false, true, k, k, k, 1.0, b.R, k, 0, Rv, k, 0, 0.0, b.M, k, 0, 1) != hipSuccess)
+  if (gemm_f64(s, false, true, k, k, k, 1.0, b.R, k, 0, Rv, k, 0, 0.0, b.M, k, 0, 1) != hipSuccess)
     return SLAR_E_HIP;
   if (svd_small(s, k, b.M, b.W, b.sv, b.Z) != hipSuccess) return SLAR_E_HIP;
   std::vector<double> sv(k);
@@ -201,9 +204,9 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
   }
   // frames X = Qu^T W_r (Nx x r), Y = Qv^T Z_r (Nv x r)
   if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
-  if (gemm_f64(ws, s, true, false, G.nx, r, k, 1.0, b.Qu, G.nx, 0, b.W, k, 0, 0.0, b.X, r, 0, 1) != hipSuccess)
+  if (gemm_f64(s, true, false, G.nx, r, k, 1.0, b.Qu, G.nx, 0, b.W, k, 0, 0.0, b.X, r, 0, 1) != hipSuccess)
     return SLAR_E_HIP;
-  if (gemm_f64(ws, ws->aux, true, false, G.nv, r, k, 1.0, b.Qv, G.nv, 0, b.Z, k, 0, 0.0, b.Y, r, 0, 1) != hipSuccess)
+  if (gemm_f64(sa, true, false, G.nv, r, k, 1.0, b.Qv, G.nv, 0, b.Z, k, 0, 0.0, b.Y, r, 0, 1) != hipSuccess)
     return SLAR_E_HIP;
   if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
   // the Cholesky-QR partials in dwork are dead once both chains have joined
@@ -219,7 +222,7 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
     // Gram matrices of the four modes, one batched eigen launch, one sync
     if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
     if (side_grams(s, b.cu.part, b.X, G.n[0], G.n[1], r, b.sv, b.Xs, b.G1, b.G2) != hipSuccess) return SLAR_E_HIP;
-    if (side_grams(ws->aux, b.cv.part, b.Y, G.n[2], G.n[3], r, b.sv, b.Ys, b.G3, b.G4) != hipSuccess)
+    if (side_grams(sa, b.cv.part, b.Y, G.n[2], G.n[3], r, b.sv, b.Ys, b.G3, b.G4) != hipSuccess)
       return SLAR_E_HIP;
     if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
     const int nn[4] = {G.n[0], G.n[1], G.n[2], G.n[3]};
@@ -239,10 +242,10 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
       rk[m] = leaf_rank(l, theta, rmax, &capped);
     }
     if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
-    slar_status st = side_finish(s, ws, b.T, b.X, G.n[0], G.n[1], r, b.E1, b.E2, rk[0], rk[1],
+    slar_status st = side_finish(s, b.T, b.X, G.n[0], G.n[1], r, b.E1, b.E2, rk[0], rk[1],
                                  (double*)out->leaf[0], (double*)out->leaf[1], (double*)out->B12);
     if (st != SLAR_OK) return st;
-    st = side_finish(ws->aux, ws, b.T2, b.Y, G.n[2], G.n[3], r, b.E3, b.E4, rk[2], rk[3],
+    st = side_finish(sa, b.T2, b.Y, G.n[2], G.n[3], r, b.E3, b.E4, rk[2], rk[3],
                      (double*)out->leaf[2], (double*)out->leaf[3], (double*)out->B34);
     if (st != SLAR_OK) return st;
     if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
