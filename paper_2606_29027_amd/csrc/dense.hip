@@ -176,6 +176,15 @@ hipError_t gram_mode2(hipStream_t s, const Scratch& part, int na, int nb, int r,
 }
 
 // --------------------------------------------------- Cholesky-QR helpers
+// Lane exchange inside a DPP row (CTRL: quad_perm / mirror patterns).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // From Gram G (k x k): column scaling d = sqrt(diag G), Cholesky of
 // D^-1 G D^-1 = L L^T.  Writes Linv_scaled = L^-1 D^-1 (k x k, lower) and
 // R = L^T D (upper).  A zero column keeps d = 1 and a unit pivot.
@@ -199,50 +208,73 @@ __global__ __launch_bounds__(256) void k_chol_inv(int k, const double* __restric
     L[i][j] = G[e] / (d[i] * d[j]);
   }
   __syncthreads();
-  // right-looking Cholesky (lower)
-  for (int c = 0; c < k; ++c) {
-    const double v = L[c][c];
-    const double dc = v > 1e-300 ? sqrt(v) : 1.0;
-    __syncthreads();
-    if (t == 0) L[c][c] = dc;
-    for (int i = c + 1 + t; i < k; i += blockDim.x) L[i][c] /= dc;
-    __syncthreads();
-    // trailing update of the lower triangle: eight threads per row
-    const int m = k - c - 1;
-    for (int w = t; w < m * 8; w += blockDim.x) {
-      const int i = c + 1 + (w >> 3);
-      const double lic = L[i][c];
-      for (int j = c + 1 + (w & 7); j <= i; j += 8) L[i][j] -= lic * L[j][c];
+  // left-looking (Crout) Cholesky, lower triangle in place: column c takes
+  //   t_i = S[i][c] - sum_{m<c} L[i][m] L[c][m]   (i >= c; a quad of lanes
+  //   per row, every fourth term, DPP quad sum)
+  // then L[c][c] = sqrt(t_c) (1 for a pivot <= 1e-300) and L[i][c] = t_i / L[c][c]
+  {
+    __shared__ double tcol[SLAR_KMAX];
+    const int sub = t & 3;
+    for (int c = 0; c < k; ++c) {
+      for (int i = c + (t >> 2); i < k; i += blockDim.x >> 2) {
+        double s = 0.0;
+        for (int m = sub; m < c; m += 4) s += L[i][m] * L[c][m];
+        s += dpp_move<0xB1>(s);
+        s += dpp_move<0x4E>(s);
+        if (sub == 0) tcol[i] = L[i][c] - s;
+      }
+      __syncthreads();
+      const double v = tcol[c];
+      const double dc = v > 1e-300 ? sqrt(v) : 1.0;
+      for (int i = c + t; i < k; i += blockDim.x) L[i][c] = (i == c) ? dc : tcol[i] / dc;
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // inverse of lower triangular L by forward elimination on [L | I]: after
-  // step c row c of Li is row c of L^-1 (columns j <= c; the rest stay 0)
-  for (int i = t >> 3; i < k; i += blockDim.x >> 3)
-    for (int j = t & 7; j < k; j += 8) Li[i][j] = (i == j) ? 1.0 : 0.0;
+  // inverse of lower triangular L, column by column (forward substitution):
+  //   X[j][j] = 1 / L[j][j],  X[i][j] = -(sum_{j<=m<i} L[i][m] X[m][j]) / L[i][i]
+  // A quad of lanes owns column j (every fourth term of each sum, then a
+  // DPP quad sum); the recurrence stays inside the quad's wave, whose LDS
+  // accesses complete in order, so no block barrier is needed.
+  {
+    const int sub = t & 3;
+    for (int j = t >> 2; j < k; j += blockDim.x >> 2) {
+      for (int i = sub; i < j; i += 4) Li[i][j] = 0.0;
+      if (sub == 0) Li[j][j] = 1.0 / L[j][j];
+      for (int i = j + 1; i < k; ++i) {
+        double s = 0.0;
+        for (int m = j + sub; m < i; m += 4) s += L[i][m] * Li[m][j];
+        s += dpp_move<0xB1>(s);
+        s += dpp_move<0x4E>(s);
+        if (sub == 0) Li[i][j] = -s / L[i][i];
+      }
+    }
+  }
   __syncthreads();
-  for (int c = 0; c < k; ++c) {
-    const double inv = 1.0 / L[c][c];
-    for (int j = t; j <= c; j += blockDim.x) Li[c][j] *= inv;
-    __syncthreads();
-    const int m = k - c - 1;
-    for (int w = t; w < m * 8; w += blockDim.x) {     // eight threads per row
-      const int i = c + 1 + (w >> 3);
-      const double lic = L[i][c];
-      for (int j = w & 7; j <= c; j += 8) Li[i][j] -= lic * Li[c][j];
-    }
-    __syncthreads();
-  }
   for (int e = t; e < k * k; e += blockDim.x) {
     const int i = e / k, j = e % k;
     Linv[e] = Li[i][j] / d[j];
-    // R = L^T D (upper), optionally times Rprev (R_total = R * Rprev)
-    if (Rprev == nullptr) {
-      R[e] = (i <= j) ? L[j][i] * d[j] : 0.0;
-    } else {
-      double acc = 0.0;
-      for (int m = i; m < k; ++m) acc += L[m][i] * d[m] * Rp[m][j];
-      R[e] = acc;
+    // R = L^T D (upper)
+    if (Rprev == nullptr) R[e] = (i <= j) ? L[j][i] * d[j] : 0.0;
+  }
+  if (Rprev != nullptr) {
+    // R_total = (L^T D) Rprev: four adjacent outputs of one row per thread
+    // share the loads of (L^T D)[i][m] and keep four independent sums
+    const int q4 = (k + 3) / 4;
+    for (int w = t; w < k * q4; w += blockDim.x) {
+      const int i = w / q4, j0 = 4 * (w % q4);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int m = i; m < k; ++m) {
+        const double l = L[m][i] * d[m];
+        a0 += l * Rp[m][j0];
+        a1 += l * Rp[m][min(j0 + 1, k - 1)];
+        a2 += l * Rp[m][min(j0 + 2, k - 1)];
+        a3 += l * Rp[m][min(j0 + 3, k - 1)];
+      }
+      double* r = R + (size_t)i * k + j0;
+      r[0] = a0;
+      if (j0 + 1 < k) r[1] = a1;
+      if (j0 + 2 < k) r[2] = a2;
+      if (j0 + 3 < k) r[3] = a3;
     }
   }
 }
@@ -265,13 +297,6 @@ __device__ __forceinline__ int rr_player(int pos, int step, int kp) {
 // Sum over the 16 lanes of a DPP row (every lane gets the total): quad
 // exchanges, then the half-row and row mirrors.  Pure VALU data movement,
 // so concurrent teams do not queue on the LDS crossbar.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
   v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
