@@ -346,6 +346,18 @@ slar_status slar_cnn_grad(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, const 
 /* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the same loss             */
 slar_status slar_cnn_train_step(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, const float* x,
                                 const float* y, float lr, float* loss_host, hipStream_t stream);
+/* The learned correction alone, as slar_macro_solve (precond = 2) applies
+ * it to the spectral preconditioner's output:
+ *   z += rms(v) * CNN([v / rms(v), (U_c - mean U_c) / std U_c]),
+ * with rms over all K = dv + 2 components and pixels, the mean and standard
+ * deviation per component (std + 1e-12 |mean| + 1e-300, so a constant
+ * component maps to zero).  v, U, z device [K][Nx] FP64 on the x grid of g
+ * (Nx = n[0] n[1], x1 fastest); z is read and written, distinct from v and
+ * U.  Needs dx = 2 and channels 2K -> ... -> K (SLAR_E_INVAL otherwise); a
+ * 2K -> 16 -> 16 -> K network of any grid runs fused in one launch after a
+ * statistics pass.  Enqueued on stream.                                     */
+slar_status slar_cnn_correct(const slar_grid* g, const slar_cnn* cnn, const double* v,
+                             const double* U, double* z, slar_workspace* ws, hipStream_t stream);
 /* Records up to `capacity` training pairs from later flexible-GMRES solves
  * of this workspace: features [capacity][2K][Nx] (network input for w = J z)
  * and targets [capacity][K][Nx] ((z - P_spec(w)) / rms(w)), FP32 device

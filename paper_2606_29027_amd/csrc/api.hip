@@ -388,6 +388,14 @@ slar_status slar_macro_rhs(const slar_grid* g, const double* U, double* R_out, s
   return macro_rhs(stream, &w->w, U, R_out) == hipSuccess ? SLAR_OK : SLAR_E_HIP;
 }
 
+slar_status slar_cnn_correct(const slar_grid* g, const slar_cnn* cnn, const double* v, const double* U,
+                             double* z, slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !cnn || !v || !U || !z) return SLAR_E_INVAL;
+  if (z == v || z == U) return SLAR_E_INVAL;
+  const hipError_t e = cnn_apply(stream, &w->w, cnn, v, U, z);
+  return e == hipSuccess ? SLAR_OK : (e == hipErrorInvalidValue ? SLAR_E_INVAL : SLAR_E_HIP);
+}
+
 slar_status slar_dirk3_tableau(double* A, double* c) {
   if (!A || !c) return SLAR_E_INVAL;
   // gamma: the root in (1/6, 1/2) of p(x) = 6x^3 - 18x^2 + 9x - 1, by bisection

@@ -288,7 +288,7 @@ static hipError_t cnn_backward(hipStream_t s, slar_cnn* c, int B, int H, int W, 
 // stats[ST_SS + c] = sum v_c^2, stats[ST_MEAN + c] = mean U_c,
 // stats[ST_STD + c] = std U_c (three disjoint ranges of ST_STRIDE entries).
 constexpr int ST_STRIDE = 16, ST_SS = 0, ST_MEAN = ST_STRIDE, ST_STD = 2 * ST_STRIDE;
-constexpr int ST_ELEMS = 3 * ST_STRIDE;
+constexpr int ST_ELEMS = 3 * CNN_CMAX * 16;   // room for the fused path's partial sums too
 static_assert(ST_STRIDE >= CNN_CMAX / 2, "K = input channels / 2 fits one range");
 
 __global__ __launch_bounds__(1024) void k_cnn_stats(int Nx, int K, const double* __restrict__ v,
@@ -341,16 +341,149 @@ __global__ void k_cnn_add(int n, int Nx, int K, const float* __restrict__ out,
   z[e] += cnn_rms(stats, Nx, K) * (double)out[e];
 }
 
+// Partial sums for the statistics, NP chunks per channel: part[(q K + c) NP + b]
+// for q = 0 (sum v^2), 1 (sum U), 2 (sum U^2).
+constexpr int ST_NP = 16;
+static_assert(3 * (CNN_CMAX / 2) * ST_NP <= ST_ELEMS, "partial sums fit the statistics buffer");
+
+__global__ __launch_bounds__(256) void k_cnn_stats_part(int Nx, int K, const double* __restrict__ v,
+                                                        const double* __restrict__ U,
+                                                        double* __restrict__ part) {
+  __shared__ double r0[256], r1[256], r2[256];
+  const int c = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+  const int len = (Nx + ST_NP - 1) / ST_NP, e0 = b * len, e1 = min(Nx, e0 + len);
+  double a = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int e = e0 + t; e < e1; e += 256) {
+    const double x = v[(size_t)c * Nx + e], u = U[(size_t)c * Nx + e];
+    a += x * x; s1 += u; s2 += u * u;
+  }
+  r0[t] = a; r1[t] = s1; r2[t] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) { r0[t] += r0[t + o]; r1[t] += r1[t + o]; r2[t] += r2[t + o]; }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[(size_t)(0 * K + c) * ST_NP + b] = r0[0];
+    part[(size_t)(1 * K + c) * ST_NP + b] = r1[0];
+    part[(size_t)(2 * K + c) * ST_NP + b] = r2[0];
+  }
+}
+
+// One 3x3 periodic layer on an LDS tile: in [CI][IW][IW] -> out [CO][OW][OW]
+// with OW = IW - 2 (the valid part).  Work items are (64-pixel block, group
+// of OG outputs) with the group uniform over a wave, so the weights are
+// wave-uniform loads; per output the sum runs bias, c, dy, dx as in
+// k_conv_fwd_t.
+template <int CI, int CO, int OG, int IW, bool ACT>
+__device__ inline void tile_layer(const float* __restrict__ in, float* __restrict__ out,
+                                  const float* __restrict__ prm) {
+  constexpr int OW = IW - 2, P = OW * OW, NPB = (P + 63) / 64, NJ = NPB * (CO / OG);
+  const int lane = threadIdx.x & 63;
+  for (int j = threadIdx.x >> 6; j < NJ; j += blockDim.x >> 6) {
+    const int wj = __builtin_amdgcn_readfirstlane(j);
+    const int pb = wj % NPB, o0 = (wj / NPB) * OG;
+    const int p = pb * 64 + lane;
+    if (p >= P) continue;
+    const int py = p / OW, px = p - py * OW;
+    float acc[OG];
+#pragma unroll
+    for (int o = 0; o < OG; ++o) acc[o] = prm[CO * CI * 9 + o0 + o];
+#pragma unroll 4
+    for (int c = 0; c < CI; ++c) {
+      const float* ic = in + (c * IW + py) * IW + px;
+      const float v[9] = {ic[0], ic[1], ic[2], ic[IW], ic[IW + 1], ic[IW + 2],
+                          ic[2 * IW], ic[2 * IW + 1], ic[2 * IW + 2]};
+#pragma unroll
+      for (int o = 0; o < OG; ++o) {
+        const float* wo = prm + ((o0 + o) * CI + c) * 9;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[o] += wo[t] * v[t];
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < OG; ++o) out[((o0 + o) * OW + py) * OW + px] = ACT ? tanhf(acc[o]) : acc[o];
+  }
+}
+
+// The whole correction for a three-layer network C0 -> C1 -> C2 -> C3
+// (C0 = 2K, C3 = K): one block per TS x TS output tile of the H x W grid.
+// The statistics are finished from the partial sums, the normalised input
+// is built on the tile plus a three-pixel periodic halo, the layers run in
+// LDS, and z[c][pixel] += rms(v) * out[c] is added in place.
+constexpr int CNN_TS = 8;
+
+template <int C0, int C1, int C2, int C3>
+__global__ __launch_bounds__(256) void k_cnn_fused(int H, int W, const double* __restrict__ v,
+                                                   const double* __restrict__ U,
+                                                   const double* __restrict__ part,
+                                                   const float* __restrict__ theta, int off1, int off2,
+                                                   double* __restrict__ z) {
+  constexpr int K = C3, I0 = CNN_TS + 6, I1 = CNN_TS + 4, I2 = CNN_TS + 2;
+  static_assert(C0 == 2 * C3, "input channels 2K, output channels K");
+  __shared__ float a0[C0 * I0 * I0];
+  __shared__ float a1[C1 * I1 * I1];
+  __shared__ float a2[C2 * I2 * I2];
+  __shared__ float a3[C3 * CNN_TS * CNN_TS];
+  __shared__ double sums[3 * K];
+  __shared__ double s_rms;
+  const int t = threadIdx.x, Nx = H * W;
+  const int tx0 = blockIdx.x * CNN_TS, ty0 = blockIdx.y * CNN_TS;
+  if (t < 3 * K) {
+    double a = 0.0;
+    for (int b = 0; b < ST_NP; ++b) a += part[(size_t)t * ST_NP + b];
+    sums[t] = a;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double ss = 0.0;
+    for (int q = 0; q < K; ++q) ss += sums[q];
+    s_rms = sqrt(ss / (double)(Nx * K));
+  }
+  __syncthreads();
+  const double rms = s_rms, inv = rms > 0.0 ? 1.0 / rms : 0.0;
+  for (int e = t; e < K * I0 * I0; e += blockDim.x) {
+    const int c = e / (I0 * I0), q = e - c * (I0 * I0), iy = q / I0, ix = q - iy * I0;
+    int gy = (ty0 + iy - 3) % H, gx = (tx0 + ix - 3) % W;
+    gy += gy < 0 ? H : 0;
+    gx += gx < 0 ? W : 0;
+    const size_t g = (size_t)c * Nx + (size_t)gy * W + gx;
+    const double mean = sums[K + c] / Nx;
+    const double var = fmax(sums[2 * K + c] / Nx - mean * mean, 0.0);
+    const double sd = sqrt(var) + 1e-12 * fabs(mean) + 1e-300;
+    a0[e] = (float)(v[g] * inv);
+    a0[K * I0 * I0 + e] = (float)((U[g] - mean) / sd);
+  }
+  __syncthreads();
+  tile_layer<C0, C1, 4, I0, true>(a0, a1, theta);
+  __syncthreads();
+  tile_layer<C1, C2, 4, I1, true>(a1, a2, theta + off1);
+  __syncthreads();
+  tile_layer<C2, C3, 1, I2, false>(a2, a3, theta + off2);
+  __syncthreads();
+  for (int e = t; e < K * CNN_TS * CNN_TS; e += blockDim.x) {
+    const int c = e / (CNN_TS * CNN_TS), q = e - c * (CNN_TS * CNN_TS);
+    const int y = ty0 + q / CNN_TS, x = tx0 + q % CNN_TS;
+    if (y < H && x < W) z[(size_t)c * Nx + (size_t)y * W + x] += rms * (double)a3[e];
+  }
+}
+
 hipError_t cnn_apply(hipStream_t s, Workspace* ws, const slar_cnn* net, const double* v,
                      const double* U, double* z) {
   slar_cnn* c = const_cast<slar_cnn*>(net);
   const GridDev& G = ws->G;
   if (G.dx != 2 || c->ch[0] != 2 * (G.dv + 2) || c->ch[c->nl] != G.dv + 2) return hipErrorInvalidValue;
-  const int K = G.dv + 2, Nx = G.nx;
+  const int K = G.dv + 2, Nx = G.nx, H = G.n[0], W = G.n[1];
+  if (c->nl == 3 && K == 4 && c->ch[1] == 16 && c->ch[2] == 16) {
+    k_cnn_stats_part<<<dim3(ST_NP, K), 256, 0, s>>>(Nx, K, v, U, c->stats);
+    const dim3 grid((W + CNN_TS - 1) / CNN_TS, (H + CNN_TS - 1) / CNN_TS);
+    k_cnn_fused<8, 16, 16, 4><<<grid, 256, 0, s>>>(H, W, v, U, c->stats, c->theta, c->off[1], c->off[2], z);
+    return hipGetLastError();
+  }
   if (Nx > c->maxHW) return hipErrorInvalidValue;
   k_cnn_stats<<<K, 1024, 0, s>>>(Nx, K, v, U, c->stats);
   k_cnn_features<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx, K, v, U, c->stats, c->act[0]);
-  HIP_CHK(cnn_forward(s, c, 1, G.n[0], G.n[1], c->act[0]));
+  HIP_CHK(cnn_forward(s, c, 1, H, W, c->act[0]));
   k_cnn_add<<<(Nx * K + 255) / 256, 256, 0, s>>>(Nx * K, Nx, K, c->act[c->nl], c->stats, z);
   return hipGetLastError();
 }

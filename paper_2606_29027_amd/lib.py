@@ -29,6 +29,7 @@ EXPORTS = (
     "slar_batch_cross_update", "slar_batch_truncate", "slar_batch_efield", "slar_batch_get_config",
     "slar_batch_set_config", "slar_batch_tune", "slar_batch_timing", "slar_batch_timing_reset",
     "slar_macro_solve_system", "slar_macro_rhs", "slar_dirk3_tableau", "slar_bdf_weights",
+    "slar_cnn_correct",
 )
 
 
@@ -135,6 +136,7 @@ def load(path: str = LIB_PATH):
         "slar_batch_timing_reset": (i32, [vp]),
         "slar_macro_solve_system": (i32, [P(Grid), P(MacroSystem), dbl, dbl, i32, vp, vp, P(i32), vp, vp]),
         "slar_macro_rhs": (i32, [P(Grid), vp, vp, vp, vp]),
+        "slar_cnn_correct": (i32, [P(Grid), vp, vp, vp, vp, vp, vp]),
         "slar_dirk3_tableau": (i32, [P(dbl), P(dbl)]),
         "slar_bdf_weights": (i32, [i32, P(dbl), P(dbl), P(dbl)]),
     }
@@ -347,6 +349,13 @@ def slar_lomac_project(grid, Fs, U_new, out: Frames, ws):
 
 
 # ------------------------------------------------------- learned preconditioner
+def slar_cnn_correct(grid, cnn, v, U, z, ws):
+    """z += rms(v) CNN(features(v, U)) in place (device [K][Nx] FP64)."""
+    _check(load().slar_cnn_correct(C.byref(grid), cnn.handle, _ptr(v), _ptr(U), _ptr(z), ws.h, _stream()),
+           "slar_cnn_correct")
+    return z
+
+
 class Cnn:
     """Handle of a device CNN (see slar.h); parameters as a host float32 array."""
 

@@ -114,3 +114,78 @@ def test_learned_solve_is_bitwise_reproducible():
     (U0, X0, P0, it0), (U1, X1, P1, it1) = runs
     assert it0 == it1
     assert np.array_equal(U0, U1) and np.array_equal(X0, X1) and np.array_equal(P0, P1)
+
+
+def _correction_case(n0, n1, chs, theta, seed, const_channel=None):
+    p = SI.config("stronglandau2d", n=8).with_(n=(n0, n1, 8, 8))
+    K = p.dv + 2
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 8)
+    net = L.Cnn(chs, 1, n0 * n1)
+    net.set_params(theta.astype(np.float32))
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((K, n0, n1))
+    U = np.array([1.0, 0.0, 0.0, 1.5])[:, None, None] + 0.1 * rng.standard_normal((K, n0, n1))
+    if const_channel is not None:
+        U[const_channel] = 1.0
+    z0 = rng.standard_normal((K, n0, n1))
+    z = torch.as_tensor(z0.copy(), device="cuda")
+    L.slar_cnn_correct(g, net, torch.as_tensor(v, device="cuda"), torch.as_tensor(U, device="cuda"), z, ws)
+    torch.cuda.synchronize()
+    shapes = list(zip(chs[:-1], chs[1:]))
+    th = net.get_params().astype(np.float64)
+    ref = CN.apply(th, shapes, v, U, z0)
+    return z.cpu().numpy() - z0, ref - z0
+
+
+@pytest.mark.parametrize("n0,n1,chs,const", [
+    (16, 16, [8, 16, 16, 4], None),     # fused, whole tiles
+    (20, 12, [8, 16, 16, 4], 2),        # fused, ragged tiles, a constant U channel
+    (5, 4, [8, 16, 16, 4], None),       # fused, grid smaller than the halo
+    (20, 12, [8, 8, 4], None),          # generic layer-by-layer path
+])
+def test_cnn_correction_matches_oracle(n0, n1, chs, const):
+    """slar_cnn_correct against oracle.cnn.apply: the added correction
+    rms(v) CNN(features(v, U)) within the FP32 network's rounding (1e-5)."""
+    rng = np.random.default_rng(11)
+    shapes = list(zip(chs[:-1], chs[1:]))
+    theta = 0.3 * rng.standard_normal(CN.nparams(shapes))
+    got, ref = _correction_case(n0, n1, chs, theta, 12, const)
+    assert normwise(got, ref) < 1e-5
+
+
+def test_cnn_correction_trained_network_full_grid():
+    """The committed trained network on the 128 x 128 x grid of the 2D2V
+    workloads (the launch the macro solve makes)."""
+    theta = np.load(CNN.WEIGHTS)["params"].astype(np.float64)
+    got, ref = _correction_case(128, 128, CNN.channels(2), theta, 13)
+    assert normwise(got, ref) < 1e-5
+
+
+def test_cnn_correction_of_zero_residual_is_zero():
+    """rms(v) = 0: the correction vanishes and z is left as it was."""
+    p = SI.config("stronglandau2d", n=8).with_(n=(16, 16, 8, 8))
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 8)
+    net = L.Cnn(CNN.channels(2), 1, 64)
+    net.set_params(np.full(net.nparams, 0.1, dtype=np.float32))
+    z0 = np.random.default_rng(1).standard_normal((4, 16, 16))
+    z = torch.as_tensor(z0.copy(), device="cuda")
+    U = torch.ones((4, 16, 16), dtype=torch.float64, device="cuda")
+    L.slar_cnn_correct(g, net, torch.zeros_like(U), U, z, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(z.cpu().numpy(), z0)
+
+
+def test_cnn_correction_rejects_bad_arguments():
+    p = SI.config("stronglandau2d", n=8).with_(n=(16, 16, 8, 8))
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 8)
+    net = L.Cnn([6, 8, 3], 1, 64)     # channels not 2K -> K for K = 4
+    a = torch.zeros((4, 16, 16), dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(a)
+    with pytest.raises(L.SlarError):
+        L.slar_cnn_correct(g, net, a, b, torch.zeros_like(a), ws)
+    good = L.Cnn(CNN.channels(2), 1, 64)
+    with pytest.raises(L.SlarError):
+        L.slar_cnn_correct(g, good, a, b, a, ws)
