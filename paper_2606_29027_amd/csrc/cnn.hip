@@ -39,6 +39,7 @@ struct slar_cnn {
   float* lossp = nullptr;
   double* stats = nullptr;
   float* host_loss = nullptr;
+  float* bpack = nullptr;   // matrix-core operands of the fused inference (fusable shapes only)
 };
 
 namespace slar {
@@ -353,6 +354,7 @@ __global__ __launch_bounds__(256) void k_cnn_stats_part(int Nx, int K, const dou
   const int c = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
   const int len = (Nx + ST_NP - 1) / ST_NP, e0 = b * len, e1 = min(Nx, e0 + len);
   double a = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
   for (int e = e0 + t; e < e1; e += 256) {
     const double x = v[(size_t)c * Nx + e], u = U[(size_t)c * Nx + e];
     a += x * x; s1 += u; s2 += u * u;
@@ -370,102 +372,198 @@ __global__ __launch_bounds__(256) void k_cnn_stats_part(int Nx, int K, const dou
   }
 }
 
-// One 3x3 periodic layer on an LDS tile: in [CI][IW][IW] -> out [CO][OW][OW]
-// with OW = IW - 2 (the valid part).  Work items are (64-pixel block, group
-// of OG outputs) with the group uniform over a wave, so the weights are
-// wave-uniform loads; per output the sum runs bias, c, dy, dx as in
-// k_conv_fwd_t.
-template <int CI, int CO, int OG, int IW, bool ACT>
-__device__ inline void tile_layer(const float* __restrict__ in, float* __restrict__ out,
-                                  const float* __restrict__ prm) {
-  constexpr int OW = IW - 2, P = OW * OW, NPB = (P + 63) / 64, NJ = NPB * (CO / OG);
-  const int lane = threadIdx.x & 63;
-  for (int j = threadIdx.x >> 6; j < NJ; j += blockDim.x >> 6) {
-    const int wj = __builtin_amdgcn_readfirstlane(j);
-    const int pb = wj % NPB, o0 = (wj / NPB) * OG;
-    const int p = pb * 64 + lane;
-    if (p >= P) continue;
-    const int py = p / OW, px = p - py * OW;
-    float acc[OG];
+// ---- fused inference: the convolutions as FP32 matrix-core products.
+// A layer on an LDS tile is out[p][o] = b[o] + sum_k X[p][k] W[k][o] with
+// k = t CI + c over the taps t = 3 dy + dx and input channels c, X[p][k] =
+// in[c][py + dy][px + dx].  One v_mfma_f32_16x16x4f32 step takes 16 pixels
+// x 4 values of k: lane l supplies X[16 m + (l & 15)][4 s + (l >> 4)] and
+// W[4 s + (l >> 4)][l & 15] and ends with out[16 m + 4 (l >> 4) + i][l & 15],
+// i < 4.  With CI a multiple of 4 the tap is the same for the four k of a
+// step, so the A operand is an LDS read at a fixed offset from a per-lane
+// base.  LDS planes have a channel stride of 16 mod 32 floats, which puts
+// the four k rows of a step in disjoint banks.
+typedef float cnn_v4f __attribute__((ext_vector_type(4)));
+
+constexpr int cnn_plane(int w) { return ((w * w + 15) / 32) * 32 + 16; }
+
+// B operands of one layer in matrix-core order: row s < CI 9 / 4 holds, at
+// lane l, W[k = 4 s + (l >> 4)][o = l & 15] (zero for o >= CO); row
+// CI 9 / 4 holds the bias of o = l & 15.  (CI 9 / 4 + 1) x 64 floats.
+template <int CI, int CO>
+__device__ inline float cnn_b_entry(const float* __restrict__ prm, int s, int l) {
+  const int q = l >> 4, o = l & 15;
+  if (o >= CO) return 0.f;
+  if (s == CI * 9 / 4) return prm[CO * CI * 9 + o];
+  const int t = (4 * s) / CI, c = (4 * s) % CI + q;
+  return prm[(o * CI + c) * 9 + t];
+}
+
+template <int C0, int C1, int C2, int C3>
+struct CnnPack {
+  static constexpr int R1 = C0 * 9 / 4 + 1, R2 = C1 * 9 / 4 + 1, R3 = C2 * 9 / 4 + 1;
+  static constexpr int ELEMS = (R1 + R2 + R3) * 64;
+};
+
+template <int C0, int C1, int C2, int C3>
+__global__ void k_cnn_pack(const float* __restrict__ theta, int off1, int off2, float* __restrict__ bp) {
+  using PK = CnnPack<C0, C1, C2, C3>;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= PK::ELEMS) return;
+  const int row = e >> 6, l = e & 63;
+  float x;
+  if (row < PK::R1) x = cnn_b_entry<C0, C1>(theta, row, l);
+  else if (row < PK::R1 + PK::R2) x = cnn_b_entry<C1, C2>(theta + off1, row - PK::R1, l);
+  else x = cnn_b_entry<C2, C3>(theta + off2, row - PK::R1 - PK::R2, l);
+  bp[e] = x;
+}
+
+// this lane's B operands and bias of one layer from its packed rows
+template <int CI>
+__device__ inline void cnn_load_b(const float* __restrict__ rows, float* wb, float& bias) {
+  const int l = threadIdx.x & 63;
 #pragma unroll
-    for (int o = 0; o < OG; ++o) acc[o] = prm[CO * CI * 9 + o0 + o];
-#pragma unroll 4
-    for (int c = 0; c < CI; ++c) {
-      const float* ic = in + (c * IW + py) * IW + px;
-      const float v[9] = {ic[0], ic[1], ic[2], ic[IW], ic[IW + 1], ic[IW + 2],
-                          ic[2 * IW], ic[2 * IW + 1], ic[2 * IW + 2]};
+  for (int s = 0; s < CI * 9 / 4; ++s) wb[s] = rows[s * 64 + l];
+  bias = rows[(CI * 9 / 4) * 64 + l];
+}
+
+// in: [CI] planes of IW x IW (stride cnn_plane(IW)); out: [CO] planes of
+// OW x OW, OW = IW - 2, with channel stride OS
+template <int CI, int CO, int IW, int OS, bool ACT>
+__device__ inline void cnn_layer_mfma(const float* __restrict__ in, float* __restrict__ out,
+                                     const float* wb, float bias) {
+  static_assert(CI % 4 == 0 && CO <= 16, "four k per step, one column tile");
+  constexpr int OW = IW - 2, P = OW * OW, MT = (P + 15) / 16, KS = CI * 9 / 4, IS = cnn_plane(IW);
+  const int l = threadIdx.x & 63, q = l >> 4, r = l & 15;
+  for (int m = threadIdx.x >> 6; m < MT; m += blockDim.x >> 6) {
+    const int pa = min(16 * m + r, P - 1);   // rows past P read a valid pixel and are dropped
+    const int py = pa / OW, px = pa - py * OW;
+    const float* base = in + q * IS + py * IW + px;
+    cnn_v4f acc = {bias, bias, bias, bias};
 #pragma unroll
-      for (int o = 0; o < OG; ++o) {
-        const float* wo = prm + ((o0 + o) * CI + c) * 9;
+    for (int s = 0; s < KS; ++s) {
+      const int t = (4 * s) / CI, c0 = (4 * s) % CI;
+      const float a = base[c0 * IS + (t / 3) * IW + t % 3];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wb[s], acc, 0, 0, 0);
+    }
+    if (r < CO) {
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc[o] += wo[t] * v[t];
+      for (int i = 0; i < 4; ++i) {
+        const int p = 16 * m + 4 * q + i;
+        if (p < P) out[r * OS + p] = ACT ? tanhf(acc[i]) : acc[i];
       }
     }
-#pragma unroll
-    for (int o = 0; o < OG; ++o) out[((o0 + o) * OW + py) * OW + px] = ACT ? tanhf(acc[o]) : acc[o];
   }
 }
 
 // The whole correction for a three-layer network C0 -> C1 -> C2 -> C3
 // (C0 = 2K, C3 = K): one block per TS x TS output tile of the H x W grid.
-// The statistics are finished from the partial sums, the normalised input
-// is built on the tile plus a three-pixel periodic halo, the layers run in
-// LDS, and z[c][pixel] += rms(v) * out[c] is added in place.
-constexpr int CNN_TS = 8;
+// Every global load (partial sums, v and U on the tile plus a three-pixel
+// periodic halo, the z entries of the tile, this lane's packed weights) is issued
+// up front; the statistics are then finished, the normalised input is
+// written to LDS, the layers run in LDS and z[c][pixel] += rms(v) out[c] is
+// stored.
+constexpr int CNN_TS = 8, CNN_NT = 512;
 
 template <int C0, int C1, int C2, int C3>
-__global__ __launch_bounds__(256) void k_cnn_fused(int H, int W, const double* __restrict__ v,
-                                                   const double* __restrict__ U,
-                                                   const double* __restrict__ part,
-                                                   const float* __restrict__ theta, int off1, int off2,
-                                                   double* __restrict__ z) {
+__global__ __launch_bounds__(CNN_NT) void k_cnn_fused(int H, int W, const double* __restrict__ v,
+                                                      const double* __restrict__ U,
+                                                      const double* __restrict__ part,
+                                                      const float* __restrict__ bp,
+                                                      double* __restrict__ z) {
+  using PK = CnnPack<C0, C1, C2, C3>;
   constexpr int K = C3, I0 = CNN_TS + 6, I1 = CNN_TS + 4, I2 = CNN_TS + 2;
+  constexpr int S0 = cnn_plane(I0), S1 = cnn_plane(I1), S2 = cnn_plane(I2), S3 = CNN_TS * CNN_TS;
+  constexpr int NE = K * I0 * I0, NR = (NE + CNN_NT - 1) / CNN_NT, NZ = K * S3;
   static_assert(C0 == 2 * C3, "input channels 2K, output channels K");
-  __shared__ float a0[C0 * I0 * I0];
-  __shared__ float a1[C1 * I1 * I1];
-  __shared__ float a2[C2 * I2 * I2];
-  __shared__ float a3[C3 * CNN_TS * CNN_TS];
-  __shared__ double sums[3 * K];
+  static_assert(NZ <= CNN_NT && 3 * K <= CNN_NT, "one output entry per thread");
+  __shared__ float a0[C0 * S0];
+  __shared__ float a1[C1 * S1];
+  __shared__ float a2[C2 * S2];
+  __shared__ float a3[C3 * S3];
+  __shared__ double sums[3 * K], s_mean[K], s_sd[K];
   __shared__ double s_rms;
   const int t = threadIdx.x, Nx = H * W;
   const int tx0 = blockIdx.x * CNN_TS, ty0 = blockIdx.y * CNN_TS;
+  double acc = 0.0;
   if (t < 3 * K) {
-    double a = 0.0;
-    for (int b = 0; b < ST_NP; ++b) a += part[(size_t)t * ST_NP + b];
-    sums[t] = a;
+#pragma unroll
+    for (int b = 0; b < ST_NP; ++b) acc += part[(size_t)t * ST_NP + b];
   }
+  double vv[NR], uu[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int e = t + r * CNN_NT;
+    vv[r] = 0.0; uu[r] = 0.0;
+    if (e < NE) {
+      const int c = e / (I0 * I0), q = e - c * (I0 * I0), iy = q / I0, ix = q - iy * I0;
+      int gy = (ty0 + iy - 3) % H, gx = (tx0 + ix - 3) % W;
+      gy += gy < 0 ? H : 0;
+      gx += gx < 0 ? W : 0;
+      const size_t g = (size_t)c * Nx + (size_t)gy * W + gx;
+      vv[r] = v[g];
+      uu[r] = U[g];
+    }
+  }
+  long long zi = -1;
+  double zz = 0.0;
+  if (t < NZ) {
+    const int c = t / S3, q = t - c * S3;
+    const int y = ty0 + q / CNN_TS, x = tx0 + q % CNN_TS;
+    if (y < H && x < W) {
+      zi = (long long)c * Nx + (long long)y * W + x;
+      zz = z[zi];
+    }
+  }
+  float w1[C0 * 9 / 4], w2[C1 * 9 / 4], w3[C2 * 9 / 4], b1, b2, b3;
+  cnn_load_b<C0>(bp, w1, b1);
+  cnn_load_b<C1>(bp + PK::R1 * 64, w2, b2);
+  cnn_load_b<C2>(bp + (PK::R1 + PK::R2) * 64, w3, b3);
+  if (t < 3 * K) sums[t] = acc;
   __syncthreads();
-  if (t == 0) {
+  if (t < K) {
+    const double mean = sums[K + t] / Nx;
+    const double var = fmax(sums[2 * K + t] / Nx - mean * mean, 0.0);
+    s_mean[t] = mean;
+    s_sd[t] = sqrt(var) + 1e-12 * fabs(mean) + 1e-300;
+  } else if (t == K) {
     double ss = 0.0;
     for (int q = 0; q < K; ++q) ss += sums[q];
     s_rms = sqrt(ss / (double)(Nx * K));
   }
   __syncthreads();
   const double rms = s_rms, inv = rms > 0.0 ? 1.0 / rms : 0.0;
-  for (int e = t; e < K * I0 * I0; e += blockDim.x) {
-    const int c = e / (I0 * I0), q = e - c * (I0 * I0), iy = q / I0, ix = q - iy * I0;
-    int gy = (ty0 + iy - 3) % H, gx = (tx0 + ix - 3) % W;
-    gy += gy < 0 ? H : 0;
-    gx += gx < 0 ? W : 0;
-    const size_t g = (size_t)c * Nx + (size_t)gy * W + gx;
-    const double mean = sums[K + c] / Nx;
-    const double var = fmax(sums[2 * K + c] / Nx - mean * mean, 0.0);
-    const double sd = sqrt(var) + 1e-12 * fabs(mean) + 1e-300;
-    a0[e] = (float)(v[g] * inv);
-    a0[K * I0 * I0 + e] = (float)((U[g] - mean) / sd);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int e = t + r * CNN_NT;
+    if (e < NE) {
+      const int c = e / (I0 * I0), q = e - c * (I0 * I0);
+      a0[c * S0 + q] = (float)(vv[r] * inv);
+      a0[(K + c) * S0 + q] = (float)((uu[r] - s_mean[c]) / s_sd[c]);
+    }
   }
   __syncthreads();
-  tile_layer<C0, C1, 4, I0, true>(a0, a1, theta);
+  cnn_layer_mfma<C0, C1, I0, S1, true>(a0, a1, w1, b1);
   __syncthreads();
-  tile_layer<C1, C2, 4, I1, true>(a1, a2, theta + off1);
+  cnn_layer_mfma<C1, C2, I1, S2, true>(a1, a2, w2, b2);
   __syncthreads();
-  tile_layer<C2, C3, 1, I2, false>(a2, a3, theta + off2);
+  cnn_layer_mfma<C2, C3, I2, S3, false>(a2, a3, w3, b3);
   __syncthreads();
-  for (int e = t; e < K * CNN_TS * CNN_TS; e += blockDim.x) {
-    const int c = e / (CNN_TS * CNN_TS), q = e - c * (CNN_TS * CNN_TS);
-    const int y = ty0 + q / CNN_TS, x = tx0 + q % CNN_TS;
-    if (y < H && x < W) z[(size_t)c * Nx + (size_t)y * W + x] += rms * (double)a3[e];
-  }
+  if (zi >= 0) z[zi] = zz + rms * (double)a3[t];
+}
+
+// the fused inference covers 8 -> 16 -> 16 -> 4 (2D2V moments, 16 hidden)
+static bool cnn_fusable(const slar_cnn* c) {
+  return c->nl == 3 && c->ch[0] == 8 && c->ch[1] == 16 && c->ch[2] == 16 && c->ch[3] == 4;
+}
+
+static constexpr int CNN_PACK_ELEMS = CnnPack<8, 16, 16, 4>::ELEMS;
+
+// refresh the packed operands after the parameters changed (stream order)
+static hipError_t cnn_repack(hipStream_t s, slar_cnn* c) {
+  if (!c->bpack) return hipSuccess;
+  k_cnn_pack<8, 16, 16, 4><<<(CNN_PACK_ELEMS + 255) / 256, 256, 0, s>>>(c->theta, c->off[1], c->off[2],
+                                                                       c->bpack);
+  return hipGetLastError();
 }
 
 hipError_t cnn_apply(hipStream_t s, Workspace* ws, const slar_cnn* net, const double* v,
@@ -474,10 +572,10 @@ hipError_t cnn_apply(hipStream_t s, Workspace* ws, const slar_cnn* net, const do
   const GridDev& G = ws->G;
   if (G.dx != 2 || c->ch[0] != 2 * (G.dv + 2) || c->ch[c->nl] != G.dv + 2) return hipErrorInvalidValue;
   const int K = G.dv + 2, Nx = G.nx, H = G.n[0], W = G.n[1];
-  if (c->nl == 3 && K == 4 && c->ch[1] == 16 && c->ch[2] == 16) {
+  if (c->bpack) {
     k_cnn_stats_part<<<dim3(ST_NP, K), 256, 0, s>>>(Nx, K, v, U, c->stats);
     const dim3 grid((W + CNN_TS - 1) / CNN_TS, (H + CNN_TS - 1) / CNN_TS);
-    k_cnn_fused<8, 16, 16, 4><<<grid, 256, 0, s>>>(H, W, v, U, c->stats, c->theta, c->off[1], c->off[2], z);
+    k_cnn_fused<8, 16, 16, 4><<<grid, CNN_NT, 0, s>>>(H, W, v, U, c->stats, c->bpack, z);
     return hipGetLastError();
   }
   if (Nx > c->maxHW) return hipErrorInvalidValue;
@@ -550,11 +648,13 @@ slar_status slar_cnn_create(int32_t nlayers, const int32_t* channels, int32_t ma
   al((void**)&c->gpart, sizeof(float) * c->gpart_elems);
   al((void**)&c->lossp, sizeof(float) * (actn / 256 + 2));
   al((void**)&c->stats, sizeof(double) * ST_ELEMS);
+  if (cnn_fusable(c)) al((void**)&c->bpack, sizeof(float) * CNN_PACK_ELEMS);
   if (ok) {
     if (hipMemset(c->theta, 0, sizeof(float) * o) != hipSuccess || hipMemset(c->m, 0, sizeof(float) * o) != hipSuccess ||
         hipMemset(c->v, 0, sizeof(float) * o) != hipSuccess)
       ok = false;
   }
+  if (ok && (cnn_repack(nullptr, c) != hipSuccess || hipDeviceSynchronize() != hipSuccess)) ok = false;
   if (!ok) { slar_cnn_destroy(c); return SLAR_E_NOMEM; }
   *out = c;
   return SLAR_OK;
@@ -562,7 +662,7 @@ slar_status slar_cnn_create(int32_t nlayers, const int32_t* channels, int32_t ma
 
 slar_status slar_cnn_destroy(slar_cnn* c) {
   if (!c) return SLAR_OK;
-  void* ptrs[] = {c->theta, c->grad, c->m, c->v, c->d0, c->d1, c->gpart, c->lossp, c->stats};
+  void* ptrs[] = {c->theta, c->grad, c->m, c->v, c->d0, c->d1, c->gpart, c->lossp, c->stats, c->bpack};
   for (void* p : ptrs) if (p) (void)hipFree(p);
   for (int l = 0; l <= CNN_LMAX; ++l) if (c->act[l]) (void)hipFree(c->act[l]);
   delete c;
@@ -576,6 +676,8 @@ slar_status slar_cnn_set_params(slar_cnn* c, const float* host, int32_t n) {
   HIP_TRY(hipMemcpy(c->theta, host, sizeof(float) * n, hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(c->m, 0, sizeof(float) * n));
   HIP_TRY(hipMemset(c->v, 0, sizeof(float) * n));
+  HIP_TRY(cnn_repack(nullptr, c));
+  HIP_TRY(hipDeviceSynchronize());
   c->step = 0;
   return SLAR_OK;
 }
@@ -620,6 +722,7 @@ slar_status slar_cnn_train_step(slar_cnn* c, int32_t B, int32_t H, int32_t W, co
   k_adam<<<(c->nparam + 255) / 256, 256, 0, s>>>(c->nparam, c->theta, c->grad, c->m, c->v, lr, b1, b2,
                                                  1e-8f, c1, c2);
   HIP_TRY(hipGetLastError());
+  HIP_TRY(cnn_repack(s, c));
   return SLAR_OK;
 }
 
