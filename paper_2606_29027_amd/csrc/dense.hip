@@ -334,8 +334,11 @@ __device__ __forceinline__ double rsq_nr(double x) {
 //    the two teams of a half-wave touch disjoint LDS banks whatever their
 //    columns (ldc and ldv are multiples of 32 doubles).
 // A pair is rotated when |x.y| exceeds the rounding level of its dot
-// product (orth |x| |y|) and |x| |y| > floor_abs.  Returns the number of
-// sweeps.
+// product (orth |x| |y|) and |x| |y| > floor_abs.  Cyclic Jacobi converges
+// quadratically, so a sweep whose rotated pairs all had cosines below
+// sqrt(orth) / 8 leaves cosines near orth / 64 for the next one, which then
+// rotates nothing: the loop ends there instead of running that sweep.
+// s_rot: two LDS flags.  Returns the number of sweeps.
 template <int RPL, int VPL>
 __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv, int kv, double orth,
                            double floor_abs, int maxsweep, double* nrm2, int* s_rot) {
@@ -344,9 +347,10 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
   const int odd = team & 1;
   const int nteam = blockDim.x >> 4;
   const int npair = kp / 2;
+  const double stop2 = orth / 64.0;   // (sqrt(orth) / 8)^2
   int sweep = 0;
   for (; sweep < maxsweep; ++sweep) {
-    if (threadIdx.x == 0) *s_rot = 0;
+    if (threadIdx.x == 0) { s_rot[0] = 0; s_rot[1] = 0; }
     for (int c = team; c < kp; c += nteam) {
       const double* cc = C + (size_t)c * ldc;
       double a = 0.0;
@@ -360,7 +364,7 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
       if (lane == 0) nrm2[c] = a;
     }
     __syncthreads();
-    bool rotated = false;
+    bool rotated = false, big = false;
     for (int step = 0; step < kp - 1; ++step) {
       if (team < npair) {
         // rr_player without a division: positions 1 .. kp-1 rotate by step
@@ -422,15 +426,18 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
             nrm2[q] = fmax(be + tt * ga, 0.0);
           }
           rotated = true;
+          big = big || ga * ga > stop2 * ab2;
         }
       }
       __syncthreads();
     }
-    if (rotated && lane == 0) *s_rot = 1;
+    if (rotated && lane == 0) s_rot[0] = 1;
+    if (big && lane == 0) s_rot[1] = 1;
     __syncthreads();
-    const bool again = *s_rot != 0;
-    __syncthreads();   // every wave has read the flag before thread 0 resets it
+    const bool again = s_rot[0] != 0, more = s_rot[1] != 0;
+    __syncthreads();   // every wave has read the flags before thread 0 resets them
     if (!again) break;
+    if (!more) { ++sweep; break; }
   }
   return sweep;
 }
@@ -450,7 +457,7 @@ __global__ __launch_bounds__(512) void k_svd_jacobi(int k, const double* __restr
   __shared__ double nrm[SVD_KM];
   __shared__ int order[SVD_KM];
   __shared__ double red[8];
-  __shared__ int s_rot;
+  __shared__ int s_rot[2];
   const int t = threadIdx.x;
   const int kp = (k + 1) & ~1;   // even count (a zero column pads odd k)
   double part = 0.0;
@@ -468,7 +475,7 @@ __global__ __launch_bounds__(512) void k_svd_jacobi(int k, const double* __restr
   for (int w = 0; w < 8; ++w) fro += red[w];
   const double floor_abs = 1e-300 + 1e-22 * fro;   // columns below this are negligible
   const double orth = 4.0 * kp * 2.220446049250313e-16;
-  jacobi_cols<4, 4>(A, SVD_KM, kp, kp, V, SVD_KM, kp, orth, floor_abs, 60, nrm, &s_rot);
+  jacobi_cols<4, 4>(A, SVD_KM, kp, kp, V, SVD_KM, kp, orth, floor_abs, 60, nrm, s_rot);
   for (int c = t; c < kp; c += blockDim.x) {
     double acc = 0.0;
     for (int r = 0; r < kp; ++r) acc += A[c * SVD_KM + r] * A[c * SVD_KM + r];
@@ -531,7 +538,7 @@ __global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
   __shared__ double nrm[EIG_CM];
   __shared__ int order[EIG_CM];
   __shared__ double s_piv;
-  __shared__ int s_p, s_rot, s_nc;
+  __shared__ int s_p, s_rot[2], s_nc;
   __shared__ double s_trace, s_rest;
   const int t = threadIdx.x;
   for (int i = t; i < n; i += blockDim.x) { dres[i] = fmax(G[(size_t)i * n + i], 0.0); taken[i] = 0; }
@@ -607,7 +614,7 @@ __global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
   __syncthreads();
   const double floor_abs = 1e-22 * trace + 1e-300;   // columns below this are negligible
   const double orth = 4.0 * n * 2.220446049250313e-16;
-  if (kp >= 2) jacobi_cols<8, 0>(L, SLAR_NMAX, n, kp, nullptr, 0, 0, orth, floor_abs, 40, nrm, &s_rot);
+  if (kp >= 2) jacobi_cols<8, 0>(L, SLAR_NMAX, n, kp, nullptr, 0, 0, orth, floor_abs, 40, nrm, s_rot);
   for (int j = t; j < kp; j += blockDim.x) {
     double acc = 0.0;
     for (int r = 0; r < n; ++r) acc += L[j * SLAR_NMAX + r] * L[j * SLAR_NMAX + r];
