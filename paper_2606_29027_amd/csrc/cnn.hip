@@ -2,7 +2,9 @@
 // macroscopic system (an addition to the paper's method, which names
 // preconditioning of that solve as future work): FP32 periodic 3x3
 // convolutions with tanh between layers, hand-written forward, backward
-// (data and weights) and Adam kernels.
+// (data and weights) and Adam kernels for training, and for use inside the
+// solve one fused launch that runs the whole 8 -> 16 -> 16 -> 4 network per
+// output tile on the matrix cores (other shapes run layer by layer).
 //
 // Layout: activations [B][C][H][W]; parameters packed per layer as
 // w [Co][Ci][3][3] then b [Co]; out[o,y,x] = b[o] +
