@@ -355,7 +355,9 @@ slar_status slar_cnn_train_step(slar_cnn* cnn, int32_t B, int32_t H, int32_t W, 
  * (Nx = n[0] n[1], x1 fastest); z is read and written, distinct from v and
  * U.  Needs dx = 2 and channels 2K -> ... -> K (SLAR_E_INVAL otherwise); a
  * 2K -> 16 -> 16 -> K network of any grid runs fused in one launch after a
- * statistics pass.  Enqueued on stream.                                     */
+ * statistics pass.  Enqueued on stream.  The network object holds the
+ * statistics and activation buffers, so calls that share one network
+ * (here, in slar_macro_solve or in training) must not overlap in time.     */
 slar_status slar_cnn_correct(const slar_grid* g, const slar_cnn* cnn, const double* v,
                              const double* U, double* z, slar_workspace* ws, hipStream_t stream);
 /* Records up to `capacity` training pairs from later flexible-GMRES solves
