@@ -234,12 +234,13 @@ hipError_t spectral_symbol(hipStream_t s, Workspace* ws, int op, int nvec, const
 //   SPEC_POISSON  rho -> (phi, E_m = -i k_m phi), phi = rho / |k|^2
 //   SPEC_DTPHI    J_m -> i k_m dtphi, dtphi = -(sum_m i k_m J_m) / |k|^2
 //   SPEC_DIV      F[q][m] -> sum_m i k_m F[q][m]
-//   SPEC_PRECOND  x_b -> sum_b Minv[a][b] x_b (per-mode K x K inverse)
+//   SPEC_PRECOND  x_b -> sum_b Minv[a][b] x_b (per-mode K x K inverse; the
+//                 modes stored transposed, pm = i1 n0 + i0 for p = i0 n1 + i1)
 // Null modes (|k| = 0) and Nyquist wavenumbers map to zero as in k_symbol.
 constexpr int SPEC_MAXIN = 8, SPEC_MAXOUT = 4;
 
 __device__ __forceinline__ void spec_map(int op, int dx, int K, const double* k, const double2* x,
-                                         double2* y, const double2* __restrict__ Minv, long long p,
+                                         double2* y, const double2* __restrict__ Minv, long long pm,
                                          int Nx) {
   const double k2 = k[0] * k[0] + k[1] * k[1];
   if (op == SPEC_POISSON) {
@@ -268,7 +269,7 @@ __device__ __forceinline__ void spec_map(int op, int dx, int K, const double* k,
     for (int a = 0; a < K; ++a) {
       double sr = 0.0, si = 0.0;
       for (int b = 0; b < K; ++b) {
-        const double2 m = Minv[(size_t)(a * K + b) * Nx + p];
+        const double2 m = Minv[(size_t)(a * K + b) * Nx + pm];
         sr += m.x * x[b].x - m.y * x[b].y;
         si += m.x * x[b].y + m.y * x[b].x;
       }
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(256) void k_spec_line(Kgrid Kg, int op, int K, int 
     kvec(Kg, p, k);
     double2 x[SPEC_MAXIN], y[SPEC_MAXOUT];
     for (int f = 0; f < Bin; ++f) x[f] = a[f * L + e];
-    spec_map(op, Kg.dx, K, k, x, y, Minv, p, Nx);
+    spec_map(op, Kg.dx, K, k, x, y, Minv, (long long)other * L + e, Nx);
     const int r = __brev((unsigned)e) >> (32 - logL);
     for (int g = 0; g < Bout; ++g) b[g * L + r] = y[g];
   }
@@ -340,7 +341,7 @@ __global__ void k_spec_point(Kgrid Kg, int op, int K, int Bin, int Bout, const d
   kvec(Kg, p, k);
   double2 x[SPEC_MAXIN], y[SPEC_MAXOUT];
   for (int f = 0; f < Bin; ++f) x[f] = in[(size_t)f * Nx + p];
-  spec_map(op, Kg.dx, K, k, x, y, Minv, p, Nx);
+  spec_map(op, Kg.dx, K, k, x, y, Minv, (long long)(p % Kg.n1) * Kg.n0 + p / Kg.n1, Nx);
   for (int g = 0; g < Bout; ++g) out[(size_t)g * Nx + p] = y[g];
 }
 

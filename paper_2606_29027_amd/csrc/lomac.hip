@@ -464,7 +464,9 @@ __global__ void k_meanfix(int Nx, int K, const double* __restrict__ md, const do
 // (complex Gauss-Jordan, partial pivoting) and applied as a matrix-vector
 // product; the field-energy flux and the E-dependent parts are left to the
 // Krylov iteration.  A_mu [dx][K][K] is precomputed on the host.
-// Minv[(a K + b) Nx + p] holds entry (a, b) of mode p's inverse.
+// Minv[(a K + b) Nx + pt] holds entry (a, b) of the inverse of mode
+// p = i0 n1 + i1 at the transposed position pt = i1 n0 + i0, so that the
+// modes of one axis-0 line (the spectral line kernel's lanes) are adjacent.
 __global__ void k_spec_setup(int n0, int n1, int dx, double L0, double L1, int K,
                              const double* __restrict__ A, double bdt, double ni,
                              double2* __restrict__ Minv, int Nx) {
@@ -520,7 +522,8 @@ __global__ void k_spec_setup(int n0, int n1, int dx, double L0, double L1, int K
     }
   }
   for (int a = 0; a < K; ++a)
-    for (int b = 0; b < K; ++b) Minv[(size_t)(a * K + b) * Nx + p] = make_double2(Mr[a][K + b], Mi[a][K + b]);
+    for (int b = 0; b < K; ++b)
+      Minv[(size_t)(a * K + b) * Nx + (size_t)(p % n1) * n0 + p / n1] = make_double2(Mr[a][K + b], Mi[a][K + b]);
 }
 
 static hipError_t spectral_setup(hipStream_t s, Workspace* ws, double bdt, double2* Minv) {
