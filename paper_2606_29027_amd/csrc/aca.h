@@ -53,6 +53,9 @@ struct AcaInst {
   const int* rowtab = nullptr;
   const int* coltab = nullptr;
   int* piv = nullptr;
+  // host-mapped pinned word that receives the phase after every
+  // bookkeeping launch (single-instance driver; null elsewhere)
+  int* phase_host = nullptr;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -609,6 +612,10 @@ __global__ __launch_bounds__(FS_THREADS) void k_aca_row(AcaInst I) { aca_row_bod
 template <typename T, int W, int DX, bool TAB = false>
 __global__ __launch_bounds__(FS_THREADS) void k_aca_col(AcaInst I) { aca_col_body<T, W, DX, TAB>(I, blockIdx.x); }
 template <typename T, int W, int DX, bool TAB = false>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_fin(AcaInst I) { aca_fin_body<T, W, DX, TAB>(I); }
+__global__ __launch_bounds__(FS_THREADS) void k_aca_fin(AcaInst I) {
+  aca_fin_body<T, W, DX, TAB>(I);
+  // thread 0 made every change of the phase, so it reads the final value
+  if (I.phase_host && threadIdx.x == 0) *(volatile int*)I.phase_host = I.ctl->phase;
+}
 
 }  // namespace slar

@@ -116,6 +116,7 @@ slar_status slar_workspace_destroy(slar_workspace* w) {
   }
   if (ws.aca_ctl_host) (void)hipHostFree(ws.aca_ctl_host);
   if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
+  if (ws.phase_host) (void)hipHostFree(ws.phase_host);
   delete w;
   return SLAR_OK;
 }
@@ -184,6 +185,8 @@ slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspa
   for (hipEvent_t& e : ws.poll_ev)
     if (ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
   if (ok && hipHostMalloc(&ws.host_pinned, 65536, 0) != hipSuccess) ok = false;
+  if (ok && hipHostMalloc((void**)&ws.phase_host, 256, hipHostMallocMapped) != hipSuccess) ok = false;
+  if (ok && hipHostGetDevicePointer((void**)&ws.phase_dev, ws.phase_host, 0) != hipSuccess) ok = false;
   if (ok && hipStreamCreateWithFlags(&ws.aux, hipStreamNonBlocking) != hipSuccess) ok = false;
   if (ok && hipEventCreateWithFlags(&ws.ev_fork, hipEventDisableTiming) != hipSuccess) ok = false;
   if (ok && hipEventCreateWithFlags(&ws.ev_join, hipEventDisableTiming) != hipSuccess) ok = false;

@@ -33,10 +33,11 @@ template <typename T, int W, int DX>
 static hipError_t aca_iterate(hipStream_t s, const GridDev& G, const AdvDev& A, const T* X,
                               const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
                               unsigned char* used, double* part, int nprobe, const int* probes,
-                              hipEvent_t* ev) {
+                              hipEvent_t* ev, int* phase_dev) {
   const unsigned bRow = (G.nv + ACA_TILE - 1) / ACA_TILE;
   const unsigned bCol = (G.nx + ACA_TILE - 1) / ACA_TILE;
   AcaInst I{G, A, X, P, ld, r, ctl, U, V, used, part, (int)bRow, (int)bCol, nprobe, 16, probes};
+  I.phase_host = phase_dev;
   if (ev) {
     // events attached to the dispatches themselves: start and end of the
     // kernel, without marker packets between the launches
@@ -54,12 +55,13 @@ template <typename T>
 static hipError_t aca_iter_dispatch(hipStream_t s, const GridDev& G, const AdvDev& A, const T* X,
                                     const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
                                     unsigned char* used, double* part, int nprobe,
-                                    const int* probes, hipEvent_t* ev) {
+                                    const int* probes, hipEvent_t* ev, int* phase_dev) {
   if (G.dx == 1) {
-    if (A.order == 5) return aca_iterate<T, 5, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev);
-    return aca_iterate<T, 3, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev);
+    if (A.order == 5)
+      return aca_iterate<T, 5, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev);
+    return aca_iterate<T, 3, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev);
   }
-  return aca_iterate<T, 3, 2>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev);
+  return aca_iterate<T, 3, 2>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev);
 }
 
 hipError_t table_copy(hipStream_t s, int rows, int r, int ldin, const double* in, int ldo,
@@ -97,15 +99,16 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   const int rx = (G.dx == 2) ? adv.order * adv.order : adv.order;
   const double gather_bytes = 2.0 * rx * ldt * (dt == SLAR_F32 ? 4.0 : 8.0) + 8.0;
   const bool timing = ws->timing && (int)ws->events.size() >= 4 * maxit;
-  // Iterations are enqueued in chunks of CH; after each chunk a copy of the
-  // control block goes to one of two pinned slots with an event.  The host
-  // waits for the previous chunk's copy only after the next chunk is
-  // queued, so the device never idles on a poll.  Iterations enqueued after
-  // the stop see phase != RUN and exit at once (their launches did no work
-  // and are left out of the timing below).
+  // Iterations are enqueued in chunks of CH with an event after each.
+  // Every bookkeeping launch writes the phase to a host-mapped pinned word;
+  // the host reads it once the previous chunk's event has completed (only
+  // after the next chunk is queued, so the device never idles on a poll).
+  // A newer value than that chunk's is harmless: DONE is final.
+  // Iterations enqueued after the stop see phase != RUN and exit at once
+  // (their launches did no work and are left out of the timing below).
   constexpr int CH = 4;
   auto timed = [&](int q) { return timing && (q % ws->timing_every) == ws->timing_every - 1; };
-  AcaCtl* ring = hc + 1;
+  *(volatile int*)ws->phase_host = ACA_RUN;   // no launch of this workspace is in flight
   int it = 0, pending = -1;
   bool stop = false;
   while (it < maxit && !stop) {
@@ -115,18 +118,17 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
       if (dt == SLAR_F32)
         e = aca_iter_dispatch<float>(s, G, A, ws->X32, ws->P32, ldt, r, ctl, out->U, out->V,
                                      ws->used, ws->aca_part, nprobe, probes,
-                                     timed(it) ? &ws->events[4 * it] : nullptr);
+                                     timed(it) ? &ws->events[4 * it] : nullptr, ws->phase_dev);
       else
         e = aca_iter_dispatch<double>(s, G, A, X64, P64, ldt, r, ctl, out->U, out->V, ws->used,
                                       ws->aca_part, nprobe, probes,
-                                      timed(it) ? &ws->events[4 * it] : nullptr);
+                                      timed(it) ? &ws->events[4 * it] : nullptr, ws->phase_dev);
       if (e != hipSuccess) return SLAR_E_HIP;
     }
-    HIP_TRY(hipMemcpyAsync(&ring[c & 1], ctl, sizeof(AcaCtl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(ws->poll_ev[c & 1], s));
     if (pending >= 0) {
       HIP_TRY(hipEventSynchronize(ws->poll_ev[pending & 1]));
-      stop = ring[pending & 1].phase == ACA_DONE;
+      stop = *(volatile int*)ws->phase_host == ACA_DONE;
     }
     pending = c;
   }

@@ -45,6 +45,8 @@ struct Workspace {
   void* aca_ctl = nullptr;       // AcaCtl
   void* aca_ctl_host = nullptr;  // pinned copies: [0] final, [1], [2] polling ring
   hipEvent_t poll_ev[2] = {nullptr, nullptr};   // completion of the ring copies
+  int* phase_host = nullptr;       // host-mapped pinned word: cross phase written by the device
+  int* phase_dev = nullptr;        // its device address
   double* aca_part = nullptr;    // partial reductions
   unsigned char* used = nullptr; // [Nx]
   double* resid = nullptr;       // [max(Nx,Nv)]
