@@ -388,15 +388,18 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
         ga = row16_sum(ga);
         const double ab2 = al * be;
         if (ga * ga > orth * orth * ab2 && ab2 > floor_abs * floor_abs) {
-          const double zeta = (be - al) * rcp_nr(2.0 * ga);
+          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)); 1 / (2 zeta) for
+          // huge |zeta|.  t only steers convergence (the rotation stays
+          // orthogonal through c below), so it takes the hardware estimates
+          // without refinement; c = 1 / sqrt(1 + t^2) is refined.
+          const double zeta = (be - al) * __builtin_amdgcn_rcp(2.0 * ga);
           const double az = fabs(zeta);
-          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)); 1 / (2 zeta) for huge |zeta|
           double tt;
           if (az < 1e100) {
             const double z2 = fma(zeta, zeta, 1.0);
-            tt = rcp_nr(az + z2 * rsq_nr(z2));
+            tt = __builtin_amdgcn_rcp(az + z2 * __builtin_amdgcn_rsq(z2));
           } else {
-            tt = 0.5 * rcp_nr(az);
+            tt = 0.5 * __builtin_amdgcn_rcp(az);
           }
           tt = (zeta >= 0.0) ? tt : -tt;
           const double c = rsq_nr(fma(tt, tt, 1.0)), sn = c * tt;
