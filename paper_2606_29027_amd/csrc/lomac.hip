@@ -686,10 +686,11 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
       std::fill(gv.begin(), gv.end(), 0.0);
       gv[0] = beta;
       int jl = 0;
+      int pre = -1;   // basis vector whose preconditioned copy is already enqueued
       for (int j = 0; j < m; ++j) {
         double* vj = b.V + (size_t)j * n;
         double* zj = flexible ? b.Z + (size_t)j * n : vj;
-        if (flexible) {
+        if (flexible && pre != j) {
           if (apply_pc(vj, zj) != hipSuccess) return SLAR_E_HIP;
           norm2(zj, nrm + 2);
         }
@@ -707,7 +708,17 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
         cgs(0, b.V, h2, b.w, nrm + 3);       // w -= V h2 ; ||w||^2
         k_scale_by_norm<<<nb, 256, 0, s>>>(n, b.w, nrm + 3, b.V + (size_t)(j + 1) * n);
         HIP_TRY(hipMemcpyAsync(hh, hdev, sizeof(double) * 208, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipEventRecord(ws->poll_ev[0], s));
+        // the next basis vector is on the device: its preconditioner runs
+        // while the host waits for this column (the same launches in the
+        // same order as without; wasted once, when the solve stops here)
+        if (flexible && j + 1 < m) {
+          double* zn = b.Z + (size_t)(j + 1) * n;
+          if (apply_pc(b.V + (size_t)(j + 1) * n, zn) != hipSuccess) return SLAR_E_HIP;
+          norm2(zn, nrm + 2);
+          pre = j + 1;
+        }
+        HIP_TRY(hipEventSynchronize(ws->poll_ev[0]));
         for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[80 + i];
         const double hn = std::sqrt(std::max(hh[203], 0.0));
         H[(size_t)(j + 1) * m + j] = hn;
