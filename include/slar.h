@@ -289,6 +289,16 @@ slar_status slar_macro_solve_system(const slar_grid* g, const slar_macro_system*
                                     const slar_cnn* cnn, double* U_out, int32_t* iters,
                                     slar_workspace* ws, hipStream_t stream);
 
+/* Convergence record of the last slar_macro_solve / _system on ws, one
+ * record of 4 doubles per Newton iteration (at most 32 records):
+ * {RMS residual ||G||_2 / sqrt(n) at the start of the iteration, Krylov
+ * iterations of its linear solve, true linear residual ||J d + G|| / ||G||
+ * at its end, GMRES restarts}.  The last record holds the final residual
+ * (its other fields 0 when Newton converged there).  Copies
+ * min(count, cap) records into out (host [cap][4]) and returns count, or
+ * -1 on invalid arguments.  Host only; reflects the last solve that ran. */
+int32_t slar_macro_history(const slar_workspace* ws, double* out, int32_t cap);
+
 /* Right-hand side R(U) = D.F(U) - S(U) of the moment system U' = -R(U)
  * (eq. (BE_nonlinear_system) without the history), with the closure of the
  * last slar_lomac_prepare on ws (SLAR_E_INVAL if none).  U, R_out device

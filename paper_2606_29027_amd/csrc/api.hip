@@ -472,4 +472,11 @@ slar_status slar_timing_read(const slar_workspace* w, double* out /* host [8] */
   return SLAR_OK;
 }
 
+int32_t slar_macro_history(const slar_workspace* w, double* out, int32_t cap) {
+  if (!w || (!out && cap > 0) || cap < 0) return -1;
+  const int n = std::min(w->w.newton_hist_n, (int)cap);
+  for (int i = 0; i < 4 * n; ++i) out[i] = w->w.newton_hist[i];
+  return w->w.newton_hist_n;
+}
+
 }  // extern "C"

@@ -330,40 +330,87 @@ hipError_t macro_residual(hipStream_t s, Workspace* ws, const double* U, const d
 // ------------------------------------------------------ vector kernels
 constexpr int MD_CHUNK = 512;   // elements per block in the Krylov passes
 
-// One classical Gram--Schmidt pass over the basis V[0..nv):
-//   if sub: w -= sum_v V[v] h[v]   (h from the previous pass)
-//   part[v][block] = V[v] . w  (v < nv),  part[nv][block] = w . w
-__global__ __launch_bounds__(256) void k_cgs_pass(int n, int nv, const double* __restrict__ V,
-                                                  long long ldv, const double* __restrict__ h,
-                                                  double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double red[4][SLAR_KMAX + 1];
+// Sum of per-block partials, the same fixed order in every block that asks:
+// out[v] = sum_b part[v][b] for v < nv, one wave per value, lanes over b,
+// then a butterfly.  Every block gets bitwise the same sums.
+__device__ __forceinline__ void reduce_parts_block(int nb, int nv, const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+  const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int v = wv; v < nv; v += nw) {
+    double acc = 0.0;
+    for (int b = ln; b < nb; b += 64) acc += part[(size_t)v * nb + b];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (ln == 0) out[v] = acc;
+  }
+}
+
+// One classical Gram--Schmidt pass of the Arnoldi step over V[0..nv):
+//   nsub > 0: h = sum of the previous pass's partials hpart (nbk per value,
+//             reduced redundantly by every block), block 0 stores h in hout;
+//             w -= sum_{v < nsub} V[v] h[v]
+//   then part[v][block] = V[v] . w for v < ndot, and part[ndot][block] =
+//   w . w when wnorm.
+__global__ __launch_bounds__(256) void k_cgs_pass(int n, int nsub, int ndot, int wnorm,
+                                                  const double* __restrict__ V, long long ldv,
+                                                  const double* __restrict__ hpart,
+                                                  double* __restrict__ hout, double* __restrict__ w,
+                                                  double* __restrict__ part) {
+  __shared__ double red[4][SLAR_KMAX + 2];
+  __shared__ double hs[SLAR_KMAX + 2];
   const int t = threadIdx.x;
   const int e0 = blockIdx.x * MD_CHUNK;
+  if (nsub > 0) {
+    reduce_parts_block(gridDim.x, nsub, hpart, hs);
+    __syncthreads();
+    if (blockIdx.x == 0 && hout)
+      for (int v = t; v < nsub; v += 256) hout[v] = hs[v];
+  }
   double wl[MD_CHUNK / 256];
   for (int q = 0; q < MD_CHUNK / 256; ++q) {
     const int e = e0 + t + q * 256;
     double x = 0.0;
     if (e < n) {
       x = w[e];
-      if (h) {
-        for (int v = 0; v < nv; ++v) x -= V[v * ldv + e] * h[v];
+      if (nsub > 0) {
+        for (int v = 0; v < nsub; ++v) x -= V[v * ldv + e] * hs[v];
         w[e] = x;
       }
     }
     wl[q] = x;
   }
-  for (int v = 0; v <= nv; ++v) {
+  const int nd = ndot + (wnorm ? 1 : 0);
+  for (int v = 0; v < nd; ++v) {
     double acc = 0.0;
     for (int q = 0; q < MD_CHUNK / 256; ++q) {
       const int e = e0 + t + q * 256;
-      if (e < n) acc += (v < nv ? V[v * ldv + e] : wl[q]) * wl[q];
+      if (e < n) acc += (v < ndot ? V[v * ldv + e] : wl[q]) * wl[q];
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((t & 63) == 0) red[t >> 6][v] = acc;
   }
   __syncthreads();
-  for (int v = t; v <= nv; v += 256)
+  for (int v = t; v < nd; v += 256)
     part[(size_t)v * gridDim.x + blockIdx.x] = red[0][v] + red[1][v] + red[2][v] + red[3][v];
+}
+
+// Last step of the Arnoldi orthogonalisation: ||w||^2 = sum of the partials
+// (same fixed order as above), out = w / ||w|| (0 if w == 0); block 0
+// stores ||w||^2 in nout.  Launched with the grid of the partials.
+__global__ __launch_bounds__(256) void k_cgs_normalize(int n, const double* __restrict__ npart,
+                                                       double* __restrict__ nout,
+                                                       const double* __restrict__ w,
+                                                       double* __restrict__ out) {
+  __shared__ double nn[1];
+  reduce_parts_block(gridDim.x, 1, npart, nn);
+  __syncthreads();
+  const double s2 = nn[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) nout[0] = s2;
+  const double nz = sqrt(s2);
+  const int e0 = blockIdx.x * MD_CHUNK;
+  for (int q = 0; q < MD_CHUNK / 256; ++q) {
+    const int e = e0 + threadIdx.x + q * 256;
+    if (e < n) out[e] = nz > 0.0 ? w[e] / nz : 0.0;
+  }
 }
 
 // out[v] = sum_b part[v][b]: one wave per v, lanes over b (coalesced),
@@ -409,14 +456,6 @@ __global__ void k_fd_diff(int n, const double* __restrict__ Gh, const double* __
   w[e] = residual_form ? -g0[e] - jv : jv;
 }
 
-// w_out = w / sqrt(nrm2)
-__global__ void k_scale_by_norm(int n, const double* __restrict__ w, const double* __restrict__ nrm2,
-                                double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const double nz = sqrt(nrm2[0]);
-  out[e] = nz > 0.0 ? w[e] / nz : 0.0;
-}
 
 // x += sum_v A[v] y[v]
 __global__ void k_add_combo(int n, int nv, const double* __restrict__ A, long long lda,
@@ -544,6 +583,7 @@ static hipError_t spectral_precond(hipStream_t s, Workspace* ws, const double* v
 
 struct KryBufs {
   double *V, *Z, *w, *g0, *Uh, *Gh, *d, *r, *x, *U;
+  double *partA, *partB;   // per-block partial dot products, [m + 2][nbk] each
   double2* Minv;   // spectral preconditioner inverses [K][K][Nx]
 };
 
@@ -561,12 +601,16 @@ static KryBufs kry_bufs(Workspace* ws, int n, int m) {
   b.x = p; p += n;
   b.U = p; p += n;
   b.Minv = (double2*)p; p += (size_t)2 * 4 * n;   // K^2 Nx complex, K <= 4
+  const size_t np = (size_t)(m + 2) * ((n + MD_CHUNK - 1) / MD_CHUNK);
+  b.partA = p; p += np;
+  b.partB = p; p += np;
   return b;
 }
 
 size_t kry_elems_for(int Nx, int K, int m) {
   const size_t n = (size_t)Nx * K;
-  return macro_fixed_elems(Nx) + (size_t)(2 * m + 1) * n + 8 * n + (size_t)8 * n + 4096;
+  return macro_fixed_elems(Nx) + (size_t)(2 * m + 1) * n + 8 * n + (size_t)8 * n +
+         (size_t)2 * (m + 2) * ((n + MD_CHUNK - 1) / MD_CHUNK) + 4096;
 }
 
 // host-side flux Jacobian of the closure (see k_spec_setup)
@@ -634,15 +678,13 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
   double* hdev = ws->small;            // [0..72] dots, [80..] second pass, [160] h, [170..] means
   double* h1 = hdev, * h2 = hdev + 80, * hval = hdev + 160, * means = hdev + 170;
   double* nrm = hdev + 200;            // norms
-  double* part = ws->small + 512;
   double* hh = (double*)ws->host_pinned;
   const unsigned nb = (n + 255) / 256;
   const int nbk = (n + MD_CHUNK - 1) / MD_CHUNK;
-  auto cgs = [&](int nv, const double* V, const double* hprev, double* w, double* out) {
-    k_cgs_pass<<<nbk, 256, 0, s>>>(n, nv, V, n, hprev, w, part);
-    k_reduce_parts<<<nv + 1, 64, 0, s>>>(nbk, part, out);
+  auto norm2 = [&](const double* x, double* out) {
+    k_cgs_pass<<<nbk, 256, 0, s>>>(n, 0, 0, 1, nullptr, n, nullptr, nullptr, (double*)x, b.partA);
+    k_reduce_parts<<<1, 64, 0, s>>>(nbk, b.partA, out);
   };
-  auto norm2 = [&](double* x, double* out) { cgs(0, nullptr, nullptr, x, out); };
   double* Uhist = b.x;
   const double bdt = beta;
   k_hist_combine<<<nb, 256, 0, s>>>(n, hist, Uhist);
@@ -652,6 +694,7 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
   const double sqeps = std::sqrt(2.220446049250313e-16);
   int newton = 0, krylov = 0;
   bool converged = false;
+  ws->newton_hist_n = 0;
   const bool flexible = precond != 0;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
   auto apply_pc = [&](const double* v, double* z) -> hipError_t {
@@ -671,6 +714,9 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
     const double gn = std::sqrt(hh[0]);
     if (!std::isfinite(gn)) return SLAR_E_NUMERIC;
     const double rms = gn / std::sqrt((double)n);
+    double* rec = ws->newton_hist + 4 * std::min(it, 31);
+    rec[0] = rms; rec[1] = 0.0; rec[2] = 0.0; rec[3] = 0.0;
+    ws->newton_hist_n = std::min(it + 1, 32);
     if (rms <= newton_tol) { converged = true; break; }
     if (it == KRY_MAX_NEWTON) break;
     const double fdc = sqeps * (1.0 + std::sqrt(hh[1]));
@@ -702,11 +748,12 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
           if (spectral_precond(s, ws, b.w, b.Minv, b.Uh) != hipSuccess) return SLAR_E_HIP;
           if (record_pair(s, ws, b.w, zj, U, b.Uh) != hipSuccess) return SLAR_E_HIP;
         }
-        // CGS2 against V[0..j]
-        cgs(j + 1, b.V, nullptr, b.w, h1);
-        cgs(j + 1, b.V, h1, b.w, h2);
-        cgs(0, b.V, h2, b.w, nrm + 3);       // w -= V h2 ; ||w||^2
-        k_scale_by_norm<<<nb, 256, 0, s>>>(n, b.w, nrm + 3, b.V + (size_t)(j + 1) * n);
+        // CGS2 against V[0..j]: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2;
+        // V[j+1] = w / ||w||.  The Hessenberg column is h1 + h2.
+        k_cgs_pass<<<nbk, 256, 0, s>>>(n, 0, j + 1, 0, b.V, n, nullptr, nullptr, b.w, b.partA);
+        k_cgs_pass<<<nbk, 256, 0, s>>>(n, j + 1, j + 1, 0, b.V, n, b.partA, h1, b.w, b.partB);
+        k_cgs_pass<<<nbk, 256, 0, s>>>(n, j + 1, 0, 1, b.V, n, b.partB, h2, b.w, b.partA);
+        k_cgs_normalize<<<nbk, 256, 0, s>>>(n, b.partA, nrm + 3, b.w, b.V + (size_t)(j + 1) * n);
         HIP_TRY(hipMemcpyAsync(hh, hdev, sizeof(double) * 208, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(ws->poll_ev[0], s));
         // the next basis vector is on the device: its preconditioner runs
@@ -757,8 +804,11 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
       HIP_TRY(hipMemcpyAsync(hh, nrm + 5, sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       beta = std::sqrt(std::max(hh[0], 0.0));
+      rec[2] = bn > 0.0 ? beta / bn : 0.0;
+      rec[3] += 1.0;
       if (beta <= krylov_tol * bn || beta == 0.0) done = true;
     }
+    rec[1] = kits;
     krylov += kits;
     // exact step on the per-component mean
     k_comp_means<<<K, 256, 0, s>>>(Nx, b.d, b.g0, means);

@@ -72,6 +72,10 @@ struct Workspace {
   // macro / Krylov
   double* kry = nullptr;
   size_t kry_elems = 0;
+  // history of the last macro solve, one record per Newton iteration:
+  // {RMS residual, Krylov iterations, true GMRES residual / ||G||, restarts}
+  double newton_hist[4 * 32];
+  int newton_hist_n = 0;
   // second stream (default priority) for independent chains inside a call,
   // joined back before the call returns; fork_aux = false keeps every chain
   // on the caller's stream (batched instances: the pool already overlaps

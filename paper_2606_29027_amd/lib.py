@@ -29,7 +29,7 @@ EXPORTS = (
     "slar_batch_cross_update", "slar_batch_truncate", "slar_batch_efield", "slar_batch_get_config",
     "slar_batch_set_config", "slar_batch_tune", "slar_batch_timing", "slar_batch_timing_reset",
     "slar_macro_solve_system", "slar_macro_rhs", "slar_dirk3_tableau", "slar_bdf_weights",
-    "slar_cnn_correct",
+    "slar_cnn_correct", "slar_macro_history",
 )
 
 
@@ -139,6 +139,7 @@ def load(path: str = LIB_PATH):
         "slar_cnn_correct": (i32, [P(Grid), vp, vp, vp, vp, vp, vp]),
         "slar_dirk3_tableau": (i32, [P(dbl), P(dbl)]),
         "slar_bdf_weights": (i32, [i32, P(dbl), P(dbl), P(dbl)]),
+        "slar_macro_history": (i32, [vp, P(dbl), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -319,6 +320,16 @@ def slar_macro_solve_system(grid, hist, stages, beta, newton_tol, krylov_tol, pr
                                         int(precond), cnn, _ptr(U_out), iters, ws.h, _stream())
     _check(st, "slar_macro_solve_system", ok=(SLAR_OK, SLAR_E_NOCONV))
     return st, (iters[0], iters[1])
+
+
+def slar_macro_history(ws):
+    """Per-Newton records of the last macro solve: list of (rms, krylov,
+    true relative linear residual, restarts)."""
+    out = (C.c_double * (4 * 32))()
+    n = load().slar_macro_history(ws.h, out, 32)
+    if n < 0:
+        raise SlarError(SLAR_E_INVAL, "slar_macro_history")
+    return [tuple(out[4 * i: 4 * i + 4]) for i in range(min(n, 32))]
 
 
 def slar_macro_rhs(grid, U, R_out, ws):

@@ -31,7 +31,8 @@ RCAP = 64
 
 class Solver:
     def __init__(self, p, precision: int = L.F64, probes=None, delta: float = 1e-12,
-                 precond: int = 0, cnn=None, newton_tol: float = 1e-10, krylov_tol: float = 1e-4):
+                 precond: int = 0, cnn=None, newton_tol: float = 1e-10, krylov_tol: float = 1e-4,
+                 strict: bool = True):
         self.p = p
         self.grid = L.make_grid(p)
         self.ws = L.Workspace(self.grid, min(p.rmax, RCAP))
@@ -41,6 +42,11 @@ class Solver:
         self.cnn = cnn
         self.newton_tol = newton_tol
         self.krylov_tol = krylov_tol
+        # strict: a macroscopic solve that misses the Newton tolerance raises
+        # SlarError(SLAR_E_NOCONV) after the step's records are stored;
+        # otherwise the step is completed and reported with converged False
+        self.strict = strict
+        self.macro_log = []           # per solve: Newton records (rms, krylov, lin. residual, restarts)
         self.d = p.dx + p.dv
         self.Nx = int(np.prod(p.n[: p.dx]))
         self.Nv = int(np.prod(p.n[p.dx:]))
@@ -172,6 +178,7 @@ class Solver:
                                                  self.krylov_tol, self.precond,
                                                  None if self.cnn is None else self.cnn.handle, U_out, self.ws)
         self.tphase["macro"] += time.perf_counter() - t0
+        self.macro_log.append(L.slar_macro_history(self.ws))
         return st == L.SLAR_OK, nn, nk
 
     def _step_dirk3_bdf3(self, h):
@@ -211,7 +218,7 @@ class Solver:
             info = self._step_dirk3_bdf3(h)
             torch.cuda.synchronize()
             info["seconds"] = time.perf_counter() - t0
-            return info
+            return self._finish(info)
         Fs, Hs, slot = self.strang(h) if p.split else self.slar_vp(h)
         info = {}
         if p.lomac:
@@ -223,6 +230,7 @@ class Solver:
                                               self.newton_tol, self.krylov_tol, self.precond,
                                               None if self.cnn is None else self.cnn.handle, U_new, self.ws)
             self.tphase["macro"] += time.perf_counter() - tm
+            self.macro_log.append(L.slar_macro_history(self.ws))
             out_slot = [s for s in range(4) if s not in (slot,)][0]
             Fn = L.slar_lomac_project(self.grid, Fs, U_new, self._frames(out_slot), self.ws)
             self.U_nm1, self.U_n = self.U_n, U_new
@@ -232,6 +240,15 @@ class Solver:
             self.state, self.state_slot = Fs, slot
         torch.cuda.synchronize()
         info["seconds"] = time.perf_counter() - t0
+        return self._finish(info)
+
+    def _finish(self, info):
+        if "converged" in info:
+            info["newton_log"] = self.macro_log[-1] if self.macro_log else []
+            if self.strict and not info["converged"]:
+                raise L.SlarError(L.SLAR_E_NOCONV, "macroscopic Newton solve of the step "
+                                  f"(final RMS residual {info['newton_log'][-1][0]:.3e})"
+                                  if info["newton_log"] else "macroscopic Newton solve of the step")
         return info
 
     # ---------------------------------------------------------- diagnostics
