@@ -252,7 +252,8 @@ slar_status slar_lomac_prepare(const slar_grid* g, const slar_ht* Fstar,
  *              mode inverse of the linear constant-coefficient part of the
  *              Jacobian (kinetic flux of the closure + linearised Poisson
  *              source);
- *           2: as 1 plus the learned convolutional correction cnn.
+ *           2: as 1 plus the learned convolutional correction cnn, with
+ *              plain GMRES as the fallback (slar_macro_fallbacks).
  * The converged answer is the same Newton root; only the iteration counts
  * change.  iters (host, int32[2]) receives Newton and Krylov counts.
  * Returns SLAR_E_NOCONV if Newton did not reach newton_tol.                 */
@@ -299,6 +300,15 @@ slar_status slar_macro_solve_system(const slar_grid* g, const slar_macro_system*
  * -1 on invalid arguments.  Host only; reflects the last solve that ran. */
 int32_t slar_macro_history(const slar_workspace* ws, double* out, int32_t cap);
 
+/* Fallback of the learned preconditioner: a solve with precond = 2 whose
+ * network-preconditioned attempt fails (a Newton step's linear solve not at
+ * krylov_tol within 100 iterations, no Newton convergence, a non-finite
+ * residual or a failed launch) is repeated from U(F*) with plain GMRES, and
+ * its status is the plain solve's.  Returns the number of solves on ws that
+ * fell back since it was created (-1 if ws is NULL); *last (host, may be
+ * NULL) is 1 if the last solve did.  Host only.                           */
+int32_t slar_macro_fallbacks(const slar_workspace* ws, int32_t* last);
+
 /* Right-hand side R(U) = D.F(U) - S(U) of the moment system U' = -R(U)
  * (eq. (BE_nonlinear_system) without the history), with the closure of the
  * last slar_lomac_prepare on ws (SLAR_E_INVAL if none).  U, R_out device
@@ -322,6 +332,20 @@ slar_status slar_dirk3_tableau(double* A, double* c);
  * 18/11, -9/11, 2/11 and 6h/11.  Host only; SLAR_E_INVAL unless the times
  * decrease strictly.                                                       */
 slar_status slar_bdf_weights(int32_t k, const double* t, double* c, double* beta);
+
+/* Band-limited LoMaC correction (a stabilisation of this implementation,
+ * not in the paper): U <- U(F*) + sigma (U - U(F*)) with U(F*) the
+ * conserved variables of the prepared closure and sigma the exponential
+ * filter prod_d exp(-36 kappa_d^36) of each x-mode (kappa_d = |m_d| /
+ * (n_d / 2), the mode index relative to the Nyquist index; sigma = 1 on
+ * the zero mode, below 1e-15 of a change for kappa <= 1/3).  The
+ * macroscopic and kinetic discretisations differ at the top x-modes
+ * (spectral flux divergence against SL interpolation); imposing the
+ * macroscopic top modes on the kinetic state let that mismatch grow from
+ * step to step at 128^2 x-cells.  Totals (mass, momentum, energy) are
+ * unchanged exactly.  U device [dv+2][Nx] FP64, in place; needs
+ * slar_lomac_prepare on ws.  Enqueued on stream.                          */
+slar_status slar_lomac_filter(const slar_grid* g, double* U, slar_workspace* ws, hipStream_t stream);
 
 /* LoMaC update eq. (LoMaC_update_discrete):
  *   F^{n+1} = F* - R(U(F*)) + R(U_new) = F* + sum_k dC_k (x) Q_k,

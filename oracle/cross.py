@@ -24,6 +24,14 @@ multi-index, columns: velocity multi-index, both row-major):
      exceeds tol ||S_k||_F / sqrt(nrows ncols), continue from the row of the
      largest such residual.
 
+Term cap: the cross may take up to kmax terms (min(2 rmax, 128) in the
+workloads).  If it stops at that cap before meeting its tolerance, the
+skeleton C W^-1 R (pivot columns C, pivot rows R, pivot block W) is
+replaced by C W_r^+ R, the pseudo-inverse of W truncated at the HT rank cap
+r = rmax (``cur_core``); a skeleton cut off by the cap has no error control,
+and its interpolation through W^-1 let the error grow from step to step on
+the strong-Landau workload, where the truncated core did not.
+
 Truncation (recompression + HT): QR of both factor sets, SVD of the small
 core, root rank = smallest r with tail sqrt(sum_{i>=r} s_i^2) <= theta,
 theta = tol ||F||_F / sqrt(2d-3) (one share of the error budget per tree
@@ -105,6 +113,28 @@ def aca(row_fn, col_fn, pts_fn, nrows: int, ncols: int, tol: float, kmax: int,
     V = np.stack(Vs, axis=1)
     info["rank"] = U.shape[1]
     return U, V, info
+
+
+def cur_core(U: np.ndarray, V: np.ndarray, pivots, rmax: int):
+    """Regularised skeleton of a cross that stopped at its term cap.
+
+    The cross U V^T interpolates its pivot rows I and columns J, so with the
+    sampled fibers C = A[:, J], R = A[I, :] and W = A[I, J] it equals
+    C W^-1 R.  When the cap was hit before the tolerance, W^-1 is replaced
+    by the pseudo-inverse of W truncated to its leading min(rmax, rank W)
+    singular triplets: A ~ C W_r^+ R, returned as factors (U', V') with
+    U' = C Z_r diag(1/s_r) and V' = R^T Y_r for W = Y diag(s) Z^T."""
+    I = np.array([p[0] for p in pivots], dtype=np.int64)
+    J = np.array([p[1] for p in pivots], dtype=np.int64)
+    C = U @ V[J].T               # A[:, J]: the cross reproduces its pivot columns
+    R = (U[I] @ V.T)             # A[I, :]
+    W = U[I] @ V[J].T            # A[I, J]
+    Y, s, Zt = np.linalg.svd(W)
+    r = int(min(rmax, np.count_nonzero(s > 1e-14 * s[0]))) if s[0] > 0 else 1
+    r = max(r, 1)
+    Uc = C @ (Zt[:r].T / s[:r][None, :])
+    Vc = R.T @ Y[:, :r]
+    return Uc, Vc
 
 
 def _probe_continue(Us, Vs, pts_fn, probes, tol, norm2, nrows, ncols, used, info) -> bool:

@@ -137,6 +137,29 @@ def project_dense(Ffull: np.ndarray, dx: int, B: dict, vgrids, dvol: float) -> n
     return expand(coefficients(np.stack(M), B), B["Q"])
 
 
+def mode_filter(n: int) -> np.ndarray:
+    """sigma(m) = exp(-36 kappa^36), kappa = |m| / (n / 2), for the FFT mode
+    indices 0..n-1 of an axis of n cells (|m| the distance to mode 0)."""
+    i = np.arange(n)
+    kap = np.minimum(i, n - i) / (0.5 * n)
+    return np.exp(-36.0 * kap ** 36)
+
+
+def filter_correction(U: np.ndarray, U0: np.ndarray) -> np.ndarray:
+    """Band-limited correction (a stabilisation of this implementation, not
+    in the paper): U0 + sigma (U - U0) per component, sigma the tensor
+    product of ``mode_filter`` over the x axes.  Mode 0 has sigma = 1, so
+    the totals of U are kept."""
+    d = U - U0
+    axes = tuple(range(1, U.ndim))
+    sig = 1.0
+    for a in axes:
+        shape = [1] * U.ndim
+        shape[a] = U.shape[a]
+        sig = sig * mode_filter(U.shape[a]).reshape(shape)
+    return U0 + np.real(np.fft.ifftn(sig * np.fft.fftn(d, axes=axes), axes=axes))
+
+
 def velocity_integrals(B: dict, psis, dvol: float) -> np.ndarray:
     """<psi, Q_k> = sum_v psi Q_k w^v for each psi: shape (npsi, K)."""
     Q = B["Q"]

@@ -83,7 +83,11 @@ class Oracle:
         def pts(I, J):
             return self.entries(F, self._idx(I, J), kind, tau, cv, E)
 
-        U, V, info = CR.aca(row, col, pts, nrows, ncols, self.p.tol, self.p.rmax, 0, self.probes)
+        kc = self.p.cross_cap
+        U, V, info = CR.aca(row, col, pts, nrows, ncols, self.p.tol, kc, 0, self.probes)
+        info["capped"] = (not info["converged"]) and U.shape[1] >= kc
+        if info["capped"] and U.shape[1] > self.p.rmax:
+            U, V = CR.cur_core(U, V, info["pivots"], self.p.rmax)
         Fn = CR.truncate_lowrank(U, V, self.nx, self.nv, self.p.tol, self.p.rmax)
         info["ranks"] = HT.ranks(Fn)
         self.stats.append(info)
@@ -141,6 +145,8 @@ class Oracle:
         sysm = MA.MacroSystem(Mstar, B, self.n_i, self.lengths, self.dvol_v, self.vgrids,
                               U_hist, beta_dt)
         U, info = MA.jfnk(sysm, U0, newton_tol=self.newton_tol, precond=precond, record=record)
+        if getattr(self.p, "lomac_filter", False):
+            U = LM.filter_correction(U, U0)
         Mraw = LM.raw_from_conserved(U, self.n_i, self.lengths)
         dC = LM.coefficients(Mraw, B) - sysm.Cstar
         Fn = dict(Fs)

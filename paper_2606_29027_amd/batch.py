@@ -22,7 +22,8 @@ import torch
 from . import lib as L
 
 KCAP = 72
-RCAP = 64
+RCAP = 64          # HT rank cap
+CCAP = 128         # cross-approximation terms
 
 
 class _Inst:
@@ -38,8 +39,8 @@ class _Inst:
         z = lambda *s: torch.zeros(*s, **f64)   # noqa: E731
         self.frames_buf = [(z(self.Nx, KCAP), z(self.Nv, KCAP)) for _ in range(4)]
         self.ht = [self._ht() for _ in range(2)]
-        self.U = z(RCAP, self.Nx)
-        self.V = z(RCAP, self.Nv)
+        self.U = z(CCAP, self.Nx)
+        self.V = z(CCAP, self.Nv)
         self.M = z(self.nmom, self.Nx)
         self.E = [z(p.dx, self.Nx) for _ in range(3)]
         self.n_i = None
@@ -84,6 +85,10 @@ class BatchSolver:
         self.dt = dts.pop()
         self.tol = tol if tol is not None else max(p.tol for p in self.problems)
         self.rmax = min(rmax if rmax is not None else max(p.rmax for p in self.problems), RCAP)
+        # the cross of every instance may run past the rank cap (the
+        # truncation caps the rank); the shared cap follows the same rule
+        self.kcross = min(2 * self.rmax, CCAP) if rmax is not None else \
+            min(max(p.cross_cap for p in self.problems), CCAP)
         self.batch = L.Batch([L.make_grid(p) for p in self.problems], self.rmax)
         self.inst = [_Inst(p) for p in self.problems]
         self.probes = None
@@ -127,7 +132,7 @@ class BatchSolver:
         return [I.E[e] for I in self.inst]
 
     def slar(self, src, advs, ht_slot, frame_slot):
-        lrs, info, _ = self.batch.cross_update(src, advs, self.tol, self.rmax, self.probes,
+        lrs, info, _ = self.batch.cross_update(src, advs, self.tol, self.kcross, self.probes,
                                                [I.U for I in self.inst], [I.V for I in self.inst])
         hts = [I.ht_desc(ht_slot) for I in self.inst]
         outs = [I.frames(frame_slot) for I in self.inst]
@@ -145,7 +150,7 @@ class BatchSolver:
         the current state (outputs are scratch)."""
         E1 = self.efield(self.state, 0)
         advs = [L.make_adv(2, self.dt / 3.0, 1.0, E) for E in E1]
-        return self.batch.tune(self.state, advs, self.tol, self.rmax, self.probes,
+        return self.batch.tune(self.state, advs, self.tol, self.kcross, self.probes,
                                [I.U for I in self.inst], [I.V for I in self.inst], reps)
 
     def step(self):

@@ -47,8 +47,9 @@ struct AcaInst {
   const int* probes;
   // index-table mode (nested cross searches): the matrix is nrows x ncols,
   // entry (row, col) is the grid point whose multi-index joins
-  // rowtab[4 row ..] and coltab[4 col ..] (entries < 0 unset); accepted
-  // pivots (row, col) are logged in piv[2 k ..]
+  // rowtab[4 row ..] and coltab[4 col ..] (entries < 0 unset).  In both
+  // modes accepted pivots (row, col) are logged in piv[2 k ..] when piv is
+  // set.
   int nrows = 0, ncols = 0;
   const int* rowtab = nullptr;
   const int* coltab = nullptr;
@@ -155,13 +156,16 @@ __device__ __forceinline__ void entry_index(const AcaInst& I, int row, int col, 
 
 // Partial-sum layout (doubles): part[q * ACA_MAXBLK + b]
 //   row kernel: q = 0 block max|r|, q = 1 block candidate index,
-//               q = 2 + l  v_l . r  (l <= k < 64), q = PVAL candidate |r|
+//               q = 2 + l  v_l . r  (l <= k < ACA_KC), q = PVAL candidate |r|
 //   col kernel: same with base PCOL
 //   q = GSUM: sum over row blocks of v_l . r at slot l (written by the
 //   column kernel, read by the bookkeeping kernel)
-constexpr int PCOL = SLAR_KMAX + 4;
-constexpr int PVAL = PCOL - 1;
-constexpr int GSUM = 66;
+constexpr int ACA_KC = SLAR_CROSS_KMAX;
+constexpr int PVAL = ACA_KC + 2;
+constexpr int GSUM = ACA_KC + 3;
+constexpr int PCOL = ACA_KC + 4;
+constexpr int ACA_PART_SLOTS = PCOL + PVAL + 1;
+static_assert(ACA_KC <= ACA_MAXBLK, "GSUM holds one slot per cross term");
 
 // Per-block max of |x| (entries with skip() excluded), the lowest index in
 // the block whose |x| is within the tie tolerance of that block max, and
@@ -236,9 +240,11 @@ struct SkipUsed {
 };
 
 // Earlier cross vectors at this thread's position, cached in registers:
-// slot m holds l = wave + 4 m (k <= 64, so m < 16).
+// slot m holds l = wave + 4 m for the first 64 terms; terms 64..127 (when
+// the cross runs past 64) are read in a second chunk, l = 64 + wave + 4 m.
 constexpr int ACA_LREG = 16;
-static_assert(4 * ACA_LREG >= 64, "register cache covers every earlier cross vector (kmax <= 64)");
+constexpr int ACA_CHUNK = 4 * ACA_LREG;
+static_assert(2 * ACA_CHUNK >= ACA_KC, "two chunks cover every cross term");
 
 template <typename T, int W, int DX, bool TAB = false>
 __device__ void aca_row_body(const AcaInst& I, int tile) {
@@ -290,6 +296,13 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
 #pragma unroll
     for (int m = 0; m < ACA_LREG; ++m)
       if (wv + 4 * m < k) acc += ui[m] * vl[m];
+    if (k > ACA_CHUNK) {
+#pragma unroll 4
+      for (int m = 0; m < ACA_LREG; ++m) {
+        const int l = ACA_CHUNK + wv + 4 * m;
+        if (l < k && ln < ns) acc += U[(size_t)l * Nx + i] * V[(size_t)l * Nv + J0 + ln];
+      }
+    }
     acc4[wv][ln] = acc;
   }
   __syncthreads();
@@ -315,6 +328,18 @@ __device__ void aca_row_body(const AcaInst& I, int tile) {
     const double p = wave_sum16_scatter(pv, ln);
     const int l = wv + 4 * scatter_slot(ln);
     if ((ln & 3) == 0 && l <= k) part[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+    if (k >= ACA_CHUNK) {
+      // second chunk of the dot products, l = 64 + wave + 4 m
+#pragma unroll
+      for (int m = 0; m < ACA_LREG; ++m) {
+        const int l2 = ACA_CHUNK + wv + 4 * m;
+        const double v2 = (l2 < k && ln < ns) ? V[(size_t)l2 * Nv + J0 + ln] : (l2 == k ? r_ : 0.0);
+        pv[m] = v2 * r_;
+      }
+      const double p2 = wave_sum16_scatter(pv, ln);
+      const int l2 = ACA_CHUNK + wv + 4 * scatter_slot(ln);
+      if ((ln & 3) == 0 && l2 <= k) part[(size_t)(2 + l2) * ACA_MAXBLK + tile] = p2;
+    }
   }
   block_candidate(rres, ns, J0, NoSkip{}, red, redi, &part[tile], &part[ACA_MAXBLK + tile],
                   &part[(size_t)PVAL * ACA_MAXBLK + tile]);
@@ -396,6 +421,13 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
 #pragma unroll
     for (int m = 0; m < ACA_LREG; ++m)
       if (wv + 4 * m < k) acc += vj[m] * ul[m];
+    if (k > ACA_CHUNK) {
+#pragma unroll 4
+      for (int m = 0; m < ACA_LREG; ++m) {
+        const int l = ACA_CHUNK + wv + 4 * m;
+        if (l < k && ln < ns) acc += V[(size_t)l * Nv + j] * U[(size_t)l * Nx + I0 + ln];
+      }
+    }
     acc4[wv][ln] = acc;
   }
   __syncthreads();
@@ -422,6 +454,17 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
     const double p = wave_sum16_scatter(pu, ln);
     const int l = wv + 4 * scatter_slot(ln);
     if ((ln & 3) == 0 && l <= k) pc[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+    if (k >= ACA_CHUNK) {
+#pragma unroll
+      for (int m = 0; m < ACA_LREG; ++m) {
+        const int l2 = ACA_CHUNK + wv + 4 * m;
+        const double x2 = (l2 < k && ln < ns) ? U[(size_t)l2 * Nx + I0 + ln] : (l2 == k ? u_ : 0.0);
+        pu[m] = x2 * u_;
+      }
+      const double p2 = wave_sum16_scatter(pu, ln);
+      const int l2 = ACA_CHUNK + wv + 4 * scatter_slot(ln);
+      if ((ln & 3) == 0 && l2 <= k) pc[(size_t)(2 + l2) * ACA_MAXBLK + tile] = p2;
+    }
   }
   block_candidate(ures, ns, I0, SkipUsed{used, i}, red, redi, &pc[tile], &pc[ACA_MAXBLK + tile],
                   &pc[(size_t)PVAL * ACA_MAXBLK + tile]);
@@ -454,7 +497,7 @@ __device__ void aca_fin_body(const AcaInst& I) {
   __shared__ FsLds<W, DX> L;
   __shared__ double red[4];
   __shared__ int redi[4];
-  __shared__ double sgv[SLAR_KMAX + 1], sgu[SLAR_KMAX + 1];
+  __shared__ double sgv[ACA_KC + 1], sgu[ACA_KC + 1];
   __shared__ double cmax_[FIN_NB], cidx_[FIN_NB], cval_[FIN_NB];
   __shared__ double res[1024];
   __shared__ int pi[1024];
@@ -487,39 +530,43 @@ __device__ void aca_fin_body(const AcaInst& I) {
   }
   if (!zero_row) {
     // gv[l]: reduced by the column launch; gu[l] = sum_b (u_l . u)_b here:
-    // wave w takes l = w + 4 m (m < 16), lanes run over the blocks, all
-    // loads are issued before the sums, then a butterfly reduce-scatter
-    // leaves the total of value m(lane) in every lane
+    // wave w takes l = w + 4 m (m < 16) of each 64-term chunk, lanes run
+    // over the blocks, all loads of a chunk are issued before the sums,
+    // then a butterfly reduce-scatter leaves the total of value m(lane) in
+    // every lane
     {
       const int wv = t >> 6, ln = t & 63;
-      double acc[16];
+      for (int c0 = 0; c0 <= k; c0 += ACA_CHUNK) {
+        double acc[16];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int l = min(wv + 4 * m, 63);
-        const double* q = pc + (size_t)(2 + l) * ACA_MAXBLK;
-        double a4 = 0.0;
+        for (int m = 0; m < 16; ++m) {
+          const int l = min(c0 + wv + 4 * m, ACA_KC - 1);
+          const double* q = pc + (size_t)(2 + l) * ACA_MAXBLK;
+          double a4 = 0.0;
 #pragma unroll
-        for (int i4 = 0; i4 < FIN_NB / 64; ++i4) {
-          const int b = ln + 64 * i4;
-          const double v = q[b];
-          a4 += (b < nbcol) ? v : 0.0;
+          for (int i4 = 0; i4 < FIN_NB / 64; ++i4) {
+            const int b = ln + 64 * i4;
+            const double v = q[b];
+            a4 += (b < nbcol) ? v : 0.0;
+          }
+          acc[m] = (c0 + wv + 4 * m <= k) ? a4 : 0.0;
         }
-        acc[m] = (wv + 4 * m <= k) ? a4 : 0.0;
+        const double tot = wave_sum16_scatter(acc, ln);
+        const int m = scatter_slot(ln);
+        const int l = c0 + wv + 4 * m;
+        if ((ln & 3) == 0 && l <= k) sgu[l] = tot;
       }
-      const double tot = wave_sum16_scatter(acc, ln);
-      const int m = scatter_slot(ln);
-      const int l = wv + 4 * m;
-      if ((ln & 3) == 0 && l <= k) sgu[l] = tot;
       if (t <= k) sgv[t] = part[(size_t)GSUM * ACA_MAXBLK + t];
     }
     __syncthreads();
     if (t < 64) {
-      // cross terms sum_{l<k} (u_l . u_k)(v_l . v_k), k < 64
+      // cross terms sum_{l<k} (u_l . u_k)(v_l . v_k), k < 128
       double c = (t < k) ? sgu[t] * sgv[t] : 0.0;
+      if (t + 64 < k) c += sgu[t + 64] * sgv[t + 64];
       c = wave_sum(c);
       if (t == 0) {
         ctl->samples += Nx;
-        if (TAB && I.piv) { I.piv[2 * k] = i; I.piv[2 * k + 1] = j; }
+        if (I.piv) { I.piv[2 * k] = i; I.piv[2 * k + 1] = j; }
         const double nk = sgu[k] * sgv[k];
         const double norm2 = s_norm2 + 2.0 * c + nk;
         ctl->norm2 = norm2;

@@ -26,6 +26,7 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
 slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, double tol,
                          int rmax, slar_ht* out);
 size_t aca_ctl_bytes();
+size_t aca_part_elems();
 size_t truncate_scratch_elems(const GridDev& G);
 }  // namespace slar
 
@@ -97,7 +98,7 @@ const char* slar_status_str(slar_status s) {
 slar_status slar_workspace_destroy(slar_workspace* w) {
   if (!w) return SLAR_OK;
   Workspace& ws = w->w;
-  void* dev[] = {ws.Eeff, ws.X32, ws.P32, ws.aca_ctl, ws.aca_part, ws.used, ws.resid, ws.dwork,
+  void* dev[] = {ws.Eeff, ws.X32, ws.P32, ws.aca_ctl, ws.aca_part, ws.aca_piv, ws.used, ws.resid, ws.dwork,
                  ws.small, ws.ismall, ws.tw[0], ws.tw[1], ws.cbuf, ws.psi, ws.lm, ws.kry,
                  ws.nest_U, ws.nest_V, ws.nest_used, ws.nest_rowtab, ws.nest_coltab, ws.nest_probes,
                  ws.nest_piv, ws.nest_idx, ws.nest_vals, ws.nest_small, ws.nest_flag, ws.nest_fX,
@@ -153,7 +154,8 @@ slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspa
   dalloc((void**)&ws.X32, sizeof(float) * G.nx * ws.ld32);
   dalloc((void**)&ws.P32, sizeof(float) * G.nv * ws.ld32);
   dalloc(&ws.aca_ctl, aca_ctl_bytes());
-  dalloc((void**)&ws.aca_part, sizeof(double) * (2 * (K + 4) + 4) * 1024);
+  dalloc((void**)&ws.aca_part, sizeof(double) * aca_part_elems());
+  dalloc((void**)&ws.aca_piv, sizeof(int) * 2 * SLAR_CROSS_KMAX);
   dalloc((void**)&ws.used, G.nx);
   dalloc((void**)&ws.dwork, sizeof(double) * ws.dwork_elems);
   dalloc((void**)&ws.small, sizeof(double) * ws.small_elems);
@@ -290,7 +292,7 @@ slar_status slar_cross_update(const slar_grid* g, const slar_frames* src, const 
                               slar_workspace* w, hipStream_t stream) {
   if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !frames_ok(src) || !adv_ok(g, a))
     return SLAR_E_INVAL;
-  if (!(tol > 0.0) || kmax < 1 || kmax > 64 || nprobe < 0 || nprobe > 1024) return SLAR_E_INVAL;
+  if (!(tol > 0.0) || kmax < 1 || kmax > SLAR_CROSS_KMAX || nprobe < 0 || nprobe > 1024) return SLAR_E_INVAL;
   if (nprobe > 0 && !probes) return SLAR_E_INVAL;
   if (!out || !out->U || !out->V) return SLAR_E_INVAL;
   if (dtype != SLAR_F32 && dtype != SLAR_F64) return SLAR_E_INVAL;
@@ -300,7 +302,8 @@ slar_status slar_cross_update(const slar_grid* g, const slar_frames* src, const 
 slar_status slar_truncate(const slar_grid* g, const slar_lowrank* in, double tol, int32_t rmax,
                           slar_ht* out, slar_workspace* w, hipStream_t stream) {
   if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !in || !in->U || !in->V) return SLAR_E_INVAL;
-  if (in->k < 1 || in->k > 64 || !(tol > 0.0) || rmax < 1 || rmax > 64 || !out) return SLAR_E_INVAL;
+  if (in->k < 1 || in->k > SLAR_CROSS_KMAX || !(tol > 0.0) || rmax < 1 || rmax > 64 || !out)
+    return SLAR_E_INVAL;
   const int d = g->dx + g->dv;
   for (int m = 0; m < d; ++m)
     if (!out->leaf[m]) return SLAR_E_INVAL;
@@ -437,6 +440,11 @@ slar_status slar_bdf_weights(int32_t k, const double* t, double* c, double* beta
   return SLAR_OK;
 }
 
+slar_status slar_lomac_filter(const slar_grid* g, double* U, slar_workspace* w, hipStream_t stream) {
+  if (!w || !grid_ok(g) || !same_grid(g, &w->w.grid) || !U) return SLAR_E_INVAL;
+  return lomac_filter_run(stream, &w->w, U);
+}
+
 slar_status slar_lomac_project(const slar_grid* g, const slar_frames* Fstar_frames,
                                const double* U_new, slar_frames* out, slar_workspace* w,
                                hipStream_t stream) {
@@ -451,7 +459,7 @@ slar_status slar_timing_enable(slar_workspace* w, int32_t on) {
   if (!w) return SLAR_E_INVAL;
   Workspace& ws = w->w;
   if (on && ws.events.empty()) {
-    const int need = 4 * (64 + 64);
+    const int need = 4 * (SLAR_CROSS_KMAX + 64);
     ws.events.resize(need);
     for (int i = 0; i < need; ++i)
       if (hipEventCreate(&ws.events[i]) != hipSuccess) {
@@ -477,6 +485,12 @@ int32_t slar_macro_history(const slar_workspace* w, double* out, int32_t cap) {
   const int n = std::min(w->w.newton_hist_n, (int)cap);
   for (int i = 0; i < 4 * n; ++i) out[i] = w->w.newton_hist[i];
   return w->w.newton_hist_n;
+}
+
+int32_t slar_macro_fallbacks(const slar_workspace* w, int32_t* last) {
+  if (!w) return -1;
+  if (last) *last = w->w.macro_fell_back ? 1 : 0;
+  return w->w.macro_fallbacks;
 }
 
 }  // extern "C"

@@ -338,6 +338,7 @@ static slar_status batch_cross(slar_batch* b, const slar_frames* src, const slar
     I.X = w.X32; I.P = w.P32; I.ld = ldt; I.r = r;
     I.ctl = (AcaCtl*)w.aca_ctl; I.U = out[q].U; I.V = out[q].V; I.used = w.used;
     I.part = w.aca_part; I.nbrow = b->nbrow[q]; I.nbcol = b->nbcol[q];
+    I.piv = w.aca_piv;
     I.nprobe = nprobe; I.team = b->team[bucket_of(r)];
     I.probes = nprobe > 0 ? probes[q] : nullptr;
   }
@@ -374,6 +375,15 @@ static slar_status batch_cross(slar_batch* b, const slar_frames* src, const slar
     }
     if (!std::isfinite(m.norm2)) st = SLAR_E_NUMERIC;
     else if ((m.capped || m.phase != ACA_DONE) && st == SLAR_OK) st = SLAR_E_RANK_CAP;
+  }
+  // instances stopped at the term cap: regularised skeleton (as slar_cross_update)
+  for (int q = 0; q < b->count && st != SLAR_E_NUMERIC; ++q) {
+    const BSummary& m = b->h_sum[q];
+    if ((m.capped || m.phase != ACA_DONE) && out[q].k > b->rmax) {
+      const slar_status sq = cur_core_run(s, &b->ws[q]->w, &out[q], b->rmax);
+      if (sq != SLAR_OK) return sq;
+      if (info) info[q].rank = out[q].k;
+    }
   }
   b->tstat[0] += ms; b->tstat[1] += chunks; b->tstat[2] += maxiters; b->tstat[3] += 1;
   return st;
@@ -523,7 +533,7 @@ slar_status slar_batch_cross_update(slar_batch* b, const slar_frames* src, const
                                     const int32_t* const* probes, slar_lowrank* out,
                                     slar_cross_info* info, hipStream_t stream) {
   if (!b || !src || !adv || !out || !batch_frames_ok(b, src)) return SLAR_E_INVAL;
-  if (!(tol > 0.0) || kmax < 1 || kmax > 64 || nprobe < 0 || nprobe > 1024) return SLAR_E_INVAL;
+  if (!(tol > 0.0) || kmax < 1 || kmax > SLAR_CROSS_KMAX || nprobe < 0 || nprobe > 1024) return SLAR_E_INVAL;
   if (nprobe > 0 && !probes) return SLAR_E_INVAL;
   for (int q = 0; q < b->count; ++q) {
     const slar_adv& a = adv[q];

@@ -24,20 +24,23 @@
 #include <hip/hip_ext.h>
 
 #include "aca.h"
+#include "dense.h"
 
 namespace slar {
 
 size_t aca_ctl_bytes() { return sizeof(AcaCtl); }
+size_t aca_part_elems() { return (size_t)ACA_PART_SLOTS * ACA_MAXBLK; }
 
 template <typename T, int W, int DX>
 static hipError_t aca_iterate(hipStream_t s, const GridDev& G, const AdvDev& A, const T* X,
                               const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
                               unsigned char* used, double* part, int nprobe, const int* probes,
-                              hipEvent_t* ev, int* phase_dev) {
+                              hipEvent_t* ev, int* phase_dev, int* piv) {
   const unsigned bRow = (G.nv + ACA_TILE - 1) / ACA_TILE;
   const unsigned bCol = (G.nx + ACA_TILE - 1) / ACA_TILE;
   AcaInst I{G, A, X, P, ld, r, ctl, U, V, used, part, (int)bRow, (int)bCol, nprobe, 16, probes};
   I.phase_host = phase_dev;
+  I.piv = piv;
   if (ev) {
     // events attached to the dispatches themselves: start and end of the
     // kernel, without marker packets between the launches
@@ -55,13 +58,13 @@ template <typename T>
 static hipError_t aca_iter_dispatch(hipStream_t s, const GridDev& G, const AdvDev& A, const T* X,
                                     const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
                                     unsigned char* used, double* part, int nprobe,
-                                    const int* probes, hipEvent_t* ev, int* phase_dev) {
+                                    const int* probes, hipEvent_t* ev, int* phase_dev, int* piv) {
   if (G.dx == 1) {
     if (A.order == 5)
-      return aca_iterate<T, 5, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev);
-    return aca_iterate<T, 3, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev);
+      return aca_iterate<T, 5, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, piv);
+    return aca_iterate<T, 3, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, piv);
   }
-  return aca_iterate<T, 3, 2>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev);
+  return aca_iterate<T, 3, 2>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, piv);
 }
 
 hipError_t table_copy(hipStream_t s, int rows, int r, int ldin, const double* in, int ldo,
@@ -118,11 +121,11 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
       if (dt == SLAR_F32)
         e = aca_iter_dispatch<float>(s, G, A, ws->X32, ws->P32, ldt, r, ctl, out->U, out->V,
                                      ws->used, ws->aca_part, nprobe, probes,
-                                     timed(it) ? &ws->events[4 * it] : nullptr, ws->phase_dev);
+                                     timed(it) ? &ws->events[4 * it] : nullptr, ws->phase_dev, ws->aca_piv);
       else
         e = aca_iter_dispatch<double>(s, G, A, X64, P64, ldt, r, ctl, out->U, out->V, ws->used,
                                       ws->aca_part, nprobe, probes,
-                                      timed(it) ? &ws->events[4 * it] : nullptr, ws->phase_dev);
+                                      timed(it) ? &ws->events[4 * it] : nullptr, ws->phase_dev, ws->aca_piv);
       if (e != hipSuccess) return SLAR_E_HIP;
     }
     HIP_TRY(hipEventRecord(ws->poll_ev[c & 1], s));
@@ -156,7 +159,87 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
     info->samples = hc->samples;
   }
   if (!std::isfinite(hc->norm2)) return SLAR_E_NUMERIC;
-  if (hc->capped || hc->phase != ACA_DONE) return SLAR_E_RANK_CAP;
+  if (hc->capped || hc->phase != ACA_DONE) {
+    // stopped at the term cap: the skeleton's pivot block gets a
+    // pseudo-inverse truncated at the workspace's rank cap
+    if (out->k > ws->rmax) {
+      const slar_status st = cur_core_run(s, ws, out, ws->rmax);
+      if (st != SLAR_OK) return st;
+      if (info) info->rank = out->k;
+    }
+    return SLAR_E_RANK_CAP;
+  }
+  return SLAR_OK;
+}
+
+// Ui[l][m] = u_m[i_l], Vjt[l][m] = v_m[j_l] for the logged pivots (i_l, j_l)
+__global__ void k_cur_gather(int k, const double* __restrict__ U, int Nx, const double* __restrict__ V,
+                             int Nv, const int* __restrict__ piv, double* __restrict__ Ui,
+                             double* __restrict__ Vjt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int l = e / k, m = e % k;
+  Ui[e] = U[(size_t)m * Nx + piv[2 * l]];
+  Vjt[e] = V[(size_t)m * Nv + piv[2 * l + 1]];
+}
+
+// The k terms of a capped cross are U^T V = C W^-1 R with the pivot
+// columns C = U^T Vjt^T, the pivot rows R = Ui V and the pivot block
+// W = Ui Vjt^T.  With W = Y diag(s) Z^T and r = min(rcap, #{s > 1e-14 s_1})
+// the regularised skeleton C Z_r diag(s_r)^-1 Y_r^T R is returned as the r
+// terms U' = (Z_r diag(s_r)^-1)^T Vjt U and V' = Y_r^T Ui V.
+slar_status cur_core_run(hipStream_t s, Workspace* ws, slar_lowrank* out, int rcap) {
+  const GridDev& G = ws->G;
+  const int k = out->k, Nx = G.nx, Nv = G.nv;
+  double* U = out->U;
+  double* V = out->V;
+  double* p = ws->small;
+  double* Ui = p; p += (size_t)k * k;
+  double* Vjt = p; p += (size_t)k * k;
+  double* W = p; p += (size_t)k * k;
+  double* Y = p; p += (size_t)k * k;
+  double* Z = p; p += (size_t)k * k;
+  double* sv = p; p += k;
+  double* Pm = p; p += (size_t)k * k;
+  double* Qm = p; p += (size_t)k * k;
+  double* Ut = p; p += (size_t)k * Nx;
+  double* Vt = p; p += (size_t)k * Nv;
+  k_cur_gather<<<(k * k + 255) / 256, 256, 0, s>>>(k, U, Nx, V, Nv, ws->aca_piv, Ui, Vjt);
+  HIP_TRY(hipGetLastError());
+  if (gemm_f64(s, false, true, k, k, k, 1.0, Ui, k, 0, Vjt, k, 0, 0.0, W, k, 0, 1) != hipSuccess)
+    return SLAR_E_HIP;
+  const bool big = k > 64;
+  if (big) {
+    if (svd_left_big(s, k, W, Y, sv) != hipSuccess) return SLAR_E_HIP;
+  } else if (svd_small(s, k, W, Y, sv, Z) != hipSuccess) {
+    return SLAR_E_HIP;
+  }
+  double* hs = (double*)ws->host_pinned;
+  HIP_TRY(hipMemcpyAsync(hs, sv, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!(hs[0] > 0.0) || !std::isfinite(hs[0])) return SLAR_E_NUMERIC;
+  int r = 0;
+  while (r < k && r < rcap && hs[r] > 1e-14 * hs[0]) ++r;
+  r = std::max(r, 1);
+  if (big) {
+    // right vectors of the kept triplets: Z_r = W^T Y_r diag(s_r)^-1
+    if (gemm_f64(s, true, false, k, r, k, 1.0, W, k, 0, Y, k, 0, 0.0, Z, k, 0, 1) != hipSuccess)
+      return SLAR_E_HIP;
+    if (scale_cols_inv(s, k, r, Z, k, sv) != hipSuccess) return SLAR_E_HIP;
+  }
+  if (scale_cols_inv(s, k, r, Z, k, sv) != hipSuccess) return SLAR_E_HIP;   // Z_r diag(s_r)^-1
+  if (gemm_f64(s, true, false, r, k, k, 1.0, Z, k, 0, Vjt, k, 0, 0.0, Pm, k, 0, 1) != hipSuccess)
+    return SLAR_E_HIP;
+  if (gemm_f64(s, true, false, r, k, k, 1.0, Y, k, 0, Ui, k, 0, 0.0, Qm, k, 0, 1) != hipSuccess)
+    return SLAR_E_HIP;
+  if (gemm_f64(s, false, false, r, Nx, k, 1.0, Pm, k, 0, U, Nx, 0, 0.0, Ut, Nx, 0, 1) != hipSuccess)
+    return SLAR_E_HIP;
+  if (gemm_f64(s, false, false, r, Nv, k, 1.0, Qm, k, 0, V, Nv, 0, 0.0, Vt, Nv, 0, 1) != hipSuccess)
+    return SLAR_E_HIP;
+  HIP_TRY(hipMemcpyAsync(U, Ut, sizeof(double) * r * Nx, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(V, Vt, sizeof(double) * r * Nv, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->k = r;
   return SLAR_OK;
 }
 

@@ -12,6 +12,10 @@ hipError_t gram_rows(hipStream_t s, const Scratch& part, int k, int n, const dou
 hipError_t gram_mode2(hipStream_t s, const Scratch& part, int na, int nb, int r, const double* X, double* G);
 hipError_t chol_inv(hipStream_t s, int k, const double* G, double* Linv, double* R, const double* Rprev);
 hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z);
+// left singular vectors / values for 64 < k <= 128 (right vectors not formed)
+hipError_t svd_left_big(hipStream_t s, int k, const double* M, double* W, double* sv);
+// Z[:, j] /= sv[j] for j < r (Z row-major, k rows, leading dimension ld)
+hipError_t scale_cols_inv(hipStream_t s, int k, int r, double* Z, int ld, const double* sv);
 hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* const* G,
                          double* const* lam, double* const* V);
 hipError_t sign_fix(hipStream_t s, int rows, int cols, double* A, int lda, double* B, int ldb, int rowsB);

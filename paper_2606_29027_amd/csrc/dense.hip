@@ -279,9 +279,79 @@ __global__ __launch_bounds__(256) void k_chol_inv(int k, const double* __restric
   }
 }
 
+// The same factorisation for SLAR_KMAX < k <= 128 (cross approximations
+// that ran past the HT rank cap) in one LDS array: L in the lower
+// triangle, L^-1 transposed in the strict upper triangle (Li[i][j] at
+// A[j][i], i > j) with its diagonal in li_d; Rprev is read from global
+// memory.  Same arithmetic and summation order as k_chol_inv.
+constexpr int CHOL_BIG = SLAR_CROSS_KMAX;
+__global__ __launch_bounds__(256) void k_chol_inv_big(int k, const double* __restrict__ G,
+                                                      double* __restrict__ Linv, double* __restrict__ R,
+                                                      const double* __restrict__ Rprev) {
+  __shared__ double A[CHOL_BIG][CHOL_BIG + 1];
+  __shared__ double d[CHOL_BIG], tcol[CHOL_BIG], li_d[CHOL_BIG];
+  const int t = threadIdx.x;
+  for (int i = t; i < k; i += blockDim.x) {
+    const double g = G[i * k + i];
+    d[i] = g > 0.0 ? sqrt(g) : 1.0;
+  }
+  __syncthreads();
+  for (int e = t; e < k * k; e += blockDim.x) {
+    const int i = e / k, j = e % k;
+    if (j <= i) A[i][j] = G[e] / (d[i] * d[j]);
+  }
+  __syncthreads();
+  const int sub = t & 3;
+  for (int c = 0; c < k; ++c) {
+    for (int i = c + (t >> 2); i < k; i += blockDim.x >> 2) {
+      double sm = 0.0;
+      for (int m = sub; m < c; m += 4) sm += A[i][m] * A[c][m];
+      sm += dpp_move<0xB1>(sm);
+      sm += dpp_move<0x4E>(sm);
+      if (sub == 0) tcol[i] = A[i][c] - sm;
+    }
+    __syncthreads();
+    const double v = tcol[c];
+    const double dc = v > 1e-300 ? sqrt(v) : 1.0;
+    for (int i = c + t; i < k; i += blockDim.x) A[i][c] = (i == c) ? dc : tcol[i] / dc;
+    __syncthreads();
+  }
+  // forward substitution per column j (a quad of lanes), into the upper triangle
+  for (int j = t >> 2; j < k; j += blockDim.x >> 2) {
+    if (sub == 0) li_d[j] = 1.0 / A[j][j];
+    for (int i = j + 1; i < k; ++i) {
+      double sm = 0.0;
+      for (int m = j + sub; m < i; m += 4) sm += A[i][m] * (m == j ? li_d[j] : A[j][m]);
+      sm += dpp_move<0xB1>(sm);
+      sm += dpp_move<0x4E>(sm);
+      if (sub == 0) A[j][i] = -sm / A[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < k * k; e += blockDim.x) {
+    const int i = e / k, j = e % k;
+    const double li = (i == j) ? li_d[i] : (i > j ? A[j][i] : 0.0);
+    Linv[e] = li / d[j];
+    if (Rprev == nullptr) R[e] = (i <= j) ? A[j][i == j ? j : i] * d[j] : 0.0;
+  }
+  if (Rprev != nullptr) {
+    // R_total = (L^T D) Rprev, (L^T D)[i][m] = L[m][i] d[m] for m >= i
+    for (int e = t; e < k * k; e += blockDim.x) {
+      const int i = e / k, j = e % k;
+      double acc = 0.0;
+      for (int m = i; m < k; ++m) acc += (m == i ? A[i][i] : A[m][i]) * d[m] * Rprev[(size_t)m * k + j];
+      R[e] = acc;
+    }
+  }
+}
+
 hipError_t chol_inv(hipStream_t s, int k, const double* G, double* Linv, double* R,
                     const double* Rprev) {
-  k_chol_inv<<<1, 256, 0, s>>>(k, G, Linv, R, Rprev);
+  if (k < 1 || k > SLAR_CROSS_KMAX) return hipErrorInvalidValue;
+  if (k <= SLAR_KMAX)
+    k_chol_inv<<<1, 256, 0, s>>>(k, G, Linv, R, Rprev);
+  else
+    k_chol_inv_big<<<1, 256, 0, s>>>(k, G, Linv, R, Rprev);
   return hipGetLastError();
 }
 
@@ -505,6 +575,78 @@ __global__ __launch_bounds__(512) void k_svd_jacobi(int k, const double* __restr
 hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z) {
   if (k < 1 || k > SVD_KM) return hipErrorInvalidValue;
   k_svd_jacobi<<<1, 512, 0, s>>>(k, M, W, sv, Z);
+  return hipGetLastError();
+}
+
+// Left singular vectors and values of M (k x k, row-major, SVD_KM < k <=
+// 128): one-sided Jacobi on the columns of M in LDS (1024 threads, one
+// 16-lane team per pair of 128 columns); the rotated columns, normalised
+// and sorted by norm (descending, ties by index), are the left singular
+// vectors, their norms the singular values.  The right vectors are not
+// accumulated: the caller forms the ones it keeps as M^T w / s.
+constexpr int SVD_BIG = SLAR_CROSS_KMAX;
+__global__ __launch_bounds__(1024) void k_svd_left_big(int k, const double* __restrict__ Min,
+                                                       double* __restrict__ W, double* __restrict__ sv) {
+  __shared__ double A[SVD_BIG * SVD_BIG];   // column c at A + c * SVD_BIG
+  __shared__ double nrm[SVD_BIG];
+  __shared__ int order[SVD_BIG];
+  __shared__ double red[16];
+  __shared__ int s_rot[2];
+  const int t = threadIdx.x;
+  const int kp = (k + 1) & ~1;
+  double part = 0.0;
+  for (int e = t; e < kp * kp; e += blockDim.x) {
+    const int c = e / kp, r = e % kp;
+    const double v = (r < k && c < k) ? Min[r * k + c] : 0.0;
+    A[c * SVD_BIG + r] = v;
+    part += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((t & 63) == 0) red[t >> 6] = part;
+  __syncthreads();
+  double fro = 0.0;
+  for (int w = 0; w < 16; ++w) fro += red[w];
+  const double floor_abs = 1e-300 + 1e-22 * fro;
+  const double orth = 4.0 * kp * 2.220446049250313e-16;
+  jacobi_cols<8, 0>(A, SVD_BIG, kp, kp, nullptr, 0, 0, orth, floor_abs, 60, nrm, s_rot);
+  for (int c = t; c < kp; c += blockDim.x) {
+    double acc = 0.0;
+    for (int r = 0; r < kp; ++r) acc += A[c * SVD_BIG + r] * A[c * SVD_BIG + r];
+    nrm[c] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int c = t; c < kp; c += blockDim.x) {
+    int rank = 0;
+    for (int o = 0; o < kp; ++o)
+      if (nrm[o] > nrm[c] || (nrm[o] == nrm[c] && o < c)) ++rank;
+    order[rank] = c;
+  }
+  __syncthreads();
+  for (int e = t; e < k * k; e += blockDim.x) {
+    const int r = e / k, j = e % k;
+    const int c = order[j];
+    W[e] = nrm[c] > 0.0 ? A[c * SVD_BIG + r] / nrm[c] : (r == j ? 1.0 : 0.0);
+  }
+  for (int j = t; j < k; j += blockDim.x) sv[j] = nrm[order[j]];
+}
+
+hipError_t svd_left_big(hipStream_t s, int k, const double* M, double* W, double* sv) {
+  if (k <= SVD_KM || k > SVD_BIG) return hipErrorInvalidValue;
+  k_svd_left_big<<<1, 1024, 0, s>>>(k, M, W, sv);
+  return hipGetLastError();
+}
+
+// Z[:, j] *= 1 / sv[j] (0 where sv[j] == 0), Z row-major k x ld, j < r
+__global__ void k_scale_cols_inv(int k, int r, double* __restrict__ Z, int ld, const double* __restrict__ sv) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * r) return;
+  const int i = e / r, j = e % r;
+  const double s = sv[j];
+  Z[(size_t)i * ld + j] = s > 0.0 ? Z[(size_t)i * ld + j] / s : 0.0;
+}
+
+hipError_t scale_cols_inv(hipStream_t s, int k, int r, double* Z, int ld, const double* sv) {
+  k_scale_cols_inv<<<(k * r + 255) / 256, 256, 0, s>>>(k, r, Z, ld, sv);
   return hipGetLastError();
 }
 

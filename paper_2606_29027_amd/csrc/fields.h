@@ -12,10 +12,11 @@ hipError_t spectral_symbol(hipStream_t s, Workspace* ws, int op, int nvec, const
 // Spectral stage: Bin real fields [Bin][Nx] -> one pointwise map per
 // Fourier mode -> Bout real fields [Bout][Nx] (op, Bin -> Bout):
 // SPEC_POISSON 1 -> 1 + dx (phi, E), SPEC_DTPHI dx -> dx (grad dt phi),
-// SPEC_DIV K dx -> K, SPEC_PRECOND K -> K (Minv [K][K][Nx] complex).
+// SPEC_DIV K dx -> K, SPEC_PRECOND K -> K (Minv [K][K][Nx] complex),
+// SPEC_FILTER K -> K (exponential filter sigma(m0) sigma(m1) per mode).
 // scr holds 20 Nx complex values.  Power-of-two grids run the axis-1
 // forward pass, one fused axis-0 launch and the axis-1 inverse pass.
-enum SpecOp { SPEC_POISSON = 0, SPEC_DTPHI = 1, SPEC_DIV = 2, SPEC_PRECOND = 3 };
+enum SpecOp { SPEC_POISSON = 0, SPEC_DTPHI = 1, SPEC_DIV = 2, SPEC_PRECOND = 3, SPEC_FILTER = 4 };
 hipError_t spectral_stage(hipStream_t s, Workspace* ws, int op, const double* in, double* out,
                           const double2* Minv, double2* scr);
 hipError_t poisson_run(hipStream_t s, Workspace* ws, const double* n_e, double n_i, double* phi, double* E);

@@ -236,13 +236,29 @@ hipError_t spectral_symbol(hipStream_t s, Workspace* ws, int op, int nvec, const
 //   SPEC_DIV      F[q][m] -> sum_m i k_m F[q][m]
 //   SPEC_PRECOND  x_b -> sum_b Minv[a][b] x_b (per-mode K x K inverse; the
 //                 modes stored transposed, pm = i1 n0 + i0 for p = i0 n1 + i1)
+//   SPEC_FILTER   x_q -> sigma x_q, sigma = prod_d exp(-36 kappa_d^36),
+//                 kappa_d = |m_d| / (n_d / 2) the mode index of axis d
+//                 relative to the Nyquist index (1 on the zero mode)
 // Null modes (|k| = 0) and Nyquist wavenumbers map to zero as in k_symbol.
 constexpr int SPEC_MAXIN = 8, SPEC_MAXOUT = 4;
 
+// one axis of the exponential filter, from the mode index i of n cells
+__device__ __forceinline__ double filt_axis(int i, int n) {
+  if (n <= 1) return 1.0;
+  const int m = i < n - i ? i : n - i;
+  const double kap = (double)m / (0.5 * n);
+  double k2 = kap * kap, k4 = k2 * k2, k8 = k4 * k4, k16 = k8 * k8, k32 = k16 * k16;
+  return exp(-36.0 * k32 * k4);
+}
+
 __device__ __forceinline__ void spec_map(int op, int dx, int K, const double* k, const double2* x,
                                          double2* y, const double2* __restrict__ Minv, long long pm,
-                                         int Nx) {
+                                         int Nx, double sigma) {
   const double k2 = k[0] * k[0] + k[1] * k[1];
+  if (op == SPEC_FILTER) {
+    for (int q = 0; q < K; ++q) y[q] = make_double2(sigma * x[q].x, sigma * x[q].y);
+    return;
+  }
   if (op == SPEC_POISSON) {
     const double2 ph = k2 > 0.0 ? make_double2(x[0].x / k2, x[0].y / k2) : make_double2(0.0, 0.0);
     y[0] = ph;
@@ -318,7 +334,8 @@ __global__ __launch_bounds__(256) void k_spec_line(Kgrid Kg, int op, int K, int 
     kvec(Kg, p, k);
     double2 x[SPEC_MAXIN], y[SPEC_MAXOUT];
     for (int f = 0; f < Bin; ++f) x[f] = a[f * L + e];
-    spec_map(op, Kg.dx, K, k, x, y, Minv, (long long)other * L + e, Nx);
+    const double sg = (op == SPEC_FILTER) ? filt_axis(e, Kg.n0) * (Kg.dx == 2 ? filt_axis(other, n1) : 1.0) : 1.0;
+    spec_map(op, Kg.dx, K, k, x, y, Minv, (long long)other * L + e, Nx, sg);
     const int r = __brev((unsigned)e) >> (32 - logL);
     for (int g = 0; g < Bout; ++g) b[g * L + r] = y[g];
   }
@@ -341,7 +358,9 @@ __global__ void k_spec_point(Kgrid Kg, int op, int K, int Bin, int Bout, const d
   kvec(Kg, p, k);
   double2 x[SPEC_MAXIN], y[SPEC_MAXOUT];
   for (int f = 0; f < Bin; ++f) x[f] = in[(size_t)f * Nx + p];
-  spec_map(op, Kg.dx, K, k, x, y, Minv, (long long)(p % Kg.n1) * Kg.n0 + p / Kg.n1, Nx);
+  const double sg = (op == SPEC_FILTER)
+                        ? filt_axis(p / Kg.n1, Kg.n0) * (Kg.dx == 2 ? filt_axis(p % Kg.n1, Kg.n1) : 1.0) : 1.0;
+  spec_map(op, Kg.dx, K, k, x, y, Minv, (long long)(p % Kg.n1) * Kg.n0 + p / Kg.n1, Nx, sg);
   for (int g = 0; g < Bout; ++g) out[(size_t)g * Nx + p] = y[g];
 }
 

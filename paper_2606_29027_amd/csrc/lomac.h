@@ -6,12 +6,16 @@ namespace slar {
 constexpr int KRY_RESTART = 50;     // GMRES restart length
 constexpr int KRY_MAXIT = 500;      // Krylov iterations per Newton step
 constexpr int KRY_MAX_NEWTON = 30;
+// Krylov iterations per Newton step after which a solve preconditioned by
+// the learned network is abandoned for plain GMRES
+constexpr int KRY_LEARNED_LIMIT = 100;
 
 struct LmLayout {
   size_t gs, scal, Q, psiQ, Mstar, Cstar, U0, Aflux, total;
 };
 LmLayout lm_layout(const GridDev& G);
 size_t kry_elems_for(int Nx, int K, int m);
+slar_status lomac_filter_run(hipStream_t s, Workspace* ws, double* U);
 slar_status lomac_prepare_run(hipStream_t s, Workspace* ws, const slar_ht& Fs,
                               const slar_frames& Ff, double delta, double n_i);
 hipError_t macro_residual(hipStream_t s, Workspace* ws, const double* U, const double* Uhist,

@@ -666,9 +666,13 @@ hipError_t macro_rhs(hipStream_t s, Workspace* ws, const double* U, double* Rout
   return macro_residual(s, ws, U, U, 1.0, Rout);
 }
 
-slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist, double beta,
-                            double newton_tol, double krylov_tol, int precond,
-                            const slar_cnn* cnn, double* Uout, int* iters) {
+// One JFNK solve with the given preconditioner, from U(F*).  kry_limit
+// bounds the Krylov iterations of each Newton step: a linear solve that
+// does not reach krylov_tol within it ends the whole solve with
+// SLAR_E_NOCONV.
+static slar_status macro_solve_once(hipStream_t s, Workspace* ws, const MacroHist& hist, double beta,
+                                    double newton_tol, double krylov_tol, int precond,
+                                    const slar_cnn* cnn, double* Uout, int* iters, int kry_limit) {
   if (!ws->lm_ready) return SLAR_E_INVAL;
   const GridDev& G = ws->G;
   const int K = G.dv + 2, Nx = G.nx, n = K * Nx;
@@ -726,7 +730,7 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
     k_axpby<<<nb, 256, 0, s>>>(n, -1.0, b.g0, 0.0, b.r, 0.0, nullptr);
     int kits = 0;
     bool done = false;
-    while (!done && kits < KRY_MAXIT) {
+    while (!done && kits < kry_limit) {
       k_axpby<<<nb, 256, 0, s>>>(n, 1.0 / beta, b.r, 0.0, b.V, 0.0, nullptr);
       std::fill(H.begin(), H.end(), 0.0);
       std::fill(gv.begin(), gv.end(), 0.0);
@@ -783,7 +787,7 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
         gv[j] = cs[j] * gv[j];
         ++kits;
         jl = j;
-        if (std::fabs(gv[j + 1]) <= krylov_tol * bn || kits >= KRY_MAXIT || den == 0.0) break;
+        if (std::fabs(gv[j + 1]) <= krylov_tol * bn || kits >= kry_limit || den == 0.0) break;
       }
       const int kk = jl + 1;
       for (int i = kk - 1; i >= 0; --i) {
@@ -810,6 +814,11 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
     }
     rec[1] = kits;
     krylov += kits;
+    if (!done && kry_limit < KRY_MAXIT) {
+      // a preconditioned linear solve that stalls: give up on this solve
+      if (iters) { iters[0] = newton; iters[1] = krylov; }
+      return SLAR_E_NOCONV;
+    }
     // exact step on the per-component mean
     k_comp_means<<<K, 256, 0, s>>>(Nx, b.d, b.g0, means);
     k_meanfix<<<nb, 256, 0, s>>>(Nx, K, means, means + 8, b.d);
@@ -820,6 +829,55 @@ slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist,
   HIP_TRY(hipStreamSynchronize(s));
   if (iters) { iters[0] = newton; iters[1] = krylov; }
   return converged ? SLAR_OK : SLAR_E_NOCONV;
+}
+
+// The learned preconditioner has plain GMRES as its fallback: when the
+// network's solve fails (a stalled linear solve, no Newton convergence, a
+// non-finite value, a failed launch), the system is solved again from
+// U(F*) without preconditioning.  The answer is judged by the same Newton
+// tolerance either way; iteration counts include the failed attempt.
+slar_status macro_solve_run(hipStream_t s, Workspace* ws, const MacroHist& hist, double beta,
+                            double newton_tol, double krylov_tol, int precond,
+                            const slar_cnn* cnn, double* Uout, int* iters) {
+  ws->macro_fell_back = false;
+  if (precond != 2)
+    return macro_solve_once(s, ws, hist, beta, newton_tol, krylov_tol, precond, cnn, Uout, iters,
+                            KRY_MAXIT);
+  int it1[2] = {0, 0};
+  slar_status st = macro_solve_once(s, ws, hist, beta, newton_tol, krylov_tol, 2, cnn, Uout, it1,
+                                    KRY_LEARNED_LIMIT);
+  if (st == SLAR_OK || st == SLAR_E_INVAL) {
+    if (iters) { iters[0] = it1[0]; iters[1] = it1[1]; }
+    return st;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipGetLastError();
+  ++ws->macro_fallbacks;
+  ws->macro_fell_back = true;
+  int it2[2] = {0, 0};
+  st = macro_solve_once(s, ws, hist, beta, newton_tol, krylov_tol, 0, nullptr, Uout, it2, KRY_MAXIT);
+  if (iters) { iters[0] = it1[0] + it2[0]; iters[1] = it1[1] + it2[1]; }
+  return st;
+}
+
+// ------------------------------------------------- correction filter
+// U <- U(F*) + sigma (U - U(F*)) with the exponential mode filter of
+// SPEC_FILTER: the LoMaC correction acts on the resolved band of x-modes
+// and leaves the kinetic solution's top modes to the kinetic update.  The
+// zero mode is untouched (sigma = 1), so the totals of U are kept exactly.
+slar_status lomac_filter_run(hipStream_t s, Workspace* ws, double* U) {
+  if (!ws->lm_ready) return SLAR_E_INVAL;
+  const GridDev& G = ws->G;
+  const int K = G.dv + 2, Nx = G.nx, n = K * Nx;
+  const LmLayout L = lm_layout(G);
+  const double* U0 = ws->lm + L.U0;
+  KryBufs b = kry_bufs(ws, n, KRY_RESTART);
+  const unsigned nb = (n + 255) / 256;
+  k_axpby<<<nb, 256, 0, s>>>(n, 1.0, U, 0.0, b.Uh, -1.0, U0);          // d = U - U0
+  HIP_TRY(spectral_stage(s, ws, SPEC_FILTER, b.Uh, b.Gh, nullptr, (double2*)ws->cbuf + (size_t)24 * Nx));
+  k_axpby<<<nb, 256, 0, s>>>(n, 1.0, U0, 0.0, U, 1.0, b.Gh);           // U = U0 + sigma d
+  HIP_TRY(hipGetLastError());
+  return SLAR_OK;
 }
 
 // --------------------------------------------------------------- project

@@ -9,7 +9,8 @@
 #include "../../include/slar.h"
 #include "sl_device.h"
 
-#define SLAR_KMAX 72      // largest cross rank / frame width handled
+#define SLAR_KMAX 72      // largest frame width (HT rank cap 64 + LoMaC columns)
+#define SLAR_CROSS_KMAX 128  // largest number of cross-approximation terms
 #define SLAR_NMAX 128     // largest cells per dimension of a 2D2V grid
 #define SLAR_NMAX_1D 512  // largest cells per dimension of a 1D1V grid
 #define SLAR_NLINE 512    // longest 1D line: FFT lines, 1D velocity bases
@@ -48,6 +49,7 @@ struct Workspace {
   int* phase_host = nullptr;       // host-mapped pinned word: cross phase written by the device
   int* phase_dev = nullptr;        // its device address
   double* aca_part = nullptr;    // partial reductions
+  int* aca_piv = nullptr;        // [2 SLAR_CROSS_KMAX] accepted pivots (row, col)
   unsigned char* used = nullptr; // [Nx]
   double* resid = nullptr;       // [max(Nx,Nv)]
   // dense linear algebra scratch
@@ -76,6 +78,10 @@ struct Workspace {
   // {RMS residual, Krylov iterations, true GMRES residual / ||G||, restarts}
   double newton_hist[4 * 32];
   int newton_hist_n = 0;
+  // learned-preconditioner solves that fell back to plain GMRES (count
+  // since creation; whether the last solve did)
+  int macro_fallbacks = 0;
+  bool macro_fell_back = false;
   // second stream (default priority) for independent chains inside a call,
   // joined back before the call returns; fork_aux = false keeps every chain
   // on the caller's stream (batched instances: the pool already overlaps
@@ -130,6 +136,9 @@ slar_status nested_run(hipStream_t s, Workspace* ws, const slar_frames& src, con
 // destroys the rocBLAS handle of stream s (before the library destroys s)
 void blas_forget(hipStream_t s);
 hipError_t combine_field(hipStream_t s, const GridDev& G, const slar_adv* a, double* out);
+// Regularised skeleton of a cross that stopped at its term cap: replaces
+// the k terms in out by min(rcap, rank W) terms of C W_r^+ R (synchronises)
+slar_status cur_core_run(hipStream_t s, Workspace* ws, slar_lowrank* out, int rcap);
 
 }  // namespace slar
 

@@ -1,8 +1,10 @@
 // HTACA final truncation (Supplement B): from the cross factors
-// F ~ sum_l U[l] (x) V[l] to a truncated HT tensor.
+// F ~ sum_l U[l] (x) V[l] (k <= 128 terms) to a truncated HT tensor.
 //   1. Cholesky-QR2 (with column scaling) of both factor sets:
 //      U^T = Qu^T Ru, V^T = Qv^T Rv (Q rows orthonormal);
-//   2. one-sided Jacobi SVD of the core Ru Rv^T = W diag(s) Z^T;
+//   2. one-sided Jacobi SVD of the core Ru Rv^T = W diag(s) Z^T (for
+//      k > 64 only W and s come from the Jacobi sweeps, and the kept
+//      right vectors are Z_r = (Ru Rv^T)^T W_r diag(s_r)^-1);
 //   3. root rank r = smallest with tail ||s[r:]|| <= theta,
 //      theta = tol ||s|| / sqrt(2d - 3), capped at rmax; frames
 //      X = Qu^T W_r, Y = Qv^T Z_r, sign rule on X (flip Y alike);
@@ -49,11 +51,12 @@ static Tbuf carve(Workspace* ws) {
   const GridDev& G = ws->G;
   double* p = ws->small;   // large enough for everything below (see api.hip)
   const size_t K = SLAR_KMAX, NN = (size_t)SLAR_NMAX * SLAR_NMAX;
+  const size_t CK = SLAR_CROSS_KMAX;
   Tbuf b;
-  b.Q1u = p; p += K * G.nx;
-  b.Qu = p; p += K * G.nx;
-  b.Q1v = p; p += K * G.nv;
-  b.Qv = p; p += K * G.nv;
+  b.Q1u = p; p += CK * G.nx;
+  b.Qu = p; p += CK * G.nx;
+  b.Q1v = p; p += CK * G.nv;
+  b.Qv = p; p += CK * G.nv;
   b.X = p; p += (size_t)G.nx * K;
   b.Y = p; p += (size_t)G.nv * K;
   b.Xs = p; p += (size_t)G.nx * K;
@@ -61,18 +64,18 @@ static Tbuf carve(Workspace* ws) {
   b.T = p; p += K * SLAR_NMAX * K;
   b.T2 = p; p += K * SLAR_NMAX * K;
   for (Chain* c : {&b.cu, &b.cv}) {
-    c->G = p; p += K * K;
-    c->Linv = p; p += K * K;
-    c->R1 = p; p += K * K;
+    c->G = p; p += CK * CK;
+    c->Linv = p; p += CK * CK;
+    c->R1 = p; p += CK * CK;
   }
   const size_t half = ws->dwork_elems / 2;
   b.cu.part = Scratch{ws->dwork, half};
   b.cv.part = Scratch{ws->dwork + half, half};
-  b.R = p; p += K * K * 2;
-  b.M = p; p += K * K;
-  b.W = p; p += K * K;
-  b.Z = p; p += K * K;
-  b.sv = p; p += K;
+  b.R = p; p += CK * CK * 2;
+  b.M = p; p += CK * CK;
+  b.W = p; p += CK * CK;
+  b.Z = p; p += CK * CK;
+  b.sv = p; p += CK;
   b.G1 = p; p += NN;
   b.G2 = p; p += NN;
   b.G3 = p; p += NN;
@@ -90,9 +93,9 @@ static Tbuf carve(Workspace* ws) {
 }
 
 size_t truncate_scratch_elems(const GridDev& G) {
-  const size_t K = SLAR_KMAX, NN = (size_t)SLAR_NMAX * SLAR_NMAX;
-  return 2 * K * G.nx + 2 * K * G.nv + 2 * (size_t)G.nx * K + 2 * (size_t)G.nv * K +
-         2 * K * SLAR_NMAX * K + 12 * K * K + K + 9 * NN + 4 * SLAR_NMAX + 64;
+  const size_t K = SLAR_KMAX, NN = (size_t)SLAR_NMAX * SLAR_NMAX, CK = SLAR_CROSS_KMAX;
+  return 2 * CK * G.nx + 2 * CK * G.nv + 2 * (size_t)G.nx * K + 2 * (size_t)G.nv * K +
+         2 * K * SLAR_NMAX * K + 12 * CK * CK + CK + 9 * NN + 4 * SLAR_NMAX + 64;
 }
 
 // Orthonormal rows Q (k x n) and upper R (k x k) with A = R^T Q... i.e.
@@ -173,7 +176,7 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
   Tbuf b = carve(ws);
   const int k = in.k;
   const hipStream_t sa = ws->fork_aux ? ws->aux : s;   // the V-side chain
-  double* Rv = b.R + SLAR_KMAX * SLAR_KMAX;
+  double* Rv = b.R + SLAR_CROSS_KMAX * SLAR_CROSS_KMAX;
   // the U and V orthogonalisations are independent: U on s, V on aux
   if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
   if (cholqr2(s, b.cu, k, G.nx, in.U, b.Q1u, b.Qu, b.R) != hipSuccess) return SLAR_E_HIP;
@@ -182,7 +185,12 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
   // core M = Ru Rv^T
   if (gemm_f64(s, false, true, k, k, k, 1.0, b.R, k, 0, Rv, k, 0, 0.0, b.M, k, 0, 1) != hipSuccess)
     return SLAR_E_HIP;
-  if (svd_small(s, k, b.M, b.W, b.sv, b.Z) != hipSuccess) return SLAR_E_HIP;
+  const bool big = k > 64;
+  if (big) {
+    if (svd_left_big(s, k, b.M, b.W, b.sv) != hipSuccess) return SLAR_E_HIP;
+  } else if (svd_small(s, k, b.M, b.W, b.sv, b.Z) != hipSuccess) {
+    return SLAR_E_HIP;
+  }
   std::vector<double> sv(k);
   HIP_TRY(hipMemcpyAsync(sv.data(), b.sv, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -201,6 +209,12 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
     double tail = 0.0;
     for (int i = r; i < k; ++i) tail += s2[i];
     if (r == rmax && std::sqrt(tail) > theta) capped = true;
+  }
+  if (big) {
+    // kept right singular vectors Z_r = M^T W_r diag(s_r)^-1 (k x r, ld k)
+    if (gemm_f64(s, true, false, k, r, k, 1.0, b.M, k, 0, b.W, k, 0, 0.0, b.Z, k, 0, 1) != hipSuccess)
+      return SLAR_E_HIP;
+    if (scale_cols_inv(s, k, r, b.Z, k, b.sv) != hipSuccess) return SLAR_E_HIP;
   }
   // frames X = Qu^T W_r (Nx x r), Y = Qv^T Z_r (Nv x r)
   if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;

@@ -29,7 +29,7 @@ EXPORTS = (
     "slar_batch_cross_update", "slar_batch_truncate", "slar_batch_efield", "slar_batch_get_config",
     "slar_batch_set_config", "slar_batch_tune", "slar_batch_timing", "slar_batch_timing_reset",
     "slar_macro_solve_system", "slar_macro_rhs", "slar_dirk3_tableau", "slar_bdf_weights",
-    "slar_cnn_correct", "slar_macro_history",
+    "slar_cnn_correct", "slar_macro_history", "slar_macro_fallbacks", "slar_lomac_filter",
 )
 
 
@@ -140,6 +140,8 @@ def load(path: str = LIB_PATH):
         "slar_dirk3_tableau": (i32, [P(dbl), P(dbl)]),
         "slar_bdf_weights": (i32, [i32, P(dbl), P(dbl), P(dbl)]),
         "slar_macro_history": (i32, [vp, P(dbl), i32]),
+        "slar_macro_fallbacks": (i32, [vp, P(i32)]),
+        "slar_lomac_filter": (i32, [P(Grid), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -332,6 +334,15 @@ def slar_macro_history(ws):
     return [tuple(out[4 * i: 4 * i + 4]) for i in range(min(n, 32))]
 
 
+def slar_macro_fallbacks(ws):
+    """(solves that fell back to plain GMRES since creation, last solve did)."""
+    last = C.c_int32(0)
+    n = load().slar_macro_fallbacks(ws.h, C.byref(last))
+    if n < 0:
+        raise SlarError(SLAR_E_INVAL, "slar_macro_fallbacks")
+    return n, bool(last.value)
+
+
 def slar_macro_rhs(grid, U, R_out, ws):
     _check(load().slar_macro_rhs(C.byref(grid), _ptr(U), _ptr(R_out), ws.h, _stream()), "slar_macro_rhs")
     return R_out
@@ -351,6 +362,11 @@ def slar_bdf_weights(times):
     beta = C.c_double()
     _check(load().slar_bdf_weights(int(k), t, c, C.byref(beta)), "slar_bdf_weights")
     return [c[j] for j in range(k)], beta.value
+
+
+def slar_lomac_filter(grid, U, ws):
+    _check(load().slar_lomac_filter(C.byref(grid), _ptr(U), ws.h, _stream()), "slar_lomac_filter")
+    return U
 
 
 def slar_lomac_project(grid, Fs, U_new, out: Frames, ws):

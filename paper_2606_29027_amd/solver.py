@@ -26,7 +26,8 @@ import torch
 from . import lib as L
 
 KCAP = 72          # frame columns (rank cap 64 + LoMaC columns)
-RCAP = 64
+RCAP = 64          # HT rank cap
+CCAP = 128         # cross-approximation terms
 
 
 class Solver:
@@ -47,6 +48,7 @@ class Solver:
         # otherwise the step is completed and reported with converged False
         self.strict = strict
         self.macro_log = []           # per solve: Newton records (rms, krylov, lin. residual, restarts)
+        self.fallbacks = 0            # learned-preconditioner solves redone with plain GMRES
         self.d = p.dx + p.dv
         self.Nx = int(np.prod(p.n[: p.dx]))
         self.Nv = int(np.prod(p.n[p.dx:]))
@@ -56,8 +58,9 @@ class Solver:
         z = lambda *s: torch.zeros(*s, **f64)   # noqa: E731
         self.frames_buf = [(z(self.Nx, KCAP), z(self.Nv, KCAP)) for _ in range(4)]
         self.ht_buf = [self._ht_buffers() for _ in range(2)]
-        self.U = z(RCAP, self.Nx)
-        self.V = z(RCAP, self.Nv)
+        self.kcross = min(p.cross_cap, CCAP)
+        self.U = z(self.kcross, self.Nx)
+        self.V = z(self.kcross, self.Nv)
         self.M = z(self.nmom, self.Nx)
         self.E = [z(p.dx, self.Nx) for _ in range(3)]
         self.Ubuf = [z(self.K, self.Nx) for _ in range(4)]
@@ -134,7 +137,7 @@ class Solver:
     def slar(self, src: L.Frames, adv, ht_slot: int, frame_slot: int):
         """One SLAR call: cross approximation + truncation + frames."""
         t0 = time.perf_counter()
-        lr, info, st = L.slar_cross_update(self.grid, src, adv, self.prec, self.p.tol, min(self.p.rmax, RCAP),
+        lr, info, st = L.slar_cross_update(self.grid, src, adv, self.prec, self.p.tol, self.kcross,
                                            self.probes, self.U, self.V, self.ws)
         t1 = time.perf_counter()
         H, _ = self.ht_buf[ht_slot]
@@ -177,8 +180,11 @@ class Solver:
         st, (nn, nk) = L.slar_macro_solve_system(self.grid, hist, stages, beta, self.newton_tol,
                                                  self.krylov_tol, self.precond,
                                                  None if self.cnn is None else self.cnn.handle, U_out, self.ws)
+        if self.p.lomac_filter:
+            L.slar_lomac_filter(self.grid, U_out, self.ws)
         self.tphase["macro"] += time.perf_counter() - t0
         self.macro_log.append(L.slar_macro_history(self.ws))
+        self.fallbacks += int(L.slar_macro_fallbacks(self.ws)[1])
         return st == L.SLAR_OK, nn, nk
 
     def _step_dirk3_bdf3(self, h):
@@ -229,8 +235,11 @@ class Solver:
             st, (nn, nk) = L.slar_macro_solve(self.grid, self.U_n, self.U_nm1 if bdf == 2 else None, h, bdf,
                                               self.newton_tol, self.krylov_tol, self.precond,
                                               None if self.cnn is None else self.cnn.handle, U_new, self.ws)
+            if p.lomac_filter:
+                L.slar_lomac_filter(self.grid, U_new, self.ws)
             self.tphase["macro"] += time.perf_counter() - tm
             self.macro_log.append(L.slar_macro_history(self.ws))
+            self.fallbacks += int(L.slar_macro_fallbacks(self.ws)[1])
             out_slot = [s for s in range(4) if s not in (slot,)][0]
             Fn = L.slar_lomac_project(self.grid, Fs, U_new, self._frames(out_slot), self.ws)
             self.U_nm1, self.U_n = self.U_n, U_new

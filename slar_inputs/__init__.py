@@ -57,10 +57,18 @@ class Problem:
     bdf: int = 2
     integrator: str = "bdf2"      # or "dirk3_bdf3" (the paper's section 4 choice)
     bump: tuple = ()              # bump-on-tail (n_p, n_b, u, v_t)
+    kcross: int = 0               # cross-approximation term cap (0: min(2 rmax, 128))
+    lomac_filter: bool = True     # band-limited LoMaC correction (mode filter)
 
     @property
     def d(self) -> int:
         return self.dx + self.dv
+
+    @property
+    def cross_cap(self) -> int:
+        """Most terms one cross approximation may take before the truncation
+        caps the rank at rmax."""
+        return self.kcross if self.kcross > 0 else min(2 * self.rmax, 128)
 
     def with_(self, **kw) -> "Problem":
         return dataclasses.replace(self, **kw)

@@ -664,3 +664,54 @@ def test_paper_workload_initial_data(name, N):
     dx = (p.hi[0] - p.lo[0]) / p.n[0]
     assert abs(p.dt - 5 * dx / p.hi[p.dx]) < 1e-15
     assert p.integrator == "dirk3_bdf3" and not p.split and p.order == 3
+
+
+def test_cur_core_reproduces_skeleton_and_exact_low_rank():
+    """CUR identities behind the regularised skeleton: with W invertible and
+    no truncation, C W^+ R is the cross itself (it interpolates its pivot
+    fibers); for a matrix of rank r whose pivot block has rank r, the
+    rank-r truncated core gives the matrix exactly (A = C W^+ R when
+    rank W = rank A)."""
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((40, 5)) @ rng.standard_normal((5, 50))
+    U, V, info = CR.aca(lambda i: A[i], lambda j: A[:, j], lambda I, J: A[I, J], 40, 50,
+                        1e-14, 5, 0, None)
+    Uc, Vc = CR.cur_core(U, V, info["pivots"], 5)
+    assert np.abs(Uc @ Vc.T - U @ V.T).max() < 1e-12 * np.abs(A).max()
+    assert np.abs(Uc @ Vc.T - A).max() < 1e-12 * np.abs(A).max()
+    # a rank-12 matrix crossed with 9 terms, core truncated to 4: the result
+    # has rank 4 and reproduces C W_4^+ R built from the sampled fibers
+    B = rng.standard_normal((30, 12)) @ rng.standard_normal((12, 35))
+    U, V, info = CR.aca(lambda i: B[i], lambda j: B[:, j], lambda I, J: B[I, J], 30, 35,
+                        1e-14, 9, 0, None)
+    I = [p[0] for p in info["pivots"]]; J = [p[1] for p in info["pivots"]]
+    Uc, Vc = CR.cur_core(U, V, info["pivots"], 4)
+    assert Uc.shape[1] == 4 and np.linalg.matrix_rank(Uc @ Vc.T) == 4
+    Y, s, Zt = np.linalg.svd(B[np.ix_(I, J)])
+    ref = B[:, J] @ (Zt[:4].T @ np.diag(1.0 / s[:4]) @ Y[:, :4].T) @ B[I, :]
+    assert np.abs(Uc @ Vc.T - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_correction_filter_keeps_totals_and_resolved_band():
+    """The band-limited LoMaC correction: the zero mode (hence mass,
+    momentum and energy totals) and every mode up to a third of the Nyquist
+    index are unchanged to rounding, the Nyquist mode is removed (e^-36),
+    and the result is real."""
+    rng = np.random.default_rng(3)
+    n = 24
+    U0 = rng.standard_normal((4, n, n))
+    x = np.arange(n) * 2 * math.pi / n
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    low = np.cos(2 * X1 + 0.3) * np.sin(4 * X2) + 0.7      # modes |m| <= 4 = n / 6
+    U = U0 + low[None] * np.arange(1, 5)[:, None, None]
+    Uf = LM.filter_correction(U, U0)
+    assert np.abs(Uf - U).max() < 1e-13
+    nyq = np.cos(math.pi * np.arange(n))[:, None] * np.ones((1, n))   # pure Nyquist along axis 0
+    Un = U0 + nyq[None]
+    Uf = LM.filter_correction(Un, U0)
+    assert np.abs(Uf - U0).max() < 1e-14 + 3e-16 * n
+    Ur = U0 + rng.standard_normal((4, n, n))
+    Uf = LM.filter_correction(Ur, U0)
+    assert np.isrealobj(Uf)
+    assert np.abs(Uf.sum(axis=(1, 2)) - Ur.sum(axis=(1, 2))).max() < 1e-12
+    assert np.linalg.norm(Uf - U0) < np.linalg.norm(Ur - U0)
