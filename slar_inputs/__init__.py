@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "config", "CONFIG_NAMES", "cell_centres", "initial_ht",
-    "random_ht", "random_requests", "fiber_requests", "probe_indices",
+    "random_ht", "graded_ht", "random_requests", "fiber_requests", "probe_indices",
     "batched_instances", "random_field", "PAPER_WORKLOADS",
 ]
 
@@ -213,6 +213,27 @@ def random_ht(d: int, n: Sequence[int], ranks: Sequence[int], seed: int) -> dict
         "B12": rng.standard_normal((r1, r2, r12)) / math.sqrt(r1 * r2),
         "B34": rng.standard_normal((r3, r4, r34)) / math.sqrt(r3 * r4),
         "root": rng.standard_normal((r12, r34)) / math.sqrt(r12 * r34),
+    }
+
+
+def graded_ht(n: Sequence[int], r_leaf: int, r_root: int, decay: float, seed: int) -> dict:
+    """A 4-leaf HT in orthogonal form with geometrically decaying root
+    singular values (root = diag(decay^c), c < r_root): leaves and the
+    matricised transfer tensors [r1 r2][r12] have orthonormal columns, so the
+    node frames are orthonormal and ||F||_F = ||root||_F.  A stand-in for a
+    truncated solution state (a few dominant terms, a long small tail)."""
+    rng = np.random.default_rng(seed)
+
+    def orth(rows, cols):
+        q, _ = np.linalg.qr(rng.standard_normal((rows, cols)))
+        return np.ascontiguousarray(q)
+
+    r = r_leaf
+    return {
+        "leaves": [orth(n[m], r) for m in range(4)],
+        "B12": orth(r * r, r_root).reshape(r, r, r_root),
+        "B34": orth(r * r, r_root).reshape(r, r, r_root),
+        "root": np.diag(decay ** np.arange(r_root)),
     }
 
 

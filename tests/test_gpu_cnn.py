@@ -55,24 +55,47 @@ def test_training_reduces_loss_on_recorded_systems():
     assert np.mean(hist[-10:]) < np.mean(hist[:3])
 
 
-def test_learned_preconditioner_same_root_fewer_iterations_than_plain():
+def _solve_counts(p, pc, cnn, steps=2, newton_tol=1e-12):
+    pr = SI.probe_indices(256, 256, 64, 5)
+    s = Solver(p, L.F64, probes=pr, precond=pc, cnn=cnn, newton_tol=newton_tol)
+    s.set_initial(SI.initial_ht(p))
+    d0 = s.diagnostics()
+    infos = [s.step() for _ in range(steps)]
+    d = s.diagnostics()
+    assert abs(d["mass"] - d0["mass"]) < 1e-12 * d0["mass"]
+    return s, s.U_n.cpu().numpy(), sum(i["krylov"] for i in infos)
+
+
+def test_learned_preconditioner_against_spectral_and_plain():
+    """The committed network inside FGMRES: the same Newton root as plain
+    GMRES (pc 0) and as the spectral preconditioner alone (pc 1).  Its gain
+    is measured against both: the spectral part is nearly exact on these
+    systems, so the network is held to no more than 25 % extra Krylov
+    iterations over spectral-only (it does not reduce them: the measured
+    counts on the 128^4 strong-Landau run are 218 against 206 over steps
+    5-30), while spectral + network must use fewer than plain GMRES."""
     p = SI.config("stronglandau2d", n=16).with_(rmax=40)
-    data = CNN.collect([SI.config("landau2d", n=16).with_(rmax=30)], steps=3, capacity=24)
-    net = CNN.make(max_batch=8, max_pixels=16 * 16)
-    CNN.train(net, data, iters=40, batch=8)
-    Nx = 256
-    pr = SI.probe_indices(Nx, Nx, 64, 5)
-    out = {}
-    for pc, cnn in ((0, None), (2, net)):
-        s = Solver(p, L.F64, probes=pr, precond=pc, cnn=cnn, newton_tol=1e-12)
-        s.set_initial(SI.initial_ht(p))
-        d0 = s.diagnostics()
-        infos = [s.step() for _ in range(2)]
-        d = s.diagnostics()
-        assert abs(d["mass"] - d0["mass"]) < 1e-12 * d0["mass"]
-        out[pc] = (s.U_n.cpu().numpy(), sum(i["krylov"] for i in infos))
-    assert normwise(out[2][0], out[0][0]) < 1e-9
-    assert out[2][1] < out[0][1]
+    net = CNN.load_trained(p)
+    _, U0, k0 = _solve_counts(p, 0, None)
+    _, U1, k1 = _solve_counts(p, 1, None)
+    s2, U2, k2 = _solve_counts(p, 2, net)
+    assert s2.fallbacks == 0
+    assert normwise(U2, U0) < 1e-9 and normwise(U1, U0) < 1e-9
+    assert k2 < k0
+    assert k2 <= 1.25 * k1 + 2, (k2, k1)
+
+
+def test_learned_preconditioner_falls_back_to_plain_gmres():
+    """A network that returns non-finite values (parameters set to NaN from
+    the host) cannot precondition: each solve is abandoned and repeated
+    with plain GMRES, and the run reaches the plain solver's root."""
+    p = SI.config("stronglandau2d", n=16).with_(rmax=40)
+    bad = CNN.make(max_batch=1, max_pixels=16 * 16)
+    bad.set_params(np.full(bad.nparams, np.nan, dtype=np.float32))
+    _, U0, _ = _solve_counts(p, 0, None)
+    s, U2, _ = _solve_counts(p, 2, bad)
+    assert s.fallbacks == 2
+    assert normwise(U2, U0) < 1e-12
 
 
 def test_recorded_features_are_standardised():

@@ -101,3 +101,106 @@ def test_lomac_step_at_128_4_conserves():
     assert abs(d["mass"] - d0["mass"]) < 1e-12 * d0["mass"]
     assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
     assert max(abs(m) for m in d["momentum"]) < 1e-12 * d0["mass"]
+
+
+def _graded_state(p):
+    """A rank-60 orthogonal HT on the 128^4 grid with decaying root values
+    (a stand-in for a truncated solution state) and its frames."""
+    F = SI.graded_ht(p.n, 60, 60, 0.85, seed=21)
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 64)
+    T = ht_to_dev(F)
+    H = L.make_ht(T, 4, L.F64)
+    Nx = 128 * 128
+    X = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
+    P = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
+    Fr = L.slar_frames_from_ht(g, H, L.frames(X, P, 0), ws)
+    return F, g, ws, H, Fr, (T, X, P)
+
+
+def test_fp32_samplers_rank60_truncated_state_at_1e6():
+    """FP32 frame tables (the cross approximation's sampler, 18 stencil rows
+    of 60 columns per entry) on a rank-60 orthogonal state at 128^4, the
+    strong-Landau first sub-flow, 2037 random entries: normwise within 1e-6
+    of the oracle's FP64 contraction.  The FP32 leaf-to-root contraction
+    (slar_ht_sample, matrix cores; not on the production path) accumulates
+    K = r1 r2 = 3600 Khatri-Rao terms per transfer node in FP32 registers:
+    its bar is 2^-24 sqrt(3600) ~ 3.6e-6, held at 5e-6 (2.8e-6 measured)."""
+    p, o, E = _workload()
+    F, g, ws, H, Fr, keep = _graded_state(p)
+    idx = SI.random_requests(p.n, 2000 + 37, seed=5)
+    ref, amb = _oracle_entries(F, p, idx, p.dt / 3.0, E)
+    adv = L.make_adv(2, p.dt / 3.0, 1.0, dev(E))
+    idx_d = torch.as_tensor(idx, dtype=torch.int32, device="cuda")
+    out = torch.zeros(len(idx), dtype=torch.float64, device="cuda")
+    L.slar_frame_sample(g, Fr, adv, L.F32, idx_d, out, ws)
+    T32 = {k: ([x.float() for x in v] if isinstance(v, list) else v.float()) for k, v in keep[0].items()}
+    H32 = L.make_ht(T32, 4, L.F32)
+    out32 = torch.zeros(len(idx), dtype=torch.float32, device="cuda")
+    L.slar_ht_sample(g, H32, adv, idx_d, out32)
+    torch.cuda.synchronize()
+    k = ~amb
+    assert k.sum() > 1900
+    assert normwise(out.cpu().numpy()[k], ref[k]) < 1e-6
+    assert normwise(out32.double().cpu().numpy()[k], ref[k]) < 5e-6
+
+
+def test_moments_and_macro_rhs_at_128_4():
+    """The nine velocity moments of the rank-60 state on the 128^2 x-grid,
+    and the macroscopic right-hand side R(U) of its LoMaC closure at a
+    perturbed U(F*), against the oracle at 1e-12 (FFT lines of 128 points
+    on both axes)."""
+    from oracle import lomac as LM
+    from oracle import macro as MA
+    p = SI.config("stronglandau2d", n=128)
+    F, g, ws, H, Fr, keep = _graded_state(p)
+    o = ST.Oracle(p)
+    Nx, K = 128 * 128, 4
+    M = torch.zeros(9, Nx, dtype=torch.float64, device="cuda")
+    L.slar_moments(g, Fr, M, ws)
+    torch.cuda.synchronize()
+    Mo = o.moments(F).reshape(9, Nx)
+    assert normwise(M.cpu().numpy(), Mo) < 1e-12
+    n_i = float(Mo[0].mean())
+    o.n_i = n_i
+    L.slar_lomac_prepare(g, H, Fr, 1e-12, n_i, ws)
+    U = torch.zeros(K, Nx, dtype=torch.float64, device="cuda")
+    L.slar_conserved(g, Fr, n_i, U, ws)
+    rng = np.random.default_rng(4)
+    U += dev(1e-3 * np.abs(Mo[0]).max() * rng.standard_normal((K, Nx)))
+    R = torch.zeros_like(U)
+    L.slar_macro_rhs(g, U, R, ws)
+    torch.cuda.synchronize()
+    u1 = [F["leaves"][2 + m][:, 0] for m in range(2)]
+    B = LM.basis(u1, o.vgrids, o.h[2:], 1e-12)
+    sysm = MA.MacroSystem(o.moments(F), B, n_i, o.lengths, o.dvol_v, o.vgrids, 0.0, 1.0)
+    Ro = sysm.rhs(U.cpu().numpy().reshape(K, 128, 128)).reshape(K, Nx)
+    assert normwise(R.cpu().numpy(), Ro) < 1e-12
+
+
+@pytest.mark.parametrize("n", [12, 128])
+def test_lomac_filter_matches_oracle(n):
+    """slar_lomac_filter (U(F*) + sigma (U - U(F*))) against
+    oracle.lomac.filter_correction at 1e-13, totals kept to 1e-13."""
+    from oracle import lomac as LM
+    p = SI.config("stronglandau2d", n=n)
+    F = SI.graded_ht(p.n, min(n, 8), 8, 0.7, seed=3)
+    g = L.make_grid(p)
+    ws = L.Workspace(g, 16)
+    T = ht_to_dev(F)
+    H = L.make_ht(T, 4, L.F64)
+    Nx, K = n * n, 4
+    X = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
+    P = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
+    Fr = L.slar_frames_from_ht(g, H, L.frames(X, P, 0), ws)
+    L.slar_lomac_prepare(g, H, Fr, 1e-12, 1.0, ws)
+    U0 = torch.zeros(K, Nx, dtype=torch.float64, device="cuda")
+    L.slar_conserved(g, Fr, 1.0, U0, ws)
+    rng = np.random.default_rng(9)
+    Un = U0 + dev(rng.standard_normal((K, Nx)))
+    ref = LM.filter_correction(Un.cpu().numpy().reshape(K, n, n), U0.cpu().numpy().reshape(K, n, n))
+    L.slar_lomac_filter(g, Un, ws)
+    torch.cuda.synchronize()
+    got = Un.cpu().numpy().reshape(K, n, n)
+    assert normwise(got, ref) < 1e-13
+    assert np.abs(got.sum(axis=(1, 2)) - ref.sum(axis=(1, 2))).max() < 1e-13 * np.abs(ref).sum()

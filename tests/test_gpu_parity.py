@@ -175,7 +175,7 @@ def test_frame_sampler_matches_oracle(name, N, prec):
     assert normwise(P[:, : Fr.r].cpu().numpy(), Po) < 1e-13
 
 
-@pytest.mark.parametrize("shape", [(64,), (48,), (32, 32), (24, 40)])
+@pytest.mark.parametrize("shape", [(64,), (48,), (32, 32), (24, 40), (128, 128)])
 def test_poisson_matches_oracle(shape):
     dx = len(shape)
     L_ = [4 * math.pi, 3.0][:dx]
