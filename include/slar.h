@@ -227,6 +227,21 @@ slar_status slar_moments(const slar_grid* g, const slar_frames* F, double* M,
 slar_status slar_poisson(const slar_grid* g, const double* n_e, double n_i, double* phi,
                          double* E, slar_workspace* ws, hipStream_t stream);
 
+/* slar_poisson without a workspace and without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * result as slar_poisson.  Its scratch (the transform buffers and twiddle
+ * tables, at most 3.2 MB: 2048 + 24 Nx doubles with Nx <= 128^2) is a
+ * file-scope device array that every GPU holds until the process ends;
+ * the device address is resolved once per device on the first call there.
+ * Every call on a device shares that array: calls that overlap in time on
+ * one device race and must be serialised by the caller (e.g. one stream).
+ * A call writes every scratch element it reads.  Returns SLAR_E_NOMEM if
+ * the grid needs more scratch than the array holds, SLAR_E_INVAL on a bad
+ * grid or pointer.  Enqueued on stream.                                     */
+slar_status slar_poisson_noalloc(const slar_grid* g, const double* n_e, double n_i, double* phi,
+                                 double* E, hipStream_t stream);
+
 /* Conserved variables U = (n, m n u, e_k + e_p) of a tensor ([dv+2][Nx]),
  * eq. (macro_sys_comp) with m_e = 1.                                        */
 slar_status slar_conserved(const slar_grid* g, const slar_frames* F, double n_i, double* U,

@@ -28,6 +28,8 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
 size_t aca_ctl_bytes();
 size_t aca_part_elems();
 size_t truncate_scratch_elems(const GridDev& G);
+slar_status poisson_noalloc_run(hipStream_t s, const slar_grid& grid, const double* n_e, double n_i,
+                                double* phi, double* E);
 }  // namespace slar
 
 using namespace slar;
@@ -438,6 +440,12 @@ slar_status slar_bdf_weights(int32_t k, const double* t, double* c, double* beta
   }
   *beta = 1.0 / l0;
   return SLAR_OK;
+}
+
+slar_status slar_poisson_noalloc(const slar_grid* g, const double* n_e, double n_i, double* phi,
+                                 double* E, hipStream_t stream) {
+  if (!grid_ok(g) || !n_e || !E || !std::isfinite(n_i)) return SLAR_E_INVAL;
+  return poisson_noalloc_run(stream, *g, n_e, n_i, phi, E);
 }
 
 slar_status slar_lomac_filter(const slar_grid* g, double* U, slar_workspace* w, hipStream_t stream) {

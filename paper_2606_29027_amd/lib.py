@@ -30,6 +30,7 @@ EXPORTS = (
     "slar_batch_set_config", "slar_batch_tune", "slar_batch_timing", "slar_batch_timing_reset",
     "slar_macro_solve_system", "slar_macro_rhs", "slar_dirk3_tableau", "slar_bdf_weights",
     "slar_cnn_correct", "slar_macro_history", "slar_macro_fallbacks", "slar_lomac_filter",
+    "slar_poisson_noalloc",
 )
 
 
@@ -142,6 +143,7 @@ def load(path: str = LIB_PATH):
         "slar_macro_history": (i32, [vp, P(dbl), i32]),
         "slar_macro_fallbacks": (i32, [vp, P(i32)]),
         "slar_lomac_filter": (i32, [P(Grid), vp, vp, vp]),
+        "slar_poisson_noalloc": (i32, [P(Grid), vp, dbl, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -286,6 +288,13 @@ def slar_moments(grid, F, M, ws):
 def slar_poisson(grid, n_e, n_i, phi, E, ws):
     _check(load().slar_poisson(C.byref(grid), _ptr(n_e), float(n_i), _ptr(phi), _ptr(E), ws.h,
                                _stream()), "slar_poisson")
+
+
+def slar_poisson_noalloc(grid, n_e, n_i, phi, E):
+    """slar_poisson without a workspace or device allocation."""
+    _check(load().slar_poisson_noalloc(C.byref(grid), _ptr(n_e), float(n_i), _ptr(phi), _ptr(E), _stream()),
+           "slar_poisson_noalloc")
+    return E
 
 
 def slar_conserved(grid, F, n_i, U, ws):
