@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--nested-config", default="stronglandau2d",
                     help="2D2V workload whose state the nested workload compares the samplers on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=18.0)
     ap.add_argument("--variants", default="plain,spectral,learned",
                     help="comma list of macro solvers to time: plain, spectral, learned "
                          "(the last one listed is the headline)")
@@ -85,36 +85,79 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(p, budget_s: float):
-    """The oracle's SL-FD entry evaluation (HT contraction of section 3.1) on
-    whole row fibers of a 128^4 tensor at the workload's rank (random HT,
-    all six ranks 60, seed 11), first RK sub-flow (tau = dt / 3) in the
-    field of the initial state, until about ``budget_s`` seconds of CPU
-    time are spent."""
-    import slar_inputs as SI
-    from oracle import step as ST
+def _cpu_model() -> str:
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, budget_s: float):
+    """The CPU oracle on a bounded sample of the workload, at all host
+    threads and at one BLAS thread:
+
+    * SL-FD entries/s of the frame-form evaluation (the algorithm the GPU's
+      cross approximation runs: both frame gathers and an r-term dot
+      product) and of the leaf-to-root HT contraction, on whole row fibers
+      of a rank-60 orthogonal 128^4 state (graded singular values, seed 21),
+      first RK sub-flow (tau = dt / 3) in the initial state's field;
+    * seconds per time step of the 64^4 weak-Landau workload (its first
+      steps; the 128^4 steps take the oracle hours).
+
+    value = frame-form entries/s at all threads.  Each timing runs for
+    about budget_s / 6 seconds."""
+    import slar_inputs as SI
+    from oracle import feet as FT
+    from oracle import ht as HT
+    from oracle import step as ST
+    from threadpoolctl import threadpool_info, threadpool_limits
+    nthreads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     o = ST.Oracle(p)
     E = o.efield(SI.initial_ht(p))
-    r = min(p.rmax, 60)
-    F = SI.random_ht(4, p.n, (r,) * 6, seed=11)
+    F = SI.graded_ht(p.n, 60, 60, 0.85, seed=21)
+    X = HT.x_frame(F)
+    P = np.tensordot(HT.v_frame(F), F["root"], axes=([2], [1]))
     Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
-    done = 0
-    t0 = time.perf_counter()
-    fib = 0
-    while time.perf_counter() - t0 < budget_s:
-        idx = o._idx(np.full(Nv, fib * 997 % Nx), np.arange(Nv))
-        o.entries(F, idx, 2, p.dt / 3.0, 1.0, E)
-        done += Nv
-        fib += 1
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "entries/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{fib} row fibers ({done} SL-FD entries) of a rank-{r} random HT on the "
-                      f"{p.n[0]}^4 grid, first RK sub-flow of the workload, FP64 NumPy"}
+    slot = budget_s / 6.0
+
+    def fibers(fn):
+        done, fib = 0, 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < slot:
+            idx = o._idx(np.full(Nv, fib * 997 % Nx), np.arange(Nv))
+            foot = FT.feet(idx, p.lo, p.hi, p.n, p.dx, 2, p.dt / 3.0, 1.0, E)
+            rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, 3, 2, p.dx)
+            fn(rows, wts)
+            done += Nv
+            fib += 1
+        return done / (time.perf_counter() - t0), fib
+
+    def cfg2_steps(nsteps):
+        q = SI.config("landau2d")
+        oq = ST.Oracle(q, probes=SI.probe_indices(64 * 64, 64 * 64, 64, 1234))
+        t0 = time.perf_counter()
+        oq.run(SI.initial_ht(q), nsteps)
+        return (time.perf_counter() - t0) / nsteps
+
+    res = {}
+    for label, lim in (("threads_all", nthreads), ("threads_1", 1)):
+        with threadpool_limits(limits=lim):
+            fr, nf = fibers(lambda r, w: HT.sample_frames(X, P, r, w))
+            ct, nc = fibers(lambda r, w: HT.sample(F, r, w))
+            st = cfg2_steps(2 if lim > 1 else 1)
+        res[label] = {"frame_entries_per_s": fr, "contraction_entries_per_s": ct,
+                      "cfg2_64_4_s_per_step": st, "fibers": [nf, nc]}
+    return {"value": res["threads_all"]["frame_entries_per_s"], "unit": "entries/s",
+            "cores": int(nthreads), "kind": "oracle",
+            "sample": f"row fibers of {Nv} SL-FD entries of a rank-60 orthogonal 128^4 state, first RK "
+                      "sub-flow of the workload, frame-form evaluation (the GPU cross's algorithm), "
+                      "FP64 NumPy; plus the leaf-to-root contraction and 64^4 weak-Landau steps",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "blas_threads": int(nthreads),
+            "threads_all": res["threads_all"], "threads_1": res["threads_1"]}
 
 
 def batched_main(args):

@@ -99,6 +99,17 @@ def sample(F, rows, wts, chunk: int = 4096) -> np.ndarray:
     return out
 
 
+def sample_frames(X: np.ndarray, P: np.ndarray, rows, wts) -> np.ndarray:
+    """The same SL-FD value from the frame form F[I, J] = sum_c X[I, c] P[J, c]
+    (X of shape (N_x1.., r), P of shape (N_v1.., r); the root folded into P):
+    eq. (tp_interp) applied to each frame separately, then the length-r dot
+    product.  This is what the cross approximation samples."""
+    dx = X.ndim - 1
+    cx = block_interp(np.moveaxis(X, -1, 0), rows[:dx], wts[:dx])
+    cp = block_interp(np.moveaxis(P, -1, 0), rows[dx:], wts[dx:])
+    return np.sum(cx * cp, axis=1)
+
+
 # ---------------------------------------------------------------- moments
 
 def psi_list(vgrids):

@@ -715,3 +715,19 @@ def test_correction_filter_keeps_totals_and_resolved_band():
     assert np.isrealobj(Uf)
     assert np.abs(Uf.sum(axis=(1, 2)) - Ur.sum(axis=(1, 2))).max() < 1e-12
     assert np.linalg.norm(Uf - U0) < np.linalg.norm(Ur - U0)
+
+
+def test_frame_sampling_equals_leaf_to_root_contraction():
+    """Eq. (tp_interp) evaluated on the node frames (x frame, v frame times
+    the root) gives the leaf-to-root HT contraction's value at every foot."""
+    p = SI.config("landau2d", n=10)
+    F = SI.random_ht(4, p.n, (3, 4, 5, 3, 6, 5), seed=44)
+    idx = SI.random_requests(p.n, 400, 8)
+    E = 0.5 * np.stack([SI.random_field((10, 10), 1), SI.random_field((10, 10), 2)])
+    foot = FT.feet(idx, p.lo, p.hi, p.n, 2, 2, 0.6, 1.0, E)
+    rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, 3, 2, 2)
+    a = HT.sample(F, rows, wts)
+    X = HT.x_frame(F)
+    P = np.tensordot(HT.v_frame(F), F["root"], axes=([2], [1]))
+    b = HT.sample_frames(X, P, rows, wts)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
