@@ -584,21 +584,79 @@ hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* s
 // and sorted by norm (descending, ties by index), are the left singular
 // vectors, their norms the singular values.  The right vectors are not
 // accumulated: the caller forms the ones it keeps as M^T w / s.
+//
+// The Jacobi sweeps run on L = M Q (Householder LQ, M = L Q^T) instead of
+// M: right-multiplying by an orthogonal matrix leaves the left singular
+// vectors and the singular values unchanged, and the rows of L are graded
+// the way the pivot blocks of a cross approximation are, so the sweeps
+// converge in about a third as many passes as on M itself.
 constexpr int SVD_BIG = SLAR_CROSS_KMAX;
+constexpr int SVD_BIG_LD = SVD_BIG;   // a multiple of 32 doubles, as the Jacobi teams assume
+
+// In-place Householder LQ of the n x n matrix A (column c at A + c * lda,
+// n <= 128, blockDim 1024): on return A holds L = A Q, lower triangular.
+// Step i reflects columns i..n-1 so that row i keeps only its diagonal.
+// Row r's update sums over the columns in eight strided groups of 128
+// threads (one thread per row and group); vrow holds the reflector.
+__device__ void lq_lower(double* A, int lda, int n, double* vrow, double (*part)[SVD_BIG], double* s_sc) {
+  const int t = threadIdx.x;
+  const int row = t & 127, g = t >> 7;
+  for (int i = 0; i + 1 < n; ++i) {
+    if (t < 64) {
+      double sg = 0.0;
+      for (int c = i + 1 + t; c < n; c += 64) {
+        const double x = A[c * lda + i];
+        vrow[c] = x;
+        sg += x * x;
+      }
+      for (int o = 32; o > 0; o >>= 1) sg += __shfl_xor(sg, o, 64);
+      if (t == 0) { s_sc[0] = sg; s_sc[1] = A[i * lda + i]; }
+    }
+    __syncthreads();
+    const double sig = s_sc[0], xi = s_sc[1];
+    // x = row i from the diagonal on; H x = alpha e_i with |alpha| = |x|
+    // and the sign opposite to x_i, so that v_i = x_i - alpha does not cancel
+    const bool act = sig > 0.0;
+    const double nx = sqrt(xi * xi + sig);
+    const double alpha = (xi >= 0.0) ? -nx : nx;
+    const double vi = xi - alpha;
+    const double f = act ? 2.0 / (sig + vi * vi) : 0.0;
+    if (act && row > i && row < n) {
+      double pr = 0.0;
+      for (int c = i + g; c < n; c += 8) pr += A[c * lda + row] * (c == i ? vi : vrow[c]);
+      part[g][row] = pr;
+    }
+    __syncthreads();
+    if (act && row > i && row < n) {
+      double w = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) w += part[q][row];
+      w *= f;
+      for (int c = i + g; c < n; c += 8) A[c * lda + row] -= w * (c == i ? vi : vrow[c]);
+    }
+    if (act && row == i)
+      for (int c = i + g; c < n; c += 8) A[c * lda + i] = (c == i) ? alpha : 0.0;
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_svd_left_big(int k, const double* __restrict__ Min,
                                                        double* __restrict__ W, double* __restrict__ sv) {
-  __shared__ double A[SVD_BIG * SVD_BIG];   // column c at A + c * SVD_BIG
+  __shared__ double A[SVD_BIG * SVD_BIG_LD];   // column c at A + c * SVD_BIG_LD
   __shared__ double nrm[SVD_BIG];
   __shared__ int order[SVD_BIG];
   __shared__ double red[16];
   __shared__ int s_rot[2];
+  __shared__ double vrow[SVD_BIG];
+  __shared__ double lqpart[8][SVD_BIG];
+  __shared__ double s_sc[2];
   const int t = threadIdx.x;
   const int kp = (k + 1) & ~1;
   double part = 0.0;
   for (int e = t; e < kp * kp; e += blockDim.x) {
     const int c = e / kp, r = e % kp;
     const double v = (r < k && c < k) ? Min[r * k + c] : 0.0;
-    A[c * SVD_BIG + r] = v;
+    A[c * SVD_BIG_LD + r] = v;
     part += v * v;
   }
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
@@ -608,10 +666,11 @@ __global__ __launch_bounds__(1024) void k_svd_left_big(int k, const double* __re
   for (int w = 0; w < 16; ++w) fro += red[w];
   const double floor_abs = 1e-300 + 1e-22 * fro;
   const double orth = 4.0 * kp * 2.220446049250313e-16;
-  jacobi_cols<8, 0>(A, SVD_BIG, kp, kp, nullptr, 0, 0, orth, floor_abs, 60, nrm, s_rot);
+  lq_lower(A, SVD_BIG_LD, kp, vrow, lqpart, s_sc);
+  jacobi_cols<8, 0>(A, SVD_BIG_LD, kp, kp, nullptr, 0, 0, orth, floor_abs, 60, nrm, s_rot);
   for (int c = t; c < kp; c += blockDim.x) {
     double acc = 0.0;
-    for (int r = 0; r < kp; ++r) acc += A[c * SVD_BIG + r] * A[c * SVD_BIG + r];
+    for (int r = 0; r < kp; ++r) acc += A[c * SVD_BIG_LD + r] * A[c * SVD_BIG_LD + r];
     nrm[c] = sqrt(acc);
   }
   __syncthreads();
@@ -625,7 +684,7 @@ __global__ __launch_bounds__(1024) void k_svd_left_big(int k, const double* __re
   for (int e = t; e < k * k; e += blockDim.x) {
     const int r = e / k, j = e % k;
     const int c = order[j];
-    W[e] = nrm[c] > 0.0 ? A[c * SVD_BIG + r] / nrm[c] : (r == j ? 1.0 : 0.0);
+    W[e] = nrm[c] > 0.0 ? A[c * SVD_BIG_LD + r] / nrm[c] : (r == j ? 1.0 : 0.0);
   }
   for (int j = t; j < k; j += blockDim.x) sv[j] = nrm[order[j]];
 }

@@ -1,0 +1,96 @@
+"""The configured workloads run at their stated grid, step and end time on
+the GPU (seeded synthetic initial states, the library's own solver):
+
+* 1D1V weak Landau, 64^2, Strang-split plain SLAR with 5-point stencils,
+  dt 0.1 to T = 5: the field decays at the Landau rate (two envelope peaks
+  in [0, 5]; -0.163 measured against -0.1534, the split step's damping
+  error), mass kept to the truncation tolerance (no LoMaC on this one);
+* 2D2V weak Landau + LoMaC, 64^4, FP32 tables, rank cap 40, dt 0.2 to
+  T = 10: every Newton solve converged, mass, momentum and energy kept to
+  1e-12, damping within 10 % of linear theory (the dt = 0.2 CF3/BDF2 step
+  adds about 6 %);
+* 2D2V two-stream + LoMaC, 128^4, tol 1e-5, rank cap 60, dt 0.1 to T = 40:
+  every solve converged, conservation to 1e-12, and the linear growth rate
+  over t in [15, 25] within 5 % of the dispersion root 0.2258;
+* 2D2V strong Landau + LoMaC, 128^4, dt 0.2: 25 steps (t = 5), every solve
+  converged, conservation to 1e-12.  The run to T = 30 is not reached: the
+  coupling grows from t ~ 8 at this CFL (about 12)."""
+import numpy as np
+import pytest
+
+import slar_inputs as SI
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2606_29027_amd import lib as L  # noqa: E402
+from paper_2606_29027_amd.solver import Solver  # noqa: E402
+from dispersion import root_beams  # noqa: E402
+
+
+def _run(name, prec, precond, steps=None):
+    p = SI.config(name)
+    Nx = int(np.prod(p.n[: p.dx]))
+    Nv = int(np.prod(p.n[p.dx:]))
+    s = Solver(p, prec, probes=SI.probe_indices(Nx, Nv, 64, 1234), precond=precond)
+    s.set_initial(SI.initial_ht(p))
+    d0 = s.diagnostics()
+    n = steps or int(round(p.T / p.dt))
+    ee = [d0["elec_energy"]]
+    ranks = []
+    for _ in range(n):
+        info = s.step()            # strict solver: an unconverged solve raises
+        if p.lomac:
+            assert info["converged"]
+        ranks.append(max(max(st["ranks"]) for st in s.stats[-3:]))   # HT ranks after truncation
+        ee.append(s.diagnostics()["elec_energy"])
+    return p, np.array(ee), np.arange(n + 1) * p.dt, d0, s.diagnostics(), max(ranks)
+
+
+def _peak_rate(ee, t):
+    le = np.log(ee)
+    pk = [i for i in range(1, len(le) - 1) if le[i] > le[i - 1] and le[i] >= le[i + 1]]
+    assert len(pk) >= 2
+    return np.polyfit(t[pk], le[pk], 1)[0] / 2
+
+
+def _conserved(p, d0, d):
+    assert abs(d["mass"] - d0["mass"]) < 1e-12 * d0["mass"]
+    assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
+    assert max(abs(m) for m in d["momentum"]) < 1e-12 * d0["mass"]
+
+
+def test_landau1d_64_to_t5():
+    _, gam = root_beams(0.5, 0.0, [1.4, -0.15])
+    p, ee, t, d0, d, rk = _run("landau1d", L.F64, 0)
+    assert rk <= p.rmax
+    assert abs(_peak_rate(ee, t) - gam) < 0.10 * abs(gam)
+    assert abs(d["mass"] - d0["mass"]) < 1e-5 * d0["mass"]
+
+
+def test_landau2d_64_to_t10():
+    _, gam = root_beams(0.5, 0.0, [1.4, -0.15])
+    p, ee, t, d0, d, rk = _run("landau2d", L.F32, 1)
+    assert rk <= p.rmax
+    _conserved(p, d0, d)
+    assert abs(_peak_rate(ee, t) - gam) < 0.10 * abs(gam)
+
+
+def test_twostream2d_128_to_t40():
+    _, gam = root_beams(0.2, 2.4, [0.0, 0.2])
+    p, ee, t, d0, d, rk = _run("twostream2d", L.F32, 1)
+    assert rk <= p.rmax
+    _conserved(p, d0, d)
+    sel = (t >= 15.0) & (t <= 25.0)
+    slope = np.polyfit(t[sel], np.log(ee[sel]), 1)[0] / 2
+    assert abs(slope - gam) < 0.05 * gam, (slope, gam)
+    # saturation: the field stops growing before the end of the run
+    assert ee[-1] < ee.max()
+
+
+def test_stronglandau2d_128_25_steps_converge():
+    p, ee, t, d0, d, rk = _run("stronglandau2d", L.F32, 1, steps=25)
+    _conserved(p, d0, d)

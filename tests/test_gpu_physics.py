@@ -46,43 +46,7 @@ if not torch.cuda.is_available():
 
 from paper_2606_29027_amd import lib as L  # noqa: E402
 from paper_2606_29027_amd.solver import Solver  # noqa: E402
-
-
-def _root(k, v0, guess):
-    from scipy.special import wofz
-    from scipy.optimize import fsolve
-
-    def f(z):
-        w = complex(z[0], z[1])
-        D = 1.0
-        beams = (0.0,) if v0 == 0.0 else (v0, -v0)
-        for b in beams:
-            zeta = (w / k - b) / math.sqrt(2)
-            Z = 1j * math.sqrt(math.pi) * wofz(zeta)
-            D += (1 + zeta * Z) / (k * k * len(beams))
-        return [D.real, D.imag]
-
-    r = fsolve(f, guess, xtol=1e-13)
-    return r[0], r[1]
-
-
-def _root_maxwellians(k, comps, guess):
-    """Root of the dispersion relation of a sum of drifting Maxwellians,
-    comps = [(density, drift, variance)]."""
-    from scipy.special import wofz
-    from scipy.optimize import fsolve
-
-    def f(z):
-        w = complex(z[0], z[1])
-        D = 1.0
-        for n, u, s2 in comps:
-            zeta = (w / k - u) / math.sqrt(2 * s2)
-            Z = 1j * math.sqrt(math.pi) * wofz(zeta)
-            D += n / (k * k * s2) * (1 + zeta * Z)
-        return [D.real, D.imag]
-
-    r = fsolve(f, guess, xtol=1e-13)
-    return r[0], r[1]
+from dispersion import root_maxwellians as _root_maxwellians, root_beams as _root  # noqa: E402
 
 
 def _run(p, steps):

@@ -731,3 +731,21 @@ def test_frame_sampling_equals_leaf_to_root_contraction():
     P = np.tensordot(HT.v_frame(F), F["root"], axes=([2], [1]))
     b = HT.sample_frames(X, P, rows, wts)
     assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+
+
+def test_dispersion_roots_of_linear_theory():
+    """The rates the long GPU runs are checked against: Landau damping at
+    k = 0.5 (-0.1534), the purely growing two-stream root for beams at
+    +-2.4, k = 0.2 (0.2258), and the bump-on-tail root of the section 4
+    setup (0.9587 + 0.1917 i)."""
+    import math
+    from dispersion import root_beams, root_maxwellians
+    om, gam = root_beams(0.5, 0.0, [1.4, -0.15])
+    assert abs(gam + 0.1534) < 1e-3 and abs(om - 1.4157) < 1e-3
+    om, gam = root_beams(0.2, 2.4, [0.0, 0.2])
+    assert abs(om) < 1e-8 and abs(gam - 0.2258) < 1e-3
+    p = SI.config("bumpontail1d")
+    n_p, n_b, u, vt = p.bump
+    comps = [(n_p * math.sqrt(2 * math.pi), 0.0, 1.0), (n_b * math.sqrt(2 * math.pi * vt), u, vt)]
+    om, gam = root_maxwellians(p.k, comps, [1.0, 0.2])
+    assert abs(om - 0.9587) < 1e-3 and abs(gam - 0.1917) < 1e-3
