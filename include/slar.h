@@ -416,6 +416,16 @@ slar_status slar_cnn_correct(const slar_grid* g, const slar_cnn* cnn, const doub
 slar_status slar_record_krylov(slar_workspace* ws, float* features, float* targets, int32_t capacity);
 int32_t slar_recorded_pairs(const slar_workspace* ws);
 
+/* Leaf bases of slar_truncate (Supplement B, HOSVD of the mode
+ * matricisations A): the eigenvectors E of A A^T carry errors of eps s_1^2
+ * / (gap of the squared singular values); the refinement pass (on = 1, the
+ * default) completes E to an orthonormal basis and re-diagonalises the
+ * Gram of E^T A, which brings the leaves to the accuracy of an SVD of A
+ * (about eps s_1 / gap).  on = 0 skips it: for FP32 frame tables, whose
+ * sampling error is far above either bound.  Returns SLAR_E_INVAL for a
+ * null workspace or on outside {0, 1}.                                     */
+slar_status slar_leaf_refine(slar_workspace* ws, int32_t on);
+
 /* Timing of the two sampling kernels of slar_cross_update.  on = 0 turns
  * it off; on = n >= 1 times every n-th iteration of each cross
  * approximation (iterations n-1, 2n-1, ...): its row-fiber and

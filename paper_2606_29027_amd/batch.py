@@ -90,6 +90,10 @@ class BatchSolver:
         self.kcross = min(2 * self.rmax, CCAP) if rmax is not None else \
             min(max(p.cross_cap for p in self.problems), CCAP)
         self.batch = L.Batch([L.make_grid(p) for p in self.problems], self.rmax)
+        # FP32 frame tables: their sampling error is far above the Gram
+        # accuracy of the leaf bases, so the truncation skips the refinement
+        for ws in self.batch.ws:
+            L.slar_leaf_refine(ws, False)
         self.inst = [_Inst(p) for p in self.problems]
         self.probes = None
         if probes is not None:

@@ -463,6 +463,12 @@ slar_status slar_lomac_project(const slar_grid* g, const slar_frames* Fstar_fram
   return lomac_project_run(stream, &w->w, *Fstar_frames, U_new, out);
 }
 
+slar_status slar_leaf_refine(slar_workspace* w, int32_t on) {
+  if (!w || (on != 0 && on != 1)) return SLAR_E_INVAL;
+  w->w.leaf_refine = on != 0;
+  return SLAR_OK;
+}
+
 slar_status slar_timing_enable(slar_workspace* w, int32_t on) {
   if (!w) return SLAR_E_INVAL;
   Workspace& ws = w->w;

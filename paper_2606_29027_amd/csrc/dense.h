@@ -16,8 +16,13 @@ hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* s
 hipError_t svd_left_big(hipStream_t s, int k, const double* M, double* W, double* sv);
 // Z[:, j] /= sv[j] for j < r (Z row-major, k rows, leading dimension ld)
 hipError_t scale_cols_inv(hipStream_t s, int k, int r, double* Z, int ld, const double* sv);
+// at most EIG_COLS eigenpairs come back nonzero (the factor's column cap)
+constexpr int EIG_COLS = 64;
 hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* const* G,
                          double* const* lam, double* const* V);
+// fill the zero columns of up to four row-major n x n matrices whose other
+// columns are orthonormal, so that each becomes an orthonormal basis
+hipError_t complete_basis_batch(hipStream_t s, int count, const int* n, double* const* E);
 hipError_t sign_fix(hipStream_t s, int rows, int cols, double* A, int lda, double* B, int ldb, int rowsB);
 // the same rule for tall A (cols <= 64) in three coalesced passes; scratch
 // holds (min(256, rows / 64) + 1) cols doubles (else the one-pass form runs)

@@ -722,7 +722,7 @@ hipError_t scale_cols_inv(hipStream_t s, int k, int r, double* Z, int ld, const 
 // Eigenvalues beyond the factor rank are returned as 0 with zero vectors,
 // except that lam[c] (c < n) receives the trace left after c columns, so
 // that tail sums over lam never undercount.
-constexpr int EIG_CM = 64;
+constexpr int EIG_CM = EIG_COLS;
 
 struct EigBatch {
   int n[4];
@@ -856,6 +856,118 @@ hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* c
     B.n[i] = n[i]; B.G[i] = G[i]; B.lam[i] = lam[i]; B.U[i] = V[i];
   }
   k_eig_psd<<<count, 512, 0, s>>>(B);
+  return hipGetLastError();
+}
+
+// Completion of an orthonormal set to a basis of R^n (n <= 128): E is
+// row-major n x n, column j either a unit vector of the set or zero (as the
+// eigen kernel leaves the columns past its factor rank).  Each zero column,
+// in order, becomes the unit vector e_p with the largest residual
+// 1 - sum_c E[p][c]^2 (lowest p on ties), orthogonalised twice against every
+// filled column and normalised.  One block per matrix, 512 threads, the
+// matrix in LDS column-major.
+struct CompleteBatch {
+  int n[4];
+  double* E[4];
+};
+
+__global__ __launch_bounds__(512) void k_complete_basis(CompleteBatch B) {
+  const int n = B.n[blockIdx.x];
+  double* __restrict__ E = B.E[blockIdx.x];
+  __shared__ double C[SLAR_NMAX * SLAR_NMAX];   // column c at C + c * SLAR_NMAX
+  __shared__ double res[SLAR_NMAX], v[SLAR_NMAX], h[SLAR_NMAX], part[4][SLAR_NMAX];
+  __shared__ unsigned char filled[SLAR_NMAX];
+  __shared__ double red[8];
+  __shared__ int redi[8];
+  const int t = threadIdx.x;
+  for (int e = t; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e % n;
+    C[c * SLAR_NMAX + r] = E[e];
+  }
+  __syncthreads();
+  for (int c = t; c < n; c += blockDim.x) {
+    double a = 0.0;
+    for (int r = 0; r < n; ++r) a += C[c * SLAR_NMAX + r] * C[c * SLAR_NMAX + r];
+    filled[c] = a > 0.5;
+  }
+  __syncthreads();
+  for (int r = t; r < n; r += blockDim.x) {
+    double a = 0.0;
+    for (int c = 0; c < n; ++c)
+      if (filled[c]) a += C[c * SLAR_NMAX + r] * C[c * SLAR_NMAX + r];
+    res[r] = 1.0 - a;
+  }
+  __syncthreads();
+  const int row = t & 127, grp = t >> 7;   // 4 groups of 128 threads
+  for (int z = 0; z < n; ++z) {
+    if (filled[z]) continue;   // uniform: filled is in LDS and only changes below
+    // pivot: largest residual, lowest index on ties
+    double m = -1.0;
+    int mi = n;
+    for (int r = t; r < n; r += blockDim.x)
+      if (res[r] > m) { m = res[r]; mi = r; }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double m2 = __shfl_xor(m, o, 64);
+      const int i2 = __shfl_xor(mi, o, 64);
+      if (m2 > m || (m2 == m && i2 < mi)) { m = m2; mi = i2; }
+    }
+    if ((t & 63) == 0) { red[t >> 6] = m; redi[t >> 6] = mi; }
+    __syncthreads();
+    int p = redi[0];
+    double mp = red[0];
+    for (int w = 1; w < 8; ++w)
+      if (red[w] > mp || (red[w] == mp && redi[w] < p)) { mp = red[w]; p = redi[w]; }
+    for (int r = t; r < n; r += blockDim.x) v[r] = (r == p) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      // h[c] = C[:, c] . v over the filled columns (one thread per column)
+      for (int c = t; c < n; c += blockDim.x) {
+        double a = 0.0;
+        if (filled[c])
+          for (int r = 0; r < n; ++r) a += C[c * SLAR_NMAX + r] * v[r];
+        h[c] = a;
+      }
+      __syncthreads();
+      // v[r] -= sum_c C[r][c] h[c]: four column groups per row
+      if (row < n) {
+        double a = 0.0;
+        for (int c = grp; c < n; c += 4) a += C[c * SLAR_NMAX + row] * h[c];
+        part[grp][row] = a;
+      }
+      __syncthreads();
+      if (t < n) v[t] -= (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+      __syncthreads();
+    }
+    double a = 0.0;
+    for (int r = t; r < n; r += blockDim.x) a += v[r] * v[r];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((t & 63) == 0) red[t >> 6] = a;
+    __syncthreads();
+    double nv = 0.0;
+    for (int w = 0; w < 8; ++w) nv += red[w];
+    const double inv = 1.0 / sqrt(nv);
+    for (int r = t; r < n; r += blockDim.x) {
+      const double x = v[r] * inv;
+      C[z * SLAR_NMAX + r] = x;
+      res[r] -= x * x;
+    }
+    if (t == 0) filled[z] = 1;
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e % n;
+    E[e] = C[c * SLAR_NMAX + r];
+  }
+}
+
+hipError_t complete_basis_batch(hipStream_t s, int count, const int* n, double* const* E) {
+  if (count < 1 || count > 4) return hipErrorInvalidValue;
+  CompleteBatch B{};
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > SLAR_NMAX) return hipErrorInvalidValue;
+    B.n[i] = n[i]; B.E[i] = E[i];
+  }
+  k_complete_basis<<<count, 512, 0, s>>>(B);
   return hipGetLastError();
 }
 

@@ -89,6 +89,9 @@ struct Workspace {
   // hardware queues)
   hipStream_t aux = nullptr;
   bool fork_aux = true;
+  // refinement pass of the leaf bases in the truncation (accuracy to the
+  // singular-value gaps instead of the squared ones); on by default
+  bool leaf_refine = true;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional in-stream event timing of the cross-approximation sampling
   // kernels: [0] row ms, [1] row launches, [2] row bytes, [3] col ms,

@@ -9,10 +9,18 @@
 //      theta = tol ||s|| / sqrt(2d - 3), capped at rmax; frames
 //      X = Qu^T W_r, Y = Qv^T Z_r, sign rule on X (flip Y alike);
 //   4. d = 2: leaves X, Y, root diag(s_r);
-//      d = 4: per side, Gram matrices of the two mode matricisations of
-//      frame * diag(s) (split-K GEMMs), Jacobi eigendecompositions, leaf =
-//      leading eigenvectors (same theta on sqrt(eigenvalue) tails, sign
-//      rule), transfer tensor = frame projected on the two leaf bases.
+//      d = 4: per side, Gram matrices of the two mode matricisations A of
+//      frame * diag(s) (split-K GEMMs) and their Jacobi eigendecompositions
+//      E; then (unless switched off for the workspace) one refinement pass:
+//      E completed to an orthonormal basis of the mode's grid, the rotated
+//      matricisation E^T A has a nearly diagonal Gram whose entries carry
+//      rounding relative to their own rows, so its eigenvectors V are
+//      accurate to the singular-value gaps rather than the squared ones;
+//      leaf = leading columns of E V (same theta on sqrt(eigenvalue)
+//      tails, sign rule), transfer tensor = frame projected on the two
+//      leaf bases.  The completion matters: directions missing from E
+//      (past the eigen factor's rank) leave the refined small-eigenvalue
+//      vectors no more accurate than the first ones.
 #include <cmath>
 #include <vector>
 
@@ -61,8 +69,8 @@ static Tbuf carve(Workspace* ws) {
   b.Y = p; p += (size_t)G.nv * K;
   b.Xs = p; p += (size_t)G.nx * K;
   b.Ys = p; p += (size_t)G.nv * K;
-  b.T = p; p += K * SLAR_NMAX * K;
-  b.T2 = p; p += K * SLAR_NMAX * K;
+  b.T = p; p += NN * K;
+  b.T2 = p; p += NN * K;
   for (Chain* c : {&b.cu, &b.cv}) {
     c->G = p; p += CK * CK;
     c->Linv = p; p += CK * CK;
@@ -84,7 +92,7 @@ static Tbuf carve(Workspace* ws) {
   b.E2 = p; p += NN;
   b.E3 = p; p += NN;
   b.E4 = p; p += NN;
-  b.Vw = p; p += NN;
+  b.Vw = p; p += 4 * NN;
   b.lam1 = p; p += SLAR_NMAX;
   b.lam2 = p; p += SLAR_NMAX;
   b.lam3 = p; p += SLAR_NMAX;
@@ -95,7 +103,7 @@ static Tbuf carve(Workspace* ws) {
 size_t truncate_scratch_elems(const GridDev& G) {
   const size_t K = SLAR_KMAX, NN = (size_t)SLAR_NMAX * SLAR_NMAX, CK = SLAR_CROSS_KMAX;
   return 2 * CK * G.nx + 2 * CK * G.nv + 2 * (size_t)G.nx * K + 2 * (size_t)G.nv * K +
-         2 * K * SLAR_NMAX * K + 12 * CK * CK + CK + 9 * NN + 4 * SLAR_NMAX + 64;
+         2 * NN * K + 12 * CK * CK + CK + 12 * NN + 4 * SLAR_NMAX + 64;
 }
 
 // Orthonormal rows Q (k x n) and upper R (k x k) with A = R^T Q... i.e.
@@ -139,10 +147,10 @@ static hipError_t join(hipStream_t s, Workspace* ws) {
 // Leaf bases (leading eigenvectors, sign rule) and the transfer tensor of
 // one side once the eigendecompositions are known.
 static slar_status side_finish(hipStream_t s, double* T, const double* frame, int na, int nb, int r,
-                               const double* Ea, const double* Eb, int ra, int rb, double* Ua,
-                               double* Ub, double* Bt) {
-  if (copy2d(s, na, ra, Ea, na, Ua, ra, nullptr) != hipSuccess) return SLAR_E_HIP;
-  if (copy2d(s, nb, rb, Eb, nb, Ub, rb, nullptr) != hipSuccess) return SLAR_E_HIP;
+                               const double* Ea, int lda, const double* Eb, int ldb, int ra, int rb,
+                               double* Ua, double* Ub, double* Bt) {
+  if (copy2d(s, na, ra, Ea, lda, Ua, ra, nullptr) != hipSuccess) return SLAR_E_HIP;
+  if (copy2d(s, nb, rb, Eb, ldb, Ub, rb, nullptr) != hipSuccess) return SLAR_E_HIP;
   if (sign_fix(s, na, ra, Ua, ra, nullptr, 0, 0) != hipSuccess) return SLAR_E_HIP;
   if (sign_fix(s, nb, rb, Ub, rb, nullptr, 0, 0) != hipSuccess) return SLAR_E_HIP;
   // T[a][(i2, c)] = sum_i1 Ua[i1][a] frame[i1][(i2, c)]
@@ -154,6 +162,23 @@ static slar_status side_finish(hipStream_t s, double* T, const double* frame, in
                (long long)rb * r, ra) != hipSuccess)
     return SLAR_E_HIP;
   return SLAR_OK;
+}
+
+// Refinement Grams of one side: with Ea, Eb the eigenvector matrices of
+// the two mode Grams (row-major na x na / nb x nb, eigenvector j in column
+// j) and c = min(n, 64) leading columns, Ga' = (Ea_c^T A_a)(Ea_c^T A_a)^T
+// and Gb' likewise for mode 2 (c x c each).  Xs = frame * diag(s) packed
+// [na][nb][r]; T is scratch of c * max(na, nb) * r doubles.
+static hipError_t side_refine_grams(hipStream_t s, const Scratch& part, const double* Xs, int na, int nb,
+                                    int r, const double* Ea, const double* Eb, int ca, int cb, double* T,
+                                    double* Ga, double* Gb) {
+  // mode 1: T[a][(i2, c)] = sum_i1 Ea[i1][a] Xs[i1][(i2, c)], a < ca
+  HIP_CHK(gemm_f64(s, true, false, ca, nb * r, na, 1.0, Ea, na, 0, Xs, nb * r, 0, 0.0, T, nb * r, 0, 1));
+  HIP_CHK(gram_rows(s, part, ca, nb * r, T, nb * r, Ga));
+  // mode 2: T[i1][b][c] = sum_i2 Eb[i2][b] Xs[i1][i2][c], b < cb (batched over i1)
+  HIP_CHK(gemm_f64(s, true, false, cb, r, nb, 1.0, Eb, nb, 0, Xs, r, (long long)nb * r, 0.0, T, r,
+                   (long long)cb * r, na));
+  return gram_mode2(s, part, na, cb, r, T, Gb);
 }
 
 static int leaf_rank(const std::vector<double>& lam, double theta, int rmax, bool* capped) {
@@ -240,10 +265,39 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
       return SLAR_E_HIP;
     if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
     const int nn[4] = {G.n[0], G.n[1], G.n[2], G.n[3]};
+    double* Gw[4] = {b.G1, b.G2, b.G3, b.G4};
     const double* Gs[4] = {b.G1, b.G2, b.G3, b.G4};
     double* lams[4] = {b.lam1, b.lam2, b.lam3, b.lam4};
     double* Es[4] = {b.E1, b.E2, b.E3, b.E4};
     if (eig_sym_batch(s, 4, nn, Gs, lams, Es) != hipSuccess) return SLAR_E_HIP;
+    // leaf bases and their leading dimensions: the eigenvectors, or (with
+    // the refinement pass) E V, where E is the eigenvector set completed to
+    // an orthonormal basis of the mode's grid and V the eigenvectors of the
+    // Gram of E^T A, nearly diagonal (into G1..G4, four n x n blocks of Vw)
+    const double* Ub[4] = {b.E1, b.E2, b.E3, b.E4};
+    int ldu[4] = {nn[0], nn[1], nn[2], nn[3]};
+    if (ws->leaf_refine) {
+      if (complete_basis_batch(s, 4, nn, Es) != hipSuccess) return SLAR_E_HIP;
+      if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
+      if (side_refine_grams(s, b.cu.part, b.Xs, G.n[0], G.n[1], r, b.E1, b.E2, nn[0], nn[1], b.T, b.G1,
+                            b.G2) != hipSuccess)
+        return SLAR_E_HIP;
+      if (side_refine_grams(sa, b.cv.part, b.Ys, G.n[2], G.n[3], r, b.E3, b.E4, nn[2], nn[3], b.T2, b.G3,
+                            b.G4) != hipSuccess)
+        return SLAR_E_HIP;
+      if (join(s, ws) != hipSuccess) return SLAR_E_HIP;
+      double* Vs[4];
+      for (int m = 0; m < 4; ++m) Vs[m] = b.Vw + (size_t)m * SLAR_NMAX * SLAR_NMAX;
+      if (eig_sym_batch(s, 4, nn, Gs, lams, Vs) != hipSuccess) return SLAR_E_HIP;
+      for (int m = 0; m < 4; ++m) {
+        const int c2 = std::min(nn[m], EIG_COLS);
+        if (gemm_f64(s, false, false, nn[m], c2, nn[m], 1.0, Es[m], nn[m], 0, Vs[m], nn[m], 0, 0.0, Gw[m],
+                     c2, 0, 1) != hipSuccess)
+          return SLAR_E_HIP;
+        Ub[m] = Gw[m];
+        ldu[m] = c2;
+      }
+    }
     std::vector<double> lh(4 * SLAR_NMAX);
     for (int m = 0; m < 4; ++m)
       HIP_TRY(hipMemcpyAsync(lh.data() + m * SLAR_NMAX, lams[m], sizeof(double) * nn[m],
@@ -256,10 +310,10 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
       rk[m] = leaf_rank(l, theta, rmax, &capped);
     }
     if (fork(s, ws) != hipSuccess) return SLAR_E_HIP;
-    slar_status st = side_finish(s, b.T, b.X, G.n[0], G.n[1], r, b.E1, b.E2, rk[0], rk[1],
+    slar_status st = side_finish(s, b.T, b.X, G.n[0], G.n[1], r, Ub[0], ldu[0], Ub[1], ldu[1], rk[0], rk[1],
                                  (double*)out->leaf[0], (double*)out->leaf[1], (double*)out->B12);
     if (st != SLAR_OK) return st;
-    st = side_finish(sa, b.T2, b.Y, G.n[2], G.n[3], r, b.E3, b.E4, rk[2], rk[3],
+    st = side_finish(sa, b.T2, b.Y, G.n[2], G.n[3], r, Ub[2], ldu[2], Ub[3], ldu[3], rk[2], rk[3],
                      (double*)out->leaf[2], (double*)out->leaf[3], (double*)out->B34);
     if (st != SLAR_OK) return st;
     if (join(s, ws) != hipSuccess) return SLAR_E_HIP;

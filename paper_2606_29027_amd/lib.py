@@ -24,7 +24,7 @@ EXPORTS = (
     "slar_moments", "slar_poisson", "slar_conserved", "slar_lomac_prepare", "slar_macro_solve",
     "slar_lomac_project", "slar_cnn_create", "slar_cnn_destroy", "slar_cnn_nparams",
     "slar_cnn_set_params", "slar_cnn_get_params", "slar_cnn_forward", "slar_cnn_grad",
-    "slar_cnn_train_step", "slar_record_krylov", "slar_recorded_pairs", "slar_timing_enable",
+    "slar_cnn_train_step", "slar_record_krylov", "slar_recorded_pairs", "slar_timing_enable", "slar_leaf_refine",
     "slar_timing_read", "slar_batch_create", "slar_batch_destroy", "slar_batch_workspace",
     "slar_batch_cross_update", "slar_batch_truncate", "slar_batch_efield", "slar_batch_get_config",
     "slar_batch_set_config", "slar_batch_tune", "slar_batch_timing", "slar_batch_timing_reset",
@@ -122,6 +122,7 @@ def load(path: str = LIB_PATH):
         "slar_record_krylov": (i32, [vp, vp, vp, i32]),
         "slar_recorded_pairs": (i32, [vp]),
         "slar_timing_enable": (i32, [vp, i32]),
+        "slar_leaf_refine": (i32, [vp, i32]),
         "slar_timing_read": (i32, [vp, P(C.c_double)]),
         "slar_batch_create": (i32, [i32, P(Grid), i32, P(vp)]),
         "slar_batch_destroy": (i32, [vp]),
@@ -452,6 +453,11 @@ def slar_record_krylov(ws, feats, targs, capacity):
 
 def slar_recorded_pairs(ws) -> int:
     return int(load().slar_recorded_pairs(ws.h))
+
+
+def slar_leaf_refine(ws, on: bool):
+    """Switch the refinement pass of the truncation's leaf bases."""
+    _check(load().slar_leaf_refine(ws.h, 1 if on else 0), "slar_leaf_refine")
 
 
 def slar_timing_enable(ws, on, every: int = 1):

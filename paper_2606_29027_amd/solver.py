@@ -38,6 +38,9 @@ class Solver:
         self.grid = L.make_grid(p)
         self.ws = L.Workspace(self.grid, min(p.rmax, RCAP))
         self.prec = precision
+        # the truncation's leaf refinement buys FP64-level agreement; with FP32
+        # frame tables the sampling error is far above the Gram accuracy
+        L.slar_leaf_refine(self.ws, precision == L.F64)
         self.delta = delta
         self.precond = precond
         self.cnn = cnn

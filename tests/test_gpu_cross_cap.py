@@ -95,8 +95,7 @@ def test_cross_past_64_terms_matches_oracle():
 def test_truncate_of_more_than_64_terms_matches_oracle():
     """The truncation of a k > 64 cross to rank <= 64 (Cholesky-QR of 128
     columns, left-vector Jacobi SVD, right vectors M^T w / s) reconstructs
-    the oracle's truncated tensor (QR + SVD) to the conditioning of the
-    kept singular values."""
+    the oracle's truncated tensor (QR + SVD) to 1e-12."""
     c = _setup(N=24, smooth=True)
     p = c["p"]
     pr = torch.as_tensor(c["probes"], dtype=torch.int32, device="cuda")
@@ -122,7 +121,7 @@ def test_truncate_of_more_than_64_terms_matches_oracle():
     got = HT.full(ht_from_dev(H, T, 4, n))
     # the best rank-48 approximation: its error is set by the tail, the
     # difference between two computations of it by rounding of the kept part
-    assert normwise(got, ref) < 1e-9
+    assert normwise(got, ref) < 1e-12, normwise(got, ref)
     assert np.linalg.norm(got) <= np.linalg.norm(Uf @ Vf.T) * (1 + 1e-12)
 
 

@@ -228,8 +228,9 @@ def _lowrank_input(nx, nv, k, seed, decay=0.5):
                                           ("landau2d", 16, 30, 1e-5), ("landau2d", 24, 9, 1e-8)])
 def test_truncate_matches_oracle(name, N, k, tol):
     """slar_truncate vs the oracle's QR + SVD truncation on the same factors:
-    same ranks; reconstructed tensors agree to the truncation-conditioning
-    bound eps * sigma_1^2 / theta (see the module docstring of the step test)."""
+    same ranks; reconstructed tensors agree to 1e-12 (the refined leaf bases
+    are as accurate as SVDs of the unfoldings; the unrefined Gram
+    eigenvectors alone would carry eps sigma_1^2 / theta)."""
     from oracle import cross as CR
     p = SI.config(name, n=N)
     nx = tuple(p.n[: p.dx]); nv = tuple(p.n[p.dx:])
@@ -248,10 +249,7 @@ def test_truncate_matches_oracle(name, N, k, tol):
     Fg = ht_from_dev(H, T, p.d, p.n)
     assert tuple(H.rank[: (2 if p.d == 2 else 6)]) == HT.ranks(Fo)
     err = normwise(HT.full(Fg), HT.full(Fo))
-    sv = np.linalg.svd(U.T @ V, compute_uv=False)
-    theta = tol * np.linalg.norm(sv) / np.sqrt(2 * p.d - 3)
-    bound = 64 * np.finfo(float).eps * sv[0] ** 2 / theta / np.abs(HT.full(Fo)).max()
-    assert err < max(1e-12, bound), (err, bound)
+    assert err < 1e-12, err
     # column 0 of every leaf is the leading left singular vector of its mode
     for m in range(p.d):
         assert abs(abs(Fg["leaves"][m][:, 0] @ Fo["leaves"][m][:, 0]) - 1) < 1e-10

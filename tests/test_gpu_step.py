@@ -2,14 +2,16 @@
 the CPU oracle on the same seeded inputs.
 
 Both sides run the same deterministic pivoting rules in FP64, so the pivots
-and ranks coincide.  The reconstructed tensors then agree to a tolerance set
-by the conditioning of the leaf truncation: the GPU takes leaf bases from
-Jacobi eigenvectors of FP64 Gram matrices (the oracle from SVDs of the
-unfoldings), and a Gram eigenvector of a kept singular value sigma carries
-an error of about eps sigma_1^2 / sigma^2, i.e. eps sigma_1^2 / sigma in the
-tensor.  With sigma >= theta = tol ||F|| / sqrt(2d - 3) and at most r kept
-directions per leaf this is at most r eps sqrt(2d - 3) / tol of ||F|| per
-truncation; fp64_bound() adds it over the truncations of the run.
+and ranks coincide.  The GPU takes leaf bases from Jacobi eigenvectors of
+FP64 Gram matrices refined once (the eigenvector set completed to a basis,
+the rotated matricisation's nearly diagonal Gram diagonalised again), which
+brings them to the accuracy of the oracle's SVDs of the unfoldings; the
+reconstructed tensors then differ by rounding, held at 1e-13 of ||F|| per
+truncation of the run (2e-14 .. 3.4e-14 measured).  With LoMaC both sides
+also stop Newton at different iterates within the same RMS tolerance: the
+oracle itself moves by delta_N when its tolerance drops tenfold, and the
+bar adds 4 delta_N (about 8e-12 on the 256-cell 1D1V setups at CFL 5, where
+the implicit system amplifies the tolerance; below 1e-14 on 12^4).
 Conservation is exact up to round-off and checked at 1e-12."""
 import numpy as np
 import pytest
@@ -29,9 +31,17 @@ from paper_2606_29027_amd.solver import Solver  # noqa: E402
 from gpu_util import normwise  # noqa: E402
 
 
-def fp64_bound(p, truncations):
-    """Gram-conditioning bound of the module docstring (relative, normwise)."""
-    return truncations * p.rmax * np.finfo(float).eps * np.sqrt(2 * p.d - 3) / p.tol
+def fp64_bound(truncations, newton_shift=0.0):
+    """Bar of the module docstring (relative, normwise)."""
+    return 1e-13 * truncations + 4.0 * newton_shift
+
+
+def newton_shift(p, pr, F0, steps, dts=None):
+    """delta_N: how far the oracle's own state moves when its Newton
+    tolerance drops from 1e-13 to 1e-14."""
+    a = HT.full(ST.Oracle(p, probes=pr, newton_tol=1e-13).run(F0, steps, dts=dts)[0])
+    b = HT.full(ST.Oracle(p, probes=pr, newton_tol=1e-14).run(F0, steps, dts=dts)[0])
+    return normwise(a, b)
 
 
 def _probes(p):
@@ -54,7 +64,7 @@ def test_plain_slar_steps_match_oracle(name, N, steps):
         s.step()
     assert [st["rank"] for st in s.stats] == [st["rank"] for st in o.stats]
     err = normwise(s.dense(), HT.full(Fo))
-    assert err < fp64_bound(p, 3 * steps), err   # conditioning bound, see module docstring
+    assert err < fp64_bound(3 * steps), err
 
 
 @pytest.mark.parametrize("prec", [L.F64, L.F32])
@@ -77,7 +87,7 @@ def test_lomac_steps_match_oracle_and_conserve(prec):
     assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
     assert max(abs(m) for m in d["momentum"]) < 1e-12 * d0["mass"]
     err = normwise(s.dense(), HT.full(Fo))
-    assert err < (fp64_bound(p, 6) if prec == L.F64 else 10 * p.tol), err
+    assert err < (fp64_bound(6, newton_shift(p, pr, F0, 2)) if prec == L.F64 else 10 * p.tol), err
 
 
 def test_spectral_preconditioner_same_root_fewer_iterations():
@@ -132,7 +142,8 @@ def test_dirk3_bdf3_steps_match_oracle_and_conserve(prec):
     assert max(abs(m) for m in d["momentum"]) < 1e-12 * d0["mass"]
     err = normwise(s.dense(), HT.full(Fo))
     assert len(s.stats) == 24
-    assert err < (fp64_bound(p, 24) if prec == L.F64 else 4 * p.tol * 24), err
+    assert err < (fp64_bound(24, newton_shift(p, pr, F0, len(dts), dts)) if prec == L.F64
+                  else 4 * p.tol * 24), err
 
 
 def p_tol(name):
@@ -222,4 +233,4 @@ def test_paper_workloads_match_oracle_and_conserve(name, N, steps):
     assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
     assert max(abs(m - m0) for m, m0 in zip(d["momentum"], d0["momentum"])) < 1e-12 * d0["mass"]
     err = normwise(s.dense(), HT.full(Fo))
-    assert err < fp64_bound(p, 9 * 2 + 3 * (steps - 2)), err
+    assert err < fp64_bound(9 * 2 + 3 * (steps - 2), newton_shift(p, pr, F0, steps)), err
