@@ -10,6 +10,7 @@
 
 #include "slar_internal.h"
 #include "dense.h"
+#include "dpp.h"
 
 namespace slar {
 
@@ -176,14 +177,6 @@ hipError_t gram_mode2(hipStream_t s, const Scratch& part, int na, int nb, int r,
 }
 
 // --------------------------------------------------- Cholesky-QR helpers
-// Lane exchange inside a DPP row (CTRL: quad_perm / mirror patterns).
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 
 // From Gram G (k x k): column scaling d = sqrt(diag G), Cholesky of
 // D^-1 G D^-1 = L L^T.  Writes Linv_scaled = L^-1 D^-1 (k x k, lower) and

@@ -12,6 +12,7 @@
 // small rank (r < 4 TEAM) against samples per team; 16 is the default.
 #pragma once
 #include "slar_internal.h"
+#include "dpp.h"
 
 namespace slar {
 
@@ -30,7 +31,7 @@ struct FsLds {
 
 // Phase 1 for one sample: grid multi-index -> stencil rows and weights.
 // NL = 4: the four lanes of a quad share the foot computation (all pass the
-// same sample); lane 0 writes the LDS entries.
+// same sample) and the LDS writes.
 template <int W, int DX, int NL = 1>
 __device__ __forceinline__ void fs_prepare(const GridDev& g, const AdvDev& a, const int* gidx,
                                            FsLds<W, DX>& L, int s, int lane = 0) {
@@ -40,23 +41,27 @@ __device__ __forceinline__ void fs_prepare(const GridDev& g, const AdvDev& a, co
   double w[4][W];
 #pragma unroll
   for (int m = 0; m < 2 * DX; ++m) stencil_of<W>(g, a, m, ft[m], gidx[m], r[m], w[m]);
-  if (lane != 0) return;
   if (DX == 1) {
+    if (lane != 0) return;
 #pragma unroll
     for (int b = 0; b < W; ++b) {
       L.xrow[s][b] = r[0][b]; L.xw[s][b] = w[0][b];
       L.vrow[s][b] = r[1][b]; L.vw[s][b] = w[1][b];
     }
   } else {
+    // the W^2 entries are shared out over the lanes of the quad
     const int n1 = g.n[1], n3 = g.n[3];
 #pragma unroll
     for (int p = 0; p < W; ++p)
 #pragma unroll
       for (int q = 0; q < W; ++q) {
-        L.xrow[s][p * W + q] = r[0][p] * n1 + r[1][q];
-        L.xw[s][p * W + q] = w[0][p] * w[1][q];
-        L.vrow[s][p * W + q] = r[2][p] * n3 + r[3][q];
-        L.vw[s][p * W + q] = w[2][p] * w[3][q];
+        const int e = p * W + q;
+        if (NL == 1 || (e % NL) == lane) {
+          L.xrow[s][e] = r[0][p] * n1 + r[1][q];
+          L.xw[s][e] = w[0][p] * w[1][q];
+          L.vrow[s][e] = r[2][p] * n3 + r[3][q];
+          L.vw[s][e] = w[2][p] * w[3][q];
+        }
       }
   }
 }
@@ -79,36 +84,62 @@ template <> struct Vec4<double> {
 };
 
 // Phase 2: values of the prepared samples [0, ns) into L.val (FP64).
-// Tables are [rows][ld] with ld % 4 == 0 and zero columns beyond r.
+// Tables are [rows][ld] with ld % 4 == 0 and zero columns beyond r.  With
+// FP32 tables a team keeps the gathers of two samples in flight (all their
+// row loads issued before the first FMA), so a block's 64 samples take two
+// rounds of L2 latency instead of four; FP64 tables keep one sample per
+// pass (twice the registers per row).  The team's partial dot products are
+// summed with DPP row exchanges.
 template <typename T, int W, int DX, int TEAM = 16>
 __device__ __forceinline__ void fs_evaluate(const T* __restrict__ X, const T* __restrict__ P,
                                             int ld, int r, FsLds<W, DX>& L, int ns) {
   static_assert(TEAM == 4 || TEAM == 8 || TEAM == 16, "team width");
   constexpr int RX = FsLds<W, DX>::RX;
+  constexpr int NT = FS_THREADS / TEAM;
+  constexpr int UNR = (sizeof(T) == 4) ? 2 : 1;
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
-  for (int s = team; s < ns; s += FS_THREADS / TEAM) {
-    T acc = 0;
+  for (int s0 = team; s0 < ns; s0 += UNR * NT) {
+    int sm[UNR];
+    bool ok[UNR];
+    T acc[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      ok[u] = s0 + u * NT < ns;
+      sm[u] = ok[u] ? s0 + u * NT : s0;   // a valid sample's rows; result dropped
+      acc[u] = 0;
+    }
     for (int c0 = lane * 4; c0 < r; c0 += 4 * TEAM) {
-      T y[4] = {0, 0, 0, 0}, z[4] = {0, 0, 0, 0};
+      T vx[UNR][RX][4], vp[UNR][RX][4];
 #pragma unroll
-      for (int b = 0; b < RX; ++b) {
-        T v[4];
-        const T wx = (T)L.xw[s][b];
-        Vec4<T>::load(X + (size_t)L.xrow[s][b] * ld + c0, v);
+      for (int u = 0; u < UNR; ++u)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) y[e] += wx * v[e];
-        const T wv = (T)L.vw[s][b];
-        Vec4<T>::load(P + (size_t)L.vrow[s][b] * ld + c0, v);
+        for (int b = 0; b < RX; ++b) {
+          Vec4<T>::load(X + (size_t)L.xrow[sm[u]][b] * ld + c0, vx[u][b]);
+          Vec4<T>::load(P + (size_t)L.vrow[sm[u]][b] * ld + c0, vp[u][b]);
+        }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) z[e] += wv * v[e];
+      for (int u = 0; u < UNR; ++u) {
+        T y[4] = {0, 0, 0, 0}, z[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < RX; ++b) {
+          const T wx = (T)L.xw[sm[u]][b];
+          const T wv = (T)L.vw[sm[u]][b];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            y[e] += wx * vx[u][b][e];
+            z[e] += wv * vp[u][b][e];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[u] += y[e] * z[e];
       }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc += y[e] * z[e];
     }
 #pragma unroll
-    for (int o = TEAM / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, TEAM);
-    if (lane == 0) L.val[s] = (double)acc;
+    for (int u = 0; u < UNR; ++u) {
+      const T tot = group_sum<TEAM>(acc[u]);
+      if (lane == 0 && ok[u]) L.val[sm[u]] = (double)tot;
+    }
   }
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/slar.h"
+#include "dpp.h"
 
 namespace slar {
 
@@ -172,8 +173,8 @@ __device__ __forceinline__ void efield_all(const GridDev& g, const AdvDev& ad, c
       f0 += w0[a] * v.x; f1 += w0[a] * v.y;
     }
     double s0 = ad.cE0 * (wq * e0 + w2 * f0), s1 = ad.cE0 * (wq * e1 + w2 * f1);
-    s0 += __shfl_xor(s0, 1, 4); s1 += __shfl_xor(s1, 1, 4);
-    s0 += __shfl_xor(s0, 2, 4); s1 += __shfl_xor(s1, 2, 4);
+    s0 = group_sum<4>(s0);
+    s1 = group_sum<4>(s1);
     out[0] = s0;
     out[1] = s1;
     return;
@@ -191,22 +192,24 @@ __device__ __forceinline__ void efield_all(const GridDev& g, const AdvDev& ad, c
     for (int b = 0; b < 5; ++b) r += w1[b] * efield_node<TWO>(ad, efield_off(g, ad, ra * n1 + col[b], c));
     acc += wa * r;
   }
-  acc += __shfl_xor(acc, 2, 4);                 // both row halves (a + b == b + a: same in both lanes)
-  const double other = __shfl_xor(acc, 1, 4);   // the other component
+  acc += dpp_move<0x4E>(acc);                 // both row halves (a + b == b + a: same in both lanes)
+  const double other = dpp_move<0xB1>(acc);   // the other component
   out[0] = (c == 0) ? acc : other;
   out[1] = (c == 0) ? other : acc;
 }
 
 // RK4 backwards along the frozen-field flow: d/ds (X, V) = (-c V, +E(X)),
 // s in [0, tau], from the grid point (X, V).
+// The first stage evaluates the field at the grid node itself, where the
+// interpolant equals the nodal value: it is read directly.
 template <int DX, int NL, bool TWO>
 __device__ __forceinline__ void foot_rk4(const GridDev& g, const AdvDev& a, const double* X,
-                                         const double* V, double* out, int lane) {
+                                         const double* V, int node, double* out, int lane) {
   constexpr int dx = DX;
   const double t = a.tau, c = a.cv;
   double k1x[2], k1v[2], k2x[2], k2v[2], k3x[2], k3v[2], k4x[2], k4v[2], Y[2];
   for (int m = 0; m < dx; ++m) k1x[m] = -c * V[m];
-  efield_all<DX, NL, TWO>(g, a, X, lane, k1v);
+  for (int m = 0; m < dx; ++m) k1v[m] = efield_node<TWO>(a, efield_off(g, a, node, m));
   for (int m = 0; m < dx; ++m) Y[m] = X[m] + 0.5 * t * k1x[m];
   for (int m = 0; m < dx; ++m) k2x[m] = -c * (V[m] + 0.5 * t * k1v[m]);
   efield_all<DX, NL, TWO>(g, a, Y, lane, k2v);
@@ -247,8 +250,9 @@ __device__ __forceinline__ void foot_of(const GridDev& g, const AdvDev& a, const
     }
     return;
   }
-  if (a.E1 != nullptr) foot_rk4<DX, NL, true>(g, a, X, V, out, lane);
-  else foot_rk4<DX, NL, false>(g, a, X, V, out, lane);
+  const int node = (DX == 2) ? idx[0] * g.n[1] + idx[1] : idx[0];
+  if (a.E1 != nullptr) foot_rk4<DX, NL, true>(g, a, X, V, node, out, lane);
+  else foot_rk4<DX, NL, false>(g, a, X, V, node, out, lane);
 }
 
 // Stencil rows (wrapped) and weights of dimension m for a foot coordinate.
