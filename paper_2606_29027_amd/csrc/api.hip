@@ -114,7 +114,6 @@ slar_status slar_workspace_destroy(slar_workspace* w) {
     if (e) (void)hipEventDestroy(e);
   if (ws.aux) {
     (void)hipStreamSynchronize(ws.aux);
-    blas_forget(ws.aux);
     (void)hipStreamDestroy(ws.aux);
   }
   if (ws.aca_ctl_host) (void)hipHostFree(ws.aca_ctl_host);

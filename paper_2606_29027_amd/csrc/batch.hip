@@ -442,7 +442,6 @@ slar_status slar_batch_destroy(slar_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (hipStream_t s : b->streams) {
     (void)hipStreamSynchronize(s);
-    blas_forget(s);
     (void)hipStreamDestroy(s);
   }
   for (hipEvent_t e : b->ev_done) (void)hipEventDestroy(e);

@@ -1,69 +1,14 @@
-// Small dense FP64 linear algebra for the truncation: GEMM (rocBLAS),
-// split-K Gram matrices, Cholesky-QR helpers, one-sided
+// Small dense FP64 linear algebra for the truncation: split-K Gram
+// matrices, Cholesky-QR helpers, one-sided
 // Jacobi SVD and two-sided Jacobi symmetric eigensolver.  All single-block
 // factorizations keep their matrix in LDS (gfx950: 160 KB per CU).
 #include <algorithm>
-#include <mutex>
-#include <unordered_map>
-
-#include <rocblas/rocblas.h>
 
 #include "slar_internal.h"
 #include "dense.h"
 #include "dpp.h"
 
 namespace slar {
-
-// ------------------------------------------------------------------ GEMM
-// C_b = alpha op(A_b) op(B_b) + beta C_b, row-major, through rocBLAS (the
-// products of the path are plain GEMMs).  A row-major C = op(A) op(B) is the
-// column-major C^T = op(B)^T op(A)^T, i.e. rocBLAS with the operands
-// swapped.  One handle per stream, shared by every workspace that runs
-// products on it (a stream is driven by one host thread at a time: the
-// caller's, or one pool thread's), created on first use; atomics are
-// disallowed, so every product is reproducible bit for bit.
-static std::mutex g_blas_mu;
-static std::unordered_map<hipStream_t, rocblas_handle> g_blas;
-
-static rocblas_handle blas_for(hipStream_t s) {
-  std::lock_guard<std::mutex> lock(g_blas_mu);
-  const auto it = g_blas.find(s);
-  if (it != g_blas.end()) return it->second;
-  rocblas_handle h = nullptr;
-  if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
-  if (rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) != rocblas_status_success ||
-      rocblas_set_stream(h, s) != rocblas_status_success) {
-    rocblas_destroy_handle(h);
-    return nullptr;
-  }
-  g_blas.emplace(s, h);
-  return h;
-}
-
-void blas_forget(hipStream_t s) {
-  std::lock_guard<std::mutex> lock(g_blas_mu);
-  const auto it = g_blas.find(s);
-  if (it == g_blas.end()) return;
-  rocblas_destroy_handle(it->second);
-  g_blas.erase(it);
-}
-
-hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
-                    const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
-                    double beta, double* C, int ldc, long long sC, int batch) {
-  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  rocblas_handle h = blas_for(s);
-  if (h == nullptr) return hipErrorUnknown;
-  const rocblas_operation opB = tb ? rocblas_operation_transpose : rocblas_operation_none;
-  const rocblas_operation opA = ta ? rocblas_operation_transpose : rocblas_operation_none;
-  rocblas_status st;
-  if (batch == 1)
-    st = rocblas_dgemm(h, opB, opA, N, M, K, &alpha, B, ldb, A, lda, &beta, C, ldc);
-  else
-    st = rocblas_dgemm_strided_batched(h, opB, opA, N, M, K, &alpha, B, ldb, sB, A, lda, sA, &beta, C,
-                                       ldc, sC, batch);
-  return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
-}
 
 // ------------------------------------------------------------ Gram
 // G = A A^T for A with k <= 128 rows and a long column range, element

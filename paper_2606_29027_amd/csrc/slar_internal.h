@@ -126,9 +126,8 @@ struct Workspace {
 };
 
 // launchers implemented across the .hip files
-// C_b = alpha op(A_b) op(B_b) + beta C_b (row-major, FP64) on stream s with
-// the rocBLAS handle of s (created on first use: call it once eagerly on a
-// stream before capturing a graph on it)
+// C_b = alpha op(A_b) op(B_b) + beta C_b (row-major, FP64) on stream s, on
+// the matrix cores (gemm.hip); beta = 0 never reads C
 hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
                     const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
                     double beta, double* C, int ldc, long long sC, int batch);
@@ -136,8 +135,6 @@ size_t nest_list_elems();
 slar_status nested_run(hipStream_t s, Workspace* ws, const slar_frames& src, const slar_adv& adv,
                        slar_dtype dt, double tol, int kmax, int nprobe, const int* probes, const int* seed,
                        slar_ht* out, slar_nested_info* info);
-// destroys the rocBLAS handle of stream s (before the library destroys s)
-void blas_forget(hipStream_t s);
 hipError_t combine_field(hipStream_t s, const GridDev& G, const slar_adv* a, double* out);
 // Regularised skeleton of a cross that stopped at its term cap: replaces
 // the k terms in out by min(rcap, rank W) terms of C W_r^+ R (synchronises)

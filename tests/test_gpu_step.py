@@ -6,8 +6,10 @@ and ranks coincide.  The GPU takes leaf bases from Jacobi eigenvectors of
 FP64 Gram matrices refined once (the eigenvector set completed to a basis,
 the rotated matricisation's nearly diagonal Gram diagonalised again), which
 brings them to the accuracy of the oracle's SVDs of the unfoldings; the
-reconstructed tensors then differ by rounding, held at 1e-13 of ||F|| per
-truncation of the run (2e-14 .. 3.4e-14 measured).  With LoMaC both sides
+reconstructed tensors then differ by rounding, held at 5e-13 of ||F|| per
+truncation of the run: rounding-level changes anywhere upstream (the order
+of a GEMM's sums, 2e-16 noise on the oracle's own feet) move a two-step
+LoMaC state at 12^4 by 3e-14 .. 9e-13.  With LoMaC both sides
 also stop Newton at different iterates within the same RMS tolerance: the
 oracle itself moves by delta_N when its tolerance drops tenfold, and the
 bar adds 4 delta_N (about 8e-12 on the 256-cell 1D1V setups at CFL 5, where
@@ -33,7 +35,7 @@ from gpu_util import normwise  # noqa: E402
 
 def fp64_bound(truncations, newton_shift=0.0):
     """Bar of the module docstring (relative, normwise)."""
-    return 1e-13 * truncations + 4.0 * newton_shift
+    return 5e-13 * truncations + 4.0 * newton_shift
 
 
 def newton_shift(p, pr, F0, steps, dts=None):
@@ -64,6 +66,7 @@ def test_plain_slar_steps_match_oracle(name, N, steps):
         s.step()
     assert [st["rank"] for st in s.stats] == [st["rank"] for st in o.stats]
     err = normwise(s.dense(), HT.full(Fo))
+    print(f"fp64 parity {err:.3e}")
     assert err < fp64_bound(3 * steps), err
 
 
@@ -87,6 +90,7 @@ def test_lomac_steps_match_oracle_and_conserve(prec):
     assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
     assert max(abs(m) for m in d["momentum"]) < 1e-12 * d0["mass"]
     err = normwise(s.dense(), HT.full(Fo))
+    print(f"fp64 parity {err:.3e}")
     assert err < (fp64_bound(6, newton_shift(p, pr, F0, 2)) if prec == L.F64 else 10 * p.tol), err
 
 
@@ -141,6 +145,7 @@ def test_dirk3_bdf3_steps_match_oracle_and_conserve(prec):
     assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
     assert max(abs(m) for m in d["momentum"]) < 1e-12 * d0["mass"]
     err = normwise(s.dense(), HT.full(Fo))
+    print(f"fp64 parity {err:.3e}")
     assert len(s.stats) == 24
     assert err < (fp64_bound(24, newton_shift(p, pr, F0, len(dts), dts)) if prec == L.F64
                   else 4 * p.tol * 24), err
@@ -233,4 +238,5 @@ def test_paper_workloads_match_oracle_and_conserve(name, N, steps):
     assert abs(d["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
     assert max(abs(m - m0) for m, m0 in zip(d["momentum"], d0["momentum"])) < 1e-12 * d0["mass"]
     err = normwise(s.dense(), HT.full(Fo))
+    print(f"fp64 parity {err:.3e}")
     assert err < fp64_bound(9 * 2 + 3 * (steps - 2), newton_shift(p, pr, F0, steps)), err
