@@ -17,6 +17,7 @@ CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -62,6 +63,32 @@ def measured_traffic():
         return None
 
 
+BATCH_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_batched_cross_64.md")
+BATCH_SOURCES = ("batch.hip", "aca.h", "frame_sampler.h", "sl_device.h")
+
+
+def measured_batch_traffic():
+    """HBM bytes per step of the batched cross approximation (FETCH_SIZE +
+    WRITE_SIZE over its launches in the timed steps, calibrated), from the
+    committed counter summary, or None when its kernels changed since."""
+    try:
+        vals = {}
+        with open(BATCH_TRAFFIC_SUMMARY) as fh:
+            for line in fh:
+                if ":" in line and line.split(":")[0].strip() in ("source_sha256", "traffic_bytes_per_step"):
+                    k, v = line.split(":", 1)
+                    vals[k.strip()] = v.strip().strip("`")
+        h = hashlib.sha256()
+        for fn in BATCH_SOURCES:
+            with open(os.path.join(ROOT, "paper_2606_29027_amd", "csrc", fn), "rb") as fh:
+                h.update(fh.read())
+        if vals.get("source_sha256") != h.hexdigest():
+            return None
+        return float(vals["traffic_bytes_per_step"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +107,9 @@ def parse():
                     help="batched: 64 independent 1D1V/2D2V Landau instances of uneven size")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch configuration")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="default workload: leave out the batched-instances leg of the line")
+    ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one device copy of this size (for counter calibration)")
     return ap.parse_args()
@@ -160,10 +190,48 @@ def cpu_baseline(p, budget_s: float):
             "threads_all": res["threads_all"], "threads_1": res["threads_1"]}
 
 
-def batched_main(args):
+def cpu_baseline_batched(problems, budget_s: float):
+    """The CPU oracle on a bounded sample of the batched workload: whole row
+    fibers of the instances' initial states at their first RK sub-flow (each
+    instance in its own field), frame-form evaluation, instances taken in
+    turn until budget_s has passed; entries/s at all host threads."""
+    import slar_inputs as SI
+    from oracle import feet as FT
+    from oracle import ht as HT
+    from oracle import step as ST
+    from threadpoolctl import threadpool_info
+    nthreads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    done, fib, inst, cache = 0, 0, set(), {}
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        q = fib % len(problems)
+        p = problems[q]
+        if q not in cache:
+            o = ST.Oracle(p)
+            F = SI.initial_ht(p)
+            V = HT.v_frame(F)
+            cache[q] = (o, o.efield(F), HT.x_frame(F), np.tensordot(V, F["root"], axes=([V.ndim - 1], [1])))
+        o, E, X, P = cache[q]
+        Nx = int(np.prod(p.n[: p.dx])); Nv = int(np.prod(p.n[p.dx:]))
+        idx = o._idx(np.full(Nv, (fib * 997) % Nx), np.arange(Nv))
+        foot = FT.feet(idx, p.lo, p.hi, p.n, p.dx, 2, p.dt / 3.0, 1.0, E)
+        rows, wts = FT.stencils(foot, idx, p.lo, p.hi, p.n, 3, 2, p.dx)
+        HT.sample_frames(X, P, rows, wts)
+        done += Nv
+        fib += 1
+        inst.add(q)
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "entries/s", "cores": int(nthreads), "kind": "oracle",
+            "sample": f"{fib} row fibers ({done} SL-FD entries) over {len(inst)} of the instances' initial "
+                      "states, first RK sub-flow, frame-form evaluation, FP64 NumPy",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def batched_run(args, steps, warmup, cpu_seconds=None):
     """64 independent Landau instances (1D1V or 2D2V, N per dimension from
     {32, 48, 64, 96, 128}) advanced together: one SLAR_VP step of every
-    instance per step; value = sampled entries of all instances per second."""
+    instance per step; value = sampled entries of all instances per second.
+    Returns the record of the batched workload."""
     import torch
     import slar_inputs as SI
     from paper_2606_29027_amd.batch import BatchSolver
@@ -180,13 +248,20 @@ def batched_main(args):
     if not args.no_tune:
         tuned = b.tune(reps=2)
     t_tune = time.perf_counter() - t_tune
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         b.step()
     torch.cuda.synchronize()
+    if args.calib_copy_mib > 0:
+        # marks the start of the timed steps in a counter trace
+        a = torch.ones(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
     n0 = len(b.stats)
     b.batch.timing_reset()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         b.step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -205,14 +280,23 @@ def batched_main(args):
             by += st["samples_q"][q] * (2.0 * rx * ldt * 4 + 8 + 16 * st["ranks"][q] / 2.0)
     achieved = by / (tim["cross_ms"] * 1e-3) / 1e9 if tim["cross_ms"] > 0 else 0.0
     n1 = sum(1 for p in problems if p.dx == 1)
+    traffic = measured_batch_traffic()
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "batched cross approximation (prep + row + col + fin launches, graph replays)",
+            "algorithmic_bytes_per_step": by / steps, "cross_ms_per_step": tim["cross_ms"] / steps}
+    if traffic and tim["cross_ms"] > 0:
+        hbm = traffic / (tim["cross_ms"] / steps * 1e-3) / 1e9
+        roof["hbm_measured_GBps"] = hbm
+        roof["hbm_measured_frac"] = hbm / HBM_PEAK_GBS
     out = {
         "metric": "HT-SL sampled entries/s & time/step, batched independent instances",
         "value": samples / elapsed,
         "unit": "entries/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -221,13 +305,20 @@ def batched_main(args):
         "config": {"workload": f"{len(problems)} independent Landau instances ({n1} 1D1V, {len(problems) - n1} 2D2V), "
                                "N per dim from {32,48,64,96,128}, tol 1e-6, rmax 40, dt 0.1, CF3, FP32 tables",
                    "tuned": tuned, "tune_seconds": t_tune,
-                   "cross_ms_per_step": tim["cross_ms"] / args.steps,
-                   "graph_chunks_per_step": tim["chunks"] / args.steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "batched cross approximation (prep + row + col + fin launches, graph replays)"},
+                   "cross_ms_per_step": tim["cross_ms"] / steps,
+                   "graph_chunks_per_step": tim["chunks"] / steps},
+        "roofline": roof,
         "cpu_baseline": None,
     }
+    del b
+    torch.cuda.synchronize()
+    if cpu_seconds:
+        out["cpu_baseline"] = cpu_baseline_batched(problems, cpu_seconds)
+    return out
+
+
+def batched_main(args):
+    out = batched_run(args, args.steps, args.warmup, None if args.no_cpu_baseline else args.cpu_seconds / 3.0)
     print(json.dumps(out))
 
 
@@ -505,6 +596,11 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not args.no_batched:
+        # the batched-instances workload, measured in the same run
+        b = batched_run(args, args.batched_steps, 1, None if args.no_cpu_baseline else args.cpu_seconds / 3.0)
+        out["config"]["batched"] = {k: b[k] for k in ("metric", "value", "unit", "steps", "warmup", "ms_per_step",
+                                                      "dtype", "config", "roofline", "cpu_baseline")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out))

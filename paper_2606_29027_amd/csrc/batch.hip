@@ -551,7 +551,7 @@ slar_status slar_batch_truncate(slar_batch* b, const slar_lowrank* in, double to
   if (!b || !in || !out || !(tol > 0.0) || rmax < 1 || rmax > 64) return SLAR_E_INVAL;
   for (int q = 0; q < b->count; ++q) {
     const Workspace& w = b->ws[q]->w;
-    if (!in[q].U || !in[q].V || in[q].k < 1 || in[q].k > 64) return SLAR_E_INVAL;
+    if (!in[q].U || !in[q].V || in[q].k < 1 || in[q].k > SLAR_CROSS_KMAX) return SLAR_E_INVAL;
     const int d = w.G.d;
     if (out[q].d != d) return SLAR_E_INVAL;
     for (int m = 0; m < d; ++m)

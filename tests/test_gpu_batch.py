@@ -109,3 +109,40 @@ def test_batch_rejects_bad_arguments():
     assert e.value.status == L.SLAR_E_INVAL
     with pytest.raises(L.SlarError):
         b.batch.set_config(256, 1, 8, (4, 5, 16))
+
+
+def test_batch_truncation_of_more_than_64_terms_equals_single_instance():
+    """Converged crosses of up to min(2 rmax, 128) terms reach the batched
+    truncation (the rank cap applies after it): factor sets of 80 terms
+    give, bit for bit, the HT tensors of the one-instance slar_truncate on a
+    workspace with the same settings (no leaf refinement)."""
+    from paper_2606_29027_amd.batch import _Inst
+    from gpu_util import dev, ht_from_dev
+    problems = SI.batched_instances(4, sizes=(12, 16), sizes_1d=(96, 128))
+    b, _ = _solver(problems)
+    k, tol = 80, 1e-6
+    keep, lrs = [], []
+    for q, I in enumerate(b.inst):
+        rng = np.random.default_rng(40 + q)
+        U = dev(rng.standard_normal((k, I.Nx)) * (0.8 ** np.arange(k))[:, None])
+        V = dev(rng.standard_normal((k, I.Nv)))
+        keep.append((U, V))
+        lrs.append(L.LowRank(k, U.data_ptr(), V.data_ptr()))
+    hts = [I.ht_desc(0) for I in b.inst]
+    b.batch.truncate(lrs, tol, b.rmax, hts, [I.frames(0) for I in b.inst])
+    torch.cuda.synchronize()
+    for q, p in enumerate(problems):
+        one = _Inst(p)
+        H = one.ht_desc(0)
+        ws = L.Workspace(L.make_grid(p), b.rmax)
+        L.slar_leaf_refine(ws, False)
+        L.slar_truncate(ws.grid, lrs[q], tol, b.rmax, H, ws)
+        torch.cuda.synchronize()
+        assert list(H.rank) == list(hts[q].rank), q
+        a = ht_from_dev(hts[q], b.inst[q].ht[0], p.dx + p.dv, p.n)
+        c = ht_from_dev(H, one.ht[0], p.dx + p.dv, p.n)
+        for key in ("root", "B12", "B34"):
+            if key in a:
+                assert np.array_equal(a[key], c[key]), (q, key)
+        for m in range(p.dx + p.dv):
+            assert np.array_equal(a["leaves"][m], c["leaves"][m]), (q, m)
