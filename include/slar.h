@@ -351,13 +351,13 @@ slar_status slar_bdf_weights(int32_t k, const double* t, double* c, double* beta
 /* Band-limited LoMaC correction (a stabilisation of this implementation,
  * not in the paper): U <- U(F*) + sigma (U - U(F*)) with U(F*) the
  * conserved variables of the prepared closure and sigma the exponential
- * filter prod_d exp(-36 kappa_d^36) of each x-mode (kappa_d = |m_d| /
+ * filter prod_d exp(-36 kappa_d^8) of each x-mode (kappa_d = |m_d| /
  * (n_d / 2), the mode index relative to the Nyquist index; sigma = 1 on
- * the zero mode, below 1e-15 of a change for kappa <= 1/3).  The
- * macroscopic and kinetic discretisations differ at the top x-modes
- * (spectral flux divergence against SL interpolation); imposing the
- * macroscopic top modes on the kinetic state let that mismatch grow from
- * step to step at 128^2 x-cells.  Totals (mass, momentum, energy) are
+ * the zero mode, 1 - 1e-4 at kappa = 1/5, 0.87 at kappa = 1/2, e^-36 at
+ * the Nyquist index).  The macroscopic and kinetic discretisations differ
+ * at the upper x-modes (spectral flux divergence against SL
+ * interpolation); imposing the macroscopic upper modes on the kinetic
+ * state let that mismatch grow from step to step at 128^2 x-cells.  Totals (mass, momentum, energy) are
  * unchanged exactly.  U device [dv+2][Nx] FP64, in place; needs
  * slar_lomac_prepare on ws.  Enqueued on stream.                          */
 slar_status slar_lomac_filter(const slar_grid* g, double* U, slar_workspace* ws, hipStream_t stream);

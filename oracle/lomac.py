@@ -138,11 +138,11 @@ def project_dense(Ffull: np.ndarray, dx: int, B: dict, vgrids, dvol: float) -> n
 
 
 def mode_filter(n: int) -> np.ndarray:
-    """sigma(m) = exp(-36 kappa^36), kappa = |m| / (n / 2), for the FFT mode
+    """sigma(m) = exp(-36 kappa^8), kappa = |m| / (n / 2), for the FFT mode
     indices 0..n-1 of an axis of n cells (|m| the distance to mode 0)."""
     i = np.arange(n)
     kap = np.minimum(i, n - i) / (0.5 * n)
-    return np.exp(-36.0 * kap ** 36)
+    return np.exp(-36.0 * kap ** 8)
 
 
 def filter_correction(U: np.ndarray, U0: np.ndarray) -> np.ndarray:

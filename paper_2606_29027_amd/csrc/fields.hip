@@ -236,19 +236,20 @@ hipError_t spectral_symbol(hipStream_t s, Workspace* ws, int op, int nvec, const
 //   SPEC_DIV      F[q][m] -> sum_m i k_m F[q][m]
 //   SPEC_PRECOND  x_b -> sum_b Minv[a][b] x_b (per-mode K x K inverse; the
 //                 modes stored transposed, pm = i1 n0 + i0 for p = i0 n1 + i1)
-//   SPEC_FILTER   x_q -> sigma x_q, sigma = prod_d exp(-36 kappa_d^36),
+//   SPEC_FILTER   x_q -> sigma x_q, sigma = prod_d exp(-36 kappa_d^8),
 //                 kappa_d = |m_d| / (n_d / 2) the mode index of axis d
 //                 relative to the Nyquist index (1 on the zero mode)
 // Null modes (|k| = 0) and Nyquist wavenumbers map to zero as in k_symbol.
 constexpr int SPEC_MAXIN = 8, SPEC_MAXOUT = 4;
 
-// one axis of the exponential filter, from the mode index i of n cells
+// one axis of the exponential filter exp(-36 kappa^8), kappa = |m| / (n / 2),
+// from the mode index i of n cells
 __device__ __forceinline__ double filt_axis(int i, int n) {
   if (n <= 1) return 1.0;
   const int m = i < n - i ? i : n - i;
   const double kap = (double)m / (0.5 * n);
-  double k2 = kap * kap, k4 = k2 * k2, k8 = k4 * k4, k16 = k8 * k8, k32 = k16 * k16;
-  return exp(-36.0 * k32 * k4);
+  const double k2 = kap * kap, k4 = k2 * k2;
+  return exp(-36.0 * (k4 * k4));
 }
 
 __device__ __forceinline__ void spec_map(int op, int dx, int K, const double* k, const double2* x,

@@ -694,21 +694,31 @@ def test_cur_core_reproduces_skeleton_and_exact_low_rank():
 
 def test_correction_filter_keeps_totals_and_resolved_band():
     """The band-limited LoMaC correction: the zero mode (hence mass,
-    momentum and energy totals) and every mode up to a third of the Nyquist
-    index are unchanged to rounding, the Nyquist mode is removed (e^-36),
-    and the result is real."""
+    momentum and energy totals) is unchanged to rounding, modes up to a
+    sixth of the Nyquist index to 1e-4, a mode at half the Nyquist index is
+    scaled by e^-(36/256) = 0.868815 per axis, the Nyquist mode is removed
+    (e^-36), the scaling is a tensor product over the axes, and the result
+    is real."""
     rng = np.random.default_rng(3)
     n = 24
     U0 = rng.standard_normal((4, n, n))
     x = np.arange(n) * 2 * math.pi / n
     X1, X2 = np.meshgrid(x, x, indexing="ij")
-    low = np.cos(2 * X1 + 0.3) * np.sin(4 * X2) + 0.7      # modes |m| <= 4 = n / 6
+    const = np.full((n, n), 0.7)
+    Uf = LM.filter_correction(U0 + const[None], U0)
+    assert np.abs(Uf - U0 - const[None]).max() < 1e-14
+    low = np.cos(2 * X1 + 0.3) * np.sin(X2)               # modes |m| <= 2 = n / 12
     U = U0 + low[None] * np.arange(1, 5)[:, None, None]
     Uf = LM.filter_correction(U, U0)
-    assert np.abs(Uf - U).max() < 1e-13
+    assert np.abs(Uf - U).max() < 1e-4 * 4
+    half = np.cos(6 * X1 + 0.4)                            # |m| = 6 = Nyquist / 2 along axis 0
+    Uf = LM.filter_correction(U0 + half[None], U0)
+    assert np.abs(Uf - U0 - 0.868815 * half[None]).max() < 1e-6
+    both = np.cos(6 * X1) * np.cos(6 * X2)                 # half the Nyquist index on both axes
+    Uf = LM.filter_correction(U0 + both[None], U0)
+    assert np.abs(Uf - U0 - 0.868815 ** 2 * both[None]).max() < 1e-6
     nyq = np.cos(math.pi * np.arange(n))[:, None] * np.ones((1, n))   # pure Nyquist along axis 0
-    Un = U0 + nyq[None]
-    Uf = LM.filter_correction(Un, U0)
+    Uf = LM.filter_correction(U0 + nyq[None], U0)
     assert np.abs(Uf - U0).max() < 1e-14 + 3e-16 * n
     Ur = U0 + rng.standard_normal((4, n, n))
     Uf = LM.filter_correction(Ur, U0)
