@@ -1,5 +1,6 @@
 """Train the learned preconditioner on Newton systems of the weak Landau
-(64^4) and two-stream (128^4) workloads and save its parameters.
+(64^4, from t = 4) and two-stream (128^4, from t = 15) workloads and save
+its parameters.
 
     python -m paper_2606_29027_amd.train_precond [--iters N] [--out PATH]
 """
@@ -20,15 +21,16 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--iters", type=int, default=600)
-    ap.add_argument("--steps", type=int, default=6)
-    ap.add_argument("--capacity", type=int, default=160)
+    ap.add_argument("--iters", type=int, default=1500)
+    ap.add_argument("--steps", type=int, default=150)
+    ap.add_argument("--capacity", type=int, default=200)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     from paper_2606_29027_amd import cnn as CNN
     t0 = time.perf_counter()
-    data = CNN.collect(CNN.training_problems(), steps=args.steps, capacity=args.capacity)
+    data = CNN.collect(CNN.training_problems(), steps=args.steps, capacity=args.capacity,
+                       skip=CNN.TRAINING_SKIP)
     t1 = time.perf_counter()
     net = CNN.make()
     hist = CNN.train(net, data, iters=args.iters, lr=args.lr)
