@@ -68,8 +68,8 @@ def _setup(N=16, kmax=128, tol=1e-9, seed=31, rmax=64, smooth=False):
 
 def test_cross_past_64_terms_matches_oracle():
     """FP64 tables: the GPU cross takes the oracle's pivots and terms past
-    64 (it converges at k = 86 here), and U V^T agrees with the oracle's at
-    every probe and on two fibers to 1e-10 of the largest entry."""
+    64 (it converges at k = 86 here), and U V^T agrees with the oracle's
+    everywhere to 1e-12 of the largest entry."""
     c = _setup(N=24, smooth=True)
     p = c["p"]
     Uo, Vo, info_o = CR.aca(c["row"], c["col"], c["pts"], c["Nx"], c["Nx"], p.tol, c["kmax"], 0,
@@ -86,10 +86,11 @@ def test_cross_past_64_terms_matches_oracle():
     got = Ug @ Vg.T
     scale = np.abs(ref).max()
     for i in (0, 37, 300):
-        assert np.abs(got[i] - ref[i]).max() < 1e-10 * scale
-        assert np.abs(got[:, i] - ref[:, i]).max() < 1e-10 * scale
+        assert np.abs(got[i] - ref[i]).max() < 1e-12 * scale
+        assert np.abs(got[:, i] - ref[:, i]).max() < 1e-12 * scale
     I, J = c["probes"][:, 0], c["probes"][:, 1]
-    assert np.abs(got[I, J] - ref[I, J]).max() < 1e-10 * np.abs(ref).max()
+    assert np.abs(got[I, J] - ref[I, J]).max() < 1e-12 * np.abs(ref).max()
+    assert np.abs(got - ref).max() < 1e-12 * scale   # 7e-15 measured
 
 
 def test_truncate_of_more_than_64_terms_matches_oracle():
@@ -144,4 +145,5 @@ def test_capped_cross_regularised_skeleton_matches_oracle(kmax, rmax):
     assert lr.k == Uc.shape[1] == rmax
     got = c["U"][: lr.k].cpu().numpy().T @ c["V"][: lr.k].cpu().numpy()
     ref = Uc @ Vc.T
-    assert normwise(got, ref) < 1e-9, normwise(got, ref)
+    # rounding of the pivot-block SVD and of W_r^+ (6e-14 and 2.2e-13 measured)
+    assert normwise(got, ref) < 2e-12, normwise(got, ref)
