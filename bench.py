@@ -260,6 +260,7 @@ def batched_run(args, steps, warmup, cpu_seconds=None):
         del a, c
     n0 = len(b.stats)
     b.batch.timing_reset()
+    b.tphase = {k: 0.0 for k in b.tphase}
     t0 = time.perf_counter()
     for _ in range(steps):
         b.step()
@@ -306,7 +307,8 @@ def batched_run(args, steps, warmup, cpu_seconds=None):
                                "N per dim from {32,48,64,96,128}, tol 1e-6, rmax 40, dt 0.1, CF3, FP32 tables",
                    "tuned": tuned, "tune_seconds": t_tune,
                    "cross_ms_per_step": tim["cross_ms"] / steps,
-                   "graph_chunks_per_step": tim["chunks"] / steps},
+                   "graph_chunks_per_step": tim["chunks"] / steps,
+                   "host_phase_ms_per_step": {k: 1e3 * v / steps for k, v in b.tphase.items()}},
         "roofline": roof,
         "cpu_baseline": None,
     }

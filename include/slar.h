@@ -479,11 +479,14 @@ slar_status slar_batch_cross_update(slar_batch* b, const slar_frames* src, const
                                     const int32_t* const* probes, slar_lowrank* out,
                                     slar_cross_info* info, hipStream_t stream);
 
-/* slar_truncate for every instance (host thread pool, one stream per
- * thread, ordered after the work already on `stream`), followed, when
- * frames != NULL, by slar_frames_from_ht into frames[q] (ld >= rmax).
- * status (host int32[count], may be NULL) receives per-instance statuses;
- * the return value is the most severe of them.                              */
+/* slar_truncate for every instance (bit-identical results), ordered after
+ * the work already on `stream`: the single-block factorisations of all
+ * instances run as one launch per phase, the per-instance products on a
+ * host thread pool (one stream per thread); followed, when frames != NULL,
+ * by slar_frames_from_ht into frames[q] (ld >= rmax).  Each workspace's
+ * leaf-refinement setting applies to its instance.  status (host
+ * int32[count], may be NULL) receives per-instance statuses; the return
+ * value is the most severe of them.                                         */
 slar_status slar_batch_truncate(slar_batch* b, const slar_lowrank* in, double tol, int32_t rmax,
                                 slar_ht* out, slar_frames* frames, int32_t* status,
                                 hipStream_t stream);

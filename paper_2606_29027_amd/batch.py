@@ -5,8 +5,9 @@ driver (section 3.1: the three frozen-field sub-flows of the third-order
 commutator-free exponential integrator, each one cross approximation plus
 truncation), but each stage is one batched library call for all instances:
 slar_batch_efield, slar_batch_cross_update (persistent multi-instance
-launches replayed from a captured hipGraph) and slar_batch_truncate (host
-thread pool, per-instance streams).  Instances differ in dimension, grid
+launches replayed from a captured hipGraph) and slar_batch_truncate (the
+single-block factorisations of all instances grouped into one launch per
+phase, the per-instance products on a host thread pool).  Instances differ in dimension, grid
 size and rank; they share tolerance, rank cap and time step.
 
 This module only sequences library calls and owns the device buffers; it
@@ -102,6 +103,10 @@ class BatchSolver:
         self.state = None          # list of Frames
         self.state_slot = 0
         self.stats = []
+        # host wall time per stage: the field solves are only enqueued (their
+        # device time lands in the cross call, which synchronises); the cross
+        # and truncation calls return once their work is done
+        self.tphase = {"efield": 0.0, "cross": 0.0, "truncation": 0.0}
 
     @property
     def count(self):
@@ -132,15 +137,21 @@ class BatchSolver:
 
     # --------------------------------------------------------------- stages
     def efield(self, F, e):
+        t0 = time.perf_counter()
         self.batch.efield(F, [I.n_i for I in self.inst], [I.M for I in self.inst], [I.E[e] for I in self.inst])
+        self.tphase["efield"] += time.perf_counter() - t0
         return [I.E[e] for I in self.inst]
 
     def slar(self, src, advs, ht_slot, frame_slot):
+        t0 = time.perf_counter()
         lrs, info, _ = self.batch.cross_update(src, advs, self.tol, self.kcross, self.probes,
                                                [I.U for I in self.inst], [I.V for I in self.inst])
+        t1 = time.perf_counter()
         hts = [I.ht_desc(ht_slot) for I in self.inst]
         outs = [I.frames(frame_slot) for I in self.inst]
         self.batch.truncate(lrs, self.tol, self.rmax, hts, outs)
+        self.tphase["cross"] += t1 - t0
+        self.tphase["truncation"] += time.perf_counter() - t1
         self.stats.append({"ranks": [x.rank for x in info], "samples": int(sum(x.samples for x in info)),
                            "samples_q": [int(x.samples) for x in info], "src_ranks": [f.r for f in src],
                            "iters": max(x.iterations for x in info)})

@@ -9,6 +9,7 @@
 #include "dense.h"
 #include "fields.h"
 #include "lomac.h"
+#include "truncate.h"
 
 namespace slar {
 hipError_t ht_sample(hipStream_t st, const GridDev& G, const AdvDev& A, const slar_ht& F,
@@ -23,11 +24,8 @@ hipError_t frame_points(hipStream_t s, const GridDev& G, const AdvDev& A, slar_d
 slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, const slar_adv& adv,
                       slar_dtype dt, double tol, int kmax, int nprobe, const int* probes,
                       slar_lowrank* out, slar_cross_info* info);
-slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, double tol,
-                         int rmax, slar_ht* out);
 size_t aca_ctl_bytes();
 size_t aca_part_elems();
-size_t truncate_scratch_elems(const GridDev& G);
 slar_status poisson_noalloc_run(hipStream_t s, const slar_grid& grid, const double* n_e, double n_i,
                                 double* phi, double* E);
 }  // namespace slar

@@ -13,9 +13,12 @@
 // inputs and picks the persistent grid size, the tiles per work item, the
 // iterations per graph chunk, and the gather team width per rank bucket.
 //
-// Truncation, frames and the field solves are per instance and contain host
-// decisions (ranks), so a pool of host threads runs them, one HIP stream
-// (default priority) per thread.
+// Truncation: the grouped form (truncate.hip) runs the single-block
+// factorisations of every instance (Cholesky, core SVD, Gram eigenpairs) as
+// one launch per phase and takes the rank decisions of all instances after
+// one gathered read per phase; the per-instance products between the
+// phases, the frames and the field solves are enqueued by a pool of host
+// threads, one HIP stream (default priority) per thread.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -29,12 +32,11 @@
 
 #include "aca.h"
 #include "fields.h"
+#include "truncate.h"
 
 namespace slar {
 hipError_t frames_from_ht(hipStream_t s, Workspace* ws, const GridDev& G, const slar_ht& F,
                           slar_frames* out);
-slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, double tol,
-                         int rmax, slar_ht* out);
 
 struct BItem {
   int q;    // instance
@@ -269,6 +271,9 @@ struct slar_batch {
   hipEvent_t ev_in = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double tstat[4] = {0, 0, 0, 0};  // cross ms, chunks, iterations (max over instances), calls
+  // grouped truncation: descriptors and gathered values (device, pinned mirror)
+  void* d_tg = nullptr;
+  void* h_tg = nullptr;
 };
 
 static int bucket_of(int r) { return r <= 16 ? 0 : (r <= 32 ? 1 : 2); }
@@ -397,6 +402,15 @@ static bool batch_frames_ok(const slar_batch* b, const slar_frames* F) {
   return true;
 }
 
+// most severe status first; a capped rank is reported but not fatal
+static slar_status worst_of(const std::vector<slar_status>& st) {
+  static const slar_status sev[] = {SLAR_E_HIP, SLAR_E_NUMERIC, SLAR_E_NOMEM, SLAR_E_INVAL,
+                                    SLAR_E_NOCONV, SLAR_E_RANK_CAP};
+  for (slar_status c : sev)
+    if (std::find(st.begin(), st.end(), c) != st.end()) return c;
+  return SLAR_OK;
+}
+
 // Run fn(q, stream, ws) for every instance on the pool; the pool streams
 // wait for the work already on s, and s waits for everything they enqueue.
 static slar_status pool_run(slar_batch* b, hipStream_t s,
@@ -421,16 +435,9 @@ static slar_status pool_run(slar_batch* b, hipStream_t s,
     if (bad[w]) return SLAR_E_HIP;
     if (hipStreamWaitEvent(s, b->ev_done[w], 0) != hipSuccess) return SLAR_E_HIP;
   }
-  // most severe status first; a capped rank is reported but not fatal
-  static const slar_status sev[] = {SLAR_E_HIP, SLAR_E_NUMERIC, SLAR_E_NOMEM, SLAR_E_INVAL,
-                                    SLAR_E_NOCONV, SLAR_E_RANK_CAP};
-  slar_status worst = SLAR_OK;
-  for (slar_status c : sev) {
-    if (std::find(st.begin(), st.end(), c) != st.end()) { worst = c; break; }
-  }
   if (status)
     for (int q = 0; q < b->count; ++q) status[q] = st[q];
-  return worst;
+  return worst_of(st);
 }
 
 extern "C" {
@@ -449,9 +456,9 @@ slar_status slar_batch_destroy(slar_batch* b) {
     if (e) (void)hipEventDestroy(e);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   for (void* p : {(void*)b->d_inst, (void*)b->d_prep, (void*)b->d_rows, (void*)b->d_cols,
-                  (void*)b->d_active, (void*)b->d_sum})
+                  (void*)b->d_active, (void*)b->d_sum, b->d_tg})
     if (p) (void)hipFree(p);
-  for (void* p : {(void*)b->h_inst, (void*)b->h_prep, (void*)b->h_active, (void*)b->h_sum})
+  for (void* p : {(void*)b->h_inst, (void*)b->h_prep, (void*)b->h_active, (void*)b->h_sum, b->h_tg})
     if (p) (void)hipHostFree(p);
   for (slar_workspace* w : b->ws) slar_workspace_destroy(w);
   delete b;
@@ -499,6 +506,8 @@ slar_status slar_batch_create(int32_t count, const slar_grid* grids, int32_t rma
   hal((void**)&b->h_prep, sizeof(BPrep) * count);
   hal((void**)&b->h_active, sizeof(int));
   hal((void**)&b->h_sum, sizeof(BSummary) * count);
+  dal(&b->d_tg, truncate_group_bytes(count));
+  hal(&b->h_tg, truncate_group_bytes(count));
   if (!ok) return fail(SLAR_E_NOMEM);
   std::memset(b->h_inst, 0, sizeof(AcaInst) * count);
   if (hipMemcpy(b->d_inst, b->h_inst, sizeof(AcaInst) * count, hipMemcpyHostToDevice) != hipSuccess)
@@ -559,13 +568,34 @@ slar_status slar_batch_truncate(slar_batch* b, const slar_lowrank* in, double to
     if (!out[q].root || (d == 4 && (!out[q].B12 || !out[q].B34))) return SLAR_E_INVAL;
     if (frames && (!frames[q].X || !frames[q].P || frames[q].ld < rmax)) return SLAR_E_INVAL;
   }
-  return pool_run(b, stream, [&](int q, hipStream_t s, Workspace* w) -> slar_status {
-    slar_status st = truncate_run(s, w, in[q], tol, rmax, &out[q]);
-    if ((st == SLAR_OK || st == SLAR_E_RANK_CAP) && frames) {
-      if (frames_from_ht(s, w, w->G, out[q], &frames[q]) != hipSuccess) return SLAR_E_HIP;
-    }
-    return st;
-  }, status);
+  std::vector<TruncJob> jobs(b->count);
+  for (int q = 0; q < b->count; ++q) {
+    jobs[q].ws = &b->ws[q]->w;
+    jobs[q].in = in[q];
+    jobs[q].out = &out[q];
+  }
+  // per-job work on the pool streams, single-block factorisations grouped
+  const TruncEach each = [&](const std::function<void(int, hipStream_t)>& fn) -> slar_status {
+    return pool_run(b, stream, [&](int q, hipStream_t s, Workspace*) -> slar_status {
+      fn(q, s);
+      return SLAR_OK;
+    }, nullptr);
+  };
+  const slar_status e = truncate_group(stream, jobs, tol, rmax, each, b->d_tg, b->h_tg);
+  if (e != SLAR_OK) return e;
+  std::vector<slar_status> st(b->count);
+  for (int q = 0; q < b->count; ++q) st[q] = jobs[q].st;
+  if (frames) {
+    const slar_status ef = pool_run(b, stream, [&](int q, hipStream_t s, Workspace* w) -> slar_status {
+      if (st[q] != SLAR_OK && st[q] != SLAR_E_RANK_CAP) return SLAR_OK;
+      if (frames_from_ht(s, w, w->G, out[q], &frames[q]) != hipSuccess) st[q] = SLAR_E_HIP;
+      return SLAR_OK;
+    }, nullptr);
+    if (ef != SLAR_OK) return ef;
+  }
+  if (status)
+    for (int q = 0; q < b->count; ++q) status[q] = st[q];
+  return worst_of(st);
 }
 
 slar_status slar_batch_efield(slar_batch* b, const slar_frames* F, const double* n_i,

@@ -31,4 +31,41 @@ hipError_t sign_fix_tall(hipStream_t s, double* scratch, size_t scratch_elems, i
 hipError_t copy2d(hipStream_t s, int rows, int cols, const double* A, int lda, double* B, int ldb,
                   const double* colscale);
 hipError_t fill(hipStream_t s, double* p, long long n, double v);
+
+// Grouped launches of the single-block factorisations: one block per
+// descriptor, the descriptors in device memory, each problem computed
+// exactly as by the one-problem call.  *_copy pointers (may be null)
+// receive a second copy of the values, for one gathered host read.
+struct CholDesc {   // chol_inv
+  int k;
+  const double* G;
+  double* Linv;
+  double* R;
+  const double* Rprev;
+};
+struct SvdDesc {    // svd_small (k <= 64) or svd_left_big (64 < k <= 128; Z unused)
+  int k;
+  const double* M;
+  double* W;
+  double* sv;
+  double* Z;
+  double* sv_copy;
+};
+struct EigDesc {    // eig_sym_batch
+  int n;
+  const double* G;
+  double* lam;
+  double* U;
+  double* lam_copy;
+};
+struct BasisDesc {  // complete_basis_batch
+  int n;
+  double* E;
+};
+// big: every k in (SLAR_KMAX, SLAR_CROSS_KMAX], else every k <= SLAR_KMAX
+hipError_t chol_inv_group(hipStream_t s, int count, const CholDesc* d, bool big);
+// big: every k in (64, 128], else every k <= 64
+hipError_t svd_group(hipStream_t s, int count, const SvdDesc* d, bool big);
+hipError_t eig_sym_group(hipStream_t s, int count, const EigDesc* d);
+hipError_t complete_basis_group(hipStream_t s, int count, const BasisDesc* d);
 }  // namespace slar

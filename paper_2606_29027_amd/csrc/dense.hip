@@ -126,9 +126,8 @@ hipError_t gram_mode2(hipStream_t s, const Scratch& part, int na, int nb, int r,
 // From Gram G (k x k): column scaling d = sqrt(diag G), Cholesky of
 // D^-1 G D^-1 = L L^T.  Writes Linv_scaled = L^-1 D^-1 (k x k, lower) and
 // R = L^T D (upper).  A zero column keeps d = 1 and a unit pivot.
-__global__ __launch_bounds__(256) void k_chol_inv(int k, const double* __restrict__ G,
-                                                  double* __restrict__ Linv, double* __restrict__ R,
-                                                  const double* __restrict__ Rprev) {
+__device__ __forceinline__ void chol_inv_dev(int k, const double* __restrict__ G, double* __restrict__ Linv,
+                                             double* __restrict__ R, const double* __restrict__ Rprev) {
   __shared__ double L[SLAR_KMAX][SLAR_KMAX + 1];
   __shared__ double Li[SLAR_KMAX][SLAR_KMAX + 1];
   __shared__ double Rp[SLAR_KMAX][SLAR_KMAX + 1];
@@ -223,9 +222,9 @@ __global__ __launch_bounds__(256) void k_chol_inv(int k, const double* __restric
 // A[j][i], i > j) with its diagonal in li_d; Rprev is read from global
 // memory.  Same arithmetic and summation order as k_chol_inv.
 constexpr int CHOL_BIG = SLAR_CROSS_KMAX;
-__global__ __launch_bounds__(256) void k_chol_inv_big(int k, const double* __restrict__ G,
-                                                      double* __restrict__ Linv, double* __restrict__ R,
-                                                      const double* __restrict__ Rprev) {
+__device__ __forceinline__ void chol_inv_big_dev(int k, const double* __restrict__ G,
+                                                 double* __restrict__ Linv, double* __restrict__ R,
+                                                 const double* __restrict__ Rprev) {
   __shared__ double A[CHOL_BIG][CHOL_BIG + 1];
   __shared__ double d[CHOL_BIG], tcol[CHOL_BIG], li_d[CHOL_BIG];
   const int t = threadIdx.x;
@@ -283,6 +282,24 @@ __global__ __launch_bounds__(256) void k_chol_inv_big(int k, const double* __res
   }
 }
 
+__global__ __launch_bounds__(256) void k_chol_inv(int k, const double* __restrict__ G,
+                                                  double* __restrict__ Linv, double* __restrict__ R,
+                                                  const double* __restrict__ Rprev) {
+  chol_inv_dev(k, G, Linv, R, Rprev);
+}
+__global__ __launch_bounds__(256) void k_chol_inv_big(int k, const double* __restrict__ G,
+                                                      double* __restrict__ Linv, double* __restrict__ R,
+                                                      const double* __restrict__ Rprev) {
+  chol_inv_big_dev(k, G, Linv, R, Rprev);
+}
+// one block per descriptor
+template <bool BIG>
+__global__ __launch_bounds__(256) void k_chol_inv_group(const CholDesc* __restrict__ D) {
+  const CholDesc d = D[blockIdx.x];
+  if (BIG) chol_inv_big_dev(d.k, d.G, d.Linv, d.R, d.Rprev);
+  else chol_inv_dev(d.k, d.G, d.Linv, d.R, d.Rprev);
+}
+
 hipError_t chol_inv(hipStream_t s, int k, const double* G, double* Linv, double* R,
                     const double* Rprev) {
   if (k < 1 || k > SLAR_CROSS_KMAX) return hipErrorInvalidValue;
@@ -290,6 +307,14 @@ hipError_t chol_inv(hipStream_t s, int k, const double* G, double* Linv, double*
     k_chol_inv<<<1, 256, 0, s>>>(k, G, Linv, R, Rprev);
   else
     k_chol_inv_big<<<1, 256, 0, s>>>(k, G, Linv, R, Rprev);
+  return hipGetLastError();
+}
+
+hipError_t chol_inv_group(hipStream_t s, int count, const CholDesc* d, bool big) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  if (big) k_chol_inv_group<true><<<count, 256, 0, s>>>(d);
+  else k_chol_inv_group<false><<<count, 256, 0, s>>>(d);
   return hipGetLastError();
 }
 
@@ -460,9 +485,10 @@ __device__ int jacobi_cols(double* C, int ldc, int n, int kp, double* V, int ldv
 // singular vectors).
 constexpr int SVD_KM = 64;
 
-__global__ __launch_bounds__(512) void k_svd_jacobi(int k, const double* __restrict__ Min,
-                                                    double* __restrict__ W, double* __restrict__ sv,
-                                                    double* __restrict__ Z) {
+// sv_copy (may be null) receives a second copy of the singular values
+__device__ __forceinline__ void svd_jacobi_dev(int k, const double* __restrict__ Min, double* __restrict__ W,
+                                               double* __restrict__ sv, double* __restrict__ Z,
+                                               double* __restrict__ sv_copy) {
   __shared__ double A[SVD_KM * SVD_KM];   // column c at A + c * SVD_KM
   __shared__ double V[SVD_KM * SVD_KM];
   __shared__ double nrm[SVD_KM];
@@ -507,7 +533,16 @@ __global__ __launch_bounds__(512) void k_svd_jacobi(int k, const double* __restr
     W[e] = nrm[c] > 0.0 ? A[c * SVD_KM + r] / nrm[c] : (r == j ? 1.0 : 0.0);
     Z[e] = V[c * SVD_KM + r];
   }
-  for (int j = t; j < k; j += blockDim.x) sv[j] = nrm[order[j]];
+  for (int j = t; j < k; j += blockDim.x) {
+    sv[j] = nrm[order[j]];
+    if (sv_copy) sv_copy[j] = nrm[order[j]];
+  }
+}
+
+__global__ __launch_bounds__(512) void k_svd_jacobi(int k, const double* __restrict__ Min,
+                                                    double* __restrict__ W, double* __restrict__ sv,
+                                                    double* __restrict__ Z) {
+  svd_jacobi_dev(k, Min, W, sv, Z, nullptr);
 }
 
 hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* sv, double* Z) {
@@ -578,8 +613,8 @@ __device__ void lq_lower(double* A, int lda, int n, double* vrow, double (*part)
   }
 }
 
-__global__ __launch_bounds__(1024) void k_svd_left_big(int k, const double* __restrict__ Min,
-                                                       double* __restrict__ W, double* __restrict__ sv) {
+__device__ __forceinline__ void svd_left_big_dev(int k, const double* __restrict__ Min, double* __restrict__ W,
+                                                 double* __restrict__ sv, double* __restrict__ sv_copy) {
   __shared__ double A[SVD_BIG * SVD_BIG_LD];   // column c at A + c * SVD_BIG_LD
   __shared__ double nrm[SVD_BIG];
   __shared__ int order[SVD_BIG];
@@ -624,12 +659,39 @@ __global__ __launch_bounds__(1024) void k_svd_left_big(int k, const double* __re
     const int c = order[j];
     W[e] = nrm[c] > 0.0 ? A[c * SVD_BIG_LD + r] / nrm[c] : (r == j ? 1.0 : 0.0);
   }
-  for (int j = t; j < k; j += blockDim.x) sv[j] = nrm[order[j]];
+  for (int j = t; j < k; j += blockDim.x) {
+    sv[j] = nrm[order[j]];
+    if (sv_copy) sv_copy[j] = nrm[order[j]];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_svd_left_big(int k, const double* __restrict__ Min,
+                                                       double* __restrict__ W, double* __restrict__ sv) {
+  svd_left_big_dev(k, Min, W, sv, nullptr);
 }
 
 hipError_t svd_left_big(hipStream_t s, int k, const double* M, double* W, double* sv) {
   if (k <= SVD_KM || k > SVD_BIG) return hipErrorInvalidValue;
   k_svd_left_big<<<1, 1024, 0, s>>>(k, M, W, sv);
+  return hipGetLastError();
+}
+
+// one block per descriptor: k <= 64 (full SVD, 512 threads) or 64 < k <=
+// 128 (left vectors and values, 1024 threads), as the caller groups them
+__global__ __launch_bounds__(512) void k_svd_group_small(const SvdDesc* __restrict__ D) {
+  const SvdDesc d = D[blockIdx.x];
+  svd_jacobi_dev(d.k, d.M, d.W, d.sv, d.Z, d.sv_copy);
+}
+__global__ __launch_bounds__(1024) void k_svd_group_big(const SvdDesc* __restrict__ D) {
+  const SvdDesc d = D[blockIdx.x];
+  svd_left_big_dev(d.k, d.M, d.W, d.sv, d.sv_copy);
+}
+
+hipError_t svd_group(hipStream_t s, int count, const SvdDesc* d, bool big) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  if (big) k_svd_group_big<<<count, 1024, 0, s>>>(d);
+  else k_svd_group_small<<<count, 512, 0, s>>>(d);
   return hipGetLastError();
 }
 
@@ -669,11 +731,9 @@ struct EigBatch {
   double* U[4];
 };
 
-__global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
-  const int n = B.n[blockIdx.x];
-  const double* __restrict__ G = B.G[blockIdx.x];
-  double* __restrict__ lam = B.lam[blockIdx.x];
-  double* __restrict__ Uout = B.U[blockIdx.x];
+// lam_copy (may be null) receives a second copy of lam
+__device__ __forceinline__ void eig_psd_dev(int n, const double* __restrict__ G, double* __restrict__ lam,
+                                            double* __restrict__ Uout, double* __restrict__ lam_copy) {
   __shared__ double L[EIG_CM * SLAR_NMAX];   // column c at L + c * SLAR_NMAX
   __shared__ double dres[SLAR_NMAX];
   __shared__ unsigned char taken[SLAR_NMAX];
@@ -780,8 +840,19 @@ __global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
     }
     Uout[e] = v;
   }
-  for (int j = t; j < n; j += blockDim.x)
-    lam[j] = (j < nc) ? nrm[order[j]] : (j == nc ? s_rest : 0.0);
+  for (int j = t; j < n; j += blockDim.x) {
+    const double l = (j < nc) ? nrm[order[j]] : (j == nc ? s_rest : 0.0);
+    lam[j] = l;
+    if (lam_copy) lam_copy[j] = l;
+  }
+}
+
+__global__ __launch_bounds__(512) void k_eig_psd(EigBatch B) {
+  eig_psd_dev(B.n[blockIdx.x], B.G[blockIdx.x], B.lam[blockIdx.x], B.U[blockIdx.x], nullptr);
+}
+__global__ __launch_bounds__(512) void k_eig_psd_group(const EigDesc* __restrict__ D) {
+  const EigDesc d = D[blockIdx.x];
+  eig_psd_dev(d.n, d.G, d.lam, d.U, d.lam_copy);
 }
 
 // up to four independent eigenproblems in one launch (one block each)
@@ -797,6 +868,13 @@ hipError_t eig_sym_batch(hipStream_t s, int count, const int* n, const double* c
   return hipGetLastError();
 }
 
+hipError_t eig_sym_group(hipStream_t s, int count, const EigDesc* d) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  k_eig_psd_group<<<count, 512, 0, s>>>(d);
+  return hipGetLastError();
+}
+
 // Completion of an orthonormal set to a basis of R^n (n <= 128): E is
 // row-major n x n, column j either a unit vector of the set or zero (as the
 // eigen kernel leaves the columns past its factor rank).  Each zero column,
@@ -809,9 +887,7 @@ struct CompleteBatch {
   double* E[4];
 };
 
-__global__ __launch_bounds__(512) void k_complete_basis(CompleteBatch B) {
-  const int n = B.n[blockIdx.x];
-  double* __restrict__ E = B.E[blockIdx.x];
+__device__ __forceinline__ void complete_basis_dev(int n, double* __restrict__ E) {
   __shared__ double C[SLAR_NMAX * SLAR_NMAX];   // column c at C + c * SLAR_NMAX
   __shared__ double res[SLAR_NMAX], v[SLAR_NMAX], h[SLAR_NMAX], part[4][SLAR_NMAX];
   __shared__ unsigned char filled[SLAR_NMAX];
@@ -896,6 +972,21 @@ __global__ __launch_bounds__(512) void k_complete_basis(CompleteBatch B) {
     const int r = e / n, c = e % n;
     E[e] = C[c * SLAR_NMAX + r];
   }
+}
+
+__global__ __launch_bounds__(512) void k_complete_basis(CompleteBatch B) {
+  complete_basis_dev(B.n[blockIdx.x], B.E[blockIdx.x]);
+}
+__global__ __launch_bounds__(512) void k_complete_basis_group(const BasisDesc* __restrict__ D) {
+  const BasisDesc d = D[blockIdx.x];
+  complete_basis_dev(d.n, d.E);
+}
+
+hipError_t complete_basis_group(hipStream_t s, int count, const BasisDesc* d) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  k_complete_basis_group<<<count, 512, 0, s>>>(d);
+  return hipGetLastError();
 }
 
 hipError_t complete_basis_batch(hipStream_t s, int count, const int* n, double* const* E) {

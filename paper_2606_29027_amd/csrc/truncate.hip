@@ -21,11 +21,14 @@
 //      leaf bases.  The completion matters: directions missing from E
 //      (past the eigen factor's rank) leave the refined small-eigenvalue
 //      vectors no more accurate than the first ones.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <vector>
 
 #include "slar_internal.h"
 #include "dense.h"
+#include "truncate.h"
 
 namespace slar {
 
@@ -325,6 +328,326 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   return capped ? SLAR_E_RANK_CAP : SLAR_OK;
+}
+
+// ------------------------------------------------------------ grouped form
+// The steps of truncate_run, phase by phase over a group of jobs: the
+// per-job products (Grams, GEMMs, sign rules) are enqueued through `each`;
+// the single-block factorisations of all jobs run as one launch per phase
+// (descriptors copied from pinned host memory, one region per phase); the
+// singular values and eigenvalues of all jobs come back in one copy each.
+namespace {
+struct GroupLayout {
+  size_t chol1, chol2, svd, eig1, eig2, basis, sv, lam, total;
+};
+GroupLayout group_layout(int n) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  GroupLayout L{};
+  size_t o = 0;
+  L.chol1 = o; o += al(sizeof(CholDesc) * 2 * n);
+  L.chol2 = o; o += al(sizeof(CholDesc) * 2 * n);
+  L.svd = o; o += al(sizeof(SvdDesc) * n);
+  L.eig1 = o; o += al(sizeof(EigDesc) * 4 * n);
+  L.eig2 = o; o += al(sizeof(EigDesc) * 4 * n);
+  L.basis = o; o += al(sizeof(BasisDesc) * 4 * n);
+  L.sv = o; o += al(sizeof(double) * SLAR_CROSS_KMAX * n);
+  L.lam = o; o += al(sizeof(double) * 4 * SLAR_NMAX * n);
+  L.total = o;
+  return L;
+}
+
+// descriptors of two size classes, small ones first, copied to the device
+template <class D>
+hipError_t upload(hipStream_t s, char* dmem, char* hmem, size_t off, const std::vector<D>& a,
+                  const std::vector<D>& b) {
+  const size_t n = a.size() + b.size();
+  if (n == 0) return hipSuccess;
+  D* h = (D*)(hmem + off);
+  std::copy(a.begin(), a.end(), h);
+  std::copy(b.begin(), b.end(), h + a.size());
+  return hipMemcpyAsync(dmem + off, hmem + off, sizeof(D) * n, hipMemcpyHostToDevice, s);
+}
+}  // namespace
+
+size_t truncate_group_bytes(int count) { return group_layout(std::max(count, 1)).total; }
+
+slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double tol, int rmax,
+                           const TruncEach& each, void* dmem, void* hmem) {
+  const int n = (int)jobs.size();
+  if (n == 0) return SLAR_OK;
+  const GroupLayout GL = group_layout(n);
+  char* D = (char*)dmem;
+  char* H = (char*)hmem;
+  const size_t CK = SLAR_CROSS_KMAX;
+  std::vector<Tbuf> tb(n);
+  for (int j = 0; j < n; ++j) tb[j] = carve(jobs[j].ws);
+  auto live = [&](int j) { return jobs[j].st == SLAR_OK; };
+  auto fail = [&](int j, slar_status e) {
+    if (jobs[j].st == SLAR_OK) jobs[j].st = e;
+  };
+  auto Rv_of = [&](int j) { return tb[j].R + CK * CK; };
+  slar_status e;
+
+  // Cholesky-QR2 of both factor sets; pass 2 takes R1 of pass 1 as Rprev
+  auto chol_phase = [&](size_t off, bool second) -> slar_status {
+    std::vector<CholDesc> sm, bg;
+    for (int j = 0; j < n; ++j) {
+      if (!live(j)) continue;
+      const Tbuf& b = tb[j];
+      const int k = jobs[j].in.k;
+      auto& v = (k <= SLAR_KMAX) ? sm : bg;
+      if (second) {
+        v.push_back(CholDesc{k, b.cu.G, b.cu.Linv, b.R, b.cu.R1});
+        v.push_back(CholDesc{k, b.cv.G, b.cv.Linv, Rv_of(j), b.cv.R1});
+      } else {
+        v.push_back(CholDesc{k, b.cu.G, b.cu.Linv, b.cu.R1, nullptr});
+        v.push_back(CholDesc{k, b.cv.G, b.cv.Linv, b.cv.R1, nullptr});
+      }
+    }
+    if (upload(s, D, H, off, sm, bg) != hipSuccess) return SLAR_E_HIP;
+    if (chol_inv_group(s, (int)sm.size(), (const CholDesc*)(D + off), false) != hipSuccess) return SLAR_E_HIP;
+    if (chol_inv_group(s, (int)bg.size(), (const CholDesc*)(D + off) + sm.size(), true) != hipSuccess)
+      return SLAR_E_HIP;
+    return SLAR_OK;
+  };
+
+  // A1: Grams of U and V
+  if ((e = each([&](int j, hipStream_t st) {
+         if (!live(j)) return;
+         const GridDev& G = jobs[j].ws->G;
+         const Tbuf& b = tb[j];
+         const int k = jobs[j].in.k;
+         if (gram_rows(st, b.cu.part, k, G.nx, jobs[j].in.U, G.nx, b.cu.G) != hipSuccess ||
+             gram_rows(st, b.cv.part, k, G.nv, jobs[j].in.V, G.nv, b.cv.G) != hipSuccess)
+           fail(j, SLAR_E_HIP);
+       })) != SLAR_OK)
+    return e;
+  if ((e = chol_phase(GL.chol1, false)) != SLAR_OK) return e;
+  // A2: first orthogonalisation and the Grams of its result
+  if ((e = each([&](int j, hipStream_t st) {
+         if (!live(j)) return;
+         const GridDev& G = jobs[j].ws->G;
+         const Tbuf& b = tb[j];
+         const int k = jobs[j].in.k;
+         if (gemm_f64(st, false, false, k, G.nx, k, 1.0, b.cu.Linv, k, 0, jobs[j].in.U, G.nx, 0, 0.0, b.Q1u,
+                      G.nx, 0, 1) != hipSuccess ||
+             gram_rows(st, b.cu.part, k, G.nx, b.Q1u, G.nx, b.cu.G) != hipSuccess ||
+             gemm_f64(st, false, false, k, G.nv, k, 1.0, b.cv.Linv, k, 0, jobs[j].in.V, G.nv, 0, 0.0, b.Q1v,
+                      G.nv, 0, 1) != hipSuccess ||
+             gram_rows(st, b.cv.part, k, G.nv, b.Q1v, G.nv, b.cv.G) != hipSuccess)
+           fail(j, SLAR_E_HIP);
+       })) != SLAR_OK)
+    return e;
+  if ((e = chol_phase(GL.chol2, true)) != SLAR_OK) return e;
+  // A3: second orthogonalisation, core M = Ru Rv^T
+  if ((e = each([&](int j, hipStream_t st) {
+         if (!live(j)) return;
+         const GridDev& G = jobs[j].ws->G;
+         const Tbuf& b = tb[j];
+         const int k = jobs[j].in.k;
+         if (gemm_f64(st, false, false, k, G.nx, k, 1.0, b.cu.Linv, k, 0, b.Q1u, G.nx, 0, 0.0, b.Qu, G.nx, 0,
+                      1) != hipSuccess ||
+             gemm_f64(st, false, false, k, G.nv, k, 1.0, b.cv.Linv, k, 0, b.Q1v, G.nv, 0, 0.0, b.Qv, G.nv, 0,
+                      1) != hipSuccess ||
+             gemm_f64(st, false, true, k, k, k, 1.0, b.R, k, 0, Rv_of(j), k, 0, 0.0, b.M, k, 0, 1) != hipSuccess)
+           fail(j, SLAR_E_HIP);
+       })) != SLAR_OK)
+    return e;
+  // A4: core SVDs, singular values gathered for the host
+  {
+    std::vector<SvdDesc> sm, bg;
+    double* svs = (double*)(D + GL.sv);
+    for (int j = 0; j < n; ++j) {
+      if (!live(j)) continue;
+      const Tbuf& b = tb[j];
+      const int k = jobs[j].in.k;
+      if (k > 64) bg.push_back(SvdDesc{k, b.M, b.W, b.sv, nullptr, svs + (size_t)j * CK});
+      else sm.push_back(SvdDesc{k, b.M, b.W, b.sv, b.Z, svs + (size_t)j * CK});
+    }
+    if (upload(s, D, H, GL.svd, sm, bg) != hipSuccess) return SLAR_E_HIP;
+    if (svd_group(s, (int)sm.size(), (const SvdDesc*)(D + GL.svd), false) != hipSuccess) return SLAR_E_HIP;
+    if (svd_group(s, (int)bg.size(), (const SvdDesc*)(D + GL.svd) + sm.size(), true) != hipSuccess)
+      return SLAR_E_HIP;
+    HIP_TRY(hipMemcpyAsync(H + GL.sv, D + GL.sv, sizeof(double) * CK * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  // root ranks (the rule of truncate_run)
+  for (int j = 0; j < n; ++j) {
+    if (!live(j)) continue;
+    TruncJob& J = jobs[j];
+    const int k = J.in.k;
+    const double* sv = (const double*)(H + GL.sv) + (size_t)j * CK;
+    double norm2 = 0.0;
+    bool finite = true;
+    for (int i = 0; i < k; ++i) {
+      if (!std::isfinite(sv[i])) finite = false;
+      norm2 += sv[i] * sv[i];
+    }
+    if (!finite) { fail(j, SLAR_E_NUMERIC); continue; }
+    const int d = J.ws->G.d;
+    J.theta = tol * std::sqrt(norm2) / std::sqrt((double)std::max(2 * d - 3, 1));
+    std::vector<double> s2(k);
+    for (int i = 0; i < k; ++i) s2[i] = sv[i] * sv[i];
+    J.r = tail_rank(s2, J.theta, rmax);
+    double tail = 0.0;
+    for (int i = J.r; i < k; ++i) tail += s2[i];
+    J.capped = J.r == rmax && std::sqrt(tail) > J.theta;
+  }
+  // B1: kept right vectors (k > 64), frames, sign rule, root; d = 2 ends
+  // here, d = 4 forms the mode Grams
+  if ((e = each([&](int j, hipStream_t st) {
+         if (!live(j)) return;
+         TruncJob& J = jobs[j];
+         Workspace* ws = J.ws;
+         const GridDev& G = ws->G;
+         const Tbuf& b = tb[j];
+         const int k = J.in.k, r = J.r;
+         bool ok = true;
+         if (k > 64) {
+           ok = ok && gemm_f64(st, true, false, k, r, k, 1.0, b.M, k, 0, b.W, k, 0, 0.0, b.Z, k, 0, 1) == hipSuccess;
+           ok = ok && scale_cols_inv(st, k, r, b.Z, k, b.sv) == hipSuccess;
+         }
+         ok = ok && gemm_f64(st, true, false, G.nx, r, k, 1.0, b.Qu, G.nx, 0, b.W, k, 0, 0.0, b.X, r, 0, 1) ==
+                        hipSuccess;
+         ok = ok && gemm_f64(st, true, false, G.nv, r, k, 1.0, b.Qv, G.nv, 0, b.Z, k, 0, 0.0, b.Y, r, 0, 1) ==
+                        hipSuccess;
+         ok = ok && sign_fix_tall(st, ws->dwork, ws->dwork_elems, G.nx, r, b.X, r, b.Y, r, G.nv) == hipSuccess;
+         if (ok) k_diag<<<(r * r + 255) / 256, 256, 0, st>>>(r, b.sv, (double*)J.out->root);
+         if (G.d == 2) {
+           ok = ok && copy2d(st, G.nx, r, b.X, r, (double*)J.out->leaf[0], r, nullptr) == hipSuccess;
+           ok = ok && copy2d(st, G.nv, r, b.Y, r, (double*)J.out->leaf[1], r, nullptr) == hipSuccess;
+           J.out->rank[0] = r; J.out->rank[1] = r;
+           for (int m = 2; m < 6; ++m) J.out->rank[m] = 0;
+         } else {
+           ok = ok && side_grams(st, b.cu.part, b.X, G.n[0], G.n[1], r, b.sv, b.Xs, b.G1, b.G2) == hipSuccess;
+           ok = ok && side_grams(st, b.cv.part, b.Y, G.n[2], G.n[3], r, b.sv, b.Ys, b.G3, b.G4) == hipSuccess;
+         }
+         if (!ok || hipGetLastError() != hipSuccess) fail(j, SLAR_E_HIP);
+       })) != SLAR_OK)
+    return e;
+  // B2: Gram eigenpairs of every d = 4 job; with the refinement pass, basis
+  // completion, refined Grams, their eigenpairs and E V
+  auto four = [&](int j) { return live(j) && jobs[j].ws->G.d == 4; };
+  auto refine = [&](int j) { return four(j) && jobs[j].ws->leaf_refine; };
+  double* lst = (double*)(D + GL.lam);
+  auto lam_slot = [&](int j, int m) { return lst + ((size_t)j * 4 + m) * SLAR_NMAX; };
+  bool any4 = false, anyref = false;
+  for (int j = 0; j < n; ++j) { any4 = any4 || four(j); anyref = anyref || refine(j); }
+  if (any4) {
+    std::vector<EigDesc> ed, none;
+    for (int j = 0; j < n; ++j) {
+      if (!four(j)) continue;
+      const Tbuf& b = tb[j];
+      const GridDev& G = jobs[j].ws->G;
+      const double* Gm[4] = {b.G1, b.G2, b.G3, b.G4};
+      double* lm[4] = {b.lam1, b.lam2, b.lam3, b.lam4};
+      double* Em[4] = {b.E1, b.E2, b.E3, b.E4};
+      for (int m = 0; m < 4; ++m)
+        ed.push_back(EigDesc{G.n[m], Gm[m], lm[m], Em[m], refine(j) ? nullptr : lam_slot(j, m)});
+    }
+    if (upload(s, D, H, GL.eig1, ed, none) != hipSuccess) return SLAR_E_HIP;
+    if (eig_sym_group(s, (int)ed.size(), (const EigDesc*)(D + GL.eig1)) != hipSuccess) return SLAR_E_HIP;
+  }
+  if (anyref) {
+    std::vector<BasisDesc> bd, none;
+    for (int j = 0; j < n; ++j) {
+      if (!refine(j)) continue;
+      const Tbuf& b = tb[j];
+      const GridDev& G = jobs[j].ws->G;
+      double* Em[4] = {b.E1, b.E2, b.E3, b.E4};
+      for (int m = 0; m < 4; ++m) bd.push_back(BasisDesc{G.n[m], Em[m]});
+    }
+    if (upload(s, D, H, GL.basis, bd, none) != hipSuccess) return SLAR_E_HIP;
+    if (complete_basis_group(s, (int)bd.size(), (const BasisDesc*)(D + GL.basis)) != hipSuccess)
+      return SLAR_E_HIP;
+    if ((e = each([&](int j, hipStream_t st) {
+           if (!refine(j)) return;
+           const GridDev& G = jobs[j].ws->G;
+           const Tbuf& b = tb[j];
+           const int r = jobs[j].r;
+           if (side_refine_grams(st, b.cu.part, b.Xs, G.n[0], G.n[1], r, b.E1, b.E2, G.n[0], G.n[1], b.T, b.G1,
+                                 b.G2) != hipSuccess ||
+               side_refine_grams(st, b.cv.part, b.Ys, G.n[2], G.n[3], r, b.E3, b.E4, G.n[2], G.n[3], b.T2, b.G3,
+                                 b.G4) != hipSuccess)
+             fail(j, SLAR_E_HIP);
+         })) != SLAR_OK)
+      return e;
+    std::vector<EigDesc> ed, nonee;
+    for (int j = 0; j < n; ++j) {
+      if (!refine(j)) continue;
+      const Tbuf& b = tb[j];
+      const GridDev& G = jobs[j].ws->G;
+      const double* Gm[4] = {b.G1, b.G2, b.G3, b.G4};
+      double* lm[4] = {b.lam1, b.lam2, b.lam3, b.lam4};
+      for (int m = 0; m < 4; ++m)
+        ed.push_back(EigDesc{G.n[m], Gm[m], lm[m], b.Vw + (size_t)m * SLAR_NMAX * SLAR_NMAX, lam_slot(j, m)});
+    }
+    if (upload(s, D, H, GL.eig2, ed, nonee) != hipSuccess) return SLAR_E_HIP;
+    if (eig_sym_group(s, (int)ed.size(), (const EigDesc*)(D + GL.eig2)) != hipSuccess) return SLAR_E_HIP;
+    if ((e = each([&](int j, hipStream_t st) {
+           if (!refine(j)) return;
+           const GridDev& G = jobs[j].ws->G;
+           const Tbuf& b = tb[j];
+           double* Em[4] = {b.E1, b.E2, b.E3, b.E4};
+           double* Gw[4] = {b.G1, b.G2, b.G3, b.G4};
+           for (int m = 0; m < 4; ++m) {
+             const int nm = G.n[m], c2 = std::min(nm, EIG_COLS);
+             if (gemm_f64(st, false, false, nm, c2, nm, 1.0, Em[m], nm, 0, b.Vw + (size_t)m * SLAR_NMAX * SLAR_NMAX,
+                          nm, 0, 0.0, Gw[m], c2, 0, 1) != hipSuccess) {
+               fail(j, SLAR_E_HIP);
+               return;
+             }
+           }
+         })) != SLAR_OK)
+      return e;
+  }
+  if (any4) {
+    HIP_TRY(hipMemcpyAsync(H + GL.lam, D + GL.lam, sizeof(double) * 4 * SLAR_NMAX * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // C: leaf ranks, leaf bases and transfer tensors
+    std::vector<std::array<int, 4>> rk(n);
+    for (int j = 0; j < n; ++j) {
+      if (!four(j)) continue;
+      const GridDev& G = jobs[j].ws->G;
+      const double* lh = (const double*)(H + GL.lam) + (size_t)j * 4 * SLAR_NMAX;
+      for (int m = 0; m < 4 && live(j); ++m) {
+        std::vector<double> l(lh + m * SLAR_NMAX, lh + m * SLAR_NMAX + G.n[m]);
+        for (double v : l)
+          if (!std::isfinite(v)) fail(j, SLAR_E_NUMERIC);
+        if (live(j)) rk[j][m] = leaf_rank(l, jobs[j].theta, rmax, &jobs[j].capped);
+      }
+    }
+    if ((e = each([&](int j, hipStream_t st) {
+           if (!four(j)) return;
+           TruncJob& J = jobs[j];
+           const GridDev& G = J.ws->G;
+           const Tbuf& b = tb[j];
+           const int r = J.r;
+           const bool rf = J.ws->leaf_refine;
+           const double* Ub[4] = {rf ? b.G1 : b.E1, rf ? b.G2 : b.E2, rf ? b.G3 : b.E3, rf ? b.G4 : b.E4};
+           int ldu[4];
+           for (int m = 0; m < 4; ++m) ldu[m] = rf ? std::min(G.n[m], EIG_COLS) : G.n[m];
+           const int* R = rk[j].data();
+           slar_status q = side_finish(st, b.T, b.X, G.n[0], G.n[1], r, Ub[0], ldu[0], Ub[1], ldu[1], R[0], R[1],
+                                       (double*)J.out->leaf[0], (double*)J.out->leaf[1], (double*)J.out->B12);
+           if (q == SLAR_OK)
+             q = side_finish(st, b.T2, b.Y, G.n[2], G.n[3], r, Ub[2], ldu[2], Ub[3], ldu[3], R[2], R[3],
+                             (double*)J.out->leaf[2], (double*)J.out->leaf[3], (double*)J.out->B34);
+           if (q != SLAR_OK) { fail(j, q); return; }
+           for (int m = 0; m < 4; ++m) J.out->rank[m] = R[m];
+           J.out->rank[4] = r; J.out->rank[5] = r;
+         })) != SLAR_OK)
+      return e;
+  }
+  for (TruncJob& J : jobs) {
+    if (J.st != SLAR_OK) continue;
+    J.out->dtype = SLAR_F64;
+    J.out->d = J.ws->G.d;
+    if (J.capped) J.st = SLAR_E_RANK_CAP;
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return SLAR_OK;
 }
 
 }  // namespace slar

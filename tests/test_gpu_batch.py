@@ -111,18 +111,28 @@ def test_batch_rejects_bad_arguments():
         b.batch.set_config(256, 1, 8, (4, 5, 16))
 
 
-def test_batch_truncation_of_more_than_64_terms_equals_single_instance():
-    """Converged crosses of up to min(2 rmax, 128) terms reach the batched
-    truncation (the rank cap applies after it): factor sets of 80 terms
-    give, bit for bit, the HT tensors of the one-instance slar_truncate on a
-    workspace with the same settings (no leaf refinement)."""
+@pytest.mark.parametrize("refine", [False, True])
+def test_grouped_truncation_equals_single_instance(refine):
+    """The batched truncation runs every instance's single-block
+    factorisations (Cholesky, core SVD, Gram eigenpairs, basis completion)
+    as one grouped launch per phase; each instance must still get, bit for
+    bit, the HT tensor and ranks of the one-instance slar_truncate on a
+    workspace with the same leaf-refinement setting.  Factor sets of 40 to
+    96 terms (the k <= 64 and k > 64 SVD forms in the same group), 1D1V and
+    2D2V instances mixed; converged crosses of up to min(2 rmax, 128) terms
+    reach the truncation (the rank cap applies after it)."""
     from paper_2606_29027_amd.batch import _Inst
     from gpu_util import dev, ht_from_dev
-    problems = SI.batched_instances(4, sizes=(12, 16), sizes_1d=(96, 128))
+    problems = SI.batched_instances(6, sizes=(12, 16), sizes_1d=(96, 128))
+    assert {p.dx for p in problems} == {1, 2}
     b, _ = _solver(problems)
-    k, tol = 80, 1e-6
+    for ws in b.batch.ws:
+        L.slar_leaf_refine(ws, refine)
+    tol = 1e-6
+    ks = [40, 80, 64, 96, 72, 50]
     keep, lrs = [], []
     for q, I in enumerate(b.inst):
+        k = ks[q]
         rng = np.random.default_rng(40 + q)
         U = dev(rng.standard_normal((k, I.Nx)) * (0.8 ** np.arange(k))[:, None])
         V = dev(rng.standard_normal((k, I.Nv)))
@@ -135,7 +145,7 @@ def test_batch_truncation_of_more_than_64_terms_equals_single_instance():
         one = _Inst(p)
         H = one.ht_desc(0)
         ws = L.Workspace(L.make_grid(p), b.rmax)
-        L.slar_leaf_refine(ws, False)
+        L.slar_leaf_refine(ws, refine)
         L.slar_truncate(ws.grid, lrs[q], tol, b.rmax, H, ws)
         torch.cuda.synchronize()
         assert list(H.rank) == list(hts[q].rank), q
