@@ -271,7 +271,8 @@ struct slar_batch {
   hipEvent_t ev_in = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double tstat[4] = {0, 0, 0, 0};  // cross ms, chunks, iterations (max over instances), calls
-  // grouped truncation: descriptors and gathered values (device, pinned mirror)
+  // grouped truncation and skeleton cores: descriptors and gathered values
+  // (device, pinned mirror)
   void* d_tg = nullptr;
   void* h_tg = nullptr;
 };
@@ -381,13 +382,28 @@ static slar_status batch_cross(slar_batch* b, const slar_frames* src, const slar
     if (!std::isfinite(m.norm2)) st = SLAR_E_NUMERIC;
     else if ((m.capped || m.phase != ACA_DONE) && st == SLAR_OK) st = SLAR_E_RANK_CAP;
   }
-  // instances stopped at the term cap: regularised skeleton (as slar_cross_update)
-  for (int q = 0; q < b->count && st != SLAR_E_NUMERIC; ++q) {
-    const BSummary& m = b->h_sum[q];
-    if ((m.capped || m.phase != ACA_DONE) && out[q].k > b->rmax) {
-      const slar_status sq = cur_core_run(s, &b->ws[q]->w, &out[q], b->rmax);
-      if (sq != SLAR_OK) return sq;
-      if (info) info[q].rank = out[q].k;
+  // instances stopped at the term cap: regularised skeleton (as
+  // slar_cross_update), their pivot-block SVDs grouped
+  if (st != SLAR_E_NUMERIC) {
+    std::vector<Workspace*> cws;
+    std::vector<slar_lowrank*> cout;
+    std::vector<int> cq, ccap;
+    for (int q = 0; q < b->count; ++q) {
+      const BSummary& m = b->h_sum[q];
+      if ((m.capped || m.phase != ACA_DONE) && out[q].k > b->rmax) {
+        cws.push_back(&b->ws[q]->w);
+        cout.push_back(&out[q]);
+        cq.push_back(q);
+        ccap.push_back(b->rmax);
+      }
+    }
+    std::vector<slar_status> cst(cq.size(), SLAR_OK);
+    const slar_status e = cur_core_group(s, (int)cq.size(), cws.data(), cout.data(), ccap.data(), cst.data(),
+                                         b->d_tg, b->h_tg);
+    if (e != SLAR_OK) return e;
+    for (size_t j = 0; j < cq.size(); ++j) {
+      if (cst[j] != SLAR_OK) return cst[j];
+      if (info) info[cq[j]].rank = out[cq[j]].k;
     }
   }
   b->tstat[0] += ms; b->tstat[1] += chunks; b->tstat[2] += maxiters; b->tstat[3] += 1;
@@ -506,8 +522,11 @@ slar_status slar_batch_create(int32_t count, const slar_grid* grids, int32_t rma
   hal((void**)&b->h_prep, sizeof(BPrep) * count);
   hal((void**)&b->h_active, sizeof(int));
   hal((void**)&b->h_sum, sizeof(BSummary) * count);
-  dal(&b->d_tg, truncate_group_bytes(count));
-  hal(&b->h_tg, truncate_group_bytes(count));
+  // shared by the grouped truncation and the grouped skeleton cores (never
+  // in use at the same time: each returns after synchronising)
+  const size_t tg = std::max(truncate_group_bytes(count), cur_core_group_bytes(count));
+  dal(&b->d_tg, tg);
+  hal(&b->h_tg, tg);
   if (!ok) return fail(SLAR_E_NOMEM);
   std::memset(b->h_inst, 0, sizeof(AcaInst) * count);
   if (hipMemcpy(b->d_inst, b->h_inst, sizeof(AcaInst) * count, hipMemcpyHostToDevice) != hipSuccess)

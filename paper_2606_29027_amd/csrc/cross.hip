@@ -19,7 +19,9 @@
 // Kernel boundaries order the partial sums; no inter-block fences are used.
 // The rank-1 terms are u_k v_k^T with u_k = column residual / r_j and
 // v_k = row residual (the same product as the textbook v = r / r_j).
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include <hip/hip_ext.h>
 
@@ -188,58 +190,122 @@ __global__ void k_cur_gather(int k, const double* __restrict__ U, int Nx, const 
 // W = Ui Vjt^T.  With W = Y diag(s) Z^T and r = min(rcap, #{s > 1e-14 s_1})
 // the regularised skeleton C Z_r diag(s_r)^-1 Y_r^T R is returned as the r
 // terms U' = (Z_r diag(s_r)^-1)^T Vjt U and V' = Y_r^T Ui V.
-slar_status cur_core_run(hipStream_t s, Workspace* ws, slar_lowrank* out, int rcap) {
+namespace {
+struct CurBuf {
+  double *Ui, *Vjt, *W, *Y, *Z, *sv, *Pm, *Qm, *Ut, *Vt;
+};
+CurBuf cur_carve(Workspace* ws, int k) {
   const GridDev& G = ws->G;
-  const int k = out->k, Nx = G.nx, Nv = G.nv;
-  double* U = out->U;
-  double* V = out->V;
   double* p = ws->small;
-  double* Ui = p; p += (size_t)k * k;
-  double* Vjt = p; p += (size_t)k * k;
-  double* W = p; p += (size_t)k * k;
-  double* Y = p; p += (size_t)k * k;
-  double* Z = p; p += (size_t)k * k;
-  double* sv = p; p += k;
-  double* Pm = p; p += (size_t)k * k;
-  double* Qm = p; p += (size_t)k * k;
-  double* Ut = p; p += (size_t)k * Nx;
-  double* Vt = p; p += (size_t)k * Nv;
-  k_cur_gather<<<(k * k + 255) / 256, 256, 0, s>>>(k, U, Nx, V, Nv, ws->aca_piv, Ui, Vjt);
-  HIP_TRY(hipGetLastError());
-  if (gemm_f64(s, false, true, k, k, k, 1.0, Ui, k, 0, Vjt, k, 0, 0.0, W, k, 0, 1) != hipSuccess)
-    return SLAR_E_HIP;
-  const bool big = k > 64;
-  if (big) {
-    if (svd_left_big(s, k, W, Y, sv) != hipSuccess) return SLAR_E_HIP;
-  } else if (svd_small(s, k, W, Y, sv, Z) != hipSuccess) {
+  CurBuf c;
+  c.Ui = p; p += (size_t)k * k;
+  c.Vjt = p; p += (size_t)k * k;
+  c.W = p; p += (size_t)k * k;
+  c.Y = p; p += (size_t)k * k;
+  c.Z = p; p += (size_t)k * k;
+  c.sv = p; p += k;
+  c.Pm = p; p += (size_t)k * k;
+  c.Qm = p; p += (size_t)k * k;
+  c.Ut = p; p += (size_t)k * G.nx;
+  c.Vt = p; p += (size_t)k * G.nv;
+  return c;
+}
+// pivot rows / columns and the pivot block W
+hipError_t cur_front(hipStream_t s, Workspace* ws, const slar_lowrank* out, const CurBuf& c) {
+  const int k = out->k;
+  k_cur_gather<<<(k * k + 255) / 256, 256, 0, s>>>(k, out->U, ws->G.nx, out->V, ws->G.nv, ws->aca_piv, c.Ui, c.Vjt);
+  HIP_CHK(hipGetLastError());
+  return gemm_f64(s, false, true, k, k, k, 1.0, c.Ui, k, 0, c.Vjt, k, 0, 0.0, c.W, k, 0, 1);
+}
+// kept triplets: s_i > 1e-14 s_1, at most rcap, at least one; 0 if s_1 is
+// not a positive finite number
+int cur_rank(const double* hs, int k, int rcap) {
+  if (!(hs[0] > 0.0) || !std::isfinite(hs[0])) return 0;
+  int r = 0;
+  while (r < k && r < rcap && hs[r] > 1e-14 * hs[0]) ++r;
+  return std::max(r, 1);
+}
+// the r new terms, written over the first r of U and V
+hipError_t cur_back(hipStream_t s, Workspace* ws, slar_lowrank* out, const CurBuf& c, int r) {
+  const int k = out->k, Nx = ws->G.nx, Nv = ws->G.nv;
+  if (k > 64) {
+    // right vectors of the kept triplets: Z_r = W^T Y_r diag(s_r)^-1
+    HIP_CHK(gemm_f64(s, true, false, k, r, k, 1.0, c.W, k, 0, c.Y, k, 0, 0.0, c.Z, k, 0, 1));
+    HIP_CHK(scale_cols_inv(s, k, r, c.Z, k, c.sv));
+  }
+  HIP_CHK(scale_cols_inv(s, k, r, c.Z, k, c.sv));   // Z_r diag(s_r)^-1
+  HIP_CHK(gemm_f64(s, true, false, r, k, k, 1.0, c.Z, k, 0, c.Vjt, k, 0, 0.0, c.Pm, k, 0, 1));
+  HIP_CHK(gemm_f64(s, true, false, r, k, k, 1.0, c.Y, k, 0, c.Ui, k, 0, 0.0, c.Qm, k, 0, 1));
+  HIP_CHK(gemm_f64(s, false, false, r, Nx, k, 1.0, c.Pm, k, 0, out->U, Nx, 0, 0.0, c.Ut, Nx, 0, 1));
+  HIP_CHK(gemm_f64(s, false, false, r, Nv, k, 1.0, c.Qm, k, 0, out->V, Nv, 0, 0.0, c.Vt, Nv, 0, 1));
+  HIP_CHK(hipMemcpyAsync(out->U, c.Ut, sizeof(double) * r * Nx, hipMemcpyDeviceToDevice, s));
+  return hipMemcpyAsync(out->V, c.Vt, sizeof(double) * r * Nv, hipMemcpyDeviceToDevice, s);
+}
+}  // namespace
+
+slar_status cur_core_run(hipStream_t s, Workspace* ws, slar_lowrank* out, int rcap) {
+  const int k = out->k;
+  const CurBuf c = cur_carve(ws, k);
+  if (cur_front(s, ws, out, c) != hipSuccess) return SLAR_E_HIP;
+  if (k > 64) {
+    if (svd_left_big(s, k, c.W, c.Y, c.sv) != hipSuccess) return SLAR_E_HIP;
+  } else if (svd_small(s, k, c.W, c.Y, c.sv, c.Z) != hipSuccess) {
     return SLAR_E_HIP;
   }
   double* hs = (double*)ws->host_pinned;
-  HIP_TRY(hipMemcpyAsync(hs, sv, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hs, c.sv, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (!(hs[0] > 0.0) || !std::isfinite(hs[0])) return SLAR_E_NUMERIC;
-  int r = 0;
-  while (r < k && r < rcap && hs[r] > 1e-14 * hs[0]) ++r;
-  r = std::max(r, 1);
-  if (big) {
-    // right vectors of the kept triplets: Z_r = W^T Y_r diag(s_r)^-1
-    if (gemm_f64(s, true, false, k, r, k, 1.0, W, k, 0, Y, k, 0, 0.0, Z, k, 0, 1) != hipSuccess)
-      return SLAR_E_HIP;
-    if (scale_cols_inv(s, k, r, Z, k, sv) != hipSuccess) return SLAR_E_HIP;
-  }
-  if (scale_cols_inv(s, k, r, Z, k, sv) != hipSuccess) return SLAR_E_HIP;   // Z_r diag(s_r)^-1
-  if (gemm_f64(s, true, false, r, k, k, 1.0, Z, k, 0, Vjt, k, 0, 0.0, Pm, k, 0, 1) != hipSuccess)
-    return SLAR_E_HIP;
-  if (gemm_f64(s, true, false, r, k, k, 1.0, Y, k, 0, Ui, k, 0, 0.0, Qm, k, 0, 1) != hipSuccess)
-    return SLAR_E_HIP;
-  if (gemm_f64(s, false, false, r, Nx, k, 1.0, Pm, k, 0, U, Nx, 0, 0.0, Ut, Nx, 0, 1) != hipSuccess)
-    return SLAR_E_HIP;
-  if (gemm_f64(s, false, false, r, Nv, k, 1.0, Qm, k, 0, V, Nv, 0, 0.0, Vt, Nv, 0, 1) != hipSuccess)
-    return SLAR_E_HIP;
-  HIP_TRY(hipMemcpyAsync(U, Ut, sizeof(double) * r * Nx, hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipMemcpyAsync(V, Vt, sizeof(double) * r * Nv, hipMemcpyDeviceToDevice, s));
+  const int r = cur_rank(hs, k, rcap);
+  if (r == 0) return SLAR_E_NUMERIC;
+  if (cur_back(s, ws, out, c, r) != hipSuccess) return SLAR_E_HIP;
   HIP_TRY(hipStreamSynchronize(s));
   out->k = r;
+  return SLAR_OK;
+}
+
+// The same for several capped crosses at once: the pivot-block SVDs run as
+// one grouped launch per size class, and the host reads all singular
+// values in one copy.  dmem / hmem: cur_core_group_bytes(n) of device /
+// pinned host memory.
+static size_t cg_align(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t cur_core_group_bytes(int n) {
+  n = std::max(n, 1);
+  return cg_align(sizeof(SvdDesc) * n) + cg_align(sizeof(double) * SLAR_CROSS_KMAX * n);
+}
+
+slar_status cur_core_group(hipStream_t s, int n, Workspace* const* ws, slar_lowrank* const* out,
+                           const int* rcap, slar_status* st, void* dmem, void* hmem) {
+  if (n <= 0) return SLAR_OK;
+  const size_t CK = SLAR_CROSS_KMAX, off_sv = cg_align(sizeof(SvdDesc) * n);
+  std::vector<CurBuf> cb(n);
+  std::vector<SvdDesc> sm, bg;
+  double* svs = (double*)((char*)dmem + off_sv);
+  for (int j = 0; j < n; ++j) {
+    const int k = out[j]->k;
+    st[j] = SLAR_OK;
+    cb[j] = cur_carve(ws[j], k);
+    if (cur_front(s, ws[j], out[j], cb[j]) != hipSuccess) return SLAR_E_HIP;
+    if (k > 64) bg.push_back(SvdDesc{k, cb[j].W, cb[j].Y, cb[j].sv, nullptr, svs + (size_t)j * CK});
+    else sm.push_back(SvdDesc{k, cb[j].W, cb[j].Y, cb[j].sv, cb[j].Z, svs + (size_t)j * CK});
+  }
+  SvdDesc* hd = (SvdDesc*)hmem;
+  std::copy(sm.begin(), sm.end(), hd);
+  std::copy(bg.begin(), bg.end(), hd + sm.size());
+  HIP_TRY(hipMemcpyAsync(dmem, hmem, sizeof(SvdDesc) * n, hipMemcpyHostToDevice, s));
+  if (svd_group(s, (int)sm.size(), (const SvdDesc*)dmem, false) != hipSuccess) return SLAR_E_HIP;
+  if (svd_group(s, (int)bg.size(), (const SvdDesc*)dmem + sm.size(), true) != hipSuccess) return SLAR_E_HIP;
+  const double* hs = (const double*)((char*)hmem + off_sv);
+  HIP_TRY(hipMemcpyAsync((char*)hmem + off_sv, svs, sizeof(double) * CK * n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int> r(n);
+  for (int j = 0; j < n; ++j) {
+    r[j] = cur_rank(hs + (size_t)j * CK, out[j]->k, rcap[j]);
+    if (r[j] == 0) { st[j] = SLAR_E_NUMERIC; continue; }
+    if (cur_back(s, ws[j], out[j], cb[j], r[j]) != hipSuccess) return SLAR_E_HIP;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int j = 0; j < n; ++j)
+    if (st[j] == SLAR_OK) out[j]->k = r[j];
   return SLAR_OK;
 }
 

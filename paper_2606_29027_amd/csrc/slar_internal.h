@@ -139,6 +139,12 @@ hipError_t combine_field(hipStream_t s, const GridDev& G, const slar_adv* a, dou
 // Regularised skeleton of a cross that stopped at its term cap: replaces
 // the k terms in out by min(rcap, rank W) terms of C W_r^+ R (synchronises)
 slar_status cur_core_run(hipStream_t s, Workspace* ws, slar_lowrank* out, int rcap);
+// The same for n crosses at once (the pivot-block SVDs in one grouped
+// launch, one host read of all singular values); per-cross statuses in
+// st[j].  dmem / hmem: cur_core_group_bytes(n) device / pinned host bytes.
+size_t cur_core_group_bytes(int n);
+slar_status cur_core_group(hipStream_t s, int n, Workspace* const* ws, slar_lowrank* const* out,
+                           const int* rcap, slar_status* st, void* dmem, void* hmem);
 
 }  // namespace slar
 

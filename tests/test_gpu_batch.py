@@ -1,6 +1,7 @@
 """Batched multi-instance path (slar_batch_*): the persistent multi-instance
-cross approximation replayed from a captured hipGraph against the
-one-instance library call, and whole batched steps against the CPU oracle.
+cross approximation replayed from a captured hipGraph, the grouped skeleton
+cores of capped crosses and the grouped truncation against the one-instance
+library calls, and whole batched steps against the CPU oracle.
 
 With the default team width (16 lanes per sample) a batched tile runs the
 same arithmetic as the one-instance kernels on the same FP32 tables, so U,
@@ -70,6 +71,40 @@ def test_batch_cross_bitwise_equals_single_instance_over_replays():
             assert info[q].samples == inf.samples and info[q].probe_rounds == inf.probe_rounds, q
             assert torch.equal(got[q][0][:k], U[:k]) and torch.equal(got[q][1][:k], V[:k]), q
     assert b.batch.config()["captures"] == 1
+
+
+def test_batch_capped_crosses_equal_single_instance():
+    """Crosses that stop at the term cap (k = 2 rmax > rmax) are replaced by
+    the regularised skeleton C W_r^+ R; the batched call groups the pivot-
+    block SVDs of all capped instances into one launch per size class.
+    Every instance must still get, bit for bit, the terms and rank of the
+    one-instance slar_cross_update on a workspace of the same rank cap."""
+    problems = SI.batched_instances(10)
+    pr = [_probes(p, 100 + q) for q, p in enumerate(problems)]
+    b = BatchSolver(problems, probes=pr, rmax=6)
+    b.set_initial([SI.initial_ht(p) for p in problems])
+    assert b.kcross == 12
+    E1 = b.efield(b.state, 0)
+    advs = [L.make_adv(2, b.dt / 3.0, 1.0, E) for E in E1]
+    lrs, info, _ = b.batch.cross_update(b.state, advs, b.tol, b.kcross, b.probes,
+                                        [I.U for I in b.inst], [I.V for I in b.inst])
+    torch.cuda.synchronize()
+    got = [(I.U.clone(), I.V.clone()) for I in b.inst]
+    capped = 0
+    for q in range(b.count):
+        I = b.inst[q]
+        ws = b.batch.ws[q]
+        U = torch.zeros_like(I.U); V = torch.zeros_like(I.V)
+        lr, inf, st = L.slar_cross_update(ws.grid, b.state[q], advs[q], L.F32, b.tol, b.kcross, b.probes[q],
+                                          U, V, ws)
+        torch.cuda.synchronize()
+        k = inf.rank
+        if st == L.SLAR_E_RANK_CAP:         # skeleton of at most rmax terms
+            capped += 1
+            assert k <= b.rmax, q
+        assert info[q].rank == k, q
+        assert torch.equal(got[q][0][:k], U[:k]) and torch.equal(got[q][1][:k], V[:k]), q
+    assert capped >= 2
 
 
 def test_batch_step_matches_oracle():
