@@ -592,26 +592,13 @@ slar_status slar_batch_truncate(slar_batch* b, const slar_lowrank* in, double to
     jobs[q].ws = &b->ws[q]->w;
     jobs[q].in = in[q];
     jobs[q].out = &out[q];
+    jobs[q].frames = frames ? &frames[q] : nullptr;
   }
-  // per-job work on the pool streams, single-block factorisations grouped
-  const TruncEach each = [&](const std::function<void(int, hipStream_t)>& fn) -> slar_status {
-    return pool_run(b, stream, [&](int q, hipStream_t s, Workspace*) -> slar_status {
-      fn(q, s);
-      return SLAR_OK;
-    }, nullptr);
-  };
-  const slar_status e = truncate_group(stream, jobs, tol, rmax, each, b->d_tg, b->h_tg);
+  // every step one grouped launch over all instances, on the caller stream
+  const slar_status e = truncate_group(stream, jobs, tol, rmax, b->d_tg, b->h_tg);
   if (e != SLAR_OK) return e;
   std::vector<slar_status> st(b->count);
   for (int q = 0; q < b->count; ++q) st[q] = jobs[q].st;
-  if (frames) {
-    const slar_status ef = pool_run(b, stream, [&](int q, hipStream_t s, Workspace* w) -> slar_status {
-      if (st[q] != SLAR_OK && st[q] != SLAR_E_RANK_CAP) return SLAR_OK;
-      if (frames_from_ht(s, w, w->G, out[q], &frames[q]) != hipSuccess) st[q] = SLAR_E_HIP;
-      return SLAR_OK;
-    }, nullptr);
-    if (ef != SLAR_OK) return ef;
-  }
   if (status)
     for (int q = 0; q < b->count; ++q) status[q] = st[q];
   return worst_of(st);

@@ -7,6 +7,7 @@
 #include "slar_internal.h"
 #include "dense.h"
 #include "dpp.h"
+#include "group.h"
 
 namespace slar {
 
@@ -36,8 +37,23 @@ struct Mode2 {
   }
 };
 
+// either addressing, chosen per problem (grouped launches)
+struct AnyAddr {
+  const double* A;
+  int lda, nb, r, mode2;
+  __device__ double operator()(int i, int j) const {
+    if (mode2) {
+      const int i1 = j / r, c = j - i1 * r;
+      return A[((long long)i1 * nb + i) * r + c];
+    }
+    return A[(long long)i * lda + j];
+  }
+};
+
+// block blk of nblk: chunks blk, blk + nblk, ...; partial at part + blk k^2
 template <int MT, class Addr>
-__global__ __launch_bounds__(256) void k_gram_part(int k, int n, Addr A, double* __restrict__ part) {
+__device__ __forceinline__ void gram_part_dev(int k, int n, const Addr& A, double* __restrict__ part, int blk,
+                                              int nblk) {
   __shared__ double S[16 * MT][GR_C + 1];
   const int t = threadIdx.x;
   const int tr = t >> 4, tc = t & 15;
@@ -47,7 +63,7 @@ __global__ __launch_bounds__(256) void k_gram_part(int k, int n, Addr A, double*
 #pragma unroll
     for (int b = 0; b < MT; ++b) acc[a][b] = 0.0;
   const int nchunk = (n + GR_C - 1) / GR_C;
-  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+  for (int ch = blk; ch < nchunk; ch += nblk) {
     const int j0 = ch * GR_C;
     __syncthreads();
     for (int e = t; e < 16 * MT * GR_C; e += 256) {
@@ -66,7 +82,7 @@ __global__ __launch_bounds__(256) void k_gram_part(int k, int n, Addr A, double*
         for (int b = 0; b < MT; ++b) acc[a][b] = fma(x[a], y[b], acc[a][b]);
     }
   }
-  double* out = part + (size_t)blockIdx.x * k * k;
+  double* out = part + (size_t)blk * k * k;
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
@@ -76,13 +92,28 @@ __global__ __launch_bounds__(256) void k_gram_part(int k, int n, Addr A, double*
     }
 }
 
+template <int MT, class Addr>
+__global__ __launch_bounds__(256) void k_gram_part(int k, int n, Addr A, double* __restrict__ part) {
+  gram_part_dev<MT>(k, n, A, part, blockIdx.x, gridDim.x);
+}
+
+template <int MT>
+__global__ __launch_bounds__(256) void k_gram_part_group(const GramDesc* __restrict__ D,
+                                                         const int* __restrict__ first, int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const GramDesc g = D[d];
+  const AnyAddr A{g.A, g.lda, g.nb, g.r, g.mode2};
+  gram_part_dev<MT>(g.k, g.n, A, g.part, b - first[d], g.nblk);
+}
+
 // 64 outputs per block, four waves each summing every fourth partial
 // (coalesced over the outputs), combined in a fixed order.
-__global__ __launch_bounds__(256) void k_gram_sum(int kk, int nblk, const double* __restrict__ part,
-                                                  double* __restrict__ G) {
+__device__ __forceinline__ void gram_sum_dev(int kk, int nblk, const double* __restrict__ part,
+                                             double* __restrict__ G, int blk) {
   __shared__ double q4[4][64];
   const int t = threadIdx.x, ln = t & 63, w = t >> 6;
-  const int e = blockIdx.x * 64 + ln;
+  const int e = blk * 64 + ln;
   double acc = 0.0;
   if (e < kk) {
 #pragma unroll 8
@@ -91,6 +122,33 @@ __global__ __launch_bounds__(256) void k_gram_sum(int kk, int nblk, const double
   q4[w][ln] = acc;
   __syncthreads();
   if (w == 0 && e < kk) G[e] = ((q4[0][ln] + q4[1][ln]) + q4[2][ln]) + q4[3][ln];
+}
+
+__global__ __launch_bounds__(256) void k_gram_sum(int kk, int nblk, const double* __restrict__ part,
+                                                  double* __restrict__ G) {
+  gram_sum_dev(kk, nblk, part, G, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_gram_sum_group(const GramDesc* __restrict__ D,
+                                                        const int* __restrict__ first, int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const GramDesc g = D[d];
+  gram_sum_dev(g.k * g.k, g.nblk, g.part, g.G, b - first[d]);
+}
+
+hipError_t gram_part_group_launch(hipStream_t s, bool mt8, const GramDesc* d, const int* first, int nd,
+                                  int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  if (mt8) k_gram_part_group<8><<<nblocks, 256, 0, s>>>(d, first, nd);
+  else k_gram_part_group<4><<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
+}
+
+hipError_t gram_sum_group_launch(hipStream_t s, const GramDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_gram_sum_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
 }
 
 // part: scratch for the per-block partials, cap doubles (the block count
@@ -696,12 +754,36 @@ hipError_t svd_group(hipStream_t s, int count, const SvdDesc* d, bool big) {
 }
 
 // Z[:, j] *= 1 / sv[j] (0 where sv[j] == 0), Z row-major k x ld, j < r
-__global__ void k_scale_cols_inv(int k, int r, double* __restrict__ Z, int ld, const double* __restrict__ sv) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void scale_cols_inv_dev(int k, int r, double* __restrict__ Z, int ld,
+                                                   const double* __restrict__ sv, int e) {
   if (e >= k * r) return;
   const int i = e / r, j = e % r;
   const double s = sv[j];
   Z[(size_t)i * ld + j] = s > 0.0 ? Z[(size_t)i * ld + j] / s : 0.0;
+}
+
+__global__ void k_scale_cols_inv(int k, int r, double* __restrict__ Z, int ld, const double* __restrict__ sv) {
+  scale_cols_inv_dev(k, r, Z, ld, sv, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// grouped: scale_cols_inv, or (diag) the r x r root diag(sv[:r]) into Z
+__global__ __launch_bounds__(256) void k_scale_group(const ScaleDesc* __restrict__ D, const int* __restrict__ first,
+                                                     int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const ScaleDesc g = D[d];
+  const int e = (b - first[d]) * 256 + (int)threadIdx.x;
+  if (g.diag) {
+    if (e < g.r * g.r) g.Z[e] = (e / g.r == e % g.r) ? g.sv[e / g.r] : 0.0;
+  } else {
+    scale_cols_inv_dev(g.k, g.r, g.Z, g.ld, g.sv, e);
+  }
+}
+
+hipError_t scale_group_launch(hipStream_t s, const ScaleDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_scale_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
 }
 
 hipError_t scale_cols_inv(hipStream_t s, int k, int r, double* Z, int ld, const double* sv) {
@@ -1004,9 +1086,8 @@ hipError_t complete_basis_batch(hipStream_t s, int count, const int* n, double* 
 // near-ties within 1e-10) is made positive; the same flip is applied to the
 // matching column of B (if given).  A is [rows][lda] (column c), one block
 // per column.
-__global__ void k_sign_fix(int rows, int cols, double* __restrict__ A, int lda,
-                           double* __restrict__ B, int ldb, int rowsB) {
-  const int c = blockIdx.x;
+__device__ __forceinline__ void sign_fix_dev(int rows, int cols, double* __restrict__ A, int lda,
+                                             double* __restrict__ B, int ldb, int rowsB, int c) {
   if (c >= cols) return;
   __shared__ double red[256];
   __shared__ int redi[256];
@@ -1039,6 +1120,25 @@ __global__ void k_sign_fix(int rows, int cols, double* __restrict__ A, int lda,
   }
 }
 
+__global__ void k_sign_fix(int rows, int cols, double* __restrict__ A, int lda,
+                           double* __restrict__ B, int ldb, int rowsB) {
+  sign_fix_dev(rows, cols, A, lda, B, ldb, rowsB, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_sign_fix_group(const SignDesc* __restrict__ D,
+                                                        const int* __restrict__ first, int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const SignDesc g = D[d];
+  sign_fix_dev(g.rows, g.cols, g.A, g.lda, g.B, g.ldb, g.rowsB, b - first[d]);
+}
+
+hipError_t sign_fix_group_launch(hipStream_t s, const SignDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_sign_fix_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
+}
+
 hipError_t sign_fix(hipStream_t s, int rows, int cols, double* A, int lda, double* B, int ldb,
                     int rowsB) {
   if (cols <= 0) return hipSuccess;
@@ -1052,27 +1152,31 @@ hipError_t sign_fix(hipStream_t s, int rows, int cols, double* A, int lda, doubl
 // it (the lowest qualifying index overall); the flips.
 constexpr int SF_COLS = 64;
 
-__global__ __launch_bounds__(256) void k_sign_part(int rows, int cols, const double* __restrict__ A,
-                                                   int lda, int rb, double* __restrict__ part) {
+__device__ __forceinline__ void sign_part_dev(int rows, int cols, const double* __restrict__ A, int lda, int rb,
+                                              double* __restrict__ part, int blk) {
   __shared__ double red[4][SF_COLS];
   const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * rb, r1 = min(rows, r0 + rb);
+  const int r0 = blk * rb, r1 = min(rows, r0 + rb);
   double m = -1.0;
   if (c < cols)
     for (int r = r0 + rl; r < r1; r += 4) m = fmax(m, fabs(A[(long long)r * lda + c]));
   red[rl][c] = m;
   __syncthreads();
   if (rl == 0 && c < cols)
-    part[(size_t)blockIdx.x * cols + c] = fmax(fmax(red[0][c], red[1][c]), fmax(red[2][c], red[3][c]));
+    part[(size_t)blk * cols + c] = fmax(fmax(red[0][c], red[1][c]), fmax(red[2][c], red[3][c]));
 }
 
-__global__ __launch_bounds__(256) void k_sign_decide(int rows, int cols, const double* __restrict__ A,
-                                                     int lda, int rb, int nb,
-                                                     const double* __restrict__ part,
-                                                     double* __restrict__ sgn) {
+__global__ __launch_bounds__(256) void k_sign_part(int rows, int cols, const double* __restrict__ A,
+                                                   int lda, int rb, double* __restrict__ part) {
+  sign_part_dev(rows, cols, A, lda, rb, part, blockIdx.x);
+}
+
+__device__ __forceinline__ void sign_decide_dev(int rows, int cols, const double* __restrict__ A, int lda, int rb,
+                                                int nb, const double* __restrict__ part, double* __restrict__ sgn,
+                                                int c) {
   __shared__ double redm[256];
   __shared__ int redi[256];
-  const int c = blockIdx.x, t = threadIdx.x;
+  const int t = threadIdx.x;
   double m = -1.0;
   for (int b = t; b < nb; b += blockDim.x) m = fmax(m, part[(size_t)b * cols + c]);
   redm[t] = m;
@@ -1112,9 +1216,16 @@ __global__ __launch_bounds__(256) void k_sign_decide(int rows, int cols, const d
   }
 }
 
-__global__ void k_sign_apply(long long na, int cols, double* __restrict__ A, int lda, long long nbe,
-                             double* __restrict__ B, int ldb, const double* __restrict__ sgn) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_sign_decide(int rows, int cols, const double* __restrict__ A,
+                                                     int lda, int rb, int nb,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ sgn) {
+  sign_decide_dev(rows, cols, A, lda, rb, nb, part, sgn, blockIdx.x);
+}
+
+__device__ __forceinline__ void sign_apply_dev(long long na, int cols, double* __restrict__ A, int lda,
+                                               long long nbe, double* __restrict__ B, int ldb,
+                                               const double* __restrict__ sgn, long long e) {
   if (e < na) {
     const int c = (int)(e % cols);
     if (sgn[c] < 0.0) {
@@ -1129,6 +1240,52 @@ __global__ void k_sign_apply(long long na, int cols, double* __restrict__ A, int
       *b = -*b;
     }
   }
+}
+
+__global__ void k_sign_apply(long long na, int cols, double* __restrict__ A, int lda, long long nbe,
+                             double* __restrict__ B, int ldb, const double* __restrict__ sgn) {
+  sign_apply_dev(na, cols, A, lda, nbe, B, ldb, sgn, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// grouped tall form: desc.part holds [nb][cols] partial maxima then [cols] signs
+__global__ __launch_bounds__(256) void k_sign_part_group(const SignDesc* __restrict__ D,
+                                                         const int* __restrict__ first, int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const SignDesc g = D[d];
+  sign_part_dev(g.rows, g.cols, g.A, g.lda, g.rb, g.part, b - first[d]);
+}
+__global__ __launch_bounds__(256) void k_sign_decide_group(const SignDesc* __restrict__ D,
+                                                           const int* __restrict__ first, int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const SignDesc g = D[d];
+  sign_decide_dev(g.rows, g.cols, g.A, g.lda, g.rb, g.nb, g.part, g.part + (size_t)g.nb * g.cols, b - first[d]);
+}
+__global__ __launch_bounds__(256) void k_sign_apply_group(const SignDesc* __restrict__ D,
+                                                          const int* __restrict__ first, int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const SignDesc g = D[d];
+  const long long na = (long long)g.rows * g.cols, nbe = g.B ? (long long)g.rowsB * g.cols : 0;
+  sign_apply_dev(na, g.cols, g.A, g.lda, nbe, g.B, g.ldb, g.part + (size_t)g.nb * g.cols,
+                 (long long)(b - first[d]) * 256 + threadIdx.x);
+}
+
+hipError_t sign_part_group_launch(hipStream_t s, const SignDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_sign_part_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
+}
+hipError_t sign_decide_group_launch(hipStream_t s, const SignDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_sign_decide_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
+}
+hipError_t sign_apply_group_launch(hipStream_t s, const SignDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_sign_apply_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
 }
 
 hipError_t sign_fix_tall(hipStream_t s, double* scratch, size_t scratch_elems, int rows, int cols,
@@ -1148,14 +1305,33 @@ hipError_t sign_fix_tall(hipStream_t s, double* scratch, size_t scratch_elems, i
 }
 
 // ------------------------------------------------------------- helpers
-__global__ void k_copy2d(int rows, int cols, const double* __restrict__ A, int lda,
-                         double* __restrict__ B, int ldb, const double* __restrict__ colscale) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void copy2d_dev(int rows, int cols, const double* __restrict__ A, int lda,
+                                           double* __restrict__ B, int ldb, const double* __restrict__ colscale,
+                                           long long e) {
   if (e >= (long long)rows * cols) return;
   const int r = (int)(e / cols), c = (int)(e % cols);
   double v = A[(long long)r * lda + c];
   if (colscale) v *= colscale[c];
   B[(long long)r * ldb + c] = v;
+}
+
+__global__ void k_copy2d(int rows, int cols, const double* __restrict__ A, int lda,
+                         double* __restrict__ B, int ldb, const double* __restrict__ colscale) {
+  copy2d_dev(rows, cols, A, lda, B, ldb, colscale, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_copy2d_group(const CopyDesc* __restrict__ D, const int* __restrict__ first,
+                                                      int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const CopyDesc g = D[d];
+  copy2d_dev(g.rows, g.cols, g.A, g.lda, g.B, g.ldb, g.colscale, (long long)(b - first[d]) * 256 + threadIdx.x);
+}
+
+hipError_t copy2d_group_launch(hipStream_t s, const CopyDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_copy2d_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
 }
 
 hipError_t copy2d(hipStream_t s, int rows, int cols, const double* A, int lda, double* B, int ldb,

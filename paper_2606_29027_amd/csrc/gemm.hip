@@ -16,6 +16,7 @@
 // bit for bit.
 #include "slar_internal.h"
 #include "dense.h"
+#include "group.h"
 
 namespace slar {
 
@@ -40,20 +41,15 @@ __device__ __forceinline__ void chunk_coords(int t, int j, int* outer, int* inne
   }
 }
 
+// the 64 x 64 output tile at (m0, n0) of one batch item (A, B, C already
+// offset to it)
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double alpha,
-                                                  const double* __restrict__ A, int lda, long long sA,
-                                                  const double* __restrict__ B, int ldb, long long sB,
-                                                  double beta, double* __restrict__ C, int ldc,
-                                                  long long sC) {
+__device__ __forceinline__ void gemm_tile(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                          int lda, const double* __restrict__ B, int ldb, double beta,
+                                          double* __restrict__ C, int ldc, int m0, int n0) {
   __shared__ double As[GB_K][GB_LDA];   // As[k][m] = op(A)[m0 + m][k0 + k]
   __shared__ double Bs[GB_K][GB_LDB];   // Bs[k][n] = op(B)[k0 + k][n0 + n]
   const int t = threadIdx.x;
-  const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
-  const long long bz = blockIdx.z;
-  A += bz * sA;
-  B += bz * sB;
-  C += bz * sC;
   // op(A)[m][k] is A[m * lda + k] (row-major M x K) or A[k * lda + m] (A^T)
   auto ldA = [&](int k0, double* r) {
 #pragma unroll
@@ -144,6 +140,33 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
       }
 }
 
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double alpha,
+                                                  const double* __restrict__ A, int lda, long long sA,
+                                                  const double* __restrict__ B, int ldb, long long sB,
+                                                  double beta, double* __restrict__ C, int ldc,
+                                                  long long sC) {
+  const long long bz = blockIdx.z;
+  gemm_tile<TA, TB>(M, N, K, alpha, A + bz * sA, lda, B + bz * sB, ldb, beta, C + bz * sC, ldc,
+                    blockIdx.y * GB_M, blockIdx.x * GB_N);
+}
+
+// problem d owns tm * tn * batch blocks: batch item, then tile row, then
+// tile column, as the one-problem grid (x: tile column, y: tile row, z: item)
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_f64_group(const GemmDesc* __restrict__ D,
+                                                        const int* __restrict__ first, int nd) {
+  const int b = blockIdx.x;
+  const int d = group_find(first, nd, b);
+  const GemmDesc g = D[d];
+  const int local = b - first[d];
+  const int per = g.tm * g.tn;
+  const int bz = local / per, rem = local - bz * per;
+  const int mt = rem / g.tn, nt = rem - mt * g.tn;
+  gemm_tile<TA, TB>(g.M, g.N, g.K, g.alpha, g.A + (long long)bz * g.sA, g.lda, g.B + (long long)bz * g.sB, g.ldb,
+                    g.beta, g.C + (long long)bz * g.sC, g.ldc, mt * GB_M, nt * GB_N);
+}
+
 }  // namespace
 
 hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
@@ -160,6 +183,16 @@ hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double
     k_gemm_f64<false, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else
     k_gemm_f64<true, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  return hipGetLastError();
+}
+
+hipError_t gemm_group_launch(hipStream_t s, bool ta, bool tb, const GemmDesc* d, const int* first, int nd,
+                             int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  if (!ta && !tb) k_gemm_f64_group<false, false><<<nblocks, 256, 0, s>>>(d, first, nd);
+  else if (ta && !tb) k_gemm_f64_group<true, false><<<nblocks, 256, 0, s>>>(d, first, nd);
+  else if (!ta && tb) k_gemm_f64_group<false, true><<<nblocks, 256, 0, s>>>(d, first, nd);
+  else k_gemm_f64_group<true, true><<<nblocks, 256, 0, s>>>(d, first, nd);
   return hipGetLastError();
 }
 

@@ -9,9 +9,12 @@
 //    two GEMMs per node.
 //  * k_frame_points: eq. (tp_interp) from the node frames (frame_sampler.h)
 //    for an explicit list of grid points.
+#include <vector>
+
 #include "slar_internal.h"
 #include "dense.h"
 #include "frame_sampler.h"
+#include "group.h"
 
 namespace slar {
 
@@ -343,6 +346,51 @@ hipError_t frames_from_ht(hipStream_t s, Workspace* ws, const GridDev& G, const 
                0.0, out->P, ld, 0, 1);
   out->r = r12;
   return e;
+}
+
+// The same for n tensors at once, as grouped launches appended to q (one
+// per step of the one-tensor call, so each frame is bit-identical to it);
+// out[j]->r is set on return.
+hipError_t frames_from_ht_group(GroupQueue& q, int n, Workspace* const* ws, const slar_ht* const* F,
+                                slar_frames* const* out) {
+  std::vector<GemmArgs> g1, g2, g3, g4, g5;
+  std::vector<CopyDesc> cp;
+  for (int j = 0; j < n; ++j) {
+    const GridDev& G = ws[j]->G;
+    const slar_ht& H = *F[j];
+    slar_frames& o = *out[j];
+    const int ld = o.ld;
+    if (H.d == 2) {
+      const int rx = H.rank[0], rv = H.rank[1];
+      cp.push_back(CopyDesc{G.n[0], rx, rx, ld, (const double*)H.leaf[0], o.X, nullptr});
+      g5.push_back(GemmArgs{G.n[1], rx, rv, 1.0, (const double*)H.leaf[1], rv, 0, (const double*)H.root, rv, 0,
+                            0.0, o.P, ld, 0, 1});
+      o.r = rx;
+      continue;
+    }
+    const int r1 = H.rank[0], r2 = H.rank[1], r3 = H.rank[2], r4 = H.rank[3];
+    const int r12 = H.rank[4], r34 = H.rank[5];
+    const int n1 = G.n[0], n2 = G.n[1], n3 = G.n[2], n4 = G.n[3];
+    double* Z = ws[j]->dwork;
+    double* V = ws[j]->dwork + (size_t)SLAR_NMAX * SLAR_KMAX * SLAR_KMAX;
+    g1.push_back(GemmArgs{n1, r2 * r12, r1, 1.0, (const double*)H.leaf[0], r1, 0, (const double*)H.B12, r2 * r12, 0,
+                          0.0, Z, r2 * r12, 0, 1});
+    g2.push_back(GemmArgs{n2, r12, r2, 1.0, (const double*)H.leaf[1], r2, 0, Z, r12, (long long)r2 * r12, 0.0, o.X,
+                          ld, (long long)n2 * ld, n1});
+    g3.push_back(GemmArgs{n3, r4 * r34, r3, 1.0, (const double*)H.leaf[2], r3, 0, (const double*)H.B34, r4 * r34, 0,
+                          0.0, Z, r4 * r34, 0, 1});
+    g4.push_back(GemmArgs{n4, r34, r4, 1.0, (const double*)H.leaf[3], r4, 0, Z, r34, (long long)r4 * r34, 0.0, V,
+                          r34, (long long)n4 * r34, n3});
+    g5.push_back(GemmArgs{n3 * n4, r12, r34, 1.0, V, r34, 0, (const double*)H.root, r34, 0, 0.0, o.P, ld, 0, 1});
+    o.r = r12;
+  }
+  // the scratch Z serves the x side, then the v side (as the one-tensor call)
+  HIP_CHK(q.copy2d(cp));
+  HIP_CHK(q.gemm(false, false, g1));
+  HIP_CHK(q.gemm(false, false, g2));
+  HIP_CHK(q.gemm(false, false, g3));
+  HIP_CHK(q.gemm(false, false, g4));
+  return q.gemm(false, true, g5);
 }
 
 // ------------------------------------------------ table copies (padded)

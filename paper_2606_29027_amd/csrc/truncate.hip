@@ -28,6 +28,7 @@
 
 #include "slar_internal.h"
 #include "dense.h"
+#include "group.h"
 #include "truncate.h"
 
 namespace slar {
@@ -331,68 +332,81 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
 }
 
 // ------------------------------------------------------------ grouped form
-// The steps of truncate_run, phase by phase over a group of jobs: the
-// per-job products (Grams, GEMMs, sign rules) are enqueued through `each`;
-// the single-block factorisations of all jobs run as one launch per phase
-// (descriptors copied from pinned host memory, one region per phase); the
-// singular values and eigenvalues of all jobs come back in one copy each.
+// The steps of truncate_run, phase by phase over a group of jobs, every
+// step one grouped launch for all jobs (group.h): the products, Grams,
+// sign rules and copies run the one-problem bodies per job, and the
+// single-block factorisations (Cholesky, core SVD, Gram eigenpairs, basis
+// completion) one block per job.  The host takes the rank decisions of all
+// jobs after one gathered read of the singular values, then of the
+// eigenvalues.
 namespace {
 struct GroupLayout {
-  size_t chol1, chol2, svd, eig1, eig2, basis, sv, lam, total;
+  size_t queue, sv, lam, total;
 };
 GroupLayout group_layout(int n) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   GroupLayout L{};
-  size_t o = 0;
-  L.chol1 = o; o += al(sizeof(CholDesc) * 2 * n);
-  L.chol2 = o; o += al(sizeof(CholDesc) * 2 * n);
-  L.svd = o; o += al(sizeof(SvdDesc) * n);
-  L.eig1 = o; o += al(sizeof(EigDesc) * 4 * n);
-  L.eig2 = o; o += al(sizeof(EigDesc) * 4 * n);
-  L.basis = o; o += al(sizeof(BasisDesc) * 4 * n);
-  L.sv = o; o += al(sizeof(double) * SLAR_CROSS_KMAX * n);
-  L.lam = o; o += al(sizeof(double) * 4 * SLAR_NMAX * n);
-  L.total = o;
+  L.queue = al((size_t)256 * 1024 + (size_t)n * 32 * 1024);   // descriptors of one call
+  L.sv = L.queue;
+  L.lam = L.sv + al(sizeof(double) * SLAR_CROSS_KMAX * n);
+  L.total = L.lam + al(sizeof(double) * 4 * SLAR_NMAX * n);
   return L;
 }
 
-// descriptors of two size classes, small ones first, copied to the device
-template <class D>
-hipError_t upload(hipStream_t s, char* dmem, char* hmem, size_t off, const std::vector<D>& a,
-                  const std::vector<D>& b) {
-  const size_t n = a.size() + b.size();
-  if (n == 0) return hipSuccess;
-  D* h = (D*)(hmem + off);
-  std::copy(a.begin(), a.end(), h);
-  std::copy(b.begin(), b.end(), h + a.size());
-  return hipMemcpyAsync(dmem + off, hmem + off, sizeof(D) * n, hipMemcpyHostToDevice, s);
+// factorisation descriptors of two size classes (small ones first), staged
+// in q and launched with `launch(stream, device descriptors, small, big)`
+template <class D, class F>
+hipError_t stage_group(GroupQueue& q, const std::vector<D>& sm, const std::vector<D>& bg, F launch) {
+  if (sm.empty() && bg.empty()) return hipSuccess;
+  std::vector<D> all(sm);
+  all.insert(all.end(), bg.begin(), bg.end());
+  const D* d = (const D*)q.stage(all.data(), sizeof(D) * all.size());
+  if (!d) return hipErrorOutOfMemory;
+  const int ns = (int)sm.size(), nb = (int)bg.size();
+  q.then([=](hipStream_t s) { return launch(s, d, ns, nb); });
+  return hipSuccess;
 }
 }  // namespace
 
 size_t truncate_group_bytes(int count) { return group_layout(std::max(count, 1)).total; }
 
-slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double tol, int rmax,
-                           const TruncEach& each, void* dmem, void* hmem) {
+slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double tol, int rmax, void* dmem,
+                           void* hmem) {
   const int n = (int)jobs.size();
   if (n == 0) return SLAR_OK;
   const GroupLayout GL = group_layout(n);
   char* D = (char*)dmem;
   char* H = (char*)hmem;
+  GroupQueue q(dmem, hmem, GL.queue);
   const size_t CK = SLAR_CROSS_KMAX;
   std::vector<Tbuf> tb(n);
   for (int j = 0; j < n; ++j) tb[j] = carve(jobs[j].ws);
   auto live = [&](int j) { return jobs[j].st == SLAR_OK; };
-  auto fail = [&](int j, slar_status e) {
-    if (jobs[j].st == SLAR_OK) jobs[j].st = e;
-  };
   auto Rv_of = [&](int j) { return tb[j].R + CK * CK; };
-  slar_status e;
+  // a failure of a grouped launch fails every job of the call
+  auto fatal = [&](hipError_t e) {
+    if (e == hipSuccess) return false;
+    for (TruncJob& J : jobs)
+      if (J.st == SLAR_OK) J.st = SLAR_E_HIP;
+    return true;
+  };
+  using GA = GroupQueue::GramArgs;
 
-  // Cholesky-QR2 of both factor sets; pass 2 takes R1 of pass 1 as Rprev
-  auto chol_phase = [&](size_t off, bool second) -> slar_status {
+  // ---- A: Cholesky-QR2 of both factor sets, core M = Ru Rv^T, core SVD
+  {
+    std::vector<GA> gr;
+    for (int j = 0; j < n; ++j) {
+      const GridDev& G = jobs[j].ws->G;
+      const Tbuf& b = tb[j];
+      const int k = jobs[j].in.k;
+      gr.push_back(GA{k, G.nx, 0, jobs[j].in.U, G.nx, 0, 0, b.cu.part.p, b.cu.part.cap, b.cu.G});
+      gr.push_back(GA{k, G.nv, 0, jobs[j].in.V, G.nv, 0, 0, b.cv.part.p, b.cv.part.cap, b.cv.G});
+    }
+    if (fatal(q.gram(gr))) return SLAR_E_HIP;
+  }
+  auto chol = [&](bool second) -> hipError_t {
     std::vector<CholDesc> sm, bg;
     for (int j = 0; j < n; ++j) {
-      if (!live(j)) continue;
       const Tbuf& b = tb[j];
       const int k = jobs[j].in.k;
       auto& v = (k <= SLAR_KMAX) ? sm : bg;
@@ -404,76 +418,54 @@ slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double to
         v.push_back(CholDesc{k, b.cv.G, b.cv.Linv, b.cv.R1, nullptr});
       }
     }
-    if (upload(s, D, H, off, sm, bg) != hipSuccess) return SLAR_E_HIP;
-    if (chol_inv_group(s, (int)sm.size(), (const CholDesc*)(D + off), false) != hipSuccess) return SLAR_E_HIP;
-    if (chol_inv_group(s, (int)bg.size(), (const CholDesc*)(D + off) + sm.size(), true) != hipSuccess)
-      return SLAR_E_HIP;
-    return SLAR_OK;
+    return stage_group(q, sm, bg, [](hipStream_t st, const CholDesc* d, int ns, int nb) {
+      hipError_t e = chol_inv_group(st, ns, d, false);
+      return e == hipSuccess ? chol_inv_group(st, nb, d + ns, true) : e;
+    });
   };
-
-  // A1: Grams of U and V
-  if ((e = each([&](int j, hipStream_t st) {
-         if (!live(j)) return;
-         const GridDev& G = jobs[j].ws->G;
-         const Tbuf& b = tb[j];
-         const int k = jobs[j].in.k;
-         if (gram_rows(st, b.cu.part, k, G.nx, jobs[j].in.U, G.nx, b.cu.G) != hipSuccess ||
-             gram_rows(st, b.cv.part, k, G.nv, jobs[j].in.V, G.nv, b.cv.G) != hipSuccess)
-           fail(j, SLAR_E_HIP);
-       })) != SLAR_OK)
-    return e;
-  if ((e = chol_phase(GL.chol1, false)) != SLAR_OK) return e;
-  // A2: first orthogonalisation and the Grams of its result
-  if ((e = each([&](int j, hipStream_t st) {
-         if (!live(j)) return;
-         const GridDev& G = jobs[j].ws->G;
-         const Tbuf& b = tb[j];
-         const int k = jobs[j].in.k;
-         if (gemm_f64(st, false, false, k, G.nx, k, 1.0, b.cu.Linv, k, 0, jobs[j].in.U, G.nx, 0, 0.0, b.Q1u,
-                      G.nx, 0, 1) != hipSuccess ||
-             gram_rows(st, b.cu.part, k, G.nx, b.Q1u, G.nx, b.cu.G) != hipSuccess ||
-             gemm_f64(st, false, false, k, G.nv, k, 1.0, b.cv.Linv, k, 0, jobs[j].in.V, G.nv, 0, 0.0, b.Q1v,
-                      G.nv, 0, 1) != hipSuccess ||
-             gram_rows(st, b.cv.part, k, G.nv, b.Q1v, G.nv, b.cv.G) != hipSuccess)
-           fail(j, SLAR_E_HIP);
-       })) != SLAR_OK)
-    return e;
-  if ((e = chol_phase(GL.chol2, true)) != SLAR_OK) return e;
-  // A3: second orthogonalisation, core M = Ru Rv^T
-  if ((e = each([&](int j, hipStream_t st) {
-         if (!live(j)) return;
-         const GridDev& G = jobs[j].ws->G;
-         const Tbuf& b = tb[j];
-         const int k = jobs[j].in.k;
-         if (gemm_f64(st, false, false, k, G.nx, k, 1.0, b.cu.Linv, k, 0, b.Q1u, G.nx, 0, 0.0, b.Qu, G.nx, 0,
-                      1) != hipSuccess ||
-             gemm_f64(st, false, false, k, G.nv, k, 1.0, b.cv.Linv, k, 0, b.Q1v, G.nv, 0, 0.0, b.Qv, G.nv, 0,
-                      1) != hipSuccess ||
-             gemm_f64(st, false, true, k, k, k, 1.0, b.R, k, 0, Rv_of(j), k, 0, 0.0, b.M, k, 0, 1) != hipSuccess)
-           fail(j, SLAR_E_HIP);
-       })) != SLAR_OK)
-    return e;
-  // A4: core SVDs, singular values gathered for the host
+  if (fatal(chol(false))) return SLAR_E_HIP;
   {
+    std::vector<GemmArgs> g;
+    std::vector<GA> gr;
+    for (int j = 0; j < n; ++j) {
+      const GridDev& G = jobs[j].ws->G;
+      const Tbuf& b = tb[j];
+      const int k = jobs[j].in.k;
+      g.push_back(GemmArgs{k, G.nx, k, 1.0, b.cu.Linv, k, 0, jobs[j].in.U, G.nx, 0, 0.0, b.Q1u, G.nx, 0, 1});
+      g.push_back(GemmArgs{k, G.nv, k, 1.0, b.cv.Linv, k, 0, jobs[j].in.V, G.nv, 0, 0.0, b.Q1v, G.nv, 0, 1});
+      gr.push_back(GA{k, G.nx, 0, b.Q1u, G.nx, 0, 0, b.cu.part.p, b.cu.part.cap, b.cu.G});
+      gr.push_back(GA{k, G.nv, 0, b.Q1v, G.nv, 0, 0, b.cv.part.p, b.cv.part.cap, b.cv.G});
+    }
+    if (fatal(q.gemm(false, false, g)) || fatal(q.gram(gr))) return SLAR_E_HIP;
+  }
+  if (fatal(chol(true))) return SLAR_E_HIP;
+  {
+    std::vector<GemmArgs> g, gm;
     std::vector<SvdDesc> sm, bg;
     double* svs = (double*)(D + GL.sv);
     for (int j = 0; j < n; ++j) {
-      if (!live(j)) continue;
+      const GridDev& G = jobs[j].ws->G;
       const Tbuf& b = tb[j];
       const int k = jobs[j].in.k;
+      g.push_back(GemmArgs{k, G.nx, k, 1.0, b.cu.Linv, k, 0, b.Q1u, G.nx, 0, 0.0, b.Qu, G.nx, 0, 1});
+      g.push_back(GemmArgs{k, G.nv, k, 1.0, b.cv.Linv, k, 0, b.Q1v, G.nv, 0, 0.0, b.Qv, G.nv, 0, 1});
+      gm.push_back(GemmArgs{k, k, k, 1.0, b.R, k, 0, Rv_of(j), k, 0, 0.0, b.M, k, 0, 1});
       if (k > 64) bg.push_back(SvdDesc{k, b.M, b.W, b.sv, nullptr, svs + (size_t)j * CK});
       else sm.push_back(SvdDesc{k, b.M, b.W, b.sv, b.Z, svs + (size_t)j * CK});
     }
-    if (upload(s, D, H, GL.svd, sm, bg) != hipSuccess) return SLAR_E_HIP;
-    if (svd_group(s, (int)sm.size(), (const SvdDesc*)(D + GL.svd), false) != hipSuccess) return SLAR_E_HIP;
-    if (svd_group(s, (int)bg.size(), (const SvdDesc*)(D + GL.svd) + sm.size(), true) != hipSuccess)
+    if (fatal(q.gemm(false, false, g)) || fatal(q.gemm(false, true, gm))) return SLAR_E_HIP;
+    if (fatal(stage_group(q, sm, bg, [](hipStream_t st, const SvdDesc* d, int ns, int nb) {
+          hipError_t e = svd_group(st, ns, d, false);
+          return e == hipSuccess ? svd_group(st, nb, d + ns, true) : e;
+        })))
       return SLAR_E_HIP;
+    if (fatal(q.flush(s))) return SLAR_E_HIP;
     HIP_TRY(hipMemcpyAsync(H + GL.sv, D + GL.sv, sizeof(double) * CK * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    q.reset();
   }
   // root ranks (the rule of truncate_run)
   for (int j = 0; j < n; ++j) {
-    if (!live(j)) continue;
     TruncJob& J = jobs[j];
     const int k = J.in.k;
     const double* sv = (const double*)(H + GL.sv) + (size_t)j * CK;
@@ -483,7 +475,7 @@ slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double to
       if (!std::isfinite(sv[i])) finite = false;
       norm2 += sv[i] * sv[i];
     }
-    if (!finite) { fail(j, SLAR_E_NUMERIC); continue; }
+    if (!finite) { J.st = SLAR_E_NUMERIC; continue; }
     const int d = J.ws->G.d;
     J.theta = tol * std::sqrt(norm2) / std::sqrt((double)std::max(2 * d - 3, 1));
     std::vector<double> s2(k);
@@ -493,48 +485,60 @@ slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double to
     for (int i = J.r; i < k; ++i) tail += s2[i];
     J.capped = J.r == rmax && std::sqrt(tail) > J.theta;
   }
-  // B1: kept right vectors (k > 64), frames, sign rule, root; d = 2 ends
-  // here, d = 4 forms the mode Grams
-  if ((e = each([&](int j, hipStream_t st) {
-         if (!live(j)) return;
-         TruncJob& J = jobs[j];
-         Workspace* ws = J.ws;
-         const GridDev& G = ws->G;
-         const Tbuf& b = tb[j];
-         const int k = J.in.k, r = J.r;
-         bool ok = true;
-         if (k > 64) {
-           ok = ok && gemm_f64(st, true, false, k, r, k, 1.0, b.M, k, 0, b.W, k, 0, 0.0, b.Z, k, 0, 1) == hipSuccess;
-           ok = ok && scale_cols_inv(st, k, r, b.Z, k, b.sv) == hipSuccess;
-         }
-         ok = ok && gemm_f64(st, true, false, G.nx, r, k, 1.0, b.Qu, G.nx, 0, b.W, k, 0, 0.0, b.X, r, 0, 1) ==
-                        hipSuccess;
-         ok = ok && gemm_f64(st, true, false, G.nv, r, k, 1.0, b.Qv, G.nv, 0, b.Z, k, 0, 0.0, b.Y, r, 0, 1) ==
-                        hipSuccess;
-         ok = ok && sign_fix_tall(st, ws->dwork, ws->dwork_elems, G.nx, r, b.X, r, b.Y, r, G.nv) == hipSuccess;
-         if (ok) k_diag<<<(r * r + 255) / 256, 256, 0, st>>>(r, b.sv, (double*)J.out->root);
-         if (G.d == 2) {
-           ok = ok && copy2d(st, G.nx, r, b.X, r, (double*)J.out->leaf[0], r, nullptr) == hipSuccess;
-           ok = ok && copy2d(st, G.nv, r, b.Y, r, (double*)J.out->leaf[1], r, nullptr) == hipSuccess;
-           J.out->rank[0] = r; J.out->rank[1] = r;
-           for (int m = 2; m < 6; ++m) J.out->rank[m] = 0;
-         } else {
-           ok = ok && side_grams(st, b.cu.part, b.X, G.n[0], G.n[1], r, b.sv, b.Xs, b.G1, b.G2) == hipSuccess;
-           ok = ok && side_grams(st, b.cv.part, b.Y, G.n[2], G.n[3], r, b.sv, b.Ys, b.G3, b.G4) == hipSuccess;
-         }
-         if (!ok || hipGetLastError() != hipSuccess) fail(j, SLAR_E_HIP);
-       })) != SLAR_OK)
-    return e;
-  // B2: Gram eigenpairs of every d = 4 job; with the refinement pass, basis
-  // completion, refined Grams, their eigenpairs and E V
+
+  // ---- B: kept right vectors (k > 64), frames, sign rule, root; d = 2
+  // leaves; d = 4 mode Grams, eigenpairs (and the refinement pass)
   auto four = [&](int j) { return live(j) && jobs[j].ws->G.d == 4; };
   auto refine = [&](int j) { return four(j) && jobs[j].ws->leaf_refine; };
   double* lst = (double*)(D + GL.lam);
   auto lam_slot = [&](int j, int m) { return lst + ((size_t)j * 4 + m) * SLAR_NMAX; };
-  bool any4 = false, anyref = false;
-  for (int j = 0; j < n; ++j) { any4 = any4 || four(j); anyref = anyref || refine(j); }
+  {
+    std::vector<GemmArgs> gz, gxy;
+    std::vector<ScaleDesc> sz, droot;
+    std::vector<GroupQueue::SignArgs> sg;
+    std::vector<CopyDesc> cp;
+    std::vector<GA> g1, g2;
+    for (int j = 0; j < n; ++j) {
+      if (!live(j)) continue;
+      TruncJob& J = jobs[j];
+      Workspace* ws = J.ws;
+      const GridDev& G = ws->G;
+      const Tbuf& b = tb[j];
+      const int k = J.in.k, r = J.r;
+      if (k > 64) {
+        gz.push_back(GemmArgs{k, r, k, 1.0, b.M, k, 0, b.W, k, 0, 0.0, b.Z, k, 0, 1});
+        sz.push_back(ScaleDesc{k, r, k, 0, b.Z, b.sv});
+      }
+      gxy.push_back(GemmArgs{G.nx, r, k, 1.0, b.Qu, G.nx, 0, b.W, k, 0, 0.0, b.X, r, 0, 1});
+      gxy.push_back(GemmArgs{G.nv, r, k, 1.0, b.Qv, G.nv, 0, b.Z, k, 0, 0.0, b.Y, r, 0, 1});
+      sg.push_back(GroupQueue::SignArgs{G.nx, r, b.X, r, b.Y, r, G.nv, ws->dwork, ws->dwork_elems});
+      droot.push_back(ScaleDesc{0, r, 0, 1, (double*)J.out->root, b.sv});
+      if (G.d == 2) {
+        cp.push_back(CopyDesc{G.nx, r, r, r, b.X, (double*)J.out->leaf[0], nullptr});
+        cp.push_back(CopyDesc{G.nv, r, r, r, b.Y, (double*)J.out->leaf[1], nullptr});
+        J.out->rank[0] = r; J.out->rank[1] = r;
+        for (int m = 2; m < 6; ++m) J.out->rank[m] = 0;
+      } else {
+        // side_grams of both sides: frame * diag(s), mode-1 and mode-2 Grams
+        // (the mode-2 Gram reuses the side's partial-sum scratch: next launch)
+        cp.push_back(CopyDesc{G.n[0] * G.n[1], r, r, r, b.X, b.Xs, b.sv});
+        cp.push_back(CopyDesc{G.n[2] * G.n[3], r, r, r, b.Y, b.Ys, b.sv});
+        g1.push_back(GA{G.n[0], G.n[1] * r, 0, b.Xs, G.n[1] * r, 0, 0, b.cu.part.p, b.cu.part.cap, b.G1});
+        g1.push_back(GA{G.n[2], G.n[3] * r, 0, b.Ys, G.n[3] * r, 0, 0, b.cv.part.p, b.cv.part.cap, b.G3});
+        g2.push_back(GA{G.n[1], G.n[0] * r, 1, b.Xs, 0, G.n[1], r, b.cu.part.p, b.cu.part.cap, b.G2});
+        g2.push_back(GA{G.n[3], G.n[2] * r, 1, b.Ys, 0, G.n[3], r, b.cv.part.p, b.cv.part.cap, b.G4});
+      }
+    }
+    if (fatal(q.gemm(true, false, gz)) || fatal(q.scale(sz)) || fatal(q.gemm(true, false, gxy)) ||
+        fatal(q.sign_fix_tall(sg)) || fatal(q.scale(droot)) || fatal(q.copy2d(cp)) || fatal(q.gram(g1)) ||
+        fatal(q.gram(g2)))
+      return SLAR_E_HIP;
+  }
+  bool any4 = false;
+  for (int j = 0; j < n; ++j) any4 = any4 || four(j);
   if (any4) {
     std::vector<EigDesc> ed, none;
+    std::vector<BasisDesc> bd, noneb;
     for (int j = 0; j < n; ++j) {
       if (!four(j)) continue;
       const Tbuf& b = tb[j];
@@ -542,70 +546,68 @@ slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double to
       const double* Gm[4] = {b.G1, b.G2, b.G3, b.G4};
       double* lm[4] = {b.lam1, b.lam2, b.lam3, b.lam4};
       double* Em[4] = {b.E1, b.E2, b.E3, b.E4};
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m) {
         ed.push_back(EigDesc{G.n[m], Gm[m], lm[m], Em[m], refine(j) ? nullptr : lam_slot(j, m)});
+        if (refine(j)) bd.push_back(BasisDesc{G.n[m], Em[m]});
+      }
     }
-    if (upload(s, D, H, GL.eig1, ed, none) != hipSuccess) return SLAR_E_HIP;
-    if (eig_sym_group(s, (int)ed.size(), (const EigDesc*)(D + GL.eig1)) != hipSuccess) return SLAR_E_HIP;
-  }
-  if (anyref) {
-    std::vector<BasisDesc> bd, none;
-    for (int j = 0; j < n; ++j) {
-      if (!refine(j)) continue;
-      const Tbuf& b = tb[j];
-      const GridDev& G = jobs[j].ws->G;
-      double* Em[4] = {b.E1, b.E2, b.E3, b.E4};
-      for (int m = 0; m < 4; ++m) bd.push_back(BasisDesc{G.n[m], Em[m]});
-    }
-    if (upload(s, D, H, GL.basis, bd, none) != hipSuccess) return SLAR_E_HIP;
-    if (complete_basis_group(s, (int)bd.size(), (const BasisDesc*)(D + GL.basis)) != hipSuccess)
+    if (fatal(stage_group(q, ed, none, [](hipStream_t st, const EigDesc* d, int ns, int) {
+          return eig_sym_group(st, ns, d);
+        })))
       return SLAR_E_HIP;
-    if ((e = each([&](int j, hipStream_t st) {
-           if (!refine(j)) return;
-           const GridDev& G = jobs[j].ws->G;
-           const Tbuf& b = tb[j];
-           const int r = jobs[j].r;
-           if (side_refine_grams(st, b.cu.part, b.Xs, G.n[0], G.n[1], r, b.E1, b.E2, G.n[0], G.n[1], b.T, b.G1,
-                                 b.G2) != hipSuccess ||
-               side_refine_grams(st, b.cv.part, b.Ys, G.n[2], G.n[3], r, b.E3, b.E4, G.n[2], G.n[3], b.T2, b.G3,
-                                 b.G4) != hipSuccess)
-             fail(j, SLAR_E_HIP);
-         })) != SLAR_OK)
-      return e;
-    std::vector<EigDesc> ed, nonee;
-    for (int j = 0; j < n; ++j) {
-      if (!refine(j)) continue;
-      const Tbuf& b = tb[j];
-      const GridDev& G = jobs[j].ws->G;
-      const double* Gm[4] = {b.G1, b.G2, b.G3, b.G4};
-      double* lm[4] = {b.lam1, b.lam2, b.lam3, b.lam4};
-      for (int m = 0; m < 4; ++m)
-        ed.push_back(EigDesc{G.n[m], Gm[m], lm[m], b.Vw + (size_t)m * SLAR_NMAX * SLAR_NMAX, lam_slot(j, m)});
+    if (!bd.empty()) {
+      // refinement: completed bases, Grams of the rotated matricisations,
+      // their eigenpairs, leaf candidates E V (side_refine_grams)
+      if (fatal(stage_group(q, bd, noneb, [](hipStream_t st, const BasisDesc* d, int ns, int) {
+            return complete_basis_group(st, ns, d);
+          })))
+        return SLAR_E_HIP;
+      std::vector<GemmArgs> ga, gb, gev;
+      std::vector<GA> r1, r2;
+      std::vector<EigDesc> ed2;
+      for (int j = 0; j < n; ++j) {
+        if (!refine(j)) continue;
+        const Tbuf& b = tb[j];
+        const GridDev& G = jobs[j].ws->G;
+        const int r = jobs[j].r;
+        const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2], n3 = G.n[3];
+        ga.push_back(GemmArgs{n0, n1 * r, n0, 1.0, b.E1, n0, 0, b.Xs, n1 * r, 0, 0.0, b.T, n1 * r, 0, 1});
+        ga.push_back(GemmArgs{n2, n3 * r, n2, 1.0, b.E3, n2, 0, b.Ys, n3 * r, 0, 0.0, b.T2, n3 * r, 0, 1});
+        r1.push_back(GA{n0, n1 * r, 0, b.T, n1 * r, 0, 0, b.cu.part.p, b.cu.part.cap, b.G1});
+        r1.push_back(GA{n2, n3 * r, 0, b.T2, n3 * r, 0, 0, b.cv.part.p, b.cv.part.cap, b.G3});
+        gb.push_back(GemmArgs{n1, r, n1, 1.0, b.E2, n1, 0, b.Xs, r, (long long)n1 * r, 0.0, b.T, r,
+                              (long long)n1 * r, n0});
+        gb.push_back(GemmArgs{n3, r, n3, 1.0, b.E4, n3, 0, b.Ys, r, (long long)n3 * r, 0.0, b.T2, r,
+                              (long long)n3 * r, n2});
+        r2.push_back(GA{n1, n0 * r, 1, b.T, 0, n1, r, b.cu.part.p, b.cu.part.cap, b.G2});
+        r2.push_back(GA{n3, n2 * r, 1, b.T2, 0, n3, r, b.cv.part.p, b.cv.part.cap, b.G4});
+        const double* Gm[4] = {b.G1, b.G2, b.G3, b.G4};
+        double* lm[4] = {b.lam1, b.lam2, b.lam3, b.lam4};
+        double* Em[4] = {b.E1, b.E2, b.E3, b.E4};
+        double* Gw[4] = {b.G1, b.G2, b.G3, b.G4};
+        for (int m = 0; m < 4; ++m) {
+          double* Vm = b.Vw + (size_t)m * SLAR_NMAX * SLAR_NMAX;
+          const int nm = G.n[m], c2 = std::min(nm, EIG_COLS);
+          ed2.push_back(EigDesc{nm, Gm[m], lm[m], Vm, lam_slot(j, m)});
+          gev.push_back(GemmArgs{nm, c2, nm, 1.0, Em[m], nm, 0, Vm, nm, 0, 0.0, Gw[m], c2, 0, 1});
+        }
+      }
+      if (fatal(q.gemm(true, false, ga)) || fatal(q.gram(r1)) || fatal(q.gemm(true, false, gb)) ||
+          fatal(q.gram(r2)))
+        return SLAR_E_HIP;
+      if (fatal(stage_group(q, ed2, none, [](hipStream_t st, const EigDesc* d, int ns, int) {
+            return eig_sym_group(st, ns, d);
+          })))
+        return SLAR_E_HIP;
+      if (fatal(q.gemm(false, false, gev))) return SLAR_E_HIP;
     }
-    if (upload(s, D, H, GL.eig2, ed, nonee) != hipSuccess) return SLAR_E_HIP;
-    if (eig_sym_group(s, (int)ed.size(), (const EigDesc*)(D + GL.eig2)) != hipSuccess) return SLAR_E_HIP;
-    if ((e = each([&](int j, hipStream_t st) {
-           if (!refine(j)) return;
-           const GridDev& G = jobs[j].ws->G;
-           const Tbuf& b = tb[j];
-           double* Em[4] = {b.E1, b.E2, b.E3, b.E4};
-           double* Gw[4] = {b.G1, b.G2, b.G3, b.G4};
-           for (int m = 0; m < 4; ++m) {
-             const int nm = G.n[m], c2 = std::min(nm, EIG_COLS);
-             if (gemm_f64(st, false, false, nm, c2, nm, 1.0, Em[m], nm, 0, b.Vw + (size_t)m * SLAR_NMAX * SLAR_NMAX,
-                          nm, 0, 0.0, Gw[m], c2, 0, 1) != hipSuccess) {
-               fail(j, SLAR_E_HIP);
-               return;
-             }
-           }
-         })) != SLAR_OK)
-      return e;
   }
+  if (fatal(q.flush(s))) return SLAR_E_HIP;
+  std::vector<std::array<int, 4>> rk(n);
   if (any4) {
     HIP_TRY(hipMemcpyAsync(H + GL.lam, D + GL.lam, sizeof(double) * 4 * SLAR_NMAX * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    // C: leaf ranks, leaf bases and transfer tensors
-    std::vector<std::array<int, 4>> rk(n);
+    q.reset();
     for (int j = 0; j < n; ++j) {
       if (!four(j)) continue;
       const GridDev& G = jobs[j].ws->G;
@@ -613,31 +615,46 @@ slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double to
       for (int m = 0; m < 4 && live(j); ++m) {
         std::vector<double> l(lh + m * SLAR_NMAX, lh + m * SLAR_NMAX + G.n[m]);
         for (double v : l)
-          if (!std::isfinite(v)) fail(j, SLAR_E_NUMERIC);
+          if (!std::isfinite(v)) jobs[j].st = SLAR_E_NUMERIC;
         if (live(j)) rk[j][m] = leaf_rank(l, jobs[j].theta, rmax, &jobs[j].capped);
       }
     }
-    if ((e = each([&](int j, hipStream_t st) {
-           if (!four(j)) return;
-           TruncJob& J = jobs[j];
-           const GridDev& G = J.ws->G;
-           const Tbuf& b = tb[j];
-           const int r = J.r;
-           const bool rf = J.ws->leaf_refine;
-           const double* Ub[4] = {rf ? b.G1 : b.E1, rf ? b.G2 : b.E2, rf ? b.G3 : b.E3, rf ? b.G4 : b.E4};
-           int ldu[4];
-           for (int m = 0; m < 4; ++m) ldu[m] = rf ? std::min(G.n[m], EIG_COLS) : G.n[m];
-           const int* R = rk[j].data();
-           slar_status q = side_finish(st, b.T, b.X, G.n[0], G.n[1], r, Ub[0], ldu[0], Ub[1], ldu[1], R[0], R[1],
-                                       (double*)J.out->leaf[0], (double*)J.out->leaf[1], (double*)J.out->B12);
-           if (q == SLAR_OK)
-             q = side_finish(st, b.T2, b.Y, G.n[2], G.n[3], r, Ub[2], ldu[2], Ub[3], ldu[3], R[2], R[3],
-                             (double*)J.out->leaf[2], (double*)J.out->leaf[3], (double*)J.out->B34);
-           if (q != SLAR_OK) { fail(j, q); return; }
-           for (int m = 0; m < 4; ++m) J.out->rank[m] = R[m];
-           J.out->rank[4] = r; J.out->rank[5] = r;
-         })) != SLAR_OK)
-      return e;
+    // ---- C: leaf bases (sign rule) and transfer tensors (side_finish)
+    std::vector<CopyDesc> cp;
+    std::vector<GroupQueue::SignArgs> sg;
+    std::vector<GemmArgs> gt, gbt;
+    for (int j = 0; j < n; ++j) {
+      if (!four(j)) continue;
+      TruncJob& J = jobs[j];
+      const GridDev& G = J.ws->G;
+      const Tbuf& b = tb[j];
+      const int r = J.r;
+      const bool rf = J.ws->leaf_refine;
+      const double* Ub[4] = {rf ? b.G1 : b.E1, rf ? b.G2 : b.E2, rf ? b.G3 : b.E3, rf ? b.G4 : b.E4};
+      const int* R = rk[j].data();
+      double* leaf[4] = {(double*)J.out->leaf[0], (double*)J.out->leaf[1], (double*)J.out->leaf[2],
+                         (double*)J.out->leaf[3]};
+      for (int m = 0; m < 4; ++m) {
+        const int ldu = rf ? std::min(G.n[m], EIG_COLS) : G.n[m];
+        cp.push_back(CopyDesc{G.n[m], R[m], ldu, R[m], Ub[m], leaf[m], nullptr});
+        sg.push_back(GroupQueue::SignArgs{G.n[m], R[m], leaf[m], R[m], nullptr, 0, 0, nullptr, 0});
+      }
+      const double* frame[2] = {b.X, b.Y};
+      double* T[2] = {b.T, b.T2};
+      double* Bt[2] = {(double*)J.out->B12, (double*)J.out->B34};
+      for (int sd = 0; sd < 2; ++sd) {
+        const int na = G.n[2 * sd], nb = G.n[2 * sd + 1], ra = R[2 * sd], rb = R[2 * sd + 1];
+        gt.push_back(GemmArgs{ra, nb * r, na, 1.0, leaf[2 * sd], ra, 0, frame[sd], nb * r, 0, 0.0, T[sd], nb * r,
+                              0, 1});
+        gbt.push_back(GemmArgs{rb, r, nb, 1.0, leaf[2 * sd + 1], rb, 0, T[sd], r, (long long)nb * r, 0.0, Bt[sd],
+                               r, (long long)rb * r, ra});
+      }
+      for (int m = 0; m < 4; ++m) J.out->rank[m] = R[m];
+      J.out->rank[4] = r; J.out->rank[5] = r;
+    }
+    if (fatal(q.copy2d(cp)) || fatal(q.sign_fix(sg)) || fatal(q.gemm(true, false, gt)) ||
+        fatal(q.gemm(true, false, gbt)))
+      return SLAR_E_HIP;
   }
   for (TruncJob& J : jobs) {
     if (J.st != SLAR_OK) continue;
@@ -645,6 +662,21 @@ slar_status truncate_group(hipStream_t s, std::vector<TruncJob>& jobs, double to
     J.out->d = J.ws->G.d;
     if (J.capped) J.st = SLAR_E_RANK_CAP;
   }
+  // ---- frames of the new tensors
+  {
+    std::vector<Workspace*> fw;
+    std::vector<const slar_ht*> fh;
+    std::vector<slar_frames*> fo;
+    for (TruncJob& J : jobs)
+      if ((J.st == SLAR_OK || J.st == SLAR_E_RANK_CAP) && J.frames) {
+        fw.push_back(J.ws);
+        fh.push_back(J.out);
+        fo.push_back(J.frames);
+      }
+    if (!fw.empty() && fatal(frames_from_ht_group(q, (int)fw.size(), fw.data(), fh.data(), fo.data())))
+      return SLAR_E_HIP;
+  }
+  if (fatal(q.flush(s))) return SLAR_E_HIP;
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   return SLAR_OK;

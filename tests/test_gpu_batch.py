@@ -148,11 +148,13 @@ def test_batch_rejects_bad_arguments():
 
 @pytest.mark.parametrize("refine", [False, True])
 def test_grouped_truncation_equals_single_instance(refine):
-    """The batched truncation runs every instance's single-block
-    factorisations (Cholesky, core SVD, Gram eigenpairs, basis completion)
-    as one grouped launch per phase; each instance must still get, bit for
-    bit, the HT tensor and ranks of the one-instance slar_truncate on a
-    workspace with the same leaf-refinement setting.  Factor sets of 40 to
+    """The batched truncation runs each of its steps (products, Grams, sign
+    rules, copies, and the single-block factorisations: Cholesky, core SVD,
+    Gram eigenpairs, basis completion) as one grouped launch over all
+    instances, then the frame builds; each instance must still get, bit for
+    bit, the HT tensor, ranks and frames of the one-instance slar_truncate
+    and slar_frames_from_ht on a workspace with the same leaf-refinement
+    setting.  Factor sets of 40 to
     96 terms (the k <= 64 and k > 64 SVD forms in the same group), 1D1V and
     2D2V instances mixed; converged crosses of up to min(2 rmax, 128) terms
     reach the truncation (the rank cap applies after it)."""
@@ -174,7 +176,8 @@ def test_grouped_truncation_equals_single_instance(refine):
         keep.append((U, V))
         lrs.append(L.LowRank(k, U.data_ptr(), V.data_ptr()))
     hts = [I.ht_desc(0) for I in b.inst]
-    b.batch.truncate(lrs, tol, b.rmax, hts, [I.frames(0) for I in b.inst])
+    frs = [I.frames(0) for I in b.inst]
+    b.batch.truncate(lrs, tol, b.rmax, hts, frs)
     torch.cuda.synchronize()
     for q, p in enumerate(problems):
         one = _Inst(p)
@@ -182,8 +185,15 @@ def test_grouped_truncation_equals_single_instance(refine):
         ws = L.Workspace(L.make_grid(p), b.rmax)
         L.slar_leaf_refine(ws, refine)
         L.slar_truncate(ws.grid, lrs[q], tol, b.rmax, H, ws)
+        X, P = one.frames_buf[0]
+        F1 = L.slar_frames_from_ht(ws.grid, H, one.frames(0), ws)
         torch.cuda.synchronize()
         assert list(H.rank) == list(hts[q].rank), q
+        # the frames built in the same grouped call
+        r = F1.r
+        assert frs[q].r == r, q
+        Xb, Pb = b.inst[q].frames_buf[0]
+        assert torch.equal(Xb[:, :r], X[:, :r]) and torch.equal(Pb[:, :r], P[:, :r]), q
         a = ht_from_dev(hts[q], b.inst[q].ht[0], p.dx + p.dv, p.n)
         c = ht_from_dev(H, one.ht[0], p.dx + p.dv, p.n)
         for key in ("root", "B12", "B34"):
