@@ -447,8 +447,9 @@ slar_status slar_timing_read(const slar_workspace* ws, double* out);
  * Vlasov--Poisson problem advanced by the same SLAR sub-flows, section 3.1).
  * A batch owns one workspace per instance, the device tables of the
  * persistent multi-instance cross approximation, a captured hipGraph of its
- * iteration chunk, and a pool of host threads with one stream each for the
- * per-instance work that contains host decisions (truncation ranks).
+ * iteration chunk, and the staging memory of the grouped launches (one
+ * launch per step for all instances) of the truncation, frame builds and
+ * field solves; all work runs on the caller's stream.
  * Array arguments below are host arrays of `count` entries, in instance
  * order; the device buffers they point to belong to the caller.  A batch is
  * used from one host thread and one caller stream at a time.
@@ -479,21 +480,22 @@ slar_status slar_batch_cross_update(slar_batch* b, const slar_frames* src, const
                                     const int32_t* const* probes, slar_lowrank* out,
                                     slar_cross_info* info, hipStream_t stream);
 
-/* slar_truncate for every instance (bit-identical results), ordered after
- * the work already on `stream`: the single-block factorisations of all
- * instances run as one launch per phase, the per-instance products on a
- * host thread pool (one stream per thread); followed, when frames != NULL,
- * by slar_frames_from_ht into frames[q] (ld >= rmax).  Each workspace's
- * leaf-refinement setting applies to its instance.  status (host
- * int32[count], may be NULL) receives per-instance statuses; the return
- * value is the most severe of them.                                         */
+/* slar_truncate for every instance (bit-identical results), followed,
+ * when frames != NULL, by slar_frames_from_ht into frames[q] (ld >= rmax);
+ * every step is one grouped launch over all instances on `stream`, and the
+ * host reads the singular values and eigenvalues of all instances in one
+ * copy each.  Each workspace's leaf-refinement setting applies to its
+ * instance.  status (host int32[count], may be NULL) receives per-instance
+ * statuses; the return value is the most severe of them.  Synchronises the
+ * stream.                                                                   */
 slar_status slar_batch_truncate(slar_batch* b, const slar_lowrank* in, double tol, int32_t rmax,
                                 slar_ht* out, slar_frames* frames, int32_t* status,
                                 hipStream_t stream);
 
 /* Per instance: moments M[q] ([nmom][Nx], as slar_moments) of F[q] and the
- * spectral Poisson field E[q] ([dx][Nx]) with ion density n_i[q] (host).
- * Enqueued by the pool; `stream` waits for the result.                      */
+ * spectral Poisson field E[q] ([dx][Nx]) with ion density n_i[q] (host),
+ * bit-identical to slar_moments + slar_poisson; every step one grouped
+ * launch over all instances, enqueued on `stream` (no synchronisation).     */
 slar_status slar_batch_efield(slar_batch* b, const slar_frames* F, const double* n_i,
                               double* const* M, double* const* E, hipStream_t stream);
 

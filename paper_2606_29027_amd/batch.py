@@ -4,10 +4,9 @@ Every instance is advanced by the same SLAR_VP step as the one-instance
 driver (section 3.1: the three frozen-field sub-flows of the third-order
 commutator-free exponential integrator, each one cross approximation plus
 truncation), but each stage is one batched library call for all instances:
-slar_batch_efield, slar_batch_cross_update (persistent multi-instance
-launches replayed from a captured hipGraph) and slar_batch_truncate (the
-single-block factorisations of all instances grouped into one launch per
-phase, the per-instance products on a host thread pool).  Instances differ in dimension, grid
+slar_batch_efield and slar_batch_truncate (every step one grouped launch
+over all instances) and slar_batch_cross_update (persistent multi-instance
+launches replayed from a captured hipGraph).  Instances differ in dimension, grid
 size and rank; they share tolerance, rank cap and time step.
 
 This module only sequences library calls and owns the device buffers; it

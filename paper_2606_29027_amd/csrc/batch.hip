@@ -13,25 +13,19 @@
 // inputs and picks the persistent grid size, the tiles per work item, the
 // iterations per graph chunk, and the gather team width per rank bucket.
 //
-// Truncation: the grouped form (truncate.hip) runs the single-block
-// factorisations of every instance (Cholesky, core SVD, Gram eigenpairs) as
-// one launch per phase and takes the rank decisions of all instances after
-// one gathered read per phase; the per-instance products between the
-// phases, the frames and the field solves are enqueued by a pool of host
-// threads, one HIP stream (default priority) per thread.
+// Truncation, frames and field solves: every step one grouped launch over
+// all instances on the caller stream (group.h); the truncation takes the
+// rank decisions of all instances after one gathered read of their
+// singular values and one of their eigenvalues.
 #include <algorithm>
-#include <atomic>
 #include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <functional>
-#include <mutex>
 #include <new>
-#include <thread>
 #include <vector>
 
 #include "aca.h"
 #include "fields.h"
+#include "group.h"
 #include "truncate.h"
 
 namespace slar {
@@ -162,76 +156,6 @@ __global__ __launch_bounds__(256) void k_batch_status(const AcaInst* __restrict_
   if (threadIdx.x == 0) *active = red[0] + red[1] + red[2] + red[3];
 }
 
-// ------------------------------------------------------------ host pool
-// Fixed set of worker threads; run() hands out task indices and returns when
-// every task has finished.
-class Pool {
- public:
-  explicit Pool(int n) {
-    for (int w = 0; w < n; ++w) threads_.emplace_back([this, w] { loop(w); });
-  }
-  ~Pool() {
-    {
-      std::lock_guard<std::mutex> g(m_);
-      stop_ = true;
-      ++gen_;
-    }
-    cv_.notify_all();
-    for (auto& t : threads_) t.join();
-  }
-  int size() const { return (int)threads_.size(); }
-  // fn(worker, task) for task in [0, ntasks); begin(worker)/end(worker) run
-  // once per worker around its share
-  void run(int ntasks, const std::function<void(int)>& begin, const std::function<void(int, int)>& fn,
-           const std::function<void(int)>& end) {
-    std::unique_lock<std::mutex> g(m_);
-    ntasks_ = ntasks;
-    next_.store(0);
-    begin_ = &begin; fn_ = &fn; end_ = &end;
-    finished_ = 0;
-    ++gen_;
-    cv_.notify_all();
-    done_cv_.wait(g, [this] { return finished_ == (int)threads_.size(); });
-  }
-
- private:
-  void loop(int w) {
-    long long seen = 0;
-    for (;;) {
-      const std::function<void(int)>* b;
-      const std::function<void(int, int)>* f;
-      const std::function<void(int)>* e;
-      int n;
-      {
-        std::unique_lock<std::mutex> g(m_);
-        cv_.wait(g, [&] { return gen_ != seen; });
-        seen = gen_;
-        if (stop_) return;
-        b = begin_; f = fn_; e = end_; n = ntasks_;
-      }
-      (*b)(w);
-      for (int t = next_.fetch_add(1); t < n; t = next_.fetch_add(1)) (*f)(w, t);
-      (*e)(w);
-      {
-        std::lock_guard<std::mutex> g(m_);
-        ++finished_;
-      }
-      done_cv_.notify_all();
-    }
-  }
-  std::vector<std::thread> threads_;
-  std::mutex m_;
-  std::condition_variable cv_, done_cv_;
-  long long gen_ = 0;
-  bool stop_ = false;
-  int ntasks_ = 0, finished_ = 0;
-  std::atomic<int> next_{0};
-  const std::function<void(int)>* begin_ = nullptr;
-  const std::function<void(int, int)>* fn_ = nullptr;
-  const std::function<void(int)>* end_ = nullptr;
-};
-
-constexpr int BATCH_POOL = 8;
 
 }  // namespace slar
 
@@ -264,17 +188,18 @@ struct slar_batch {
   hipGraphExec_t exec = nullptr;
   int captured_grid = -1, captured_group = -1, captured_chunk = -1;
   int captures = 0;
-  // host work pool
-  Pool* pool = nullptr;
-  std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> ev_done;
-  hipEvent_t ev_in = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double tstat[4] = {0, 0, 0, 0};  // cross ms, chunks, iterations (max over instances), calls
   // grouped truncation and skeleton cores: descriptors and gathered values
-  // (device, pinned mirror)
+  // (device, pinned mirror); both synchronise before they return
   void* d_tg = nullptr;
   void* h_tg = nullptr;
+  // grouped field solves (asynchronous): their own staging, reusable once
+  // ev_fg (recorded after the upload) has completed
+  void* d_fg = nullptr;
+  void* h_fg = nullptr;
+  size_t fg_bytes = 0;
+  hipEvent_t ev_fg = nullptr;
 };
 
 static int bucket_of(int r) { return r <= 16 ? 0 : (r <= 32 ? 1 : 2); }
@@ -427,54 +352,21 @@ static slar_status worst_of(const std::vector<slar_status>& st) {
   return SLAR_OK;
 }
 
-// Run fn(q, stream, ws) for every instance on the pool; the pool streams
-// wait for the work already on s, and s waits for everything they enqueue.
-static slar_status pool_run(slar_batch* b, hipStream_t s,
-                            const std::function<slar_status(int, hipStream_t, Workspace*)>& fn,
-                            int32_t* status) {
-  if (hipEventRecord(b->ev_in, s) != hipSuccess) return SLAR_E_HIP;
-  std::vector<slar_status> st(b->count, SLAR_OK);
-  std::vector<int> bad(b->pool->size(), 0);
-  auto begin = [&](int w) {
-    if (hipSetDevice(b->device) != hipSuccess || hipStreamWaitEvent(b->streams[w], b->ev_in, 0) != hipSuccess)
-      bad[w] = 1;
-  };
-  auto task = [&](int w, int t) {
-    const int q = b->order[t];
-    st[q] = bad[w] ? SLAR_E_HIP : fn(q, b->streams[w], &b->ws[q]->w);
-  };
-  auto end = [&](int w) {
-    if (hipEventRecord(b->ev_done[w], b->streams[w]) != hipSuccess) bad[w] = 1;
-  };
-  b->pool->run(b->count, begin, task, end);
-  for (int w = 0; w < b->pool->size(); ++w) {
-    if (bad[w]) return SLAR_E_HIP;
-    if (hipStreamWaitEvent(s, b->ev_done[w], 0) != hipSuccess) return SLAR_E_HIP;
-  }
-  if (status)
-    for (int q = 0; q < b->count; ++q) status[q] = st[q];
-  return worst_of(st);
-}
 
 extern "C" {
 
 slar_status slar_batch_destroy(slar_batch* b) {
   if (!b) return SLAR_OK;
-  delete b->pool;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (hipStream_t s : b->streams) {
-    (void)hipStreamSynchronize(s);
-    (void)hipStreamDestroy(s);
-  }
-  for (hipEvent_t e : b->ev_done) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {b->ev_in, b->ev0, b->ev1})
+  if (b->ev_fg) (void)hipEventSynchronize(b->ev_fg);
+  for (hipEvent_t e : {b->ev0, b->ev1, b->ev_fg})
     if (e) (void)hipEventDestroy(e);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   for (void* p : {(void*)b->d_inst, (void*)b->d_prep, (void*)b->d_rows, (void*)b->d_cols,
-                  (void*)b->d_active, (void*)b->d_sum, b->d_tg})
+                  (void*)b->d_active, (void*)b->d_sum, b->d_tg, b->d_fg})
     if (p) (void)hipFree(p);
-  for (void* p : {(void*)b->h_inst, (void*)b->h_prep, (void*)b->h_active, (void*)b->h_sum, b->h_tg})
+  for (void* p : {(void*)b->h_inst, (void*)b->h_prep, (void*)b->h_active, (void*)b->h_sum, b->h_tg, b->h_fg})
     if (p) (void)hipHostFree(p);
   for (slar_workspace* w : b->ws) slar_workspace_destroy(w);
   delete b;
@@ -527,25 +419,17 @@ slar_status slar_batch_create(int32_t count, const slar_grid* grids, int32_t rma
   const size_t tg = std::max(truncate_group_bytes(count), cur_core_group_bytes(count));
   dal(&b->d_tg, tg);
   hal(&b->h_tg, tg);
+  b->fg_bytes = (size_t)64 * 1024 + (size_t)count * 4096;
+  dal(&b->d_fg, b->fg_bytes);
+  hal(&b->h_fg, b->fg_bytes);
   if (!ok) return fail(SLAR_E_NOMEM);
   std::memset(b->h_inst, 0, sizeof(AcaInst) * count);
   if (hipMemcpy(b->d_inst, b->h_inst, sizeof(AcaInst) * count, hipMemcpyHostToDevice) != hipSuccess)
     return fail(SLAR_E_HIP);
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return fail(SLAR_E_HIP);
-  if (hipEventCreate(&b->ev_in) != hipSuccess || hipEventCreate(&b->ev0) != hipSuccess ||
-      hipEventCreate(&b->ev1) != hipSuccess)
+  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fg, hipEventDisableTiming) != hipSuccess)
     return fail(SLAR_E_HIP);
-  const int np = std::min(BATCH_POOL, count);
-  for (int w = 0; w < np; ++w) {
-    hipStream_t s;
-    hipEvent_t e;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(SLAR_E_HIP);
-    b->streams.push_back(s);
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(SLAR_E_HIP);
-    b->ev_done.push_back(e);
-  }
-  b->pool = new (std::nothrow) Pool(np);
-  if (!b->pool) return fail(SLAR_E_NOMEM);
   *out = b;
   return SLAR_OK;
 }
@@ -609,11 +493,15 @@ slar_status slar_batch_efield(slar_batch* b, const slar_frames* F, const double*
   if (!b || !F || !n_i || !M || !E || !batch_frames_ok(b, F)) return SLAR_E_INVAL;
   for (int q = 0; q < b->count; ++q)
     if (!M[q] || !E[q]) return SLAR_E_INVAL;
-  return pool_run(b, stream, [&](int q, hipStream_t s, Workspace* w) -> slar_status {
-    if (moments_run(s, w, F[q], M[q]) != hipSuccess) return SLAR_E_HIP;
-    if (poisson_run(s, w, M[q], n_i[q], nullptr, E[q]) != hipSuccess) return SLAR_E_HIP;
-    return SLAR_OK;
-  }, nullptr);
+  // every step one grouped launch over all instances, on the caller stream
+  if (hipEventSynchronize(b->ev_fg) != hipSuccess) return SLAR_E_HIP;   // staging free again
+  std::vector<Workspace*> ws(b->count);
+  for (int q = 0; q < b->count; ++q) ws[q] = &b->ws[q]->w;
+  GroupQueue gq(b->d_fg, b->h_fg, b->fg_bytes);
+  if (efield_group(gq, b->count, ws.data(), F, n_i, M, E) != hipSuccess) return SLAR_E_HIP;
+  if (gq.flush(stream) != hipSuccess) return SLAR_E_HIP;
+  if (hipEventRecord(b->ev_fg, stream) != hipSuccess) return SLAR_E_HIP;
+  return SLAR_OK;
 }
 
 slar_status slar_batch_get_config(const slar_batch* b, int32_t* cfg) {

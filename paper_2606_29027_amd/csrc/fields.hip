@@ -12,6 +12,7 @@
 #include "slar_internal.h"
 #include "dense.h"
 #include "fields.h"
+#include "group.h"
 
 namespace slar {
 
@@ -28,14 +29,12 @@ void host_twiddles(int n, std::vector<double>& tw) {
 
 // line transform along the last axis (axis = 1) or the first (axis = 0)
 // of [B][n0][n1] complex (double2) data; sign -1 forward, +1 inverse.
-__global__ void k_dft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
-                           const double* __restrict__ realin, double2* __restrict__ out,
-                           const double* __restrict__ tw) {
+__device__ __forceinline__ void dft_line_dev(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
+                                             const double* __restrict__ realin, double2* __restrict__ out,
+                                             const double* __restrict__ tw, int other, int b) {
   __shared__ double2 line[SLAR_NLINE];
   __shared__ double2 w[SLAR_NLINE];
-  const int b = blockIdx.y;
   const int L = axis == 1 ? n1 : n0;          // line length
-  const int other = blockIdx.x;               // index along the other axis
   const long long base = (long long)b * n0 * n1;
   const int t = threadIdx.x;
   for (int e = t; e < L; e += blockDim.x) {
@@ -57,6 +56,12 @@ __global__ void k_dft_line(int n0, int n1, int axis, double sign, const double2*
     const long long off = axis == 1 ? base + (long long)other * n1 + kk : base + (long long)kk * n1 + other;
     out[off] = make_double2(re, im);
   }
+}
+
+__global__ void k_dft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
+                           const double* __restrict__ realin, double2* __restrict__ out,
+                           const double* __restrict__ tw) {
+  dft_line_dev(n0, n1, axis, sign, in, realin, out, tw, blockIdx.x, blockIdx.y);
 }
 
 // Radix-2 Cooley--Tukey stages over `nl` lines of length L = 2^logL held
@@ -84,14 +89,12 @@ __device__ void fft_stages(double2* a, int nl, int L, const double* __restrict__
 // FFT of one line (n a power of two <= SLAR_NLINE) per block: bit-reversed
 // load, log2(n) butterfly stages.  With realout set, the scaled real part
 // is stored instead of the complex line.
-__global__ void k_fft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
-                           const double* __restrict__ realin, double2* __restrict__ out,
-                           double* __restrict__ realout, double scale,
-                           const double* __restrict__ tw, int logL) {
+__device__ __forceinline__ void fft_line_dev(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
+                                             const double* __restrict__ realin, double2* __restrict__ out,
+                                             double* __restrict__ realout, double scale,
+                                             const double* __restrict__ tw, int logL, int other, int b) {
   __shared__ double2 a[SLAR_NLINE];
-  const int b = blockIdx.y;
   const int L = axis == 1 ? n1 : n0;
-  const int other = blockIdx.x;
   const long long base = (long long)b * n0 * n1;
   const int t = threadIdx.x;
   for (int e = t; e < L; e += blockDim.x) {
@@ -107,6 +110,34 @@ __global__ void k_fft_line(int n0, int n1, int axis, double sign, const double2*
     if (realout) realout[off] = a[e].x * scale;
     else out[off] = a[e];
   }
+}
+
+__global__ void k_fft_line(int n0, int n1, int axis, double sign, const double2* __restrict__ in,
+                           const double* __restrict__ realin, double2* __restrict__ out,
+                           double* __restrict__ realout, double scale,
+                           const double* __restrict__ tw, int logL) {
+  fft_line_dev(n0, n1, axis, sign, in, realin, out, realout, scale, tw, logL, blockIdx.x, blockIdx.y);
+}
+
+// grouped line transforms: problem d owns others x B blocks (line, field)
+__global__ __launch_bounds__(64) void k_fft_line_group(const LineDesc* __restrict__ D, const int* __restrict__ first,
+                                                       int nd) {
+  const int bk = blockIdx.x;
+  const int d = group_find(first, nd, bk);
+  const LineDesc g = D[d];
+  const int local = bk - first[d];
+  const int others = g.axis == 1 ? g.n0 : g.n1;
+  fft_line_dev(g.n0, g.n1, g.axis, g.sign, g.in, g.realin, g.out, nullptr, 0.0, g.tw, g.logL, local % others,
+               local / others);
+}
+__global__ __launch_bounds__(128) void k_dft_line_group(const LineDesc* __restrict__ D, const int* __restrict__ first,
+                                                        int nd) {
+  const int bk = blockIdx.x;
+  const int d = group_find(first, nd, bk);
+  const LineDesc g = D[d];
+  const int local = bk - first[d];
+  const int others = g.axis == 1 ? g.n0 : g.n1;
+  dft_line_dev(g.n0, g.n1, g.axis, g.sign, g.in, g.realin, g.out, g.tw, local % others, local / others);
 }
 
 static int log2_exact(int n) {
@@ -132,6 +163,7 @@ __global__ void k_take_real(long long n, const double2* __restrict__ in, double 
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) out[e] = in[e].x * scale;
 }
+
 
 // Forward 2D DFT of B real fields [B][Nx] into complex [B][Nx].
 hipError_t dft_forward(hipStream_t s, Workspace* ws, int B, const double* in, double2* out,
@@ -183,9 +215,8 @@ __device__ __forceinline__ void kvec(const Kgrid& K, long long e, double* k) {
 // 1 gradient (f^ -> i k_m f^), 2 divergence (F^[m] -> sum i k_m F^_m),
 // 3 inverse negative Laplacian (f^ -> f^ / |k|^2, 0 on null modes).
 // in/out strides are in fields of Nx complex values.
-__global__ void k_symbol(Kgrid K, int op, int nvec, const double2* __restrict__ in,
-                         double2* __restrict__ out, int Nx) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void symbol_dev(const Kgrid& K, int op, int nvec, const double2* __restrict__ in,
+                                           double2* __restrict__ out, int Nx, long long e) {
   if (e >= (long long)Nx * nvec) return;
   const int v = (int)(e / Nx);
   const long long p = e % Nx;
@@ -214,6 +245,29 @@ __global__ void k_symbol(Kgrid K, int op, int nvec, const double2* __restrict__ 
   } else {
     const double2 f = in[(long long)v * Nx + p];
     out[(long long)v * Nx + p] = k2 > 0.0 ? make_double2(f.x / k2, f.y / k2) : make_double2(0.0, 0.0);
+  }
+}
+
+__global__ void k_symbol(Kgrid K, int op, int nvec, const double2* __restrict__ in,
+                         double2* __restrict__ out, int Nx) {
+  symbol_dev(K, op, nvec, in, out, Nx, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// grouped pointwise field steps (FieldDesc.op): rho = n_i - n_e, the
+// scaled real part, or the symbol map; one element per thread
+__global__ __launch_bounds__(256) void k_field_group(const FieldDesc* __restrict__ D, const int* __restrict__ first,
+                                                     int nd) {
+  const int bk = blockIdx.x;
+  const int d = group_find(first, nd, bk);
+  const FieldDesc g = D[d];
+  const long long e = (long long)(bk - first[d]) * 256 + threadIdx.x;
+  if (g.op == FIELD_RHO) {
+    if (e < g.n) g.rout[e] = g.ni - g.rin[e];
+  } else if (g.op == FIELD_REAL) {
+    if (e < g.n) g.rout[e] = g.cin[e].x * g.scale;
+  } else {
+    const Kgrid K{g.n0, g.n1, g.dx, g.L0, g.L1};
+    symbol_dev(K, g.sym, g.nvec, g.cin, g.cout, g.Nx, e);
   }
 }
 
@@ -468,14 +522,26 @@ hipError_t psi_build(hipStream_t s, Workspace* ws) {
 // reduction over long n, deterministic split: chunks of `chunk` rows as one
 // batched product (a single product over n runs on one tile), then a fixed
 // order sum of the chunk products.
-__global__ void k_sum_batches(const double* __restrict__ P, int M, int N, int batch,
-                              double* __restrict__ C, int ldc, double beta) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sum_batches_dev(const double* __restrict__ P, int M, int N, int batch,
+                                                double* __restrict__ C, int ldc, double beta, int e) {
   if (e >= M * N) return;
   double acc = 0.0;
   for (int b = 0; b < batch; ++b) acc += P[(long long)b * M * N + e];
   double* c = C + (long long)(e / N) * ldc + (e % N);
   *c = (beta == 0.0) ? acc : acc + beta * (*c);
+}
+
+__global__ void k_sum_batches(const double* __restrict__ P, int M, int N, int batch,
+                              double* __restrict__ C, int ldc, double beta) {
+  sum_batches_dev(P, M, N, batch, C, ldc, beta, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_sum_batches_group(const SumDesc* __restrict__ D,
+                                                           const int* __restrict__ first, int nd) {
+  const int bk = blockIdx.x;
+  const int d = group_find(first, nd, bk);
+  const SumDesc g = D[d];
+  sum_batches_dev(g.P, g.M, g.N, g.batch, g.C, g.ldc, 0.0, (bk - first[d]) * 256 + (int)threadIdx.x);
 }
 
 hipError_t gemm_tn_long(hipStream_t s, Workspace* ws, int rows, int cols, int n, const double* A,
@@ -505,6 +571,105 @@ hipError_t moments_run(hipStream_t s, Workspace* ws, const slar_frames& F, doubl
   if (e != hipSuccess) return e;
   // M^T = m^T X^T  -> [nmom][Nx]
   return gemm_f64(s, true, true, nmom, G.nx, F.r, 1.0, m, nmom, 0, F.X, F.ld, 0, 0.0, M, G.nx, 0, 1);
+}
+
+hipError_t line_group_launch(hipStream_t s, bool fft, const LineDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  if (fft) k_fft_line_group<<<nblocks, 64, 0, s>>>(d, first, nd);
+  else k_dft_line_group<<<nblocks, 128, 0, s>>>(d, first, nd);
+  return hipGetLastError();
+}
+
+hipError_t field_group_launch(hipStream_t s, const FieldDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_field_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
+}
+
+hipError_t sum_group_launch(hipStream_t s, const SumDesc* d, const int* first, int nd, int nblocks) {
+  if (nd <= 0 || nblocks <= 0) return hipSuccess;
+  k_sum_batches_group<<<nblocks, 256, 0, s>>>(d, first, nd);
+  return hipGetLastError();
+}
+
+// moments_run and poisson_run for n problems, every step one grouped launch
+// (the scratch of each problem as in the one-problem calls)
+hipError_t efield_group(GroupQueue& q, int n, Workspace* const* ws, const slar_frames* F, const double* n_i,
+                        double* const* M, double* const* E) {
+  std::vector<GemmArgs> m1, m3, m4;
+  std::vector<SumDesc> m2;
+  std::vector<FieldDesc> rho, real;
+  std::vector<FieldDesc> sym;
+  std::vector<LineDesc> f1, f0, i0, i1;
+  std::vector<CopyDesc> cpE;
+  for (int j = 0; j < n; ++j) {
+    Workspace* w = ws[j];
+    const GridDev& G = w->G;
+    const int Nx = G.nx, nmom = nmom_of(G.dv), r = F[j].r;
+    // moments: m = P^T Psi (chunked, fixed-order sum), M = m^T X^T
+    double* m = w->cbuf + (size_t)2 * 40 * Nx + (size_t)8 * Nx;
+    {
+      const int n_ = G.nv;
+      int chunk = 256;
+      while ((size_t)((n_ + chunk - 1) / chunk) * r * nmom > w->dwork_elems) chunk *= 2;
+      const int full = n_ / chunk, tail = n_ - full * chunk;
+      if (full > 0) {
+        m1.push_back(GemmArgs{r, nmom, chunk, 1.0, F[j].P, F[j].ld, (long long)chunk * F[j].ld, w->psi, nmom,
+                              (long long)chunk * nmom, 0.0, w->dwork, nmom, (long long)r * nmom, full});
+        m2.push_back(SumDesc{r, nmom, full, nmom, w->dwork, m});
+      }
+      if (tail > 0)
+        m3.push_back(GemmArgs{r, nmom, tail, 1.0, F[j].P + (long long)full * chunk * F[j].ld, F[j].ld, 0,
+                              w->psi + (long long)full * chunk * nmom, nmom, 0, full > 0 ? 1.0 : 0.0, m, nmom, 0,
+                              1});
+    }
+    m4.push_back(GemmArgs{nmom, Nx, r, 1.0, m, nmom, 0, F[j].X, F[j].ld, 0, 0.0, M[j], Nx, 0, 1});
+    // Poisson: rho = n_i - n_e, forward transform, symbol, inverse of
+    // (phi, E), real part, E copied out
+    double2* c0 = (double2*)w->cbuf;
+    double2* c1 = c0 + (size_t)4 * Nx;
+    double2* tmp = c0 + (size_t)12 * Nx;
+    double* rh = w->cbuf + (size_t)2 * 40 * Nx;
+    double* out = rh + Nx;
+    const int n0 = G.n[0], n1 = G.dx == 2 ? G.n[1] : 1;
+    const int lg0 = log2_exact(n0), lg1 = G.dx == 2 ? log2_exact(n1) : 0;
+    FieldDesc fr{};
+    fr.op = FIELD_RHO; fr.n = Nx; fr.ni = n_i[j]; fr.rin = M[j]; fr.rout = rh;
+    rho.push_back(fr);
+    const int B = 1 + G.dx;
+    const long long tot = (long long)B * Nx;
+    if (G.dx == 2) {
+      f1.push_back(LineDesc{n0, n1, 1, lg1, 1, -1.0, nullptr, rh, tmp, w->tw[1]});
+      f0.push_back(LineDesc{n0, n1, 0, lg0, 1, -1.0, tmp, nullptr, c0, w->tw[0]});
+      i0.push_back(LineDesc{n0, n1, 0, lg0, B, 1.0, c1, nullptr, tmp, w->tw[0]});
+      i1.push_back(LineDesc{n0, n1, 1, lg1, B, 1.0, tmp, nullptr, tmp + tot, w->tw[1]});
+    } else {
+      f0.push_back(LineDesc{n0, 1, 0, lg0, 1, -1.0, nullptr, rh, c0, w->tw[0]});
+      i0.push_back(LineDesc{n0, 1, 0, lg0, B, 1.0, c1, nullptr, tmp, w->tw[0]});
+    }
+    FieldDesc fs{};
+    fs.op = FIELD_SYMBOL; fs.sym = 0; fs.nvec = 1; fs.Nx = Nx; fs.n0 = n0; fs.n1 = n1; fs.dx = G.dx;
+    fs.L0 = w->grid.hi[0] - w->grid.lo[0];
+    fs.L1 = G.dx == 2 ? w->grid.hi[1] - w->grid.lo[1] : 1.0;
+    fs.cin = c0; fs.cout = c1;
+    sym.push_back(fs);
+    FieldDesc fx{};
+    fx.op = FIELD_REAL; fx.n = tot; fx.scale = 1.0 / Nx; fx.cin = G.dx == 2 ? tmp + tot : tmp; fx.rout = out;
+    real.push_back(fx);
+    cpE.push_back(CopyDesc{1, Nx * G.dx, Nx * G.dx, Nx * G.dx, out + Nx, E[j], nullptr});
+  }
+  HIP_CHK(q.gemm(true, false, m1));
+  HIP_CHK(q.sums(m2));
+  HIP_CHK(q.gemm(true, false, m3));
+  HIP_CHK(q.gemm(true, true, m4));
+  HIP_CHK(q.field(rho));
+  HIP_CHK(q.lines(f1));
+  HIP_CHK(q.lines(f0));
+  HIP_CHK(q.field(sym));
+  HIP_CHK(q.lines(i0));
+  HIP_CHK(q.lines(i1));
+  HIP_CHK(q.field(real));
+  return q.copy2d(cpE);
 }
 
 __global__ void k_conserved(int Nx, int dv, const double* M, const double* E, int dx, double* U) {

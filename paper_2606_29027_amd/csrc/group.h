@@ -59,6 +59,29 @@ struct SignDesc {   // sign_fix / sign_fix_tall
   double* B;
   double* part;   // tall form: [nb][cols] partial maxima, then [cols] signs
 };
+struct LineDesc {   // one batch of line transforms (FFT for 2^logL, else DFT)
+  int n0, n1, axis, logL, B;
+  double sign;
+  const double2* in;
+  const double* realin;
+  double2* out;
+  const double* tw;
+};
+enum { FIELD_RHO = 0, FIELD_REAL = 1, FIELD_SYMBOL = 2 };
+struct FieldDesc {  // pointwise field steps of the spectral solve
+  int op, sym, nvec, Nx, n0, n1, dx;
+  long long n;      // elements (RHO, REAL)
+  double ni, scale, L0, L1;
+  const double* rin;
+  double* rout;
+  const double2* cin;
+  double2* cout;
+};
+struct SumDesc {    // fixed-order sum of batched chunk products (C = sum_b P_b)
+  int M, N, batch, ldc;
+  const double* P;
+  double* C;
+};
 struct ScaleDesc {  // scale_cols_inv (k x r, ld) or the diagonal root diag(sv[:r])
   int k, r, ld, diag;
   double* Z;
@@ -76,6 +99,9 @@ hipError_t sign_part_group_launch(hipStream_t s, const SignDesc* d, const int* f
 hipError_t sign_decide_group_launch(hipStream_t s, const SignDesc* d, const int* first, int nd, int nblocks);
 hipError_t sign_apply_group_launch(hipStream_t s, const SignDesc* d, const int* first, int nd, int nblocks);
 hipError_t scale_group_launch(hipStream_t s, const ScaleDesc* d, const int* first, int nd, int nblocks);
+hipError_t line_group_launch(hipStream_t s, bool fft, const LineDesc* d, const int* first, int nd, int nblocks);
+hipError_t field_group_launch(hipStream_t s, const FieldDesc* d, const int* first, int nd, int nblocks);
+hipError_t sum_group_launch(hipStream_t s, const SumDesc* d, const int* first, int nd, int nblocks);
 
 // Arguments of one problem of a grouped operation, as the one-problem calls
 // take them.
@@ -125,6 +151,10 @@ class GroupQueue {
   hipError_t sign_fix(const std::vector<SignArgs>& p);        // sign_fix
   hipError_t sign_fix_tall(const std::vector<SignArgs>& p);   // sign_fix_tall
   hipError_t scale(const std::vector<ScaleDesc>& p);
+  // line transforms (FFT and DFT problems in two launches)
+  hipError_t lines(const std::vector<LineDesc>& p);
+  hipError_t field(const std::vector<FieldDesc>& p);
+  hipError_t sums(const std::vector<SumDesc>& p);
   // arbitrary launch that reads descriptors staged here: stage() copies
   // bytes into the staging area and returns their device address
   const void* stage(const void* src, size_t bytes);
@@ -145,6 +175,12 @@ class GroupQueue {
   bool overflow_ = false;
   std::vector<std::function<hipError_t(hipStream_t)>> ops_;
 };
+
+// grouped moments_run + poisson_run (fields.hip): per problem j the moments
+// M[j] of frames F[j] and the field E[j] with ion density n_i[j], one
+// launch per step of the one-problem calls for all n problems
+hipError_t efield_group(GroupQueue& q, int n, Workspace* const* ws, const slar_frames* F, const double* n_i,
+                        double* const* M, double* const* E);
 
 // grouped slar_frames_from_ht (sample.hip): one launch per step of the
 // one-tensor call for all n tensors; out[j]->r is set on return

@@ -206,6 +206,58 @@ hipError_t GroupQueue::scale(const std::vector<ScaleDesc>& p) {
   return hipSuccess;
 }
 
+// one launch over problems whose block count is count(desc) each
+template <class D, class C, class L>
+static hipError_t simple_group(GroupQueue& q, const std::vector<D>& p, C count, L launch) {
+  std::vector<D> ds;
+  std::vector<int> first;
+  long long nb = 0;
+  for (const D& a : p) {
+    const long long c = count(a);
+    if (c <= 0) continue;
+    ds.push_back(a);
+    first.push_back((int)nb);
+    nb += c;
+  }
+  if (ds.empty()) return hipSuccess;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+  const D* dd = (const D*)q.stage(ds.data(), sizeof(D) * ds.size());
+  const int* df = (const int*)q.stage(first.data(), sizeof(int) * first.size());
+  if (!dd || !df) return hipErrorOutOfMemory;
+  const int nd = (int)ds.size(), nbi = (int)nb;
+  q.then([=](hipStream_t s) { return launch(s, dd, df, nd, nbi); });
+  return hipSuccess;
+}
+
+hipError_t GroupQueue::lines(const std::vector<LineDesc>& p) {
+  std::vector<LineDesc> fft, dft;
+  for (const LineDesc& a : p) (a.logL >= 1 ? fft : dft).push_back(a);
+  auto count = [](const LineDesc& a) { return (long long)(a.axis == 1 ? a.n0 : a.n1) * a.B; };
+  HIP_CHK(simple_group(*this, fft, count, [](hipStream_t s, const LineDesc* d, const int* f, int nd, int nb) {
+    return line_group_launch(s, true, d, f, nd, nb);
+  }));
+  return simple_group(*this, dft, count, [](hipStream_t s, const LineDesc* d, const int* f, int nd, int nb) {
+    return line_group_launch(s, false, d, f, nd, nb);
+  });
+}
+
+hipError_t GroupQueue::field(const std::vector<FieldDesc>& p) {
+  auto count = [](const FieldDesc& a) {
+    const long long n = a.op == FIELD_SYMBOL ? (long long)a.Nx * a.nvec : a.n;
+    return (n + 255) / 256;
+  };
+  return simple_group(*this, p, count, [](hipStream_t s, const FieldDesc* d, const int* f, int nd, int nb) {
+    return field_group_launch(s, d, f, nd, nb);
+  });
+}
+
+hipError_t GroupQueue::sums(const std::vector<SumDesc>& p) {
+  auto count = [](const SumDesc& a) { return ((long long)a.M * a.N + 255) / 256; };
+  return simple_group(*this, p, count, [](hipStream_t s, const SumDesc* d, const int* f, int nd, int nb) {
+    return sum_group_launch(s, d, f, nd, nb);
+  });
+}
+
 hipError_t GroupQueue::flush(hipStream_t s) {
   if (overflow_) return hipErrorOutOfMemory;
   if (used_ > flushed_) {

@@ -107,6 +107,31 @@ def test_batch_capped_crosses_equal_single_instance():
     assert capped >= 2
 
 
+def test_batch_efield_equals_single_instance():
+    """The batched field solve runs the moments (chunked products and their
+    fixed-order sum) and the spectral Poisson solve (line FFTs for powers of
+    two, DFTs for N = 48 and 96) as one grouped launch per step over all
+    instances: moments and field must equal, bit for bit, those of the
+    one-instance slar_moments and slar_poisson.  Two calls in a row without
+    a synchronisation between them share the staging memory."""
+    problems = SI.batched_instances(12)
+    assert {p.n[0] for p in problems} & {48, 96}
+    b, _ = _solver(problems)
+    E0 = [e.clone() for e in b.efield(b.state, 0)]
+    b.efield(b.state, 1)
+    torch.cuda.synchronize()
+    for q, p in enumerate(problems):
+        I = b.inst[q]
+        ws = b.batch.ws[q]
+        M = torch.zeros_like(I.M)
+        E = torch.zeros_like(I.E[0])
+        L.slar_moments(ws.grid, b.state[q], M, ws)
+        L.slar_poisson(ws.grid, M[0], I.n_i, None, E, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(M, I.M), q
+        assert torch.equal(E, E0[q]) and torch.equal(E, I.E[1]), q
+
+
 def test_batch_step_matches_oracle():
     problems = SI.batched_instances(6, sizes=(8, 12), sizes_1d=(24, 32))
     b, pr = _solver(problems)
