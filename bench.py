@@ -64,7 +64,7 @@ def measured_traffic():
 
 
 BATCH_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_batched_cross_64.md")
-BATCH_SOURCES = ("batch.hip", "aca.h", "frame_sampler.h", "sl_device.h")
+BATCH_SOURCES = ("batch_kernels.h", "aca.h", "frame_sampler.h", "sl_device.h")
 
 
 def measured_batch_traffic():
@@ -110,6 +110,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="default workload: leave out the batched-instances leg of the line")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--no-other-precision", action="store_true",
+                    help="skip the short run of the step with the other table precision")
+    ap.add_argument("--no-samplers", action="store_true", help="skip the r = 60 entry-sampler records")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one device copy of this size (for counter calibration)")
     return ap.parse_args()
@@ -402,75 +405,93 @@ def nested_main(args):
     return 0
 
 
-def samplers_main(args):
-    """Entry-evaluation microbenchmark on the 128^4 grid: a random HT of
-    uniform rank r (orthonormal leaves, Gaussian transfer tensors, seed
-    1000 + r), 2^20 uniform random requests (seed 1234), the first sub-flow
-    of the strong-Landau workload (RK4 frozen-field feet, tau = dt / 3).
-    For each r and precision it times the leaf-to-root HT contraction
-    (slar_ht_sample, matrix cores) and the frame-table sampler
-    (slar_frame_sample; its per-call FP64 -> table copy included) with HIP
-    events on the launch stream, and prints one JSON line per case:
-    entries/s, and the contraction's flops against the dense matrix-core
-    peak of its dtype, or the tables' algorithmic gather bytes (mostly L2
-    hits: 2 x 2.4 MB tables at r = 60) per second."""
+def sampler_case(r, steps, p=None, E=None, idx=None):
+    """Entry-evaluation rates of a random HT of uniform rank r on the 128^4
+    grid (orthonormal leaves, Gaussian transfer tensors, seed 1000 + r),
+    2^20 uniform random requests (seed 1234), the first sub-flow of the
+    strong-Landau workload: the leaf-to-root contraction (slar_ht_sample,
+    matrix cores) and the frame-table sampler (slar_frame_sample, its FP64
+    -> table copy included), FP32 and FP64, timed with HIP events on the
+    launch stream.  Returns one record per (sampler, dtype)."""
     import torch
     import slar_inputs as SI
     from paper_2606_29027_amd import lib as L
     from paper_2606_29027_amd.solver import Solver
-    p = SI.config("stronglandau2d", n=128)
-    s0 = Solver(p, L.F64)                  # field of the initial state, by the library's Poisson solve
-    s0.set_initial(SI.initial_ht(p))
-    E = s0.efield(s0.state, s0.E[0]).clone()
-    del s0
+    if p is None:
+        p = SI.config("stronglandau2d", n=128)
+    if E is None:
+        s0 = Solver(p, L.F64)              # field of the initial state, by the library's Poisson solve
+        s0.set_initial(SI.initial_ht(p))
+        E = s0.efield(s0.state, s0.E[0]).clone()
+        del s0
+    S = 1 << 20
+    if idx is None:
+        idx = torch.as_tensor(SI.random_requests(p.n, S, seed=1234), dtype=torch.int32, device="cuda")
     g = L.make_grid(p)
     ws = L.Workspace(g, 64)
-    S = 1 << 20
-    idx = torch.as_tensor(SI.random_requests(p.n, S, seed=1234), dtype=torch.int32, device="cuda")
     adv = L.make_adv(2, p.dt / 3.0, 1.0, E)
     Nx = 128 * 128
-    peak = {"f32": MFMA_PEAK_TFLOPS["f32"], "f64": MFMA_PEAK_TFLOPS["f64"]}
 
     def timed(fn):
         for _ in range(2):
             fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(args.steps):
+        for _ in range(steps):
             fn()
         e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3 / args.steps
+        return e0.elapsed_time(e1) / 1e3 / steps
 
+    F = SI.random_ht(4, p.n, (r,) * 6, seed=1000 + r)
+    T64 = {"leaves": [torch.as_tensor(U, device="cuda") for U in F["leaves"]],
+           "root": torch.as_tensor(F["root"], device="cuda"),
+           "B12": torch.as_tensor(F["B12"].reshape(r * r, r), device="cuda"),
+           "B34": torch.as_tensor(F["B34"].reshape(r * r, r), device="cuda")}
+    H64 = L.make_ht(T64, 4, L.F64)
+    X = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
+    P = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
+    Fr = L.slar_frames_from_ht(g, H64, L.frames(X, P, 0), ws)
+    out_recs = []
+    for prec in ("f32", "f64"):
+        tdt = torch.float32 if prec == "f32" else torch.float64
+        T = {k: ([x.to(tdt) for x in v] if isinstance(v, list) else v.to(tdt)) for k, v in T64.items()}
+        H = L.make_ht(T, 4, L.F32 if prec == "f32" else L.F64)
+        out = torch.zeros(S, dtype=tdt, device="cuda")
+        dt = timed(lambda: L.slar_ht_sample(g, H, adv, idx, out))
+        flops = 2.0 * (4 * 3 * r + 2 * r ** 3 + r * r) * S
+        out_recs.append({"sampler": "ht_contraction", "dtype": prec, "rank": r, "entries": S,
+                         "entries_per_s": S / dt, "ms": 1e3 * dt, "tflops": flops / dt / 1e12,
+                         "frac_of_mfma_peak": flops / dt / 1e12 / MFMA_PEAK_TFLOPS[prec]})
+        outd = torch.zeros(S, dtype=torch.float64, device="cuda")
+        dtc = L.F32 if prec == "f32" else L.F64
+        dt = timed(lambda: L.slar_frame_sample(g, Fr, adv, dtc, idx, outd, ws))
+        ldt = (r + 3) & ~3
+        by = S * (2.0 * 9 * ldt * (4 if prec == "f32" else 8) + 8 + 16)
+        out_recs.append({"sampler": "frame_tables", "dtype": prec, "rank": r, "entries": S,
+                         "entries_per_s": S / dt, "ms": 1e3 * dt, "gather_GBps": by / dt / 1e9})
+    return out_recs
+
+
+def samplers_main(args):
+    """Entry-evaluation microbenchmark on the 128^4 grid (sampler_case) for
+    ranks 8 to 60; prints one JSON line per case: entries/s, and the
+    contraction's flops against the dense matrix-core peak of its dtype, or
+    the tables' algorithmic gather bytes (mostly L2 hits: 2 x 2.4 MB tables
+    at r = 60) per second."""
+    import torch
+    import slar_inputs as SI
+    from paper_2606_29027_amd import lib as L
+    from paper_2606_29027_amd.solver import Solver
+    p = SI.config("stronglandau2d", n=128)
+    s0 = Solver(p, L.F64)
+    s0.set_initial(SI.initial_ht(p))
+    E = s0.efield(s0.state, s0.E[0]).clone()
+    del s0
+    idx = torch.as_tensor(SI.random_requests(p.n, 1 << 20, seed=1234), dtype=torch.int32, device="cuda")
     for r in (8, 16, 24, 32, 40, 48, 60):
-        F = SI.random_ht(4, p.n, (r,) * 6, seed=1000 + r)
-        T64 = {"leaves": [torch.as_tensor(U, device="cuda") for U in F["leaves"]],
-               "root": torch.as_tensor(F["root"], device="cuda"),
-               "B12": torch.as_tensor(F["B12"].reshape(r * r, r), device="cuda"),
-               "B34": torch.as_tensor(F["B34"].reshape(r * r, r), device="cuda")}
-        H64 = L.make_ht(T64, 4, L.F64)
-        X = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
-        P = torch.zeros(Nx, 72, dtype=torch.float64, device="cuda")
-        Fr = L.slar_frames_from_ht(g, H64, L.frames(X, P, 0), ws)
-        for prec in ("f32", "f64"):
-            tdt = torch.float32 if prec == "f32" else torch.float64
-            T = {k: ([x.to(tdt) for x in v] if isinstance(v, list) else v.to(tdt)) for k, v in T64.items()}
-            H = L.make_ht(T, 4, L.F32 if prec == "f32" else L.F64)
-            out = torch.zeros(S, dtype=tdt, device="cuda")
-            dt = timed(lambda: L.slar_ht_sample(g, H, adv, idx, out))
-            flops = 2.0 * (4 * 3 * r + 2 * r ** 3 + r * r) * S
-            print(json.dumps({"sampler": "ht_contraction", "dtype": prec, "rank": r, "entries": S,
-                              "entries_per_s": S / dt, "ms": 1e3 * dt,
-                              "tflops": flops / dt / 1e12,
-                              "frac_of_mfma_peak": flops / dt / 1e12 / peak[prec]}), flush=True)
-            outd = torch.zeros(S, dtype=torch.float64, device="cuda")
-            dtc = L.F32 if prec == "f32" else L.F64
-            dt = timed(lambda: L.slar_frame_sample(g, Fr, adv, dtc, idx, outd, ws))
-            ldt = (r + 3) & ~3
-            by = S * (2.0 * 9 * ldt * (4 if prec == "f32" else 8) + 8 + 16)
-            print(json.dumps({"sampler": "frame_tables", "dtype": prec, "rank": r, "entries": S,
-                              "entries_per_s": S / dt, "ms": 1e3 * dt,
-                              "gather_GBps": by / dt / 1e9}), flush=True)
+        for rec in sampler_case(r, args.steps, p, E, idx):
+            print(json.dumps(rec), flush=True)
 
 
 def main():
@@ -501,15 +522,14 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    runs = {}
-    for name in [v for v in args.variants.split(",") if v]:
+    def run_variant(name, vprec, steps, warmup):
         cnn = None
         if name == "learned":
             from paper_2606_29027_amd import cnn as CNN
             cnn = CNN.load_trained(p)
-        s = Solver(p, prec, probes=probes, precond=pc_code[name], cnn=cnn, strict=False)
+        s = Solver(p, vprec, probes=probes, precond=pc_code[name], cnn=cnn, strict=False)
         s.set_initial(SI.initial_ht(p))
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             s.step()
         torch.cuda.synchronize()
         n0 = len(s.stats)
@@ -521,7 +541,7 @@ def main():
         s.tphase = {k: 0.0 for k in s.tphase}
         step_ms = []
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             ts = time.perf_counter()
             infos.append(s.step())          # ends with a device synchronisation
             step_ms.append(1e3 * (time.perf_counter() - ts))
@@ -539,19 +559,24 @@ def main():
         n_it = sum(st["iters"] for st in s.stats[n0:])
         per_it = (tim["row_ms"] / max(tim["row_launches"], 1) + tim["col_ms"] / max(tim["col_launches"], 1))
         kern_s = n_it * per_it * 1e-3
-        phase = {k: 1e3 * v / args.steps for k, v in s.tphase.items()}
-        phase["other"] = 1e3 * elapsed / args.steps - sum(phase.values())
-        runs[name] = {"value": samples / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
-                      "median_ms_per_step": float(np.median(step_ms)),
-                      "converged_steps": nconv, "timed_steps": len(infos),
-                      "t_end": round((args.warmup + args.steps) * p.dt, 6),
-                      "samples_per_step": samples / args.steps,
-                      "entries_per_s_cross": samples / (s.tphase["cross"] or float("nan")),
-                      "entries_per_s_fiber_kernels": samples / kern_s if kern_s > 0 else None,
-                      "phase_ms_per_step": phase,
-                      "newton_krylov": [[i.get("newton"), i.get("krylov")] for i in infos],
-                      "ranks": [st["ranks"] for st in s.stats[-3:]], "timing": tim}
+        phase = {k: 1e3 * v / steps for k, v in s.tphase.items()}
+        phase["other"] = 1e3 * elapsed / steps - sum(phase.values())
+        rec = {"value": samples / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+               "median_ms_per_step": float(np.median(step_ms)),
+               "converged_steps": nconv, "timed_steps": len(infos),
+               "t_end": round((warmup + steps) * p.dt, 6),
+               "samples_per_step": samples / steps,
+               "entries_per_s_cross": samples / (s.tphase["cross"] or float("nan")),
+               "entries_per_s_fiber_kernels": samples / kern_s if kern_s > 0 else None,
+               "phase_ms_per_step": phase,
+               "newton_krylov": [[i.get("newton"), i.get("krylov")] for i in infos],
+               "ranks": [st["ranks"] for st in s.stats[-3:]], "timing": tim}
         del s
+        return rec
+
+    runs = {}
+    for name in [v for v in args.variants.split(",") if v]:
+        runs[name] = run_variant(name, prec, args.steps, args.warmup)
     head = [v for v in args.variants.split(",") if v][-1]
     H = runs[head]
     tim = H.pop("timing")
@@ -598,6 +623,21 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not args.no_other_precision:
+        # the same step with the other table precision (the headline macro
+        # solver), a shorter run
+        other = L.F64 if prec == L.F32 else L.F32
+        o = run_variant(head, other, 3, 2)
+        o.pop("timing", None)
+        o["dtype"] = "f64" if other == L.F64 else "f32"
+        out["config"]["other_precision"] = {k: o[k] for k in ("dtype", "value", "ms_per_step", "median_ms_per_step",
+                                                              "converged_steps", "timed_steps", "t_end",
+                                                              "samples_per_step", "phase_ms_per_step")}
+    if not args.no_samplers:
+        # the entry samplers at the workload's rank cap (r = 60): the
+        # paper's leaf-to-root contraction on the matrix cores and the
+        # frame-table gathers, FP32 and FP64
+        out["config"]["samplers_r60"] = sampler_case(60, 10)
     if not args.no_batched:
         # the batched-instances workload, measured in the same run
         b = batched_run(args, args.batched_steps, 1, None if args.no_cpu_baseline else args.cpu_seconds / 3.0)

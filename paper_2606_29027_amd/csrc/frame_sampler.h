@@ -84,62 +84,45 @@ template <> struct Vec4<double> {
 };
 
 // Phase 2: values of the prepared samples [0, ns) into L.val (FP64).
-// Tables are [rows][ld] with ld % 4 == 0 and zero columns beyond r.  With
-// FP32 tables a team keeps the gathers of two samples in flight (all their
-// row loads issued before the first FMA), so a block's 64 samples take two
-// rounds of L2 latency instead of four; FP64 tables keep one sample per
-// pass (twice the registers per row).  The team's partial dot products are
-// summed with DPP row exchanges.
+// Tables are [rows][ld] with ld % 4 == 0 and zero columns beyond r.  A team
+// takes one sample per pass: all its row loads are issued before the first
+// FMA.  (Two samples in flight per team for FP32 tables doubled the
+// registers and lost more occupancy than it saved in L2 latency, both in
+// the cross approximation's fibers and for scattered requests.)  The
+// team's partial dot products are summed with DPP row exchanges.
 template <typename T, int W, int DX, int TEAM = 16>
 __device__ __forceinline__ void fs_evaluate(const T* __restrict__ X, const T* __restrict__ P,
                                             int ld, int r, FsLds<W, DX>& L, int ns) {
   static_assert(TEAM == 4 || TEAM == 8 || TEAM == 16, "team width");
   constexpr int RX = FsLds<W, DX>::RX;
   constexpr int NT = FS_THREADS / TEAM;
-  constexpr int UNR = (sizeof(T) == 4) ? 2 : 1;
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
-  for (int s0 = team; s0 < ns; s0 += UNR * NT) {
-    int sm[UNR];
-    bool ok[UNR];
-    T acc[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      ok[u] = s0 + u * NT < ns;
-      sm[u] = ok[u] ? s0 + u * NT : s0;   // a valid sample's rows; result dropped
-      acc[u] = 0;
-    }
+  for (int s = team; s < ns; s += NT) {
+    T acc = 0;
     for (int c0 = lane * 4; c0 < r; c0 += 4 * TEAM) {
-      T vx[UNR][RX][4], vp[UNR][RX][4];
+      T vx[RX][4], vp[RX][4];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u)
-#pragma unroll
-        for (int b = 0; b < RX; ++b) {
-          Vec4<T>::load(X + (size_t)L.xrow[sm[u]][b] * ld + c0, vx[u][b]);
-          Vec4<T>::load(P + (size_t)L.vrow[sm[u]][b] * ld + c0, vp[u][b]);
-        }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        T y[4] = {0, 0, 0, 0}, z[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int b = 0; b < RX; ++b) {
-          const T wx = (T)L.xw[sm[u]][b];
-          const T wv = (T)L.vw[sm[u]][b];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            y[e] += wx * vx[u][b][e];
-            z[e] += wv * vp[u][b][e];
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[u] += y[e] * z[e];
+      for (int b = 0; b < RX; ++b) {
+        Vec4<T>::load(X + (size_t)L.xrow[s][b] * ld + c0, vx[b]);
+        Vec4<T>::load(P + (size_t)L.vrow[s][b] * ld + c0, vp[b]);
       }
-    }
+      T y[4] = {0, 0, 0, 0}, z[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const T tot = group_sum<TEAM>(acc[u]);
-      if (lane == 0 && ok[u]) L.val[sm[u]] = (double)tot;
+      for (int b = 0; b < RX; ++b) {
+        const T wx = (T)L.xw[s][b];
+        const T wv = (T)L.vw[s][b];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          y[e] += wx * vx[b][e];
+          z[e] += wv * vp[b][e];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc += y[e] * z[e];
     }
+    const T tot = group_sum<TEAM>(acc);
+    if (lane == 0) L.val[s] = (double)tot;
   }
 }
 
