@@ -125,8 +125,23 @@ typedef struct slar_workspace slar_workspace;
 const char* slar_status_str(slar_status s);
 
 /* Allocates every device buffer the calls below need for grid g and rank
- * cap rmax (<= 64), once.  *ws is written on success.                       */
+ * cap rmax (<= 64), once.  *ws is written on success.  No call below
+ * allocates device memory (the batched, nested and CNN objects have their
+ * own create calls).                                                        */
 slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspace** ws);
+
+/* Device bytes of a workspace for grid g and rank cap rmax: *bytes is
+ * written.  Pure host arithmetic (no device call).                         */
+slar_status slar_workspace_bytes(const slar_grid* g, int32_t rmax, size_t* bytes);
+
+/* The same workspace with its device buffers carved from the caller's
+ * device memory `work` (256-byte aligned, work_bytes >= the size
+ * slar_workspace_bytes gives; SLAR_E_NOMEM if smaller, checked before any
+ * device call).  The caller keeps `work` alive and unchanged by others
+ * until slar_workspace_destroy, which does not free it.  The library still
+ * creates its own pinned host words, events and one auxiliary stream.      */
+slar_status slar_workspace_create_in(const slar_grid* g, int32_t rmax, void* work, size_t work_bytes,
+                                     slar_workspace** ws);
 slar_status slar_workspace_destroy(slar_workspace* ws);
 
 /* SL-FD update at requested grid points, evaluated directly on an HT tensor

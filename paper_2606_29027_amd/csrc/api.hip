@@ -95,16 +95,85 @@ const char* slar_status_str(slar_status s) {
   return "unknown status";
 }
 
+}  // extern "C"
+
+// Sizes of a workspace's scratch for grid g and rank cap rmax.
+static void ws_sizes(Workspace& ws, const slar_grid& g, int rmax) {
+  ws.grid = g;
+  ws.G = make_grid(g);
+  ws.rmax = rmax;
+  const GridDev& G = ws.G;
+  const size_t K = SLAR_KMAX;
+  ws.ld32 = SLAR_KMAX;
+  ws.dwork_elems = std::max({(size_t)2 * (G.nx + G.nv) * K + 64,
+                             (size_t)SLAR_NMAX * K * K + (size_t)G.nv * K + 64,
+                             (size_t)SLAR_NMAX * SLAR_NMAX * SLAR_NMAX + 64,
+                             (size_t)(G.nx / 256 + 2) * K * 9 + (size_t)(G.nx / 512 + 2) * K * K,
+                             (size_t)(SLAR_NMAX * K / 512 + 2) * SLAR_NMAX * SLAR_NMAX});
+  ws.small_elems = truncate_scratch_elems(G) + 8192;
+  ws.cbuf_elems = cbuf_elems_for(G.nx);
+  ws.lm_elems = lm_layout(G).total;
+  ws.kry_elems = kry_elems_for(G.nx, G.dv + 2, KRY_RESTART);
+}
+
+// Every device buffer of a workspace, in a fixed order: fn(slot, bytes).
+template <class F>
+static void ws_buffers(Workspace& ws, F&& fn) {
+  const GridDev& G = ws.G;
+  const int nm = nmom_of(G.dv);
+  fn((void**)&ws.Eeff, sizeof(double) * G.dx * G.nx);
+  fn((void**)&ws.X32, sizeof(float) * G.nx * ws.ld32);
+  fn((void**)&ws.P32, sizeof(float) * G.nv * ws.ld32);
+  fn(&ws.aca_ctl, aca_ctl_bytes());
+  fn((void**)&ws.aca_part, sizeof(double) * aca_part_elems());
+  fn((void**)&ws.aca_piv, sizeof(int) * 2 * SLAR_CROSS_KMAX);
+  fn((void**)&ws.used, (size_t)G.nx);
+  fn((void**)&ws.dwork, sizeof(double) * ws.dwork_elems);
+  fn((void**)&ws.small, sizeof(double) * ws.small_elems);
+  fn((void**)&ws.tw[0], sizeof(double) * 2 * SLAR_NLINE);
+  fn((void**)&ws.tw[1], sizeof(double) * 2 * SLAR_NLINE);
+  fn((void**)&ws.cbuf, sizeof(double) * ws.cbuf_elems);
+  fn((void**)&ws.psi, sizeof(double) * G.nv * nm);
+  fn((void**)&ws.lm, sizeof(double) * ws.lm_elems);
+  fn((void**)&ws.kry, sizeof(double) * ws.kry_elems);
+  if (G.d == 4) {
+    const size_t NT = 16384, NL = nest_list_elems();
+    fn((void**)&ws.nest_U, sizeof(double) * 64 * NT);
+    fn((void**)&ws.nest_V, sizeof(double) * 64 * NT);
+    fn((void**)&ws.nest_used, NT);
+    fn((void**)&ws.nest_rowtab, sizeof(int) * 4 * NT);
+    fn((void**)&ws.nest_coltab, sizeof(int) * 4 * NT);
+    fn((void**)&ws.nest_probes, sizeof(int) * 2 * 128);
+    fn((void**)&ws.nest_piv, sizeof(int) * 2 * SLAR_KMAX);
+    fn((void**)&ws.nest_idx, sizeof(int) * 4 * NL);
+    fn((void**)&ws.nest_vals, sizeof(double) * NL);
+    fn((void**)&ws.nest_small, sizeof(double) * 6 * 64 * 64);
+    fn((void**)&ws.nest_flag, sizeof(int) * 4);
+    fn((void**)&ws.nest_fX, sizeof(double) * G.nx * SLAR_KMAX);
+    fn((void**)&ws.nest_fP, sizeof(double) * G.nv * SLAR_KMAX);
+    fn((void**)&ws.nest_X64, sizeof(double) * G.nx * SLAR_KMAX);
+    fn((void**)&ws.nest_P64, sizeof(double) * G.nv * SLAR_KMAX);
+  }
+}
+
+static size_t ws_align(size_t b) { return (std::max(b, (size_t)256) + 255) & ~(size_t)255; }
+
+extern "C" {
+
+slar_status slar_workspace_bytes(const slar_grid* g, int32_t rmax, size_t* bytes) {
+  if (!bytes || !grid_ok(g) || rmax < 1 || rmax > 64) return SLAR_E_INVAL;
+  Workspace ws;
+  ws_sizes(ws, *g, rmax);
+  size_t total = 0;
+  ws_buffers(ws, [&](void**, size_t b) { total += ws_align(b); });
+  *bytes = total;
+  return SLAR_OK;
+}
+
 slar_status slar_workspace_destroy(slar_workspace* w) {
   if (!w) return SLAR_OK;
   Workspace& ws = w->w;
-  void* dev[] = {ws.Eeff, ws.X32, ws.P32, ws.aca_ctl, ws.aca_part, ws.aca_piv, ws.used, ws.resid, ws.dwork,
-                 ws.small, ws.ismall, ws.tw[0], ws.tw[1], ws.cbuf, ws.psi, ws.lm, ws.kry,
-                 ws.nest_U, ws.nest_V, ws.nest_used, ws.nest_rowtab, ws.nest_coltab, ws.nest_probes,
-                 ws.nest_piv, ws.nest_idx, ws.nest_vals, ws.nest_small, ws.nest_flag, ws.nest_fX,
-                 ws.nest_fP, ws.nest_X64, ws.nest_P64};
-  for (void* p : dev)
-    if (p) (void)hipFree(p);
+  if (ws.owns_device) ws_buffers(ws, [](void** p, size_t) { if (*p) (void)hipFree(*p); });
   for (hipEvent_t e : ws.events) (void)hipEventDestroy(e);
   if (ws.ev_fork) (void)hipEventDestroy(ws.ev_fork);
   if (ws.ev_join) (void)hipEventDestroy(ws.ev_join);
@@ -121,66 +190,34 @@ slar_status slar_workspace_destroy(slar_workspace* w) {
   return SLAR_OK;
 }
 
-slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspace** out) {
-  if (!out || !grid_ok(g) || rmax < 1 || rmax > 64) return SLAR_E_INVAL;
+// work == nullptr: the library allocates the device buffers; else they are
+// carved from the caller's work (work_bytes >= slar_workspace_bytes).
+static slar_status ws_create(const slar_grid* g, int32_t rmax, void* work, size_t work_bytes,
+                             slar_workspace** out) {
   *out = nullptr;
+  size_t need = 0;
+  if (work) {
+    if (slar_workspace_bytes(g, rmax, &need) != SLAR_OK) return SLAR_E_INVAL;
+    if (work_bytes < need || ((uintptr_t)work & 255) != 0) return work_bytes < need ? SLAR_E_NOMEM : SLAR_E_INVAL;
+  }
   slar_workspace* w = new (std::nothrow) slar_workspace();
   if (!w) return SLAR_E_NOMEM;
   Workspace& ws = w->w;
-  ws.grid = *g;
-  ws.G = make_grid(*g);
-  ws.rmax = rmax;
+  ws_sizes(ws, *g, rmax);
   const GridDev& G = ws.G;
-  const size_t K = SLAR_KMAX;
-  ws.ld32 = SLAR_KMAX;
-  ws.dwork_elems = std::max({(size_t)2 * (G.nx + G.nv) * K + 64,
-                             (size_t)SLAR_NMAX * K * K + (size_t)G.nv * K + 64,
-                             (size_t)SLAR_NMAX * SLAR_NMAX * SLAR_NMAX + 64,
-                             (size_t)(G.nx / 256 + 2) * K * 9 + (size_t)(G.nx / 512 + 2) * K * K,
-                             (size_t)(SLAR_NMAX * K / 512 + 2) * SLAR_NMAX * SLAR_NMAX});
-  ws.small_elems = truncate_scratch_elems(G) + 8192;
-  ws.cbuf_elems = cbuf_elems_for(G.nx);
-  const int nm = nmom_of(G.dv);
-  const LmLayout L = lm_layout(G);
-  ws.lm_elems = L.total;
-  ws.kry_elems = kry_elems_for(G.nx, G.dv + 2, KRY_RESTART);
   bool ok = true;
-  auto dalloc = [&](void** p, size_t bytes) {
-    if (!ok) return;
-    if (hipMalloc(p, std::max(bytes, (size_t)256)) != hipSuccess) ok = false;
-  };
-  dalloc((void**)&ws.Eeff, sizeof(double) * G.dx * G.nx);
-  dalloc((void**)&ws.X32, sizeof(float) * G.nx * ws.ld32);
-  dalloc((void**)&ws.P32, sizeof(float) * G.nv * ws.ld32);
-  dalloc(&ws.aca_ctl, aca_ctl_bytes());
-  dalloc((void**)&ws.aca_part, sizeof(double) * aca_part_elems());
-  dalloc((void**)&ws.aca_piv, sizeof(int) * 2 * SLAR_CROSS_KMAX);
-  dalloc((void**)&ws.used, G.nx);
-  dalloc((void**)&ws.dwork, sizeof(double) * ws.dwork_elems);
-  dalloc((void**)&ws.small, sizeof(double) * ws.small_elems);
-  dalloc((void**)&ws.tw[0], sizeof(double) * 2 * SLAR_NLINE);
-  dalloc((void**)&ws.tw[1], sizeof(double) * 2 * SLAR_NLINE);
-  dalloc((void**)&ws.cbuf, sizeof(double) * ws.cbuf_elems);
-  dalloc((void**)&ws.psi, sizeof(double) * G.nv * nm);
-  dalloc((void**)&ws.lm, sizeof(double) * ws.lm_elems);
-  dalloc((void**)&ws.kry, sizeof(double) * ws.kry_elems);
-  if (G.d == 4) {
-    const size_t NT = 16384, NL = nest_list_elems();
-    dalloc((void**)&ws.nest_U, sizeof(double) * 64 * NT);
-    dalloc((void**)&ws.nest_V, sizeof(double) * 64 * NT);
-    dalloc((void**)&ws.nest_used, NT);
-    dalloc((void**)&ws.nest_rowtab, sizeof(int) * 4 * NT);
-    dalloc((void**)&ws.nest_coltab, sizeof(int) * 4 * NT);
-    dalloc((void**)&ws.nest_probes, sizeof(int) * 2 * 128);
-    dalloc((void**)&ws.nest_piv, sizeof(int) * 2 * SLAR_KMAX);
-    dalloc((void**)&ws.nest_idx, sizeof(int) * 4 * NL);
-    dalloc((void**)&ws.nest_vals, sizeof(double) * NL);
-    dalloc((void**)&ws.nest_small, sizeof(double) * 6 * 64 * 64);
-    dalloc((void**)&ws.nest_flag, sizeof(int) * 4);
-    dalloc((void**)&ws.nest_fX, sizeof(double) * G.nx * SLAR_KMAX);
-    dalloc((void**)&ws.nest_fP, sizeof(double) * G.nv * SLAR_KMAX);
-    dalloc((void**)&ws.nest_X64, sizeof(double) * G.nx * SLAR_KMAX);
-    dalloc((void**)&ws.nest_P64, sizeof(double) * G.nv * SLAR_KMAX);
+  if (work) {
+    ws.owns_device = false;
+    char* p = (char*)work;
+    ws_buffers(ws, [&](void** slot, size_t b) {
+      *slot = p;
+      p += ws_align(b);
+    });
+  } else {
+    ws.owns_device = true;
+    ws_buffers(ws, [&](void** slot, size_t b) {
+      if (ok && hipMalloc(slot, std::max(b, (size_t)256)) != hipSuccess) ok = false;
+    });
   }
   if (ok && hipHostMalloc(&ws.aca_ctl_host, 3 * aca_ctl_bytes(), 0) != hipSuccess) ok = false;
   for (hipEvent_t& e : ws.poll_ev)
@@ -209,6 +246,17 @@ slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspa
   }
   *out = w;
   return SLAR_OK;
+}
+
+slar_status slar_workspace_create(const slar_grid* g, int32_t rmax, slar_workspace** out) {
+  if (!out || !grid_ok(g) || rmax < 1 || rmax > 64) return SLAR_E_INVAL;
+  return ws_create(g, rmax, nullptr, 0, out);
+}
+
+slar_status slar_workspace_create_in(const slar_grid* g, int32_t rmax, void* work, size_t work_bytes,
+                                     slar_workspace** out) {
+  if (!out || !work || !grid_ok(g) || rmax < 1 || rmax > 64) return SLAR_E_INVAL;
+  return ws_create(g, rmax, work, work_bytes, out);
 }
 
 slar_status slar_ht_sample(const slar_grid* g, const slar_ht* F, const slar_adv* a, int64_t n,

@@ -37,6 +37,7 @@ struct Workspace {
   slar_grid grid;
   GridDev G;
   int rmax;
+  bool owns_device = true;       // device buffers allocated here (else the caller's work)
   // sampling
   double* Eeff = nullptr;        // [dx][Nx]
   float* X32 = nullptr;          // [Nx][LD32]

@@ -19,7 +19,8 @@ SLAR_OK, SLAR_E_INVAL, SLAR_E_NOMEM, SLAR_E_RANK_CAP, SLAR_E_NOCONV, SLAR_E_NUME
 F32, F64 = 0, 1
 
 EXPORTS = (
-    "slar_status_str", "slar_workspace_create", "slar_workspace_destroy", "slar_ht_sample",
+    "slar_status_str", "slar_workspace_create", "slar_workspace_bytes", "slar_workspace_create_in",
+    "slar_workspace_destroy", "slar_ht_sample",
     "slar_frames_from_ht", "slar_frame_sample", "slar_cross_update", "slar_nested_cross", "slar_truncate",
     "slar_moments", "slar_poisson", "slar_conserved", "slar_lomac_prepare", "slar_macro_solve",
     "slar_lomac_project", "slar_cnn_create", "slar_cnn_destroy", "slar_cnn_nparams",
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH):
     sig = {
         "slar_status_str": (C.c_char_p, [i32]),
         "slar_workspace_create": (i32, [P(Grid), i32, P(vp)]),
+        "slar_workspace_bytes": (i32, [P(Grid), i32, P(C.c_size_t)]),
+        "slar_workspace_create_in": (i32, [P(Grid), i32, vp, C.c_size_t, P(vp)]),
         "slar_workspace_destroy": (i32, [vp]),
         "slar_ht_sample": (i32, [P(Grid), P(HT), P(Adv), i64, vp, vp, vp]),
         "slar_frames_from_ht": (i32, [P(Grid), P(HT), P(Frames), vp, vp]),
@@ -180,11 +183,27 @@ def make_grid(p) -> Grid:
     return g
 
 
+def slar_workspace_bytes(grid: Grid, rmax: int) -> int:
+    n = C.c_size_t(0)
+    _check(load().slar_workspace_bytes(C.byref(grid), int(rmax), C.byref(n)), "slar_workspace_bytes")
+    return int(n.value)
+
+
 class Workspace:
-    def __init__(self, grid: Grid, rmax: int):
+    """Library workspace; with ``work`` (a device tensor of at least
+    slar_workspace_bytes bytes, 256-byte aligned) its device buffers are
+    carved from that memory, which the object keeps alive."""
+
+    def __init__(self, grid: Grid, rmax: int, work=None):
         self.grid = grid
         h = C.c_void_p()
-        _check(load().slar_workspace_create(C.byref(grid), int(rmax), C.byref(h)), "slar_workspace_create")
+        if work is None:
+            _check(load().slar_workspace_create(C.byref(grid), int(rmax), C.byref(h)), "slar_workspace_create")
+        else:
+            nbytes = work.numel() * work.element_size()
+            _check(load().slar_workspace_create_in(C.byref(grid), int(rmax), C.c_void_p(work.data_ptr()),
+                                                   C.c_size_t(nbytes), C.byref(h)), "slar_workspace_create_in")
+        self._work = work
         self.h = h
 
     def __del__(self):

@@ -33,10 +33,12 @@ CCAP = 128         # cross-approximation terms
 class Solver:
     def __init__(self, p, precision: int = L.F64, probes=None, delta: float = 1e-12,
                  precond: int = 0, cnn=None, newton_tol: float = 1e-10, krylov_tol: float = 1e-4,
-                 strict: bool = True):
+                 strict: bool = True, work=None):
         self.p = p
         self.grid = L.make_grid(p)
-        self.ws = L.Workspace(self.grid, min(p.rmax, RCAP))
+        # work: optional caller device memory for the library workspace
+        # (slar_workspace_create_in), at least slar_workspace_bytes long
+        self.ws = L.Workspace(self.grid, min(p.rmax, RCAP), work=work)
         self.prec = precision
         # the truncation's leaf refinement buys FP64-level agreement; with FP32
         # frame tables the sampling error is far above the Gram accuracy

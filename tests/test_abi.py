@@ -87,6 +87,29 @@ int main(void) {
 """
 
 
+@needs_lib
+def test_workspace_bytes_and_caller_memory_checks_without_gpu():
+    """slar_workspace_bytes is host arithmetic: it grows with the grid, and
+    slar_workspace_create_in rejects a null, misaligned or too small buffer
+    before any device call (a host buffer stands in; it is never written)."""
+    import slar_inputs as SI
+    from paper_2606_29027_amd import lib as L
+    lib = L.load()
+    small = L.make_grid(SI.config("landau2d", n=16))
+    big = L.make_grid(SI.config("stronglandau2d"))
+    b16, b128 = L.slar_workspace_bytes(small, 40), L.slar_workspace_bytes(big, 60)
+    assert 0 < b16 < b128 and b16 % 256 == 0 and b128 % 256 == 0
+    n = C.c_size_t(0)
+    assert lib.slar_workspace_bytes(C.byref(small), 65, C.byref(n)) == L.SLAR_E_INVAL
+    h = C.c_void_p()
+    buf = (C.c_uint8 * 4096)()
+    addr = (C.addressof(buf) + 255) & ~255
+    assert lib.slar_workspace_create_in(C.byref(small), 40, None, b16, C.byref(h)) == L.SLAR_E_INVAL
+    assert lib.slar_workspace_create_in(C.byref(small), 40, C.c_void_p(addr), 2048, C.byref(h)) == L.SLAR_E_NOMEM
+    assert lib.slar_workspace_create_in(C.byref(small), 40, C.c_void_p(addr + 8), b16, C.byref(h)) == L.SLAR_E_INVAL
+    assert not h.value
+
+
 def test_ctypes_struct_layout_matches_header(tmp_path):
     gcc = shutil.which("gcc")
     inc = "/opt/rocm/include"
