@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--nested-config", default="stronglandau2d",
                     help="2D2V workload whose state the nested workload compares the samplers on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nested-dtype", choices=["auto", "f32", "f64"], default="auto",
+                    help="frame-table precision of the nested workload")
     ap.add_argument("--cpu-seconds", type=float, default=18.0)
     ap.add_argument("--variants", default="plain,spectral,learned",
                     help="comma list of macro solvers to time: plain, spectral, learned "
@@ -334,7 +336,8 @@ def nested_main(args):
     step (RK4 frozen-field feet, tau = dt / 3, the state's own field).
     HTACA (slar_cross_update, rank cap 60) and the nested cross
     (slar_nested_cross, rank cap 64, 64 seeded probes) both sample through
-    FP32 frame tables; each is timed with events on the stream (three runs
+    the same frame tables (--nested-dtype; auto: FP64 below tol 1e-5, where
+    FP32 table noise exceeds the probe threshold, else FP32); each is timed with events on the stream (three runs
     after one warm-up, the median reported), and its approximation is
     compared with the exact update (FP64 tables) at 4096 seeded random
     entries.  One JSON line."""
@@ -379,8 +382,9 @@ def nested_main(args):
             ms.append(e0.elapsed_time(e1))
         return sorted(ms)[1], out
 
-    ms_h, (lr, ih, sth) = timed(lambda: L.slar_cross_update(g, src, adv, L.F32, p.tol, 60, s.probes, s.U, s.V, ws))
-    ms_n, (inn, stn) = timed(lambda: L.slar_nested_cross(g, src, adv, L.F32, p.tol, kmax, probes4, seed, H, ws))
+    dt = {"f32": L.F32, "f64": L.F64}.get(args.nested_dtype, L.F64 if p.tol < 1e-5 else L.F32)
+    ms_h, (lr, ih, sth) = timed(lambda: L.slar_cross_update(g, src, adv, dt, p.tol, 60, s.probes, s.U, s.V, ws))
+    ms_n, (inn, stn) = timed(lambda: L.slar_nested_cross(g, src, adv, dt, p.tol, kmax, probes4, seed, H, ws))
     # accuracy at random entries against the exact update (FP64 tables)
     idx = SI.random_requests(p.n, 4096, seed=99)
     idx_d = torch.as_tensor(idx, dtype=torch.int32, device="cuda")
@@ -396,7 +400,8 @@ def nested_main(args):
     rel = lambda a: float(torch.linalg.norm(a - exact) / torch.linalg.norm(exact))   # noqa: E731
     print(json.dumps({
         "workload": f"nested HT cross vs HTACA, one SL-FD update of the {args.nested_config} {n}^4 state "
-                    "after two steps (first CF3 sub-flow), FP32 tables, tol %g" % p.tol,
+                    "after two steps (first CF3 sub-flow), %s tables, tol %g" % ("FP64" if dt == L.F64 else "FP32",
+                                                                                  p.tol),
         "htaca": {"ms": ms_h, "samples": int(ih.samples), "rank": int(ih.rank), "converged": int(ih.converged),
                   "status": int(sth), "rel_err_4096": rel(approx_h)},
         "nested": {"ms": ms_n, "samples": int(inn.samples), "ranks": list(inn.rank), "sweeps": int(inn.sweeps),
