@@ -105,10 +105,12 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   const double gather_bytes = 2.0 * rx * ldt * (dt == SLAR_F32 ? 4.0 : 8.0) + 8.0;
   const bool timing = ws->timing && (int)ws->events.size() >= 4 * maxit;
   // Iterations are enqueued in chunks of CH with an event after each.
-  // Every bookkeeping launch writes the phase to a host-mapped pinned word;
-  // the host reads it once the previous chunk's event has completed (only
-  // after the next chunk is queued, so the device never idles on a poll).
-  // A newer value than that chunk's is harmless: DONE is final.
+  // The last bookkeeping launch of a chunk writes the phase to a
+  // host-mapped pinned word (a store that crosses to host memory delays
+  // the end of its kernel, so the others skip it); the host reads it once
+  // that chunk's event has completed (only after the next chunk is queued,
+  // so the device never idles on a poll).  A newer value than that chunk's
+  // is harmless: DONE is final.
   // Iterations enqueued after the stop see phase != RUN and exit at once
   // (their launches did no work and are left out of the timing below).
   constexpr int CH = 4;
@@ -120,14 +122,15 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
     const int c = it / CH;
     for (const int end = std::min(it + CH, maxit); it < end; ++it) {
       hipError_t e;
+      int* ph = (it == end - 1) ? ws->phase_dev : nullptr;
       if (dt == SLAR_F32)
         e = aca_iter_dispatch<float>(s, G, A, ws->X32, ws->P32, ldt, r, ctl, out->U, out->V,
                                      ws->used, ws->aca_part, nprobe, probes,
-                                     timed(it) ? &ws->events[4 * it] : nullptr, ws->phase_dev, ws->aca_piv);
+                                     timed(it) ? &ws->events[4 * it] : nullptr, ph, ws->aca_piv);
       else
         e = aca_iter_dispatch<double>(s, G, A, X64, P64, ldt, r, ctl, out->U, out->V, ws->used,
                                       ws->aca_part, nprobe, probes,
-                                      timed(it) ? &ws->events[4 * it] : nullptr, ws->phase_dev, ws->aca_piv);
+                                      timed(it) ? &ws->events[4 * it] : nullptr, ph, ws->aca_piv);
       if (e != hipSuccess) return SLAR_E_HIP;
     }
     HIP_TRY(hipEventRecord(ws->poll_ev[c & 1], s));
