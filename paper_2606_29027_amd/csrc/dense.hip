@@ -616,23 +616,75 @@ hipError_t svd_small(hipStream_t s, int k, const double* M, double* W, double* s
 // vectors, their norms the singular values.  The right vectors are not
 // accumulated: the caller forms the ones it keeps as M^T w / s.
 //
-// The Jacobi sweeps run on L = M Q (Householder LQ, M = L Q^T) instead of
-// M: right-multiplying by an orthogonal matrix leaves the left singular
-// vectors and the singular values unchanged, and the rows of L are graded
-// the way the pivot blocks of a cross approximation are, so the sweeps
-// converge in about a third as many passes as on M itself.
+// The Jacobi sweeps run on L = P M Q (row-pivoted Householder LQ) instead
+// of M: right-multiplying by an orthogonal matrix leaves the left singular
+// vectors and the singular values unchanged (the row permutation P is
+// undone on output), and the rows of L are graded, so the sweeps converge
+// in about a third as many passes as on M itself.
 constexpr int SVD_BIG = SLAR_CROSS_KMAX;
 constexpr int SVD_BIG_LD = SVD_BIG;   // a multiple of 32 doubles, as the Jacobi teams assume
 
-// In-place Householder LQ of the n x n matrix A (column c at A + c * lda,
-// n <= 128, blockDim 1024): on return A holds L = A Q, lower triangular.
-// Step i reflects columns i..n-1 so that row i keeps only its diagonal.
-// Row r's update sums over the columns in eight strided groups of 128
-// threads (one thread per row and group); vrow holds the reflector.
-__device__ void lq_lower(double* A, int lda, int n, double* vrow, double (*part)[SVD_BIG], double* s_sc) {
+// In-place Householder LQ with row pivoting of the n x n matrix A (column
+// c at A + c * lda, n <= 128, blockDim 1024): on return A holds L = P A Q,
+// lower triangular, and perm[r] is the row of the input that row r of L
+// came from.  Step i first swaps in the remaining row of largest norm over
+// columns i.. (lowest index on ties; the norms are downdated by the entry
+// each step leaves in column i, so only the pivot choice depends on their
+// rounding), then reflects columns i..n-1 so that row i keeps only its
+// diagonal.  Row r's update sums over the columns in eight strided groups
+// of 128 threads (one thread per row and group); vrow holds the reflector.
+// With the rows ordered by their remaining norm, L's columns come out
+// graded and the Jacobi sweeps that follow need fewer passes.
+__device__ void lq_lower(double* A, int lda, int n, double* vrow, double (*part)[SVD_BIG], double* s_sc,
+                         double* rnorm, int* perm) {
   const int t = threadIdx.x;
   const int row = t & 127, g = t >> 7;
+  // squared row norms
+  if (row < n) {
+    double pr = 0.0;
+    for (int c = g; c < n; c += 8) pr += A[c * lda + row] * A[c * lda + row];
+    part[g][row] = pr;
+  }
+  __syncthreads();
+  if (t < n) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a += part[q][t];
+    rnorm[t] = a;
+    perm[t] = t;
+  }
+  __syncthreads();
   for (int i = 0; i + 1 < n; ++i) {
+    if (t < 64) {
+      double m = -1.0;
+      int mi = n;
+      for (int r = i + t; r < n; r += 64)
+        if (rnorm[r] > m) { m = rnorm[r]; mi = r; }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double m2 = __shfl_xor(m, o, 64);
+        const int i2 = __shfl_xor(mi, o, 64);
+        if (m2 > m || (m2 == m && i2 < mi)) { m = m2; mi = i2; }
+      }
+      if (t == 0) s_sc[2] = (double)mi;
+    }
+    __syncthreads();
+    const int p = (int)s_sc[2];
+    if (p != i && p < n) {
+      if (t < n) {
+        const double a = A[t * lda + i];
+        A[t * lda + i] = A[t * lda + p];
+        A[t * lda + p] = a;
+      }
+      if (t == 0) {
+        const double a = rnorm[i];
+        rnorm[i] = rnorm[p];
+        rnorm[p] = a;
+        const int q = perm[i];
+        perm[i] = perm[p];
+        perm[p] = q;
+      }
+      __syncthreads();
+    }
     if (t < 64) {
       double sg = 0.0;
       for (int c = i + 1 + t; c < n; c += 64) {
@@ -668,6 +720,9 @@ __device__ void lq_lower(double* A, int lda, int n, double* vrow, double (*part)
     if (act && row == i)
       for (int c = i + g; c < n; c += 8) A[c * lda + i] = (c == i) ? alpha : 0.0;
     __syncthreads();
+    // remaining norms over columns i+1.. of the rows below
+    if (t > i && t < n) rnorm[t] = fmax(rnorm[t] - A[i * lda + t] * A[i * lda + t], 0.0);
+    __syncthreads();
   }
 }
 
@@ -680,7 +735,9 @@ __device__ __forceinline__ void svd_left_big_dev(int k, const double* __restrict
   __shared__ int s_rot[2];
   __shared__ double vrow[SVD_BIG];
   __shared__ double lqpart[8][SVD_BIG];
-  __shared__ double s_sc[2];
+  __shared__ double s_sc[3];
+  __shared__ double rnorm[SVD_BIG];
+  __shared__ int perm[SVD_BIG];
   const int t = threadIdx.x;
   const int kp = (k + 1) & ~1;
   double part = 0.0;
@@ -697,7 +754,7 @@ __device__ __forceinline__ void svd_left_big_dev(int k, const double* __restrict
   for (int w = 0; w < 16; ++w) fro += red[w];
   const double floor_abs = 1e-300 + 1e-22 * fro;
   const double orth = 4.0 * kp * 2.220446049250313e-16;
-  lq_lower(A, SVD_BIG_LD, kp, vrow, lqpart, s_sc);
+  lq_lower(A, SVD_BIG_LD, kp, vrow, lqpart, s_sc, rnorm, perm);
   jacobi_cols<8, 0>(A, SVD_BIG_LD, kp, kp, nullptr, 0, 0, orth, floor_abs, 60, nrm, s_rot);
   for (int c = t; c < kp; c += blockDim.x) {
     double acc = 0.0;
@@ -712,10 +769,14 @@ __device__ __forceinline__ void svd_left_big_dev(int k, const double* __restrict
     order[rank] = c;
   }
   __syncthreads();
-  for (int e = t; e < k * k; e += blockDim.x) {
+  // row r of L is row perm[r] of the input; the zero padding row of odd k
+  // (perm[r] == k) may have moved, so every row of L is visited and only
+  // the input's k rows are written
+  for (int e = t; e < kp * k; e += blockDim.x) {
     const int r = e / k, j = e % k;
     const int c = order[j];
-    W[e] = nrm[c] > 0.0 ? A[c * SVD_BIG_LD + r] / nrm[c] : (r == j ? 1.0 : 0.0);
+    const int ro = perm[r];
+    if (ro < k) W[(size_t)ro * k + j] = nrm[c] > 0.0 ? A[c * SVD_BIG_LD + r] / nrm[c] : (ro == j ? 1.0 : 0.0);
   }
   for (int j = t; j < k; j += blockDim.x) {
     sv[j] = nrm[order[j]];
