@@ -637,7 +637,9 @@ def main():
         o["dtype"] = "f64" if other == L.F64 else "f32"
         out["config"]["other_precision"] = {k: o[k] for k in ("dtype", "value", "ms_per_step", "median_ms_per_step",
                                                               "converged_steps", "timed_steps", "t_end",
-                                                              "samples_per_step", "phase_ms_per_step")}
+                                                              "samples_per_step", "entries_per_s_cross",
+                                                              "entries_per_s_fiber_kernels", "phase_ms_per_step",
+                                                              "newton_krylov")}
     if not args.no_samplers:
         # the entry samplers at the workload's rank cap (r = 60): the
         # paper's leaf-to-root contraction on the matrix cores and the
