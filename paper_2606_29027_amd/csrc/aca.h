@@ -54,9 +54,12 @@ struct AcaInst {
   const int* rowtab = nullptr;
   const int* coltab = nullptr;
   int* piv = nullptr;
-  // host-mapped pinned word that receives the phase after every
-  // bookkeeping launch (single-instance driver; null elsewhere)
+  // host-mapped pinned words that receive, from a bookkeeping launch given
+  // them (the last of a chunk of iterations, single-instance driver; null
+  // elsewhere), the phase in [0] and then the chunk's sequence number seq
+  // in [1]
   int* phase_host = nullptr;
+  int seq = 0;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -661,8 +664,14 @@ __global__ __launch_bounds__(FS_THREADS) void k_aca_col(AcaInst I) { aca_col_bod
 template <typename T, int W, int DX, bool TAB = false>
 __global__ __launch_bounds__(FS_THREADS) void k_aca_fin(AcaInst I) {
   aca_fin_body<T, W, DX, TAB>(I);
-  // thread 0 made every change of the phase, so it reads the final value
-  if (I.phase_host && threadIdx.x == 0) *(volatile int*)I.phase_host = I.ctl->phase;
+  // thread 0 made every change of the phase, so it reads the final value;
+  // the host waits for seq, then reads the phase
+  if (I.phase_host && threadIdx.x == 0) {
+    volatile int* ph = I.phase_host;
+    ph[0] = I.ctl->phase;
+    __threadfence_system();
+    ph[1] = I.seq;
+  }
 }
 
 }  // namespace slar

@@ -37,11 +37,12 @@ template <typename T, int W, int DX>
 static hipError_t aca_iterate(hipStream_t s, const GridDev& G, const AdvDev& A, const T* X,
                               const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
                               unsigned char* used, double* part, int nprobe, const int* probes,
-                              hipEvent_t* ev, int* phase_dev, int* piv) {
+                              hipEvent_t* ev, int* phase_dev, int seq, int* piv) {
   const unsigned bRow = (G.nv + ACA_TILE - 1) / ACA_TILE;
   const unsigned bCol = (G.nx + ACA_TILE - 1) / ACA_TILE;
   AcaInst I{G, A, X, P, ld, r, ctl, U, V, used, part, (int)bRow, (int)bCol, nprobe, 16, probes};
   I.phase_host = phase_dev;
+  I.seq = seq;
   I.piv = piv;
   if (ev) {
     // events attached to the dispatches themselves: start and end of the
@@ -60,17 +61,32 @@ template <typename T>
 static hipError_t aca_iter_dispatch(hipStream_t s, const GridDev& G, const AdvDev& A, const T* X,
                                     const T* P, int ld, int r, AcaCtl* ctl, double* U, double* V,
                                     unsigned char* used, double* part, int nprobe,
-                                    const int* probes, hipEvent_t* ev, int* phase_dev, int* piv) {
+                                    const int* probes, hipEvent_t* ev, int* phase_dev, int seq, int* piv) {
   if (G.dx == 1) {
     if (A.order == 5)
-      return aca_iterate<T, 5, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, piv);
-    return aca_iterate<T, 3, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, piv);
+      return aca_iterate<T, 5, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, seq, piv);
+    return aca_iterate<T, 3, 1>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, seq, piv);
   }
-  return aca_iterate<T, 3, 2>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, piv);
+  return aca_iterate<T, 3, 2>(s, G, A, X, P, ld, r, ctl, U, V, used, part, nprobe, probes, ev, phase_dev, seq, piv);
 }
 
 hipError_t table_copy(hipStream_t s, int rows, int r, int ldin, const double* in, int ldo,
                       float* o32, double* o64);
+
+// Wait until the device has written a sequence number >= target into ph[1]
+// (host-mapped).  Every 1024 polls the stream is queried: once it has
+// drained, the number must be there (else SLAR_E_HIP), and a stream error
+// ends the wait as well.
+static slar_status wait_seq(hipStream_t s, volatile int* ph, int target) {
+  for (long n = 1;; ++n) {
+    if (ph[1] >= target) return SLAR_OK;
+    if ((n & 1023) == 0) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) return ph[1] >= target ? SLAR_OK : SLAR_E_HIP;
+      if (q != hipErrorNotReady) return SLAR_E_HIP;
+    }
+  }
+}
 
 // Host driver of the cross approximation (synchronises the stream).
 slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, const slar_adv& adv,
@@ -104,39 +120,43 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   const int rx = (G.dx == 2) ? adv.order * adv.order : adv.order;
   const double gather_bytes = 2.0 * rx * ldt * (dt == SLAR_F32 ? 4.0 : 8.0) + 8.0;
   const bool timing = ws->timing && (int)ws->events.size() >= 4 * maxit;
-  // Iterations are enqueued in chunks of CH with an event after each.
-  // The last bookkeeping launch of a chunk writes the phase to a
-  // host-mapped pinned word (a store that crosses to host memory delays
-  // the end of its kernel, so the others skip it); the host reads it once
-  // that chunk's event has completed (only after the next chunk is queued,
-  // so the device never idles on a poll).  A newer value than that chunk's
-  // is harmless: DONE is final.
+  // Iterations are enqueued in chunks of CH.  The last bookkeeping launch
+  // of chunk c writes the phase and then the sequence number c + 1 to
+  // host-mapped pinned words (a store that crosses to host memory delays
+  // the end of its kernel, so the others skip it).  Once the next chunk is
+  // queued (so the device never idles on a poll), the host waits until the
+  // sequence number reaches the previous chunk's and reads the phase.  A
+  // newer value than that chunk's is harmless: DONE is final.  (An event
+  // recorded after each chunk for the same purpose held the next launch
+  // back by ~4 us.)
   // Iterations enqueued after the stop see phase != RUN and exit at once
   // (their launches did no work and are left out of the timing below).
   constexpr int CH = 4;
   auto timed = [&](int q) { return timing && (q % ws->timing_every) == ws->timing_every - 1; };
-  *(volatile int*)ws->phase_host = ACA_RUN;   // no launch of this workspace is in flight
+  volatile int* ph = (volatile int*)ws->phase_host;
+  ph[0] = ACA_RUN;                              // no launch of this workspace is in flight
+  ph[1] = 0;
   int it = 0, pending = -1;
   bool stop = false;
   while (it < maxit && !stop) {
     const int c = it / CH;
     for (const int end = std::min(it + CH, maxit); it < end; ++it) {
       hipError_t e;
-      int* ph = (it == end - 1) ? ws->phase_dev : nullptr;
+      int* pw = (it == end - 1) ? ws->phase_dev : nullptr;
       if (dt == SLAR_F32)
         e = aca_iter_dispatch<float>(s, G, A, ws->X32, ws->P32, ldt, r, ctl, out->U, out->V,
                                      ws->used, ws->aca_part, nprobe, probes,
-                                     timed(it) ? &ws->events[4 * it] : nullptr, ph, ws->aca_piv);
+                                     timed(it) ? &ws->events[4 * it] : nullptr, pw, c + 1, ws->aca_piv);
       else
         e = aca_iter_dispatch<double>(s, G, A, X64, P64, ldt, r, ctl, out->U, out->V, ws->used,
                                       ws->aca_part, nprobe, probes,
-                                      timed(it) ? &ws->events[4 * it] : nullptr, ph, ws->aca_piv);
+                                      timed(it) ? &ws->events[4 * it] : nullptr, pw, c + 1, ws->aca_piv);
       if (e != hipSuccess) return SLAR_E_HIP;
     }
-    HIP_TRY(hipEventRecord(ws->poll_ev[c & 1], s));
     if (pending >= 0) {
-      HIP_TRY(hipEventSynchronize(ws->poll_ev[pending & 1]));
-      stop = *(volatile int*)ws->phase_host == ACA_DONE;
+      const slar_status w = wait_seq(s, ph, pending + 1);
+      if (w != SLAR_OK) return w;
+      stop = ph[0] == ACA_DONE;
     }
     pending = c;
   }
