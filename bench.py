@@ -289,7 +289,7 @@ def batched_run(args, steps, warmup, cpu_seconds=None):
     traffic = measured_batch_traffic()
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "batched cross approximation (prep + row + col + fin launches, graph replays)",
+            "kernel": "batched cross approximation (prep + row + col launches, graph replays)",
             "algorithmic_bytes_per_step": by / steps, "cross_ms_per_step": tim["cross_ms"] / steps}
     if traffic and tim["cross_ms"] > 0:
         hbm = traffic / (tim["cross_ms"] / steps * 1e-3) / 1e9

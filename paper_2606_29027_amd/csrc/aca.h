@@ -1,8 +1,8 @@
 // Device side of the adaptive cross approximation: control block, the
-// per-instance argument record and the three per-iteration bodies (row
-// fiber, column fiber, bookkeeping).  The bodies take one instance record
-// and one fiber tile index, so the same code serves one launch per
-// instance and the persistent multi-instance launches.
+// per-instance argument record and the two per-iteration bodies (row fiber,
+// column fiber).  The bodies take one instance record and one fiber tile
+// index, so the same code serves one launch per instance and the
+// persistent multi-instance launches.
 #pragma once
 #include <cmath>
 
@@ -12,11 +12,21 @@
 namespace slar {
 
 enum { ACA_RUN = 0, ACA_PROBE = 1, ACA_DONE = 2 };
+// What the row launch does before it samples: START (row i), COL (the
+// column launch before it sampled term k-1: next row pivot from its
+// candidates, and the sums of its dot products), PROBE (the column launch
+// before it sampled the probe entries: resolve the probe check).
+enum { ACA_NX_START = 0, ACA_NX_COL = 1, ACA_NX_PROBE = 2 };
 
+// Two records per cross approximation: the row launch reads ctl[0] and
+// writes ctl[1], the column launch reads ctl[1] and writes ctl[0], so no
+// launch writes the record its own blocks read.  Every block takes the
+// launch's decision from the same inputs; the block of tile 0 writes it.
 struct AcaCtl {
   int phase, k, i, j;
   int iters, probe_rounds, converged, capped;
-  unsigned cnt_row, cnt_col;
+  int next;    // ACA_NX_* (written by the column launch)
+  int rowok;   // the row launch sampled row i (written by the row launch)
   int kmax, pad;
   double pivot, norm2, tol;
   long long samples;
@@ -26,8 +36,8 @@ constexpr int ACA_MAXBLK = 1024;   // partial slots
 // Entries per fiber block (a lane quad per foot in a 256-thread block).  A
 // fiber has at most 128^2 entries, i.e. 256 blocks.  Tiles of 32 (two
 // blocks per CU) left the sampling launch as long (each block's time is
-// the latency of its feet and gathers) and made the bookkeeping launch
-// stage twice the candidates, so 64 it is.
+// the latency of its feet and gathers) and doubled the candidates every
+// block of the next launch reduces, so 64 it is.
 constexpr int ACA_TILE = 64;
 
 // Everything one cross approximation reads or writes (one instance).
@@ -54,7 +64,7 @@ struct AcaInst {
   const int* rowtab = nullptr;
   const int* coltab = nullptr;
   int* piv = nullptr;
-  // host-mapped pinned words that receive, from a bookkeeping launch given
+  // host-mapped pinned words that receive, from a column launch given
   // them (the last of a chunk of iterations, single-instance driver; null
   // elsewhere), the phase in [0] and then the chunk's sequence number seq
   // in [1]
@@ -161,13 +171,21 @@ __device__ __forceinline__ void entry_index(const AcaInst& I, int row, int col, 
 //   row kernel: q = 0 block max|r|, q = 1 block candidate index,
 //               q = 2 + l  v_l . r  (l <= k < ACA_KC), q = PVAL candidate |r|
 //   col kernel: same with base PCOL
-//   q = GSUM: sum over row blocks of v_l . r at slot l (written by the
-//   column kernel, read by the bookkeeping kernel)
+//   q = GSUM, GSUM1: sum over row blocks of v_l . r at slot l for even /
+//   odd term index (written by the column kernel of the term, read by the
+//   next column kernel)
+//   q = GSU: sum over column blocks of u_l . u at slot l (written by the
+//   row kernel after the term's column, read by the next column kernel)
+//   q = PRB, PRBI: residual (or -1) and row of each probe entry
 constexpr int ACA_KC = SLAR_CROSS_KMAX;
 constexpr int PVAL = ACA_KC + 2;
 constexpr int GSUM = ACA_KC + 3;
 constexpr int PCOL = ACA_KC + 4;
-constexpr int ACA_PART_SLOTS = PCOL + PVAL + 1;
+constexpr int GSUM1 = PCOL + PVAL + 1;
+constexpr int GSU = GSUM1 + 1;
+constexpr int PRB = GSU + 1;
+constexpr int PRBI = PRB + 1;
+constexpr int ACA_PART_SLOTS = PRBI + 1;
 static_assert(ACA_KC <= ACA_MAXBLK, "GSUM holds one slot per cross term");
 
 // Per-block max of |x| (entries with skip() excluded), the lowest index in
@@ -194,45 +212,6 @@ __device__ void block_candidate(const double* xs, int ns, int base, Skip skip, d
   __syncthreads();
 }
 
-// Global pivot from per-block candidates: lowest index whose |x| is within
-// the tie tolerance of the global maximum M (M < 0: nothing eligible).
-// pmax / pidx / pval are the per-block maximum, candidate index and
-// candidate value; only when the first qualifying block's candidate falls
-// below the tolerance is that block's range of x rescanned.
-template <typename Skip>
-__device__ int pivot_from_parts(const double* x, const double* pmax, const double* pidx,
-                                const double* pval, int nb, int n, Skip skip, double* red, int* redi,
-                                double* M_out) {
-  const int t = threadIdx.x;
-  double m = -1.0;
-  for (int b = t; b < nb; b += blockDim.x) m = fmax(m, pmax[b]);
-  const double M = block_max(m, red);
-  *M_out = M;
-  if (!(M >= 0.0)) return n;
-  const double thr = M * (1.0 - 1e-10);
-  int bb = nb;
-  for (int b = t; b < nb; b += blockDim.x)
-    if (pmax[b] >= thr && b < bb) bb = b;
-  for (int o = 32; o > 0; o >>= 1) bb = min(bb, __shfl_xor(bb, o, 64));
-  if ((t & 63) == 0) redi[t >> 6] = bb;
-  __syncthreads();
-  bb = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
-  __syncthreads();
-  if (bb >= nb) return n;
-  const int cand = (int)pidx[bb];
-  if (cand < n && pval[bb] >= thr) return cand;
-  // the block maximum is close to M but below it: rescan that block's range
-  int best = n;
-  const int e = bb * ACA_TILE + t;
-  if (t < ACA_TILE && e < n && !skip(e) && fabs(x[e]) >= thr) best = e;
-  for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
-  if ((t & 63) == 0) redi[t >> 6] = best;
-  __syncthreads();
-  best = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
-  __syncthreads();
-  return best;
-}
-
 struct NoSkip {
   __device__ bool operator()(int) const { return false; }
 };
@@ -249,168 +228,476 @@ constexpr int ACA_LREG = 16;
 constexpr int ACA_CHUNK = 4 * ACA_LREG;
 static_assert(2 * ACA_CHUNK >= ACA_KC, "two chunks cover every cross term");
 
+
+// A fiber has at most FIN_NB blocks, so one thread holds one block's pivot
+// candidate.
+constexpr int FIN_NB = 256;
+static_assert(ACA_TILE <= FS_SAMPLES, "a fiber tile fits the sampler's LDS rows");
+static_assert(FIN_NB <= FS_THREADS, "one thread per fiber block");
+static_assert(FIN_NB * ACA_TILE >= SLAR_NMAX * SLAR_NMAX && FIN_NB * ACA_TILE >= SLAR_NMAX_1D,
+              "every fiber has at most FIN_NB blocks");
+static_assert(FS_THREADS * 4 >= 1024 && ACA_MAXBLK >= 1024, "probe slots hold 1024 entries");
+
+// Per-block pivot candidates of one fiber: thread b < nb holds block b's
+// maximum, candidate index and candidate value (-1, 0, -1 elsewhere).
+struct Cand {
+  double m, idx, val;
+};
+__device__ __forceinline__ Cand load_cand(const double* base, int nb) {
+  const int t = threadIdx.x;
+  Cand c{-1.0, 0.0, -1.0};
+  if (t < nb) {
+    c.m = base[t];
+    c.idx = base[ACA_MAXBLK + t];
+    c.val = base[(size_t)PVAL * ACA_MAXBLK + t];
+  }
+  return c;
+}
+
+struct PivLds {
+  double mx[4], ci[4], cv[4];
+  int bb[4], best[4];
+};
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Global pivot from candidates held in registers, M the maximum of all
+// block maxima (M < 0: nothing eligible): the lowest block whose maximum
+// is within the tie tolerance of M gives its candidate; only when that
+// candidate falls below the tolerance is the block's range of x rescanned
+// (lowest eligible index within the tolerance).
+template <typename Skip>
+__device__ int pivot_pick(const Cand& c, double M, const double* x, int nb, int n, Skip skip, PivLds& S) {
+  const int t = threadIdx.x, wv = t >> 6;
+  if (!(M >= 0.0)) return n;
+  const double thr = M * (1.0 - 1e-10);
+  int bb = (t < nb && c.m >= thr) ? t : nb;
+  double ci = c.idx, cv = c.val;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int ob = __shfl_xor(bb, o, 64);
+    const double oi = __shfl_xor(ci, o, 64), ov = __shfl_xor(cv, o, 64);
+    if (ob < bb) { bb = ob; ci = oi; cv = ov; }
+  }
+  if ((t & 63) == 0) { S.bb[wv] = bb; S.ci[wv] = ci; S.cv[wv] = cv; }
+  __syncthreads();
+  int w0 = 0;
+#pragma unroll
+  for (int w = 1; w < 4; ++w)
+    if (S.bb[w] < S.bb[w0]) w0 = w;
+  bb = S.bb[w0]; ci = S.ci[w0]; cv = S.cv[w0];
+  if (bb >= nb) return n;
+  const int cand = (int)ci;
+  if (cand < n && cv >= thr) return cand;
+  int best = n;
+  const int e = bb * ACA_TILE + t;
+  if (t < ACA_TILE && e < n && !skip(e) && fabs(x[e]) >= thr) best = e;
+  for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+  if ((t & 63) == 0) S.best[wv] = best;
+  __syncthreads();
+  best = min(min(S.best[0], S.best[1]), min(S.best[2], S.best[3]));
+  return best;
+}
+
+// ------------------------------------------------------------ row launch
+// Decision of the row launch, taken alike by every block:
+//   START: sample row i;
+//   COL:   the next row pivot is the unused row maximising |u_(k-1)| (from
+//          the column launch's block candidates); no row when k reached
+//          the term cap or no row is eligible.  The row is sampled before
+//          the column launch has run the stopping test of term k-1, and is
+//          discarded when that test stops the iteration;
+//   PROBE: resolve the probe check of the column launch before: largest
+//          residual above the threshold among the probes (lowest index
+//          within the tie tolerance); none -> converged, term cap ->
+//          capped, else sample that probe's row.
+// The block given `writer` stores the outcome in ctl[1].
+struct RowDec {
+  int go, i, k, next;   // next < 0: the cross has stopped
+};
+
+template <bool TAB>
+__device__ RowDec aca_row_decide(const AcaInst& I, bool writer) {
+  __shared__ AcaCtl sc;
+  __shared__ PivLds S;
+  const int t = threadIdx.x, wv = t >> 6;
+  const Cand c = load_cand(I.part + (size_t)PCOL * ACA_MAXBLK, I.nbcol);
+  if (t == 0) sc = I.ctl[0];
+  __syncthreads();
+  RowDec d{1, sc.i, sc.k, sc.next};
+  if (sc.phase != ACA_RUN) {
+    if (writer && t == 0) I.ctl[1] = sc;
+    d.go = 0; d.next = -1;
+    return d;
+  }
+  const int k = sc.k;
+  const int Nx = TAB ? I.nrows : I.g.nx;
+  int phase = ACA_RUN, conv = sc.converged, capd = sc.capped, prounds = sc.probe_rounds;
+  if (sc.next == ACA_NX_COL) {
+    if (k >= sc.kmax) {
+      d.go = 0;
+    } else {
+      const double mw = wave_max(c.m);
+      if ((t & 63) == 0) S.mx[wv] = mw;
+      __syncthreads();
+      const double M = fmax(fmax(S.mx[0], S.mx[1]), fmax(S.mx[2], S.mx[3]));
+      const int ip = pivot_pick(c, M, I.U + (size_t)(k - 1) * Nx, I.nbcol, Nx, SkipUsed{I.used, sc.i}, S);
+      if (!(M >= 0.0) || ip >= Nx) d.go = 0;
+      else d.i = ip;
+    }
+  } else if (sc.next == ACA_NX_PROBE) {
+    const double* pr = I.part + (size_t)PRB * ACA_MAXBLK;
+    const int* pri = (const int*)(I.part + (size_t)PRBI * ACA_MAXBLK);
+    const int np = I.nprobe;
+    double rv[4];
+    double m = -1.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + FS_THREADS * q;
+      rv[q] = (e < np) ? pr[e] : -1.0;
+      m = fmax(m, rv[q]);
+    }
+    m = wave_max(m);
+    if ((t & 63) == 0) S.mx[wv] = m;
+    __syncthreads();
+    m = fmax(fmax(S.mx[0], S.mx[1]), fmax(S.mx[2], S.mx[3]));
+    int best = np;
+    if (m > 0.0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = t + FS_THREADS * q;
+        if (e < np && rv[q] > 0.0 && rv[q] >= m * (1.0 - 1e-10) && e < best) best = e;
+      }
+      for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+      if ((t & 63) == 0) S.best[wv] = best;
+      __syncthreads();
+      best = min(min(S.best[0], S.best[1]), min(S.best[2], S.best[3]));
+    }
+    if (m <= 0.0 || best >= np) { phase = ACA_DONE; conv = 1; d.go = 0; }
+    else if (k >= sc.kmax) { phase = ACA_DONE; capd = 1; d.go = 0; }
+    else { prounds += 1; d.i = pri[best]; }
+  }
+  if (writer && t == 0) {
+    AcaCtl o = sc;
+    o.i = d.i; o.rowok = d.go; o.phase = phase;
+    o.converged = conv; o.capped = capd; o.probe_rounds = prounds;
+    I.ctl[1] = o;
+  }
+  if (phase != ACA_RUN) d.next = -1;
+  return d;
+}
+
+// One tile of the row launch: the row fiber A[i, :] through the SL-FD
+// evaluator, the residual r = A[i,:] - sum_l u_l[i] v_l stored as V[k],
+// per-block partials of v_l . r and a per-block pivot candidate; after a
+// COL decision also this tile's share of the sums over the column blocks of
+// u_l . u_(k-1) (wave w of tile b takes l = 4 b + w, 4 b + w + 4 nbrow, ...).
 template <typename T, int W, int DX, bool TAB = false>
-__device__ void aca_row_body(const AcaInst& I, int tile) {
+__device__ void aca_row_sample(const AcaInst& I, const RowDec& d, int tile) {
+  if (d.next < 0) return;
   const GridDev& g = I.g;
   const AdvDev& a = I.a;
   const T* __restrict__ X = (const T*)I.X;
   const T* __restrict__ P = (const T*)I.P;
   const int ld = I.ld, r = I.r;
-  AcaCtl* ctl = I.ctl;
   const double* __restrict__ U = I.U;
   double* __restrict__ V = I.V;
   double* __restrict__ part = I.part;
   __shared__ FsLds<W, DX> L;
   __shared__ double red[4];
   __shared__ int redi[4];
-  __shared__ int s_phase, s_i, s_k;
   __shared__ double acc4[4][FS_SAMPLES];
   __shared__ double rres[FS_SAMPLES];
   const int t = threadIdx.x;
-  if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; }
-  __syncthreads();
-  if (s_phase != ACA_RUN) return;
-  const int i = s_i, k = s_k;
+  const int k = d.k, i = d.i;
   const int Nx = TAB ? I.nrows : g.nx, Nv = TAB ? I.ncols : g.nv;
   const int J0 = tile * ACA_TILE;
   const int ns = min(ACA_TILE, Nv - J0);
   const int wv = t >> 6, ln = t & 63;
-  // earlier row vectors v_l[J] and u_l[i] (loads in flight during the feet)
-  double vl[ACA_LREG], ui[ACA_LREG];
-#pragma unroll
-  for (int m = 0; m < ACA_LREG; ++m) {
-    const int l = wv + 4 * m;
-    const bool ok = l < k && ln < ns;
-    vl[m] = ok ? V[(size_t)l * Nv + J0 + ln] : 0.0;
-    ui[m] = ok ? U[(size_t)l * Nx + i] : 0.0;
-  }
-  {
-    const int s = t >> 2;
-    if (s < ns) {
-      int gi[4];
-      entry_index<DX, TAB>(I, i, J0 + s, gi);
-      fs_prepare<W, DX, 4>(g, a, gi, L, s, t & 3);
-    }
-  }
-  // residual r_J = A[i, J] - sum_l u_l[i] v_l[J]: the l-sum is split over
-  // the four waves (wave w takes l = w, w + 4, ...) and combined in LDS
-  {
-    double acc = 0.0;
-#pragma unroll
-    for (int m = 0; m < ACA_LREG; ++m)
-      if (wv + 4 * m < k) acc += ui[m] * vl[m];
-    if (k > ACA_CHUNK) {
-#pragma unroll 4
-      for (int m = 0; m < ACA_LREG; ++m) {
-        const int l = ACA_CHUNK + wv + 4 * m;
-        if (l < k && ln < ns) acc += U[(size_t)l * Nx + i] * V[(size_t)l * Nv + J0 + ln];
-      }
-    }
-    acc4[wv][ln] = acc;
-  }
-  __syncthreads();
-  fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
-  __syncthreads();
-  if (t < 64) {
-    double rv = 0.0;
-    if (t < ns) {
-      rv = L.val[t] - (((acc4[0][t] + acc4[1][t]) + acc4[2][t]) + acc4[3][t]);
-      V[(size_t)k * Nv + J0 + t] = rv;
-    }
-    rres[t] = rv;
-  }
-  __syncthreads();
-  {
-    const double r_ = (ln < ns) ? rres[ln] : 0.0;
-    double pv[ACA_LREG];
+  if (d.go) {
+    // earlier row vectors v_l[J] and u_l[i] (loads in flight during the feet)
+    double vl[ACA_LREG], ui[ACA_LREG];
 #pragma unroll
     for (int m = 0; m < ACA_LREG; ++m) {
       const int l = wv + 4 * m;
-      pv[m] = (l < k ? vl[m] : (l == k ? r_ : 0.0)) * r_;
+      const bool ok = l < k && ln < ns;
+      vl[m] = ok ? V[(size_t)l * Nv + J0 + ln] : 0.0;
+      ui[m] = ok ? U[(size_t)l * Nx + i] : 0.0;
     }
-    const double p = wave_sum16_scatter(pv, ln);
-    const int l = wv + 4 * scatter_slot(ln);
-    if ((ln & 3) == 0 && l <= k) part[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
-    if (k >= ACA_CHUNK) {
-      // second chunk of the dot products, l = 64 + wave + 4 m
+    {
+      const int s = t >> 2;
+      if (s < ns) {
+        int gi[4];
+        entry_index<DX, TAB>(I, i, J0 + s, gi);
+        fs_prepare<W, DX, 4>(g, a, gi, L, s, t & 3);
+      }
+    }
+    // residual r_J = A[i, J] - sum_l u_l[i] v_l[J]: the l-sum is split over
+    // the four waves (wave w takes l = w, w + 4, ...) and combined in LDS
+    {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < ACA_LREG; ++m)
+        if (wv + 4 * m < k) acc += ui[m] * vl[m];
+      if (k > ACA_CHUNK) {
+#pragma unroll 4
+        for (int m = 0; m < ACA_LREG; ++m) {
+          const int l = ACA_CHUNK + wv + 4 * m;
+          if (l < k && ln < ns) acc += U[(size_t)l * Nx + i] * V[(size_t)l * Nv + J0 + ln];
+        }
+      }
+      acc4[wv][ln] = acc;
+    }
+    __syncthreads();
+    fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
+    __syncthreads();
+    if (t < 64) {
+      double rv = 0.0;
+      if (t < ns) {
+        rv = L.val[t] - (((acc4[0][t] + acc4[1][t]) + acc4[2][t]) + acc4[3][t]);
+        V[(size_t)k * Nv + J0 + t] = rv;
+      }
+      rres[t] = rv;
+    }
+    __syncthreads();
+    {
+      const double r_ = (ln < ns) ? rres[ln] : 0.0;
+      double pv[ACA_LREG];
 #pragma unroll
       for (int m = 0; m < ACA_LREG; ++m) {
-        const int l2 = ACA_CHUNK + wv + 4 * m;
-        const double v2 = (l2 < k && ln < ns) ? V[(size_t)l2 * Nv + J0 + ln] : (l2 == k ? r_ : 0.0);
-        pv[m] = v2 * r_;
+        const int l = wv + 4 * m;
+        pv[m] = (l < k ? vl[m] : (l == k ? r_ : 0.0)) * r_;
       }
-      const double p2 = wave_sum16_scatter(pv, ln);
-      const int l2 = ACA_CHUNK + wv + 4 * scatter_slot(ln);
-      if ((ln & 3) == 0 && l2 <= k) part[(size_t)(2 + l2) * ACA_MAXBLK + tile] = p2;
+      const double p = wave_sum16_scatter(pv, ln);
+      const int l = wv + 4 * scatter_slot(ln);
+      if ((ln & 3) == 0 && l <= k) part[(size_t)(2 + l) * ACA_MAXBLK + tile] = p;
+      if (k >= ACA_CHUNK) {
+        // second chunk of the dot products, l = 64 + wave + 4 m
+#pragma unroll
+        for (int m = 0; m < ACA_LREG; ++m) {
+          const int l2 = ACA_CHUNK + wv + 4 * m;
+          const double v2 = (l2 < k && ln < ns) ? V[(size_t)l2 * Nv + J0 + ln] : (l2 == k ? r_ : 0.0);
+          pv[m] = v2 * r_;
+        }
+        const double p2 = wave_sum16_scatter(pv, ln);
+        const int l2 = ACA_CHUNK + wv + 4 * scatter_slot(ln);
+        if ((ln & 3) == 0 && l2 <= k) part[(size_t)(2 + l2) * ACA_MAXBLK + tile] = p2;
+      }
+    }
+    block_candidate(rres, ns, J0, NoSkip{}, red, redi, &part[tile], &part[ACA_MAXBLK + tile],
+                    &part[(size_t)PVAL * ACA_MAXBLK + tile]);
+  }
+  if (d.next == ACA_NX_COL) {
+    // gu[l] = sum over the column blocks of (u_l . u_(k-1)), l < k: each
+    // lane adds four blocks in order, then a wave butterfly
+    const double* pc = part + (size_t)PCOL * ACA_MAXBLK;
+    for (int l = 4 * tile + wv; l < k; l += 4 * I.nbrow) {
+      const double* q = pc + (size_t)(2 + l) * ACA_MAXBLK;
+      double a4 = 0.0;
+#pragma unroll
+      for (int i4 = 0; i4 < FIN_NB / 64; ++i4) {
+        const int b = ln + 64 * i4;
+        const double v = q[b];
+        a4 += (b < I.nbcol) ? v : 0.0;
+      }
+      a4 = wave_sum(a4);
+      if (ln == 0) part[(size_t)GSU * ACA_MAXBLK + l] = a4;
     }
   }
-  block_candidate(rres, ns, J0, NoSkip{}, red, redi, &part[tile], &part[ACA_MAXBLK + tile],
-                  &part[(size_t)PVAL * ACA_MAXBLK + tile]);
 }
 
+// --------------------------------------------------------- column launch
+// Decision of the column launch, taken alike by every block.  First the
+// stopping test of term k-1 when the column launch before sampled it
+// (COL): ||S||^2 += 2 sum_(l<k-1) (u_l . u)(v_l . v) + |u|^2 |v|^2 from the
+// finished sums; |u| |v| <= tol ||S|| -> probe check, term cap -> capped,
+// no row from the row launch -> stop.  Otherwise the row i that the row
+// launch sampled is accepted: the column pivot j comes from the row
+// candidates (lowest index within a relative 1e-10 of the maximum), and a
+// row already reproduced (|r_j| below the threshold) leads to the probe
+// check.  The block given `writer` stores the outcome in ctl[0].
+enum { ACA_A_COL = 0, ACA_A_PROBE = 1, ACA_A_NONE = 2 };
+struct ColDec {
+  int act, i, j, k;
+  double norm2, tol;
+  int also;   // row marked used by this launch (excluded from the probes), or -1
+};
+
+template <bool TAB>
+__device__ ColDec aca_col_decide(const AcaInst& I, bool writer) {
+  enum { A_COL = 0, A_PROBE = 1, A_CAP = 2, A_STOP = 3 };
+  __shared__ AcaCtl sc;
+  __shared__ PivLds S;
+  __shared__ double s_norm2;
+  __shared__ int s_act;
+  const int t = threadIdx.x, wv = t >> 6;
+  const double* __restrict__ part = I.part;
+  const Cand c = load_cand(part, I.nbrow);
+  // the finished sums of the stopping test, both parities of v
+  double gu0 = 0.0, gu1 = 0.0, ga0 = 0.0, ga1 = 0.0, gb0 = 0.0, gb1 = 0.0;
+  if (t < 64) {
+    gu0 = part[(size_t)GSU * ACA_MAXBLK + t];
+    gu1 = part[(size_t)GSU * ACA_MAXBLK + 64 + t];
+    ga0 = part[(size_t)GSUM * ACA_MAXBLK + t];
+    ga1 = part[(size_t)GSUM * ACA_MAXBLK + 64 + t];
+    gb0 = part[(size_t)GSUM1 * ACA_MAXBLK + t];
+    gb1 = part[(size_t)GSUM1 * ACA_MAXBLK + 64 + t];
+  }
+  if (t == 0) sc = I.ctl[1];
+  __syncthreads();
+  ColDec d{ACA_A_NONE, sc.i, 0, sc.k, sc.norm2, sc.tol, -1};
+  if (sc.phase != ACA_RUN) {
+    if (writer && t == 0) I.ctl[0] = sc;
+    return d;
+  }
+  const int k = sc.k;
+  const int Nx = TAB ? I.nrows : I.g.nx, Nv = TAB ? I.ncols : I.g.nv;
+  const double mw = wave_max(c.m);
+  if ((t & 63) == 0) S.mx[wv] = mw;
+  if (wv == 0) {
+    int act = sc.rowok ? A_COL : A_STOP;
+    double norm2 = sc.norm2;
+    if (sc.next == ACA_NX_COL) {
+      const int kk = k - 1;
+      const double gv0 = (kk & 1) ? gb0 : ga0, gv1 = (kk & 1) ? gb1 : ga1;
+      double cc = (t < kk) ? gu0 * gv0 : 0.0;
+      if (t + 64 < kk) cc += gu1 * gv1;
+      cc = wave_sum(cc);
+      const double guk = __shfl(kk < 64 ? gu0 : gu1, kk & 63, 64);
+      const double gvk = __shfl(kk < 64 ? gv0 : gv1, kk & 63, 64);
+      const double nk = guk * gvk;
+      norm2 = sc.norm2 + 2.0 * cc + nk;
+      if (sqrt(nk) <= sc.tol * sqrt(fmax(norm2, 0.0))) act = A_PROBE;
+      else if (k >= sc.kmax) act = A_CAP;
+      else act = sc.rowok ? A_COL : A_STOP;
+    }
+    if (t == 0) { s_norm2 = norm2; s_act = act; }
+  }
+  __syncthreads();
+  const double M = fmax(fmax(S.mx[0], S.mx[1]), fmax(S.mx[2], S.mx[3]));
+  const double norm2 = s_norm2;
+  const int act = s_act;
+  d.norm2 = norm2;
+  if (act == A_CAP || act == A_STOP) {
+    if (writer && t == 0) {
+      AcaCtl o = sc;
+      o.norm2 = norm2; o.phase = ACA_DONE;
+      if (act == A_CAP) o.capped = 1;
+      I.ctl[0] = o;
+    }
+    return d;
+  }
+  const int i = sc.i;
+  int j = Nv;
+  bool zero_row = false;
+  if (act == A_COL) {
+    j = pivot_pick(c, M, I.V + (size_t)k * Nv, I.nbrow, Nv, NoSkip{}, S);
+    const double thr = sc.tol * sqrt(norm2) / sqrt((double)Nx * (double)Nv);
+    zero_row = (M == 0.0 || M <= thr || j >= Nv);
+  }
+  const bool probe = act == A_PROBE || zero_row;
+  const bool stop_now = probe && (k == 0 || I.nprobe <= 0);
+  if (writer && t == 0) {
+    AcaCtl o = sc;
+    o.norm2 = norm2;
+    if (act == A_COL) {
+      I.used[i] = 1;
+      o.iters += 1; o.samples += Nv; o.j = j; o.pivot = M;
+    }
+    if (stop_now) {
+      o.phase = ACA_DONE; o.converged = 1;
+    } else if (probe) {
+      o.next = ACA_NX_PROBE; o.samples += I.nprobe;
+    } else {
+      o.next = ACA_NX_COL; o.k = k + 1; o.samples += Nx;
+      if (I.piv) { I.piv[2 * k] = i; I.piv[2 * k + 1] = j; }
+    }
+    I.ctl[0] = o;
+  }
+  d.act = stop_now ? ACA_A_NONE : (probe ? ACA_A_PROBE : ACA_A_COL);
+  d.j = j;
+  d.also = zero_row ? i : -1;
+  return d;
+}
+
+// One tile of the column launch.  Probe check: this tile's share of the
+// probe entries (base = 64 tile, 64 (tile + nbcol), ...), each residual
+// above the threshold in a row not yet used stored as |residual|, else -1.
+// Column: the column fiber A[:, j] (Nx entries), its residual scaled by
+// 1/r_j stored as U[k], partials of u_l . u and per-block candidates of
+// the next row pivot (unused rows), and this tile's share of the sums over
+// the row blocks of v_l . v_k for the next stopping test (l = tile,
+// tile + nbcol, ...).
 template <typename T, int W, int DX, bool TAB = false>
-__device__ void aca_col_body(const AcaInst& I, int tile) {
+__device__ void aca_col_sample(const AcaInst& I, const ColDec& d, int tile) {
+  if (d.act == ACA_A_NONE) return;
   const GridDev& g = I.g;
   const AdvDev& a = I.a;
   const T* __restrict__ X = (const T*)I.X;
   const T* __restrict__ P = (const T*)I.P;
   const int ld = I.ld, r = I.r;
-  AcaCtl* ctl = I.ctl;
   double* __restrict__ U = I.U;
   const double* __restrict__ V = I.V;
-  const unsigned char* __restrict__ used = I.used;
+  unsigned char* __restrict__ used = I.used;
   double* __restrict__ part = I.part;
   const int nbrow = I.nbrow;
   __shared__ FsLds<W, DX> L;
   __shared__ double red[4];
   __shared__ int redi[4];
-  __shared__ int s_phase, s_i, s_k;
-  __shared__ double s_norm2, s_tol;
   __shared__ double acc4[4][FS_SAMPLES];
   __shared__ double ures[FS_SAMPLES];
   const int t = threadIdx.x;
-  if (t == 0) { s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; s_norm2 = ctl->norm2; s_tol = ctl->tol; }
-  __syncthreads();
-  if (s_phase != ACA_RUN) return;
-  const int i = s_i, k = s_k;
+  const int k = d.k, i = d.i, j = d.j;
   const int Nx = TAB ? I.nrows : g.nx, Nv = TAB ? I.ncols : g.nv;
+  const int wv = t >> 6, ln = t & 63;
+  if (d.act == ACA_A_PROBE) {
+    // the quad of a sample splits the l-sum of the approximation
+    const double thr2 = d.tol * sqrt(fmax(d.norm2, 0.0)) / sqrt((double)Nx * (double)Nv);
+    double* pr = part + (size_t)PRB * ACA_MAXBLK;
+    int* pri = (int*)(part + (size_t)PRBI * ACA_MAXBLK);
+    const int* __restrict__ probes = I.probes;
+    for (int base = tile * FS_SAMPLES; base < I.nprobe; base += I.nbcol * FS_SAMPLES) {
+      const int np = min(FS_SAMPLES, I.nprobe - base);
+      const int s = t >> 2, q = t & 3;
+      int pI = 0, pJ = 0;
+      if (s < np) {
+        pI = probes[2 * (base + s)];
+        pJ = probes[2 * (base + s) + 1];
+        int gi[4];
+        entry_index<DX, TAB>(I, pI, pJ, gi);
+        fs_prepare<W, DX, 4>(g, a, gi, L, s, q);
+      }
+      double ap = 0.0;
+      if (s < np)
+        for (int l = q; l < k; l += 4) ap += U[(size_t)l * Nx + pI] * V[(size_t)l * Nv + pJ];
+      ap += __shfl_xor(ap, 1, 4);
+      ap += __shfl_xor(ap, 2, 4);
+      __syncthreads();
+      fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, np);
+      __syncthreads();
+      if (s < np && q == 0) {
+        const double v = L.val[s] - ap;
+        const bool bad = fabs(v) > thr2 && !used[pI] && pI != d.also;
+        pr[base + s] = bad ? fabs(v) : -1.0;
+        pri[base + s] = pI;
+      }
+      __syncthreads();
+    }
+    return;
+  }
   const int I0 = tile * ACA_TILE;
   const int ns = min(ACA_TILE, Nx - I0);
-  const int wv = t >> 6, ln = t & 63;
-  // earlier column vectors u_l[I] (independent of the pivot: issued first)
-  double ul[ACA_LREG];
+  // earlier column vectors u_l[I] and v_l[j] (loads in flight during the feet)
+  double ul[ACA_LREG], vj[ACA_LREG];
 #pragma unroll
   for (int m = 0; m < ACA_LREG; ++m) {
     const int l = wv + 4 * m;
     ul[m] = (l < k && ln < ns) ? U[(size_t)l * Nx + I0 + ln] : 0.0;
-  }
-  // column pivot of the row residual (every block computes the same)
-  double M;
-  const double* vk = V + (size_t)k * Nv;
-  const int j = pivot_from_parts(vk, part, part + ACA_MAXBLK, part + (size_t)PVAL * ACA_MAXBLK, nbrow, Nv,
-                                 NoSkip{}, red, redi, &M);
-  if (tile == 0 && t == 0) { ctl->j = j; ctl->pivot = M; }   // read by the bookkeeping launch
-  const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
-  if (M == 0.0 || M <= thr || j >= Nv) return;   // row already reproduced
-  // finish the row-fiber dot products for the bookkeeping launch:
-  // gv[l] = sum_b (v_l . r)_b, block `tile` takes l = tile, tile + nbcol, ...
-  for (int l = tile; l <= k; l += I.nbcol) {
-    const double* q = part + (size_t)(2 + l) * ACA_MAXBLK;
-    double acc = 0.0;
-    for (int b = t; b < nbrow; b += FS_THREADS) acc += q[b];
-    acc = wave_sum(acc);
-    if (ln == 0) acc4[wv][0] = acc;
-    __syncthreads();
-    if (t == 0) part[(size_t)GSUM * ACA_MAXBLK + l] = ((acc4[0][0] + acc4[1][0]) + acc4[2][0]) + acc4[3][0];
-    __syncthreads();
-  }
-  const double piv = vk[j];
-  double vj[ACA_LREG];
-#pragma unroll
-  for (int m = 0; m < ACA_LREG; ++m) {
-    const int l = wv + 4 * m;
     vj[m] = (l < k) ? V[(size_t)l * Nv + j] : 0.0;
   }
+  const double piv = V[(size_t)k * Nv + j];
   {
     const int s = t >> 2;
     if (s < ns) {
@@ -471,204 +758,35 @@ __device__ void aca_col_body(const AcaInst& I, int tile) {
   }
   block_candidate(ures, ns, I0, SkipUsed{used, i}, red, redi, &pc[tile], &pc[ACA_MAXBLK + tile],
                   &pc[(size_t)PVAL * ACA_MAXBLK + tile]);
-}
-
-// One block: bookkeeping of the iteration, stopping test, next row pivot,
-// and the random-probe check whenever the approximation wants to stop.
-// Every partial the iteration needs (block maxima, candidates and their
-// values of both fibers, and the per-block dot products) is loaded in one
-// pass of independent loads; the rest works from LDS.
-constexpr int FIN_NB = 256;   // blocks per fiber staged in LDS
-static_assert(ACA_TILE <= FS_SAMPLES, "a fiber tile fits the sampler's LDS rows");
-static_assert(FIN_NB * ACA_TILE >= SLAR_NMAX * SLAR_NMAX && FIN_NB * ACA_TILE >= SLAR_NMAX_1D,
-              "every fiber fits the staged partials");
-
-template <typename T, int W, int DX, bool TAB = false>
-__device__ void aca_fin_body(const AcaInst& I) {
-  const GridDev& g = I.g;
-  const AdvDev& a = I.a;
-  const T* __restrict__ X = (const T*)I.X;
-  const T* __restrict__ P = (const T*)I.P;
-  const int ld = I.ld, r = I.r;
-  AcaCtl* ctl = I.ctl;
-  const double* __restrict__ U = I.U;
-  const double* __restrict__ V = I.V;
-  unsigned char* __restrict__ used = I.used;
-  const double* __restrict__ part = I.part;
-  const int nbcol = I.nbcol, nprobe = I.nprobe;
-  const int* __restrict__ probes = I.probes;
-  __shared__ FsLds<W, DX> L;
-  __shared__ double red[4];
-  __shared__ int redi[4];
-  __shared__ double sgv[ACA_KC + 1], sgu[ACA_KC + 1];
-  __shared__ double cmax_[FIN_NB], cidx_[FIN_NB], cval_[FIN_NB];
-  __shared__ double res[1024];
-  __shared__ int pi[1024];
-  __shared__ int s_phase, s_i, s_k, s_stop, s_j;
-  __shared__ double s_tol, s_norm2, s_M;
-  const int t = threadIdx.x;
-  if (t == 0) {
-    s_phase = ctl->phase; s_i = ctl->i; s_k = ctl->k; s_tol = ctl->tol; s_norm2 = ctl->norm2;
-    s_j = ctl->j; s_M = ctl->pivot;
-  }
-  const double* pc = part + (size_t)PCOL * ACA_MAXBLK;
-  for (int b = t; b < nbcol; b += blockDim.x) {
-    cmax_[b] = pc[b]; cidx_[b] = pc[ACA_MAXBLK + b]; cval_[b] = pc[(size_t)PVAL * ACA_MAXBLK + b];
-  }
-  __syncthreads();
-  if (s_phase != ACA_RUN) return;
-  const int i = s_i;
-  int k = s_k;
-  const int Nx = TAB ? I.nrows : g.nx, Nv = TAB ? I.ncols : g.nv;
-  // column pivot j of the row residual and its maximum M, as every block
-  // of the column launch derived them from the row partials
-  const int j = s_j;
-  const double M = s_M;
-  const double thr = s_tol * sqrt(s_norm2) / sqrt((double)Nx * (double)Nv);
-  const bool zero_row = (M == 0.0 || M <= thr || j >= Nv);
-  if (t == 0) {
-    used[i] = 1;
-    ctl->iters += 1;
-    ctl->samples += Nv;
-  }
-  if (!zero_row) {
-    // gv[l]: reduced by the column launch; gu[l] = sum_b (u_l . u)_b here:
-    // wave w takes l = w + 4 m (m < 16) of each 64-term chunk, lanes run
-    // over the blocks, all loads of a chunk are issued before the sums,
-    // then a butterfly reduce-scatter leaves the total of value m(lane) in
-    // every lane
-    {
-      const int wv = t >> 6, ln = t & 63;
-      for (int c0 = 0; c0 <= k; c0 += ACA_CHUNK) {
-        double acc[16];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-          const int l = min(c0 + wv + 4 * m, ACA_KC - 1);
-          const double* q = pc + (size_t)(2 + l) * ACA_MAXBLK;
-          double a4 = 0.0;
-#pragma unroll
-          for (int i4 = 0; i4 < FIN_NB / 64; ++i4) {
-            const int b = ln + 64 * i4;
-            const double v = q[b];
-            a4 += (b < nbcol) ? v : 0.0;
-          }
-          acc[m] = (c0 + wv + 4 * m <= k) ? a4 : 0.0;
-        }
-        const double tot = wave_sum16_scatter(acc, ln);
-        const int m = scatter_slot(ln);
-        const int l = c0 + wv + 4 * m;
-        if ((ln & 3) == 0 && l <= k) sgu[l] = tot;
-      }
-      if (t <= k) sgv[t] = part[(size_t)GSUM * ACA_MAXBLK + t];
-    }
+  // gv[l] = sum over the row blocks of (v_l . v_k), l <= k
+  double* gs = part + (size_t)((k & 1) ? GSUM1 : GSUM) * ACA_MAXBLK;
+  for (int l = tile; l <= k; l += I.nbcol) {
+    const double* q = part + (size_t)(2 + l) * ACA_MAXBLK;
+    double acc = 0.0;
+    for (int b = t; b < nbrow; b += FS_THREADS) acc += q[b];
+    acc = wave_sum(acc);
+    if (ln == 0) acc4[wv][0] = acc;
     __syncthreads();
-    if (t < 64) {
-      // cross terms sum_{l<k} (u_l . u_k)(v_l . v_k), k < 128
-      double c = (t < k) ? sgu[t] * sgv[t] : 0.0;
-      if (t + 64 < k) c += sgu[t + 64] * sgv[t + 64];
-      c = wave_sum(c);
-      if (t == 0) {
-        ctl->samples += Nx;
-        if (I.piv) { I.piv[2 * k] = i; I.piv[2 * k + 1] = j; }
-        const double nk = sgu[k] * sgv[k];
-        const double norm2 = s_norm2 + 2.0 * c + nk;
-        ctl->norm2 = norm2;
-        ctl->k = k + 1;
-        s_norm2 = norm2;
-        s_stop = 0;
-        if (sqrt(nk) <= s_tol * sqrt(fmax(norm2, 0.0))) s_stop = 1;            // probe
-        else if (k + 1 >= ctl->kmax) { ctl->phase = ACA_DONE; ctl->capped = 1; s_stop = 2; }
-      }
-    }
+    if (t == 0) gs[l] = ((acc4[0][0] + acc4[1][0]) + acc4[2][0]) + acc4[3][0];
     __syncthreads();
-    k = k + 1;
-    if (s_stop == 2) return;
-    if (s_stop == 0) {
-      // next row pivot: unused row maximising |u_k| (block candidates)
-      const double* uk = U + (size_t)(k - 1) * Nx;
-      double Mu;
-      const int ip = pivot_from_parts(uk, cmax_, cidx_, cval_, nbcol, Nx, SkipUsed{used, i}, red, redi, &Mu);
-      if (t == 0) {
-        if (!(Mu >= 0.0) || ip >= Nx) ctl->phase = ACA_DONE;
-        else ctl->i = ip;
-      }
-      return;
-    }
-  }
-  // ---- probe check (the approximation wants to stop)
-  if (k == 0 || nprobe <= 0) {
-    if (t == 0) { ctl->phase = ACA_DONE; ctl->converged = 1; }
-    return;
-  }
-  const double thr2 = s_tol * sqrt(fmax(s_norm2, 0.0)) / sqrt((double)Nx * (double)Nv);
-  for (int base = 0; base < nprobe; base += FS_SAMPLES) {
-    const int ns = min(FS_SAMPLES, nprobe - base);
-    const int s = t >> 2, q = t & 3;
-    int pI = 0, pJ = 0;
-    if (s < ns) {
-      pI = probes[2 * (base + s)];
-      pJ = probes[2 * (base + s) + 1];
-      int gi[4];
-      entry_index<DX, TAB>(I, pI, pJ, gi);
-      fs_prepare<W, DX, 4>(g, a, gi, L, s, q);
-    }
-    // approximation at the probe: the quad splits the l-sum
-    double ap = 0.0;
-    if (s < ns)
-      for (int l = q; l < k; l += 4) ap += U[(size_t)l * Nx + pI] * V[(size_t)l * Nv + pJ];
-    ap += __shfl_xor(ap, 1, 4);
-    ap += __shfl_xor(ap, 2, 4);
-    __syncthreads();
-    fs_evaluate_team<T, W, DX>(I.team, X, P, ld, r, L, ns);
-    __syncthreads();
-    if (s < ns && q == 0) {
-      const double v = L.val[s] - ap;
-      const bool bad = fabs(v) > thr2 && !used[pI];
-      res[base + s] = bad ? fabs(v) : -1.0;
-      pi[base + s] = pI;
-    }
-    __syncthreads();
-  }
-  double m = -1.0;
-  for (int e = t; e < nprobe; e += blockDim.x) m = fmax(m, res[e]);
-  m = block_max(m, red);
-  int best = nprobe;
-  if (m > 0.0) {
-    for (int e = t; e < nprobe; e += blockDim.x)
-      if (res[e] > 0.0 && res[e] >= m * (1.0 - 1e-10) && e < best) best = e;
-    for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
-    if ((t & 63) == 0) redi[t >> 6] = best;
-    __syncthreads();
-    best = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
-  }
-  if (t == 0) {
-    ctl->samples += nprobe;
-    if (m <= 0.0 || best >= nprobe) {
-      ctl->phase = ACA_DONE;
-      ctl->converged = 1;
-    } else if (k >= ctl->kmax) {
-      ctl->phase = ACA_DONE;
-      ctl->capped = 1;
-    } else {
-      ctl->probe_rounds += 1;
-      ctl->i = pi[best];
-    }
   }
 }
 
 // --------------------------------------------------- single-instance kernels
 template <typename T, int W, int DX, bool TAB = false>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_row(AcaInst I) { aca_row_body<T, W, DX, TAB>(I, blockIdx.x); }
+__global__ __launch_bounds__(FS_THREADS) void k_aca_row(AcaInst I) {
+  const RowDec d = aca_row_decide<TAB>(I, blockIdx.x == 0);
+  aca_row_sample<T, W, DX, TAB>(I, d, blockIdx.x);
+}
 template <typename T, int W, int DX, bool TAB = false>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_col(AcaInst I) { aca_col_body<T, W, DX, TAB>(I, blockIdx.x); }
-template <typename T, int W, int DX, bool TAB = false>
-__global__ __launch_bounds__(FS_THREADS) void k_aca_fin(AcaInst I) {
-  aca_fin_body<T, W, DX, TAB>(I);
-  // thread 0 made every change of the phase, so it reads the final value;
-  // the host waits for seq, then reads the phase
-  if (I.phase_host && threadIdx.x == 0) {
+__global__ __launch_bounds__(FS_THREADS) void k_aca_col(AcaInst I) {
+  const ColDec d = aca_col_decide<TAB>(I, blockIdx.x == 0);
+  aca_col_sample<T, W, DX, TAB>(I, d, blockIdx.x);
+  // thread 0 of block 0 wrote ctl[0] in this launch, so it reads the
+  // current phase; the host waits for seq, then reads the phase
+  if (I.phase_host && blockIdx.x == 0 && threadIdx.x == 0) {
     volatile int* ph = I.phase_host;
-    ph[0] = I.ctl->phase;
+    ph[0] = I.ctl[0].phase;
     __threadfence_system();
     ph[1] = I.seq;
   }

@@ -6,7 +6,7 @@
 // fiber tile, tile count); each instance keeps its own control block and
 // partial-sum slots, so the per-tile arithmetic and the pivot decisions are
 // those of the one-instance kernels, whatever block runs a tile.  A chunk of
-// iterations (row / column / bookkeeping launches) plus an active-instance
+// iterations (row and column launches) plus an active-instance
 // count is captured once as a hipGraph and replayed until no instance runs.
 //
 // The autotuner times whole batched cross approximations on the caller's
@@ -91,7 +91,7 @@ static hipError_t build_items(slar_batch* b) {
   return hipSuccess;
 }
 
-// Capture `chunk` iterations of the three batched launches plus the count of
+// Capture `chunk` iterations of the two batched launches plus the count of
 // running instances.  Kernel arguments are the batch's own device tables, so
 // one capture serves every later call with the same configuration.
 static hipError_t capture_chunk(slar_batch* b) {
@@ -99,11 +99,9 @@ static hipError_t capture_chunk(slar_batch* b) {
   if (b->graph) { HIP_CHK(hipGraphDestroy(b->graph)); b->graph = nullptr; }
   HIP_CHK(build_items(b));
   HIP_CHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-  const int fin_grid = std::min(b->count, 1024);
   for (int it = 0; it < b->chunk; ++it) {
     k_batch_row<<<std::min(b->grid, b->nrow_items), FS_THREADS, 0, b->cap>>>(b->d_inst, b->d_rows, b->nrow_items);
     k_batch_col<<<std::min(b->grid, b->ncol_items), FS_THREADS, 0, b->cap>>>(b->d_inst, b->d_cols, b->ncol_items);
-    k_batch_fin<<<fin_grid, FS_THREADS, 0, b->cap>>>(b->d_inst, b->count);
   }
   k_batch_status<<<1, 256, 0, b->cap>>>(b->d_inst, b->count, b->d_active, nullptr);
   const hipError_t le = hipGetLastError();

@@ -1,8 +1,8 @@
 // Kernels of the batched multi-instance cross approximation: the
 // preparation launch (FP32 tables, combined field, cleared marks and control
-// blocks of every instance), the persistent row / column / bookkeeping
-// launches that walk a table of (instance, fiber tile) work items with the
-// one-instance bodies of aca.h, and the active-instance count.
+// blocks of every instance), the persistent row / column launches that walk
+// a table of (instance, fiber tile) work items with the one-instance bodies
+// of aca.h, and the active-instance count.
 #pragma once
 #include "aca.h"
 
@@ -70,43 +70,42 @@ __global__ __launch_bounds__(256) void k_batch_prep(const BPrep* __restrict__ pr
     AcaCtl* c = p.ctl;
     c->phase = ACA_RUN; c->k = 0; c->i = 0; c->j = 0;
     c->iters = 0; c->probe_rounds = 0; c->converged = 0; c->capped = 0;
-    c->cnt_row = 0; c->cnt_col = 0; c->kmax = p.kmax; c->pad = 0;
+    c->next = ACA_NX_START; c->rowok = 0; c->kmax = p.kmax; c->pad = 0;
     c->pivot = 0.0; c->norm2 = 0.0; c->tol = p.tol; c->samples = 0;
   }
 }
 
-__global__ __launch_bounds__(FS_THREADS) void k_batch_row(const AcaInst* __restrict__ insts,
+// Both kernels hold the 1D1V and 2D2V bodies and would take 256 VGPRs plus
+// AGPR spill slots, one wave per SIMD.  Bounded to two waves per SIMD they
+// spill a few dozen values to scratch, and the fixed-configuration batched
+// step went from 94.8 to 71.6 ms.
+__global__ __launch_bounds__(FS_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_row(const AcaInst* __restrict__ insts,
                                                            const BItem* __restrict__ items, int nitems) {
   for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
     const BItem w = items[t];
     const AcaInst& I = insts[w.q];
-    for (int u = 0; u < w.nt; ++u) {
-      __syncthreads();
-      if (I.g.dx == 1) aca_row_body<float, 3, 1>(I, w.t0 + u);
-      else aca_row_body<float, 3, 2>(I, w.t0 + u);
-    }
-  }
-}
-
-__global__ __launch_bounds__(FS_THREADS) void k_batch_col(const AcaInst* __restrict__ insts,
-                                                           const BItem* __restrict__ items, int nitems) {
-  for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
-    const BItem w = items[t];
-    const AcaInst& I = insts[w.q];
-    for (int u = 0; u < w.nt; ++u) {
-      __syncthreads();
-      if (I.g.dx == 1) aca_col_body<float, 3, 1>(I, w.t0 + u);
-      else aca_col_body<float, 3, 2>(I, w.t0 + u);
-    }
-  }
-}
-
-__global__ __launch_bounds__(FS_THREADS) void k_batch_fin(const AcaInst* __restrict__ insts, int count) {
-  for (int q = blockIdx.x; q < count; q += gridDim.x) {
     __syncthreads();
-    const AcaInst& I = insts[q];
-    if (I.g.dx == 1) aca_fin_body<float, 3, 1>(I);
-    else aca_fin_body<float, 3, 2>(I);
+    const RowDec d = aca_row_decide<false>(I, w.t0 == 0);   // once per item
+    for (int u = 0; u < w.nt; ++u) {
+      __syncthreads();
+      if (I.g.dx == 1) aca_row_sample<float, 3, 1>(I, d, w.t0 + u);
+      else aca_row_sample<float, 3, 2>(I, d, w.t0 + u);
+    }
+  }
+}
+
+__global__ __launch_bounds__(FS_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_col(const AcaInst* __restrict__ insts,
+                                                           const BItem* __restrict__ items, int nitems) {
+  for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
+    const BItem w = items[t];
+    const AcaInst& I = insts[w.q];
+    __syncthreads();
+    const ColDec d = aca_col_decide<false>(I, w.t0 == 0);   // once per item
+    for (int u = 0; u < w.nt; ++u) {
+      __syncthreads();
+      if (I.g.dx == 1) aca_col_sample<float, 3, 1>(I, d, w.t0 + u);
+      else aca_col_sample<float, 3, 2>(I, d, w.t0 + u);
+    }
   }
 }
 

@@ -1,21 +1,27 @@
 // Adaptive cross approximation of the SL-updated tensor (HTACA sampling stage,
 // introduction and section 3.1; the pivoting rules are documented in slar.h).
 //
-// Every iteration is three launches that read and write a device control
+// Every iteration is two launches that read and write a device control
 // block, so the host can enqueue several iterations before it looks at the
 // stop flag:
-//   k_aca_row : sample row fiber A[i, :] (Nv entries) through the SL-FD
-//               evaluator, residual r = A[i,:] - sum_l u_l[i] v_l, stored as
-//               V[k]; per-block partials of v_l . r and a per-block pivot
-//               candidate (block max |r| and its lowest index within the tie
-//               tolerance);
-//   k_aca_col : every block derives the column pivot j from the row
-//               candidates (lowest index within a relative 1e-10 of the
-//               maximum), samples column fiber A[:, j] (Nx entries), stores
-//               the residual scaled by 1/r_j as U[k], partials of u_l . u
-//               and per-block candidates of the next row pivot (unused rows);
-//   k_aca_fin : one block: ||S_k||^2 update, stopping test, next row pivot,
-//               and the random-probe check whenever the cross wants to stop.
+//   k_aca_row : every block derives the row pivot i (the unused row
+//               maximising the last column residual, from the column
+//               launch's block candidates, or the probe check's worst
+//               entry), samples row fiber A[i, :] (Nv entries) through the
+//               SL-FD evaluator, stores the residual
+//               r = A[i,:] - sum_l u_l[i] v_l as V[k], per-block partials of
+//               v_l . r and a per-block pivot candidate, and finishes the
+//               sums of the column launch's dot products;
+//   k_aca_col : every block runs the stopping test of the previous term
+//               (||S_k||^2 update; stop, probe check or continue), derives
+//               the column pivot j from the row candidates (lowest index
+//               within a relative 1e-10 of the maximum), samples column
+//               fiber A[:, j] (Nx entries), stores the residual scaled by
+//               1/r_j as U[k], partials of u_l . u and per-block candidates
+//               of the next row pivot (unused rows); or it samples the
+//               probe entries when the cross wants to stop.
+// A row launch samples its row before the stopping test of the previous
+// term has run; the column launch discards that row when the test stops.
 // Kernel boundaries order the partial sums; no inter-block fences are used.
 // The rank-1 terms are u_k v_k^T with u_k = column residual / r_j and
 // v_k = row residual (the same product as the textbook v = r / r_j).
@@ -30,7 +36,7 @@
 
 namespace slar {
 
-size_t aca_ctl_bytes() { return sizeof(AcaCtl); }
+size_t aca_ctl_bytes() { return 2 * sizeof(AcaCtl); }
 size_t aca_part_elems() { return (size_t)ACA_PART_SLOTS * ACA_MAXBLK; }
 
 template <typename T, int W, int DX>
@@ -53,7 +59,6 @@ static hipError_t aca_iterate(hipStream_t s, const GridDev& G, const AdvDev& A, 
     k_aca_row<T, W, DX><<<bRow, FS_THREADS, 0, s>>>(I);
     k_aca_col<T, W, DX><<<bCol, FS_THREADS, 0, s>>>(I);
   }
-  k_aca_fin<T, W, DX><<<1, FS_THREADS, 0, s>>>(I);
   return hipGetLastError();
 }
 
@@ -120,8 +125,8 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   const int rx = (G.dx == 2) ? adv.order * adv.order : adv.order;
   const double gather_bytes = 2.0 * rx * ldt * (dt == SLAR_F32 ? 4.0 : 8.0) + 8.0;
   const bool timing = ws->timing && (int)ws->events.size() >= 4 * maxit;
-  // Iterations are enqueued in chunks of CH.  The last bookkeeping launch
-  // of chunk c writes the phase and then the sequence number c + 1 to
+  // Iterations are enqueued in chunks of CH.  The last column launch of
+  // chunk c writes the phase and then the sequence number c + 1 to
   // host-mapped pinned words (a store that crosses to host memory delays
   // the end of its kernel, so the others skip it).  Once the next chunk is
   // queued (so the device never idles on a poll), the host waits until the

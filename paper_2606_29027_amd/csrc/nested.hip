@@ -3,7 +3,7 @@
 // and 5 ask for; nested skeleton after Ballani, Grasedyck and Kluge).
 //
 // Every leaf and root search is the device-resident cross approximation of
-// cross.hip (row, column and bookkeeping launches, partial pivoting, tie
+// cross.hip (row and column launches, partial pivoting, tie
 // rule, probe restart) in index-table mode: the searched matrix is
 // A^(mu)[:, candidates] or A[rows_x, rows_v], and a matrix entry is the grid
 // point whose multi-index joins the two table entries.  Between searches
@@ -204,7 +204,6 @@ static slar_status nest_search(const NestCtx& c, const std::vector<Idx4>& rowtab
     for (const int end = std::min(it + CH, maxit); it < end; ++it) {
       k_aca_row<T, 3, 2, true><<<bRow, FS_THREADS, 0, s>>>(I);
       k_aca_col<T, 3, 2, true><<<bCol, FS_THREADS, 0, s>>>(I);
-      k_aca_fin<T, 3, 2, true><<<1, FS_THREADS, 0, s>>>(I);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(&ring[ch & 1], ctl, sizeof(AcaCtl), hipMemcpyDeviceToHost, s));
