@@ -5,7 +5,7 @@ the rank at rmax: capping the cross itself keeps a skeleton whose error is
 not controlled, and on the strong-Landau workload that error grew from step
 to step (the full-grid SL update and its SVD truncation stayed bounded).
 These tests drive the second 64-term chunk of the fiber kernels, the
-bookkeeping of up to 128 terms, the 128-column Cholesky-QR and the
+pivot and stopping decisions of up to 128 terms, the 128-column Cholesky-QR and the
 left-vector Jacobi SVD of the truncation."""
 import numpy as np
 import pytest
