@@ -23,7 +23,11 @@
  *    validated before anything is enqueued; on SLAR_E_INVAL nothing ran.
  *  - Calls enqueue on the given HIP stream.  Calls whose control flow
  *    depends on device data (slar_cross_update, slar_truncate,
- *    slar_macro_solve) synchronise that stream before returning.
+ *    slar_macro_solve) wait on that stream for the data they decide on
+ *    (ranks, stopping flags, residuals); work enqueued after the last
+ *    decision may still run when they return.  Their outputs are complete
+ *    in stream order, and the host-side values they return (ranks, counts,
+ *    statuses) are final.
  *  - A workspace may be used by one stream at a time.
  */
 #ifndef SLAR_H_

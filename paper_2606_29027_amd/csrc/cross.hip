@@ -285,8 +285,8 @@ slar_status cur_core_run(hipStream_t s, Workspace* ws, slar_lowrank* out, int rc
   HIP_TRY(hipStreamSynchronize(s));
   const int r = cur_rank(hs, k, rcap);
   if (r == 0) return SLAR_E_NUMERIC;
+  // the new terms are complete in stream order; the host already knows r
   if (cur_back(s, ws, out, c, r) != hipSuccess) return SLAR_E_HIP;
-  HIP_TRY(hipStreamSynchronize(s));
   out->k = r;
   return SLAR_OK;
 }

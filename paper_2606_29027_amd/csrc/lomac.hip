@@ -825,8 +825,8 @@ static slar_status macro_solve_once(hipStream_t s, Workspace* ws, const MacroHis
     k_axpby<<<nb, 256, 0, s>>>(n, 1.0, b.d, 1.0, U, 0.0, nullptr);
     ++newton;
   }
+  // U^(n+1) is complete in stream order
   HIP_TRY(hipMemcpyAsync(Uout, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
   if (iters) { iters[0] = newton; iters[1] = krylov; }
   return converged ? SLAR_OK : SLAR_E_NOCONV;
 }

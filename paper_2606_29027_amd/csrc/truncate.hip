@@ -326,8 +326,8 @@ slar_status truncate_run(hipStream_t s, Workspace* ws, const slar_lowrank& in, d
   }
   out->dtype = SLAR_F64;
   out->d = d;
+  // the ranks are decided; the factors are complete in stream order
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(s));
   return capped ? SLAR_E_RANK_CAP : SLAR_OK;
 }
 
