@@ -136,7 +136,7 @@ slar_status cross_run(hipStream_t s, Workspace* ws, const slar_frames& src, cons
   // back by ~4 us.)
   // Iterations enqueued after the stop see phase != RUN and exit at once
   // (their launches did no work and are left out of the timing below).
-  constexpr int CH = 4;
+  constexpr int CH = 8;
   auto timed = [&](int q) { return timing && (q % ws->timing_every) == ws->timing_every - 1; };
   volatile int* ph = (volatile int*)ws->phase_host;
   ph[0] = ACA_RUN;                              // no launch of this workspace is in flight
