@@ -72,6 +72,17 @@ struct AcaInst {
   int seq = 0;
 };
 
+// The thread index through an empty volatile asm.  In the persistent
+// multi-instance kernels this keeps the compiler from hoisting every value
+// derived from it (lane masks, LDS offsets) out of the work-item loop, where
+// they held registers for the whole launch; per item they cost a few ALU
+// operations.
+__device__ __forceinline__ int aca_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -120,7 +131,7 @@ __device__ __forceinline__ int scatter_slot(int ln) {
 
 // block max of |v| over 256 threads -> returns in all threads
 __device__ double block_max(double v, double* red) {
-  const int t = threadIdx.x;
+  const int t = aca_tid();
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
@@ -132,7 +143,7 @@ __device__ double block_max(double v, double* red) {
 // out[l] = sum_b part[(1 + l) * ACA_MAXBLK + b] for l in [0, cnt), one wave
 // per l (l = wave, wave + 4, ...), lanes over b (coalesced), fixed order.
 __device__ void block_sum_parts(const double* part, int nb, int cnt, double* out) {
-  const int t = threadIdx.x;
+  const int t = aca_tid();
   const int wv = t >> 6, ln = t & 63;
   for (int l = wv; l < cnt; l += 4) {
     const double* q = part + (size_t)(1 + l) * ACA_MAXBLK;
@@ -194,7 +205,7 @@ static_assert(ACA_KC <= ACA_MAXBLK, "GSUM holds one slot per cross term");
 template <typename Skip>
 __device__ void block_candidate(const double* xs, int ns, int base, Skip skip, double* red, int* redi,
                                 double* out_max, double* out_idx, double* out_val) {
-  const int t = threadIdx.x;
+  const int t = aca_tid();
   double v = -1.0;
   if (t < ns && !skip(base + t)) v = fabs(xs[t]);
   const double m = block_max(v, red);
@@ -244,7 +255,7 @@ struct Cand {
   double m, idx, val;
 };
 __device__ __forceinline__ Cand load_cand(const double* base, int nb) {
-  const int t = threadIdx.x;
+  const int t = aca_tid();
   Cand c{-1.0, 0.0, -1.0};
   if (t < nb) {
     c.m = base[t];
@@ -271,7 +282,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // (lowest eligible index within the tolerance).
 template <typename Skip>
 __device__ int pivot_pick(const Cand& c, double M, const double* x, int nb, int n, Skip skip, PivLds& S) {
-  const int t = threadIdx.x, wv = t >> 6;
+  const int t = aca_tid(), wv = t >> 6;
   if (!(M >= 0.0)) return n;
   const double thr = M * (1.0 - 1e-10);
   int bb = (t < nb && c.m >= thr) ? t : nb;
@@ -322,7 +333,7 @@ template <bool TAB>
 __device__ RowDec aca_row_decide(const AcaInst& I, bool writer) {
   __shared__ AcaCtl sc;
   __shared__ PivLds S;
-  const int t = threadIdx.x, wv = t >> 6;
+  const int t = aca_tid(), wv = t >> 6;
   const Cand c = load_cand(I.part + (size_t)PCOL * ACA_MAXBLK, I.nbcol);
   if (t == 0) sc = I.ctl[0];
   __syncthreads();
@@ -410,7 +421,7 @@ __device__ void aca_row_sample(const AcaInst& I, const RowDec& d, int tile) {
   __shared__ int redi[4];
   __shared__ double acc4[4][FS_SAMPLES];
   __shared__ double rres[FS_SAMPLES];
-  const int t = threadIdx.x;
+  const int t = aca_tid();
   const int k = d.k, i = d.i;
   const int Nx = TAB ? I.nrows : g.nx, Nv = TAB ? I.ncols : g.nv;
   const int J0 = tile * ACA_TILE;
@@ -532,7 +543,7 @@ __device__ ColDec aca_col_decide(const AcaInst& I, bool writer) {
   __shared__ PivLds S;
   __shared__ double s_norm2;
   __shared__ int s_act;
-  const int t = threadIdx.x, wv = t >> 6;
+  const int t = aca_tid(), wv = t >> 6;
   const double* __restrict__ part = I.part;
   const Cand c = load_cand(part, I.nbrow);
   // the finished sums of the stopping test, both parities of v
@@ -648,7 +659,7 @@ __device__ void aca_col_sample(const AcaInst& I, const ColDec& d, int tile) {
   __shared__ int redi[4];
   __shared__ double acc4[4][FS_SAMPLES];
   __shared__ double ures[FS_SAMPLES];
-  const int t = threadIdx.x;
+  const int t = aca_tid();
   const int k = d.k, i = d.i, j = d.j;
   const int Nx = TAB ? I.nrows : g.nx, Nv = TAB ? I.ncols : g.nv;
   const int wv = t >> 6, ln = t & 63;
