@@ -75,10 +75,10 @@ __global__ __launch_bounds__(256) void k_batch_prep(const BPrep* __restrict__ pr
   }
 }
 
-// Both kernels hold the 1D1V and 2D2V bodies and would take 256 VGPRs plus
-// AGPR spill slots, one wave per SIMD.  Bounded to two waves per SIMD they
-// spill a few dozen values to scratch, and the fixed-configuration batched
-// step went from 94.8 to 71.6 ms.
+// Both kernels hold the 1D1V and 2D2V bodies; the column kernel would take
+// 260 registers (one wave per SIMD).  Bounded to two waves per SIMD both fit
+// 256 VGPRs without spilling, since the bodies read the thread index through
+// aca_tid() and nothing derived from it is kept across the item loop.
 __global__ __launch_bounds__(FS_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_row(const AcaInst* __restrict__ insts,
                                                            const BItem* __restrict__ items, int nitems) {
   for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
