@@ -12,7 +12,7 @@ an exact rank-3 tensor (the fourth row is reproduced: probe check, then
 stop), a rank-2 smooth part plus one entry that the pivots never visit
 (the norm test stops, a probe finds the entry, the cross resumes at its
 row), the same without probes, and the term cap reached before the norm
-test stops."""
+test stops; and seeded random cases across them."""
 import numpy as np
 import pytest
 
@@ -130,5 +130,40 @@ def test_term_cap_before_the_norm_test_stops():
     assert not io["converged"] and io["rank"] == 2
     assert c["st"] == L.SLAR_E_RANK_CAP and c["k"] == 2 and c["info"].converged == 0
     assert c["info"].samples == io["samples"]
+    scale = np.abs(c["A"]).max()
+    assert np.abs(c["got"] - c["Uo"] @ c["Vo"].T).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_low_rank_cases_match_the_oracle(seed):
+    """Seeded random cases over the same paths: rank 1..6 with a decaying
+    spectrum, sometimes one entry the pivots miss (inside the probe set),
+    0, 64 or 300 probes, tolerance 1e-4 or 1e-8, term cap 2, 4 or 32 (at
+    the cap the last term is far above the tolerance, so both sides stop
+    as capped).  Rank, stopping flags, probe rounds, sample counts and
+    U V^T agree with the oracle."""
+    rng = np.random.default_rng(1000 + seed)
+    r = int(rng.integers(1, 7))
+    X = rng.standard_normal((NX, r)) * (0.3 ** np.arange(r))[None, :]
+    P = rng.standard_normal((NX, r))
+    spike = bool(rng.integers(0, 2))
+    if spike:
+        x0, v0 = int(rng.integers(0, NX)), int(rng.integers(0, NX))
+        X = np.concatenate([X, 1e-3 * np.eye(NX, 1, -x0)], 1)
+        P = np.concatenate([P, np.eye(NX, 1, -v0)], 1)
+    nprobe = int(rng.choice([0, 64, 300]))
+    probes = SI.probe_indices(NX, NX, nprobe, 50 + seed) if nprobe else None
+    if spike and nprobe:
+        probes = np.array(probes, copy=True)
+        probes[nprobe // 2] = (x0, v0)
+    tol = float(rng.choice([1e-4, 1e-8]))
+    kmax = int(rng.choice([2, 4, 32]))
+    c = _cross(X, P, tol, kmax, probes)
+    io = c["io"]
+    assert c["k"] == io["rank"]
+    assert bool(c["info"].converged) == bool(io["converged"])
+    assert c["info"].probe_rounds == io["probe_rounds"]
+    assert c["info"].samples == io["samples"]
+    assert c["st"] == (L.SLAR_OK if io["converged"] else L.SLAR_E_RANK_CAP)
     scale = np.abs(c["A"]).max()
     assert np.abs(c["got"] - c["Uo"] @ c["Vo"].T).max() < 1e-12 * scale
