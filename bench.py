@@ -605,8 +605,9 @@ def main():
         hbm = traffic / (ms / nl * 1e-3) / 1e9
         roofline["hbm_measured_GBps"] = hbm
         roofline["hbm_measured_frac"] = hbm / HBM_PEAK_GBS
-        roofline["l2_hit_share_of_algorithmic_bytes"] = 1.0 - traffic / (by / nl)
-        roofline["limiter"] = "latency of dependent phases (gathers served from L2)"
+        # share of the gathered bytes served by the L1/L2 caches (the rest is HBM)
+        roofline["cache_share_of_algorithmic_bytes"] = 1.0 - traffic / (by / nl)
+        roofline["limiter"] = "latency of dependent phases (gathers served from the L1/L2 caches)"
     out = {
         "metric": "HT-SL sampled entries/s & time/step, 2D2V 128^4, learned vs plain at 1e-6",
         "value": H["value"],
