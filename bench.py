@@ -600,8 +600,8 @@ def main():
                 "algorithmic_bytes_per_launch": by / nl if nl else None}
     if traffic and nl and ms > 0:
         # the counters' HBM bytes over the same launch time: most of the
-        # algorithmic gather bytes are L2 hits, so the kernel is bound by
-        # the latency of its dependent phases, not by HBM bandwidth
+        # algorithmic gather bytes hit the L1 and L2 caches, so the kernel is
+        # bound by the latency of its dependent phases, not by HBM bandwidth
         hbm = traffic / (ms / nl * 1e-3) / 1e9
         roofline["hbm_measured_GBps"] = hbm
         roofline["hbm_measured_frac"] = hbm / HBM_PEAK_GBS
